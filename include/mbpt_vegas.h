@@ -1,0 +1,264 @@
+/*
+ * mbpt_vegas.h -- C ABI of the MI355X (gfx950) VEGAS Monte Carlo library for
+ * many-body perturbation theory (MBPT) energy diagrams of infinite nucleon
+ * matter (arXiv:2603.24532, Secs. "Many-body expressions" and "Automated
+ * evaluation of many-body expressions").
+ *
+ * What is computed.  For a two-body Hugenholtz energy diagram of order n at an
+ * equation-of-state point (total density n_B, proton fraction x), the library
+ * estimates the diagram's contribution to the energy per particle E/A [MeV],
+ * i.e. the momentum integral of Eqs. (1)-(5) generalised to order n (sum over
+ * holes and particles with n_k, 1 - n_k Pauli factors, antisymmetrised
+ * matrix elements with explicit spin(-isospin) sums, energy denominators of
+ * Eq. (6) with a free spectrum) divided by n_B, by adaptive importance
+ * sampling on a per-dimension piecewise-linear grid (VEGAS, Sec. "MC
+ * integration": training with refinement, inverse-variance combination).
+ *
+ * Conventions for every entry point:
+ *  - Return value: MBPT_OK (0) or a negative MBPT_E* code; no C++ exception
+ *    crosses the ABI.  After an error, mbpt_last_error(ctx) describes it.
+ *  - Handles are opaque and owned by the library; destroy them with the
+ *    matching *_destroy call.  A context and everything created from it are
+ *    used from one host thread at a time.
+ *  - Device memory is never allocated by the library: the caller binds a
+ *    device workspace (for instance a PyTorch uint8 tensor) whose size it gets
+ *    from mbpt_workspace_query; the library keeps the pointer until unbound or
+ *    destroyed and never frees it.  All GPU work is queued on the HIP stream
+ *    given at context creation (for instance torch.cuda.current_stream()).
+ *  - Host pointers are read (inputs) or written (outputs) only during the call.
+ */
+#ifndef MBPT_VEGAS_H
+#define MBPT_VEGAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define MBPT_OK 0
+#define MBPT_EINVAL (-1)   /* invalid argument                              */
+#define MBPT_ENOMEM (-2)   /* bound workspace too small for the request     */
+#define MBPT_EHIP (-3)     /* a HIP runtime call failed (message retained)   */
+#define MBPT_ENUMERIC (-4) /* non-finite estimate                            */
+#define MBPT_EBUSY (-5)    /* server queue full                              */
+#define MBPT_ESTATE (-6)   /* call not valid in the current state            */
+
+/* ---- enums ------------------------------------------------------------ */
+/* Integrand arithmetic.  FP64: everything in double.  FP32: the per-sample
+ * integrand in float with the variance sums, the grid refinement and every
+ * sample inside the near-Fermi-surface / small-denominator band re-evaluated in
+ * double (compensated fp64 accumulation). */
+enum { MBPT_FP64 = 0, MBPT_FP32 = 1 };
+/* Matter: NEUTRON = pure neutron matter, spin labels only (degeneracy 2,
+ * proton fraction must be 0); NUCLEAR = spin x isospin labels (degeneracy 4),
+ * isospin-dependent Pauli factors, any proton fraction in [0, 1]. */
+enum { MBPT_NEUTRON = 0, MBPT_NUCLEAR = 1 };
+/* How mbpt_integrate launches work.  PER_TASK: one sample launch per task and
+ * iteration (the plain path); BATCHED: one persistent launch per iteration
+ * covering every task of the set; GRAPH: BATCHED with the whole iteration
+ * sequence captured once into a HIP graph and replayed (needs a non-default
+ * stream: EINVAL on the null stream). */
+enum { MBPT_LAUNCH_PER_TASK = 0, MBPT_LAUNCH_BATCHED = 1, MBPT_LAUNCH_GRAPH = 2 };
+
+/* ---- value types -------------------------------------------------------- */
+/* Two-body interaction V(p,p') = hbarc [C0 + Cy/(|p-p'|^2 + mpi^2)]
+ * exp(-(p/Lambda)^reg_exp) exp(-(p'/Lambda)^reg_exp), antisymmetrised as
+ * <12|V(1 - P12)|34> (Sec. "Implementing chiral forces": regulator f_NN of the
+ * nonlocal form, commuting with the antisymmetrizer).  Units: C0 [fm^2], Cy
+ * dimensionless, mpi and Lambda [fm^-1], hbar2_m = hbar^2/m [MeV fm^2], hbarc
+ * [MeV fm].  reg_exp must be an even integer in [2, 16]. */
+typedef struct mbpt_interaction {
+  double C0, Cy, mpi, Lambda;
+  int reg_exp;
+  double hbar2_m, hbarc;
+} mbpt_interaction;
+
+/* Context creation parameters.  stream: a hipStream_t (NULL = default
+ * stream).  n_bins: VEGAS bins per dimension (2..128).  alpha: refinement
+ * exponent.  kcut_extra: particle-line loop momenta are sampled in a ball of
+ * radius kF,max + kcut_extra * Lambda (hole lines: kF,max, exact).
+ * fp32_band_k, fp32_band_d: FP32 precision only -- a sample is re-evaluated
+ * in fp64 if some line has |k^2 - kF^2| < band_k kF^2 or some denominator has
+ * |D| < band_d * (sum of |eps| over its lines). */
+typedef struct mbpt_context_desc {
+  int device;
+  void *stream;
+  int precision;
+  uint32_t seed;
+  int n_bins;
+  double alpha;
+  double kcut_extra;
+  double fp32_band_k;
+  double fp32_band_d;
+} mbpt_context_desc;
+
+/* One integration task: diagram `diagram_id` of order `order` (1..5; ids
+ * index the deterministic generator list, see mbpt_num_diagrams) at density
+ * [fm^-3] and proton fraction.  task_key is the second Philox key word: the
+ * random stream of a task is (seed, task_key, iteration, sample). */
+typedef struct mbpt_task_desc {
+  int order;
+  int diagram_id;
+  int matter;
+  double density;
+  double proton_fraction;
+  uint32_t task_key;
+} mbpt_task_desc;
+
+/* Result of one task (or a sum over tasks).  E_per_A: inverse-variance
+ * weighted mean over all iterations run so far [MeV]; sigma its standard
+ * error; chi2_dof the consistency of the iterations; last_E/last_sigma the
+ * last iteration alone; n_evals integrand evaluations; n_fp64_fallback samples
+ * re-evaluated in fp64 (FP32 precision). */
+typedef struct mbpt_result {
+  double E_per_A, sigma, chi2_dof, last_E, last_sigma;
+  int iters_done;
+  uint64_t n_evals;
+  uint64_t n_fp64_fallback;
+} mbpt_result;
+
+typedef struct mbpt_context mbpt_context;
+typedef struct mbpt_task_set mbpt_task_set;
+typedef struct mbpt_server mbpt_server;
+
+/* ---- context -------------------------------------------------------------- */
+/* Create a context on `device`.  desc may be NULL for defaults (device 0,
+ * default stream, FP64, seed 1, 50 bins, alpha 1.5, kcut_extra 3.0, bands
+ * 1e-4 / 1e-2).  The default interaction is the synthetic contact + Yukawa one
+ * (C0 = -1 fm^2, Cy = -2, mpi = 0.7, Lambda = 2, exponent 4, hbar^2/m = 41.47,
+ * hbarc = 197.3269804).  EINVAL on bad fields, EHIP if the device is absent. */
+int mbpt_context_create(const mbpt_context_desc *desc, mbpt_context **out);
+void mbpt_context_destroy(mbpt_context *ctx);
+/* Message of the last failed call on this context (never NULL). */
+const char *mbpt_last_error(const mbpt_context *ctx);
+/* Replace the interaction (copied).  Affects task sets created afterwards and
+ * the next integrate call of existing ones. */
+int mbpt_set_interaction(mbpt_context *ctx, const mbpt_interaction *v);
+/* Switch integrand precision (MBPT_FP64 / MBPT_FP32) for later calls. */
+int mbpt_set_precision(mbpt_context *ctx, int precision);
+
+/* ---- diagram generator (host only, no context needed) --------------------- */
+/* Number of two-body energy diagrams of an order (1, 1, 3, 39, 840 for orders
+ * 1..5; Table I, N_diag). */
+int mbpt_num_diagrams(int order, int *count);
+/* The n x n line-count matrix of a diagram, row-major into M[order*order]:
+ * M[u*order+v] lines run from time level u to level v (particle if u < v,
+ * hole if u > v; order 1: one vertex with two hole self-lines, M = {2}).
+ * Also returns the prefactor (1/2)^{n_eq} (-1)^{n_h + n_loop} if non-NULL. */
+int mbpt_diagram_matrix(int order, int id, int *M, double *prefactor);
+/* Label-sum statistics of a diagram: nonzero spin (NEUTRON) or spin-isospin
+ * (NUCLEAR) label assignments, distinct isospin configurations consistent
+ * with isospin conservation at every vertex, and compressed terms stored. */
+int mbpt_diagram_label_stats(int order, int id, int matter, int *n_assign, int *n_isospin,
+                             int *n_terms);
+
+/* ---- task sets ------------------------------------------------------------ */
+/* Create a set of tasks (copied).  EINVAL on an unknown diagram, order outside
+ * 1..5, density <= 0, proton fraction outside [0,1], or NEUTRON with x != 0. */
+int mbpt_create_task_set(mbpt_context *ctx, const mbpt_task_desc *tasks, int n_tasks,
+                         mbpt_task_set **out);
+/* Convenience: the listed diagrams of one order (ids NULL = all) at density
+ * 0.16 fm^-3, x = 0, task_key = position in the list. */
+int mbpt_create_diagram_set(mbpt_context *ctx, int order, const int *ids, int n_ids, int matter,
+                            mbpt_task_set **out);
+void mbpt_task_set_destroy(mbpt_task_set *set);
+int mbpt_task_count(const mbpt_task_set *set, int *n);
+/* Move every task of the set to a new density [fm^-3] or proton fraction; the
+ * grids are kept (warm start). */
+int mbpt_set_density(mbpt_task_set *set, double density);
+int mbpt_set_asymmetry(mbpt_task_set *set, double proton_fraction);
+int mbpt_set_launch_mode(mbpt_task_set *set, int mode);
+/* Work decomposition: threads per block (64..1024, multiple of 64) and samples
+ * per thread per work item (1..256).  Defaults 256 and 16. */
+int mbpt_set_blocking(mbpt_task_set *set, int threads_per_block, int samples_per_thread);
+
+/* Device workspace bytes needed for up to max_samples_per_iter samples per
+ * task and iteration and up to max_iters stored per-iteration estimates. */
+int mbpt_workspace_query(const mbpt_task_set *set, uint64_t max_samples_per_iter, int max_iters,
+                         size_t *bytes);
+/* Bind caller-owned device memory (256-byte aligned, >= the queried size for
+ * the limits passed to the query).  Uploads descriptors and resets every grid
+ * to uniform and every task to iteration 0.  ENOMEM if too small. */
+int mbpt_bind_workspace(mbpt_task_set *set, void *device_ptr, size_t bytes,
+                        uint64_t max_samples_per_iter, int max_iters);
+/* Reset grids to uniform and iteration counters / sums to zero. */
+int mbpt_reset(mbpt_task_set *set);
+
+/* ---- integration ---------------------------------------------------------- */
+/* Run `iters` VEGAS iterations of samples_per_iter samples for every task,
+ * continuing from the current grids and iteration counters (so repeated calls
+ * resume exactly).  Blocks until done.  per_task[n_tasks] receives the
+ * cumulative result of each task (may be NULL); total (may be NULL) receives
+ * the sum over tasks (sigmas in quadrature).  ESTATE without a workspace,
+ * ENOMEM if samples_per_iter or the iteration count exceeds the bound limits,
+ * ENUMERIC on a non-finite estimate. */
+int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int iters,
+                   mbpt_result *per_task, mbpt_result *total);
+/* Per-iteration estimates of a task: I[k], var[k] for the iterations stored
+ * so far (at most max_iters); *count receives how many were written. */
+int mbpt_iteration_log(mbpt_task_set *set, int task, double *I, double *var, int cap,
+                       int *count);
+/* Integrand weights (Jacobian included) of samples [first, first+count) of
+ * iteration `iter` of one task with its current grid, written to host memory.
+ * For per-sample parity checks. */
+int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, uint64_t first,
+                      uint64_t count, double *w_host);
+/* Grid of a task (ndim x (n_bins+1) edges, host memory) for checkpointing,
+ * and its restore.  ndim = 3 (order + 1). */
+int mbpt_get_grid(mbpt_task_set *set, int task, double *edges_host);
+int mbpt_set_grid(mbpt_task_set *set, int task, const double *edges_host);
+
+/* Timing of the sample kernels since the last call (HIP events on the
+ * context stream): launches, total kernel milliseconds, samples evaluated,
+ * and algorithmic FLOPs per evaluation counted from the descriptors (FMA = 2,
+ * add/mul = 1, each exp/sqrt/sincos/division = 1). */
+int mbpt_kernel_stats(mbpt_context *ctx, uint64_t *launches, double *kernel_ms,
+                      uint64_t *evals, double *flops);
+/* Algorithmic FLOPs and transcendental count per evaluation of a task. */
+int mbpt_task_flops(const mbpt_task_set *set, int task, double *flops, double *transcendentals);
+
+/* ---- serving: continuous batching of EOS-point requests ------------------ */
+/* A server owns one device workspace (caller-owned, size from
+ * mbpt_server_workspace_query) holding up to max_slots resident tasks.
+ * Requests queue on submit; mbpt_server_step admits queued requests into free
+ * slots (by slot count and workspace bytes), runs one VEGAS iteration for
+ * every resident task in one persistent launch, and retires tasks whose sigma
+ * reached max(sigma_rel |E|, sigma_abs) or whose evaluations reached
+ * max_evals.  A request's random stream is keyed by its ticket, so its result
+ * does not depend on what else is resident. */
+typedef struct mbpt_request {
+  int order;
+  int diagram_id;
+  int matter;
+  double density;
+  double proton_fraction;
+  double sigma_rel;
+  double sigma_abs;
+  uint64_t samples_per_iter;
+  uint64_t max_evals;
+} mbpt_request;
+
+int mbpt_server_workspace_query(const mbpt_context *ctx, int max_slots,
+                                uint64_t max_samples_per_iter, size_t *bytes);
+int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max_samples_per_iter,
+                       int max_queue, void *device_ptr, size_t bytes, mbpt_server **out);
+void mbpt_server_destroy(mbpt_server *srv);
+/* Queue a request; *ticket identifies it.  EBUSY if the queue is full. */
+int mbpt_server_submit(mbpt_server *srv, const mbpt_request *req, uint64_t *ticket);
+/* One scheduling round (admit, one iteration for all resident tasks, retire).
+ * *n_active receives the resident count after the round, *n_queued the queue
+ * length. */
+int mbpt_server_step(mbpt_server *srv, int *n_active, int *n_queued);
+/* Result of a ticket: *done = 1 once retired (result valid), else 0 (result
+ * holds the running estimate if resident).  Times are host wall-clock seconds
+ * from the server's creation: submit, admit and finish. */
+int mbpt_server_poll(mbpt_server *srv, uint64_t ticket, mbpt_result *res, int *done,
+                     double *t_submit, double *t_admit, double *t_finish);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBPT_VEGAS_H */

@@ -1,0 +1,384 @@
+"""MI355X (gfx950) VEGAS Monte Carlo for MBPT energy diagrams of nucleon matter.
+
+Thin ctypes binding of ``libmbpt_vegas.so`` (see ``include/mbpt_vegas.h``).
+Every ``mbpt_*`` function here has the C entry point's name and arguments and
+only marshals them; all work runs in the library's HIP kernels.  PyTorch is
+used for two things only: the device workspace (a uint8 tensor) and the HIP
+stream the library queues on.  The package fails loudly if the library is
+missing: there is no fallback path.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbpt_vegas.so")
+
+MBPT_OK, MBPT_EINVAL, MBPT_ENOMEM, MBPT_EHIP, MBPT_ENUMERIC, MBPT_EBUSY, MBPT_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6)
+MBPT_FP64, MBPT_FP32 = 0, 1
+MBPT_NEUTRON, MBPT_NUCLEAR = 0, 1
+MBPT_LAUNCH_PER_TASK, MBPT_LAUNCH_BATCHED, MBPT_LAUNCH_GRAPH = 0, 1, 2
+
+EXPORTED = [
+    "mbpt_context_create", "mbpt_context_destroy", "mbpt_last_error", "mbpt_set_interaction",
+    "mbpt_set_precision", "mbpt_num_diagrams", "mbpt_diagram_matrix", "mbpt_diagram_label_stats",
+    "mbpt_create_task_set", "mbpt_create_diagram_set", "mbpt_task_set_destroy", "mbpt_task_count",
+    "mbpt_set_density", "mbpt_set_asymmetry", "mbpt_set_launch_mode", "mbpt_set_blocking",
+    "mbpt_workspace_query", "mbpt_bind_workspace", "mbpt_reset", "mbpt_integrate",
+    "mbpt_iteration_log", "mbpt_dump_samples", "mbpt_get_grid", "mbpt_set_grid",
+    "mbpt_kernel_stats", "mbpt_task_flops", "mbpt_server_workspace_query", "mbpt_server_create",
+    "mbpt_server_destroy", "mbpt_server_submit", "mbpt_server_step", "mbpt_server_poll",
+]
+
+
+class mbpt_interaction(ctypes.Structure):
+    _fields_ = [("C0", ctypes.c_double), ("Cy", ctypes.c_double), ("mpi", ctypes.c_double),
+                ("Lambda", ctypes.c_double), ("reg_exp", ctypes.c_int),
+                ("hbar2_m", ctypes.c_double), ("hbarc", ctypes.c_double)]
+
+
+class mbpt_context_desc(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("precision", ctypes.c_int), ("seed", ctypes.c_uint32),
+                ("n_bins", ctypes.c_int), ("alpha", ctypes.c_double),
+                ("kcut_extra", ctypes.c_double), ("fp32_band_k", ctypes.c_double),
+                ("fp32_band_d", ctypes.c_double)]
+
+
+class mbpt_task_desc(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("diagram_id", ctypes.c_int), ("matter", ctypes.c_int),
+                ("density", ctypes.c_double), ("proton_fraction", ctypes.c_double),
+                ("task_key", ctypes.c_uint32)]
+
+
+class mbpt_result(ctypes.Structure):
+    _fields_ = [("E_per_A", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("chi2_dof", ctypes.c_double), ("last_E", ctypes.c_double),
+                ("last_sigma", ctypes.c_double), ("iters_done", ctypes.c_int),
+                ("n_evals", ctypes.c_uint64), ("n_fp64_fallback", ctypes.c_uint64)]
+
+
+class mbpt_request(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("diagram_id", ctypes.c_int), ("matter", ctypes.c_int),
+                ("density", ctypes.c_double), ("proton_fraction", ctypes.c_double),
+                ("sigma_rel", ctypes.c_double), ("sigma_abs", ctypes.c_double),
+                ("samples_per_iter", ctypes.c_uint64), ("max_evals", ctypes.c_uint64)]
+
+
+class MbptError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mbpt error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    """Load libmbpt_vegas.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2603_24532_amd.build` (no fallback path exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "mbpt_context_create": [ctypes.POINTER(mbpt_context_desc), ctypes.POINTER(_P)],
+        "mbpt_context_destroy": [_P],
+        "mbpt_last_error": [_P],
+        "mbpt_set_interaction": [_P, ctypes.POINTER(mbpt_interaction)],
+        "mbpt_set_precision": [_P, ctypes.c_int],
+        "mbpt_num_diagrams": [ctypes.c_int, _IP],
+        "mbpt_diagram_matrix": [ctypes.c_int, ctypes.c_int, _IP, _DP],
+        "mbpt_diagram_label_stats": [ctypes.c_int, ctypes.c_int, ctypes.c_int, _IP, _IP, _IP],
+        "mbpt_create_task_set": [_P, ctypes.POINTER(mbpt_task_desc), ctypes.c_int,
+                                 ctypes.POINTER(_P)],
+        "mbpt_create_diagram_set": [_P, ctypes.c_int, _IP, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(_P)],
+        "mbpt_task_set_destroy": [_P],
+        "mbpt_task_count": [_P, _IP],
+        "mbpt_set_density": [_P, ctypes.c_double],
+        "mbpt_set_asymmetry": [_P, ctypes.c_double],
+        "mbpt_set_launch_mode": [_P, ctypes.c_int],
+        "mbpt_set_blocking": [_P, ctypes.c_int, ctypes.c_int],
+        "mbpt_workspace_query": [_P, ctypes.c_uint64, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_size_t)],
+        "mbpt_bind_workspace": [_P, _P, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int],
+        "mbpt_reset": [_P],
+        "mbpt_integrate": [_P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(mbpt_result),
+                           ctypes.POINTER(mbpt_result)],
+        "mbpt_iteration_log": [_P, ctypes.c_int, _DP, _DP, ctypes.c_int, _IP],
+        "mbpt_dump_samples": [_P, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
+                              ctypes.c_uint64, _DP],
+        "mbpt_get_grid": [_P, ctypes.c_int, _DP],
+        "mbpt_set_grid": [_P, ctypes.c_int, _DP],
+        "mbpt_kernel_stats": [_P, ctypes.POINTER(ctypes.c_uint64), _DP,
+                              ctypes.POINTER(ctypes.c_uint64), _DP],
+        "mbpt_task_flops": [_P, ctypes.c_int, _DP, _DP],
+        "mbpt_server_workspace_query": [_P, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_size_t)],
+        "mbpt_server_create": [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, _P,
+                               ctypes.c_size_t, ctypes.POINTER(_P)],
+        "mbpt_server_destroy": [_P],
+        "mbpt_server_submit": [_P, ctypes.POINTER(mbpt_request), ctypes.POINTER(ctypes.c_uint64)],
+        "mbpt_server_step": [_P, _IP, _IP],
+        "mbpt_server_poll": [_P, ctypes.c_uint64, ctypes.POINTER(mbpt_result), _IP, _DP, _DP,
+                             _DP],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.mbpt_context_destroy.restype = None
+    L.mbpt_task_set_destroy.restype = None
+    L.mbpt_server_destroy.restype = None
+    L.mbpt_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc, ctx=None):
+    if rc != MBPT_OK:
+        msg = lib().mbpt_last_error(ctx).decode() if ctx else ""
+        raise MbptError(rc, msg)
+
+
+def _ctx_of_set(s):
+    return _set_ctx.get(s)
+
+
+_set_ctx = {}
+_srv_ctx = {}
+
+
+# --------------------------------------------------------------------------
+# Same-name wrappers (argument marshalling only)
+
+def mbpt_context_create(device=0, stream=None, precision=MBPT_FP64, seed=1, n_bins=50,
+                        alpha=1.5, kcut_extra=3.0, fp32_band_k=1e-4, fp32_band_d=1e-2):
+    d = mbpt_context_desc(device, stream, precision, seed, n_bins, alpha, kcut_extra,
+                          fp32_band_k, fp32_band_d)
+    h = _P()
+    _check(lib().mbpt_context_create(ctypes.byref(d), ctypes.byref(h)))
+    return h.value
+
+
+def mbpt_context_destroy(ctx):
+    lib().mbpt_context_destroy(ctx)
+
+
+def mbpt_last_error(ctx):
+    return lib().mbpt_last_error(ctx).decode()
+
+
+def mbpt_set_interaction(ctx, C0=-1.0, Cy=-2.0, mpi=0.7, Lambda=2.0, reg_exp=4, hbar2_m=41.47,
+                         hbarc=197.3269804):
+    v = mbpt_interaction(C0, Cy, mpi, Lambda, reg_exp, hbar2_m, hbarc)
+    _check(lib().mbpt_set_interaction(ctx, ctypes.byref(v)), ctx)
+
+
+def mbpt_set_precision(ctx, precision):
+    _check(lib().mbpt_set_precision(ctx, precision), ctx)
+
+
+def mbpt_num_diagrams(order):
+    n = ctypes.c_int()
+    _check(lib().mbpt_num_diagrams(order, ctypes.byref(n)))
+    return n.value
+
+
+def mbpt_diagram_matrix(order, did):
+    M = (ctypes.c_int * (order * order))()
+    pref = ctypes.c_double()
+    _check(lib().mbpt_diagram_matrix(order, did, M, ctypes.byref(pref)))
+    return [[M[u * order + v] for v in range(order)] for u in range(order)], pref.value
+
+
+def mbpt_diagram_label_stats(order, did, matter):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().mbpt_diagram_label_stats(order, did, matter, ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def mbpt_create_task_set(ctx, tasks):
+    """tasks: list of (order, diagram_id, matter, density, proton_fraction, task_key)."""
+    arr = (mbpt_task_desc * len(tasks))(*[mbpt_task_desc(*t) for t in tasks])
+    h = _P()
+    _check(lib().mbpt_create_task_set(ctx, arr, len(tasks), ctypes.byref(h)), ctx)
+    _set_ctx[h.value] = ctx
+    return h.value
+
+
+def mbpt_create_diagram_set(ctx, order, ids=None, matter=MBPT_NEUTRON):
+    h = _P()
+    if ids is None:
+        rc = lib().mbpt_create_diagram_set(ctx, order, None, 0, matter, ctypes.byref(h))
+    else:
+        arr = (ctypes.c_int * len(ids))(*ids)
+        rc = lib().mbpt_create_diagram_set(ctx, order, arr, len(ids), matter, ctypes.byref(h))
+    _check(rc, ctx)
+    _set_ctx[h.value] = ctx
+    return h.value
+
+
+def mbpt_task_set_destroy(s):
+    _set_ctx.pop(s, None)
+    lib().mbpt_task_set_destroy(s)
+
+
+def mbpt_task_count(s):
+    n = ctypes.c_int()
+    _check(lib().mbpt_task_count(s, ctypes.byref(n)), _ctx_of_set(s))
+    return n.value
+
+
+def mbpt_set_density(s, density):
+    _check(lib().mbpt_set_density(s, density), _ctx_of_set(s))
+
+
+def mbpt_set_asymmetry(s, x):
+    _check(lib().mbpt_set_asymmetry(s, x), _ctx_of_set(s))
+
+
+def mbpt_set_launch_mode(s, mode):
+    _check(lib().mbpt_set_launch_mode(s, mode), _ctx_of_set(s))
+
+
+def mbpt_set_blocking(s, threads_per_block, samples_per_thread):
+    _check(lib().mbpt_set_blocking(s, threads_per_block, samples_per_thread), _ctx_of_set(s))
+
+
+def mbpt_workspace_query(s, max_samples_per_iter, max_iters):
+    b = ctypes.c_size_t()
+    _check(lib().mbpt_workspace_query(s, max_samples_per_iter, max_iters, ctypes.byref(b)),
+           _ctx_of_set(s))
+    return b.value
+
+
+def mbpt_bind_workspace(s, device_ptr, nbytes, max_samples_per_iter, max_iters):
+    _check(lib().mbpt_bind_workspace(s, device_ptr, nbytes, max_samples_per_iter, max_iters),
+           _ctx_of_set(s))
+
+
+def mbpt_reset(s):
+    _check(lib().mbpt_reset(s), _ctx_of_set(s))
+
+
+def mbpt_integrate(s, samples_per_iter, iters):
+    """Returns (per-task results list, total result)."""
+    n = mbpt_task_count(s)
+    per = (mbpt_result * n)()
+    tot = mbpt_result()
+    _check(lib().mbpt_integrate(s, samples_per_iter, iters, per, ctypes.byref(tot)),
+           _ctx_of_set(s))
+    return list(per), tot
+
+
+def mbpt_iteration_log(s, task, cap=1024):
+    I = (ctypes.c_double * cap)()
+    V = (ctypes.c_double * cap)()
+    n = ctypes.c_int()
+    _check(lib().mbpt_iteration_log(s, task, I, V, cap, ctypes.byref(n)), _ctx_of_set(s))
+    return list(I[:n.value]), list(V[:n.value])
+
+
+def mbpt_dump_samples(s, task, it, first, count):
+    import numpy as np
+    out = np.empty(count, dtype=np.float64)
+    _check(lib().mbpt_dump_samples(s, task, it, first, count,
+                                   out.ctypes.data_as(_DP)), _ctx_of_set(s))
+    return out
+
+
+def mbpt_get_grid(s, task, ndim, n_bins=50):
+    import numpy as np
+    out = np.empty(ndim * (n_bins + 1), dtype=np.float64)
+    _check(lib().mbpt_get_grid(s, task, out.ctypes.data_as(_DP)), _ctx_of_set(s))
+    return out
+
+
+def mbpt_set_grid(s, task, edges):
+    import numpy as np
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    _check(lib().mbpt_set_grid(s, task, e.ctypes.data_as(_DP)), _ctx_of_set(s))
+
+
+def mbpt_kernel_stats(ctx):
+    a, c = ctypes.c_uint64(), ctypes.c_uint64()
+    b, d = ctypes.c_double(), ctypes.c_double()
+    _check(lib().mbpt_kernel_stats(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                   ctypes.byref(d)), ctx)
+    return dict(launches=a.value, kernel_ms=b.value, evals=c.value, flops=d.value)
+
+
+def mbpt_task_flops(s, task):
+    f, t = ctypes.c_double(), ctypes.c_double()
+    _check(lib().mbpt_task_flops(s, task, ctypes.byref(f), ctypes.byref(t)), _ctx_of_set(s))
+    return f.value, t.value
+
+
+def mbpt_server_workspace_query(ctx, max_slots, max_samples_per_iter):
+    b = ctypes.c_size_t()
+    _check(lib().mbpt_server_workspace_query(ctx, max_slots, max_samples_per_iter,
+                                             ctypes.byref(b)), ctx)
+    return b.value
+
+
+def mbpt_server_create(ctx, max_slots, max_samples_per_iter, max_queue, device_ptr, nbytes):
+    h = _P()
+    _check(lib().mbpt_server_create(ctx, max_slots, max_samples_per_iter, max_queue, device_ptr,
+                                    nbytes, ctypes.byref(h)), ctx)
+    _srv_ctx[h.value] = ctx
+    return h.value
+
+
+def mbpt_server_destroy(srv):
+    _srv_ctx.pop(srv, None)
+    lib().mbpt_server_destroy(srv)
+
+
+def mbpt_server_submit(srv, order, diagram_id, matter, density, proton_fraction, sigma_rel,
+                       sigma_abs, samples_per_iter, max_evals):
+    r = mbpt_request(order, diagram_id, matter, density, proton_fraction, sigma_rel, sigma_abs,
+                     samples_per_iter, max_evals)
+    t = ctypes.c_uint64()
+    _check(lib().mbpt_server_submit(srv, ctypes.byref(r), ctypes.byref(t)), _srv_ctx.get(srv))
+    return t.value
+
+
+def mbpt_server_step(srv):
+    a, q = ctypes.c_int(), ctypes.c_int()
+    _check(lib().mbpt_server_step(srv, ctypes.byref(a), ctypes.byref(q)), _srv_ctx.get(srv))
+    return a.value, q.value
+
+
+def mbpt_server_poll(srv, ticket):
+    r = mbpt_result()
+    done = ctypes.c_int()
+    ts, ta, tf = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().mbpt_server_poll(srv, ticket, ctypes.byref(r), ctypes.byref(done),
+                                  ctypes.byref(ts), ctypes.byref(ta), ctypes.byref(tf)),
+           _srv_ctx.get(srv))
+    return r, bool(done.value), ts.value, ta.value, tf.value
+
+
+# --------------------------------------------------------------------------
+# Device memory and stream from PyTorch
+
+def device_workspace(nbytes, device=0):
+    """A caller-owned device buffer for mbpt_bind_workspace (256-byte aligned)."""
+    import torch
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=f"cuda:{device}")
+    ptr = t.data_ptr()
+    aligned = (ptr + 255) & ~255
+    return t, aligned
+
+
+def current_stream(device=0):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream).value

@@ -1,0 +1,99 @@
+// Device-side tables shared by the kernels and the host runtime that fills
+// them.  Everything lives in the caller-bound workspace.
+#pragma once
+#include <cstdint>
+
+namespace mbpt {
+
+constexpr int kMaxBins = 128;
+constexpr int kBlockMax = 1024;
+
+// Compiled diagram (read wave-uniformly through the scalar cache).
+struct alignas(16) DiagDev {
+  int order, nlines, nloops, ncuts;
+  int group_off, ngroups, term_off, nterms;
+  int loop_part[8];       // 1 if loop j is carried by a particle line
+  uint32_t part_mask;     // bit l: line l is a particle line
+  uint32_t line_mask;     // bits of all lines
+  int pad[2];
+  double pref;            // (1/2)^{n_eq} (-1)^{n_h + n_loop} (2 pi)^{-3L}
+  double pad0;
+  double lc[10][6];       // line l momentum = sum_j lc[l][j] k_j
+  double vp[5][6];        // vertex v: p  = (k_o1 - k_o2)/2 = sum_j vp[v][j] k_j
+  double vq[5][6];        // vertex v: p' = (k_i1 - k_i2)/2 = sum_j vq[v][j] k_j
+  double cutc[4][10];     // D_c = sum_l cutc[c][l] eps_l  (+1 hole, -1 particle)
+};
+
+// Isospin configuration: lines whose bit is set carry protons.
+struct alignas(16) GroupDev {
+  uint32_t tau;
+  int first, count, pad;
+};
+
+// Compressed label-sum term: multiplicity and 2-bit vertex codes
+// (0: V_d, 1: -V_e, 2: V_d - V_e).
+struct alignas(16) TermDev {
+  double mult;
+  uint32_t codes;
+  uint32_t pad;
+};
+
+// Interaction and medium constants common to a launch.
+struct Phys {
+  double V0;        // C0 * hbarc      [MeV fm^3]
+  double Vy;        // Cy * hbarc      [MeV fm^3 * fm^-2]
+  double m2;        // mpi^2
+  double invLn;     // Lambda^{-reg_exp}
+  double hb2m;      // hbar^2 / 2m
+  int half_exp;     // reg_exp / 2
+  int nb;           // bins per dimension
+  uint32_t seed;
+  int pad;
+};
+
+// One task: parameters (host-written) and running state (device-written).
+struct alignas(16) TaskDev {
+  int diag, nd, grid_off, hist_off;
+  int item_begin, nitems, res_off, res_cap;
+  uint32_t key;
+  int order;
+  uint64_t nsamples;
+  double kF2[2];        // neutron, proton kF^2
+  double Rh, Rp;        // loop radii for hole / particle loop lines
+  double inv_density;
+  double band_k, band_d;
+  int active;
+  int pad;
+  // state (written by the device)
+  uint32_t iter;        // Philox iteration word of the next iteration
+  int it_done;
+  double shift;
+  double wsum, wisum, wi2sum, zsum;
+  int nzero;
+  int pad2;
+  double lastI, lastV;
+  uint64_t nevals, nfallback, npass, nterms;
+};
+
+// Per work item counters: fp64 fallbacks, samples past the Pauli test, label
+// terms evaluated.
+constexpr int kItemCounters = 3;
+
+struct KArgs {
+  TaskDev *tasks;
+  const DiagDev *diags;
+  const GroupDev *groups;
+  const TermDev *terms;
+  double *grids;
+  double *hists;
+  double *partials;       // 4 doubles per work item
+  uint64_t *counters;     // kItemCounters per work item
+  double *reslog;         // (I, var) pairs
+  int ntasks;
+  int total_items;
+  int spt;                // samples per thread per item
+  int pad;
+  Phys phys;
+};
+
+}  // namespace mbpt

@@ -1,0 +1,60 @@
+// Diagram generator and descriptor compiler (host side).
+//
+// Two-body Hugenholtz energy diagrams of order n (Table I of arXiv:2603.24532:
+// 1, 1, 3, 39, 840 diagrams for n = 1..5) are enumerated as n x n line-count
+// matrices; each is compiled into the tables the sample kernels read:
+// line momenta as +-1 combinations of loop momenta, vertex relative momenta,
+// energy-denominator cuts, prefactor, and the list of nonzero spin(-isospin)
+// label assignments compressed into (isospin pattern, vertex term codes,
+// multiplicity) terms.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace mbpt {
+
+constexpr int kMaxOrder = 5;
+constexpr int kMaxLines = 2 * kMaxOrder;
+constexpr int kMaxLoops = kMaxOrder + 1;
+constexpr int kMaxCuts = kMaxOrder - 1;
+constexpr int kMaxDim = 3 * kMaxLoops;
+
+struct Diagram {
+  int order = 0, id = 0;
+  int M[kMaxOrder][kMaxOrder] = {};
+  int nlines = 0, nloops = 0, ncuts = 0, ndim = 0;
+  int tail[kMaxLines] = {}, head[kMaxLines] = {};
+  bool particle[kMaxLines] = {};
+  int vout[kMaxOrder][2] = {}, vin[kMaxOrder][2] = {};  // <o1 o2|V|i1 i2>
+  int loop_line[kMaxLoops] = {};
+  int coef[kMaxLines][kMaxLoops] = {};  // k_line = sum_j coef[line][j] k_loop(j)
+  int cut[kMaxCuts][kMaxLines] = {};    // +1 hole crosses, -1 particle crosses
+  int n_eq = 0, n_h = 0, n_cycles = 0;
+  double prefactor = 0.0;
+};
+
+// Vertex term codes of one label assignment: the antisymmetrised matrix
+// element <o1 o2|V(1-P12)|i1 i2> with labels is V_d [o1=i1][o2=i2] -
+// V_e [o1=i2][o2=i1]; code 0 = V_d only, 1 = -V_e only, 2 = V_d - V_e.
+struct LabelTerm {
+  uint32_t tau_mask;  // bit l: line l carries a proton label
+  uint32_t codes;     // 2 bits per vertex
+  int mult;           // number of label assignments with this pattern
+};
+
+struct LabelList {
+  int n_assign = 0;    // nonzero label assignments
+  int n_isospin = 0;   // distinct isospin configurations among them
+  std::vector<LabelTerm> terms;  // sorted by tau_mask, then codes
+};
+
+// Number of diagrams of an order (1..5), or -1.
+int num_diagrams(int order);
+// Diagram `id` of an order (ids follow the lexicographic order of the
+// row-major matrix digits).  Returns nullptr if out of range.
+const Diagram *get_diagram(int order, int id);
+// q = 2: spin labels (neutron matter); q = 4: spin x isospin, label bit 1 is
+// the isospin (0 neutron, 1 proton).
+LabelList build_labels(const Diagram &d, int q);
+
+}  // namespace mbpt

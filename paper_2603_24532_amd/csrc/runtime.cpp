@@ -1,0 +1,870 @@
+// Host runtime and C ABI of the MI355X VEGAS library for MBPT energy
+// diagrams.  See include/mbpt_vegas.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "diagrams.hpp"
+#include "device_types.hpp"
+#include "kernels.hpp"
+#include "mbpt_vegas.h"
+#include "runtime.hpp"
+
+using namespace mbpt;
+
+namespace mbpt {
+
+void set_err(mbpt_context *ctx, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+}
+
+int hip_fail(mbpt_context *ctx, hipError_t e, const char *what) {
+  set_err(ctx, std::string(what) + ": " + hipGetErrorString(e));
+  return MBPT_EHIP;
+}
+
+#define HIPCHK(ctx, call)                                \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Algorithmic FLOPs of one evaluation, counted from the descriptor:
+// FMA = 2, add/mul = 1, each exp / sqrt / sin / cos / division = 1 (also
+// tallied separately).  Split into the part every sample needs (map, loop
+// momenta, line momenta, Pauli tests), the part a sample past the Pauli test
+// needs (denominators, matrix elements, weight, accumulation) and the part
+// per label term evaluated.
+void count_flops(const Diagram &d, int q, int half_exp, FlopModel &f) {
+  const int n = d.order, L = d.nloops, NL = d.nlines, NC = d.ncuts, ND = d.ndim;
+  double pre = 0, pre_t = 0;
+  pre += 6.0 * ND;                  // bin fraction (2), x = e + r w (2), jacobian (2)
+  pre += 13.0 * L;                  // radius, cos, sin theta, k components, jacobian
+  pre_t += 3.0 * L;                 // sqrt, sin, cos
+  for (int l = 0; l < NL; ++l) {
+    int nnz = 0;
+    for (int j = 0; j < L; ++j) nnz += d.coef[l][j] != 0;
+    pre += 3.0 * std::max(0, nnz - 1);  // tree-line sums
+    pre += 5.0 + 1.0;                    // k^2, eps
+    pre += (q == 4) ? 2.0 : 1.0;         // occupation tests
+  }
+  double post = 0, post_t = 0;
+  for (int c = 0; c < NC; ++c) {
+    int nnz = 0;
+    for (int l = 0; l < NL; ++l) nnz += d.cut[c][l] != 0;
+    post += nnz - 1;
+  }
+  post += std::max(0, NC - 1);  // product of denominators
+  // per vertex: p, p' (6 + 6), p^2, p'^2, p.p' (15), powers, exponent (2),
+  // q^2 +- (4 + 2), C0 + (2), regulator products (2), V_d - V_e (1)
+  post += n * (6 + 6 + 15 + 2.0 * (half_exp - 1) + 2 + 6 + 2 + 2 + 1);
+  post_t += n * 3.0;            // exp and two divisions
+  post += 3.0;                  // weight: jacobian * prefactor * label sum
+  post_t += 1.0;                // one division by the denominators
+  post_t += (NC == 0) ? -1.0 : 0.0;
+  double acc = 10.0 + 1.0 + ND; // shifted sums (Neumaier), w^2, histogram adds
+  f.pre = pre + pre_t + acc;    // every sample is accumulated
+  f.post = post + post_t;
+  f.per_term = n + 1.0;         // product of n factors, multiply-add with multiplicity
+  f.all_terms = 0.0;
+  f.transc_pre = pre_t;
+  f.transc_post = post_t;
+}
+
+}  // namespace mbpt
+
+// ---------------------------------------------------------------------------
+// Context
+
+extern "C" int mbpt_context_create(const mbpt_context_desc *desc, mbpt_context **out) {
+  if (!out) return MBPT_EINVAL;
+  *out = nullptr;
+  mbpt_context_desc d{};
+  d.device = 0;
+  d.stream = nullptr;
+  d.precision = MBPT_FP64;
+  d.seed = 1;
+  d.n_bins = 50;
+  d.alpha = 1.5;
+  d.kcut_extra = 3.0;
+  d.fp32_band_k = 1e-4;
+  d.fp32_band_d = 1e-2;
+  if (desc) d = *desc;
+  if (d.n_bins < 2 || d.n_bins > kMaxBins || !(d.alpha > 0.0) || !(d.kcut_extra >= 0.0) ||
+      (d.precision != MBPT_FP64 && d.precision != MBPT_FP32) || d.fp32_band_k < 0.0 ||
+      d.fp32_band_d < 0.0)
+    return MBPT_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || d.device < 0 || d.device >= ndev) return MBPT_EHIP;
+  if (hipSetDevice(d.device) != hipSuccess) return MBPT_EHIP;
+  auto *ctx = new mbpt_context();
+  ctx->desc = d;
+  ctx->stream = static_cast<hipStream_t>(d.stream);
+  ctx->v = mbpt_interaction{-1.0, -2.0, 0.7, 2.0, 4, 41.47, 197.3269804};
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, d.device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+  *out = ctx;
+  return MBPT_OK;
+}
+
+extern "C" void mbpt_context_destroy(mbpt_context *ctx) {
+  if (!ctx) return;
+  for (auto &ev : ctx->events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  delete ctx;
+}
+
+extern "C" const char *mbpt_last_error(const mbpt_context *ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+extern "C" int mbpt_set_interaction(mbpt_context *ctx, const mbpt_interaction *v) {
+  if (!ctx || !v) return MBPT_EINVAL;
+  if (v->reg_exp < 2 || v->reg_exp > 16 || (v->reg_exp & 1) || !(v->Lambda > 0) ||
+      !(v->hbar2_m > 0) || !(v->hbarc > 0) || !(v->mpi > 0)) {
+    set_err(ctx, "mbpt_set_interaction: invalid interaction parameters");
+    return MBPT_EINVAL;
+  }
+  ctx->v = *v;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_set_precision(mbpt_context *ctx, int precision) {
+  if (!ctx || (precision != MBPT_FP64 && precision != MBPT_FP32)) return MBPT_EINVAL;
+  ctx->desc.precision = precision;
+  return MBPT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Generator queries
+
+extern "C" int mbpt_num_diagrams(int order, int *count) {
+  if (!count) return MBPT_EINVAL;
+  const int n = num_diagrams(order);
+  if (n < 0) return MBPT_EINVAL;
+  *count = n;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_diagram_matrix(int order, int id, int *M, double *prefactor) {
+  const Diagram *d = get_diagram(order, id);
+  if (!d || !M) return MBPT_EINVAL;
+  for (int u = 0; u < order; ++u)
+    for (int v = 0; v < order; ++v) M[u * order + v] = d->M[u][v];
+  if (prefactor) *prefactor = d->prefactor;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_diagram_label_stats(int order, int id, int matter, int *n_assign,
+                                        int *n_isospin, int *n_terms) {
+  const Diagram *d = get_diagram(order, id);
+  if (!d || (matter != MBPT_NEUTRON && matter != MBPT_NUCLEAR)) return MBPT_EINVAL;
+  const LabelList ll = build_labels(*d, matter == MBPT_NUCLEAR ? 4 : 2);
+  if (n_assign) *n_assign = ll.n_assign;
+  if (n_isospin) *n_isospin = ll.n_isospin;
+  if (n_terms) *n_terms = static_cast<int>(ll.terms.size());
+  return MBPT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Task sets
+
+namespace mbpt {
+
+// Compile a task list's diagrams into device tables (one descriptor per
+// distinct (order, id)).
+int compile_tables(mbpt_task_set *set) {
+  mbpt_context *ctx = set->ctx;
+  const int q = set->q;
+  set->diags.clear();
+  set->groups.clear();
+  set->terms.clear();
+  set->task_diag.assign(set->tasks.size(), -1);
+  set->flops.assign(set->tasks.size(), FlopModel{});
+  std::vector<std::pair<int, int>> keys;
+  for (size_t t = 0; t < set->tasks.size(); ++t) {
+    const auto &td = set->tasks[t];
+    const std::pair<int, int> key{td.order, td.diagram_id};
+    auto it = std::find(keys.begin(), keys.end(), key);
+    if (it != keys.end()) {
+      set->task_diag[t] = static_cast<int>(it - keys.begin());
+      set->flops[t] = set->diag_flops[set->task_diag[t]];
+      continue;
+    }
+    const Diagram *d = get_diagram(td.order, td.diagram_id);
+    if (!d) {
+      set_err(ctx, "unknown diagram");
+      return MBPT_EINVAL;
+    }
+    const LabelList ll = build_labels(*d, q);
+    DiagDev dd{};
+    dd.order = d->order;
+    dd.nlines = d->nlines;
+    dd.nloops = d->nloops;
+    dd.ncuts = d->ncuts;
+    dd.group_off = static_cast<int>(set->groups.size());
+    dd.term_off = static_cast<int>(set->terms.size());
+    dd.nterms = static_cast<int>(ll.terms.size());
+    for (int j = 0; j < d->nloops; ++j) dd.loop_part[j] = d->particle[d->loop_line[j]] ? 1 : 0;
+    dd.part_mask = 0;
+    for (int l = 0; l < d->nlines; ++l)
+      if (d->particle[l]) dd.part_mask |= 1u << l;
+    dd.line_mask = (1u << d->nlines) - 1u;
+    dd.pref = d->prefactor * std::pow(2.0 * M_PI, -3.0 * d->nloops);
+    for (int l = 0; l < d->nlines; ++l)
+      for (int j = 0; j < d->nloops; ++j) dd.lc[l][j] = d->coef[l][j];
+    for (int v = 0; v < d->order; ++v)
+      for (int j = 0; j < d->nloops; ++j) {
+        dd.vp[v][j] = 0.5 * (d->coef[d->vout[v][0]][j] - d->coef[d->vout[v][1]][j]);
+        dd.vq[v][j] = 0.5 * (d->coef[d->vin[v][0]][j] - d->coef[d->vin[v][1]][j]);
+      }
+    for (int c = 0; c < d->ncuts; ++c)
+      for (int l = 0; l < d->nlines; ++l) dd.cutc[c][l] = d->cut[c][l];
+    // isospin groups: terms sorted by tau
+    for (size_t i = 0; i < ll.terms.size();) {
+      size_t j = i;
+      while (j < ll.terms.size() && ll.terms[j].tau_mask == ll.terms[i].tau_mask) ++j;
+      GroupDev g{};
+      g.tau = ll.terms[i].tau_mask;
+      g.first = static_cast<int>(set->terms.size() + i);
+      g.count = static_cast<int>(j - i);
+      set->groups.push_back(g);
+      i = j;
+    }
+    dd.ngroups = static_cast<int>(set->groups.size()) - dd.group_off;
+    for (const auto &lt : ll.terms) {
+      TermDev tm{};
+      tm.mult = lt.mult;
+      tm.codes = lt.codes;
+      set->terms.push_back(tm);
+    }
+    FlopModel fm;
+    count_flops(*d, q, ctx->v.reg_exp / 2, fm);
+    fm.all_terms = static_cast<double>(ll.terms.size());
+    set->diag_flops.push_back(fm);
+    set->diags.push_back(dd);
+    keys.push_back(key);
+    set->task_diag[t] = static_cast<int>(keys.size()) - 1;
+    set->flops[t] = fm;
+  }
+  set->max_nd = 0;
+  for (const auto &td : set->tasks) set->max_nd = std::max(set->max_nd, 3 * (td.order + 1));
+  return MBPT_OK;
+}
+
+// Host copy of the per-task parameters (the state part is device-owned).
+void fill_task_params(mbpt_task_set *set) {
+  mbpt_context *ctx = set->ctx;
+  const int nb = ctx->desc.n_bins;
+  set->h_tasks.assign(set->tasks.size(), TaskDev{});
+  int goff = 0, hoff = 0;
+  for (size_t t = 0; t < set->tasks.size(); ++t) {
+    const auto &td = set->tasks[t];
+    TaskDev &T = set->h_tasks[t];
+    const int nd = 3 * (td.order + 1);
+    T.diag = set->task_diag[t];
+    T.nd = nd;
+    T.grid_off = goff;
+    T.hist_off = hoff;
+    goff += nd * (nb + 1);
+    hoff += nd * nb;
+    T.res_off = static_cast<int>(t) * set->max_iters;
+    T.res_cap = set->max_iters;
+    T.key = td.task_key;
+    T.order = td.order;
+    const double x = td.proton_fraction;
+    const double kFn = std::cbrt(3.0 * M_PI * M_PI * ((1.0 - x) * td.density));
+    const double kFp = std::cbrt(3.0 * M_PI * M_PI * (x * td.density));
+    T.kF2[0] = kFn * kFn;
+    T.kF2[1] = kFp * kFp;
+    const double kFmax = std::max(kFn, kFp);
+    T.Rh = kFmax;
+    T.Rp = kFmax + ctx->desc.kcut_extra * ctx->v.Lambda;
+    T.inv_density = 1.0 / td.density;
+    T.band_k = ctx->desc.fp32_band_k;
+    T.band_d = ctx->desc.fp32_band_d;
+    T.active = 1;
+  }
+  set->grid_doubles = goff;
+  set->hist_doubles = hoff;
+}
+
+size_t items_for(const mbpt_task_set *set, uint64_t samples) {
+  const uint64_t chunk = static_cast<uint64_t>(set->block) * set->spt;
+  return static_cast<size_t>((samples + chunk - 1) / chunk);
+}
+
+struct Layout {
+  size_t tasks, diags, groups, terms, grids, hists, partials, counters, reslog, total;
+};
+
+Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, int nb) {
+  Layout L{};
+  size_t off = 0;
+  const size_t nt = set->tasks.size();
+  L.tasks = off;
+  off = align256(off + nt * sizeof(TaskDev));
+  L.diags = off;
+  off = align256(off + set->diags.size() * sizeof(DiagDev));
+  L.groups = off;
+  off = align256(off + std::max<size_t>(1, set->groups.size()) * sizeof(GroupDev));
+  L.terms = off;
+  off = align256(off + std::max<size_t>(1, set->terms.size()) * sizeof(TermDev));
+  size_t gd = 0, hd = 0;
+  for (const auto &td : set->tasks) {
+    gd += 3 * (td.order + 1) * (nb + 1);
+    hd += 3 * (td.order + 1) * nb;
+  }
+  L.grids = off;
+  off = align256(off + gd * sizeof(double));
+  L.hists = off;
+  off = align256(off + hd * sizeof(double));
+  const size_t items = nt * items_for(set, max_samples);
+  L.partials = off;
+  off = align256(off + items * 4 * sizeof(double));
+  L.counters = off;
+  off = align256(off + items * kItemCounters * sizeof(uint64_t));
+  L.reslog = off;
+  off = align256(off + nt * static_cast<size_t>(std::max(1, max_iters)) * 2 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+KArgs kargs_of(const mbpt_task_set *set) {
+  const mbpt_context *ctx = set->ctx;
+  KArgs a{};
+  a.tasks = set->d_tasks;
+  a.diags = set->d_diags;
+  a.groups = set->d_groups;
+  a.terms = set->d_terms;
+  a.grids = set->d_grids;
+  a.hists = set->d_hists;
+  a.partials = set->d_partials;
+  a.counters = set->d_counters;
+  a.reslog = set->d_reslog;
+  a.ntasks = static_cast<int>(set->tasks.size());
+  a.total_items = 0;
+  a.spt = set->spt;
+  const mbpt_interaction &v = ctx->v;
+  a.phys.V0 = v.C0 * v.hbarc;
+  a.phys.Vy = v.Cy * v.hbarc;
+  a.phys.m2 = v.mpi * v.mpi;
+  a.phys.invLn = std::pow(v.Lambda, -static_cast<double>(v.reg_exp));
+  a.phys.hb2m = 0.5 * v.hbar2_m;
+  a.phys.half_exp = v.reg_exp / 2;
+  a.phys.nb = ctx->desc.n_bins;
+  a.phys.seed = ctx->desc.seed;
+  return a;
+}
+
+// Upload the parameter prefix of every TaskDev (state left untouched).
+int upload_params(mbpt_task_set *set) {
+  mbpt_context *ctx = set->ctx;
+  const size_t width = offsetof(TaskDev, iter);
+  HIPCHK(ctx, hipMemcpy2DAsync(set->d_tasks, sizeof(TaskDev), set->h_tasks.data(), sizeof(TaskDev),
+                               width, set->h_tasks.size(), hipMemcpyHostToDevice, ctx->stream));
+  return MBPT_OK;
+}
+
+int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int max_iters) {
+  mbpt_context *ctx = set->ctx;
+  const int nb = ctx->desc.n_bins;
+  if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u) || max_samples < 2 || max_iters < 1) {
+    set_err(ctx, "bind_workspace: null or misaligned pointer, or bad limits");
+    return MBPT_EINVAL;
+  }
+  const Layout L = layout_of(set, max_samples, max_iters, nb);
+  if (bytes < L.total) {
+    set_err(ctx, "bind_workspace: workspace too small (" + std::to_string(bytes) + " < " +
+                     std::to_string(L.total) + ")");
+    return MBPT_ENOMEM;
+  }
+  char *base = static_cast<char *>(ptr);
+  set->ws = base;
+  set->ws_bytes = bytes;
+  set->max_samples = max_samples;
+  set->max_iters = max_iters;
+  set->max_items = set->tasks.size() * items_for(set, max_samples);
+  set->d_tasks = reinterpret_cast<TaskDev *>(base + L.tasks);
+  set->d_diags = reinterpret_cast<DiagDev *>(base + L.diags);
+  set->d_groups = reinterpret_cast<GroupDev *>(base + L.groups);
+  set->d_terms = reinterpret_cast<TermDev *>(base + L.terms);
+  set->d_grids = reinterpret_cast<double *>(base + L.grids);
+  set->d_hists = reinterpret_cast<double *>(base + L.hists);
+  set->d_partials = reinterpret_cast<double *>(base + L.partials);
+  set->d_counters = reinterpret_cast<uint64_t *>(base + L.counters);
+  set->d_reslog = reinterpret_cast<double *>(base + L.reslog);
+  fill_task_params(set);
+  HIPCHK(ctx, hipMemcpyAsync(set->d_diags, set->diags.data(), set->diags.size() * sizeof(DiagDev),
+                             hipMemcpyHostToDevice, ctx->stream));
+  if (!set->groups.empty())
+    HIPCHK(ctx, hipMemcpyAsync(set->d_groups, set->groups.data(),
+                               set->groups.size() * sizeof(GroupDev), hipMemcpyHostToDevice,
+                               ctx->stream));
+  if (!set->terms.empty())
+    HIPCHK(ctx, hipMemcpyAsync(set->d_terms, set->terms.data(), set->terms.size() * sizeof(TermDev),
+                               hipMemcpyHostToDevice, ctx->stream));
+  int rc = upload_params(set);
+  if (rc) return rc;
+  KArgs a = kargs_of(set);
+  HIPCHK(ctx, launch_init(a, static_cast<int>(set->tasks.size()), ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  set->drop_graph();
+  set->last_state.clear();
+  return MBPT_OK;
+}
+
+static hipEvent_t new_event() {
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Timing events around sample launches, resolved after the stream drains.
+void timed_begin(mbpt_context *ctx, size_t &slot) {
+  if (ctx->n_used == ctx->events.size()) ctx->events.emplace_back(new_event(), new_event());
+  slot = ctx->n_used++;
+  (void)hipEventRecord(ctx->events[slot].first, ctx->stream);
+}
+
+void timed_end(mbpt_context *ctx, size_t slot) { (void)hipEventRecord(ctx->events[slot].second, ctx->stream); }
+
+void resolve_timing(mbpt_context *ctx) {
+  for (size_t i = 0; i < ctx->n_used; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ctx->events[i].first, ctx->events[i].second) == hipSuccess)
+      ctx->kernel_ms += ms;
+    ctx->launches += 1;
+  }
+  ctx->n_used = 0;
+}
+
+void result_of(const TaskDev &S, mbpt_result &r) {
+  r = mbpt_result{};
+  r.iters_done = S.it_done;
+  r.n_evals = S.nevals;
+  r.n_fp64_fallback = S.nfallback;
+  r.last_E = S.lastI;
+  r.last_sigma = std::sqrt(std::max(0.0, S.lastV));
+  if (S.it_done == 0) return;
+  if (S.nzero > 0) {
+    r.E_per_A = S.zsum / S.nzero;
+    r.sigma = 0.0;
+    r.chi2_dof = 0.0;
+  } else {
+    r.E_per_A = S.wisum / S.wsum;
+    r.sigma = 1.0 / std::sqrt(S.wsum);
+    const double chi2 = S.wi2sum - S.wisum * S.wisum / S.wsum;
+    r.chi2_dof = S.it_done > 1 ? std::max(0.0, chi2) / (S.it_done - 1) : 0.0;
+  }
+}
+
+}  // namespace mbpt
+
+static int check_tasks(mbpt_context *ctx, const mbpt_task_desc *tasks, int n, int *q) {
+  if (!tasks || n < 1) return MBPT_EINVAL;
+  int matter = tasks[0].matter;
+  for (int i = 0; i < n; ++i) {
+    const auto &t = tasks[i];
+    if (t.matter != matter || (t.matter != MBPT_NEUTRON && t.matter != MBPT_NUCLEAR)) {
+      set_err(ctx, "task set: every task needs the same matter (NEUTRON or NUCLEAR)");
+      return MBPT_EINVAL;
+    }
+    if (!get_diagram(t.order, t.diagram_id)) {
+      set_err(ctx, "task set: unknown diagram");
+      return MBPT_EINVAL;
+    }
+    if (!(t.density > 0.0) || !(t.proton_fraction >= 0.0 && t.proton_fraction <= 1.0) ||
+        (t.matter == MBPT_NEUTRON && t.proton_fraction != 0.0)) {
+      set_err(ctx, "task set: density must be > 0, proton fraction in [0,1] (0 for NEUTRON)");
+      return MBPT_EINVAL;
+    }
+  }
+  *q = matter == MBPT_NUCLEAR ? 4 : 2;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_create_task_set(mbpt_context *ctx, const mbpt_task_desc *tasks, int n_tasks,
+                                    mbpt_task_set **out) {
+  if (!ctx || !out) return MBPT_EINVAL;
+  *out = nullptr;
+  int q = 2;
+  int rc = check_tasks(ctx, tasks, n_tasks, &q);
+  if (rc) return rc;
+  auto *set = new mbpt_task_set();
+  set->ctx = ctx;
+  set->q = q;
+  set->tasks.assign(tasks, tasks + n_tasks);
+  rc = compile_tables(set);
+  if (rc) {
+    delete set;
+    return rc;
+  }
+  *out = set;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_create_diagram_set(mbpt_context *ctx, int order, const int *ids, int n_ids,
+                                       int matter, mbpt_task_set **out) {
+  if (!ctx || !out) return MBPT_EINVAL;
+  const int nd = num_diagrams(order);
+  if (nd < 0) return MBPT_EINVAL;
+  std::vector<mbpt_task_desc> ts;
+  const int n = ids ? n_ids : nd;
+  for (int i = 0; i < n; ++i) {
+    mbpt_task_desc t{};
+    t.order = order;
+    t.diagram_id = ids ? ids[i] : i;
+    t.matter = matter;
+    t.density = 0.16;
+    t.proton_fraction = 0.0;
+    t.task_key = static_cast<uint32_t>(i);
+    ts.push_back(t);
+  }
+  if (ts.empty()) return MBPT_EINVAL;
+  return mbpt_create_task_set(ctx, ts.data(), static_cast<int>(ts.size()), out);
+}
+
+extern "C" void mbpt_task_set_destroy(mbpt_task_set *set) {
+  if (!set) return;
+  set->drop_graph();
+  delete set;
+}
+
+extern "C" int mbpt_task_count(const mbpt_task_set *set, int *n) {
+  if (!set || !n) return MBPT_EINVAL;
+  *n = static_cast<int>(set->tasks.size());
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_set_density(mbpt_task_set *set, double density) {
+  if (!set || !(density > 0.0)) return MBPT_EINVAL;
+  for (auto &t : set->tasks) t.density = density;
+  set->drop_graph();
+  if (set->ws) {
+    fill_task_params(set);
+    return upload_params(set);
+  }
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_set_asymmetry(mbpt_task_set *set, double x) {
+  if (!set || !(x >= 0.0 && x <= 1.0)) return MBPT_EINVAL;
+  if (set->q == 2 && x != 0.0) {
+    set_err(set->ctx, "set_asymmetry: neutron matter needs proton fraction 0");
+    return MBPT_EINVAL;
+  }
+  for (auto &t : set->tasks) t.proton_fraction = x;
+  set->drop_graph();
+  if (set->ws) {
+    fill_task_params(set);
+    return upload_params(set);
+  }
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_set_launch_mode(mbpt_task_set *set, int mode) {
+  if (!set || mode < MBPT_LAUNCH_PER_TASK || mode > MBPT_LAUNCH_GRAPH) return MBPT_EINVAL;
+  set->launch_mode = mode;
+  set->drop_graph();
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_set_blocking(mbpt_task_set *set, int threads_per_block, int samples_per_thread) {
+  if (!set || threads_per_block < 64 || threads_per_block > 256 || (threads_per_block % 64) ||
+      samples_per_thread < 1 || samples_per_thread > 256)
+    return MBPT_EINVAL;
+  if (set->ws && static_cast<size_t>(threads_per_block) * samples_per_thread <
+                     static_cast<size_t>(set->block) * set->spt) {
+    set_err(set->ctx, "set_blocking: smaller work items than at bind time need a larger workspace");
+    return MBPT_ESTATE;
+  }
+  set->block = threads_per_block;
+  set->spt = samples_per_thread;
+  set->drop_graph();
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_workspace_query(const mbpt_task_set *set, uint64_t max_samples_per_iter,
+                                    int max_iters, size_t *bytes) {
+  if (!set || !bytes || max_samples_per_iter < 2 || max_iters < 1) return MBPT_EINVAL;
+  *bytes = layout_of(set, max_samples_per_iter, max_iters, set->ctx->desc.n_bins).total;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_bind_workspace(mbpt_task_set *set, void *device_ptr, size_t bytes,
+                                   uint64_t max_samples_per_iter, int max_iters) {
+  if (!set) return MBPT_EINVAL;
+  return bind(set, device_ptr, bytes, max_samples_per_iter, max_iters);
+}
+
+extern "C" int mbpt_reset(mbpt_task_set *set) {
+  if (!set) return MBPT_EINVAL;
+  if (!set->ws) return MBPT_ESTATE;
+  mbpt_context *ctx = set->ctx;
+  KArgs a = kargs_of(set);
+  HIPCHK(ctx, launch_init(a, static_cast<int>(set->tasks.size()), ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  set->last_state.clear();
+  return MBPT_OK;
+}
+
+namespace mbpt {
+
+// Queue `iters` iterations of the whole set on the context stream.
+int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
+  mbpt_context *ctx = set->ctx;
+  const int nt = static_cast<int>(set->tasks.size());
+  const double alpha = ctx->desc.alpha;
+  if (set->launch_mode == MBPT_LAUNCH_PER_TASK) {
+    for (int t = 0; t < nt; ++t)
+      for (int it = 0; it < iters; ++it) {
+        size_t slot = 0;
+        if (timed) timed_begin(ctx, slot);
+        HIPCHK(ctx, launch_sample_single(a, t, set->tasks[t].order, set->q,
+                                         set->h_tasks[t].nitems, set->block, ctx->stream));
+        if (timed) timed_end(ctx, slot);
+        HIPCHK(ctx, launch_finish(a, t, 1, 3 * (set->tasks[t].order + 1), alpha, ctx->stream));
+      }
+    return MBPT_OK;
+  }
+  for (int it = 0; it < iters; ++it) {
+    size_t slot = 0;
+    if (timed) timed_begin(ctx, slot);
+    HIPCHK(ctx, launch_sample_batched(a, set->q, set->max_nd, set->grid_blocks, set->block,
+                                      ctx->stream));
+    if (timed) timed_end(ctx, slot);
+    HIPCHK(ctx, launch_finish(a, 0, nt, set->max_nd, alpha, ctx->stream));
+  }
+  return MBPT_OK;
+}
+
+int persistent_grid(mbpt_task_set *set, int total_items) {
+  mbpt_context *ctx = set->ctx;
+  int per_cu = 0;
+  const size_t lds = sample_lds_bytes(set->max_nd, ctx->desc.n_bins, set->block);
+  // occupancy of the fused kernel (register and LDS limited)
+  per_cu = batched_occupancy(set->q, set->block, lds);
+  if (per_cu < 1) per_cu = 1;
+  const int g = per_cu * std::max(1, ctx->num_cus);
+  return std::max(1, std::min(total_items, g));
+}
+
+}  // namespace mbpt
+
+extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int iters,
+                              mbpt_result *per_task, mbpt_result *total) {
+  if (!set || iters < 1 || samples_per_iter < 2) return MBPT_EINVAL;
+  mbpt_context *ctx = set->ctx;
+  if (!set->ws) {
+    set_err(ctx, "integrate: no workspace bound");
+    return MBPT_ESTATE;
+  }
+  if (samples_per_iter > set->max_samples) {
+    set_err(ctx, "integrate: samples_per_iter exceeds the bound limit");
+    return MBPT_ENOMEM;
+  }
+  const int nt = static_cast<int>(set->tasks.size());
+  // work items
+  int item = 0;
+  const int per = static_cast<int>(items_for(set, samples_per_iter));
+  if (static_cast<size_t>(per) * nt > set->max_items) {
+    set_err(ctx, "integrate: more work items than the workspace holds");
+    return MBPT_ENOMEM;
+  }
+  bool changed = false;
+  for (int t = 0; t < nt; ++t) {
+    TaskDev &T = set->h_tasks[t];
+    changed |= T.item_begin != item || T.nitems != per || T.nsamples != samples_per_iter;
+    T.item_begin = item;
+    T.nitems = per;
+    T.nsamples = samples_per_iter;
+    item += per;
+  }
+  if (changed) {
+    set->drop_graph();
+    int rc = upload_params(set);
+    if (rc) return rc;
+  }
+  KArgs a = kargs_of(set);
+  a.total_items = item;
+  set->grid_blocks = persistent_grid(set, item);
+  uint64_t evals_before = 0;
+  {
+    int rc = 0;
+    if (set->launch_mode == MBPT_LAUNCH_GRAPH) {
+      if (ctx->stream == nullptr) {
+        set_err(ctx, "integrate: GRAPH launch mode needs a non-default stream to capture on");
+        return MBPT_EINVAL;
+      }
+      if (!set->graph_exec || set->graph_iters != iters) {
+        set->drop_graph();
+        hipGraph_t graph = nullptr;
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_iterations(set, a, iters, false);
+        hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&set->graph_exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
+        set->graph_iters = iters;
+      }
+      size_t slot = 0;
+      timed_begin(ctx, slot);
+      HIPCHK(ctx, hipGraphLaunch(set->graph_exec, ctx->stream));
+      timed_end(ctx, slot);
+    } else {
+      rc = enqueue_iterations(set, a, iters, true);
+      if (rc) return rc;
+    }
+  }
+  (void)evals_before;
+  std::vector<TaskDev> st(nt);
+  HIPCHK(ctx, hipMemcpyAsync(st.data(), set->d_tasks, nt * sizeof(TaskDev), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  resolve_timing(ctx);
+  // FLOP accounting from the device counters of this call
+  uint64_t evals = 0;
+  double flops = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const TaskDev &S = st[t];
+    const TaskDev &P = set->last_state.empty() ? TaskDev{} : set->last_state[t];
+    const uint64_t de = S.nevals - P.nevals, dp = S.npass - P.npass, dt = S.nterms - P.nterms;
+    evals += de;
+    const FlopModel &f = set->flops[t];
+    flops += f.pre * de + f.post * dp + f.per_term * dt;
+  }
+  set->last_state = st;
+  ctx->evals += evals;
+  ctx->flops += flops;
+  int status = MBPT_OK;
+  mbpt_result tot{};
+  double var = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    mbpt_result r;
+    result_of(st[t], r);
+    if (!std::isfinite(r.E_per_A) || !std::isfinite(r.sigma)) status = MBPT_ENUMERIC;
+    if (per_task) per_task[t] = r;
+    tot.E_per_A += r.E_per_A;
+    var += r.sigma * r.sigma;
+    tot.last_E += r.last_E;
+    tot.n_evals += r.n_evals;
+    tot.n_fp64_fallback += r.n_fp64_fallback;
+    tot.iters_done = std::max(tot.iters_done, r.iters_done);
+    tot.chi2_dof = std::max(tot.chi2_dof, r.chi2_dof);
+  }
+  tot.sigma = std::sqrt(var);
+  if (total) *total = tot;
+  if (status) set_err(ctx, "integrate: non-finite estimate");
+  return status;
+}
+
+extern "C" int mbpt_iteration_log(mbpt_task_set *set, int task, double *I, double *var, int cap,
+                                  int *count) {
+  if (!set || !count || task < 0 || task >= static_cast<int>(set->tasks.size())) return MBPT_EINVAL;
+  if (!set->ws) return MBPT_ESTATE;
+  mbpt_context *ctx = set->ctx;
+  TaskDev S;
+  HIPCHK(ctx, hipMemcpyAsync(&S, set->d_tasks + task, sizeof(TaskDev), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  std::vector<double> lg(2 * set->max_iters);
+  HIPCHK(ctx, hipMemcpyAsync(lg.data(), set->d_reslog + 2 * static_cast<size_t>(task) * set->max_iters,
+                             lg.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const int n = std::min(std::min(S.it_done, set->max_iters), cap);
+  const int start = S.it_done - n;  // oldest stored iteration that fits
+  for (int k = 0; k < n; ++k) {
+    const int slot = (start + k) % set->max_iters;
+    if (I) I[k] = lg[2 * slot];
+    if (var) var[k] = lg[2 * slot + 1];
+  }
+  *count = n;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, uint64_t first,
+                                 uint64_t count, double *w_host) {
+  if (!set || !w_host || task < 0 || task >= static_cast<int>(set->tasks.size())) return MBPT_EINVAL;
+  if (!set->ws) return MBPT_ESTATE;
+  mbpt_context *ctx = set->ctx;
+  KArgs a = kargs_of(set);
+  // the item partials region serves as staging
+  const uint64_t cap = set->max_items * 4;
+  for (uint64_t done = 0; done < count;) {
+    const uint64_t n = std::min<uint64_t>(cap, count - done);
+    HIPCHK(ctx, launch_dump(a, task, set->tasks[task].order, set->q, iter, first + done, n,
+                            set->d_partials, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(w_host + done, set->d_partials, n * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    done += n;
+  }
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_get_grid(mbpt_task_set *set, int task, double *edges_host) {
+  if (!set || !edges_host || task < 0 || task >= static_cast<int>(set->tasks.size()))
+    return MBPT_EINVAL;
+  if (!set->ws) return MBPT_ESTATE;
+  mbpt_context *ctx = set->ctx;
+  const TaskDev &T = set->h_tasks[task];
+  HIPCHK(ctx, hipMemcpyAsync(edges_host, set->d_grids + T.grid_off,
+                             T.nd * (ctx->desc.n_bins + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_set_grid(mbpt_task_set *set, int task, const double *edges_host) {
+  if (!set || !edges_host || task < 0 || task >= static_cast<int>(set->tasks.size()))
+    return MBPT_EINVAL;
+  if (!set->ws) return MBPT_ESTATE;
+  mbpt_context *ctx = set->ctx;
+  const TaskDev &T = set->h_tasks[task];
+  const int nb = ctx->desc.n_bins;
+  for (int m = 0; m < T.nd; ++m) {
+    const double *e = edges_host + m * (nb + 1);
+    if (e[0] != 0.0 || e[nb] != 1.0) return MBPT_EINVAL;
+    for (int b = 0; b < nb; ++b)
+      if (!(e[b + 1] > e[b])) return MBPT_EINVAL;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(set->d_grids + T.grid_off, edges_host,
+                             T.nd * (nb + 1) * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_kernel_stats(mbpt_context *ctx, uint64_t *launches, double *kernel_ms,
+                                 uint64_t *evals, double *flops) {
+  if (!ctx) return MBPT_EINVAL;
+  if (launches) *launches = ctx->launches;
+  if (kernel_ms) *kernel_ms = ctx->kernel_ms;
+  if (evals) *evals = ctx->evals;
+  if (flops) *flops = ctx->flops;
+  ctx->launches = 0;
+  ctx->kernel_ms = 0.0;
+  ctx->evals = 0;
+  ctx->flops = 0.0;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_task_flops(const mbpt_task_set *set, int task, double *flops,
+                               double *transcendentals) {
+  if (!set || task < 0 || task >= static_cast<int>(set->tasks.size())) return MBPT_EINVAL;
+  const FlopModel &f = set->flops[task];
+  if (flops) *flops = f.pre + f.post + f.per_term * f.all_terms;
+  if (transcendentals) *transcendentals = f.transc_pre + f.transc_post;
+  return MBPT_OK;
+}

@@ -1,0 +1,79 @@
+// Handle types behind the opaque C ABI pointers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "device_types.hpp"
+#include "mbpt_vegas.h"
+
+namespace mbpt {
+
+// Algorithmic FLOPs of one evaluation (see count_flops).
+struct FlopModel {
+  double pre = 0.0;        // every sample
+  double post = 0.0;       // samples past the Pauli test
+  double per_term = 0.0;   // per label term evaluated
+  double transc_pre = 0.0, transc_post = 0.0;
+  double all_terms = 0.0;  // terms of the whole list
+};
+
+}  // namespace mbpt
+
+struct mbpt_context {
+  mbpt_context_desc desc{};
+  hipStream_t stream = nullptr;
+  mbpt_interaction v{};
+  int num_cus = 256;
+  std::string err;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t n_used = 0;
+  uint64_t launches = 0;
+  double kernel_ms = 0.0;
+  uint64_t evals = 0;
+  double flops = 0.0;
+};
+
+struct mbpt_task_set {
+  mbpt_context *ctx = nullptr;
+  int q = 2;
+  std::vector<mbpt_task_desc> tasks;
+  int launch_mode = MBPT_LAUNCH_PER_TASK;
+  int block = 256, spt = 16;
+  std::vector<mbpt::DiagDev> diags;
+  std::vector<mbpt::GroupDev> groups;
+  std::vector<mbpt::TermDev> terms;
+  std::vector<int> task_diag;
+  std::vector<mbpt::FlopModel> flops, diag_flops;
+  int max_nd = 0;
+  std::vector<mbpt::TaskDev> h_tasks, last_state;
+  int grid_doubles = 0, hist_doubles = 0;
+  // workspace
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  uint64_t max_samples = 0;
+  int max_iters = 0;
+  size_t max_items = 0;
+  mbpt::TaskDev *d_tasks = nullptr;
+  mbpt::DiagDev *d_diags = nullptr;
+  mbpt::GroupDev *d_groups = nullptr;
+  mbpt::TermDev *d_terms = nullptr;
+  double *d_grids = nullptr, *d_hists = nullptr, *d_partials = nullptr, *d_reslog = nullptr;
+  uint64_t *d_counters = nullptr;
+  int grid_blocks = 1;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_iters = 0;
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    graph_exec = nullptr;
+    graph_iters = 0;
+  }
+};
+
+namespace mbpt {
+void set_err(mbpt_context *ctx, const std::string &msg);
+int hip_fail(mbpt_context *ctx, hipError_t e, const char *what);
+int batched_occupancy(int q, int block, size_t lds);
+}  // namespace mbpt
