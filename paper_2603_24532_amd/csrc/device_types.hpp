@@ -18,10 +18,14 @@ struct alignas(16) DiagDev {
   int pad[2];
   double pref;            // (1/2)^{n_eq} (-1)^{n_h + n_loop} (2 pi)^{-3L}
   double pad0;
-  double lc[10][6];       // line l momentum = sum_j lc[l][j] k_j
-  double vp[5][6];        // vertex v: p  = (k_o1 - k_o2)/2 = sum_j vp[v][j] k_j
-  double vq[5][6];        // vertex v: p' = (k_i1 - k_i2)/2 = sum_j vq[v][j] k_j
-  double cutc[4][10];     // D_c = sum_l cutc[c][l] eps_l  (+1 hole, -1 particle)
+  // Signed 0/1/2 coefficients as loop bitmasks (bits 0-7: +1, 8-15: -1,
+  // 16-23: +2, 24-31: -2):
+  uint32_t lmask[10];     // line l momentum = sum_j c_lj k_j
+  uint32_t pmask_v[5];    // vertex v: 2p  = k_o1 - k_o2 = sum_j c_vj k_j
+  uint32_t qmask_v[5];    // vertex v: 2p' = k_i1 - k_i2
+  uint32_t cut_hole[4];   // D_c = sum_{holes in c} eps - sum_{particles in c} eps
+  uint32_t cut_part[4];
+  int pad3[2];
 };
 
 // Isospin configuration: lines whose bit is set carry protons.

@@ -24,14 +24,16 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
                                               uint32_t k0, uint32_t k1, uint32_t *out) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    // 32 x 32 -> 64-bit products (one v_mad_u64_u32 each)
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    // three-input XOR in one v_bitop3_b32 (truth table 0x96)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), c3, k1, 0x96);
     c0 = n0;
-    c1 = lo1;
+    c1 = static_cast<uint32_t>(p1);
     c2 = n2;
-    c3 = lo0;
+    c3 = static_cast<uint32_t>(p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -41,10 +43,49 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
   out[3] = c3;
 }
 
+// sum_j c_j v_j over loops j < L with c_j in {0, +-1, +-2} given as the
+// uniform bitmask m (bits 0-7: +1, 8-15: -1, 16-23: +2, 24-31: -2); zero
+// coefficients cost nothing (uniform branches).
+// Coefficient c in {0, +-1, +-2} of loop j in the uniform bitmask m (bits
+// 0-7: +1, 8-15: -1, 16-23: +2, 24-31: -2) as a double, built from its bit
+// pattern with scalar instructions only.
+__device__ __forceinline__ double mask_coef(uint32_t m, int j) {
+  uint32_t hi = 0u;
+  hi = (m & (1u << j)) ? 0x3FF00000u : hi;
+  hi = (m & (1u << (8 + j))) ? 0xBFF00000u : hi;
+  hi = (m & (1u << (16 + j))) ? 0x40000000u : hi;
+  hi = (m & (1u << (24 + j))) ? 0xC0000000u : hi;
+  return __hiloint2double(static_cast<int>(hi), 0);
+}
+
+// sum_j c_j v_j over loops j < L (coefficients from the uniform bitmask m)
+template <int L>
+__device__ __forceinline__ void masked_sum(uint32_t m, const double (*k)[3], double *out) {
+  double x = 0.0, y = 0.0, z = 0.0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const double c = mask_coef(m, j);
+    x = fma(c, k[j][0], x);
+    y = fma(c, k[j][1], y);
+    z = fma(c, k[j][2], z);
+  }
+  out[0] = x;
+  out[1] = y;
+  out[2] = z;
+}
+
 // Neumaier step: (s, c) += x
 __device__ __forceinline__ void neumaier(double &s, double &c, double x) {
   const double t = s + x;
   c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+  s = t;
+}
+
+// Kahan step: (s, c) tracks sum = s - c
+__device__ __forceinline__ void kahan(double &s, double &c, double x) {
+  const double y = x - c;
+  const double t = s + y;
+  c = (t - s) - y;
   s = t;
 }
 
@@ -81,15 +122,18 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(s >> 32), iter,
                   static_cast<uint32_t>(j), a.phys.seed, T->key, wd + 4 * j);
 
-  // VEGAS map: bin b = floor(w nb / 2^32), fraction ((w nb mod 2^32) + 1/2) / 2^32
+  // VEGAS map: bin b = floor(w nb / 2^32), fraction ((w nb mod 2^32) + 1/2) / 2^32.
+  // y = w nb 2^-32 is exact in fp64 (at most 39 significant bits), so b and the
+  // fraction come out exactly with full-rate fp64 instructions.
   double x[ND];
   double jac = 1.0;
+  const double nbscale = static_cast<double>(nb) * 0x1p-32;
 #pragma unroll
   for (int m = 0; m < ND; ++m) {
-    const uint32_t w = wd[m];
-    const int b = static_cast<int>(__umulhi(w, static_cast<uint32_t>(nb)));
-    const uint32_t lo = w * static_cast<uint32_t>(nb);
-    const double r = (static_cast<double>(lo) + 0.5) * 0x1p-32;
+    const double y = static_cast<double>(wd[m]) * nbscale;
+    const double fb = floor(y);
+    const int b = static_cast<int>(fb);
+    const double r = (y - fb) + 0x1p-33;
     const double2 ew = g[m * nb + b];
     x[m] = ew.x + r * ew.y;
     jac *= static_cast<double>(nb) * ew.y;
@@ -117,15 +161,9 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   uint32_t inN = 0, inP = 0;
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
-    double kx = 0.0, ky = 0.0, kz = 0.0;
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-      const double c = D->lc[l][j];
-      kx = fma(c, k[j][0], kx);
-      ky = fma(c, k[j][1], ky);
-      kz = fma(c, k[j][2], kz);
-    }
-    const double k2 = kx * kx + ky * ky + kz * kz;
+    double kv[3];
+    masked_sum<L>(D->lmask[l], k, kv);
+    const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = a.phys.hb2m * k2;
     inN |= (k2 < T->kF2[0]) ? (1u << l) : 0u;
     if (Q == 4) inP |= (k2 < T->kF2[1]) ? (1u << l) : 0u;
@@ -141,25 +179,34 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   double dprod = 1.0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
+    const uint32_t hm = D->cut_hole[c], pm = D->cut_part[c];
     double Dc = 0.0;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) Dc = fma(D->cutc[c][l], eps[l], Dc);
+    for (int l = 0; l < NL; ++l) {
+      uint32_t hi = (hm & (1u << l)) ? 0x3FF00000u : 0u;
+      hi = (pm & (1u << l)) ? 0xBFF00000u : hi;
+      Dc = fma(__hiloint2double(static_cast<int>(hi), 0), eps[l], Dc);
+    }
     dprod *= Dc;
   }
 
-  // antisymmetrised matrix elements: V_d = V(p, p'), V_e = V(p, -p')
-  double Vd[ORDER], Ve[ORDER];
+  // antisymmetrised matrix elements V_d = V(p, p'), V_e = V(p, -p') without
+  // their regulators: the regulator product over all vertices factors out of
+  // every label term and is applied once, exp(-sum_v (p^n + p'^n) / Lambda^n).
+  // The 2n Yukawa denominators and the product of energy denominators are
+  // inverted together with one division (prefix products).
+  constexpr int NR = 2 * ORDER + 1;
+  double den[NR];
+  double yreg = 0.0;
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
-    double p[3] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0};
+    double p[3], q[3];  // 2p and 2p'
+    masked_sum<L>(D->pmask_v[v], k, p);
+    masked_sum<L>(D->qmask_v[v], k, q);
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-      const double cp = D->vp[v][j], cq = D->vq[v][j];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        p[i] = fma(cp, k[j][i], p[i]);
-        q[i] = fma(cq, k[j][i], q[i]);
-      }
+    for (int i = 0; i < 3; ++i) {
+      p[i] *= 0.5;
+      q[i] *= 0.5;
     }
     const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
@@ -169,11 +216,31 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
       pn *= p2;
       qn *= q2;
     }
-    const double reg = exp(-(pn + qn) * a.phys.invLn);
+    yreg += pn + qn;
     const double s2 = p2 + q2 + a.phys.m2;
-    Vd[v] = reg * (a.phys.V0 + a.phys.Vy / (s2 - 2.0 * pq));
-    Ve[v] = reg * (a.phys.V0 + a.phys.Vy / (s2 + 2.0 * pq));
+    den[2 * v] = s2 - 2.0 * pq;
+    den[2 * v + 1] = s2 + 2.0 * pq;
   }
+  den[NR - 1] = dprod;
+  double pre[NR];
+  pre[0] = den[0];
+#pragma unroll
+  for (int i = 1; i < NR; ++i) pre[i] = pre[i - 1] * den[i];
+  double inv = 1.0 / pre[NR - 1];
+  double rinv[NR];
+#pragma unroll
+  for (int i = NR - 1; i > 0; --i) {
+    rinv[i] = inv * pre[i - 1];
+    inv *= den[i];
+  }
+  rinv[0] = inv;
+  double Vd[ORDER], Ve[ORDER];
+#pragma unroll
+  for (int v = 0; v < ORDER; ++v) {
+    Vd[v] = a.phys.V0 + a.phys.Vy * rinv[2 * v];
+    Ve[v] = a.phys.V0 + a.phys.Vy * rinv[2 * v + 1];
+  }
+  const double regall = exp(-yreg * a.phys.invLn);
 
   // label sum: isospin groups (Pauli test per group), terms with multiplicity
   double acc = 0.0;
@@ -200,7 +267,7 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
       }
     }
   }
-  return jac * (D->pref * T->inv_density) * acc / dprod;
+  return jac * (D->pref * T->inv_density) * regall * acc * rinv[NR - 1];
 }
 
 // ---------------------------------------------------------------------------
@@ -239,8 +306,8 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       int bins[ND];
       const double w = eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
       const double d = w - shift;
-      neumaier(s1, c1, d);
-      neumaier(s2, c2, d * d);
+      kahan(s1, c1, d);
+      kahan(s2, c2, d * d);
       const double w2 = w * w;
       if (w2 != 0.0) {
 #pragma unroll
@@ -248,6 +315,9 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       }
     }
   }
+  // Kahan pairs hold s - c; the merges below use s + c
+  c1 = -c1;
+  c2 = -c2;
   // wavefront butterfly, then waves in order
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -329,41 +399,100 @@ __global__ __launch_bounds__(256) void sample_batched(KArgs a) {
 // Iteration end: fixed-order reduction of the item partials, estimate and
 // variance, running inverse-variance sums, and Lepage refinement of the grid.
 
-__device__ void refine_dim(double *hist, double *edges, int nb, double alpha, double *ds,
-                           double *r, double *xnew) {
-  ds[0] = (7.0 * hist[0] + hist[1]) / 8.0;
-  for (int b = 1; b < nb - 1; ++b) ds[b] = (hist[b - 1] + 6.0 * hist[b] + hist[b + 1]) / 8.0;
-  ds[nb - 1] = (hist[nb - 2] + 7.0 * hist[nb - 1]) / 8.0;
-  double sum = 0.0;
-  for (int b = 0; b < nb; ++b) sum += ds[b];
-  if (!(sum > 0.0)) return;
-  double rtot = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    const double v = ds[b] / sum;
-    double rb;
-    if (v <= 0.0) rb = 0.0;
-    else if (v >= 1.0) rb = 1.0;
-    else rb = pow((v - 1.0) / log(v), alpha);
-    r[b] = rb;
-    rtot += rb;
-  }
-  if (!(rtot > 0.0)) return;
-  const double per = rtot / nb;
-  xnew[0] = 0.0;
-  xnew[nb] = 1.0;
-  double acc = 0.0;
-  int j = 0;
-  for (int kk = 1; kk < nb; ++kk) {
-    const double target = per * kk;
-    while (j < nb - 1 && acc + r[j] < target) {
-      acc += r[j];
-      ++j;
+// Wave-cooperative sum: every lane receives the total (fixed butterfly order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Lepage refinement of one dimension by one wavefront (lanes own bins b and
+// b + 64).  hist: sums of w^2 per bin; edges: nb + 1 edges, rewritten.
+// Smoothing (7,1)/8, (1,6,1)/8, (1,7)/8, normalisation, compression
+// ((d - 1)/ln d)^alpha, then new edges placing an equal share of the total
+// compressed weight in every new bin (weight uniform inside old bins).
+// scr: 2 nb + 2 doubles of LDS for this wave.
+__device__ void refine_dim_wave(double *hist, double *edges, int nb, double alpha, double *scr) {
+  const int lane = threadIdx.x & 63;
+  double *cum = scr;            // nb + 1 prefix sums of r
+  double *r = scr + nb + 1;     // nb compressed weights
+  double dsv[2] = {0.0, 0.0};
+  double part = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int b = lane + 64 * h;
+    if (b < nb) {
+      double d;
+      if (b == 0) d = (7.0 * hist[0] + hist[1]) / 8.0;
+      else if (b == nb - 1) d = (hist[nb - 2] + 7.0 * hist[nb - 1]) / 8.0;
+      else d = (hist[b - 1] + 6.0 * hist[b] + hist[b + 1]) / 8.0;
+      dsv[h] = d;
+      part += d;
     }
-    double frac = r[j] > 0.0 ? (target - acc) / r[j] : 0.0;
-    frac = fmin(1.0, fmax(0.0, frac));
-    xnew[kk] = edges[j] + frac * (edges[j + 1] - edges[j]);
   }
-  for (int b = 0; b <= nb; ++b) edges[b] = xnew[b];
+  const double sum = wave_sum(part);
+  if (!(sum > 0.0)) return;  // uniform across the wave
+  double rp = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int b = lane + 64 * h;
+    if (b < nb) {
+      const double v = dsv[h] / sum;
+      double rb;
+      if (v <= 0.0) rb = 0.0;
+      else if (v >= 1.0) rb = 1.0;
+      else rb = pow((v - 1.0) / log(v), alpha);
+      r[b] = rb;
+      rp += rb;
+    }
+  }
+  const double rtot = wave_sum(rp);
+  if (!(rtot > 0.0)) return;
+  __builtin_amdgcn_wave_barrier();
+  // inclusive scan over bins 0..63, then 64..127 offset by the first half
+  double carry = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int b = lane + 64 * h;
+    double x = (b < nb) ? r[b] : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (b < nb) cum[b + 1] = carry + x;
+    carry += __shfl(x, 63, 64);
+  }
+  if (lane == 0) cum[0] = 0.0;
+  __builtin_amdgcn_wave_barrier();
+  __syncwarp();
+  const double per = rtot / nb;
+  double xnew[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int kk = lane + 64 * h;
+    xnew[h] = 0.0;
+    if (kk >= 1 && kk < nb) {
+      const double target = per * kk;
+      // smallest j with cum[j + 1] >= target (j = nb - 1 if none)
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cum[mid + 1] >= target) hi = mid;
+        else lo = mid + 1;
+      }
+      const int j = lo;
+      double frac = r[j] > 0.0 ? (target - cum[j]) / r[j] : 0.0;
+      frac = fmin(1.0, fmax(0.0, frac));
+      xnew[h] = edges[j] + frac * (edges[j + 1] - edges[j]);
+    }
+  }
+  __syncwarp();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int kk = lane + 64 * h;
+    if (kk >= 1 && kk < nb) edges[kk] = xnew[h];
+  }
 }
 
 __global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task, double alpha) {
@@ -436,14 +565,16 @@ __global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task,
     T->npass += F[1];
     T->nterms += F[2];
   }
-  // refinement: one thread per dimension, scratch in LDS
+  // refinement: one wavefront per dimension
+  __syncthreads();
   const int nb = a.phys.nb;
-  for (int m = tid; m < T->nd; m += bs) {
-    double *ds = scratch + static_cast<size_t>(m) * (3 * nb + 1);
+  double *scr = scratch + static_cast<size_t>(wave) * (2 * nb + 2);
+  for (int m = wave; m < T->nd; m += (bs >> 6)) {
     double *hist = a.hists + T->hist_off + m * nb;
     double *edges = a.grids + T->grid_off + m * (nb + 1);
-    refine_dim(hist, edges, nb, alpha, ds, ds + nb, ds + 2 * nb);
-    for (int b = 0; b < nb; ++b) hist[b] = 0.0;
+    refine_dim_wave(hist, edges, nb, alpha, scr);
+    __syncwarp();
+    for (int b = lane; b < nb; b += 64) hist[b] = 0.0;
   }
 }
 
@@ -532,7 +663,8 @@ hipError_t launch_sample_batched(const KArgs &a, int q, int max_nd, int grid, in
 
 hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int max_nd, double alpha,
                          hipStream_t st) {
-  const size_t lds = static_cast<size_t>(max_nd) * (3 * a.phys.nb + 1) * sizeof(double);
+  (void)max_nd;
+  const size_t lds = 4 * static_cast<size_t>(2 * a.phys.nb + 2) * sizeof(double);
   hipLaunchKernelGGL(finish_iteration, dim3(ntasks), dim3(256), lds, st, a, first_task, alpha);
   return hipGetLastError();
 }

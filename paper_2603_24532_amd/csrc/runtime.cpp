@@ -221,15 +221,31 @@ int compile_tables(mbpt_task_set *set) {
       if (d->particle[l]) dd.part_mask |= 1u << l;
     dd.line_mask = (1u << d->nlines) - 1u;
     dd.pref = d->prefactor * std::pow(2.0 * M_PI, -3.0 * d->nloops);
-    for (int l = 0; l < d->nlines; ++l)
-      for (int j = 0; j < d->nloops; ++j) dd.lc[l][j] = d->coef[l][j];
-    for (int v = 0; v < d->order; ++v)
+    auto pack = [&](const int *c) {
+      uint32_t m = 0;
       for (int j = 0; j < d->nloops; ++j) {
-        dd.vp[v][j] = 0.5 * (d->coef[d->vout[v][0]][j] - d->coef[d->vout[v][1]][j]);
-        dd.vq[v][j] = 0.5 * (d->coef[d->vin[v][0]][j] - d->coef[d->vin[v][1]][j]);
+        if (c[j] == 1) m |= 1u << j;
+        else if (c[j] == -1) m |= 1u << (8 + j);
+        else if (c[j] == 2) m |= 1u << (16 + j);
+        else if (c[j] == -2) m |= 1u << (24 + j);
       }
+      return m;
+    };
+    for (int l = 0; l < d->nlines; ++l) dd.lmask[l] = pack(d->coef[l]);
+    for (int v = 0; v < d->order; ++v) {
+      int cp[kMaxLoops], cq[kMaxLoops];
+      for (int j = 0; j < d->nloops; ++j) {
+        cp[j] = d->coef[d->vout[v][0]][j] - d->coef[d->vout[v][1]][j];
+        cq[j] = d->coef[d->vin[v][0]][j] - d->coef[d->vin[v][1]][j];
+      }
+      dd.pmask_v[v] = pack(cp);
+      dd.qmask_v[v] = pack(cq);
+    }
     for (int c = 0; c < d->ncuts; ++c)
-      for (int l = 0; l < d->nlines; ++l) dd.cutc[c][l] = d->cut[c][l];
+      for (int l = 0; l < d->nlines; ++l) {
+        if (d->cut[c][l] > 0) dd.cut_hole[c] |= 1u << l;
+        if (d->cut[c][l] < 0) dd.cut_part[c] |= 1u << l;
+      }
     // isospin groups: terms sorted by tau
     for (size_t i = 0; i < ll.terms.size();) {
       size_t j = i;
