@@ -35,21 +35,23 @@ def parse():
     ap.add_argument("--samples-log2", type=int, default=24)
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
-    ap.add_argument("--cpu-samples-log2", type=int, default=18)
+    ap.add_argument("--cpu-samples-log2", type=int, default=20)
     return ap.parse_args()
 
 
-def gpu_run(args):
+def gpu_run(args, precision=0, steps=None, warmup=None):
     import torch
     import paper_2603_24532_amd as M
 
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     N = 1 << args.samples_log2
     iters = args.iters
     stream = M.current_stream()
     sets = {}
     bufs = []
     for order in (1, 2):
-        ctx = M.mbpt_context_create(stream=stream, precision=M.MBPT_FP64, seed=1)
+        ctx = M.mbpt_context_create(stream=stream, precision=precision, seed=1)
         tasks = [(order, 0, M.MBPT_NEUTRON, n, 0.0, 100 * order + i)
                  for i, n in enumerate(DENSITIES)]
         s = M.mbpt_create_task_set(ctx, tasks)
@@ -68,13 +70,13 @@ def gpu_run(args):
             res[order] = per
         return res
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     for ctx, s in sets.values():
         M.mbpt_kernel_stats(ctx)  # clear
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         res = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -155,6 +157,21 @@ def main():
             f"order{o}_n{DENSITIES[i]:.2f}": [round(r.E_per_A, 8), float(f"{r.sigma:.3e}")]
             for o, per in g["res"].items() for i, r in enumerate(per)
         },
+    }
+    # same workload with the fp32 integrand (fp64 map, accumulation, refinement
+    # and fp64 re-evaluation band): reported beside the fp64 value
+    g32 = gpu_run(args, precision=1, steps=1, warmup=1)
+    st32 = g32["stats"][2]
+    f32_sum = {o: sum(r.n_fp64_fallback for r in per) / max(1, sum(r.n_evals for r in per))
+               for o, per in g32["res"].items()}
+    line["fp32"] = {
+        "value": g32["evals"] / g32["dt"] / 1e9, "unit": "Gevals/s",
+        "ms_per_step": 1e3 * g32["dt"],
+        "order2_avg_launch_ms": st32["kernel_ms"] / max(1, st32["launches"]),
+        "fp64_fallback_fraction": f32_sum,
+        "max_abs_dev_over_sigma_fp64": max(
+            abs(r32.E_per_A - r64.E_per_A) / r64.sigma
+            for o in (1, 2) for r32, r64 in zip(g32["res"][o], g["res"][o])),
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args)

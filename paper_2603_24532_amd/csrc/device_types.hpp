@@ -39,7 +39,7 @@ struct alignas(16) GroupDev {
 struct alignas(16) TermDev {
   double mult;
   uint32_t codes;
-  uint32_t pad;
+  float multf;  // mult as float for the fp32 integrand
 };
 
 // Interaction and medium constants common to a launch.
@@ -58,7 +58,9 @@ struct Phys {
 // One task: parameters (host-written) and running state (device-written).
 struct alignas(16) TaskDev {
   int diag, nd, grid_off, hist_off;
-  int item_begin, nitems, res_off, res_cap;
+  int item_begin, nitems, res_off, res_cap;  // work items [item_begin, +nitems)
+  int store_begin;                           // partials/counters slot of the first item
+  int pad0;
   uint32_t key;
   int order;
   uint64_t nsamples;

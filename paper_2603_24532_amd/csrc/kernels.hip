@@ -102,30 +102,23 @@ __device__ __forceinline__ void pair_merge(double &s, double &c, double s2, doub
 // Per-sample integrand in fp64.  Returns the weight; writes the VEGAS bin of
 // every dimension to bins[].
 
-template <int ORDER, int Q>
-__device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
-                                            const DiagDev *__restrict__ D,
+// Philox words -> VEGAS bins and mapped coordinates x (fp64, identical for
+// both integrand precisions).  Returns the VEGAS Jacobian.
+template <int ND>
+__device__ __forceinline__ double vegas_map(const KArgs &a, const TaskDev *__restrict__ T,
                                             const double2 *__restrict__ g, uint64_t s,
-                                            uint32_t iter, int *bins, uint32_t &npass,
-                                            uint32_t &nterms) {
-  constexpr int L = ORDER + 1;
-  constexpr int NL = 2 * ORDER;
-  constexpr int NC = ORDER - 1;
-  constexpr int ND = 3 * L;
+                                            uint32_t iter, double *x, int *bins) {
   constexpr int NW = (ND + 3) / 4;
   const int nb = a.phys.nb;
-
-  // Philox words: counter (s lo, s hi, iteration, word block), key (seed, task)
+  // counter (s lo, s hi, iteration, word block), key (seed, task)
   uint32_t wd[4 * NW];
 #pragma unroll
   for (int j = 0; j < NW; ++j)
     philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(s >> 32), iter,
                   static_cast<uint32_t>(j), a.phys.seed, T->key, wd + 4 * j);
-
-  // VEGAS map: bin b = floor(w nb / 2^32), fraction ((w nb mod 2^32) + 1/2) / 2^32.
+  // bin b = floor(w nb / 2^32), fraction ((w nb mod 2^32) + 1/2) / 2^32.
   // y = w nb 2^-32 is exact in fp64 (at most 39 significant bits), so b and the
   // fraction come out exactly with full-rate fp64 instructions.
-  double x[ND];
   double jac = 1.0;
   const double nbscale = static_cast<double>(nb) * 0x1p-32;
 #pragma unroll
@@ -139,6 +132,21 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     jac *= static_cast<double>(nb) * ew.y;
     bins[m] = b;
   }
+  return jac;
+}
+
+template <int ORDER, int Q>
+__device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
+                                            const DiagDev *__restrict__ D,
+                                            const double2 *__restrict__ g, uint64_t s,
+                                            uint32_t iter, int *bins, uint32_t &npass,
+                                            uint32_t &nterms) {
+  constexpr int L = ORDER + 1;
+  constexpr int NL = 2 * ORDER;
+  constexpr int NC = ORDER - 1;
+  constexpr int ND = 3 * L;
+  double x[ND];
+  double jac = vegas_map<ND>(a, T, g, s, iter, x, bins);
 
   // loop momenta: radius R x0, cos theta = 2 x1 - 1, azimuth 2 pi x2
   double k[L][3];
@@ -270,10 +278,223 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   return jac * (D->pref * T->inv_density) * regall * acc * rinv[NR - 1];
 }
 
+// fp32 counterpart of masked_sum
+__device__ __forceinline__ float mask_coef_f(uint32_t m, int j) {
+  uint32_t bits = 0u;
+  bits = (m & (1u << j)) ? 0x3F800000u : bits;
+  bits = (m & (1u << (8 + j))) ? 0xBF800000u : bits;
+  bits = (m & (1u << (16 + j))) ? 0x40000000u : bits;
+  bits = (m & (1u << (24 + j))) ? 0xC0000000u : bits;
+  return __uint_as_float(bits);
+}
+
+template <int L>
+__device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], float *out) {
+  float x = 0.0f, y = 0.0f, z = 0.0f;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const float c = mask_coef_f(m, j);
+    x = fmaf(c, k[j][0], x);
+    y = fmaf(c, k[j][1], y);
+    z = fmaf(c, k[j][2], z);
+  }
+  out[0] = x;
+  out[1] = y;
+  out[2] = z;
+}
+
+// Per-sample integrand with fp32 arithmetic after the (fp64) VEGAS map; the
+// Jacobian and the final weight stay fp64.  Sets `fallback` instead of
+// returning a value when the sample lies in the band where fp32 cannot
+// resolve the result to the target accuracy: a line within band_k kF^2 of a
+// Fermi surface (the Pauli factor could flip), an energy denominator below
+// band_d times the sum of its energies (cancellation), or a regulator exponent
+// or reciprocal product outside the fp32 range.  The caller then evaluates the
+// sample in fp64 from the same random words.
+template <int ORDER, int Q>
+__device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
+                                            const DiagDev *__restrict__ D,
+                                            const double2 *__restrict__ g, uint64_t s,
+                                            uint32_t iter, int *bins, uint32_t &npass,
+                                            uint32_t &nterms, bool &fallback) {
+  constexpr int L = ORDER + 1;
+  constexpr int NL = 2 * ORDER;
+  constexpr int NC = ORDER - 1;
+  constexpr int ND = 3 * L;
+  double x[ND];
+  double jac = vegas_map<ND>(a, T, g, s, iter, x, bins);
+
+  // loop momenta; the azimuth goes to the hardware sine/cosine in revolutions
+  float k[L][3];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const double R = D->loop_part[j] ? T->Rp : T->Rh;
+    const double rad64 = R * x[3 * j];
+    jac *= R * rad64 * rad64 * (4.0 * M_PI);
+    const float rad = static_cast<float>(rad64);
+    const float ct = static_cast<float>(2.0 * x[3 * j + 1] - 1.0);
+    const float st = __builtin_sqrtf(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
+    const float rev = static_cast<float>(x[3 * j + 2]);
+    const float sp = __builtin_amdgcn_sinf(rev), cp = __builtin_amdgcn_cosf(rev);
+    const float rs = rad * st;
+    k[j][0] = rs * cp;
+    k[j][1] = rs * sp;
+    k[j][2] = rad * ct;
+  }
+
+  const float kFn2 = static_cast<float>(T->kF2[0]), kFp2 = static_cast<float>(T->kF2[1]);
+  const float bandk = static_cast<float>(T->band_k), bandd = static_cast<float>(T->band_d);
+  const float hb2m = static_cast<float>(a.phys.hb2m);
+  float eps[NL];
+  uint32_t inN = 0, inP = 0;
+  bool near = false;
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    float kv[3];
+    masked_sum_f<L>(D->lmask[l], k, kv);
+    const float k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+    eps[l] = hb2m * k2;
+    near |= fabsf(k2 - kFn2) < bandk * kFn2;
+    inN |= (k2 < kFn2) ? (1u << l) : 0u;
+    if (Q == 4) {
+      near |= fabsf(k2 - kFp2) < bandk * kFp2;
+      inP |= (k2 < kFp2) ? (1u << l) : 0u;
+    }
+  }
+  if (near) {
+    fallback = true;
+    return 0.0;
+  }
+  const uint32_t lmask = D->line_mask, pmask = D->part_mask;
+  const uint32_t okN = (inN ^ pmask) & lmask;
+  const uint32_t okP = (inP ^ pmask) & lmask;
+  if (Q == 2 && okN != lmask) return 0.0;
+
+  float dprod = 1.0f;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const uint32_t hm = D->cut_hole[c], pm = D->cut_part[c];
+    float Dc = 0.0f, Dabs = 0.0f;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      uint32_t bits = (hm & (1u << l)) ? 0x3F800000u : 0u;
+      bits = (pm & (1u << l)) ? 0xBF800000u : bits;
+      const float cf = __uint_as_float(bits);
+      Dc = fmaf(cf, eps[l], Dc);
+      Dabs = fmaf(fabsf(cf), eps[l], Dabs);
+    }
+    near |= fabsf(Dc) < bandd * Dabs;
+    dprod *= Dc;
+  }
+
+  constexpr int NR = 2 * ORDER + 1;
+  float den[NR];
+  float yreg = 0.0f;
+  const float m2 = static_cast<float>(a.phys.m2);
+#pragma unroll
+  for (int v = 0; v < ORDER; ++v) {
+    float p[3], q[3];
+    masked_sum_f<L>(D->pmask_v[v], k, p);
+    masked_sum_f<L>(D->qmask_v[v], k, q);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      p[i] *= 0.5f;
+      q[i] *= 0.5f;
+    }
+    const float p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+    const float q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+    const float pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
+    float pn = p2, qn = q2;
+    for (int e = 1; e < a.phys.half_exp; ++e) {
+      pn *= p2;
+      qn *= q2;
+    }
+    yreg += pn + qn;
+    const float s2 = p2 + q2 + m2;
+    den[2 * v] = s2 - 2.0f * pq;
+    den[2 * v + 1] = s2 + 2.0f * pq;
+  }
+  den[NR - 1] = dprod;
+  float pre[NR];
+  pre[0] = den[0];
+#pragma unroll
+  for (int i = 1; i < NR; ++i) pre[i] = pre[i - 1] * den[i];
+  const float yexp = yreg * static_cast<float>(a.phys.invLn);
+  near |= !(fabsf(pre[NR - 1]) > 1e-30f && fabsf(pre[NR - 1]) < 1e30f) || yexp > 80.0f;
+  if (near) {
+    fallback = true;
+    return 0.0;
+  }
+  float inv = __builtin_amdgcn_rcpf(pre[NR - 1]);
+  inv = inv * (2.0f - pre[NR - 1] * inv);  // one Newton step
+  float rinv[NR];
+#pragma unroll
+  for (int i = NR - 1; i > 0; --i) {
+    rinv[i] = inv * pre[i - 1];
+    inv *= den[i];
+  }
+  rinv[0] = inv;
+  const float V0 = static_cast<float>(a.phys.V0), Vy = static_cast<float>(a.phys.Vy);
+  float Vd[ORDER], Ve[ORDER];
+#pragma unroll
+  for (int v = 0; v < ORDER; ++v) {
+    Vd[v] = fmaf(Vy, rinv[2 * v], V0);
+    Ve[v] = fmaf(Vy, rinv[2 * v + 1], V0);
+  }
+  const float regall = __expf(-yexp);
+
+  uint32_t nt = 0;
+  float acc = 0.0f;
+  const GroupDev *__restrict__ G = a.groups + D->group_off;
+  const int ngroups = D->ngroups;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const uint32_t tau = G[gi].tau;
+    const int first = G[gi].first, cnt = G[gi].count;
+    bool ok = true;
+    if (Q == 4) ok = (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
+    if (ok) {
+      nt += cnt;
+      for (int t = first; t < first + cnt; ++t) {
+        const TermDev tm = a.terms[t];
+        float prod = 1.0f;
+#pragma unroll
+        for (int v = 0; v < ORDER; ++v) {
+          const uint32_t code = (tm.codes >> (2 * v)) & 3u;
+          const float ca = code != 1u ? 1.0f : 0.0f;
+          const float cb = code != 0u ? -1.0f : 0.0f;
+          prod *= fmaf(ca, Vd[v], cb * Ve[v]);
+        }
+        acc = fmaf(tm.multf, prod, acc);
+      }
+    }
+  }
+  ++npass;
+  nterms += nt;
+  return jac * (D->pref * T->inv_density) * static_cast<double>(regall) *
+         static_cast<double>(acc) * static_cast<double>(rinv[NR - 1]);
+}
+
+// One sample at precision P (0: fp64, 1: fp32 with fp64 fallback).
+template <int ORDER, int Q, int P>
+__device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__restrict__ T,
+                                              const DiagDev *__restrict__ D,
+                                              const double2 *__restrict__ g, uint64_t s,
+                                              uint32_t iter, int *bins, uint32_t &npass,
+                                              uint32_t &nterms, uint32_t &nfb) {
+  if (P == 0) return eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
+  bool fb = false;
+  double w = eval_fp32<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms, fb);
+  if (fb) {
+    ++nfb;
+    w = eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
+  }
+  return w;
+}
+
 // ---------------------------------------------------------------------------
 // Work item: blockDim.x * spt consecutive samples of one task
 
-template <int ORDER, int Q>
+template <int ORDER, int Q, int P>
 __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, double *smem) {
   constexpr int ND = 3 * (ORDER + 1);
   const TaskDev *__restrict__ T = a.tasks + t;
@@ -299,21 +520,68 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
   const double shift = T->shift;
   const uint64_t base = static_cast<uint64_t>(item - T->item_begin) * bs * a.spt;
   double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
-  uint32_t npass = 0, nterms = 0;
-  for (int kk = 0; kk < a.spt; ++kk) {
-    const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
-    if (s < N) {
-      int bins[ND];
-      const double w = eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
-      const double d = w - shift;
-      kahan(s1, c1, d);
-      kahan(s2, c2, d * d);
-      const double w2 = w * w;
-      if (w2 != 0.0) {
+  uint32_t npass = 0, nterms = 0, nfb = 0;
+  auto accumulate = [&](double w, const int *bins) {
+    const double d = w - shift;
+    kahan(s1, c1, d);
+    kahan(s2, c2, d * d);
+    const double w2 = w * w;
+    if (w2 != 0.0) {
 #pragma unroll
-        for (int m = 0; m < ND; ++m) atomicAdd(&h[m * nb + bins[m]], w2);
+      for (int m = 0; m < ND; ++m) atomicAdd(&h[m * nb + bins[m]], w2);
+    }
+  };
+  if (P == 0) {
+    for (int kk = 0; kk < a.spt; ++kk) {
+      const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
+      if (s < N) {
+        int bins[ND];
+        const double w = eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
+        accumulate(w, bins);
       }
     }
+  } else {
+    // fp32 pass; samples in the fp64 band are queued per wavefront (ballot
+    // order, so the accumulation order is deterministic) and re-evaluated in
+    // fp64 by whole wavefronts, 64 at a time
+    const int lane = tid & 63;
+    uint32_t *queue = reinterpret_cast<uint32_t *>(red + 6 * (bs >> 6)) + 128 * (tid >> 6);
+    int qn = 0;  // wave-uniform
+    auto drain = [&](int take) {
+      if (lane < take) {
+        const uint64_t s = base + queue[lane];
+        int bins[ND];
+        const double w = eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
+        accumulate(w, bins);
+      }
+      __builtin_amdgcn_wave_barrier();
+      const int rest = qn - take;
+      uint32_t moved = (lane < rest) ? queue[take + lane] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (lane < rest) queue[lane] = moved;
+      __builtin_amdgcn_wave_barrier();
+      qn = rest;
+    };
+    for (int kk = 0; kk < a.spt; ++kk) {
+      const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
+      bool fb = false;
+      if (s < N) {
+        int bins[ND];
+        const double w = eval_fp32<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms, fb);
+        if (!fb) accumulate(w, bins);
+      }
+      const uint64_t mask = __ballot(fb);
+      if (fb) {
+        const int pos = qn + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+        queue[pos] = static_cast<uint32_t>(s - base);
+        ++nfb;
+      }
+      qn += __popcll(mask);
+      __builtin_amdgcn_wave_barrier();
+      if (qn >= 64) drain(64);
+    }
+    while (qn > 0) drain(qn < 64 ? qn : 64);
   }
   // Kahan pairs hold s - c; the merges below use s + c
   c1 = -c1;
@@ -327,6 +595,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
     pair_merge(s2, c2, os2, oc2);
     npass += __shfl_xor(npass, off, 64);
     nterms += __shfl_xor(nterms, off, 64);
+    nfb += __shfl_xor(nfb, off, 64);
   }
   const int wave = tid >> 6, lane = tid & 63;
   uint32_t *ured = reinterpret_cast<uint32_t *>(red + 4 * (bs >> 6));
@@ -335,26 +604,29 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
     red[4 * wave + 1] = c1;
     red[4 * wave + 2] = s2;
     red[4 * wave + 3] = c2;
-    ured[2 * wave] = npass;
-    ured[2 * wave + 1] = nterms;
+    ured[3 * wave] = npass;
+    ured[3 * wave + 1] = nterms;
+    ured[3 * wave + 2] = nfb;
   }
   __syncthreads();
   if (tid == 0) {
     double S1 = red[0], C1 = red[1], S2 = red[2], C2 = red[3];
-    uint64_t P1 = ured[0], P2 = ured[1];
+    uint64_t P1 = ured[0], P2 = ured[1], P0 = ured[2];
     for (int w = 1; w < (bs >> 6); ++w) {
       pair_merge(S1, C1, red[4 * w + 0], red[4 * w + 1]);
       pair_merge(S2, C2, red[4 * w + 2], red[4 * w + 3]);
-      P1 += ured[2 * w];
-      P2 += ured[2 * w + 1];
+      P1 += ured[3 * w];
+      P2 += ured[3 * w + 1];
+      P0 += ured[3 * w + 2];
     }
-    double *P = a.partials + 4 * static_cast<size_t>(item);
-    P[0] = S1;
-    P[1] = C1;
-    P[2] = S2;
-    P[3] = C2;
-    uint64_t *K = a.counters + kItemCounters * static_cast<size_t>(item);
-    K[0] = 0;
+    const size_t store = static_cast<size_t>(T->store_begin) + (item - T->item_begin);
+    double *part = a.partials + 4 * store;
+    part[0] = S1;
+    part[1] = C1;
+    part[2] = S2;
+    part[3] = C2;
+    uint64_t *K = a.counters + kItemCounters * store;
+    K[0] = P0;
     K[1] = P1;
     K[2] = P2;
   }
@@ -367,14 +639,17 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 }
 
 // One task per launch: block b processes work item item_begin + b.
-template <int ORDER, int Q>
+template <int ORDER, int Q, int P>
 __global__ __launch_bounds__(256) void sample_single(KArgs a, int t) {
   extern __shared__ double smem[];
-  process_item<ORDER, Q>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
+  process_item<ORDER, Q, P>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
 }
 
-// Persistent launch over all work items of all tasks (items grouped by task).
-template <int Q>
+// Persistent launch over all work items of all tasks (items grouped by task,
+// task t owning items [item_begin, item_begin + nitems)).  MAXO is the highest
+// order present, so the register allocation of a batch is that of its largest
+// diagrams and not of fifth order.
+template <int Q, int P, int MAXO>
 __global__ __launch_bounds__(256) void sample_batched(KArgs a) {
   extern __shared__ double smem[];
   for (int item = blockIdx.x; item < a.total_items; item += gridDim.x) {
@@ -385,13 +660,12 @@ __global__ __launch_bounds__(256) void sample_batched(KArgs a) {
       else hi = mid - 1;
     }
     const int t = lo;
-    switch (a.tasks[t].order) {
-      case 1: process_item<1, Q>(a, t, item, smem); break;
-      case 2: process_item<2, Q>(a, t, item, smem); break;
-      case 3: process_item<3, Q>(a, t, item, smem); break;
-      case 4: process_item<4, Q>(a, t, item, smem); break;
-      default: process_item<5, Q>(a, t, item, smem); break;
-    }
+    const int order = a.tasks[t].order;
+    if (order == 1) process_item<1, Q, P>(a, t, item, smem);
+    else if (MAXO >= 2 && order == 2) process_item<(MAXO >= 2 ? 2 : 1), Q, P>(a, t, item, smem);
+    else if (MAXO >= 3 && order == 3) process_item<(MAXO >= 3 ? 3 : 1), Q, P>(a, t, item, smem);
+    else if (MAXO >= 4 && order == 4) process_item<(MAXO >= 4 ? 4 : 1), Q, P>(a, t, item, smem);
+    else if (MAXO >= 5 && order == 5) process_item<(MAXO >= 5 ? 5 : 1), Q, P>(a, t, item, smem);
   }
 }
 
@@ -505,7 +779,7 @@ __global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task,
   const int tid = threadIdx.x, bs = blockDim.x;
   double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
   unsigned long long kc[kItemCounters] = {0, 0, 0};
-  for (int it = T->item_begin + tid; it < T->item_begin + T->nitems; it += bs) {
+  for (int it = T->store_begin + tid; it < T->store_begin + T->nitems; it += bs) {
     const double *P = a.partials + 4 * static_cast<size_t>(it);
     pair_merge(s1, c1, P[0], P[1]);
     pair_merge(s2, c2, P[2], P[3]);
@@ -581,7 +855,7 @@ __global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task,
 // ---------------------------------------------------------------------------
 // Per-sample dump for parity checks: thread i evaluates sample first + i.
 
-template <int ORDER, int Q>
+template <int ORDER, int Q, int P>
 __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t iter, uint64_t first,
                                                    uint64_t count, double *out) {
   extern __shared__ double smem[];
@@ -600,14 +874,14 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
   const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < count) {
     int bins[ND];
-    uint32_t np = 0, nt = 0;
-    out[i] = eval_fp64<ORDER, Q>(a, T, D, g, first + i, iter, bins, np, nt);
+    uint32_t np = 0, nt = 0, nf = 0;
+    out[i] = eval_sample<ORDER, Q, P>(a, T, D, g, first + i, iter, bins, np, nt, nf);
   }
 }
 
 // Reset grids to uniform, histograms and running state to zero.
-__global__ void init_tasks(KArgs a) {
-  TaskDev *T = a.tasks + blockIdx.x;
+__global__ void init_tasks(KArgs a, int first) {
+  TaskDev *T = a.tasks + first + blockIdx.x;
   const int nb = a.phys.nb;
   for (int i = threadIdx.x; i < T->nd * (nb + 1); i += blockDim.x) {
     const int b = i % (nb + 1);
@@ -629,36 +903,56 @@ __global__ void init_tasks(KArgs a) {
 // Host-side launchers
 
 size_t sample_lds_bytes(int nd, int nb, int block) {
-  return (3 * static_cast<size_t>(nd) * nb + 5 * (block / 64)) * sizeof(double);
+  // grid (e, width) pairs + histogram + reduction scratch + fp64 re-evaluation
+  // queue (128 sample offsets per wavefront)
+  return (3 * static_cast<size_t>(nd) * nb + 6 * (block / 64)) * sizeof(double) +
+         (block / 64) * 128 * sizeof(uint32_t);
 }
 
-template <int Q>
+template <int Q, int P>
 static hipError_t single_q(const KArgs &a, int t, int order, int nitems, int block,
                            hipStream_t st) {
   const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block);
   switch (order) {
-    case 1: hipLaunchKernelGGL((sample_single<1, Q>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 2: hipLaunchKernelGGL((sample_single<2, Q>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 3: hipLaunchKernelGGL((sample_single<3, Q>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 4: hipLaunchKernelGGL((sample_single<4, Q>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 5: hipLaunchKernelGGL((sample_single<5, Q>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 1: hipLaunchKernelGGL((sample_single<1, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 2: hipLaunchKernelGGL((sample_single<2, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 3: hipLaunchKernelGGL((sample_single<3, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 4: hipLaunchKernelGGL((sample_single<4, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 5: hipLaunchKernelGGL((sample_single<5, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int nitems, int block,
-                                hipStream_t st) {
-  return q == 4 ? single_q<4>(a, t, order, nitems, block, st)
-                : single_q<2>(a, t, order, nitems, block, st);
+hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int prec, int nitems,
+                                int block, hipStream_t st) {
+  if (q == 4) return prec ? single_q<4, 1>(a, t, order, nitems, block, st)
+                          : single_q<4, 0>(a, t, order, nitems, block, st);
+  return prec ? single_q<2, 1>(a, t, order, nitems, block, st)
+              : single_q<2, 0>(a, t, order, nitems, block, st);
 }
 
-hipError_t launch_sample_batched(const KArgs &a, int q, int max_nd, int grid, int block,
+template <int Q, int P>
+static hipError_t batched_qp(const KArgs &a, int maxo, int grid, int block, size_t lds,
+                             hipStream_t st) {
+  switch (maxo) {
+    case 1:
+    case 2: hipLaunchKernelGGL((sample_batched<Q, P, 2>), dim3(grid), dim3(block), lds, st, a); break;
+    case 3: hipLaunchKernelGGL((sample_batched<Q, P, 3>), dim3(grid), dim3(block), lds, st, a); break;
+    case 4: hipLaunchKernelGGL((sample_batched<Q, P, 4>), dim3(grid), dim3(block), lds, st, a); break;
+    default: hipLaunchKernelGGL((sample_batched<Q, P, 5>), dim3(grid), dim3(block), lds, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_batched(const KArgs &a, int q, int prec, int max_nd, int grid, int block,
                                  hipStream_t st) {
   const size_t lds = sample_lds_bytes(max_nd, a.phys.nb, block);
-  if (q == 4) hipLaunchKernelGGL((sample_batched<4>), dim3(grid), dim3(block), lds, st, a);
-  else hipLaunchKernelGGL((sample_batched<2>), dim3(grid), dim3(block), lds, st, a);
-  return hipGetLastError();
+  const int maxo = max_nd / 3 - 1;
+  if (q == 4) return prec ? batched_qp<4, 1>(a, maxo, grid, block, lds, st)
+                          : batched_qp<4, 0>(a, maxo, grid, block, lds, st);
+  return prec ? batched_qp<2, 1>(a, maxo, grid, block, lds, st)
+              : batched_qp<2, 0>(a, maxo, grid, block, lds, st);
 }
 
 hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int max_nd, double alpha,
@@ -669,39 +963,53 @@ hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int max_nd,
   return hipGetLastError();
 }
 
-template <int Q>
+template <int Q, int P>
 static hipError_t dump_q(const KArgs &a, int t, int order, uint32_t iter, uint64_t first,
                          uint64_t count, double *out, hipStream_t st) {
   const int block = 256;
   const dim3 grid(static_cast<unsigned>((count + block - 1) / block));
   const size_t lds = 2 * static_cast<size_t>(3 * (order + 1)) * a.phys.nb * sizeof(double);
   switch (order) {
-    case 1: hipLaunchKernelGGL((dump_samples<1, Q>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
-    case 2: hipLaunchKernelGGL((dump_samples<2, Q>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
-    case 3: hipLaunchKernelGGL((dump_samples<3, Q>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
-    case 4: hipLaunchKernelGGL((dump_samples<4, Q>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
-    case 5: hipLaunchKernelGGL((dump_samples<5, Q>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
+    case 1: hipLaunchKernelGGL((dump_samples<1, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
+    case 2: hipLaunchKernelGGL((dump_samples<2, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
+    case 3: hipLaunchKernelGGL((dump_samples<3, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
+    case 4: hipLaunchKernelGGL((dump_samples<4, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
+    case 5: hipLaunchKernelGGL((dump_samples<5, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_dump(const KArgs &a, int t, int order, int q, uint32_t iter, uint64_t first,
-                       uint64_t count, double *out, hipStream_t st) {
-  return q == 4 ? dump_q<4>(a, t, order, iter, first, count, out, st)
-                : dump_q<2>(a, t, order, iter, first, count, out, st);
+hipError_t launch_dump(const KArgs &a, int t, int order, int q, int prec, uint32_t iter,
+                       uint64_t first, uint64_t count, double *out, hipStream_t st) {
+  if (q == 4) return prec ? dump_q<4, 1>(a, t, order, iter, first, count, out, st)
+                          : dump_q<4, 0>(a, t, order, iter, first, count, out, st);
+  return prec ? dump_q<2, 1>(a, t, order, iter, first, count, out, st)
+              : dump_q<2, 0>(a, t, order, iter, first, count, out, st);
 }
 
-int batched_occupancy(int q, int block, size_t lds) {
+template <int Q, int P>
+static int occ_qp(int maxo, int block, size_t lds) {
   int n = 0;
-  const hipError_t e =
-      q == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<4>, block, lds)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<2>, block, lds);
+  hipError_t e;
+  switch (maxo) {
+    case 1:
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<Q, P, 2>, block, lds); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<Q, P, 3>, block, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<Q, P, 4>, block, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<Q, P, 5>, block, lds); break;
+  }
   return e == hipSuccess ? n : 1;
 }
 
-hipError_t launch_init(const KArgs &a, int ntasks, hipStream_t st) {
-  hipLaunchKernelGGL(init_tasks, dim3(ntasks), dim3(256), 0, st, a);
+int batched_occupancy(int q, int prec, int max_nd, int block, size_t lds) {
+  const int maxo = max_nd / 3 - 1;
+  if (q == 4) return prec ? occ_qp<4, 1>(maxo, block, lds) : occ_qp<4, 0>(maxo, block, lds);
+  return prec ? occ_qp<2, 1>(maxo, block, lds) : occ_qp<2, 0>(maxo, block, lds);
+}
+
+hipError_t launch_init(const KArgs &a, int first, int ntasks, hipStream_t st) {
+  hipLaunchKernelGGL(init_tasks, dim3(ntasks), dim3(256), 0, st, a, first);
   return hipGetLastError();
 }
 

@@ -181,6 +181,57 @@ extern "C" int mbpt_diagram_label_stats(int order, int id, int matter, int *n_as
 
 namespace mbpt {
 
+// Descriptor fields derived from the diagram alone (loop radii, masks,
+// prefactor with the (2 pi)^{-3L} measure).
+void fill_diag_dev(const Diagram &diag, DiagDev &dd) {
+  const Diagram *d = &diag;
+  for (int j = 0; j < d->nloops; ++j) dd.loop_part[j] = d->particle[d->loop_line[j]] ? 1 : 0;
+  dd.part_mask = 0;
+  for (int l = 0; l < d->nlines; ++l)
+    if (d->particle[l]) dd.part_mask |= 1u << l;
+  dd.line_mask = (1u << d->nlines) - 1u;
+  dd.pref = d->prefactor * std::pow(2.0 * M_PI, -3.0 * d->nloops);
+  auto pack = [&](const int *c) {
+    uint32_t m = 0;
+    for (int j = 0; j < d->nloops; ++j) {
+      if (c[j] == 1) m |= 1u << j;
+      else if (c[j] == -1) m |= 1u << (8 + j);
+      else if (c[j] == 2) m |= 1u << (16 + j);
+      else if (c[j] == -2) m |= 1u << (24 + j);
+    }
+    return m;
+  };
+  for (int l = 0; l < d->nlines; ++l) dd.lmask[l] = pack(d->coef[l]);
+  for (int v = 0; v < d->order; ++v) {
+    int cp[kMaxLoops], cq[kMaxLoops];
+    for (int j = 0; j < d->nloops; ++j) {
+      cp[j] = d->coef[d->vout[v][0]][j] - d->coef[d->vout[v][1]][j];
+      cq[j] = d->coef[d->vin[v][0]][j] - d->coef[d->vin[v][1]][j];
+    }
+    dd.pmask_v[v] = pack(cp);
+    dd.qmask_v[v] = pack(cq);
+  }
+  for (int c = 0; c < d->ncuts; ++c)
+    for (int l = 0; l < d->nlines; ++l) {
+      if (d->cut[c][l] > 0) dd.cut_hole[c] |= 1u << l;
+      if (d->cut[c][l] < 0) dd.cut_part[c] |= 1u << l;
+    }
+}
+
+// Medium-dependent task fields: Fermi momenta, loop radii, 1/density, bands.
+void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T) {
+  const double kFn = std::cbrt(3.0 * M_PI * M_PI * ((1.0 - x) * density));
+  const double kFp = std::cbrt(3.0 * M_PI * M_PI * (x * density));
+  T.kF2[0] = kFn * kFn;
+  T.kF2[1] = kFp * kFp;
+  const double kFmax = std::max(kFn, kFp);
+  T.Rh = kFmax;
+  T.Rp = kFmax + ctx->desc.kcut_extra * ctx->v.Lambda;
+  T.inv_density = 1.0 / density;
+  T.band_k = ctx->desc.fp32_band_k;
+  T.band_d = ctx->desc.fp32_band_d;
+}
+
 // Compile a task list's diagrams into device tables (one descriptor per
 // distinct (order, id)).
 int compile_tables(mbpt_task_set *set) {
@@ -215,37 +266,7 @@ int compile_tables(mbpt_task_set *set) {
     dd.group_off = static_cast<int>(set->groups.size());
     dd.term_off = static_cast<int>(set->terms.size());
     dd.nterms = static_cast<int>(ll.terms.size());
-    for (int j = 0; j < d->nloops; ++j) dd.loop_part[j] = d->particle[d->loop_line[j]] ? 1 : 0;
-    dd.part_mask = 0;
-    for (int l = 0; l < d->nlines; ++l)
-      if (d->particle[l]) dd.part_mask |= 1u << l;
-    dd.line_mask = (1u << d->nlines) - 1u;
-    dd.pref = d->prefactor * std::pow(2.0 * M_PI, -3.0 * d->nloops);
-    auto pack = [&](const int *c) {
-      uint32_t m = 0;
-      for (int j = 0; j < d->nloops; ++j) {
-        if (c[j] == 1) m |= 1u << j;
-        else if (c[j] == -1) m |= 1u << (8 + j);
-        else if (c[j] == 2) m |= 1u << (16 + j);
-        else if (c[j] == -2) m |= 1u << (24 + j);
-      }
-      return m;
-    };
-    for (int l = 0; l < d->nlines; ++l) dd.lmask[l] = pack(d->coef[l]);
-    for (int v = 0; v < d->order; ++v) {
-      int cp[kMaxLoops], cq[kMaxLoops];
-      for (int j = 0; j < d->nloops; ++j) {
-        cp[j] = d->coef[d->vout[v][0]][j] - d->coef[d->vout[v][1]][j];
-        cq[j] = d->coef[d->vin[v][0]][j] - d->coef[d->vin[v][1]][j];
-      }
-      dd.pmask_v[v] = pack(cp);
-      dd.qmask_v[v] = pack(cq);
-    }
-    for (int c = 0; c < d->ncuts; ++c)
-      for (int l = 0; l < d->nlines; ++l) {
-        if (d->cut[c][l] > 0) dd.cut_hole[c] |= 1u << l;
-        if (d->cut[c][l] < 0) dd.cut_part[c] |= 1u << l;
-      }
+    fill_diag_dev(*d, dd);
     // isospin groups: terms sorted by tau
     for (size_t i = 0; i < ll.terms.size();) {
       size_t j = i;
@@ -262,6 +283,7 @@ int compile_tables(mbpt_task_set *set) {
       TermDev tm{};
       tm.mult = lt.mult;
       tm.codes = lt.codes;
+      tm.multf = static_cast<float>(lt.mult);
       set->terms.push_back(tm);
     }
     FlopModel fm;
@@ -298,17 +320,7 @@ void fill_task_params(mbpt_task_set *set) {
     T.res_cap = set->max_iters;
     T.key = td.task_key;
     T.order = td.order;
-    const double x = td.proton_fraction;
-    const double kFn = std::cbrt(3.0 * M_PI * M_PI * ((1.0 - x) * td.density));
-    const double kFp = std::cbrt(3.0 * M_PI * M_PI * (x * td.density));
-    T.kF2[0] = kFn * kFn;
-    T.kF2[1] = kFp * kFp;
-    const double kFmax = std::max(kFn, kFp);
-    T.Rh = kFmax;
-    T.Rp = kFmax + ctx->desc.kcut_extra * ctx->v.Lambda;
-    T.inv_density = 1.0 / td.density;
-    T.band_k = ctx->desc.fp32_band_k;
-    T.band_d = ctx->desc.fp32_band_d;
+    fill_medium(ctx, td.density, td.proton_fraction, T);
     T.active = 1;
   }
   set->grid_doubles = goff;
@@ -433,7 +445,7 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
   int rc = upload_params(set);
   if (rc) return rc;
   KArgs a = kargs_of(set);
-  HIPCHK(ctx, launch_init(a, static_cast<int>(set->tasks.size()), ctx->stream));
+  HIPCHK(ctx, launch_init(a, 0, static_cast<int>(set->tasks.size()), ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   set->drop_graph();
   set->last_state.clear();
@@ -629,7 +641,7 @@ extern "C" int mbpt_reset(mbpt_task_set *set) {
   if (!set->ws) return MBPT_ESTATE;
   mbpt_context *ctx = set->ctx;
   KArgs a = kargs_of(set);
-  HIPCHK(ctx, launch_init(a, static_cast<int>(set->tasks.size()), ctx->stream));
+  HIPCHK(ctx, launch_init(a, 0, static_cast<int>(set->tasks.size()), ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   set->last_state.clear();
   return MBPT_OK;
@@ -647,7 +659,7 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
       for (int it = 0; it < iters; ++it) {
         size_t slot = 0;
         if (timed) timed_begin(ctx, slot);
-        HIPCHK(ctx, launch_sample_single(a, t, set->tasks[t].order, set->q,
+        HIPCHK(ctx, launch_sample_single(a, t, set->tasks[t].order, set->q, ctx->desc.precision,
                                          set->h_tasks[t].nitems, set->block, ctx->stream));
         if (timed) timed_end(ctx, slot);
         HIPCHK(ctx, launch_finish(a, t, 1, 3 * (set->tasks[t].order + 1), alpha, ctx->stream));
@@ -657,8 +669,8 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
   for (int it = 0; it < iters; ++it) {
     size_t slot = 0;
     if (timed) timed_begin(ctx, slot);
-    HIPCHK(ctx, launch_sample_batched(a, set->q, set->max_nd, set->grid_blocks, set->block,
-                                      ctx->stream));
+    HIPCHK(ctx, launch_sample_batched(a, set->q, ctx->desc.precision, set->max_nd,
+                                      set->grid_blocks, set->block, ctx->stream));
     if (timed) timed_end(ctx, slot);
     HIPCHK(ctx, launch_finish(a, 0, nt, set->max_nd, alpha, ctx->stream));
   }
@@ -670,7 +682,7 @@ int persistent_grid(mbpt_task_set *set, int total_items) {
   int per_cu = 0;
   const size_t lds = sample_lds_bytes(set->max_nd, ctx->desc.n_bins, set->block);
   // occupancy of the fused kernel (register and LDS limited)
-  per_cu = batched_occupancy(set->q, set->block, lds);
+  per_cu = batched_occupancy(set->q, ctx->desc.precision, set->max_nd, set->block, lds);
   if (per_cu < 1) per_cu = 1;
   const int g = per_cu * std::max(1, ctx->num_cus);
   return std::max(1, std::min(total_items, g));
@@ -703,6 +715,7 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
     TaskDev &T = set->h_tasks[t];
     changed |= T.item_begin != item || T.nitems != per || T.nsamples != samples_per_iter;
     T.item_begin = item;
+    T.store_begin = item;
     T.nitems = per;
     T.nsamples = samples_per_iter;
     item += per;
@@ -820,8 +833,8 @@ extern "C" int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, ui
   const uint64_t cap = set->max_items * 4;
   for (uint64_t done = 0; done < count;) {
     const uint64_t n = std::min<uint64_t>(cap, count - done);
-    HIPCHK(ctx, launch_dump(a, task, set->tasks[task].order, set->q, iter, first + done, n,
-                            set->d_partials, ctx->stream));
+    HIPCHK(ctx, launch_dump(a, task, set->tasks[task].order, set->q, ctx->desc.precision, iter,
+                            first + done, n, set->d_partials, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(w_host + done, set->d_partials, n * sizeof(double),
                                hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));

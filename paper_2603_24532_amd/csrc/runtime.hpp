@@ -73,7 +73,21 @@ struct mbpt_task_set {
 };
 
 namespace mbpt {
+struct Diagram;
 void set_err(mbpt_context *ctx, const std::string &msg);
 int hip_fail(mbpt_context *ctx, hipError_t e, const char *what);
-int batched_occupancy(int q, int block, size_t lds);
+void count_flops(const Diagram &d, int q, int half_exp, FlopModel &f);
+void fill_diag_dev(const Diagram &d, DiagDev &dd);
+void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T);
+void result_of(const TaskDev &S, mbpt_result &r);
+void timed_begin(mbpt_context *ctx, size_t &slot);
+void timed_end(mbpt_context *ctx, size_t slot);
+void resolve_timing(mbpt_context *ctx);
+int batched_occupancy(int q, int prec, int max_nd, int block, size_t lds);
 }  // namespace mbpt
+
+#define MBPT_HIPCHK(ctx, call)                                      \
+  do {                                                              \
+    hipError_t e_ = (call);                                         \
+    if (e_ != hipSuccess) return ::mbpt::hip_fail(ctx, e_, #call);  \
+  } while (0)

@@ -1,23 +1,456 @@
-// Continuous-batching server (see include/mbpt_vegas.h).
+// Continuous-batching server for EOS-point requests (see include/mbpt_vegas.h).
+//
+// Layout of the caller's workspace: a slot table (TaskDev, DiagDev, grid,
+// histogram and iteration log per slot), two parallel per-work-item regions
+// (partial sums, counters) indexed by a storage index, and a byte arena for
+// the isospin groups and label terms of each resident request.  Storage-index
+// ranges and arena bytes are handed out first-fit and returned at retirement;
+// both are bookkept on the host.
+//
+// One round (mbpt_server_step): admit queued requests in arrival order while a
+// slot is free and there is room for the head request's items and terms; run
+// one VEGAS iteration for every resident request with a single persistent
+// launch plus the iteration-end launch; copy the task states back; retire
+// requests whose sigma reached max(sigma_rel |E|, sigma_abs) after at least
+// kMinIters iterations, or whose evaluations reached max_evals.  A request
+// samples its own Philox stream (key = ticket), so its result does not depend
+// on what else is resident.  Requests run through the spin x isospin kernel; a
+// neutron-matter request runs at proton fraction 0, where that label sum equals
+// the spin-only one sample by sample.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <vector>
+
+#include "diagrams.hpp"
+#include "device_types.hpp"
+#include "kernels.hpp"
 #include "mbpt_vegas.h"
 #include "runtime.hpp"
 
-extern "C" int mbpt_server_workspace_query(const mbpt_context *, int, uint64_t, size_t *) {
-  return MBPT_ESTATE;
+using namespace mbpt;
+
+namespace {
+
+constexpr int kMinIters = 3;
+constexpr int kBlock = 256;
+constexpr int kSpt = 16;
+constexpr size_t kTermBytesPerSlot = 64 * 1024;
+
+size_t a256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// First-fit allocator over [base, base + size) in arbitrary units.
+struct Ranges {
+  std::map<size_t, size_t> free_;  // start -> length
+  void init(size_t base, size_t size) {
+    free_.clear();
+    if (size) free_[base] = size;
+  }
+  bool alloc(size_t n, size_t &at) {
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n) {
+        at = it->first;
+        const size_t rest = it->second - n;
+        free_.erase(it);
+        if (rest) free_[at + n] = rest;
+        return true;
+      }
+    return false;
+  }
+  void release(size_t at, size_t n) {
+    if (!n) return;
+    auto it = free_.emplace(at, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Req {
+  mbpt_request r{};
+  uint64_t ticket = 0;
+  int state = 0;  // 0 queued, 1 resident, 2 done
+  int slot = -1;
+  double t_submit = 0, t_admit = -1, t_finish = -1;
+  mbpt_result res{};
+  size_t item_at = 0, item_n = 0, byte_at = 0, byte_n = 0;
+};
+
+struct Layout {
+  size_t tasks, diags, grids, hists, reslog, partials, counters, arena, arena_bytes;
+  size_t max_items;
+};
+
+size_t items_of(uint64_t samples) {
+  const uint64_t chunk = static_cast<uint64_t>(kBlock) * kSpt;
+  return static_cast<size_t>((samples + chunk - 1) / chunk);
 }
-extern "C" int mbpt_server_create(mbpt_context *ctx, int, uint64_t, int, void *, size_t,
-                                  mbpt_server **) {
-  mbpt::set_err(ctx, "server not available in this build");
-  return MBPT_ESTATE;
+
+size_t slot_table_bytes(int slots, int nb) {
+  return a256(slots * sizeof(TaskDev)) + a256(slots * sizeof(DiagDev)) +
+         a256(static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double)) +
+         a256(static_cast<size_t>(slots) * kMaxDim * nb * sizeof(double)) +
+         a256(static_cast<size_t>(slots) * 2 * sizeof(double));
 }
-extern "C" void mbpt_server_destroy(mbpt_server *) {}
-extern "C" int mbpt_server_submit(mbpt_server *, const mbpt_request *, uint64_t *) {
-  return MBPT_ESTATE;
+
+// Slot table first, then the term arena (kTermBytesPerSlot per slot), then
+// the item regions filling the rest.
+bool make_layout(int slots, int nb, size_t bytes, Layout &L) {
+  size_t off = 0;
+  L.tasks = off;
+  off = a256(off + slots * sizeof(TaskDev));
+  L.diags = off;
+  off = a256(off + slots * sizeof(DiagDev));
+  L.grids = off;
+  off = a256(off + static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double));
+  L.hists = off;
+  off = a256(off + static_cast<size_t>(slots) * kMaxDim * nb * sizeof(double));
+  L.reslog = off;
+  off = a256(off + static_cast<size_t>(slots) * 2 * sizeof(double));
+  L.arena = off;
+  L.arena_bytes = static_cast<size_t>(slots) * kTermBytesPerSlot;
+  off += L.arena_bytes;
+  if (bytes <= off + 512) return false;
+  const size_t per_item = 4 * sizeof(double) + kItemCounters * sizeof(uint64_t);
+  L.max_items = (bytes - off - 512) / per_item;
+  if (L.max_items > 0x7fffffffull) L.max_items = 0x7fffffffull;
+  L.partials = a256(off);
+  L.counters = a256(L.partials + L.max_items * 4 * sizeof(double));
+  return L.counters + L.max_items * kItemCounters * sizeof(uint64_t) <= bytes;
 }
-extern "C" int mbpt_server_step(mbpt_server *, int *, int *) { return MBPT_ESTATE; }
-extern "C" int mbpt_server_poll(mbpt_server *, uint64_t, mbpt_result *, int *, double *, double *,
-                                double *) {
-  return MBPT_ESTATE;
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct mbpt_server {
+  mbpt_context *ctx = nullptr;
+  int max_slots = 0, max_queue = 0;
+  uint64_t max_samples = 0;
+  char *ws = nullptr;
+  Layout L{};
+  Ranges items, bytes;
+  std::vector<int64_t> slot_req;  // ticket per slot, -1 if free
+  std::vector<TaskDev> h_tasks;
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, Req> reqs;
+  uint64_t next_ticket = 1;
+  std::chrono::steady_clock::time_point t0;
+  std::vector<FlopModel> flops;
+};
+
+namespace {
+
+KArgs server_kargs(const mbpt_server *s) {
+  const mbpt_context *ctx = s->ctx;
+  char *b = s->ws;
+  KArgs a{};
+  a.tasks = reinterpret_cast<TaskDev *>(b + s->L.tasks);
+  a.diags = reinterpret_cast<DiagDev *>(b + s->L.diags);
+  // group / term offsets of a descriptor are element indices from the
+  // workspace base
+  a.groups = reinterpret_cast<const GroupDev *>(b);
+  a.terms = reinterpret_cast<const TermDev *>(b);
+  a.grids = reinterpret_cast<double *>(b + s->L.grids);
+  a.hists = reinterpret_cast<double *>(b + s->L.hists);
+  a.partials = reinterpret_cast<double *>(b + s->L.partials);
+  a.counters = reinterpret_cast<uint64_t *>(b + s->L.counters);
+  a.reslog = reinterpret_cast<double *>(b + s->L.reslog);
+  a.ntasks = s->max_slots;
+  a.spt = kSpt;
+  const mbpt_interaction &v = ctx->v;
+  a.phys.V0 = v.C0 * v.hbarc;
+  a.phys.Vy = v.Cy * v.hbarc;
+  a.phys.m2 = v.mpi * v.mpi;
+  a.phys.invLn = std::pow(v.Lambda, -static_cast<double>(v.reg_exp));
+  a.phys.hb2m = 0.5 * v.hbar2_m;
+  a.phys.half_exp = v.reg_exp / 2;
+  a.phys.nb = ctx->desc.n_bins;
+  a.phys.seed = ctx->desc.seed;
+  return a;
+}
+
+// Returns 0 when admitted, 1 when it does not fit now, < 0 on a HIP error.
+int admit_one(mbpt_server *s, Req &q, int slot) {
+  mbpt_context *ctx = s->ctx;
+  const Diagram *d = get_diagram(q.r.order, q.r.diagram_id);
+  const LabelList ll = build_labels(*d, 4);
+  std::vector<GroupDev> groups;
+  std::vector<TermDev> terms;
+  for (size_t i = 0; i < ll.terms.size();) {
+    size_t j = i;
+    while (j < ll.terms.size() && ll.terms[j].tau_mask == ll.terms[i].tau_mask) ++j;
+    GroupDev g{};
+    g.tau = ll.terms[i].tau_mask;
+    g.first = static_cast<int>(i);  // rebased below
+    g.count = static_cast<int>(j - i);
+    groups.push_back(g);
+    i = j;
+  }
+  for (const auto &lt : ll.terms) {
+    TermDev tm{};
+    tm.mult = lt.mult;
+    tm.codes = lt.codes;
+    tm.multf = static_cast<float>(lt.mult);
+    terms.push_back(tm);
+  }
+  const size_t gbytes = a256(groups.size() * sizeof(GroupDev));
+  const size_t need_bytes = gbytes + a256(terms.size() * sizeof(TermDev));
+  const size_t need_items = items_of(q.r.samples_per_iter);
+  size_t byte_at = 0, item_at = 0;
+  if (!s->bytes.alloc(need_bytes, byte_at)) return 1;
+  if (!s->items.alloc(need_items, item_at)) {
+    s->bytes.release(byte_at, need_bytes);
+    return 1;
+  }
+  q.byte_at = byte_at;
+  q.byte_n = need_bytes;
+  q.item_at = item_at;
+  q.item_n = need_items;
+  const size_t g_off = s->L.arena + byte_at;  // byte offsets from the workspace base
+  const size_t t_off = g_off + gbytes;
+  const int t_index = static_cast<int>(t_off / sizeof(TermDev));
+  for (auto &g : groups) g.first += t_index;
+  DiagDev dd{};
+  dd.order = d->order;
+  dd.nlines = d->nlines;
+  dd.nloops = d->nloops;
+  dd.ncuts = d->ncuts;
+  dd.group_off = static_cast<int>(g_off / sizeof(GroupDev));
+  dd.ngroups = static_cast<int>(groups.size());
+  dd.term_off = t_index;
+  dd.nterms = static_cast<int>(terms.size());
+  fill_diag_dev(*d, dd);
+  TaskDev T{};
+  T.diag = slot;
+  T.nd = d->ndim;
+  T.grid_off = slot * kMaxDim * (ctx->desc.n_bins + 1);
+  T.hist_off = slot * kMaxDim * ctx->desc.n_bins;
+  T.res_off = slot;
+  T.res_cap = 1;
+  T.key = static_cast<uint32_t>(q.ticket);
+  T.order = d->order;
+  T.nsamples = q.r.samples_per_iter;
+  T.nitems = static_cast<int>(need_items);
+  T.store_begin = static_cast<int>(item_at);
+  const double x = q.r.matter == MBPT_NUCLEAR ? q.r.proton_fraction : 0.0;
+  fill_medium(ctx, q.r.density, x, T);
+  T.active = 1;
+  s->h_tasks[slot] = T;
+  char *b = s->ws;
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + g_off, groups.data(), groups.size() * sizeof(GroupDev),
+                                  hipMemcpyHostToDevice, ctx->stream));
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + t_off, terms.data(), terms.size() * sizeof(TermDev),
+                                  hipMemcpyHostToDevice, ctx->stream));
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.diags + slot * sizeof(DiagDev), &dd, sizeof(DiagDev),
+                                  hipMemcpyHostToDevice, ctx->stream));
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.tasks + slot * sizeof(TaskDev), &s->h_tasks[slot],
+                                  sizeof(TaskDev), hipMemcpyHostToDevice, ctx->stream));
+  KArgs a = server_kargs(s);
+  MBPT_HIPCHK(ctx, launch_init(a, slot, 1, ctx->stream));
+  // the copies above read host memory that is reused: wait for them
+  MBPT_HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  FlopModel fm;
+  count_flops(*d, 4, ctx->v.reg_exp / 2, fm);
+  s->flops[slot] = fm;
+  q.state = 1;
+  q.slot = slot;
+  q.t_admit = now_s(s->t0);
+  s->slot_req[slot] = static_cast<int64_t>(q.ticket);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int mbpt_server_workspace_query(const mbpt_context *ctx, int max_slots,
+                                           uint64_t max_samples_per_iter, size_t *bytes) {
+  if (!ctx || !bytes || max_slots < 1 || max_samples_per_iter < 2) return MBPT_EINVAL;
+  const size_t per_item = 4 * sizeof(double) + kItemCounters * sizeof(uint64_t);
+  *bytes = slot_table_bytes(max_slots, ctx->desc.n_bins) +
+           static_cast<size_t>(max_slots) * kTermBytesPerSlot +
+           static_cast<size_t>(max_slots) * items_of(max_samples_per_iter) * per_item + 2048;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max_samples_per_iter,
+                                  int max_queue, void *device_ptr, size_t bytes,
+                                  mbpt_server **out) {
+  if (!ctx || !out || max_slots < 1 || max_samples_per_iter < 2 || max_queue < 1 || !device_ptr ||
+      (reinterpret_cast<uintptr_t>(device_ptr) & 255u))
+    return MBPT_EINVAL;
+  *out = nullptr;
+  Layout L{};
+  if (!make_layout(max_slots, ctx->desc.n_bins, bytes, L) ||
+      L.max_items < items_of(max_samples_per_iter)) {
+    set_err(ctx, "server_create: workspace too small for the slot table and one request");
+    return MBPT_ENOMEM;
+  }
+  auto *s = new mbpt_server();
+  s->ctx = ctx;
+  s->max_slots = max_slots;
+  s->max_queue = max_queue;
+  s->max_samples = max_samples_per_iter;
+  s->ws = static_cast<char *>(device_ptr);
+  s->L = L;
+  s->items.init(0, L.max_items);
+  s->bytes.init(0, L.arena_bytes);
+  s->slot_req.assign(max_slots, -1);
+  s->h_tasks.assign(max_slots, TaskDev{});
+  s->flops.assign(max_slots, FlopModel{});
+  s->t0 = std::chrono::steady_clock::now();
+  if (hipMemcpyAsync(s->ws + L.tasks, s->h_tasks.data(), max_slots * sizeof(TaskDev),
+                     hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    set_err(ctx, "server_create: HIP copy failed");
+    delete s;
+    return MBPT_EHIP;
+  }
+  *out = s;
+  return MBPT_OK;
+}
+
+extern "C" void mbpt_server_destroy(mbpt_server *s) { delete s; }
+
+extern "C" int mbpt_server_submit(mbpt_server *s, const mbpt_request *req, uint64_t *ticket) {
+  if (!s || !req || !ticket) return MBPT_EINVAL;
+  mbpt_context *ctx = s->ctx;
+  const Diagram *d = get_diagram(req->order, req->diagram_id);
+  if (!d || !(req->density > 0) || !(req->proton_fraction >= 0 && req->proton_fraction <= 1) ||
+      (req->matter != MBPT_NEUTRON && req->matter != MBPT_NUCLEAR) ||
+      (req->matter == MBPT_NEUTRON && req->proton_fraction != 0.0) || req->samples_per_iter < 2 ||
+      req->samples_per_iter > s->max_samples || !(req->sigma_rel >= 0) || !(req->sigma_abs >= 0)) {
+    set_err(ctx, "server_submit: invalid request");
+    return MBPT_EINVAL;
+  }
+  if (static_cast<int>(s->queue.size()) >= s->max_queue) {
+    set_err(ctx, "server_submit: queue full");
+    return MBPT_EBUSY;
+  }
+  Req q;
+  q.r = *req;
+  q.ticket = s->next_ticket++;
+  q.t_submit = now_s(s->t0);
+  s->reqs[q.ticket] = q;
+  s->queue.push_back(q.ticket);
+  *ticket = q.ticket;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
+  if (!s) return MBPT_EINVAL;
+  mbpt_context *ctx = s->ctx;
+  while (!s->queue.empty()) {
+    int slot = -1;
+    for (int i = 0; i < s->max_slots; ++i)
+      if (s->slot_req[i] < 0) {
+        slot = i;
+        break;
+      }
+    if (slot < 0) break;
+    Req &q = s->reqs[s->queue.front()];
+    const int rc = admit_one(s, q, slot);
+    if (rc == 1) break;  // no room: wait for retirements
+    if (rc < 0) return rc;
+    s->queue.pop_front();
+  }
+  // compact work numbering over the slots in index order (free slots own none)
+  int total = 0, max_nd = 0, nactive = 0;
+  for (int i = 0; i < s->max_slots; ++i) {
+    TaskDev &T = s->h_tasks[i];
+    T.item_begin = total;
+    if (s->slot_req[i] >= 0) {
+      total += T.nitems;
+      max_nd = std::max(max_nd, T.nd);
+      ++nactive;
+    } else {
+      T.nitems = 0;
+      T.active = 0;
+    }
+  }
+  if (nactive > 0) {
+    const size_t width = offsetof(TaskDev, iter);
+    MBPT_HIPCHK(ctx, hipMemcpy2DAsync(s->ws + s->L.tasks, sizeof(TaskDev), s->h_tasks.data(),
+                                      sizeof(TaskDev), width, s->max_slots, hipMemcpyHostToDevice,
+                                      ctx->stream));
+    KArgs a = server_kargs(s);
+    a.total_items = total;
+    const int prec = ctx->desc.precision;
+    const size_t lds = sample_lds_bytes(max_nd, ctx->desc.n_bins, kBlock);
+    int per_cu = batched_occupancy(4, prec, max_nd, kBlock, lds);
+    const int grid = std::max(1, std::min(total, std::max(1, per_cu) * std::max(1, ctx->num_cus)));
+    size_t slot = 0;
+    timed_begin(ctx, slot);
+    MBPT_HIPCHK(ctx, launch_sample_batched(a, 4, prec, max_nd, grid, kBlock, ctx->stream));
+    timed_end(ctx, slot);
+    MBPT_HIPCHK(ctx, launch_finish(a, 0, s->max_slots, max_nd, ctx->desc.alpha, ctx->stream));
+    std::vector<TaskDev> st(s->max_slots);
+    MBPT_HIPCHK(ctx, hipMemcpyAsync(st.data(), s->ws + s->L.tasks, s->max_slots * sizeof(TaskDev),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+    MBPT_HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    resolve_timing(ctx);
+    const double t = now_s(s->t0);
+    uint64_t evals = 0;
+    double flops = 0.0;
+    for (int i = 0; i < s->max_slots; ++i) {
+      if (s->slot_req[i] < 0) continue;
+      Req &q = s->reqs[static_cast<uint64_t>(s->slot_req[i])];
+      const TaskDev &S = st[i];
+      TaskDev &H = s->h_tasks[i];  // host copy keeps last round's counters
+      evals += S.nevals - H.nevals;
+      flops += s->flops[i].pre * (S.nevals - H.nevals) + s->flops[i].post * (S.npass - H.npass) +
+               s->flops[i].per_term * (S.nterms - H.nterms);
+      H.nevals = S.nevals;
+      H.npass = S.npass;
+      H.nterms = S.nterms;
+      result_of(S, q.res);
+      const double target = std::max(q.r.sigma_rel * std::fabs(q.res.E_per_A), q.r.sigma_abs);
+      const bool converged = S.it_done >= kMinIters && q.res.sigma <= target;
+      const bool capped = q.r.max_evals > 0 && S.nevals >= q.r.max_evals;
+      if (converged || capped || !std::isfinite(q.res.E_per_A)) {
+        q.state = 2;
+        q.t_finish = t;
+        s->bytes.release(q.byte_at, q.byte_n);
+        s->items.release(q.item_at, q.item_n);
+        s->slot_req[i] = -1;
+        H = TaskDev{};
+      }
+    }
+    ctx->evals += evals;
+    ctx->flops += flops;
+  }
+  int na = 0;
+  for (int i = 0; i < s->max_slots; ++i) na += s->slot_req[i] >= 0;
+  if (n_active) *n_active = na;
+  if (n_queued) *n_queued = static_cast<int>(s->queue.size());
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_server_poll(mbpt_server *s, uint64_t ticket, mbpt_result *res, int *done,
+                                double *t_submit, double *t_admit, double *t_finish) {
+  if (!s) return MBPT_EINVAL;
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return MBPT_EINVAL;
+  const Req &q = it->second;
+  if (res) *res = q.res;
+  if (done) *done = q.state == 2;
+  if (t_submit) *t_submit = q.t_submit;
+  if (t_admit) *t_admit = q.t_admit;
+  if (t_finish) *t_finish = q.t_finish;
+  return MBPT_OK;
 }
