@@ -36,6 +36,14 @@ def parse():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--cpu-samples-log2", type=int, default=20)
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "batched", "nuclear4", "serve"],
+                    help="plain (default, the headline line); batched: orders 2+3 x 9 "
+                         "densities in one persistent launch; nuclear4: all 39 fourth-order "
+                         "diagrams x 15 EOS points, graph-captured; serve: Poisson request "
+                         "stream through the continuous-batching server")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rate", type=float, default=50.0)
     return ap.parse_args()
 
 
@@ -109,12 +117,254 @@ def cpu_baseline(args):
                       f"2^{args.samples_log2}; {evals} evaluations in {dt:.1f} s"}
 
 
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def _time_to_sigma(M, s, N, iters, floor_abs=1e-3, rel=0.01):
+    """Run one iteration at a time; per task, wall seconds from the start until
+    sigma <= max(rel |E|, floor_abs) first holds (None if never)."""
+    import torch
+    n = M.mbpt_task_count(s)
+    hit = [None] * n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        per, _ = M.mbpt_integrate(s, N, 1)
+        t = time.perf_counter() - t0
+        for k, r in enumerate(per):
+            if hit[k] is None and r.iters_done >= 3 and r.sigma <= max(rel * abs(r.E_per_A), floor_abs):
+                hit[k] = t
+    return hit
+
+
+def batched_workload(args):
+    """Orders 2 + 3 (pp, hh, ph) x 9 neutron-matter densities = 36 tasks,
+    2^26 samples per iteration per task, 10 iterations: fp64 and fp32 in one
+    persistent launch per iteration (graph-captured, autotuned blocking),
+    against the plain one-diagram-per-launch fp64 path on the same tasks."""
+    import torch
+    import paper_2603_24532_amd as M
+    N, iters = 1 << args.samples_log2, 10
+    tasks = [(o, d, M.MBPT_NEUTRON, n, 0.0, 1000 * o + 100 * d + i)
+             for (o, d) in ((2, 0), (3, 0), (3, 1), (3, 2)) for i, n in enumerate(DENSITIES)]
+    out = {}
+    torch_stream = torch.cuda.Stream()
+    for label, prec, mode in (("plain_fp64", 0, M.MBPT_LAUNCH_PER_TASK),
+                              ("batched_fp64", 0, M.MBPT_LAUNCH_GRAPH),
+                              ("batched_fp32", 1, M.MBPT_LAUNCH_GRAPH)):
+        ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=prec)
+        s = M.mbpt_create_task_set(ctx, tasks)
+        M.mbpt_set_launch_mode(s, mode)
+        M.mbpt_set_blocking(s, 64, 4)  # smallest items: every tuned shape fits
+        nbytes = M.mbpt_workspace_query(s, N, iters)
+        buf, ptr = M.device_workspace(nbytes)
+        M.mbpt_bind_workspace(s, ptr, nbytes, N, iters)
+        tuned = M.mbpt_autotune(s, N) if mode != M.MBPT_LAUNCH_PER_TASK else None
+        if mode == M.MBPT_LAUNCH_PER_TASK:
+            M.mbpt_set_blocking(s, 256, 16)
+        M.mbpt_integrate(s, N, 1)  # warm-up (graph capture for 1 iteration is not reused)
+        M.mbpt_reset(s)
+        M.mbpt_kernel_stats(ctx)
+        torch_stream.synchronize()
+        t0 = time.perf_counter()
+        per, tot = M.mbpt_integrate(s, N, iters)
+        torch_stream.synchronize()
+        dt = time.perf_counter() - t0
+        st = M.mbpt_kernel_stats(ctx)
+        M.mbpt_reset(s)
+        if mode == M.MBPT_LAUNCH_GRAPH:
+            M.mbpt_set_launch_mode(s, M.MBPT_LAUNCH_BATCHED)
+        hits = _time_to_sigma(M, s, N, iters)
+        out[label] = {
+            "Gevals_per_s": st["evals"] / dt / 1e9, "seconds": dt, "tuned_block_spt": tuned,
+            "kernel_ms": st["kernel_ms"],
+            "TFLOPs_algorithmic": st["flops"] / (st["kernel_ms"] * 1e-3) / 1e12,
+            "p50_time_to_1pct_sigma_s": _pct([h for h in hits if h is not None], 50),
+            "p99_time_to_1pct_sigma_s": _pct([h for h in hits if h is not None], 99),
+            "tasks_reaching_target": sum(h is not None for h in hits),
+            "E": {f"o{t[0]}d{t[1]}n{t[3]:.2f}": [round(r.E_per_A, 7), float(f"{r.sigma:.2e}")]
+                  for t, r in zip(tasks, per)},
+        }
+        M.mbpt_task_set_destroy(s)
+        M.mbpt_context_destroy(ctx)
+        print(f"[batched] {label}: {out[label]['Gevals_per_s']:.2f} Gevals/s", file=sys.stderr,
+              flush=True)
+    line = {"metric": "Gevals/s and p50/p99 time-to-1%-sigma, batched orders 2+3 (36 tasks)",
+            "workload": f"orders 2+3, neutron matter, 9 densities, 10 x 2^{args.samples_log2}",
+            "unit": "Gevals/s", "data": "synthetic", **out}
+    print(json.dumps(line), flush=True)
+
+
+def nuclear4_workload(args):
+    """All 39 fourth-order diagrams, nuclear matter, densities 0.08..0.24 x
+    proton fractions {0, 0.25, 0.5} = 585 tasks, 16 iterations x 2^24 samples
+    (2^28 per diagram and EOS point), graph-captured, fp64 and fp32."""
+    import torch
+    import paper_2603_24532_amd as M
+    N, iters = 1 << args.samples_log2, 16
+    dens = [0.08, 0.12, 0.16, 0.20, 0.24]
+    xs = [0.0, 0.25, 0.5]
+    tasks = [(4, d, M.MBPT_NUCLEAR, n, x, 10000 * d + 100 * i + j)
+             for d in range(39) for i, n in enumerate(dens) for j, x in enumerate(xs)]
+    out = {}
+    torch_stream = torch.cuda.Stream()
+    for label, prec in (("fp64", 0), ("fp32", 1)):
+        ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=prec)
+        s = M.mbpt_create_task_set(ctx, tasks)
+        M.mbpt_set_launch_mode(s, M.MBPT_LAUNCH_GRAPH)
+        nbytes = M.mbpt_workspace_query(s, N, iters)
+        buf, ptr = M.device_workspace(nbytes)
+        M.mbpt_bind_workspace(s, ptr, nbytes, N, iters)
+        M.mbpt_kernel_stats(ctx)
+        torch_stream.synchronize()
+        t0 = time.perf_counter()
+        per, tot = M.mbpt_integrate(s, N, iters)
+        torch_stream.synchronize()
+        dt = time.perf_counter() - t0
+        st = M.mbpt_kernel_stats(ctx)
+        out[label] = {"Gevals_per_s": st["evals"] / dt / 1e9, "seconds": dt,
+                      "kernel_ms": st["kernel_ms"],
+                      "TFLOPs_algorithmic": st["flops"] / (st["kernel_ms"] * 1e-3) / 1e12,
+                      "fp64_fallback_fraction": tot.n_fp64_fallback / max(1, tot.n_evals),
+                      "sum_E_x0.5_n0.16": sum(r.E_per_A for t, r in zip(tasks, per)
+                                               if t[3] == 0.16 and t[4] == 0.5)}
+        print(f"[nuclear4] {label}: {out[label]['Gevals_per_s']:.2f} Gevals/s in {dt:.1f} s",
+              file=sys.stderr, flush=True)
+        out[label + "_E"] = [r.E_per_A for r in per]
+        out[label + "_sigma"] = [r.sigma for r in per]
+        M.mbpt_task_set_destroy(s)
+        M.mbpt_context_destroy(ctx)
+    import numpy as np
+    e64, e32 = np.array(out.pop("fp64_E")), np.array(out.pop("fp32_E"))
+    s64 = np.array(out.pop("fp64_sigma"))
+    out.pop("fp32_sigma")
+    nz = s64 > 0
+    z = np.abs(e32 - e64)[nz] / s64[nz]
+    line = {"metric": "Gevals/s, all 39 fourth-order diagrams x 15 EOS points (585 tasks)",
+            "workload": f"nuclear matter, 16 x 2^{args.samples_log2}, hipGraph", "unit": "Gevals/s",
+            "data": "synthetic", **out,
+            "fp32_vs_fp64_max_dev_over_sigma": float(z.max()) if z.size else 0.0,
+            "fp32_vs_fp64_frac_within_3sigma": float((z < 3).mean()) if z.size else 1.0}
+    print(json.dumps(line), flush=True)
+
+
+def serve_workload(args):
+    """Open-loop Poisson stream of EOS-point requests (order U{2..5}, diagram
+    uniform in the order's list, n U[0.04, 0.24], x U[0, 0.5], sigma_rel
+    U[0.1%, 1%], 1 keV absolute floor), through the continuous-batching server
+    (fp32) and through the plain one-request-at-a-time fp64 path."""
+    import numpy as np
+    import torch
+    import paper_2603_24532_amd as M
+    rng = np.random.default_rng(12345)
+    nreq = args.requests
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, nreq))
+    ndiag = {o: M.mbpt_num_diagrams(o) for o in (2, 3, 4, 5)}
+    reqs = []
+    for k in range(nreq):
+        o = int(rng.integers(2, 6))
+        reqs.append(dict(order=o, did=int(rng.integers(0, ndiag[o])),
+                         n=float(rng.uniform(0.04, 0.24)), x=float(rng.uniform(0.0, 0.5)),
+                         rel=float(rng.uniform(0.001, 0.01))))
+    samples, floor, cap = 1 << 18, 1e-3, 1 << 25
+    torch_stream = torch.cuda.Stream()
+    ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP32)
+    slots = 512
+    nbytes = M.mbpt_server_workspace_query(ctx, slots, samples)
+    buf, ptr = M.device_workspace(nbytes)
+    srv = M.mbpt_server_create(ctx, slots, samples, nreq + 1, ptr, nbytes)
+    M.mbpt_kernel_stats(ctx)
+    tickets = [None] * nreq
+    t0 = time.perf_counter()
+    nxt, depth, steps = 0, [], 0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < nreq and arrivals[nxt] <= now:
+            r = reqs[nxt]
+            tickets[nxt] = M.mbpt_server_submit(srv, r["order"], r["did"], M.MBPT_NUCLEAR, r["n"],
+                                                r["x"], r["rel"], floor, samples, cap)
+            nxt += 1
+        na, nq = M.mbpt_server_step(srv)
+        steps += 1
+        if steps % 200 == 0:
+            print(f"[serve] t={now:.1f}s submitted={nxt} resident={na} queued={nq}",
+                  file=sys.stderr, flush=True)
+        depth.append(na + nq)
+        if nxt == nreq and na == 0 and nq == 0:
+            break
+        if na == 0 and nq == 0 and nxt < nreq:
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+    wall = time.perf_counter() - t0
+    st = M.mbpt_kernel_stats(ctx)
+    tts, waits = [], []
+    for t in tickets:
+        res, done, ts, ta, tf = M.mbpt_server_poll(srv, t)
+        tts.append(tf - ts)
+        waits.append(ta - ts)
+    M.mbpt_server_destroy(srv)
+    M.mbpt_context_destroy(ctx)
+    out = {"served_fp32": {"Gevals_per_s": st["evals"] / wall / 1e9, "wall_s": wall,
+                           "p50_time_to_sigma_s": _pct(tts, 50), "p99_time_to_sigma_s": _pct(tts, 99),
+                           "p99_admission_wait_s": _pct(waits, 99), "rounds": steps,
+                           "mean_in_system": float(np.mean(depth)),
+                           "kernel_busy_frac": st["kernel_ms"] * 1e-3 / wall}}
+    # plain path: one request at a time, fp64, one launch per iteration
+    nplain = min(nreq, 200)
+    ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP64)
+    t0 = time.perf_counter()
+    tts_plain, evals = [], 0
+    for k in range(nplain):
+        r = reqs[k]
+        now = time.perf_counter() - t0
+        if arrivals[k] > now:
+            time.sleep(arrivals[k] - now)
+        s = M.mbpt_create_task_set(ctx, [(r["order"], r["did"], M.MBPT_NUCLEAR, r["n"], r["x"], k + 1)])
+        nb = M.mbpt_workspace_query(s, samples, 256)
+        b2, p2 = M.device_workspace(nb)
+        M.mbpt_bind_workspace(s, p2, nb, samples, 256)
+        while True:
+            per, _ = M.mbpt_integrate(s, samples, 1)
+            res = per[0]
+            if (res.iters_done >= 3 and res.sigma <= max(r["rel"] * abs(res.E_per_A), floor)) \
+                    or res.n_evals >= cap:
+                break
+        evals += res.n_evals
+        tts_plain.append(time.perf_counter() - t0 - arrivals[k])
+        if k % 50 == 0:
+            print(f"[serve-plain] {k}/{nplain}", file=sys.stderr, flush=True)
+        M.mbpt_task_set_destroy(s)
+        del b2
+    wall_p = time.perf_counter() - t0
+    M.mbpt_context_destroy(ctx)
+    out["plain_fp64_first_%d" % nplain] = {
+        "Gevals_per_s": evals / wall_p / 1e9, "p50_time_to_sigma_s": _pct(tts_plain, 50),
+        "p99_time_to_sigma_s": _pct(tts_plain, 99)}
+    out["served_first_%d" % nplain] = {"p50_time_to_sigma_s": _pct(tts[:nplain], 50),
+                                       "p99_time_to_sigma_s": _pct(tts[:nplain], 99)}
+    line = {"metric": "p50/p99 time-to-sigma and Gevals/s, served EOS-point requests",
+            "workload": f"{nreq} Poisson requests at {args.rate}/s, orders 2-5, nuclear matter, "
+                        f"2^18 samples per iteration", "data": "synthetic", **out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
               "this build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "plain":
+        if args.workload == "batched":
+            if args.samples_log2 == 24:
+                args.samples_log2 = 26
+            batched_workload(args)
+        elif args.workload == "nuclear4":
+            nuclear4_workload(args)
+        else:
+            serve_workload(args)
+        return
     g = gpu_run(args)
     st2 = g["stats"][2]
     avg_ms = st2["kernel_ms"] / max(1, st2["launches"])

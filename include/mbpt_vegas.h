@@ -10,7 +10,7 @@
  * i.e. the momentum integral of Eqs. (1)-(5) generalised to order n (sum over
  * holes and particles with n_k, 1 - n_k Pauli factors, antisymmetrised
  * matrix elements with explicit spin(-isospin) sums, energy denominators of
- * Eq. (6) with a free spectrum) divided by n_B, by adaptive importance
+ * eq:Dijkabc with a free spectrum) divided by n_B, by adaptive importance
  * sampling on a per-dimension piecewise-linear grid (VEGAS, Sec. "MC
  * integration": training with refinement, inverse-variance combination).
  *
@@ -210,6 +210,17 @@ int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, uint64_t firs
  * and its restore.  ndim = 3 (order + 1). */
 int mbpt_get_grid(mbpt_task_set *set, int task, double *edges_host);
 int mbpt_set_grid(mbpt_task_set *set, int task, const double *edges_host);
+
+/* Autotuner: times one iteration of the whole set for each candidate work
+ * decomposition (threads per block in {64, 128, 256} x samples per thread in
+ * {4, 8, 16, 32}, limited to what the bound workspace holds), keeps the
+ * fastest (mbpt_set_blocking) and resets the set (grids uniform, iteration 0),
+ * so tuning never leaks into results.  The choice is cached per (matter,
+ * precision, launch mode, orders present, samples_per_iter); a cached choice
+ * is applied without timing.  Outputs (may be NULL): the chosen shape and its
+ * sample-kernel milliseconds per iteration.  ESTATE without a workspace. */
+int mbpt_autotune(mbpt_task_set *set, uint64_t samples_per_iter, int *threads_per_block,
+                  int *samples_per_thread, double *ms_per_iter);
 
 /* Timing of the sample kernels since the last call (HIP events on the
  * context stream): launches, total kernel milliseconds, samples evaluated,

@@ -20,8 +20,8 @@
  *  - Integrand: sum over hole/particle states with the measure
  *    sum_{sigma tau} int d^3k/(2pi)^3 n_k or (1 - n_k) (shorthand below
  *    Eq. (5)), zero-temperature n_k = theta(kF - k), kF = (3 pi^2 n_tau)^{1/3},
- *    energy denominators D = sum eps_holes - sum eps_particles (Eq. (6),
- *    "Dijkabc"), antisymmetrized matrix elements <12|V(1-P12)|34>.  Free
+ *    energy denominators D = sum eps_holes - sum eps_particles (equation
+ *    eq:Dijkabc), antisymmetrized matrix elements <12|V(1-P12)|34>.  Free
  *    spectrum eps = (hbar^2/2m) k^2.  The spin(-isospin) sum is done by brute
  *    force over all q^{2n} label assignments (the plain definition) or, as a
  *    second form pinned to the first, by the closed-loop (trace) rule.

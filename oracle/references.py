@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Plain numpy/scipy,
 fp64, written from the definitions in the paper's Sec. "Many-body
-expressions" (Eqs. (1)-(6) and the sum shorthand below Eq. (5)) and from
+expressions" (Eqs. (1)-(5), eq:Dijkabc and the sum shorthand below
+Eq. (5)) and from
 textbook results:
 
 * ``free_gas_per_particle``: kinetic part of the first-order energy with a free

@@ -26,7 +26,7 @@ EXPORTED = [
     "mbpt_set_density", "mbpt_set_asymmetry", "mbpt_set_launch_mode", "mbpt_set_blocking",
     "mbpt_workspace_query", "mbpt_bind_workspace", "mbpt_reset", "mbpt_integrate",
     "mbpt_iteration_log", "mbpt_dump_samples", "mbpt_get_grid", "mbpt_set_grid",
-    "mbpt_kernel_stats", "mbpt_task_flops", "mbpt_server_workspace_query", "mbpt_server_create",
+    "mbpt_kernel_stats", "mbpt_task_flops", "mbpt_autotune", "mbpt_server_workspace_query", "mbpt_server_create",
     "mbpt_server_destroy", "mbpt_server_submit", "mbpt_server_step", "mbpt_server_poll",
 ]
 
@@ -119,6 +119,7 @@ def lib():
         "mbpt_kernel_stats": [_P, ctypes.POINTER(ctypes.c_uint64), _DP,
                               ctypes.POINTER(ctypes.c_uint64), _DP],
         "mbpt_task_flops": [_P, ctypes.c_int, _DP, _DP],
+        "mbpt_autotune": [_P, ctypes.c_uint64, _IP, _IP, _DP],
         "mbpt_server_workspace_query": [_P, ctypes.c_int, ctypes.c_uint64,
                                         ctypes.POINTER(ctypes.c_size_t)],
         "mbpt_server_create": [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, _P,
@@ -320,6 +321,14 @@ def mbpt_task_flops(s, task):
     f, t = ctypes.c_double(), ctypes.c_double()
     _check(lib().mbpt_task_flops(s, task, ctypes.byref(f), ctypes.byref(t)), _ctx_of_set(s))
     return f.value, t.value
+
+
+def mbpt_autotune(s, samples_per_iter):
+    b, t = ctypes.c_int(), ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(lib().mbpt_autotune(s, samples_per_iter, ctypes.byref(b), ctypes.byref(t),
+                               ctypes.byref(ms)), _ctx_of_set(s))
+    return b.value, t.value, ms.value
 
 
 def mbpt_server_workspace_query(ctx, max_slots, max_samples_per_iter):

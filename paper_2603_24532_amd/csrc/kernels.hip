@@ -3,7 +3,7 @@
 // One thread evaluates one sample at a time: Philox4x32-10 words -> VEGAS
 // bins and fractions (grid in LDS) -> spherical loop momenta -> line momenta
 // from the compiled descriptor -> Pauli factors (n_k for holes, 1 - n_k for
-// particles) -> energy denominators (Eq. (6), free spectrum) ->
+// particles) -> energy denominators (eq:Dijkabc, free spectrum) ->
 // antisymmetrised matrix elements per vertex -> explicit spin(-isospin) label
 // sum -> weight.  Sums of (w - c) and (w - c)^2 are kept per thread with
 // Neumaier compensation, reduced across the wavefront and the block in a
@@ -135,6 +135,26 @@ __device__ __forceinline__ double vegas_map(const KArgs &a, const TaskDev *__res
   return jac;
 }
 
+// True if some label assignment survives the Pauli factors: neutron matter
+// needs every line allowed as a neutron; nuclear matter needs one isospin
+// configuration whose lines are all allowed.  A sample that fails does no
+// further work (its weight is exactly zero); this also keeps structurally
+// vanishing denominators (a one-particle-one-hole cut, where isospin
+// conservation forces the same Fermi momentum on both lines) out of the
+// division.
+template <int Q>
+__device__ __forceinline__ bool pauli_allowed(const KArgs &a, const DiagDev *__restrict__ D,
+                                              uint32_t okN, uint32_t okP, uint32_t lmask) {
+  if (Q == 2) return okN == lmask;
+  const GroupDev *__restrict__ G = a.groups + D->group_off;
+  bool any = false;
+  for (int gi = 0; gi < D->ngroups; ++gi) {
+    const uint32_t tau = G[gi].tau;
+    any |= (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
+  }
+  return any;
+}
+
 template <int ORDER, int Q>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
@@ -180,7 +200,7 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   const uint32_t lmask = D->line_mask, pmask = D->part_mask;
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
-  if (Q == 2 && okN != lmask) return 0.0;
+  if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
   ++npass;
 
   // energy denominators
@@ -368,7 +388,7 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
   const uint32_t lmask = D->line_mask, pmask = D->part_mask;
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
-  if (Q == 2 && okN != lmask) return 0.0;
+  if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
 
   float dprod = 1.0f;
 #pragma unroll

@@ -7,7 +7,9 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "diagrams.hpp"
@@ -895,5 +897,93 @@ extern "C" int mbpt_task_flops(const mbpt_task_set *set, int task, double *flops
   const FlopModel &f = set->flops[task];
   if (flops) *flops = f.pre + f.post + f.per_term * f.all_terms;
   if (transcendentals) *transcendentals = f.transc_pre + f.transc_post;
+  return MBPT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner
+
+namespace {
+struct TuneKey {
+  int q, prec, mode;
+  uint32_t orders;  // bit k: order k present
+  uint64_t samples;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(q, prec, mode, orders, samples) < std::tie(o.q, o.prec, o.mode, o.orders, o.samples);
+  }
+};
+std::map<TuneKey, std::pair<int, int>> &tune_cache() {
+  static std::map<TuneKey, std::pair<int, int>> c;
+  return c;
+}
+}  // namespace
+
+extern "C" int mbpt_autotune(mbpt_task_set *set, uint64_t samples_per_iter, int *threads_per_block,
+                             int *samples_per_thread, double *ms_per_iter) {
+  if (!set || samples_per_iter < 2) return MBPT_EINVAL;
+  mbpt_context *ctx = set->ctx;
+  if (!set->ws) {
+    set_err(ctx, "autotune: no workspace bound");
+    return MBPT_ESTATE;
+  }
+  if (samples_per_iter > set->max_samples) return MBPT_ENOMEM;
+  TuneKey key{set->q, ctx->desc.precision, set->launch_mode, 0u, samples_per_iter};
+  for (const auto &t : set->tasks) key.orders |= 1u << t.order;
+  const int old_block = set->block, old_spt = set->spt;
+  int best_b = old_block, best_s = old_spt;
+  double best_ms = -1.0;
+  auto it = tune_cache().find(key);
+  if (it != tune_cache().end()) {
+    best_b = it->second.first;
+    best_s = it->second.second;
+  } else {
+    // the workspace holds items for the bind-time shape: only shapes with
+    // work items at least that large fit
+    const size_t bound_chunk = set->max_items / std::max<size_t>(1, set->tasks.size());
+    const int blocks[] = {64, 128, 256};
+    const int spts[] = {4, 8, 16, 32};
+    bool warmed = false;
+    for (int b : blocks)
+      for (int sp : spts) {
+        set->block = b;
+        set->spt = sp;
+        if (items_for(set, samples_per_iter) > bound_chunk) continue;
+        set->drop_graph();
+        const int saved_mode = set->launch_mode;
+        if (set->launch_mode == MBPT_LAUNCH_GRAPH) set->launch_mode = MBPT_LAUNCH_BATCHED;
+        uint64_t l0;
+        double ms0;
+        mbpt_kernel_stats(ctx, &l0, &ms0, nullptr, nullptr);  // drain earlier stats
+        const uint64_t ev = ctx->evals;
+        const double fl = ctx->flops;
+        int rc = 0;
+        if (!warmed) {
+          rc = mbpt_integrate(set, samples_per_iter, 1, nullptr, nullptr);
+          warmed = true;
+        }
+        if (!rc) rc = mbpt_integrate(set, samples_per_iter, 1, nullptr, nullptr);
+        set->launch_mode = saved_mode;
+        uint64_t launches;
+        double ms;
+        mbpt_kernel_stats(ctx, &launches, &ms, nullptr, nullptr);
+        ctx->evals = ev;
+        ctx->flops = fl;
+        if (rc && rc != MBPT_ENUMERIC) return rc;
+        if (best_ms < 0.0 || ms < best_ms) {
+          best_ms = ms;
+          best_b = b;
+          best_s = sp;
+        }
+      }
+    tune_cache()[key] = {best_b, best_s};
+  }
+  set->block = best_b;
+  set->spt = best_s;
+  set->drop_graph();
+  const int rc = mbpt_reset(set);
+  if (rc) return rc;
+  if (threads_per_block) *threads_per_block = best_b;
+  if (samples_per_thread) *samples_per_thread = best_s;
+  if (ms_per_iter) *ms_per_iter = best_ms;
   return MBPT_OK;
 }
