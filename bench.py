@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+LABEL_MODE = 0  # set from --label-mode
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -36,6 +38,8 @@ def parse():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--cpu-samples-log2", type=int, default=20)
+    ap.add_argument("--label-mode", type=int, default=0, choices=(0, 1),
+                    help="label sums: 0 polynomial per isospin configuration, 1 explicit list")
     ap.add_argument("--workload", default="plain",
                     choices=["plain", "batched", "nuclear4", "serve"],
                     help="plain (default, the headline line); batched: orders 2+3 x 9 "
@@ -59,7 +63,7 @@ def gpu_run(args, precision=0, steps=None, warmup=None):
     sets = {}
     bufs = []
     for order in (1, 2):
-        ctx = M.mbpt_context_create(stream=stream, precision=precision, seed=1)
+        ctx = M.mbpt_context_create(stream=stream, precision=precision, seed=1, label_mode=LABEL_MODE)
         tasks = [(order, 0, M.MBPT_NEUTRON, n, 0.0, 100 * order + i)
                  for i, n in enumerate(DENSITIES)]
         s = M.mbpt_create_task_set(ctx, tasks)
@@ -154,7 +158,7 @@ def batched_workload(args):
     for label, prec, mode in (("plain_fp64", 0, M.MBPT_LAUNCH_PER_TASK),
                               ("batched_fp64", 0, M.MBPT_LAUNCH_GRAPH),
                               ("batched_fp32", 1, M.MBPT_LAUNCH_GRAPH)):
-        ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=prec)
+        ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=prec, label_mode=LABEL_MODE)
         s = M.mbpt_create_task_set(ctx, tasks)
         M.mbpt_set_launch_mode(s, mode)
         M.mbpt_set_blocking(s, 64, 4)  # smallest items: every tuned shape fits
@@ -211,7 +215,7 @@ def nuclear4_workload(args):
     out = {}
     torch_stream = torch.cuda.Stream()
     for label, prec in (("fp64", 0), ("fp32", 1)):
-        ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=prec)
+        ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=prec, label_mode=LABEL_MODE)
         s = M.mbpt_create_task_set(ctx, tasks)
         M.mbpt_set_launch_mode(s, M.MBPT_LAUNCH_GRAPH)
         nbytes = M.mbpt_workspace_query(s, N, iters)
@@ -270,7 +274,7 @@ def serve_workload(args):
                          rel=float(rng.uniform(0.001, 0.01))))
     samples, floor, cap = 1 << 18, 1e-3, 1 << 25
     torch_stream = torch.cuda.Stream()
-    ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP32)
+    ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP32, label_mode=LABEL_MODE)
     slots = 512
     nbytes = M.mbpt_server_workspace_query(ctx, slots, samples)
     buf, ptr = M.device_workspace(nbytes)
@@ -312,7 +316,7 @@ def serve_workload(args):
                            "kernel_busy_frac": st["kernel_ms"] * 1e-3 / wall}}
     # plain path: one request at a time, fp64, one launch per iteration
     nplain = min(nreq, 200)
-    ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP64)
+    ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP64, label_mode=LABEL_MODE)
     t0 = time.perf_counter()
     tts_plain, evals = [], 0
     for k in range(nplain):
@@ -350,7 +354,9 @@ def serve_workload(args):
 
 
 def main():
+    global LABEL_MODE
     args = parse()
+    LABEL_MODE = args.label_mode
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
               "this build has no multi-GPU path", file=sys.stderr)
@@ -389,6 +395,7 @@ def main():
                         "fm^-3, one diagram per launch, fp64, 20 iterations x 2^24 samples",
             "tasks": 18, "samples_per_iter": g["N"], "iterations": g["iters"],
             "interaction": "C0=-1 fm^2, Cy=-2, mpi=0.7, Lambda=2, n=4", "seed": 1,
+            "label_sum": "polynomial" if LABEL_MODE == 0 else "explicit",
         },
         "roofline": {
             "bound": "alu",

@@ -82,7 +82,11 @@ typedef struct mbpt_interaction {
  * radius kF,max + kcut_extra * Lambda (hole lines: kF,max, exact).
  * fp32_band_k, fp32_band_d: FP32 precision only -- a sample is re-evaluated
  * in fp64 if some line has |k^2 - kF^2| < band_k kF^2 or some denominator has
- * |D| < band_d * (sum of |eps| over its lines). */
+ * |D| < band_d * (sum of |eps| over its lines).  label_mode: 0 evaluates the
+ * spin(-isospin) sum of each isospin configuration as its multilinear
+ * polynomial in the vertex matrix elements (coefficients compiled from the
+ * nonzero label assignments); 1 evaluates the compressed list of nonzero
+ * assignments term by term.  Both are exact; 0 is faster at high orders. */
 typedef struct mbpt_context_desc {
   int device;
   void *stream;
@@ -93,6 +97,7 @@ typedef struct mbpt_context_desc {
   double kcut_extra;
   double fp32_band_k;
   double fp32_band_d;
+  int label_mode;
 } mbpt_context_desc;
 
 /* One integration task: diagram `diagram_id` of order `order` (1..5; ids
@@ -127,7 +132,7 @@ typedef struct mbpt_server mbpt_server;
 /* ---- context -------------------------------------------------------------- */
 /* Create a context on `device`.  desc may be NULL for defaults (device 0,
  * default stream, FP64, seed 1, 50 bins, alpha 1.5, kcut_extra 3.0, bands
- * 1e-4 / 1e-2).  The default interaction is the synthetic contact + Yukawa one
+ * 1e-4 / 1e-2, label_mode 0).  The default interaction is the synthetic contact + Yukawa one
  * (C0 = -1 fm^2, Cy = -2, mpi = 0.7, Lambda = 2, exponent 4, hbar^2/m = 41.47,
  * hbarc = 197.3269804).  EINVAL on bad fields, EHIP if the device is absent. */
 int mbpt_context_create(const mbpt_context_desc *desc, mbpt_context **out);
@@ -154,6 +159,18 @@ int mbpt_diagram_matrix(int order, int id, int *M, double *prefactor);
  * with isospin conservation at every vertex, and compressed terms stored. */
 int mbpt_diagram_label_stats(int order, int id, int matter, int *n_assign, int *n_isospin,
                              int *n_terms);
+/* The label sum of a diagram as the polynomial it is in the vertex matrix
+ * elements (eq:Dijkabc with the antisymmetrised vertex V_d - V_e): one row per
+ * isospin configuration (one row in neutron matter), 2^order integer
+ * coefficients c_E per row, where E runs over vertex subsets (bit v set:
+ * vertex v contributes its exchange element V_e, else its direct element V_d)
+ * and the configuration's sum is sum_E c_E prod_v (V_d,v or V_e,v).  coef is
+ * caller-owned host memory of max_rows * 2^order doubles, row-major; rows are
+ * ordered by the configuration's isospin mask over the kernel's line slots.
+ * *n_rows receives the row count; MBPT_ENOMEM if it exceeds max_rows
+ * (nothing written then).  coef may be NULL to query n_rows only. */
+int mbpt_diagram_label_poly(int order, int id, int matter, double *coef, int max_rows,
+                            int *n_rows);
 
 /* ---- task sets ------------------------------------------------------------ */
 /* Create a set of tasks (copied).  EINVAL on an unknown diagram, order outside

@@ -22,6 +22,7 @@ MBPT_LAUNCH_PER_TASK, MBPT_LAUNCH_BATCHED, MBPT_LAUNCH_GRAPH = 0, 1, 2
 EXPORTED = [
     "mbpt_context_create", "mbpt_context_destroy", "mbpt_last_error", "mbpt_set_interaction",
     "mbpt_set_precision", "mbpt_num_diagrams", "mbpt_diagram_matrix", "mbpt_diagram_label_stats",
+    "mbpt_diagram_label_poly",
     "mbpt_create_task_set", "mbpt_create_diagram_set", "mbpt_task_set_destroy", "mbpt_task_count",
     "mbpt_set_density", "mbpt_set_asymmetry", "mbpt_set_launch_mode", "mbpt_set_blocking",
     "mbpt_workspace_query", "mbpt_bind_workspace", "mbpt_reset", "mbpt_integrate",
@@ -42,7 +43,7 @@ class mbpt_context_desc(ctypes.Structure):
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint32),
                 ("n_bins", ctypes.c_int), ("alpha", ctypes.c_double),
                 ("kcut_extra", ctypes.c_double), ("fp32_band_k", ctypes.c_double),
-                ("fp32_band_d", ctypes.c_double)]
+                ("fp32_band_d", ctypes.c_double), ("label_mode", ctypes.c_int)]
 
 
 class mbpt_task_desc(ctypes.Structure):
@@ -95,6 +96,8 @@ def lib():
         "mbpt_num_diagrams": [ctypes.c_int, _IP],
         "mbpt_diagram_matrix": [ctypes.c_int, ctypes.c_int, _IP, _DP],
         "mbpt_diagram_label_stats": [ctypes.c_int, ctypes.c_int, ctypes.c_int, _IP, _IP, _IP],
+        "mbpt_diagram_label_poly": [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int, _IP],
         "mbpt_create_task_set": [_P, ctypes.POINTER(mbpt_task_desc), ctypes.c_int,
                                  ctypes.POINTER(_P)],
         "mbpt_create_diagram_set": [_P, ctypes.c_int, _IP, ctypes.c_int, ctypes.c_int,
@@ -160,9 +163,10 @@ _srv_ctx = {}
 # Same-name wrappers (argument marshalling only)
 
 def mbpt_context_create(device=0, stream=None, precision=MBPT_FP64, seed=1, n_bins=50,
-                        alpha=1.5, kcut_extra=3.0, fp32_band_k=1e-4, fp32_band_d=1e-2):
+                        alpha=1.5, kcut_extra=3.0, fp32_band_k=1e-4, fp32_band_d=1e-2,
+                        label_mode=0):
     d = mbpt_context_desc(device, stream, precision, seed, n_bins, alpha, kcut_extra,
-                          fp32_band_k, fp32_band_d)
+                          fp32_band_k, fp32_band_d, label_mode)
     h = _P()
     _check(lib().mbpt_context_create(ctypes.byref(d), ctypes.byref(h)))
     return h.value
@@ -204,6 +208,16 @@ def mbpt_diagram_label_stats(order, did, matter):
     _check(lib().mbpt_diagram_label_stats(order, did, matter, ctypes.byref(a), ctypes.byref(b),
                                           ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+def mbpt_diagram_label_poly(order, did, matter):
+    """Rows of 2^order coefficients c_E, one per isospin configuration."""
+    n = ctypes.c_int()
+    _check(lib().mbpt_diagram_label_poly(order, did, matter, None, 0, ctypes.byref(n)))
+    nE = 1 << order
+    buf = (ctypes.c_double * max(1, n.value * nE))()
+    _check(lib().mbpt_diagram_label_poly(order, did, matter, buf, n.value, ctypes.byref(n)))
+    return [list(buf[r * nE:(r + 1) * nE]) for r in range(n.value)]
 
 
 def mbpt_create_task_set(ctx, tasks):

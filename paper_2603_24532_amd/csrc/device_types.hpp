@@ -20,7 +20,7 @@ struct alignas(16) DiagDev {
   double pad0;
   // Signed 0/1/2 coefficients as loop bitmasks (bits 0-7: +1, 8-15: -1,
   // 16-23: +2, 24-31: -2):
-  uint32_t lmask[10];     // line l momentum = sum_j c_lj k_j
+  uint32_t lmask[10];     // line slot l momentum = sum_j c_lj k_j (slot j < L is loop j)
   uint32_t pmask_v[5];    // vertex v: 2p  = k_o1 - k_o2 = sum_j c_vj k_j
   uint32_t qmask_v[5];    // vertex v: 2p' = k_i1 - k_i2
   uint32_t cut_hole[4];   // D_c = sum_{holes in c} eps - sum_{particles in c} eps
@@ -28,10 +28,19 @@ struct alignas(16) DiagDev {
   int pad3[2];
 };
 
-// Isospin configuration: lines whose bit is set carry protons.
+// Isospin configuration: lines whose bit is set carry protons.  first/count:
+// its explicit terms; coef_off: its 2^n factorised coefficients.
 struct alignas(16) GroupDev {
   uint32_t tau;
-  int first, count, pad;
+  int first, count, coef_off;
+};
+
+// Factorised label-sum coefficient in both precisions (small integers, exact
+// in fp32).
+struct alignas(16) CoefDev {
+  double d;
+  float f;
+  float pad;
 };
 
 // Compressed label-sum term: multiplicity and 2-bit vertex codes
@@ -95,10 +104,11 @@ struct KArgs {
   double *partials;       // 4 doubles per work item
   uint64_t *counters;     // kItemCounters per work item
   double *reslog;         // (I, var) pairs
+  const CoefDev *gcoef;   // factorised label-sum coefficients
   int ntasks;
   int total_items;
   int spt;                // samples per thread per item
-  int pad;
+  int label_mode;         // 0 factorised label sums, 1 explicit terms
   Phys phys;
 };
 

@@ -279,6 +279,60 @@ const Diagram *get_diagram(int order, int id) {
   return &ds[id];
 }
 
+void line_slots(const Diagram &d, int *slot_line) {
+  bool is_loop[kMaxLines] = {};
+  for (int j = 0; j < d.nloops; ++j) {
+    slot_line[j] = d.loop_line[j];
+    is_loop[d.loop_line[j]] = true;
+  }
+  int k = d.nloops;
+  for (int l = 0; l < d.nlines; ++l)
+    if (!is_loop[l]) slot_line[k++] = l;
+}
+
+LabelTables label_tables(const Diagram &d, int q) {
+  const LabelList ll = build_labels(d, q);
+  int slot_line[kMaxLines];
+  line_slots(d, slot_line);
+  auto to_slots = [&](uint32_t tau) {
+    uint32_t t = 0;
+    for (int sl = 0; sl < d.nlines; ++sl)
+      if ((tau >> slot_line[sl]) & 1u) t |= 1u << sl;
+    return t;
+  };
+  LabelTables out;
+  std::vector<LabelTerm> terms;
+  for (const auto &t : ll.terms) terms.push_back({to_slots(t.tau_mask), t.codes, t.mult});
+  std::sort(terms.begin(), terms.end(), [](const LabelTerm &x, const LabelTerm &y) {
+    return x.tau_mask != y.tau_mask ? x.tau_mask < y.tau_mask : x.codes < y.codes;
+  });
+  out.terms = terms;
+  const int n = d.order, nE = 1 << n;
+  for (size_t i = 0; i < terms.size();) {
+    size_t j = i;
+    while (j < terms.size() && terms[j].tau_mask == terms[i].tau_mask) ++j;
+    LabelTables::Group g;
+    g.tau = terms[i].tau_mask;
+    g.first = static_cast<int>(i);
+    g.count = static_cast<int>(j - i);
+    g.coef.assign(nE, 0.0);
+    for (size_t t = i; t < j; ++t)
+      for (int E = 0; E < nE; ++E) {
+        // code 0: V_d (a = 1, b = 0); 1: -V_e (a = 0, b = -1); 2: V_d - V_e (1, -1)
+        int c = terms[t].mult;
+        for (int v = 0; v < n && c; ++v) {
+          const uint32_t code = (terms[t].codes >> (2 * v)) & 3u;
+          if ((E >> v) & 1) c *= (code == 0u) ? 0 : -1;
+          else c *= (code == 1u) ? 0 : 1;
+        }
+        g.coef[E] += c;
+      }
+    out.groups.push_back(std::move(g));
+    i = j;
+  }
+  return out;
+}
+
 LabelList build_labels(const Diagram &d, int q) {
   LabelSearch s(d, q);
   s.rec(0);

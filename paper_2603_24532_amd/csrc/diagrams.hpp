@@ -48,6 +48,26 @@ struct LabelList {
   std::vector<LabelTerm> terms;  // sorted by tau_mask, then codes
 };
 
+// Line slots: slot j < L holds the line carrying loop momentum j, the tree
+// lines follow in line order.  slot_line[slot] = line.
+void line_slots(const Diagram &d, int *slot_line);
+
+// Device-ready label tables of one diagram, with lines in slot order:
+// isospin groups (tau masks over slots), explicit terms and, per group, the
+// 2^n coefficients c_E of the multilinear expansion
+//   sum_{terms} mult prod_v (a_v V_d,v + b_v V_e,v) = sum_E c_E prod_{v not in E} V_d,v prod_{v in E} V_e,v
+// (E = set of vertices taking the exchange term; bit v of the index E).
+struct LabelTables {
+  struct Group {
+    uint32_t tau;
+    int first, count;
+    std::vector<double> coef;
+  };
+  std::vector<Group> groups;
+  std::vector<LabelTerm> terms;  // tau masks over slots
+};
+LabelTables label_tables(const Diagram &d, int q);
+
 // Number of diagrams of an order (1..5), or -1.
 int num_diagrams(int order);
 // Diagram `id` of an order (ids follow the lexicographic order of the

@@ -155,6 +155,111 @@ __device__ __forceinline__ bool pauli_allowed(const KArgs &a, const DiagDev *__r
   return any;
 }
 
+// Spin(-isospin) label sum of one diagram, summed over the isospin
+// configurations whose lines all pass the Pauli test.  Mode 0 evaluates each
+// configuration's sum as the multilinear polynomial
+//   sum_E c_E prod_{v not in E} V_d,v prod_{v in E} V_e,v
+// (E: set of vertices taking the exchange term; c_E integer, compiled on the
+// host from the nonzero label assignments): the monomials of the first
+// ORDER/2 vertices and of the rest are tabulated once per sample, so a
+// configuration costs 2^ORDER + 2^(ORDER - ORDER/2) multiply-adds however
+// many assignments it holds.  Mode 1 walks the compressed assignment list.
+template <typename F>
+__device__ __forceinline__ F fma_t(F x, F y, F z) {
+  return __builtin_fma(x, y, z);
+}
+template <>
+__device__ __forceinline__ float fma_t<float>(float x, float y, float z) {
+  return __builtin_fmaf(x, y, z);
+}
+template <typename F>
+__device__ __forceinline__ F coef_val(const CoefDev &c) {
+  return c.d;
+}
+template <>
+__device__ __forceinline__ float coef_val<float>(const CoefDev &c) {
+  return c.f;
+}
+template <typename F>
+__device__ __forceinline__ F term_mult(const TermDev &t) {
+  return t.mult;
+}
+template <>
+__device__ __forceinline__ float term_mult<float>(const TermDev &t) {
+  return t.multf;
+}
+
+// M[e] = prod_{v < NV} (bit v of e ? Ve[v] : Vd[v])
+template <int NV, typename F>
+__device__ __forceinline__ void monomials(const F *Vd, const F *Ve, F *M) {
+  M[0] = F(1);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+#pragma unroll
+    for (int e = 0; e < (1 << v); ++e) {
+      M[e + (1 << v)] = M[e] * Ve[v];
+      M[e] = M[e] * Vd[v];
+    }
+  }
+}
+
+template <int ORDER, int Q, typename F>
+__device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict__ D,
+                                       const F *Vd, const F *Ve, uint32_t okN, uint32_t okP,
+                                       uint32_t lmask, uint32_t &units) {
+  const GroupDev *__restrict__ G = a.groups + D->group_off;
+  const int ngroups = D->ngroups;
+  F acc = F(0);
+  if (a.label_mode == 0) {
+    constexpr int H = ORDER / 2;
+    constexpr int NA = 1 << H, NB = 1 << (ORDER - H);
+    F MA[NA], MB[NB];
+    monomials<H>(Vd, Ve, MA);
+    monomials<ORDER - H>(Vd + H, Ve + H, MB);
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const uint32_t tau = G[gi].tau;
+      bool ok = true;
+      if (Q == 4) ok = (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
+      if (ok) {
+        ++units;
+        const CoefDev *__restrict__ C = a.gcoef + G[gi].coef_off;
+        F gs = F(0);
+#pragma unroll
+        for (int eb = 0; eb < NB; ++eb) {
+          F in = F(0);
+#pragma unroll
+          for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(coef_val<F>(C[eb * NA + ea]), MA[ea], in);
+          gs = fma_t<F>(in, MB[eb], gs);
+        }
+        acc += gs;
+      }
+    }
+  } else {
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const uint32_t tau = G[gi].tau;
+      const int first = G[gi].first, cnt = G[gi].count;
+      bool ok = true;
+      if (Q == 4) ok = (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
+      if (ok) {
+        units += cnt;
+        for (int t = first; t < first + cnt; ++t) {
+          const TermDev tm = a.terms[t];
+          F prod = F(1);
+#pragma unroll
+          for (int v = 0; v < ORDER; ++v) {
+            const uint32_t code = (tm.codes >> (2 * v)) & 3u;
+            const F ca = code != 1u ? F(1) : F(0);
+            const F cb = code != 0u ? F(-1) : F(0);
+            prod *= fma_t<F>(ca, Vd[v], cb * Ve[v]);
+          }
+          acc = fma_t<F>(term_mult<F>(tm), prod, acc);
+        }
+      }
+    }
+  }
+  return acc;
+}
+
 template <int ORDER, int Q>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
@@ -190,7 +295,14 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
     double kv[3];
-    masked_sum<L>(D->lmask[l], k, kv);
+    if (l < L) {
+      // slot l < L carries loop momentum l itself
+      kv[0] = k[l][0];
+      kv[1] = k[l][1];
+      kv[2] = k[l][2];
+    } else {
+      masked_sum<L>(D->lmask[l], k, kv);
+    }
     const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = a.phys.hb2m * k2;
     inN |= (k2 < T->kF2[0]) ? (1u << l) : 0u;
@@ -270,31 +382,7 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   }
   const double regall = exp(-yreg * a.phys.invLn);
 
-  // label sum: isospin groups (Pauli test per group), terms with multiplicity
-  double acc = 0.0;
-  const GroupDev *__restrict__ G = a.groups + D->group_off;
-  const int ngroups = D->ngroups;
-  for (int gi = 0; gi < ngroups; ++gi) {
-    const uint32_t tau = G[gi].tau;
-    const int first = G[gi].first, cnt = G[gi].count;
-    bool ok = true;
-    if (Q == 4) ok = (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
-    if (ok) {
-      nterms += cnt;
-      for (int t = first; t < first + cnt; ++t) {
-        const TermDev tm = a.terms[t];
-        double prod = 1.0;
-#pragma unroll
-        for (int v = 0; v < ORDER; ++v) {
-          const uint32_t code = (tm.codes >> (2 * v)) & 3u;
-          const double ca = code != 1u ? 1.0 : 0.0;
-          const double cb = code != 0u ? -1.0 : 0.0;
-          prod *= fma(ca, Vd[v], cb * Ve[v]);
-        }
-        acc = fma(tm.mult, prod, acc);
-      }
-    }
-  }
+  const double acc = label_sum<ORDER, Q, double>(a, D, Vd, Ve, okN, okP, lmask, nterms);
   return jac * (D->pref * T->inv_density) * regall * acc * rinv[NR - 1];
 }
 
@@ -371,7 +459,13 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
     float kv[3];
-    masked_sum_f<L>(D->lmask[l], k, kv);
+    if (l < L) {
+      kv[0] = k[l][0];
+      kv[1] = k[l][1];
+      kv[2] = k[l][2];
+    } else {
+      masked_sum_f<L>(D->lmask[l], k, kv);
+    }
     const float k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = hb2m * k2;
     near |= fabsf(k2 - kFn2) < bandk * kFn2;
@@ -463,33 +557,8 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
   }
   const float regall = __expf(-yexp);
 
-  uint32_t nt = 0;
-  float acc = 0.0f;
-  const GroupDev *__restrict__ G = a.groups + D->group_off;
-  const int ngroups = D->ngroups;
-  for (int gi = 0; gi < ngroups; ++gi) {
-    const uint32_t tau = G[gi].tau;
-    const int first = G[gi].first, cnt = G[gi].count;
-    bool ok = true;
-    if (Q == 4) ok = (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
-    if (ok) {
-      nt += cnt;
-      for (int t = first; t < first + cnt; ++t) {
-        const TermDev tm = a.terms[t];
-        float prod = 1.0f;
-#pragma unroll
-        for (int v = 0; v < ORDER; ++v) {
-          const uint32_t code = (tm.codes >> (2 * v)) & 3u;
-          const float ca = code != 1u ? 1.0f : 0.0f;
-          const float cb = code != 0u ? -1.0f : 0.0f;
-          prod *= fmaf(ca, Vd[v], cb * Ve[v]);
-        }
-        acc = fmaf(tm.multf, prod, acc);
-      }
-    }
-  }
+  const float acc = label_sum<ORDER, Q, float>(a, D, Vd, Ve, okN, okP, lmask, nterms);
   ++npass;
-  nterms += nt;
   return jac * (D->pref * T->inv_density) * static_cast<double>(regall) *
          static_cast<double>(acc) * static_cast<double>(rinv[NR - 1]);
 }

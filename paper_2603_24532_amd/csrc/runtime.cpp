@@ -45,8 +45,9 @@ static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255);
 // momenta, line momenta, Pauli tests), the part a sample past the Pauli test
 // needs (denominators, matrix elements, weight, accumulation) and the part
 // per label term evaluated.
-void count_flops(const Diagram &d, int q, int half_exp, FlopModel &f) {
+void count_flops(const Diagram &d, int q, int half_exp, int label_mode, FlopModel &f) {
   const int n = d.order, L = d.nloops, NL = d.nlines, NC = d.ncuts, ND = d.ndim;
+  const int H = n / 2;
   double pre = 0, pre_t = 0;
   pre += 6.0 * ND;                  // bin fraction (2), x = e + r w (2), jacobian (2)
   pre += 13.0 * L;                  // radius, cos, sin theta, k components, jacobian
@@ -72,11 +73,18 @@ void count_flops(const Diagram &d, int q, int half_exp, FlopModel &f) {
   post += 3.0;                  // weight: jacobian * prefactor * label sum
   post_t += 1.0;                // one division by the denominators
   post_t += (NC == 0) ? -1.0 : 0.0;
+  if (label_mode) {
+    f.per_term = n + 1.0;       // explicit term: product of n factors, multiply-add
+  } else {
+    // factorised: monomial tables of the two vertex halves (2^H + 2^{n-H}
+    // products) once per sample, then per isospin group 2^n + 2^{n-H} FMAs
+    post += (1 << H) + (1 << (n - H)) - 2;
+    f.per_term = 2.0 * ((1 << n) + (1 << (n - H)));
+  }
   double acc = 10.0 + 1.0 + ND; // shifted sums (Neumaier), w^2, histogram adds
   f.pre = pre + pre_t + acc;    // every sample is accumulated
   f.post = post + post_t;
-  f.per_term = n + 1.0;         // product of n factors, multiply-add with multiplicity
-  f.all_terms = 0.0;
+  f.all_units = 0.0;
   f.transc_pre = pre_t;
   f.transc_post = post_t;
 }
@@ -99,10 +107,11 @@ extern "C" int mbpt_context_create(const mbpt_context_desc *desc, mbpt_context *
   d.kcut_extra = 3.0;
   d.fp32_band_k = 1e-4;
   d.fp32_band_d = 1e-2;
+  d.label_mode = 0;
   if (desc) d = *desc;
   if (d.n_bins < 2 || d.n_bins > kMaxBins || !(d.alpha > 0.0) || !(d.kcut_extra >= 0.0) ||
       (d.precision != MBPT_FP64 && d.precision != MBPT_FP32) || d.fp32_band_k < 0.0 ||
-      d.fp32_band_d < 0.0)
+      d.fp32_band_d < 0.0 || (d.label_mode != 0 && d.label_mode != 1))
     return MBPT_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || d.device < 0 || d.device >= ndev) return MBPT_EHIP;
@@ -178,24 +187,39 @@ extern "C" int mbpt_diagram_label_stats(int order, int id, int matter, int *n_as
   return MBPT_OK;
 }
 
+extern "C" int mbpt_diagram_label_poly(int order, int id, int matter, double *coef, int max_rows,
+                                       int *n_rows) {
+  const Diagram *d = get_diagram(order, id);
+  if (!d || !n_rows || (matter != MBPT_NEUTRON && matter != MBPT_NUCLEAR)) return MBPT_EINVAL;
+  const LabelTables lt = label_tables(*d, matter == MBPT_NUCLEAR ? 4 : 2);
+  *n_rows = static_cast<int>(lt.groups.size());
+  if (!coef) return MBPT_OK;
+  if (*n_rows > max_rows) return MBPT_ENOMEM;
+  const size_t nE = size_t{1} << order;
+  for (size_t g = 0; g < lt.groups.size(); ++g)
+    std::copy(lt.groups[g].coef.begin(), lt.groups[g].coef.end(), coef + g * nE);
+  return MBPT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Task sets
 
 namespace mbpt {
 
-// Descriptor fields derived from the diagram alone (loop radii, masks,
-// prefactor with the (2 pi)^{-3L} measure).
-void fill_diag_dev(const Diagram &diag, DiagDev &dd) {
-  const Diagram *d = &diag;
-  for (int j = 0; j < d->nloops; ++j) dd.loop_part[j] = d->particle[d->loop_line[j]] ? 1 : 0;
+// Descriptor fields derived from the diagram alone (loop radii, masks in
+// line-slot order, prefactor with the (2 pi)^{-3L} measure).
+void fill_diag_dev(const Diagram &d, DiagDev &dd) {
+  int slot_line[kMaxLines];
+  line_slots(d, slot_line);
+  for (int j = 0; j < d.nloops; ++j) dd.loop_part[j] = d.particle[d.loop_line[j]] ? 1 : 0;
   dd.part_mask = 0;
-  for (int l = 0; l < d->nlines; ++l)
-    if (d->particle[l]) dd.part_mask |= 1u << l;
-  dd.line_mask = (1u << d->nlines) - 1u;
-  dd.pref = d->prefactor * std::pow(2.0 * M_PI, -3.0 * d->nloops);
+  for (int sl = 0; sl < d.nlines; ++sl)
+    if (d.particle[slot_line[sl]]) dd.part_mask |= 1u << sl;
+  dd.line_mask = (1u << d.nlines) - 1u;
+  dd.pref = d.prefactor * std::pow(2.0 * M_PI, -3.0 * d.nloops);
   auto pack = [&](const int *c) {
     uint32_t m = 0;
-    for (int j = 0; j < d->nloops; ++j) {
+    for (int j = 0; j < d.nloops; ++j) {
       if (c[j] == 1) m |= 1u << j;
       else if (c[j] == -1) m |= 1u << (8 + j);
       else if (c[j] == 2) m |= 1u << (16 + j);
@@ -203,21 +227,52 @@ void fill_diag_dev(const Diagram &diag, DiagDev &dd) {
     }
     return m;
   };
-  for (int l = 0; l < d->nlines; ++l) dd.lmask[l] = pack(d->coef[l]);
-  for (int v = 0; v < d->order; ++v) {
+  for (int sl = 0; sl < d.nlines; ++sl) dd.lmask[sl] = pack(d.coef[slot_line[sl]]);
+  for (int v = 0; v < d.order; ++v) {
     int cp[kMaxLoops], cq[kMaxLoops];
-    for (int j = 0; j < d->nloops; ++j) {
-      cp[j] = d->coef[d->vout[v][0]][j] - d->coef[d->vout[v][1]][j];
-      cq[j] = d->coef[d->vin[v][0]][j] - d->coef[d->vin[v][1]][j];
+    for (int j = 0; j < d.nloops; ++j) {
+      cp[j] = d.coef[d.vout[v][0]][j] - d.coef[d.vout[v][1]][j];
+      cq[j] = d.coef[d.vin[v][0]][j] - d.coef[d.vin[v][1]][j];
     }
     dd.pmask_v[v] = pack(cp);
     dd.qmask_v[v] = pack(cq);
   }
-  for (int c = 0; c < d->ncuts; ++c)
-    for (int l = 0; l < d->nlines; ++l) {
-      if (d->cut[c][l] > 0) dd.cut_hole[c] |= 1u << l;
-      if (d->cut[c][l] < 0) dd.cut_part[c] |= 1u << l;
+  for (int c = 0; c < d.ncuts; ++c)
+    for (int sl = 0; sl < d.nlines; ++sl) {
+      const int l = slot_line[sl];
+      if (d.cut[c][l] > 0) dd.cut_hole[c] |= 1u << sl;
+      if (d.cut[c][l] < 0) dd.cut_part[c] |= 1u << sl;
     }
+}
+
+// Appends one diagram's label tables.  group_base / term_base / coef_base
+// are the device element indices at which the three vectors start, so the
+// offsets stored in the descriptor are absolute for the kernel's table bases.
+void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
+                         std::vector<TermDev> &terms, std::vector<CoefDev> &coefs,
+                         size_t group_base, size_t term_base, size_t coef_base) {
+  const LabelTables lt = label_tables(d, q);
+  dd.group_off = static_cast<int>(group_base + groups.size());
+  dd.ngroups = static_cast<int>(lt.groups.size());
+  dd.term_off = static_cast<int>(term_base + terms.size());
+  dd.nterms = static_cast<int>(lt.terms.size());
+  const size_t t0 = term_base + terms.size();
+  for (const auto &g : lt.groups) {
+    GroupDev gd{};
+    gd.tau = g.tau;
+    gd.first = static_cast<int>(t0 + g.first);
+    gd.count = g.count;
+    gd.coef_off = static_cast<int>(coef_base + coefs.size());
+    for (double c : g.coef) coefs.push_back(CoefDev{c, static_cast<float>(c), 0.0f});
+    groups.push_back(gd);
+  }
+  for (const auto &t : lt.terms) {
+    TermDev tm{};
+    tm.mult = t.mult;
+    tm.codes = t.codes;
+    tm.multf = static_cast<float>(t.mult);
+    terms.push_back(tm);
+  }
 }
 
 // Medium-dependent task fields: Fermi momenta, loop radii, 1/density, bands.
@@ -242,6 +297,7 @@ int compile_tables(mbpt_task_set *set) {
   set->diags.clear();
   set->groups.clear();
   set->terms.clear();
+  set->coefs.clear();
   set->task_diag.assign(set->tasks.size(), -1);
   set->flops.assign(set->tasks.size(), FlopModel{});
   std::vector<std::pair<int, int>> keys;
@@ -259,38 +315,16 @@ int compile_tables(mbpt_task_set *set) {
       set_err(ctx, "unknown diagram");
       return MBPT_EINVAL;
     }
-    const LabelList ll = build_labels(*d, q);
     DiagDev dd{};
     dd.order = d->order;
     dd.nlines = d->nlines;
     dd.nloops = d->nloops;
     dd.ncuts = d->ncuts;
-    dd.group_off = static_cast<int>(set->groups.size());
-    dd.term_off = static_cast<int>(set->terms.size());
-    dd.nterms = static_cast<int>(ll.terms.size());
     fill_diag_dev(*d, dd);
-    // isospin groups: terms sorted by tau
-    for (size_t i = 0; i < ll.terms.size();) {
-      size_t j = i;
-      while (j < ll.terms.size() && ll.terms[j].tau_mask == ll.terms[i].tau_mask) ++j;
-      GroupDev g{};
-      g.tau = ll.terms[i].tau_mask;
-      g.first = static_cast<int>(set->terms.size() + i);
-      g.count = static_cast<int>(j - i);
-      set->groups.push_back(g);
-      i = j;
-    }
-    dd.ngroups = static_cast<int>(set->groups.size()) - dd.group_off;
-    for (const auto &lt : ll.terms) {
-      TermDev tm{};
-      tm.mult = lt.mult;
-      tm.codes = lt.codes;
-      tm.multf = static_cast<float>(lt.mult);
-      set->terms.push_back(tm);
-    }
+    append_label_tables(*d, q, dd, set->groups, set->terms, set->coefs, 0, 0, 0);
     FlopModel fm;
-    count_flops(*d, q, ctx->v.reg_exp / 2, fm);
-    fm.all_terms = static_cast<double>(ll.terms.size());
+    count_flops(*d, q, ctx->v.reg_exp / 2, ctx->desc.label_mode, fm);
+    fm.all_units = ctx->desc.label_mode ? dd.nterms : dd.ngroups;
     set->diag_flops.push_back(fm);
     set->diags.push_back(dd);
     keys.push_back(key);
@@ -335,7 +369,7 @@ size_t items_for(const mbpt_task_set *set, uint64_t samples) {
 }
 
 struct Layout {
-  size_t tasks, diags, groups, terms, grids, hists, partials, counters, reslog, total;
+  size_t tasks, diags, groups, terms, coefs, grids, hists, partials, counters, reslog, total;
 };
 
 Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, int nb) {
@@ -350,6 +384,8 @@ Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, 
   off = align256(off + std::max<size_t>(1, set->groups.size()) * sizeof(GroupDev));
   L.terms = off;
   off = align256(off + std::max<size_t>(1, set->terms.size()) * sizeof(TermDev));
+  L.coefs = off;
+  off = align256(off + std::max<size_t>(1, set->coefs.size()) * sizeof(CoefDev));
   size_t gd = 0, hd = 0;
   for (const auto &td : set->tasks) {
     gd += 3 * (td.order + 1) * (nb + 1);
@@ -377,6 +413,7 @@ KArgs kargs_of(const mbpt_task_set *set) {
   a.diags = set->d_diags;
   a.groups = set->d_groups;
   a.terms = set->d_terms;
+  a.gcoef = set->d_coefs;
   a.grids = set->d_grids;
   a.hists = set->d_hists;
   a.partials = set->d_partials;
@@ -385,6 +422,7 @@ KArgs kargs_of(const mbpt_task_set *set) {
   a.ntasks = static_cast<int>(set->tasks.size());
   a.total_items = 0;
   a.spt = set->spt;
+  a.label_mode = ctx->desc.label_mode;
   const mbpt_interaction &v = ctx->v;
   a.phys.V0 = v.C0 * v.hbarc;
   a.phys.Vy = v.Cy * v.hbarc;
@@ -429,6 +467,7 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
   set->d_diags = reinterpret_cast<DiagDev *>(base + L.diags);
   set->d_groups = reinterpret_cast<GroupDev *>(base + L.groups);
   set->d_terms = reinterpret_cast<TermDev *>(base + L.terms);
+  set->d_coefs = reinterpret_cast<CoefDev *>(base + L.coefs);
   set->d_grids = reinterpret_cast<double *>(base + L.grids);
   set->d_hists = reinterpret_cast<double *>(base + L.hists);
   set->d_partials = reinterpret_cast<double *>(base + L.partials);
@@ -443,6 +482,9 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
                                ctx->stream));
   if (!set->terms.empty())
     HIPCHK(ctx, hipMemcpyAsync(set->d_terms, set->terms.data(), set->terms.size() * sizeof(TermDev),
+                               hipMemcpyHostToDevice, ctx->stream));
+  if (!set->coefs.empty())
+    HIPCHK(ctx, hipMemcpyAsync(set->d_coefs, set->coefs.data(), set->coefs.size() * sizeof(CoefDev),
                                hipMemcpyHostToDevice, ctx->stream));
   int rc = upload_params(set);
   if (rc) return rc;
@@ -747,7 +789,7 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
         if (rc) return rc;
         if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&set->graph_exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
         set->graph_iters = iters;
       }
@@ -895,7 +937,7 @@ extern "C" int mbpt_task_flops(const mbpt_task_set *set, int task, double *flops
                                double *transcendentals) {
   if (!set || task < 0 || task >= static_cast<int>(set->tasks.size())) return MBPT_EINVAL;
   const FlopModel &f = set->flops[task];
-  if (flops) *flops = f.pre + f.post + f.per_term * f.all_terms;
+  if (flops) *flops = f.pre + f.post + f.per_term * f.all_units;
   if (transcendentals) *transcendentals = f.transc_pre + f.transc_post;
   return MBPT_OK;
 }

@@ -15,9 +15,9 @@ namespace mbpt {
 struct FlopModel {
   double pre = 0.0;        // every sample
   double post = 0.0;       // samples past the Pauli test
-  double per_term = 0.0;   // per label term evaluated
+  double per_term = 0.0;   // per label unit evaluated (isospin group or explicit term)
   double transc_pre = 0.0, transc_post = 0.0;
-  double all_terms = 0.0;  // terms of the whole list
+  double all_units = 0.0;  // label units of the whole list (groups or terms)
 };
 
 }  // namespace mbpt
@@ -45,6 +45,7 @@ struct mbpt_task_set {
   std::vector<mbpt::DiagDev> diags;
   std::vector<mbpt::GroupDev> groups;
   std::vector<mbpt::TermDev> terms;
+  std::vector<mbpt::CoefDev> coefs;
   std::vector<int> task_diag;
   std::vector<mbpt::FlopModel> flops, diag_flops;
   int max_nd = 0;
@@ -60,6 +61,7 @@ struct mbpt_task_set {
   mbpt::DiagDev *d_diags = nullptr;
   mbpt::GroupDev *d_groups = nullptr;
   mbpt::TermDev *d_terms = nullptr;
+  mbpt::CoefDev *d_coefs = nullptr;
   double *d_grids = nullptr, *d_hists = nullptr, *d_partials = nullptr, *d_reslog = nullptr;
   uint64_t *d_counters = nullptr;
   int grid_blocks = 1;
@@ -76,7 +78,10 @@ namespace mbpt {
 struct Diagram;
 void set_err(mbpt_context *ctx, const std::string &msg);
 int hip_fail(mbpt_context *ctx, hipError_t e, const char *what);
-void count_flops(const Diagram &d, int q, int half_exp, FlopModel &f);
+void count_flops(const Diagram &d, int q, int half_exp, int label_mode, FlopModel &f);
+void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
+                         std::vector<TermDev> &terms, std::vector<CoefDev> &coefs,
+                         size_t group_base, size_t term_base, size_t coef_base);
 void fill_diag_dev(const Diagram &d, DiagDev &dd);
 void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T);
 void result_of(const TaskDev &S, mbpt_result &r);

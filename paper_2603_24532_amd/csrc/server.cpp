@@ -153,6 +153,16 @@ struct mbpt_server {
   uint64_t next_ticket = 1;
   std::chrono::steady_clock::time_point t0;
   std::vector<FlopModel> flops;
+  // compiled tables per (order, diagram id), offsets relative to 0
+  struct Compiled {
+    DiagDev dd;
+    std::vector<GroupDev> groups;
+    std::vector<TermDev> terms;
+    std::vector<CoefDev> coefs;
+    FlopModel fm;
+    size_t bytes;  // arena bytes of the three tables
+  };
+  std::map<std::pair<int, int>, Compiled> compiled;
 };
 
 namespace {
@@ -167,6 +177,7 @@ KArgs server_kargs(const mbpt_server *s) {
   // workspace base
   a.groups = reinterpret_cast<const GroupDev *>(b);
   a.terms = reinterpret_cast<const TermDev *>(b);
+  a.gcoef = reinterpret_cast<const CoefDev *>(b);
   a.grids = reinterpret_cast<double *>(b + s->L.grids);
   a.hists = reinterpret_cast<double *>(b + s->L.hists);
   a.partials = reinterpret_cast<double *>(b + s->L.partials);
@@ -174,6 +185,7 @@ KArgs server_kargs(const mbpt_server *s) {
   a.reslog = reinterpret_cast<double *>(b + s->L.reslog);
   a.ntasks = s->max_slots;
   a.spt = kSpt;
+  a.label_mode = ctx->desc.label_mode;
   const mbpt_interaction &v = ctx->v;
   a.phys.V0 = v.C0 * v.hbarc;
   a.phys.Vy = v.Cy * v.hbarc;
@@ -186,32 +198,34 @@ KArgs server_kargs(const mbpt_server *s) {
   return a;
 }
 
+// Tables of a diagram compiled once per server (offsets relative to 0).
+const mbpt_server::Compiled &compiled_of(mbpt_server *s, int order, int id) {
+  auto key = std::make_pair(order, id);
+  auto it = s->compiled.find(key);
+  if (it != s->compiled.end()) return it->second;
+  const Diagram *d = get_diagram(order, id);
+  mbpt_server::Compiled c{};
+  c.dd.order = d->order;
+  c.dd.nlines = d->nlines;
+  c.dd.nloops = d->nloops;
+  c.dd.ncuts = d->ncuts;
+  fill_diag_dev(*d, c.dd);
+  append_label_tables(*d, 4, c.dd, c.groups, c.terms, c.coefs, 0, 0, 0);
+  count_flops(*d, 4, s->ctx->v.reg_exp / 2, s->ctx->desc.label_mode, c.fm);
+  c.fm.all_units = s->ctx->desc.label_mode ? c.dd.nterms : c.dd.ngroups;
+  c.bytes = a256(c.groups.size() * sizeof(GroupDev)) + a256(c.terms.size() * sizeof(TermDev)) +
+            a256(c.coefs.size() * sizeof(CoefDev));
+  return s->compiled.emplace(key, std::move(c)).first->second;
+}
+
 // Returns 0 when admitted, 1 when it does not fit now, < 0 on a HIP error.
 int admit_one(mbpt_server *s, Req &q, int slot) {
   mbpt_context *ctx = s->ctx;
   const Diagram *d = get_diagram(q.r.order, q.r.diagram_id);
-  const LabelList ll = build_labels(*d, 4);
-  std::vector<GroupDev> groups;
-  std::vector<TermDev> terms;
-  for (size_t i = 0; i < ll.terms.size();) {
-    size_t j = i;
-    while (j < ll.terms.size() && ll.terms[j].tau_mask == ll.terms[i].tau_mask) ++j;
-    GroupDev g{};
-    g.tau = ll.terms[i].tau_mask;
-    g.first = static_cast<int>(i);  // rebased below
-    g.count = static_cast<int>(j - i);
-    groups.push_back(g);
-    i = j;
-  }
-  for (const auto &lt : ll.terms) {
-    TermDev tm{};
-    tm.mult = lt.mult;
-    tm.codes = lt.codes;
-    tm.multf = static_cast<float>(lt.mult);
-    terms.push_back(tm);
-  }
-  const size_t gbytes = a256(groups.size() * sizeof(GroupDev));
-  const size_t need_bytes = gbytes + a256(terms.size() * sizeof(TermDev));
+  const mbpt_server::Compiled &c = compiled_of(s, q.r.order, q.r.diagram_id);
+  const size_t gbytes = a256(c.groups.size() * sizeof(GroupDev));
+  const size_t tbytes = a256(c.terms.size() * sizeof(TermDev));
+  const size_t need_bytes = gbytes + tbytes + a256(c.coefs.size() * sizeof(CoefDev));
   const size_t need_items = items_of(q.r.samples_per_iter);
   size_t byte_at = 0, item_at = 0;
   if (!s->bytes.alloc(need_bytes, byte_at)) return 1;
@@ -223,20 +237,22 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   q.byte_n = need_bytes;
   q.item_at = item_at;
   q.item_n = need_items;
-  const size_t g_off = s->L.arena + byte_at;  // byte offsets from the workspace base
+  // byte offsets from the workspace base; the descriptor holds element
+  // indices from that base
+  const size_t g_off = s->L.arena + byte_at;
   const size_t t_off = g_off + gbytes;
+  const size_t c_off = t_off + tbytes;
+  const int g_index = static_cast<int>(g_off / sizeof(GroupDev));
   const int t_index = static_cast<int>(t_off / sizeof(TermDev));
-  for (auto &g : groups) g.first += t_index;
-  DiagDev dd{};
-  dd.order = d->order;
-  dd.nlines = d->nlines;
-  dd.nloops = d->nloops;
-  dd.ncuts = d->ncuts;
-  dd.group_off = static_cast<int>(g_off / sizeof(GroupDev));
-  dd.ngroups = static_cast<int>(groups.size());
-  dd.term_off = t_index;
-  dd.nterms = static_cast<int>(terms.size());
-  fill_diag_dev(*d, dd);
+  const int c_index = static_cast<int>(c_off / sizeof(CoefDev));
+  std::vector<GroupDev> groups = c.groups;
+  for (auto &g : groups) {
+    g.first += t_index;
+    g.coef_off += c_index;
+  }
+  DiagDev dd = c.dd;
+  dd.group_off += g_index;
+  dd.term_off += t_index;
   TaskDev T{};
   T.diag = slot;
   T.nd = d->ndim;
@@ -256,7 +272,9 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   char *b = s->ws;
   MBPT_HIPCHK(ctx, hipMemcpyAsync(b + g_off, groups.data(), groups.size() * sizeof(GroupDev),
                                   hipMemcpyHostToDevice, ctx->stream));
-  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + t_off, terms.data(), terms.size() * sizeof(TermDev),
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + t_off, c.terms.data(), c.terms.size() * sizeof(TermDev),
+                                  hipMemcpyHostToDevice, ctx->stream));
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + c_off, c.coefs.data(), c.coefs.size() * sizeof(CoefDev),
                                   hipMemcpyHostToDevice, ctx->stream));
   MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.diags + slot * sizeof(DiagDev), &dd, sizeof(DiagDev),
                                   hipMemcpyHostToDevice, ctx->stream));
@@ -266,9 +284,7 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   MBPT_HIPCHK(ctx, launch_init(a, slot, 1, ctx->stream));
   // the copies above read host memory that is reused: wait for them
   MBPT_HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  FlopModel fm;
-  count_flops(*d, 4, ctx->v.reg_exp / 2, fm);
-  s->flops[slot] = fm;
+  s->flops[slot] = c.fm;
   q.state = 1;
   q.slot = slot;
   q.t_admit = now_s(s->t0);
@@ -341,6 +357,10 @@ extern "C" int mbpt_server_submit(mbpt_server *s, const mbpt_request *req, uint6
   if (static_cast<int>(s->queue.size()) >= s->max_queue) {
     set_err(ctx, "server_submit: queue full");
     return MBPT_EBUSY;
+  }
+  if (compiled_of(s, req->order, req->diagram_id).bytes > kTermBytesPerSlot) {
+    set_err(ctx, "server_submit: diagram label tables exceed the per-slot table arena");
+    return MBPT_ENOMEM;
   }
   Req q;
   q.r = *req;

@@ -4,6 +4,7 @@ import itertools
 import os
 import re
 
+import numpy as np
 import pytest
 
 import oracle as O
@@ -92,3 +93,69 @@ def test_invalid_arguments(M):
         M.mbpt_num_diagrams(6)
     with pytest.raises(M.MbptError):
         M.mbpt_diagram_matrix(3, 3)
+
+
+def _brute_poly(order, did, q):
+    """Per isospin configuration, the coefficients c_E of the label sum
+    sum_labels prod_v (dir_v V_d,v - exc_v V_e,v) expanded over vertex subsets
+    E (bit v: vertex v takes -V_e), by enumerating every label assignment."""
+    d = O.diagram_dict(order, did)
+    rows = {}
+    for lab in itertools.product(range(q), repeat=d["nlines"]):
+        dirs, excs = [], []
+        for v in range(order):
+            o1, o2 = lab[d["vout"][v][0]], lab[d["vout"][v][1]]
+            i1, i2 = lab[d["vin"][v][0]], lab[d["vin"][v][1]]
+            dirs.append(1 if (o1 == i1 and o2 == i2) else 0)
+            excs.append(1 if (o1 == i2 and o2 == i1) else 0)
+        key = tuple(x >> 1 for x in lab) if q == 4 else ()
+        row = rows.setdefault(key, [0] * (1 << order))
+        for E in range(1 << order):
+            c = 1
+            for v in range(order):
+                c *= -excs[v] if (E >> v) & 1 else dirs[v]
+            row[E] += c
+    return sorted(tuple(r) for r in rows.values() if any(r))
+
+
+@pytest.mark.parametrize("order,q", [(1, 2), (1, 4), (2, 2), (2, 4), (3, 2), (3, 4), (4, 2)])
+def test_label_polynomial_vs_brute_force(M, order, q):
+    matter = M.MBPT_NUCLEAR if q == 4 else M.MBPT_NEUTRON
+    for did in range(M.mbpt_num_diagrams(order)):
+        rows = M.mbpt_diagram_label_poly(order, did, matter)
+        assert len(rows) == M.mbpt_diagram_label_stats(order, did, matter)[1]
+        got = sorted(tuple(int(round(c)) for c in r) for r in rows)
+        assert all(c == int(c) for r in rows for c in r)
+        assert got == _brute_poly(order, did, q)
+
+
+def _cycles(d, E):
+    # line -> successor line when every vertex in E swaps its outgoing pair
+    succ = []
+    for l in range(d["nlines"]):
+        v = d["head"][l]
+        slot = 0 if d["vin"][v][0] == l else 1
+        if (E >> v) & 1:
+            slot = 1 - slot
+        succ.append(d["vout"][v][slot])
+    seen, n = set(), 0
+    for l in range(d["nlines"]):
+        if l in seen:
+            continue
+        n += 1
+        while l not in seen:
+            seen.add(l)
+            l = succ[l]
+    return n
+
+
+def test_label_polynomial_closed_loop_rule_fifth_order(M):
+    # summed over isospin configurations, c_E = (-1)^{|E|} q^{cycles(E)}: each
+    # closed loop of the line permutation carries one free label (q values)
+    for did in range(0, 840, 7):
+        d = O.diagram_dict(5, did)
+        for matter, q in ((M.MBPT_NEUTRON, 2), (M.MBPT_NUCLEAR, 4)):
+            rows = np.array(M.mbpt_diagram_label_poly(5, did, matter))
+            tot = rows.sum(axis=0)
+            for E in range(32):
+                assert tot[E] == (-1) ** bin(E).count("1") * q ** _cycles(d, E), (did, q, E)

@@ -35,17 +35,20 @@ CASES = [
 def test_fp32_per_sample(M, order, did, q, n, x):
     print(f"case order={order} id={did} q={q} n={n} x={x}", flush=True)
     count = 20000 if order < 4 else 6000
-    run = Run(M, [_task(order, did, q, n, x, key=5)], max_samples=4096, precision=M.MBPT_FP32)
-    try:
-        w = M.mbpt_dump_samples(run.set, 0, 0, 0, count)
-    finally:
-        run.close()
     pb = O.problem(order, did, density=n, proton_fraction=x, q=q, seed=1, task_key=5,
                    label_method=0 if (q == 2 or order <= 3) else 1)
     wo, co = O.sample_values(pb, O.uniform_grid(3 * (order + 1)), 0, 0, count)
-    ratio = np.abs(w - wo) / np.maximum(co, 1e-300)
-    print(f"  max |dw|/W_cond = {ratio.max():.3e}, nonzero {np.count_nonzero(wo)}")
-    assert np.all(np.abs(w - wo) <= TOL32 * co + 1e-300), ratio.max()
+    for label_mode in (0, 1):
+        run = Run(M, [_task(order, did, q, n, x, key=5)], max_samples=4096,
+                  precision=M.MBPT_FP32, label_mode=label_mode)
+        try:
+            w = M.mbpt_dump_samples(run.set, 0, 0, 0, count)
+        finally:
+            run.close()
+        ratio = np.abs(w - wo) / np.maximum(co, 1e-300)
+        print(f"  label_mode {label_mode}: max |dw|/W_cond = {ratio.max():.3e}, "
+              f"nonzero {np.count_nonzero(wo)}")
+        assert np.all(np.abs(w - wo) <= TOL32 * co + 1e-300), (label_mode, ratio.max())
 
 
 @pytest.mark.parametrize("mode", [0, 1])

@@ -33,12 +33,12 @@ class Run:
     """One context + task set + workspace (torch tensor) on cuda:0."""
 
     def __init__(self, M, tasks, max_samples, max_iters=32, precision=0, mode=0, seed=1,
-                 block=256, spt=16):
+                 block=256, spt=16, label_mode=0):
         import torch
         self.M = M
         self.stream = torch.cuda.Stream()
         self.ctx = M.mbpt_context_create(stream=self.stream.cuda_stream, precision=precision,
-                                         seed=seed)
+                                         seed=seed, label_mode=label_mode)
         self.set = M.mbpt_create_task_set(self.ctx, tasks)
         M.mbpt_set_launch_mode(self.set, mode)
         M.mbpt_set_blocking(self.set, block, spt)
@@ -70,19 +70,25 @@ SAMPLE_CASES = [
 
 @pytest.mark.parametrize("order,did,q,n,x", SAMPLE_CASES)
 def test_per_sample_iteration0(M, order, did, q, n, x):
+    """Both label-sum forms (multilinear polynomial per isospin configuration,
+    and the explicit assignment list) against the oracle, sample by sample."""
     print(f"case order={order} id={did} q={q} n={n} x={x}", flush=True)
     count = 5000 if order < 4 else 3000  # several blocks plus a ragged tail
     first = (1 << 32) + 12345 if order == 2 else 0  # exercises the high counter word
-    run = Run(M, [_task(order, did, q, n, x, key=7)], max_samples=4096)
-    try:
-        w = M.mbpt_dump_samples(run.set, 0, 0, first, count)
-    finally:
-        run.close()
     pb = O.problem(order, did, density=n, proton_fraction=x, q=q, seed=1, task_key=7,
                    label_method=0 if (q == 2 or order <= 3) else 1)
     wo, co = O.sample_values(pb, O.uniform_grid(3 * (order + 1)), 0, first, count)
     assert np.count_nonzero(wo) > 0
-    _check_samples(w, wo, co, (order, did, q))
+    ws = []
+    for label_mode in (0, 1):
+        run = Run(M, [_task(order, did, q, n, x, key=7)], max_samples=4096,
+                  label_mode=label_mode)
+        try:
+            ws.append(M.mbpt_dump_samples(run.set, 0, 0, first, count))
+        finally:
+            run.close()
+        _check_samples(ws[-1], wo, co, (order, did, q, label_mode))
+    _check_samples(ws[0], ws[1], co, (order, did, q, "modes"))
 
 
 def test_full_run_config1_matches_oracle(M):
