@@ -1,6 +1,8 @@
 // Device-side tables shared by the kernels and the host runtime that fills
 // them.  Everything lives in the caller-bound workspace.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace mbpt {
@@ -105,6 +107,7 @@ struct KArgs {
   uint64_t *counters;     // kItemCounters per work item
   double *reslog;         // (I, var) pairs
   const CoefDev *gcoef;   // factorised label-sum coefficients
+  const int2 *olist;      // (first item, task), grouped by order, ascending items
   int ntasks;
   int total_items;
   int spt;                // samples per thread per item

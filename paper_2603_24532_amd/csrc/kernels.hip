@@ -734,28 +734,23 @@ __global__ __launch_bounds__(256) void sample_single(KArgs a, int t) {
   process_item<ORDER, Q, P>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
 }
 
-// Persistent launch over all work items of all tasks (items grouped by task,
-// task t owning items [item_begin, item_begin + nitems)).  MAXO is the highest
-// order present, so the register allocation of a batch is that of its largest
-// diagrams and not of fifth order.
-template <int Q, int P, int MAXO>
-__global__ __launch_bounds__(256) void sample_batched(KArgs a) {
+// One launch over the work items of the tasks of one order: olist[k0, k1)
+// lists them as (first item, task) with ascending first item, their items are
+// numbered contiguously from olist[k0].x, and block b takes item
+// olist[k0].x + b.  One launch per order keeps each launch's register
+// allocation that of its own order.
+template <int ORDER, int Q, int P>
+__global__ __launch_bounds__(256) void sample_order(KArgs a, int k0, int k1) {
   extern __shared__ double smem[];
-  for (int item = blockIdx.x; item < a.total_items; item += gridDim.x) {
-    int lo = 0, hi = a.ntasks - 1;  // last task with item_begin <= item
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.tasks[mid].item_begin <= item) lo = mid;
-      else hi = mid - 1;
-    }
-    const int t = lo;
-    const int order = a.tasks[t].order;
-    if (order == 1) process_item<1, Q, P>(a, t, item, smem);
-    else if (MAXO >= 2 && order == 2) process_item<(MAXO >= 2 ? 2 : 1), Q, P>(a, t, item, smem);
-    else if (MAXO >= 3 && order == 3) process_item<(MAXO >= 3 ? 3 : 1), Q, P>(a, t, item, smem);
-    else if (MAXO >= 4 && order == 4) process_item<(MAXO >= 4 ? 4 : 1), Q, P>(a, t, item, smem);
-    else if (MAXO >= 5 && order == 5) process_item<(MAXO >= 5 ? 5 : 1), Q, P>(a, t, item, smem);
+  const int2 *__restrict__ ol = a.olist;
+  const int item = ol[k0].x + static_cast<int>(blockIdx.x);
+  int lo = k0, hi = k1 - 1;  // last entry with first item <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ol[mid].x <= item) lo = mid;
+    else hi = mid - 1;
   }
+  process_item<ORDER, Q, P>(a, ol[lo].y, item, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1022,26 +1017,26 @@ hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int pre
 }
 
 template <int Q, int P>
-static hipError_t batched_qp(const KArgs &a, int maxo, int grid, int block, size_t lds,
-                             hipStream_t st) {
-  switch (maxo) {
-    case 1:
-    case 2: hipLaunchKernelGGL((sample_batched<Q, P, 2>), dim3(grid), dim3(block), lds, st, a); break;
-    case 3: hipLaunchKernelGGL((sample_batched<Q, P, 3>), dim3(grid), dim3(block), lds, st, a); break;
-    case 4: hipLaunchKernelGGL((sample_batched<Q, P, 4>), dim3(grid), dim3(block), lds, st, a); break;
-    default: hipLaunchKernelGGL((sample_batched<Q, P, 5>), dim3(grid), dim3(block), lds, st, a); break;
+static hipError_t order_qp(const KArgs &a, int order, int k0, int k1, int grid, int block,
+                           size_t lds, hipStream_t st) {
+  switch (order) {
+    case 1: hipLaunchKernelGGL((sample_order<1, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 2: hipLaunchKernelGGL((sample_order<2, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 3: hipLaunchKernelGGL((sample_order<3, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 4: hipLaunchKernelGGL((sample_order<4, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 5: hipLaunchKernelGGL((sample_order<5, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sample_batched(const KArgs &a, int q, int prec, int max_nd, int grid, int block,
-                                 hipStream_t st) {
-  const size_t lds = sample_lds_bytes(max_nd, a.phys.nb, block);
-  const int maxo = max_nd / 3 - 1;
-  if (q == 4) return prec ? batched_qp<4, 1>(a, maxo, grid, block, lds, st)
-                          : batched_qp<4, 0>(a, maxo, grid, block, lds, st);
-  return prec ? batched_qp<2, 1>(a, maxo, grid, block, lds, st)
-              : batched_qp<2, 0>(a, maxo, grid, block, lds, st);
+hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, int k0, int k1,
+                               int nitems, int block, hipStream_t st) {
+  const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block);
+  if (q == 4) return prec ? order_qp<4, 1>(a, order, k0, k1, nitems, block, lds, st)
+                          : order_qp<4, 0>(a, order, k0, k1, nitems, block, lds, st);
+  return prec ? order_qp<2, 1>(a, order, k0, k1, nitems, block, lds, st)
+              : order_qp<2, 0>(a, order, k0, k1, nitems, block, lds, st);
 }
 
 hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int max_nd, double alpha,
@@ -1075,26 +1070,6 @@ hipError_t launch_dump(const KArgs &a, int t, int order, int q, int prec, uint32
                           : dump_q<4, 0>(a, t, order, iter, first, count, out, st);
   return prec ? dump_q<2, 1>(a, t, order, iter, first, count, out, st)
               : dump_q<2, 0>(a, t, order, iter, first, count, out, st);
-}
-
-template <int Q, int P>
-static int occ_qp(int maxo, int block, size_t lds) {
-  int n = 0;
-  hipError_t e;
-  switch (maxo) {
-    case 1:
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<Q, P, 2>, block, lds); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<Q, P, 3>, block, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<Q, P, 4>, block, lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sample_batched<Q, P, 5>, block, lds); break;
-  }
-  return e == hipSuccess ? n : 1;
-}
-
-int batched_occupancy(int q, int prec, int max_nd, int block, size_t lds) {
-  const int maxo = max_nd / 3 - 1;
-  if (q == 4) return prec ? occ_qp<4, 1>(maxo, block, lds) : occ_qp<4, 0>(maxo, block, lds);
-  return prec ? occ_qp<2, 1>(maxo, block, lds) : occ_qp<2, 0>(maxo, block, lds);
 }
 
 hipError_t launch_init(const KArgs &a, int first, int ntasks, hipStream_t st) {

@@ -147,12 +147,14 @@ extern "C" int mbpt_set_interaction(mbpt_context *ctx, const mbpt_interaction *v
     return MBPT_EINVAL;
   }
   ctx->v = *v;
+  ++ctx->epoch;
   return MBPT_OK;
 }
 
 extern "C" int mbpt_set_precision(mbpt_context *ctx, int precision) {
   if (!ctx || (precision != MBPT_FP64 && precision != MBPT_FP32)) return MBPT_EINVAL;
   ctx->desc.precision = precision;
+  ++ctx->epoch;
   return MBPT_OK;
 }
 
@@ -369,7 +371,7 @@ size_t items_for(const mbpt_task_set *set, uint64_t samples) {
 }
 
 struct Layout {
-  size_t tasks, diags, groups, terms, coefs, grids, hists, partials, counters, reslog, total;
+  size_t tasks, olist, diags, groups, terms, coefs, grids, hists, partials, counters, reslog, total;
 };
 
 Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, int nb) {
@@ -378,6 +380,8 @@ Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, 
   const size_t nt = set->tasks.size();
   L.tasks = off;
   off = align256(off + nt * sizeof(TaskDev));
+  L.olist = off;
+  off = align256(off + nt * sizeof(int2));
   L.diags = off;
   off = align256(off + set->diags.size() * sizeof(DiagDev));
   L.groups = off;
@@ -414,6 +418,7 @@ KArgs kargs_of(const mbpt_task_set *set) {
   a.groups = set->d_groups;
   a.terms = set->d_terms;
   a.gcoef = set->d_coefs;
+  a.olist = set->d_olist;
   a.grids = set->d_grids;
   a.hists = set->d_hists;
   a.partials = set->d_partials;
@@ -441,6 +446,9 @@ int upload_params(mbpt_task_set *set) {
   const size_t width = offsetof(TaskDev, iter);
   HIPCHK(ctx, hipMemcpy2DAsync(set->d_tasks, sizeof(TaskDev), set->h_tasks.data(), sizeof(TaskDev),
                                width, set->h_tasks.size(), hipMemcpyHostToDevice, ctx->stream));
+  if (!set->olist.empty())
+    HIPCHK(ctx, hipMemcpyAsync(set->d_olist, set->olist.data(), set->olist.size() * sizeof(int2),
+                               hipMemcpyHostToDevice, ctx->stream));
   return MBPT_OK;
 }
 
@@ -464,6 +472,7 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
   set->max_iters = max_iters;
   set->max_items = set->tasks.size() * items_for(set, max_samples);
   set->d_tasks = reinterpret_cast<TaskDev *>(base + L.tasks);
+  set->d_olist = reinterpret_cast<int2 *>(base + L.olist);
   set->d_diags = reinterpret_cast<DiagDev *>(base + L.diags);
   set->d_groups = reinterpret_cast<GroupDev *>(base + L.groups);
   set->d_terms = reinterpret_cast<TermDev *>(base + L.terms);
@@ -474,6 +483,7 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
   set->d_counters = reinterpret_cast<uint64_t *>(base + L.counters);
   set->d_reslog = reinterpret_cast<double *>(base + L.reslog);
   fill_task_params(set);
+  set->oranges.clear();
   HIPCHK(ctx, hipMemcpyAsync(set->d_diags, set->diags.data(), set->diags.size() * sizeof(DiagDev),
                              hipMemcpyHostToDevice, ctx->stream));
   if (!set->groups.empty())
@@ -649,6 +659,7 @@ extern "C" int mbpt_set_launch_mode(mbpt_task_set *set, int mode) {
   if (!set || mode < MBPT_LAUNCH_PER_TASK || mode > MBPT_LAUNCH_GRAPH) return MBPT_EINVAL;
   set->launch_mode = mode;
   set->drop_graph();
+  set->oranges.clear();
   return MBPT_OK;
 }
 
@@ -664,6 +675,7 @@ extern "C" int mbpt_set_blocking(mbpt_task_set *set, int threads_per_block, int 
   set->block = threads_per_block;
   set->spt = samples_per_thread;
   set->drop_graph();
+  set->oranges.clear();
   return MBPT_OK;
 }
 
@@ -713,23 +725,41 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
   for (int it = 0; it < iters; ++it) {
     size_t slot = 0;
     if (timed) timed_begin(ctx, slot);
-    HIPCHK(ctx, launch_sample_batched(a, set->q, ctx->desc.precision, set->max_nd,
-                                      set->grid_blocks, set->block, ctx->stream));
+    for (const auto &r : set->oranges)
+      HIPCHK(ctx, launch_sample_order(a, r.order, set->q, ctx->desc.precision, r.k0, r.k1,
+                                      r.nitems, set->block, ctx->stream));
     if (timed) timed_end(ctx, slot);
     HIPCHK(ctx, launch_finish(a, 0, nt, set->max_nd, alpha, ctx->stream));
   }
   return MBPT_OK;
 }
 
-int persistent_grid(mbpt_task_set *set, int total_items) {
-  mbpt_context *ctx = set->ctx;
-  int per_cu = 0;
-  const size_t lds = sample_lds_bytes(set->max_nd, ctx->desc.n_bins, set->block);
-  // occupancy of the fused kernel (register and LDS limited)
-  per_cu = batched_occupancy(set->q, ctx->desc.precision, set->max_nd, set->block, lds);
-  if (per_cu < 1) per_cu = 1;
-  const int g = per_cu * std::max(1, ctx->num_cus);
-  return std::max(1, std::min(total_items, g));
+// Work numbering grouped by order: the tasks of each order own a contiguous
+// item range, listed in olist as (first item, task), so one launch per order
+// (one block per item) covers them.
+void order_items(std::vector<TaskDev> &T, const std::vector<int> &active,
+                 std::vector<int2> &olist, std::vector<OrderRange> &ranges) {
+  olist.clear();
+  ranges.clear();
+  int item = 0;
+  for (int o = 1; o <= kMaxOrder; ++o) {
+    const int k0 = static_cast<int>(olist.size());
+    for (int t : active) {
+      if (T[t].order != o) continue;
+      T[t].item_begin = item;
+      olist.push_back(make_int2(item, t));
+      item += T[t].nitems;
+    }
+    const int k1 = static_cast<int>(olist.size());
+    if (k1 == k0) continue;
+    OrderRange r{};
+    r.order = o;
+    r.k0 = k0;
+    r.k1 = k1;
+    r.item_end = item;
+    r.nitems = item - olist[k0].x;
+    ranges.push_back(r);
+  }
 }
 
 }  // namespace mbpt
@@ -754,15 +784,28 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
     set_err(ctx, "integrate: more work items than the workspace holds");
     return MBPT_ENOMEM;
   }
+  if (set->epoch != ctx->epoch) {
+    // precision or interaction changed: captured launches and grids are stale
+    set->drop_graph();
+    set->oranges.clear();
+    set->epoch = ctx->epoch;
+  }
   bool changed = false;
+  std::vector<int> all(nt);
   for (int t = 0; t < nt; ++t) {
     TaskDev &T = set->h_tasks[t];
-    changed |= T.item_begin != item || T.nitems != per || T.nsamples != samples_per_iter;
-    T.item_begin = item;
-    T.store_begin = item;
+    all[t] = t;
+    changed |= T.nitems != per || T.nsamples != samples_per_iter;
     T.nitems = per;
     T.nsamples = samples_per_iter;
-    item += per;
+  }
+  if (changed || set->oranges.empty()) {
+    order_items(set->h_tasks, all, set->olist, set->oranges);
+    for (int t = 0; t < nt; ++t) set->h_tasks[t].store_begin = set->h_tasks[t].item_begin;
+    item = set->oranges.back().item_end;
+    changed = true;
+  } else {
+    item = set->oranges.back().item_end;
   }
   if (changed) {
     set->drop_graph();
@@ -771,7 +814,6 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
   }
   KArgs a = kargs_of(set);
   a.total_items = item;
-  set->grid_blocks = persistent_grid(set, item);
   uint64_t evals_before = 0;
   {
     int rc = 0;
@@ -989,6 +1031,7 @@ extern "C" int mbpt_autotune(mbpt_task_set *set, uint64_t samples_per_iter, int 
       for (int sp : spts) {
         set->block = b;
         set->spt = sp;
+        set->oranges.clear();
         if (items_for(set, samples_per_iter) > bound_chunk) continue;
         set->drop_graph();
         const int saved_mode = set->launch_mode;
@@ -1021,6 +1064,7 @@ extern "C" int mbpt_autotune(mbpt_task_set *set, uint64_t samples_per_iter, int 
   }
   set->block = best_b;
   set->spt = best_s;
+  set->oranges.clear();
   set->drop_graph();
   const int rc = mbpt_reset(set);
   if (rc) return rc;

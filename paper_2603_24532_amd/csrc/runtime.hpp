@@ -11,6 +11,12 @@
 
 namespace mbpt {
 
+// One sample launch over the tasks of one order: olist entries [k0, k1),
+// nitems items ending at item_end.
+struct OrderRange {
+  int order, k0, k1, item_end, nitems;
+};
+
 // Algorithmic FLOPs of one evaluation (see count_flops).
 struct FlopModel {
   double pre = 0.0;        // every sample
@@ -34,10 +40,12 @@ struct mbpt_context {
   double kernel_ms = 0.0;
   uint64_t evals = 0;
   double flops = 0.0;
+  uint64_t epoch = 0;  // bumped when precision or interaction changes
 };
 
 struct mbpt_task_set {
   mbpt_context *ctx = nullptr;
+  uint64_t epoch = ~uint64_t{0};  // context epoch the launches were set up for
   int q = 2;
   std::vector<mbpt_task_desc> tasks;
   int launch_mode = MBPT_LAUNCH_PER_TASK;
@@ -58,13 +66,15 @@ struct mbpt_task_set {
   int max_iters = 0;
   size_t max_items = 0;
   mbpt::TaskDev *d_tasks = nullptr;
+  int2 *d_olist = nullptr;
   mbpt::DiagDev *d_diags = nullptr;
   mbpt::GroupDev *d_groups = nullptr;
   mbpt::TermDev *d_terms = nullptr;
   mbpt::CoefDev *d_coefs = nullptr;
   double *d_grids = nullptr, *d_hists = nullptr, *d_partials = nullptr, *d_reslog = nullptr;
   uint64_t *d_counters = nullptr;
-  int grid_blocks = 1;
+  std::vector<int2> olist;                 // (first item, task) grouped by order
+  std::vector<mbpt::OrderRange> oranges;   // one sample launch per order
   hipGraphExec_t graph_exec = nullptr;
   int graph_iters = 0;
   void drop_graph() {
@@ -88,7 +98,8 @@ void result_of(const TaskDev &S, mbpt_result &r);
 void timed_begin(mbpt_context *ctx, size_t &slot);
 void timed_end(mbpt_context *ctx, size_t slot);
 void resolve_timing(mbpt_context *ctx);
-int batched_occupancy(int q, int prec, int max_nd, int block, size_t lds);
+void order_items(std::vector<TaskDev> &T, const std::vector<int> &active,
+                 std::vector<int2> &olist, std::vector<OrderRange> &ranges);
 }  // namespace mbpt
 
 #define MBPT_HIPCHK(ctx, call)                                      \

@@ -91,9 +91,14 @@ struct Req {
 };
 
 struct Layout {
-  size_t tasks, diags, grids, hists, reslog, partials, counters, arena, arena_bytes;
+  size_t tasks, olist, diags, grids, hists, reslog, partials, counters, arena, arena_bytes;
   size_t max_items;
 };
+
+// Pinned host staging of one step: admitted tables, descriptors and task
+// records, the parameter upload, the order list and the state download.  It
+// is reused once the step's closing synchronisation has passed.
+constexpr size_t kStageBytes = 4u << 20;
 
 size_t items_of(uint64_t samples) {
   const uint64_t chunk = static_cast<uint64_t>(kBlock) * kSpt;
@@ -101,7 +106,8 @@ size_t items_of(uint64_t samples) {
 }
 
 size_t slot_table_bytes(int slots, int nb) {
-  return a256(slots * sizeof(TaskDev)) + a256(slots * sizeof(DiagDev)) +
+  return a256(slots * sizeof(TaskDev)) + a256(slots * sizeof(int2)) +
+         a256(slots * sizeof(DiagDev)) +
          a256(static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double)) +
          a256(static_cast<size_t>(slots) * kMaxDim * nb * sizeof(double)) +
          a256(static_cast<size_t>(slots) * 2 * sizeof(double));
@@ -113,6 +119,8 @@ bool make_layout(int slots, int nb, size_t bytes, Layout &L) {
   size_t off = 0;
   L.tasks = off;
   off = a256(off + slots * sizeof(TaskDev));
+  L.olist = off;
+  off = a256(off + slots * sizeof(int2));
   L.diags = off;
   off = a256(off + slots * sizeof(DiagDev));
   L.grids = off;
@@ -163,6 +171,20 @@ struct mbpt_server {
     size_t bytes;  // arena bytes of the three tables
   };
   std::map<std::pair<int, int>, Compiled> compiled;
+  // pinned staging (see kStageBytes) and its fill level within a step
+  char *stage = nullptr;
+  size_t stage_used = 0;
+  TaskDev *pin_tasks = nullptr;   // parameter upload / state download
+  int2 *pin_olist = nullptr;
+  std::vector<int2> olist;
+  std::vector<OrderRange> ranges;
+  std::vector<int> admitted;      // slots admitted in the current step
+  ~mbpt_server() {
+    if (ctx) (void)hipStreamSynchronize(ctx->stream);
+    if (stage) (void)hipHostFree(stage);
+    if (pin_tasks) (void)hipHostFree(pin_tasks);
+    if (pin_olist) (void)hipHostFree(pin_olist);
+  }
 };
 
 namespace {
@@ -178,6 +200,7 @@ KArgs server_kargs(const mbpt_server *s) {
   a.groups = reinterpret_cast<const GroupDev *>(b);
   a.terms = reinterpret_cast<const TermDev *>(b);
   a.gcoef = reinterpret_cast<const CoefDev *>(b);
+  a.olist = reinterpret_cast<const int2 *>(b + s->L.olist);
   a.grids = reinterpret_cast<double *>(b + s->L.grids);
   a.hists = reinterpret_cast<double *>(b + s->L.hists);
   a.partials = reinterpret_cast<double *>(b + s->L.partials);
@@ -227,6 +250,9 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   const size_t tbytes = a256(c.terms.size() * sizeof(TermDev));
   const size_t need_bytes = gbytes + tbytes + a256(c.coefs.size() * sizeof(CoefDev));
   const size_t need_items = items_of(q.r.samples_per_iter);
+  // staging: tables (arena image), descriptor, task record
+  const size_t stage_need = need_bytes + a256(sizeof(DiagDev)) + a256(sizeof(TaskDev));
+  if (s->stage_used + stage_need > kStageBytes) return 1;  // next step
   size_t byte_at = 0, item_at = 0;
   if (!s->bytes.alloc(need_bytes, byte_at)) return 1;
   if (!s->items.alloc(need_items, item_at)) {
@@ -245,14 +271,20 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   const int g_index = static_cast<int>(g_off / sizeof(GroupDev));
   const int t_index = static_cast<int>(t_off / sizeof(TermDev));
   const int c_index = static_cast<int>(c_off / sizeof(CoefDev));
-  std::vector<GroupDev> groups = c.groups;
-  for (auto &g : groups) {
-    g.first += t_index;
-    g.coef_off += c_index;
+  char *st = s->stage + s->stage_used;
+  auto *sg = reinterpret_cast<GroupDev *>(st);
+  for (size_t i = 0; i < c.groups.size(); ++i) {
+    sg[i] = c.groups[i];
+    sg[i].first += t_index;
+    sg[i].coef_off += c_index;
   }
-  DiagDev dd = c.dd;
-  dd.group_off += g_index;
-  dd.term_off += t_index;
+  std::memcpy(st + gbytes, c.terms.data(), c.terms.size() * sizeof(TermDev));
+  std::memcpy(st + gbytes + tbytes, c.coefs.data(), c.coefs.size() * sizeof(CoefDev));
+  auto *sd = reinterpret_cast<DiagDev *>(st + need_bytes);
+  *sd = c.dd;
+  sd->group_off += g_index;
+  sd->term_off += t_index;
+  auto *sT = reinterpret_cast<TaskDev *>(st + need_bytes + a256(sizeof(DiagDev)));
   TaskDev T{};
   T.diag = slot;
   T.nd = d->ndim;
@@ -269,21 +301,18 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   fill_medium(ctx, q.r.density, x, T);
   T.active = 1;
   s->h_tasks[slot] = T;
+  *sT = T;
   char *b = s->ws;
-  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + g_off, groups.data(), groups.size() * sizeof(GroupDev),
+  // asynchronous copies from pinned staging: the step's closing
+  // synchronisation orders them before the staging is reused
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + g_off, st, need_bytes, hipMemcpyHostToDevice, ctx->stream));
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.diags + slot * sizeof(DiagDev), sd, sizeof(DiagDev),
                                   hipMemcpyHostToDevice, ctx->stream));
-  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + t_off, c.terms.data(), c.terms.size() * sizeof(TermDev),
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.tasks + slot * sizeof(TaskDev), sT, sizeof(TaskDev),
                                   hipMemcpyHostToDevice, ctx->stream));
-  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + c_off, c.coefs.data(), c.coefs.size() * sizeof(CoefDev),
-                                  hipMemcpyHostToDevice, ctx->stream));
-  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.diags + slot * sizeof(DiagDev), &dd, sizeof(DiagDev),
-                                  hipMemcpyHostToDevice, ctx->stream));
-  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.tasks + slot * sizeof(TaskDev), &s->h_tasks[slot],
-                                  sizeof(TaskDev), hipMemcpyHostToDevice, ctx->stream));
   KArgs a = server_kargs(s);
   MBPT_HIPCHK(ctx, launch_init(a, slot, 1, ctx->stream));
-  // the copies above read host memory that is reused: wait for them
-  MBPT_HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  s->stage_used += stage_need;
   s->flops[slot] = c.fm;
   q.state = 1;
   q.slot = slot;
@@ -330,7 +359,18 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
   s->h_tasks.assign(max_slots, TaskDev{});
   s->flops.assign(max_slots, FlopModel{});
   s->t0 = std::chrono::steady_clock::now();
-  if (hipMemcpyAsync(s->ws + L.tasks, s->h_tasks.data(), max_slots * sizeof(TaskDev),
+  if (hipHostMalloc(reinterpret_cast<void **>(&s->stage), kStageBytes, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&s->pin_tasks), max_slots * sizeof(TaskDev),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&s->pin_olist), max_slots * sizeof(int2),
+                    hipHostMallocDefault) != hipSuccess) {
+    set_err(ctx, "server_create: pinned host allocation failed");
+    delete s;
+    return MBPT_EHIP;
+  }
+  std::memset(s->pin_tasks, 0, max_slots * sizeof(TaskDev));
+  if (hipMemcpyAsync(s->ws + L.tasks, s->pin_tasks, max_slots * sizeof(TaskDev),
                      hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess) {
     set_err(ctx, "server_create: HIP copy failed");
@@ -389,40 +429,46 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
     if (rc < 0) return rc;
     s->queue.pop_front();
   }
-  // compact work numbering over the slots in index order (free slots own none)
-  int total = 0, max_nd = 0, nactive = 0;
+  // work numbering grouped by order over the resident slots (free slots own
+  // none); one sample launch per order present
+  std::vector<int> active;
   for (int i = 0; i < s->max_slots; ++i) {
     TaskDev &T = s->h_tasks[i];
-    T.item_begin = total;
     if (s->slot_req[i] >= 0) {
-      total += T.nitems;
-      max_nd = std::max(max_nd, T.nd);
-      ++nactive;
+      active.push_back(i);
     } else {
       T.nitems = 0;
       T.active = 0;
     }
   }
+  const int nactive = static_cast<int>(active.size());
   if (nactive > 0) {
+    order_items(s->h_tasks, active, s->olist, s->ranges);
+    std::memcpy(s->pin_tasks, s->h_tasks.data(), s->max_slots * sizeof(TaskDev));
+    std::memcpy(s->pin_olist, s->olist.data(), s->olist.size() * sizeof(int2));
     const size_t width = offsetof(TaskDev, iter);
-    MBPT_HIPCHK(ctx, hipMemcpy2DAsync(s->ws + s->L.tasks, sizeof(TaskDev), s->h_tasks.data(),
+    MBPT_HIPCHK(ctx, hipMemcpy2DAsync(s->ws + s->L.tasks, sizeof(TaskDev), s->pin_tasks,
                                       sizeof(TaskDev), width, s->max_slots, hipMemcpyHostToDevice,
                                       ctx->stream));
+    MBPT_HIPCHK(ctx, hipMemcpyAsync(s->ws + s->L.olist, s->pin_olist,
+                                    s->olist.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                    ctx->stream));
     KArgs a = server_kargs(s);
-    a.total_items = total;
+    a.total_items = s->ranges.back().item_end;
     const int prec = ctx->desc.precision;
-    const size_t lds = sample_lds_bytes(max_nd, ctx->desc.n_bins, kBlock);
-    int per_cu = batched_occupancy(4, prec, max_nd, kBlock, lds);
-    const int grid = std::max(1, std::min(total, std::max(1, per_cu) * std::max(1, ctx->num_cus)));
     size_t slot = 0;
     timed_begin(ctx, slot);
-    MBPT_HIPCHK(ctx, launch_sample_batched(a, 4, prec, max_nd, grid, kBlock, ctx->stream));
+    for (const auto &r : s->ranges)
+      MBPT_HIPCHK(ctx, launch_sample_order(a, r.order, 4, prec, r.k0, r.k1, r.nitems, kBlock,
+                                           ctx->stream));
     timed_end(ctx, slot);
-    MBPT_HIPCHK(ctx, launch_finish(a, 0, s->max_slots, max_nd, ctx->desc.alpha, ctx->stream));
-    std::vector<TaskDev> st(s->max_slots);
-    MBPT_HIPCHK(ctx, hipMemcpyAsync(st.data(), s->ws + s->L.tasks, s->max_slots * sizeof(TaskDev),
-                                    hipMemcpyDeviceToHost, ctx->stream));
+    MBPT_HIPCHK(ctx, launch_finish(a, 0, s->max_slots, kMaxDim, ctx->desc.alpha, ctx->stream));
+    const TaskDev *st = s->pin_tasks;
+    MBPT_HIPCHK(ctx, hipMemcpyAsync(s->pin_tasks, s->ws + s->L.tasks,
+                                    s->max_slots * sizeof(TaskDev), hipMemcpyDeviceToHost,
+                                    ctx->stream));
     MBPT_HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    s->stage_used = 0;
     resolve_timing(ctx);
     const double t = now_s(s->t0);
     uint64_t evals = 0;
