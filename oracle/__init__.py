@@ -59,6 +59,8 @@ class Problem(ctypes.Structure):
         ("kcut_extra", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("task_key", ctypes.c_uint32),
         ("label_method", ctypes.c_int),
+        ("spectrum", ctypes.c_int), ("hf_n", ctypes.c_int), ("hf_kmax", ctypes.c_double),
+        ("hf_y", ctypes.POINTER(ctypes.c_double)), ("hf_m", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -95,6 +97,13 @@ def lib():
                                     ctypes.c_uint32, ctypes.c_int, dp, dp,
                                     ctypes.POINTER(Result)]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
+        L.orc_hf_sigma.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_int]
+        L.orc_hf_sigma.restype = ctypes.c_double
+        L.orc_spline_flat_ends.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        L.orc_hf_spline_eval.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_double]
+        L.orc_hf_spline_eval.restype = ctypes.c_double
         L.orc_map_samples.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_uint32,
                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                       ctypes.c_uint64, dp, dp, ctypes.POINTER(ctypes.c_int)]
@@ -116,16 +125,57 @@ DEFAULTS = dict(C0=-1.0, Cy=-2.0, mpi=0.7, Lambda=2.0, reg_exp=4.0, hbar2_m=41.4
                 hbarc=197.3269804, n_bins=50, alpha=1.5, kcut_extra=3.0)
 
 
+# HF spectrum tables: cubic spline (zero end slopes) of Sigma_tau(k) on HF_INTERVALS
+# equal steps of [0, kF,max + HF_RANGE_LAMBDA * Lambda] (beyond it the
+# regulator makes Sigma vanish to double precision), node values by
+# HF_GAUSS-point Gauss-Legendre quadrature in |k'| and the angle.
+HF_INTERVALS = 512
+HF_RANGE_LAMBDA = 6.0
+HF_GAUSS = 64
+
+
 def problem(order, diagram_id=0, density=0.08, proton_fraction=0.0, q=2, seed=1,
-            task_key=0, label_method=0, **kw):
+            task_key=0, label_method=0, spectrum=0, **kw):
     p = dict(DEFAULTS)
     p.update(kw)
-    return Problem(order=order, diagram_id=diagram_id, q=q, density=density,
-                   proton_fraction=proton_fraction, C0=p["C0"], Cy=p["Cy"], mpi=p["mpi"],
-                   Lambda=p["Lambda"], reg_exp=p["reg_exp"], hbar2_m=p["hbar2_m"],
-                   hbarc=p["hbarc"], n_bins=p["n_bins"], alpha=p["alpha"],
-                   kcut_extra=p["kcut_extra"], seed=seed, task_key=task_key,
-                   label_method=label_method)
+    pb = Problem(order=order, diagram_id=diagram_id, q=q, density=density,
+                 proton_fraction=proton_fraction, C0=p["C0"], Cy=p["Cy"], mpi=p["mpi"],
+                 Lambda=p["Lambda"], reg_exp=p["reg_exp"], hbar2_m=p["hbar2_m"],
+                 hbarc=p["hbarc"], n_bins=p["n_bins"], alpha=p["alpha"],
+                 kcut_extra=p["kcut_extra"], seed=seed, task_key=task_key,
+                 label_method=label_method, spectrum=spectrum)
+    if spectrum:
+        if q == 4 and label_method != 0:
+            raise ValueError("HF spectrum in nuclear matter needs the brute-force label sum")
+        hf_tables(pb)
+    return pb
+
+
+def hf_sigma(pb, tau, k, ng=HF_GAUSS):
+    """Sigma_tau(k) [MeV] by direct quadrature (no table)."""
+    return float(lib().orc_hf_sigma(ctypes.byref(pb), tau, k, ng))
+
+
+def hf_tables(pb, n=HF_INTERVALS, ng=HF_GAUSS):
+    """Fill pb's HF spline tables (node values and second derivatives)."""
+    kf = fermi_momenta(pb)
+    pb.hf_n = n
+    pb.hf_kmax = max(kf[0], kf[1]) + HF_RANGE_LAMBDA * pb.Lambda
+    h = pb.hf_kmax / n
+    y = np.zeros((2, n + 1))
+    m = np.zeros((2, n + 1))
+    for t in range(2):
+        for i in range(n + 1):
+            y[t, i] = hf_sigma(pb, t, i * h, ng)
+        lib().orc_spline_flat_ends(n, h, _dp(y[t]), _dp(m[t]))
+    pb._hf_keep = (y, m)
+    pb.hf_y = _dp(y)
+    pb.hf_m = _dp(m)
+    return y, m
+
+
+def hf_spline(pb, tau, k):
+    return float(lib().orc_hf_spline_eval(ctypes.byref(pb), tau, k))
 
 
 def philox(ctr, key):

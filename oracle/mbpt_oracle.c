@@ -391,6 +391,11 @@ typedef struct {
   double kcut_extra;      /* particle-loop radius = kF,max + kcut_extra * Lambda */
   uint32_t seed, task_key;
   int label_method;       /* 0: brute force over q^{2n}; 1: closed-loop rule */
+  int spectrum;           /* 0: free eps = hbar^2 k^2 / 2m; 1: Hartree-Fock (eq:spe) */
+  int hf_n;               /* HF: spline intervals on [0, hf_kmax] */
+  double hf_kmax;         /* HF: table range; Sigma = its last node value beyond */
+  const double *hf_y;     /* HF: Sigma_tau(k_i), tau = n then p, 2 x (hf_n + 1) */
+  const double *hf_m;     /* HF: natural-spline second derivatives, same layout */
 } orc_problem;
 
 typedef struct {
@@ -423,6 +428,112 @@ static double pot(const orc_problem *pb, const double p[3], const double pp[3]) 
   return pb->hbarc * (pb->C0 + pb->Cy / (q2 + pb->mpi * pb->mpi)) * fp * fpp;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Hartree-Fock single-particle energies (eq:spe)                            */
+/* ------------------------------------------------------------------------ */
+
+/* Gauss-Legendre rule on [-1, 1]: nodes are the roots of P_n (Newton from
+ * the usual cosine guesses), weights 2 / ((1 - x^2) P_n'(x)^2). */
+void orc_gauss_legendre(int n, double *x, double *w) {
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 200; ++it) {
+      double p1 = 1.0, p0 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        const double pm = p0;
+        p0 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p0 - (j - 1.0) * pm) / j;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-17) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+/* HF self-energy Sigma_tau(k) [MeV] of a nucleon of isospin tau (0 n, 1 p):
+ * the sum over occupied partners j of <ij|Vbar|ij>, Vbar = V (1 - P12).  With
+ * p = (k - k') / 2 the direct element is V(p, p) for every partner spin (2
+ * spins) and the exchange element V(p, -p) needs equal spin and isospin:
+ *   Sigma_tau(k) = sum_tau' \int_{k' < kF_tau'} d^3k' / (2 pi)^3
+ *                  [2 V(p, p) - delta_{tau tau'} V(p, -p)].
+ * Neutron matter (q = 2) has only tau' = n.  ng-point Gauss-Legendre in |k'|
+ * and in the cosine of the angle between k and k'. */
+double orc_hf_sigma(const orc_problem *pb, int tau, double k, int ng) {
+  double xg[256], wg[256];
+  if (ng > 256) ng = 256;
+  orc_gauss_legendre(ng, xg, wg);
+  const double x = pb->q == 4 ? pb->proton_fraction : 0.0;
+  const double kF[2] = {cbrt(3.0 * M_PI * M_PI * (1.0 - x) * pb->density),
+                        cbrt(3.0 * M_PI * M_PI * x * pb->density)};
+  double total = 0.0;
+  for (int tp = 0; tp < (pb->q == 4 ? 2 : 1); ++tp) {
+    if (kF[tp] <= 0.0) continue;
+    double sum = 0.0;
+    for (int a = 0; a < ng; ++a) {
+      const double kp = 0.5 * kF[tp] * (xg[a] + 1.0), wk = 0.5 * kF[tp] * wg[a];
+      for (int b = 0; b < ng; ++b) {
+        const double mu = xg[b], sn = sqrt(fmax(0.0, 1.0 - mu * mu));
+        double p[3] = {-0.5 * kp * sn, 0.0, 0.5 * (k - kp * mu)};
+        double mp[3] = {-p[0], -p[1], -p[2]};
+        double f = 2.0 * pot(pb, p, p);
+        if (tp == tau) f -= pot(pb, p, mp);
+        sum += wk * wg[b] * kp * kp * f;
+      }
+    }
+    total += sum * 2.0 * M_PI / pow(2.0 * M_PI, 3.0);
+  }
+  return total;
+}
+
+/* Cubic spline through y_0..y_n at spacing h with zero end slopes (Sigma is
+ * even in k, and flat where the regulator has switched it off): second
+ * derivatives m from
+ *   2 m_0 + m_1 = 6 (y_1 - y_0) / h^2,
+ *   m_{i-1} + 4 m_i + m_{i+1} = 6 (y_{i+1} - 2 y_i + y_{i-1}) / h^2,
+ *   m_{n-1} + 2 m_n = -6 (y_n - y_{n-1}) / h^2,
+ * solved by the Thomas algorithm. */
+void orc_spline_flat_ends(int n, double h, const double *y, double *m) {
+  static double a[4097], b[4097], c[4097], r[4097];
+  if (n < 2 || n > 4096) return;
+  for (int i = 0; i <= n; ++i) {
+    a[i] = 1.0;
+    b[i] = 4.0;
+    c[i] = 1.0;
+  }
+  b[0] = b[n] = 2.0;
+  r[0] = 6.0 * (y[1] - y[0]) / (h * h);
+  for (int i = 1; i < n; ++i) r[i] = 6.0 * (y[i + 1] - 2.0 * y[i] + y[i - 1]) / (h * h);
+  r[n] = -6.0 * (y[n] - y[n - 1]) / (h * h);
+  /* forward elimination */
+  for (int i = 1; i <= n; ++i) {
+    const double f = a[i] / b[i - 1];
+    b[i] -= f * c[i - 1];
+    r[i] -= f * r[i - 1];
+  }
+  m[n] = r[n] / b[n];
+  for (int i = n - 1; i >= 0; --i) m[i] = (r[i] - c[i] * m[i + 1]) / b[i];
+}
+
+/* The spline at k (constant beyond the last node). */
+static double spline_eval(int n, double h, const double *y, const double *m, double k) {
+  if (k >= n * h) return y[n];
+  int i = (int)(k / h);
+  if (i > n - 1) i = n - 1;
+  const double t = (k - i * h) / h, u = 1.0 - t;
+  return u * y[i] + t * y[i + 1] + h * h / 6.0 * ((u * u * u - u) * m[i] + (t * t * t - t) * m[i + 1]);
+}
+
+double orc_hf_spline_eval(const orc_problem *pb, int tau, double k) {
+  const double h = pb->hf_kmax / pb->hf_n;
+  const int off = tau * (pb->hf_n + 1);
+  return spline_eval(pb->hf_n, h, pb->hf_y + off, pb->hf_m + off, k);
+}
+
 /* Integrand in loop-momentum space, as a contribution to E/N [MeV]:
  *   f = prefactor * (2pi)^{-3L} * [sum over labels of Pauli * prod <..|Vbar|..>]
  *       / prod_c D_c / n.
@@ -445,6 +556,7 @@ static void eval_point(const orc_problem *pb, const orc_diagram *d,
                        orc_point *out) {
   const int n = d->order, nl = d->nlines, L = d->nloops;
   double k[ORC_MAXLINES][3], k2[ORC_MAXLINES], eps[ORC_MAXLINES];
+  double epst[ORC_MAXLINES][2];  /* per isospin (HF spectrum) */
   for (int l = 0; l < nl; ++l) {
     for (int i = 0; i < 3; ++i) {
       double s = 0;
@@ -453,6 +565,19 @@ static void eval_point(const orc_problem *pb, const orc_diagram *d,
     }
     k2[l] = k[l][0] * k[l][0] + k[l][1] * k[l][1] + k[l][2] * k[l][2];
     eps[l] = 0.5 * pb->hbar2_m * k2[l];
+    for (int t = 0; t < 2; ++t)
+      epst[l][t] = eps[l] + (pb->spectrum ? orc_hf_spline_eval(pb, t, sqrt(k2[l])) : 0.0);
+    eps[l] = epst[l][0];
+  }
+  /* HF energies of nuclear matter depend on each line's isospin: the
+   * denominators are then taken per label assignment (brute force only) */
+  const int iso_den = pb->spectrum && pb->q == 4;
+  if (iso_den && pb->label_method != 0) {
+    out->f = NAN;
+    out->wcond = NAN;
+    out->labelsum = out->labelabs = NAN;
+    out->pauli_any = 1;
+    return;
   }
   /* occupation factors per line and isospin: n_k for holes, 1 - n_k for particles */
   double P[ORC_MAXLINES][2];
@@ -501,6 +626,22 @@ static void eval_point(const orc_problem *pb, const orc_diagram *d,
         prodabs *= dir * fabs(Vd[v]) + exc * fabs(Ve[v]);
       }
       if (prodabs != 0.0) any = 1;
+      if (iso_den && prodabs != 0.0) {
+        double dp = 1.0, dc = 0.0;
+        for (int c = 0; c < d->ncuts; ++c) {
+          double D = 0.0, Dabs = 0.0;
+          for (int l = 0; l < nl; ++l) {
+            const double e = epst[l][tau_of(q, lab[l])];
+            D += d->cut[c][l] * e;
+            Dabs += d->cut[c][l] ? fabs(e) : 0.0;
+          }
+          dp *= D;
+          dc += Dabs / fabs(D);
+        }
+        ls += pauli * prod / dp;
+        lsabs += pauli * prodabs / fabs(dp) * (1.0 + dc + regcond);
+        continue;
+      }
       ls += pauli * prod;
       lsabs += pauli * prodabs;
     }
@@ -551,7 +692,7 @@ static void eval_point(const orc_problem *pb, const orc_diagram *d,
     double D = 0.0, Dabs = 0.0;
     for (int l = 0; l < nl; ++l) {
       D += d->cut[c][l] * eps[l];
-      Dabs += d->cut[c][l] ? eps[l] : 0.0;
+      Dabs += d->cut[c][l] ? fabs(eps[l]) : 0.0;
     }
     dprod *= D;
     if (any) dcond += Dabs / fabs(D);
@@ -563,6 +704,13 @@ static void eval_point(const orc_problem *pb, const orc_diagram *d,
   if (!any) {
     out->f = 0.0;
     out->wcond = 0.0;
+    return;
+  }
+  if (iso_den) {
+    /* denominators already inside ls; lsabs carries the condition terms */
+    const double sc = d->prefactor * measure / pb->density;
+    out->f = sc * ls;
+    out->wcond = fabs(sc) * lsabs;
     return;
   }
   double scale = d->prefactor * measure / pb->density / dprod;
