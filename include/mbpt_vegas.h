@@ -62,6 +62,18 @@ enum { MBPT_NEUTRON = 0, MBPT_NUCLEAR = 1 };
  * sequence captured once into a HIP graph and replayed (needs a non-default
  * stream: EINVAL on the null stream). */
 enum { MBPT_LAUNCH_PER_TASK = 0, MBPT_LAUNCH_BATCHED = 1, MBPT_LAUNCH_GRAPH = 2 };
+/* Single-particle energies in the energy denominators (eq:Dijkabc).  FREE:
+ * eps = hbar^2 k^2 / 2m.  HF: the Hartree-Fock spectrum of eq:spe,
+ * eps_tau(k) = hbar^2 k^2 / 2m + Sigma_tau(k) with Sigma_tau(k) the sum over
+ * occupied partners of <k tau, j|V(1 - P12)|k tau, j>; isospin dependent in
+ * asymmetric matter (the paper's explicit treatment, no isospin averaging).
+ * Sigma is tabulated per task once per medium on 512 equal steps of
+ * [0, kF,max + 6 Lambda] by 64 x 64-point Gauss-Legendre quadrature and
+ * interpolated by a cubic spline with zero end slopes (the paper's fine grid
+ * plus cubic spline, Sec. "Automated evaluation").  The FP32 integrand
+ * implements FREE only: with HF every sample takes the fp64 path.  The
+ * continuous-batching server supports FREE only. */
+enum { MBPT_SPECTRUM_FREE = 0, MBPT_SPECTRUM_HF = 1 };
 
 /* ---- value types -------------------------------------------------------- */
 /* Two-body interaction V(p,p') = hbarc [C0 + Cy/(|p-p'|^2 + mpi^2)]
@@ -98,6 +110,7 @@ typedef struct mbpt_context_desc {
   double fp32_band_k;
   double fp32_band_d;
   int label_mode;
+  int spectrum;
 } mbpt_context_desc;
 
 /* One integration task: diagram `diagram_id` of order `order` (1..5; ids
@@ -132,7 +145,7 @@ typedef struct mbpt_server mbpt_server;
 /* ---- context -------------------------------------------------------------- */
 /* Create a context on `device`.  desc may be NULL for defaults (device 0,
  * default stream, FP64, seed 1, 50 bins, alpha 1.5, kcut_extra 3.0, bands
- * 1e-4 / 1e-2, label_mode 0).  The default interaction is the synthetic contact + Yukawa one
+ * 1e-4 / 1e-2, label_mode 0, spectrum FREE).  The default interaction is the synthetic contact + Yukawa one
  * (C0 = -1 fm^2, Cy = -2, mpi = 0.7, Lambda = 2, exponent 4, hbar^2/m = 41.47,
  * hbarc = 197.3269804).  EINVAL on bad fields, EHIP if the device is absent. */
 int mbpt_context_create(const mbpt_context_desc *desc, mbpt_context **out);
@@ -144,6 +157,9 @@ const char *mbpt_last_error(const mbpt_context *ctx);
 int mbpt_set_interaction(mbpt_context *ctx, const mbpt_interaction *v);
 /* Switch integrand precision (MBPT_FP64 / MBPT_FP32) for later calls. */
 int mbpt_set_precision(mbpt_context *ctx, int precision);
+/* Switch the single-particle spectrum (MBPT_SPECTRUM_FREE / _HF) for later
+ * integrate calls of every task set of the context. */
+int mbpt_set_spectrum(mbpt_context *ctx, int spectrum);
 
 /* ---- diagram generator (host only, no context needed) --------------------- */
 /* Number of two-body energy diagrams of an order (1, 1, 3, 39, 840 for orders
@@ -223,6 +239,12 @@ int mbpt_iteration_log(mbpt_task_set *set, int task, double *I, double *var, int
  * For per-sample parity checks. */
 int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, uint64_t first,
                       uint64_t count, double *w_host);
+/* HF self-energy Sigma_tau(k_i) [MeV] of a task at the spline nodes
+ * k_i = i * (*h), i = 0..512 (eq:spe; tau 0 neutron, 1 proton, proton only in
+ * NUCLEAR sets), written to sigma_host (513 doubles, caller-owned host
+ * memory); computes the tables first if needed.  MBPT_ESTATE unless the
+ * context's spectrum is HF and a workspace is bound.  Blocks on the stream. */
+int mbpt_hf_nodes(mbpt_task_set *set, int task, int tau, double *sigma_host, double *h);
 /* Grid of a task (ndim x (n_bins+1) edges, host memory) for checkpointing,
  * and its restore.  ndim = 3 (order + 1). */
 int mbpt_get_grid(mbpt_task_set *set, int task, double *edges_host);

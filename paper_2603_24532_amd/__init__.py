@@ -18,11 +18,13 @@ MBPT_OK, MBPT_EINVAL, MBPT_ENOMEM, MBPT_EHIP, MBPT_ENUMERIC, MBPT_EBUSY, MBPT_ES
 MBPT_FP64, MBPT_FP32 = 0, 1
 MBPT_NEUTRON, MBPT_NUCLEAR = 0, 1
 MBPT_LAUNCH_PER_TASK, MBPT_LAUNCH_BATCHED, MBPT_LAUNCH_GRAPH = 0, 1, 2
+MBPT_SPECTRUM_FREE, MBPT_SPECTRUM_HF = 0, 1
+HF_ENTRIES = 513  # spline nodes of an HF table
 
 EXPORTED = [
     "mbpt_context_create", "mbpt_context_destroy", "mbpt_last_error", "mbpt_set_interaction",
     "mbpt_set_precision", "mbpt_num_diagrams", "mbpt_diagram_matrix", "mbpt_diagram_label_stats",
-    "mbpt_diagram_label_poly",
+    "mbpt_diagram_label_poly", "mbpt_set_spectrum", "mbpt_hf_nodes",
     "mbpt_create_task_set", "mbpt_create_diagram_set", "mbpt_task_set_destroy", "mbpt_task_count",
     "mbpt_set_density", "mbpt_set_asymmetry", "mbpt_set_launch_mode", "mbpt_set_blocking",
     "mbpt_workspace_query", "mbpt_bind_workspace", "mbpt_reset", "mbpt_integrate",
@@ -43,7 +45,8 @@ class mbpt_context_desc(ctypes.Structure):
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint32),
                 ("n_bins", ctypes.c_int), ("alpha", ctypes.c_double),
                 ("kcut_extra", ctypes.c_double), ("fp32_band_k", ctypes.c_double),
-                ("fp32_band_d", ctypes.c_double), ("label_mode", ctypes.c_int)]
+                ("fp32_band_d", ctypes.c_double), ("label_mode", ctypes.c_int),
+                ("spectrum", ctypes.c_int)]
 
 
 class mbpt_task_desc(ctypes.Structure):
@@ -93,6 +96,9 @@ def lib():
         "mbpt_last_error": [_P],
         "mbpt_set_interaction": [_P, ctypes.POINTER(mbpt_interaction)],
         "mbpt_set_precision": [_P, ctypes.c_int],
+        "mbpt_set_spectrum": [_P, ctypes.c_int],
+        "mbpt_hf_nodes": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_double)],
         "mbpt_num_diagrams": [ctypes.c_int, _IP],
         "mbpt_diagram_matrix": [ctypes.c_int, ctypes.c_int, _IP, _DP],
         "mbpt_diagram_label_stats": [ctypes.c_int, ctypes.c_int, ctypes.c_int, _IP, _IP, _IP],
@@ -164,9 +170,9 @@ _srv_ctx = {}
 
 def mbpt_context_create(device=0, stream=None, precision=MBPT_FP64, seed=1, n_bins=50,
                         alpha=1.5, kcut_extra=3.0, fp32_band_k=1e-4, fp32_band_d=1e-2,
-                        label_mode=0):
+                        label_mode=0, spectrum=0):
     d = mbpt_context_desc(device, stream, precision, seed, n_bins, alpha, kcut_extra,
-                          fp32_band_k, fp32_band_d, label_mode)
+                          fp32_band_k, fp32_band_d, label_mode, spectrum)
     h = _P()
     _check(lib().mbpt_context_create(ctypes.byref(d), ctypes.byref(h)))
     return h.value
@@ -188,6 +194,20 @@ def mbpt_set_interaction(ctx, C0=-1.0, Cy=-2.0, mpi=0.7, Lambda=2.0, reg_exp=4, 
 
 def mbpt_set_precision(ctx, precision):
     _check(lib().mbpt_set_precision(ctx, precision), ctx)
+
+
+def mbpt_set_spectrum(ctx, spectrum):
+    _check(lib().mbpt_set_spectrum(ctx, spectrum), ctx)
+
+
+def mbpt_hf_nodes(set_, task, tau):
+    """(Sigma_tau at the HF spline nodes [MeV] as a numpy array, node step h)."""
+    import numpy as np
+    out = np.zeros(HF_ENTRIES)
+    h = ctypes.c_double()
+    _check(lib().mbpt_hf_nodes(set_, task, tau, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(h)), _set_ctx.get(set_))
+    return out, h.value
 
 
 def mbpt_num_diagrams(order):

@@ -63,15 +63,24 @@ struct Phys {
   int half_exp;     // reg_exp / 2
   int nb;           // bins per dimension
   uint32_t seed;
-  int pad;
+  int spectrum;     // 0 free, 1 Hartree-Fock (eq:spe)
 };
+
+// Hartree-Fock spectrum: cubic spline of Sigma_tau(k) on kHfIntervals equal
+// steps of [0, kF,max + kHfRangeLambda * Lambda]; entry i holds the
+// coefficients (a, b, c, d) of a + b t + c t^2 + d t^3 on [k_i, k_i + h],
+// entry kHfIntervals holds (Sigma at the last node, 0, 0, 0).
+constexpr int kHfIntervals = 512;
+constexpr int kHfEntries = kHfIntervals + 1;
+constexpr double kHfRangeLambda = 6.0;
+constexpr int kHfGauss = 64;  // Gauss-Legendre points per dimension
 
 // One task: parameters (host-written) and running state (device-written).
 struct alignas(16) TaskDev {
   int diag, nd, grid_off, hist_off;
   int item_begin, nitems, res_off, res_cap;  // work items [item_begin, +nitems)
   int store_begin;                           // partials/counters slot of the first item
-  int pad0;
+  int hf_off;                                // first HF spline entry of this task
   uint32_t key;
   int order;
   uint64_t nsamples;
@@ -79,6 +88,7 @@ struct alignas(16) TaskDev {
   double Rh, Rp;        // loop radii for hole / particle loop lines
   double inv_density;
   double band_k, band_d;
+  double hf_h, hf_inv_h;  // HF spline step and its inverse
   int active;
   int pad;
   // state (written by the device)
@@ -108,6 +118,7 @@ struct KArgs {
   double *reslog;         // (I, var) pairs
   const CoefDev *gcoef;   // factorised label-sum coefficients
   const int2 *olist;      // (first item, task), grouped by order, ascending items
+  double *hf;             // HF spline entries, 4 doubles each
   int ntasks;
   int total_items;
   int spt;                // samples per thread per item

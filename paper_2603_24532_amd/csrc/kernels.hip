@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_types.hpp"
+#include "turn_table.hpp"
 #include "kernels.hpp"
 
 namespace mbpt {
@@ -49,22 +50,111 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 // Coefficient c in {0, +-1, +-2} of loop j in the uniform bitmask m (bits
 // 0-7: +1, 8-15: -1, 16-23: +2, 24-31: -2) as a double, built from its bit
 // pattern with scalar instructions only.
+// sin and cos of 2 pi k / MBPT_TURN_STEPS (copied into LDS by every sample
+// kernel).
+struct alignas(16) SinCos {
+  double s, c;
+};
+constexpr int kTurnEntries = MBPT_TURN_STEPS + 1;
+__constant__ SinCos kTurnDev[kTurnEntries] = {MBPT_TURN_TABLE_INIT};
+
+__device__ __forceinline__ void load_turn_table(SinCos *dst) {
+  for (int i = threadIdx.x; i < kTurnEntries; i += blockDim.x) dst[i] = kTurnDev[i];
+}
+
+// What the integrand reads from LDS: the turn table, the HF spline entries of
+// the task (ntab isospin tables of kHfEntries x 4 doubles, absent with the
+// free spectrum) and the grid (e, width) pairs.  Block layout: turn table, HF
+// tables, grid pairs, then the kernel's own scratch.
+struct SampleLds {
+  const SinCos *turn;
+  const double *hf;
+  const double2 *g;
+};
+
+__host__ __device__ constexpr size_t hf_lds_doubles(int ntab) {
+  return static_cast<size_t>(ntab) * kHfEntries * 4;
+}
+
+// Carves the block's dynamic LDS; returns the first free double after the
+// grid pairs and fills the pointers.  Copies the turn and HF tables (the grid
+// pairs are the caller's).
+__device__ __forceinline__ double *carve_lds(const KArgs &a, const TaskDev *__restrict__ T,
+                                             int ntab, int nd, double *smem, SampleLds &L,
+                                             double2 *&g) {
+  SinCos *turn = reinterpret_cast<SinCos *>(smem);
+  double *hf = reinterpret_cast<double *>(turn + kTurnEntries);
+  g = reinterpret_cast<double2 *>(hf + hf_lds_doubles(ntab));
+  load_turn_table(turn);
+  if (ntab) {
+    const double *src = a.hf + 4 * static_cast<size_t>(T->hf_off);
+    const int n = static_cast<int>(hf_lds_doubles(ntab));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) hf[i] = src[i];
+  }
+  L.turn = turn;
+  L.hf = ntab ? hf : nullptr;
+  L.g = g;
+  return reinterpret_cast<double *>(g + nd * a.phys.nb);
+}
+
+// HF self-energy of table tau at |k| = kk from the LDS spline (constant
+// beyond the last node).
+__device__ __forceinline__ double hf_sigma(const double *__restrict__ hf, int tau, double kk,
+                                           double inv_h) {
+  const double u = kk * inv_h;
+  int i = static_cast<int>(u);
+  double t = u - static_cast<double>(i);
+  if (i >= kHfIntervals) {
+    i = kHfIntervals;
+    t = 0.0;
+  }
+  const double *e = hf + 4 * (tau * kHfEntries + i);
+  return fma(t, fma(t, fma(t, e[3], e[2]), e[1]), e[0]);
+}
+
+// sin(2 pi x) and cos(2 pi x) for x in [0, 1]: the nearest table angle
+// 2 pi k / 64 rotated by the residual d, |d| <= pi / 64, whose sine and
+// cosine - 1 come from their Taylor series (first omitted terms below 1e-17
+// relative).
+__device__ __forceinline__ void sincos_turn(const SinCos *__restrict__ tab, double x, double &s,
+                                            double &c) {
+  const double u = x * static_cast<double>(MBPT_TURN_STEPS);  // exact
+  const double kf = rint(u);
+  const double d = (u - kf) * (2.0 * M_PI / MBPT_TURN_STEPS);  // u - kf exact
+  const double z = d * d;
+  double ps = fma(z, 1.0 / 362880.0, -1.0 / 5040.0);
+  ps = fma(z, ps, 1.0 / 120.0);
+  ps = fma(z, ps, -1.0 / 6.0);
+  const double sd = fma(d * z, ps, d);
+  double pc = fma(z, 1.0 / 40320.0, -1.0 / 720.0);
+  pc = fma(z, pc, 1.0 / 24.0);
+  pc = fma(z, pc, -0.5);
+  const double cm = z * pc;
+  const int k = min(max(static_cast<int>(kf), 0), MBPT_TURN_STEPS);
+  const SinCos t = tab[k];
+  s = fma(t.s, cm, fma(t.c, sd, t.s));
+  c = fma(t.c, cm, fma(-t.s, sd, t.c));
+}
+
+// HALF: the coefficients halved (vertex relative momenta are half the
+// difference of two line momenta)
+template <bool HALF = false>
 __device__ __forceinline__ double mask_coef(uint32_t m, int j) {
   uint32_t hi = 0u;
-  hi = (m & (1u << j)) ? 0x3FF00000u : hi;
-  hi = (m & (1u << (8 + j))) ? 0xBFF00000u : hi;
-  hi = (m & (1u << (16 + j))) ? 0x40000000u : hi;
-  hi = (m & (1u << (24 + j))) ? 0xC0000000u : hi;
+  hi = (m & (1u << j)) ? (HALF ? 0x3FE00000u : 0x3FF00000u) : hi;
+  hi = (m & (1u << (8 + j))) ? (HALF ? 0xBFE00000u : 0xBFF00000u) : hi;
+  hi = (m & (1u << (16 + j))) ? (HALF ? 0x3FF00000u : 0x40000000u) : hi;
+  hi = (m & (1u << (24 + j))) ? (HALF ? 0xBFF00000u : 0xC0000000u) : hi;
   return __hiloint2double(static_cast<int>(hi), 0);
 }
 
 // sum_j c_j v_j over loops j < L (coefficients from the uniform bitmask m)
-template <int L>
+template <int L, bool HALF = false>
 __device__ __forceinline__ void masked_sum(uint32_t m, const double (*k)[3], double *out) {
   double x = 0.0, y = 0.0, z = 0.0;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    const double c = mask_coef(m, j);
+    const double c = mask_coef<HALF>(m, j);
     x = fma(c, k[j][0], x);
     y = fma(c, k[j][1], y);
     z = fma(c, k[j][2], z);
@@ -72,6 +162,24 @@ __device__ __forceinline__ void masked_sum(uint32_t m, const double (*k)[3], dou
   out[0] = x;
   out[1] = y;
   out[2] = z;
+}
+
+// Square root of a finite a >= 0: hardware reciprocal square root refined by
+// Newton steps on g = sqrt(a) and h = 1 / (2 sqrt(a)).  No rescaling: a is
+// clamped to the smallest normal (so 0 gives 1.5e-154), and the squared
+// momenta and (1 - c)(1 + c) that reach here are far from overflow.
+__device__ __forceinline__ double sqrt_normal(double a) {
+  a = fmax(a, 0x1p-1022);
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y;
+  double h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, a);
+  g = fma(d, h, g);
+  d = fma(-g, g, a);
+  return fma(d, h, g);
 }
 
 // Neumaier step: (s, c) += x
@@ -203,10 +311,36 @@ __device__ __forceinline__ void monomials(const F *Vd, const F *Ve, F *M) {
   }
 }
 
-template <int ORDER, int Q, typename F>
+// Product of the energy denominators of one isospin configuration when the
+// single-particle energies depend on isospin (HF spectrum in nuclear matter):
+// D_c = Dn_c + sum over the cut's proton lines of +-(eps_p - eps_n), with
+// Dn_c the denominator with every line a neutron.
+template <int ORDER>
+__device__ __forceinline__ double group_den(const DiagDev *__restrict__ D, uint32_t tau,
+                                            const double *Dn, const double *deps) {
+  constexpr int NL = 2 * ORDER;
+  double prod = 1.0;
+#pragma unroll
+  for (int c = 0; c < ORDER - 1; ++c) {
+    const uint32_t hm = D->cut_hole[c] & tau, pm = D->cut_part[c] & tau;
+    double Dc = Dn[c];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      uint32_t hi = (hm & (1u << l)) ? 0x3FF00000u : 0u;
+      hi = (pm & (1u << l)) ? 0xBFF00000u : hi;
+      Dc = fma(__hiloint2double(static_cast<int>(hi), 0), deps[l], Dc);
+    }
+    prod *= Dc;
+  }
+  return prod;
+}
+
+// ISO: divide each configuration's sum by its own denominators (Dn, deps).
+template <int ORDER, int Q, typename F, bool ISO>
 __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict__ D,
                                        const F *Vd, const F *Ve, uint32_t okN, uint32_t okP,
-                                       uint32_t lmask, uint32_t &units) {
+                                       uint32_t lmask, uint32_t &units, const double *Dn,
+                                       const double *deps) {
   const GroupDev *__restrict__ G = a.groups + D->group_off;
   const int ngroups = D->ngroups;
   F acc = F(0);
@@ -231,6 +365,7 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
           for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(coef_val<F>(C[eb * NA + ea]), MA[ea], in);
           gs = fma_t<F>(in, MB[eb], gs);
         }
+        if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER>(D, tau, Dn, deps));
         acc += gs;
       }
     }
@@ -242,6 +377,7 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
       if (Q == 4) ok = (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
       if (ok) {
         units += cnt;
+        F gs = F(0);
         for (int t = first; t < first + cnt; ++t) {
           const TermDev tm = a.terms[t];
           F prod = F(1);
@@ -252,18 +388,21 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
             const F cb = code != 0u ? F(-1) : F(0);
             prod *= fma_t<F>(ca, Vd[v], cb * Ve[v]);
           }
-          acc = fma_t<F>(term_mult<F>(tm), prod, acc);
+          gs = fma_t<F>(term_mult<F>(tm), prod, gs);
         }
+        if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER>(D, tau, Dn, deps));
+        acc += gs;
       }
     }
   }
   return acc;
 }
 
-template <int ORDER, int Q>
+// HF: single-particle energies of the Hartree-Fock spectrum (tables in LDS).
+template <int ORDER, int Q, bool HF>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
-                                            const double2 *__restrict__ g, uint64_t s,
+                                            const SampleLds &Ls, uint64_t s,
                                             uint32_t iter, int *bins, uint32_t &npass,
                                             uint32_t &nterms) {
   constexpr int L = ORDER + 1;
@@ -271,7 +410,7 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   constexpr int NC = ORDER - 1;
   constexpr int ND = 3 * L;
   double x[ND];
-  double jac = vegas_map<ND>(a, T, g, s, iter, x, bins);
+  double jac = vegas_map<ND>(a, T, Ls.g, s, iter, x, bins);
 
   // loop momenta: radius R x0, cos theta = 2 x1 - 1, azimuth 2 pi x2
   double k[L][3];
@@ -280,17 +419,18 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     const double R = D->loop_part[j] ? T->Rp : T->Rh;
     const double rad = R * x[3 * j];
     const double ct = 2.0 * x[3 * j + 1] - 1.0;
-    const double st = sqrt(fmax(0.0, (1.0 - ct) * (1.0 + ct)));
+    const double st = sqrt_normal((1.0 - ct) * (1.0 + ct));
     double sp, cp;
-    sincospi(2.0 * x[3 * j + 2], &sp, &cp);
+    sincos_turn(Ls.turn, x[3 * j + 2], sp, cp);
     k[j][0] = rad * st * cp;
     k[j][1] = rad * st * sp;
     k[j][2] = rad * ct;
     jac *= R * rad * rad * (4.0 * M_PI);
   }
 
-  // line momenta -> occupation tests and energies
-  double eps[NL];
+  // line momenta -> occupation tests and energies (HF: plus the self-energy
+  // of a neutron, and for nuclear matter the proton-neutron difference)
+  double eps[NL], deps[NL];
   uint32_t inN = 0, inP = 0;
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
@@ -305,6 +445,13 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     }
     const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = a.phys.hb2m * k2;
+    deps[l] = 0.0;
+    if constexpr (HF) {
+      const double kk = sqrt_normal(k2);
+      const double sn = hf_sigma(Ls.hf, 0, kk, T->hf_inv_h);
+      if (Q == 4) deps[l] = hf_sigma(Ls.hf, 1, kk, T->hf_inv_h) - sn;
+      eps[l] += sn;
+    }
     inN |= (k2 < T->kF2[0]) ? (1u << l) : 0u;
     if (Q == 4) inP |= (k2 < T->kF2[1]) ? (1u << l) : 0u;
   }
@@ -315,8 +462,11 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
   ++npass;
 
-  // energy denominators
+  // energy denominators (with every line a neutron when they depend on
+  // isospin; the label sum then corrects them per configuration)
+  constexpr bool iso_den = Q == 4 && HF;
   double dprod = 1.0;
+  double Dn[NC > 0 ? NC : 1];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const uint32_t hm = D->cut_hole[c], pm = D->cut_part[c];
@@ -327,6 +477,7 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
       hi = (pm & (1u << l)) ? 0xBFF00000u : hi;
       Dc = fma(__hiloint2double(static_cast<int>(hi), 0), eps[l], Dc);
     }
+    Dn[c] = Dc;
     dprod *= Dc;
   }
 
@@ -340,14 +491,9 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   double yreg = 0.0;
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
-    double p[3], q[3];  // 2p and 2p'
-    masked_sum<L>(D->pmask_v[v], k, p);
-    masked_sum<L>(D->qmask_v[v], k, q);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      p[i] *= 0.5;
-      q[i] *= 0.5;
-    }
+    double p[3], q[3];  // relative momenta p and p'
+    masked_sum<L, true>(D->pmask_v[v], k, p);
+    masked_sum<L, true>(D->qmask_v[v], k, q);
     const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const double pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
@@ -361,7 +507,7 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     den[2 * v] = s2 - 2.0 * pq;
     den[2 * v + 1] = s2 + 2.0 * pq;
   }
-  den[NR - 1] = dprod;
+  den[NR - 1] = iso_den ? 1.0 : dprod;
   double pre[NR];
   pre[0] = den[0];
 #pragma unroll
@@ -382,26 +528,28 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   }
   const double regall = exp(-yreg * a.phys.invLn);
 
-  const double acc = label_sum<ORDER, Q, double>(a, D, Vd, Ve, okN, okP, lmask, nterms);
+  const double acc =
+      label_sum<ORDER, Q, double, iso_den>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn, deps);
   return jac * (D->pref * T->inv_density) * regall * acc * rinv[NR - 1];
 }
 
 // fp32 counterpart of masked_sum
+template <bool HALF = false>
 __device__ __forceinline__ float mask_coef_f(uint32_t m, int j) {
   uint32_t bits = 0u;
-  bits = (m & (1u << j)) ? 0x3F800000u : bits;
-  bits = (m & (1u << (8 + j))) ? 0xBF800000u : bits;
-  bits = (m & (1u << (16 + j))) ? 0x40000000u : bits;
-  bits = (m & (1u << (24 + j))) ? 0xC0000000u : bits;
+  bits = (m & (1u << j)) ? (HALF ? 0x3F000000u : 0x3F800000u) : bits;
+  bits = (m & (1u << (8 + j))) ? (HALF ? 0xBF000000u : 0xBF800000u) : bits;
+  bits = (m & (1u << (16 + j))) ? (HALF ? 0x3F800000u : 0x40000000u) : bits;
+  bits = (m & (1u << (24 + j))) ? (HALF ? 0xBF800000u : 0xC0000000u) : bits;
   return __uint_as_float(bits);
 }
 
-template <int L>
+template <int L, bool HALF = false>
 __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], float *out) {
   float x = 0.0f, y = 0.0f, z = 0.0f;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    const float c = mask_coef_f(m, j);
+    const float c = mask_coef_f<HALF>(m, j);
     x = fmaf(c, k[j][0], x);
     y = fmaf(c, k[j][1], y);
     z = fmaf(c, k[j][2], z);
@@ -422,7 +570,7 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 template <int ORDER, int Q>
 __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
-                                            const double2 *__restrict__ g, uint64_t s,
+                                            const SampleLds &Ls, uint64_t s,
                                             uint32_t iter, int *bins, uint32_t &npass,
                                             uint32_t &nterms, bool &fallback) {
   constexpr int L = ORDER + 1;
@@ -430,7 +578,7 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
   constexpr int NC = ORDER - 1;
   constexpr int ND = 3 * L;
   double x[ND];
-  double jac = vegas_map<ND>(a, T, g, s, iter, x, bins);
+  double jac = vegas_map<ND>(a, T, Ls.g, s, iter, x, bins);
 
   // loop momenta; the azimuth goes to the hardware sine/cosine in revolutions
   float k[L][3];
@@ -508,13 +656,8 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
     float p[3], q[3];
-    masked_sum_f<L>(D->pmask_v[v], k, p);
-    masked_sum_f<L>(D->qmask_v[v], k, q);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      p[i] *= 0.5f;
-      q[i] *= 0.5f;
-    }
+    masked_sum_f<L, true>(D->pmask_v[v], k, p);
+    masked_sum_f<L, true>(D->qmask_v[v], k, q);
     const float p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const float q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const float pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
@@ -557,27 +700,35 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
   }
   const float regall = __expf(-yexp);
 
-  const float acc = label_sum<ORDER, Q, float>(a, D, Vd, Ve, okN, okP, lmask, nterms);
+  const float acc =
+      label_sum<ORDER, Q, float, false>(a, D, Vd, Ve, okN, okP, lmask, nterms, nullptr, nullptr);
   ++npass;
   return jac * (D->pref * T->inv_density) * static_cast<double>(regall) *
          static_cast<double>(acc) * static_cast<double>(rinv[NR - 1]);
 }
 
-// One sample at precision P (0: fp64, 1: fp32 with fp64 fallback).
+// One sample in mode P: 0 fp64; 1 fp32 with the fp64 fallback; 2 fp64 with
+// the Hartree-Fock spectrum (the fp32 integrand has the free spectrum only).
 template <int ORDER, int Q, int P>
 __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__restrict__ T,
                                               const DiagDev *__restrict__ D,
-                                              const double2 *__restrict__ g, uint64_t s,
+                                              const SampleLds &Ls, uint64_t s,
                                               uint32_t iter, int *bins, uint32_t &npass,
                                               uint32_t &nterms, uint32_t &nfb) {
-  if (P == 0) return eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
+  if (P != 1) return eval_fp64<ORDER, Q, P == 2>(a, T, D, Ls, s, iter, bins, npass, nterms);
   bool fb = false;
-  double w = eval_fp32<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms, fb);
+  double w = eval_fp32<ORDER, Q>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
   if (fb) {
     ++nfb;
-    w = eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
+    w = eval_fp64<ORDER, Q, false>(a, T, D, Ls, s, iter, bins, npass, nterms);
   }
   return w;
+}
+
+// HF spline tables held in LDS in mode P
+template <int Q, int P>
+constexpr int lds_tables() {
+  return P == 2 ? (Q == 4 ? 2 : 1) : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -590,11 +741,13 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
   const DiagDev *__restrict__ D = a.diags + T->diag;
   const int nb = a.phys.nb;
   const int tid = threadIdx.x, bs = blockDim.x;
-  double2 *g = reinterpret_cast<double2 *>(smem);
-  double *h = smem + 2 * ND * nb;
-  double *red = h + ND * nb;
-
+  // LDS: turn table, HF tables, grid (e, width) pairs, histogram, reduction
+  // scratch
   __syncthreads();  // previous item done with LDS
+  SampleLds Ls;
+  double2 *g;
+  double *h = carve_lds(a, T, lds_tables<Q, P>(), ND, smem, Ls, g);
+  double *red = h + ND * nb;
   const double *ge = a.grids + T->grid_off;
   for (int i = tid; i < ND * nb; i += bs) {
     const int m = i / nb, b = i - m * nb;
@@ -620,12 +773,12 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       for (int m = 0; m < ND; ++m) atomicAdd(&h[m * nb + bins[m]], w2);
     }
   };
-  if (P == 0) {
+  if (P != 1) {
     for (int kk = 0; kk < a.spt; ++kk) {
       const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
       if (s < N) {
         int bins[ND];
-        const double w = eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
+        const double w = eval_fp64<ORDER, Q, P == 2>(a, T, D, Ls, s, iter, bins, npass, nterms);
         accumulate(w, bins);
       }
     }
@@ -640,7 +793,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       if (lane < take) {
         const uint64_t s = base + queue[lane];
         int bins[ND];
-        const double w = eval_fp64<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms);
+        const double w = eval_fp64<ORDER, Q, false>(a, T, D, Ls, s, iter, bins, npass, nterms);
         accumulate(w, bins);
       }
       __builtin_amdgcn_wave_barrier();
@@ -656,7 +809,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       bool fb = false;
       if (s < N) {
         int bins[ND];
-        const double w = eval_fp32<ORDER, Q>(a, T, D, g, s, iter, bins, npass, nterms, fb);
+        const double w = eval_fp32<ORDER, Q>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
         if (!fb) accumulate(w, bins);
       }
       const uint64_t mask = __ballot(fb);
@@ -947,7 +1100,9 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
   const TaskDev *T = a.tasks + t;
   const DiagDev *D = a.diags + T->diag;
   const int nb = a.phys.nb;
-  double2 *g = reinterpret_cast<double2 *>(smem);
+  SampleLds Ls;
+  double2 *g;
+  carve_lds(a, T, lds_tables<Q, P>(), ND, smem, Ls, g);
   const double *ge = a.grids + T->grid_off;
   for (int i = threadIdx.x; i < ND * nb; i += blockDim.x) {
     const int m = i / nb, b = i - m * nb;
@@ -959,8 +1114,101 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
   if (i < count) {
     int bins[ND];
     uint32_t np = 0, nt = 0, nf = 0;
-    out[i] = eval_sample<ORDER, Q, P>(a, T, D, g, first + i, iter, bins, np, nt, nf);
+    out[i] = eval_sample<ORDER, Q, P>(a, T, D, Ls, first + i, iter, bins, np, nt, nf);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Hartree-Fock spectrum tables (eq:spe)
+
+// Sigma_tau(k_i) [MeV] at the spline nodes k_i = i h of tasks [first,
+// first + ntasks), one wavefront per (task, tau, node).  Over the occupied
+// partners (isospin tau' < npartner, |k'| < kF_tau', every direction), with
+// p = (k - k') / 2, the direct element V(p, p) counts for both partner spins
+// and the exchange element V(p, -p) for equal spin and isospin:
+//   Sigma_tau(k) = sum_tau' \int d^3k' / (2 pi)^3 [2 V(p, p) - delta_{tau tau'} V(p, -p)].
+// Gauss-Legendre rule gl = (x[kHfGauss], w[kHfGauss]) on [-1, 1]: lane b takes
+// the cosine node b and loops over the |k'| nodes; the azimuth gives 2 pi.
+__global__ __launch_bounds__(256) void hf_nodes(KArgs a, const double *__restrict__ gl,
+                                                int first, int ntasks, int ntab, int npartner) {
+  const int wave = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int per_task = ntab * kHfEntries;
+  if (wave >= ntasks * per_task) return;  // uniform per wavefront
+  const int tl = wave / per_task, r = wave - tl * per_task;
+  const int tau = r / kHfEntries, i = r - tau * kHfEntries;
+  const TaskDev *__restrict__ T = a.tasks + first + tl;
+  const double k = static_cast<double>(i) * T->hf_h;
+  const Phys &ph = a.phys;
+  const double vq0 = ph.V0 + ph.Vy / ph.m2;  // zero momentum transfer
+  const double mu = gl[lane], wmu = gl[kHfGauss + lane];
+  double acc = 0.0;
+  for (int tp = 0; tp < npartner; ++tp) {
+    const double kF = sqrt(T->kF2[tp]);
+    if (!(kF > 0.0)) continue;
+    double sum = 0.0;
+    for (int j = 0; j < kHfGauss; ++j) {
+      const double kp = 0.5 * kF * (gl[j] + 1.0), wk = 0.5 * kF * gl[kHfGauss + j];
+      const double P2 = fmax(0.0, 0.25 * (k * k + kp * kp - 2.0 * k * kp * mu));
+      double pn = P2;
+      for (int e = 1; e < ph.half_exp; ++e) pn *= P2;
+      const double reg = exp(-2.0 * pn * ph.invLn);
+      double f = 2.0 * vq0;
+      if (tp == tau) f -= ph.V0 + ph.Vy / (4.0 * P2 + ph.m2);
+      sum = fma(wk * kp * kp, f * reg, sum);
+    }
+    acc = fma(wmu, sum, acc);
+  }
+  acc = wave_sum(acc) * (1.0 / (4.0 * M_PI * M_PI));  // 2 pi / (2 pi)^3
+  if (lane == 0) a.hf[4 * static_cast<size_t>(T->hf_off + tau * kHfEntries + i)] = acc;
+}
+
+// Cubic spline with zero end slopes (Sigma is even in k and flat where the
+// regulator has switched it off) through the node values of each (task, tau)
+// table, one thread per table: second derivatives m from
+//   2 m_0 + m_1 = 6 (y_1 - y_0) / h^2,
+//   m_{i-1} + 4 m_i + m_{i+1} = 6 (y_{i+1} - 2 y_i + y_{i-1}) / h^2,
+//   m_{n-1} + 2 m_n = -6 (y_n - y_{n-1}) / h^2
+// (Thomas algorithm, the entries' spare slots as scratch), then per interval
+// the coefficients of y_i + b t + c t^2 + d t^3, t = (k - k_i) / h.
+__global__ void hf_spline(KArgs a, int first, int ntasks, int ntab) {
+  const int id = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (id >= ntasks * ntab) return;
+  const int tl = id / ntab, tau = id - tl * ntab;
+  const TaskDev *__restrict__ T = a.tasks + first + tl;
+  double *E = a.hf + 4 * static_cast<size_t>(T->hf_off + tau * kHfEntries);
+  constexpr int n = kHfIntervals;
+  const double h2 = T->hf_h * T->hf_h;
+  double bprev = 1.0, rprev = 0.0;
+  for (int i = 0; i <= n; ++i) {
+    double diag = (i == 0 || i == n) ? 2.0 : 4.0, r;
+    if (i == 0) r = 6.0 * (E[4] - E[0]) / h2;
+    else if (i == n) r = -6.0 * (E[4 * n] - E[4 * (n - 1)]) / h2;
+    else r = 6.0 * (E[4 * (i + 1)] - 2.0 * E[4 * i] + E[4 * (i - 1)]) / h2;
+    if (i > 0) {
+      const double f = 1.0 / bprev;
+      diag -= f;
+      r -= f * rprev;
+    }
+    E[4 * i + 1] = diag;
+    E[4 * i + 2] = r;
+    bprev = diag;
+    rprev = r;
+  }
+  double mnext = E[4 * n + 2] / E[4 * n + 1];
+  E[4 * n + 3] = mnext;
+  for (int i = n - 1; i >= 0; --i) {
+    mnext = (E[4 * i + 2] - mnext) / E[4 * i + 1];
+    E[4 * i + 3] = mnext;
+  }
+  for (int i = 0; i < n; ++i) {
+    const double y0 = E[4 * i], y1 = E[4 * (i + 1)];
+    const double m0 = E[4 * i + 3], m1 = E[4 * (i + 1) + 3];
+    E[4 * i + 1] = (y1 - y0) - h2 * (2.0 * m0 + m1) / 6.0;
+    E[4 * i + 2] = 0.5 * h2 * m0;
+    E[4 * i + 3] = h2 * (m1 - m0) / 6.0;
+  }
+  E[4 * n + 1] = E[4 * n + 2] = E[4 * n + 3] = 0.0;
 }
 
 // Reset grids to uniform, histograms and running state to zero.
@@ -986,17 +1234,22 @@ __global__ void init_tasks(KArgs a, int first) {
 // ---------------------------------------------------------------------------
 // Host-side launchers
 
-size_t sample_lds_bytes(int nd, int nb, int block) {
-  // grid (e, width) pairs + histogram + reduction scratch + fp64 re-evaluation
-  // queue (128 sample offsets per wavefront)
-  return (3 * static_cast<size_t>(nd) * nb + 6 * (block / 64)) * sizeof(double) +
+// Kernel mode from the precision and the spectrum: the HF spectrum runs the
+// fp64 integrand (mode 2) whatever the precision.
+static int mode_of(const KArgs &a, int prec) { return a.phys.spectrum ? 2 : (prec ? 1 : 0); }
+
+size_t sample_lds_bytes(int nd, int nb, int block, int ntab) {
+  // turn table + HF tables + grid (e, width) pairs + histogram + reduction
+  // scratch + fp64 re-evaluation queue (128 sample offsets per wavefront)
+  return kTurnEntries * sizeof(SinCos) + hf_lds_doubles(ntab) * sizeof(double) +
+         (3 * static_cast<size_t>(nd) * nb + 6 * (block / 64)) * sizeof(double) +
          (block / 64) * 128 * sizeof(uint32_t);
 }
 
 template <int Q, int P>
 static hipError_t single_q(const KArgs &a, int t, int order, int nitems, int block,
                            hipStream_t st) {
-  const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block);
+  const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block, lds_tables<Q, P>());
   switch (order) {
     case 1: hipLaunchKernelGGL((sample_single<1, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
     case 2: hipLaunchKernelGGL((sample_single<2, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
@@ -1010,15 +1263,20 @@ static hipError_t single_q(const KArgs &a, int t, int order, int nitems, int blo
 
 hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int prec, int nitems,
                                 int block, hipStream_t st) {
-  if (q == 4) return prec ? single_q<4, 1>(a, t, order, nitems, block, st)
-                          : single_q<4, 0>(a, t, order, nitems, block, st);
-  return prec ? single_q<2, 1>(a, t, order, nitems, block, st)
-              : single_q<2, 0>(a, t, order, nitems, block, st);
+  switch (mode_of(a, prec) + 3 * (q == 4)) {
+    case 0: return single_q<2, 0>(a, t, order, nitems, block, st);
+    case 1: return single_q<2, 1>(a, t, order, nitems, block, st);
+    case 2: return single_q<2, 2>(a, t, order, nitems, block, st);
+    case 3: return single_q<4, 0>(a, t, order, nitems, block, st);
+    case 4: return single_q<4, 1>(a, t, order, nitems, block, st);
+    default: return single_q<4, 2>(a, t, order, nitems, block, st);
+  }
 }
 
 template <int Q, int P>
 static hipError_t order_qp(const KArgs &a, int order, int k0, int k1, int grid, int block,
-                           size_t lds, hipStream_t st) {
+                           hipStream_t st) {
+  const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block, lds_tables<Q, P>());
   switch (order) {
     case 1: hipLaunchKernelGGL((sample_order<1, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
     case 2: hipLaunchKernelGGL((sample_order<2, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
@@ -1032,11 +1290,14 @@ static hipError_t order_qp(const KArgs &a, int order, int k0, int k1, int grid, 
 
 hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, int k0, int k1,
                                int nitems, int block, hipStream_t st) {
-  const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block);
-  if (q == 4) return prec ? order_qp<4, 1>(a, order, k0, k1, nitems, block, lds, st)
-                          : order_qp<4, 0>(a, order, k0, k1, nitems, block, lds, st);
-  return prec ? order_qp<2, 1>(a, order, k0, k1, nitems, block, lds, st)
-              : order_qp<2, 0>(a, order, k0, k1, nitems, block, lds, st);
+  switch (mode_of(a, prec) + 3 * (q == 4)) {
+    case 0: return order_qp<2, 0>(a, order, k0, k1, nitems, block, st);
+    case 1: return order_qp<2, 1>(a, order, k0, k1, nitems, block, st);
+    case 2: return order_qp<2, 2>(a, order, k0, k1, nitems, block, st);
+    case 3: return order_qp<4, 0>(a, order, k0, k1, nitems, block, st);
+    case 4: return order_qp<4, 1>(a, order, k0, k1, nitems, block, st);
+    default: return order_qp<4, 2>(a, order, k0, k1, nitems, block, st);
+  }
 }
 
 hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int max_nd, double alpha,
@@ -1052,7 +1313,8 @@ static hipError_t dump_q(const KArgs &a, int t, int order, uint32_t iter, uint64
                          uint64_t count, double *out, hipStream_t st) {
   const int block = 256;
   const dim3 grid(static_cast<unsigned>((count + block - 1) / block));
-  const size_t lds = 2 * static_cast<size_t>(3 * (order + 1)) * a.phys.nb * sizeof(double);
+  const size_t lds = kTurnEntries * sizeof(SinCos) + hf_lds_doubles(lds_tables<Q, P>()) * sizeof(double) +
+                     2 * static_cast<size_t>(3 * (order + 1)) * a.phys.nb * sizeof(double);
   switch (order) {
     case 1: hipLaunchKernelGGL((dump_samples<1, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
     case 2: hipLaunchKernelGGL((dump_samples<2, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
@@ -1066,10 +1328,26 @@ static hipError_t dump_q(const KArgs &a, int t, int order, uint32_t iter, uint64
 
 hipError_t launch_dump(const KArgs &a, int t, int order, int q, int prec, uint32_t iter,
                        uint64_t first, uint64_t count, double *out, hipStream_t st) {
-  if (q == 4) return prec ? dump_q<4, 1>(a, t, order, iter, first, count, out, st)
-                          : dump_q<4, 0>(a, t, order, iter, first, count, out, st);
-  return prec ? dump_q<2, 1>(a, t, order, iter, first, count, out, st)
-              : dump_q<2, 0>(a, t, order, iter, first, count, out, st);
+  switch (mode_of(a, prec) + 3 * (q == 4)) {
+    case 0: return dump_q<2, 0>(a, t, order, iter, first, count, out, st);
+    case 1: return dump_q<2, 1>(a, t, order, iter, first, count, out, st);
+    case 2: return dump_q<2, 2>(a, t, order, iter, first, count, out, st);
+    case 3: return dump_q<4, 0>(a, t, order, iter, first, count, out, st);
+    case 4: return dump_q<4, 1>(a, t, order, iter, first, count, out, st);
+    default: return dump_q<4, 2>(a, t, order, iter, first, count, out, st);
+  }
+}
+
+hipError_t launch_hf(const KArgs &a, const double *gl, int first, int ntasks, int ntab,
+                     int npartner, hipStream_t st) {
+  const long waves = static_cast<long>(ntasks) * ntab * kHfEntries;
+  hipLaunchKernelGGL(hf_nodes, dim3(static_cast<unsigned>((waves + 3) / 4)), dim3(256), 0, st, a,
+                     gl, first, ntasks, ntab, npartner);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int threads = ntasks * ntab;
+  hipLaunchKernelGGL(hf_spline, dim3((threads + 63) / 64), dim3(64), 0, st, a, first, ntasks, ntab);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(const KArgs &a, int first, int ntasks, hipStream_t st) {

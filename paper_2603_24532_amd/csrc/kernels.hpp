@@ -6,7 +6,8 @@
 
 namespace mbpt {
 
-size_t sample_lds_bytes(int nd, int nb, int block);
+// Dynamic LDS of a sample kernel; ntab = HF spline tables held (0, 1 or 2).
+size_t sample_lds_bytes(int nd, int nb, int block, int ntab);
 hipError_t launch_sample_single(const KArgs &a, int task, int order, int q, int prec, int nitems,
                                 int block, hipStream_t st);
 // Items [olist[k0].x, olist[k0].x + nitems) of the tasks listed in olist[k0, k1).
@@ -17,5 +18,10 @@ hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int max_nd,
 hipError_t launch_dump(const KArgs &a, int task, int order, int q, int prec, uint32_t iter,
                        uint64_t first, uint64_t count, double *out, hipStream_t st);
 hipError_t launch_init(const KArgs &a, int first, int ntasks, hipStream_t st);
+// HF spline tables of tasks [first, first + ntasks): ntab isospin tables each,
+// partners summed over npartner isospins; gl = Gauss-Legendre (x, w) on the
+// device.
+hipError_t launch_hf(const KArgs &a, const double *gl, int first, int ntasks, int ntab,
+                     int npartner, hipStream_t st);
 
 }  // namespace mbpt

@@ -45,7 +45,8 @@ static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255);
 // momenta, line momenta, Pauli tests), the part a sample past the Pauli test
 // needs (denominators, matrix elements, weight, accumulation) and the part
 // per label term evaluated.
-void count_flops(const Diagram &d, int q, int half_exp, int label_mode, FlopModel &f) {
+void count_flops(const Diagram &d, int q, int half_exp, int label_mode, int spectrum,
+                 FlopModel &f) {
   const int n = d.order, L = d.nloops, NL = d.nlines, NC = d.ncuts, ND = d.ndim;
   const int H = n / 2;
   double pre = 0, pre_t = 0;
@@ -58,6 +59,10 @@ void count_flops(const Diagram &d, int q, int half_exp, int label_mode, FlopMode
     pre += 3.0 * std::max(0, nnz - 1);  // tree-line sums
     pre += 5.0 + 1.0;                    // k^2, eps
     pre += (q == 4) ? 2.0 : 1.0;         // occupation tests
+    if (spectrum) {
+      pre_t += 1.0;                      // |k|
+      pre += 8.0 * (q == 4 ? 2 : 1) + 1; // spline(s) and their sum / difference
+    }
   }
   double post = 0, post_t = 0;
   for (int c = 0; c < NC; ++c) {
@@ -73,13 +78,16 @@ void count_flops(const Diagram &d, int q, int half_exp, int label_mode, FlopMode
   post += 3.0;                  // weight: jacobian * prefactor * label sum
   post_t += 1.0;                // one division by the denominators
   post_t += (NC == 0) ? -1.0 : 0.0;
+  // HF in nuclear matter: per isospin configuration its own denominators
+  // (2 per line of each cut, their product) and one division
+  const double iso_den = (spectrum && q == 4) ? 2.0 * NC * NL + NC + 1.0 : 0.0;
   if (label_mode) {
     f.per_term = n + 1.0;       // explicit term: product of n factors, multiply-add
   } else {
     // factorised: monomial tables of the two vertex halves (2^H + 2^{n-H}
     // products) once per sample, then per isospin group 2^n + 2^{n-H} FMAs
     post += (1 << H) + (1 << (n - H)) - 2;
-    f.per_term = 2.0 * ((1 << n) + (1 << (n - H)));
+    f.per_term = 2.0 * ((1 << n) + (1 << (n - H))) + iso_den;
   }
   double acc = 10.0 + 1.0 + ND; // shifted sums (Neumaier), w^2, histogram adds
   f.pre = pre + pre_t + acc;    // every sample is accumulated
@@ -108,10 +116,12 @@ extern "C" int mbpt_context_create(const mbpt_context_desc *desc, mbpt_context *
   d.fp32_band_k = 1e-4;
   d.fp32_band_d = 1e-2;
   d.label_mode = 0;
+  d.spectrum = MBPT_SPECTRUM_FREE;
   if (desc) d = *desc;
   if (d.n_bins < 2 || d.n_bins > kMaxBins || !(d.alpha > 0.0) || !(d.kcut_extra >= 0.0) ||
       (d.precision != MBPT_FP64 && d.precision != MBPT_FP32) || d.fp32_band_k < 0.0 ||
-      d.fp32_band_d < 0.0 || (d.label_mode != 0 && d.label_mode != 1))
+      d.fp32_band_d < 0.0 || (d.label_mode != 0 && d.label_mode != 1) ||
+      (d.spectrum != MBPT_SPECTRUM_FREE && d.spectrum != MBPT_SPECTRUM_HF))
     return MBPT_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || d.device < 0 || d.device >= ndev) return MBPT_EHIP;
@@ -147,6 +157,13 @@ extern "C" int mbpt_set_interaction(mbpt_context *ctx, const mbpt_interaction *v
     return MBPT_EINVAL;
   }
   ctx->v = *v;
+  ++ctx->epoch;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_set_spectrum(mbpt_context *ctx, int spectrum) {
+  if (!ctx || (spectrum != MBPT_SPECTRUM_FREE && spectrum != MBPT_SPECTRUM_HF)) return MBPT_EINVAL;
+  ctx->desc.spectrum = spectrum;
   ++ctx->epoch;
   return MBPT_OK;
 }
@@ -289,6 +306,46 @@ void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T) 
   T.inv_density = 1.0 / density;
   T.band_k = ctx->desc.fp32_band_k;
   T.band_d = ctx->desc.fp32_band_d;
+  // HF spline range: beyond kF,max + kHfRangeLambda Lambda every partner
+  // momentum p exceeds 3 Lambda and the regulator leaves Sigma < 1e-70
+  T.hf_h = (kFmax + kHfRangeLambda * ctx->v.Lambda) / kHfIntervals;
+  T.hf_inv_h = 1.0 / T.hf_h;
+}
+
+// Gauss-Legendre rule on [-1, 1]: the nodes are the zeros of P_n, found by
+// Newton's method from cos(pi (i + 3/4) / (n + 1/2)) with P_n and P_n' from
+// the three-term recurrence; the weights are 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, double *x, double *w) {
+  for (int i = 0; i < n / 2 + n % 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double d = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p = 1.0, pm = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        const double pn = ((2 * j - 1) * z * p - (j - 1) * pm) / j;
+        pm = p;
+        p = pn;
+      }
+      d = n * (pm - z * p) / (1.0 - z * z);
+      const double step = p / d;
+      z -= step;
+      if (std::fabs(step) <= 1e-16 * std::fabs(z) + 1e-300) {
+        // one more evaluation at the converged z for the weight
+        p = 1.0;
+        pm = 0.0;
+        for (int j = 1; j <= n; ++j) {
+          const double pn = ((2 * j - 1) * z * p - (j - 1) * pm) / j;
+          pm = p;
+          p = pn;
+        }
+        d = n * (pm - z * p) / (1.0 - z * z);
+        break;
+      }
+    }
+    x[n - 1 - i] = z;
+    x[i] = -z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * d * d);
+  }
 }
 
 // Compile a task list's diagrams into device tables (one descriptor per
@@ -325,7 +382,7 @@ int compile_tables(mbpt_task_set *set) {
     fill_diag_dev(*d, dd);
     append_label_tables(*d, q, dd, set->groups, set->terms, set->coefs, 0, 0, 0);
     FlopModel fm;
-    count_flops(*d, q, ctx->v.reg_exp / 2, ctx->desc.label_mode, fm);
+    count_flops(*d, q, ctx->v.reg_exp / 2, ctx->desc.label_mode, ctx->desc.spectrum, fm);
     fm.all_units = ctx->desc.label_mode ? dd.nterms : dd.ngroups;
     set->diag_flops.push_back(fm);
     set->diags.push_back(dd);
@@ -350,6 +407,7 @@ void fill_task_params(mbpt_task_set *set) {
     const int nd = 3 * (td.order + 1);
     T.diag = set->task_diag[t];
     T.nd = nd;
+    T.hf_off = static_cast<int>(t) * 2 * kHfEntries;
     T.grid_off = goff;
     T.hist_off = hoff;
     goff += nd * (nb + 1);
@@ -371,7 +429,8 @@ size_t items_for(const mbpt_task_set *set, uint64_t samples) {
 }
 
 struct Layout {
-  size_t tasks, olist, diags, groups, terms, coefs, grids, hists, partials, counters, reslog, total;
+  size_t tasks, olist, diags, groups, terms, coefs, grids, hists, partials, counters, reslog, hf,
+      gl, total;
 };
 
 Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, int nb) {
@@ -406,6 +465,10 @@ Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, 
   off = align256(off + items * kItemCounters * sizeof(uint64_t));
   L.reslog = off;
   off = align256(off + nt * static_cast<size_t>(std::max(1, max_iters)) * 2 * sizeof(double));
+  L.hf = off;  // two isospin tables per task, used with the HF spectrum
+  off = align256(off + nt * 2 * static_cast<size_t>(kHfEntries) * 4 * sizeof(double));
+  L.gl = off;
+  off = align256(off + 2 * kHfGauss * sizeof(double));
   L.total = off;
   return L;
 }
@@ -419,6 +482,7 @@ KArgs kargs_of(const mbpt_task_set *set) {
   a.terms = set->d_terms;
   a.gcoef = set->d_coefs;
   a.olist = set->d_olist;
+  a.hf = set->d_hf;
   a.grids = set->d_grids;
   a.hists = set->d_hists;
   a.partials = set->d_partials;
@@ -437,7 +501,30 @@ KArgs kargs_of(const mbpt_task_set *set) {
   a.phys.half_exp = v.reg_exp / 2;
   a.phys.nb = ctx->desc.n_bins;
   a.phys.seed = ctx->desc.seed;
+  a.phys.spectrum = ctx->desc.spectrum;
   return a;
+}
+
+// Precision, interaction or spectrum changed since the set last ran: captured
+// launches, launch shapes and HF tables are stale.
+void sync_epoch(mbpt_task_set *set) {
+  if (set->epoch == set->ctx->epoch) return;
+  set->drop_graph();
+  set->oranges.clear();
+  set->hf_dirty = true;
+  set->epoch = set->ctx->epoch;
+}
+
+// (Re)computes the HF spline tables of every task when the spectrum is HF and
+// the medium, interaction or spectrum changed since they were made.
+int ensure_hf(mbpt_task_set *set) {
+  mbpt_context *ctx = set->ctx;
+  if (!ctx->desc.spectrum || !set->hf_dirty) return MBPT_OK;
+  const KArgs a = kargs_of(set);
+  HIPCHK(ctx, launch_hf(a, set->d_gl, 0, static_cast<int>(set->tasks.size()),
+                        set->q == 4 ? 2 : 1, set->q == 4 ? 2 : 1, ctx->stream));
+  set->hf_dirty = false;
+  return MBPT_OK;
 }
 
 // Upload the parameter prefix of every TaskDev (state left untouched).
@@ -482,6 +569,13 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
   set->d_partials = reinterpret_cast<double *>(base + L.partials);
   set->d_counters = reinterpret_cast<uint64_t *>(base + L.counters);
   set->d_reslog = reinterpret_cast<double *>(base + L.reslog);
+  set->d_hf = reinterpret_cast<double *>(base + L.hf);
+  set->d_gl = reinterpret_cast<double *>(base + L.gl);
+  set->h_gl.assign(2 * kHfGauss, 0.0);
+  gauss_legendre(kHfGauss, set->h_gl.data(), set->h_gl.data() + kHfGauss);
+  HIPCHK(ctx, hipMemcpyAsync(set->d_gl, set->h_gl.data(), set->h_gl.size() * sizeof(double),
+                             hipMemcpyHostToDevice, ctx->stream));
+  set->hf_dirty = true;
   fill_task_params(set);
   set->oranges.clear();
   HIPCHK(ctx, hipMemcpyAsync(set->d_diags, set->diags.data(), set->diags.size() * sizeof(DiagDev),
@@ -633,6 +727,7 @@ extern "C" int mbpt_set_density(mbpt_task_set *set, double density) {
   if (!set || !(density > 0.0)) return MBPT_EINVAL;
   for (auto &t : set->tasks) t.density = density;
   set->drop_graph();
+  set->hf_dirty = true;
   if (set->ws) {
     fill_task_params(set);
     return upload_params(set);
@@ -648,6 +743,7 @@ extern "C" int mbpt_set_asymmetry(mbpt_task_set *set, double x) {
   }
   for (auto &t : set->tasks) t.proton_fraction = x;
   set->drop_graph();
+  set->hf_dirty = true;
   if (set->ws) {
     fill_task_params(set);
     return upload_params(set);
@@ -784,12 +880,7 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
     set_err(ctx, "integrate: more work items than the workspace holds");
     return MBPT_ENOMEM;
   }
-  if (set->epoch != ctx->epoch) {
-    // precision or interaction changed: captured launches and grids are stale
-    set->drop_graph();
-    set->oranges.clear();
-    set->epoch = ctx->epoch;
-  }
+  sync_epoch(set);
   bool changed = false;
   std::vector<int> all(nt);
   for (int t = 0; t < nt; ++t) {
@@ -810,6 +901,10 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
   if (changed) {
     set->drop_graph();
     int rc = upload_params(set);
+    if (rc) return rc;
+  }
+  {
+    const int rc = ensure_hf(set);
     if (rc) return rc;
   }
   KArgs a = kargs_of(set);
@@ -914,6 +1009,11 @@ extern "C" int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, ui
   if (!set || !w_host || task < 0 || task >= static_cast<int>(set->tasks.size())) return MBPT_EINVAL;
   if (!set->ws) return MBPT_ESTATE;
   mbpt_context *ctx = set->ctx;
+  sync_epoch(set);
+  {
+    const int rc = ensure_hf(set);
+    if (rc) return rc;
+  }
   KArgs a = kargs_of(set);
   // the item partials region serves as staging
   const uint64_t cap = set->max_items * 4;
@@ -926,6 +1026,28 @@ extern "C" int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, ui
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     done += n;
   }
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_hf_nodes(mbpt_task_set *set, int task, int tau, double *sigma_host,
+                             double *h) {
+  if (!set || !sigma_host || task < 0 || task >= static_cast<int>(set->tasks.size()) ||
+      tau < 0 || tau > (set->q == 4 ? 1 : 0))
+    return MBPT_EINVAL;
+  mbpt_context *ctx = set->ctx;
+  if (!set->ws || ctx->desc.spectrum != MBPT_SPECTRUM_HF) {
+    set_err(ctx, "hf_nodes: needs the HF spectrum and a bound workspace");
+    return MBPT_ESTATE;
+  }
+  sync_epoch(set);
+  int rc = ensure_hf(set);
+  if (rc) return rc;
+  const TaskDev &T = set->h_tasks[task];
+  const double *src = set->d_hf + 4 * static_cast<size_t>(T.hf_off + tau * kHfEntries);
+  HIPCHK(ctx, hipMemcpy2DAsync(sigma_host, sizeof(double), src, 4 * sizeof(double),
+                               sizeof(double), kHfEntries, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (h) *h = T.hf_h;
   return MBPT_OK;
 }
 

@@ -71,6 +71,10 @@ struct mbpt_task_set {
   mbpt::GroupDev *d_groups = nullptr;
   mbpt::TermDev *d_terms = nullptr;
   mbpt::CoefDev *d_coefs = nullptr;
+  double *d_hf = nullptr;   // HF spline entries (2 tables per task)
+  double *d_gl = nullptr;   // Gauss-Legendre rule for the HF tables
+  bool hf_dirty = true;     // HF tables must be (re)computed before use
+  std::vector<double> h_gl; // host copy of the rule (source of an async copy)
   double *d_grids = nullptr, *d_hists = nullptr, *d_partials = nullptr, *d_reslog = nullptr;
   uint64_t *d_counters = nullptr;
   std::vector<int2> olist;                 // (first item, task) grouped by order
@@ -88,7 +92,8 @@ namespace mbpt {
 struct Diagram;
 void set_err(mbpt_context *ctx, const std::string &msg);
 int hip_fail(mbpt_context *ctx, hipError_t e, const char *what);
-void count_flops(const Diagram &d, int q, int half_exp, int label_mode, FlopModel &f);
+void count_flops(const Diagram &d, int q, int half_exp, int label_mode, int spectrum,
+                 FlopModel &f);
 void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
                          std::vector<TermDev> &terms, std::vector<CoefDev> &coefs,
                          size_t group_base, size_t term_base, size_t coef_base);
@@ -98,6 +103,9 @@ void result_of(const TaskDev &S, mbpt_result &r);
 void timed_begin(mbpt_context *ctx, size_t &slot);
 void timed_end(mbpt_context *ctx, size_t slot);
 void resolve_timing(mbpt_context *ctx);
+void gauss_legendre(int n, double *x, double *w);
+int ensure_hf(mbpt_task_set *set);
+void sync_epoch(mbpt_task_set *set);
 void order_items(std::vector<TaskDev> &T, const std::vector<int> &active,
                  std::vector<int2> &olist, std::vector<OrderRange> &ranges);
 }  // namespace mbpt

@@ -218,6 +218,7 @@ KArgs server_kargs(const mbpt_server *s) {
   a.phys.half_exp = v.reg_exp / 2;
   a.phys.nb = ctx->desc.n_bins;
   a.phys.seed = ctx->desc.seed;
+  a.phys.spectrum = MBPT_SPECTRUM_FREE;
   return a;
 }
 
@@ -234,7 +235,7 @@ const mbpt_server::Compiled &compiled_of(mbpt_server *s, int order, int id) {
   c.dd.ncuts = d->ncuts;
   fill_diag_dev(*d, c.dd);
   append_label_tables(*d, 4, c.dd, c.groups, c.terms, c.coefs, 0, 0, 0);
-  count_flops(*d, 4, s->ctx->v.reg_exp / 2, s->ctx->desc.label_mode, c.fm);
+  count_flops(*d, 4, s->ctx->v.reg_exp / 2, s->ctx->desc.label_mode, MBPT_SPECTRUM_FREE, c.fm);
   c.fm.all_units = s->ctx->desc.label_mode ? c.dd.nterms : c.dd.ngroups;
   c.bytes = a256(c.groups.size() * sizeof(GroupDev)) + a256(c.terms.size() * sizeof(TermDev)) +
             a256(c.coefs.size() * sizeof(CoefDev));
@@ -340,6 +341,10 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
       (reinterpret_cast<uintptr_t>(device_ptr) & 255u))
     return MBPT_EINVAL;
   *out = nullptr;
+  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE) {
+    set_err(ctx, "server_create: the server supports the free spectrum only");
+    return MBPT_EINVAL;
+  }
   Layout L{};
   if (!make_layout(max_slots, ctx->desc.n_bins, bytes, L) ||
       L.max_items < items_of(max_samples_per_iter)) {
@@ -415,6 +420,10 @@ extern "C" int mbpt_server_submit(mbpt_server *s, const mbpt_request *req, uint6
 extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
   if (!s) return MBPT_EINVAL;
   mbpt_context *ctx = s->ctx;
+  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE) {
+    set_err(ctx, "server_step: the server supports the free spectrum only");
+    return MBPT_ESTATE;
+  }
   while (!s->queue.empty()) {
     int slot = -1;
     for (int i = 0; i < s->max_slots; ++i)
