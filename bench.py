@@ -36,7 +36,20 @@ DENSITIES = [0.04 + 0.02 * i for i in range(9)]
 KERNEL_SOURCES = ("paper_2603_24532_amd/csrc/kernels.hip",
                   "paper_2603_24532_amd/csrc/device_types.hpp",
                   "paper_2603_24532_amd/csrc/turn_table.hpp")
-TRAFFIC = None  # {"sha256": ..., "bytes_per_launch": ..., "fetch_kib": ..., ...}
+# Measured on MI355X: sample_single<2,2,0>, 2^24 samples, block 256 x 16
+# samples per thread (4096 work items), 18 dispatches each.  Copy reference:
+# a 256 MiB device-to-device copy reads as FETCH_SIZE 131087.5 KiB and writes
+# as WRITE_SIZE 262144 KiB, so FETCH is scaled by 2.0 and WRITE by 1.0.  The
+# writes are the per-item histogram merges (450 fp64 atomics per item,
+# performed memory-side), not data the integrand needs.
+TRAFFIC = {
+    "sha256": "01f51526a36527225cc91202f2cdde6df3ef04f264d7ed73e40d5f0dd400a84f",
+    "block": 256, "spt": 16,
+    "fetch_kib": 127.45, "write_kib": 14940.44,
+    "fetch_scale": 262144.0 / 131087.5, "write_scale": 1.0,
+}
+TRAFFIC["bytes_per_launch"] = 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] +
+                                        TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
 
 
 def kernel_sources_sha256():
@@ -48,8 +61,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def traffic_bytes_per_launch():
-    if TRAFFIC is None or TRAFFIC.get("sha256") != kernel_sources_sha256():
+def traffic_bytes_per_launch(block, spt):
+    """Measured HBM bytes per launch, or None if the kernel sources or the
+    work decomposition differ from those it was measured with."""
+    if (TRAFFIC is None or TRAFFIC.get("sha256") != kernel_sources_sha256()
+            or (block, spt) != (TRAFFIC["block"], TRAFFIC["spt"])):
         return None
     return TRAFFIC["bytes_per_launch"]
 
@@ -76,6 +92,9 @@ def parse():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--cpu-samples-log2", type=int, default=20)
+    ap.add_argument("--block", type=int, default=256, help="threads per block (plain path)")
+    ap.add_argument("--spt", type=int, default=16, help="samples per thread per work item "
+                                                        "(plain path)")
     ap.add_argument("--label-mode", type=int, default=0, choices=(0, 1),
                     help="label sums: 0 polynomial per isospin configuration, 1 explicit list")
     ap.add_argument("--workload", default="plain",
@@ -109,6 +128,7 @@ def gpu_run(args, precision=0, steps=None, warmup=None):
                  for i, n in enumerate(DENSITIES)]
         s = M.mbpt_create_task_set(ctx, tasks)
         M.mbpt_set_launch_mode(s, M.MBPT_LAUNCH_PER_TASK)
+        M.mbpt_set_blocking(s, args.block, args.spt)
         nbytes = M.mbpt_workspace_query(s, N, iters)
         buf, ptr = M.device_workspace(nbytes)
         bufs.append(buf)
@@ -448,6 +468,7 @@ def main():
             "tasks": 18, "samples_per_iter": g["N"], "iterations": g["iters"],
             "interaction": "C0=-1 fm^2, Cy=-2, mpi=0.7, Lambda=2, n=4", "seed": 1,
             "label_sum": "polynomial" if LABEL_MODE == 0 else "explicit",
+            "block": args.block, "samples_per_thread": args.spt,
         },
         "roofline": {
             "bound": "alu",
@@ -456,7 +477,7 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": traffic_bytes_per_launch(),
+            "traffic": traffic_bytes_per_launch(args.block, args.spt),
             "avg_launch_ms": avg_ms,
             "launches": st2["launches"],
             "algorithmic_flops_per_launch": flops_per_launch,
