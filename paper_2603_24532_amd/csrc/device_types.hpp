@@ -90,7 +90,7 @@ struct alignas(16) TaskDev {
   double band_k, band_d;
   double hf_h, hf_inv_h;  // HF spline step and its inverse
   int active;
-  int pad;
+  int plan;             // iterations of the current launch sequence it takes part in
   // state (written by the device)
   uint32_t iter;        // Philox iteration word of the next iteration
   int it_done;

@@ -1006,13 +1006,16 @@ __device__ void refine_dim_wave(double *hist, double *edges, int nb, double alph
   }
 }
 
-__global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task, double alpha) {
+// step_iter: index of this iteration within the launch sequence; tasks whose
+// plan ends before it sit this iteration out.
+__global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task, double alpha,
+                                                        int step_iter) {
   __shared__ double red[4 * 4];
   __shared__ unsigned long long kred[4][kItemCounters];
   extern __shared__ double scratch[];
   const int t = first_task + blockIdx.x;
   TaskDev *T = a.tasks + t;
-  if (!T->active) return;
+  if (!T->active || T->plan <= step_iter) return;
   const int tid = threadIdx.x, bs = blockDim.x;
   double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
   unsigned long long kc[kItemCounters] = {0, 0, 0};
@@ -1300,11 +1303,11 @@ hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, int k
   }
 }
 
-hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int max_nd, double alpha,
+hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_iter, double alpha,
                          hipStream_t st) {
-  (void)max_nd;
   const size_t lds = 4 * static_cast<size_t>(2 * a.phys.nb + 2) * sizeof(double);
-  hipLaunchKernelGGL(finish_iteration, dim3(ntasks), dim3(256), lds, st, a, first_task, alpha);
+  hipLaunchKernelGGL(finish_iteration, dim3(ntasks), dim3(256), lds, st, a, first_task, alpha,
+                     step_iter);
   return hipGetLastError();
 }
 

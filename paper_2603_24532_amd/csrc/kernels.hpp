@@ -13,7 +13,9 @@ hipError_t launch_sample_single(const KArgs &a, int task, int order, int q, int 
 // Items [olist[k0].x, olist[k0].x + nitems) of the tasks listed in olist[k0, k1).
 hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, int k0, int k1,
                                int nitems, int block, hipStream_t st);
-hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int max_nd, double alpha,
+// Iteration end of tasks [first_task, first_task + ntasks) that take part in
+// iteration step_iter of the current launch sequence (plan > step_iter).
+hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_iter, double alpha,
                          hipStream_t st);
 hipError_t launch_dump(const KArgs &a, int task, int order, int q, int prec, uint32_t iter,
                        uint64_t first, uint64_t count, double *out, hipStream_t st);

@@ -418,6 +418,7 @@ void fill_task_params(mbpt_task_set *set) {
     T.order = td.order;
     fill_medium(ctx, td.density, td.proton_fraction, T);
     T.active = 1;
+    T.plan = 0x7fffffff;  // every iteration
   }
   set->grid_doubles = goff;
   set->hist_doubles = hoff;
@@ -814,7 +815,7 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
         HIPCHK(ctx, launch_sample_single(a, t, set->tasks[t].order, set->q, ctx->desc.precision,
                                          set->h_tasks[t].nitems, set->block, ctx->stream));
         if (timed) timed_end(ctx, slot);
-        HIPCHK(ctx, launch_finish(a, t, 1, 3 * (set->tasks[t].order + 1), alpha, ctx->stream));
+        HIPCHK(ctx, launch_finish(a, t, 1, 0, alpha, ctx->stream));
       }
     return MBPT_OK;
   }
@@ -825,7 +826,7 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
       HIPCHK(ctx, launch_sample_order(a, r.order, set->q, ctx->desc.precision, r.k0, r.k1,
                                       r.nitems, set->block, ctx->stream));
     if (timed) timed_end(ctx, slot);
-    HIPCHK(ctx, launch_finish(a, 0, nt, set->max_nd, alpha, ctx->stream));
+    HIPCHK(ctx, launch_finish(a, 0, nt, 0, alpha, ctx->stream));
   }
   return MBPT_OK;
 }

@@ -38,6 +38,7 @@ using namespace mbpt;
 namespace {
 
 constexpr int kMinIters = 3;
+constexpr int kMaxPlan = 32;  // iterations per step at most
 constexpr int kBlock = 256;
 constexpr int kSpt = 16;
 constexpr size_t kTermBytesPerSlot = 64 * 1024;
@@ -220,6 +221,34 @@ KArgs server_kargs(const mbpt_server *s) {
   a.phys.seed = ctx->desc.seed;
   a.phys.spectrum = MBPT_SPECTRUM_FREE;
   return a;
+}
+
+// Iterations a resident request runs in the next step: the first kMinIters
+// at once, then as many as the 1/sqrt(iterations) decrease of the combined
+// sigma predicts are needed to reach its target (at least 1, at most
+// kMaxPlan), within its evaluation cap.  It depends on the request's own
+// state only, so a result does not depend on the requests sharing the GPU.
+int plan_of(const Req &q) {
+  const mbpt_result &r = q.res;
+  int plan;
+  if (r.iters_done < kMinIters) {
+    plan = kMinIters - r.iters_done;
+  } else {
+    const double target = std::max(q.r.sigma_rel * std::fabs(r.E_per_A), q.r.sigma_abs);
+    if (target > 0.0 && r.sigma > 0.0) {
+      const double ratio = (r.sigma / target) * (r.sigma / target);
+      const double need = std::ceil(r.iters_done * (ratio - 1.0));
+      plan = need < 1.0 ? 1 : (need > kMaxPlan ? kMaxPlan : static_cast<int>(need));
+    } else {
+      plan = kMaxPlan;
+    }
+  }
+  if (q.r.max_evals > 0) {
+    const uint64_t done = r.n_evals, cap = q.r.max_evals, per = q.r.samples_per_iter;
+    const uint64_t left = cap > done ? (cap - done + per - 1) / per : 1;
+    if (left < static_cast<uint64_t>(plan)) plan = static_cast<int>(std::max<uint64_t>(1, left));
+  }
+  return plan;
 }
 
 // Tables of a diagram compiled once per server (offsets relative to 0).
@@ -438,18 +467,26 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
     if (rc < 0) return rc;
     s->queue.pop_front();
   }
-  // work numbering grouped by order over the resident slots (free slots own
-  // none); one sample launch per order present
+  // plans, and work numbering grouped by order over the resident slots (free
+  // slots own none), longest plan first within an order: in iteration j of
+  // the step the requests still running are a prefix of each order's list
   std::vector<int> active;
+  int K = 0;
   for (int i = 0; i < s->max_slots; ++i) {
     TaskDev &T = s->h_tasks[i];
     if (s->slot_req[i] >= 0) {
+      T.plan = plan_of(s->reqs[static_cast<uint64_t>(s->slot_req[i])]);
+      K = std::max(K, T.plan);
       active.push_back(i);
     } else {
       T.nitems = 0;
       T.active = 0;
+      T.plan = 0;
     }
   }
+  std::stable_sort(active.begin(), active.end(), [&](int x, int y) {
+    return s->h_tasks[x].plan > s->h_tasks[y].plan;
+  });
   const int nactive = static_cast<int>(active.size());
   if (nactive > 0) {
     order_items(s->h_tasks, active, s->olist, s->ranges);
@@ -467,11 +504,18 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
     const int prec = ctx->desc.precision;
     size_t slot = 0;
     timed_begin(ctx, slot);
-    for (const auto &r : s->ranges)
-      MBPT_HIPCHK(ctx, launch_sample_order(a, r.order, 4, prec, r.k0, r.k1, r.nitems, kBlock,
-                                           ctx->stream));
+    for (int j = 0; j < K; ++j) {
+      for (const auto &r : s->ranges) {
+        int k1 = r.k0;  // end of the prefix still running in iteration j
+        while (k1 < r.k1 && s->h_tasks[s->olist[k1].y].plan > j) ++k1;
+        if (k1 == r.k0) continue;
+        const int end = k1 < r.k1 ? s->olist[k1].x : r.item_end;
+        MBPT_HIPCHK(ctx, launch_sample_order(a, r.order, 4, prec, r.k0, k1,
+                                             end - s->olist[r.k0].x, kBlock, ctx->stream));
+      }
+      MBPT_HIPCHK(ctx, launch_finish(a, 0, s->max_slots, j, ctx->desc.alpha, ctx->stream));
+    }
     timed_end(ctx, slot);
-    MBPT_HIPCHK(ctx, launch_finish(a, 0, s->max_slots, kMaxDim, ctx->desc.alpha, ctx->stream));
     const TaskDev *st = s->pin_tasks;
     MBPT_HIPCHK(ctx, hipMemcpyAsync(s->pin_tasks, s->ws + s->L.tasks,
                                     s->max_slots * sizeof(TaskDev), hipMemcpyDeviceToHost,
