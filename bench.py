@@ -374,18 +374,28 @@ def serve_workload(args):
             time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
     wall = time.perf_counter() - t0
     st = M.mbpt_kernel_stats(ctx)
-    tts, waits = [], []
-    for t in tickets:
+    tts, waits, per_order = [], [], {}
+    for t, r in zip(tickets, reqs):
         res, done, ts, ta, tf = M.mbpt_server_poll(srv, t)
         tts.append(tf - ts)
         waits.append(ta - ts)
+        po = per_order.setdefault(r["order"], {"tts": [], "iters": [], "capped": 0})
+        po["tts"].append(tf - ts)
+        po["iters"].append(res.iters_done)
+        po["capped"] += int(res.n_evals >= cap)
     M.mbpt_server_destroy(srv)
     M.mbpt_context_destroy(ctx)
     out = {"served_fp32": {"Gevals_per_s": st["evals"] / wall / 1e9, "wall_s": wall,
                            "p50_time_to_sigma_s": _pct(tts, 50), "p99_time_to_sigma_s": _pct(tts, 99),
                            "p99_admission_wait_s": _pct(waits, 99), "rounds": steps,
                            "mean_in_system": float(np.mean(depth)),
-                           "kernel_busy_frac": st["kernel_ms"] * 1e-3 / wall}}
+                           "kernel_busy_frac": st["kernel_ms"] * 1e-3 / wall,
+                           "per_order": {str(o): {"requests": len(v["tts"]),
+                                                  "p50_s": _pct(v["tts"], 50),
+                                                  "p99_s": _pct(v["tts"], 99),
+                                                  "mean_iterations": float(np.mean(v["iters"])),
+                                                  "at_eval_cap": v["capped"]}
+                                         for o, v in sorted(per_order.items())}}}
     # plain path: one request at a time, fp64, one launch per iteration
     nplain = min(nreq, 200)
     ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP64, label_mode=LABEL_MODE)

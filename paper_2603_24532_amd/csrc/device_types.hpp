@@ -37,13 +37,11 @@ struct alignas(16) GroupDev {
   int first, count, coef_off;
 };
 
-// Factorised label-sum coefficient in both precisions (small integers, exact
-// in fp32).
-struct alignas(16) CoefDev {
-  double d;
-  float f;
-  float pad;
-};
+// Factorised label-sum coefficients of one isospin configuration (2^n small
+// integers) are stored as 2^n doubles followed by the same values as 2^n
+// floats packed two per double slot, so either precision loads a contiguous
+// run.
+constexpr int coef_slots(int order) { return (1 << order) + ((1 << order) + 1) / 2; }
 
 // Compressed label-sum term: multiplicity and 2-bit vertex codes
 // (0: V_d, 1: -V_e, 2: V_d - V_e).
@@ -116,7 +114,7 @@ struct KArgs {
   double *partials;       // 4 doubles per work item
   uint64_t *counters;     // kItemCounters per work item
   double *reslog;         // (I, var) pairs
-  const CoefDev *gcoef;   // factorised label-sum coefficients
+  const double *gcoef;    // factorised label-sum coefficients (see coef_slots)
   const int2 *olist;      // (first item, task), grouped by order, ascending items
   double *hf;             // HF spline entries, 4 doubles each
   int ntasks;

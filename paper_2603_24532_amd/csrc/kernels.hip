@@ -226,7 +226,8 @@ __device__ __forceinline__ double vegas_map(const KArgs &a, const TaskDev *__res
                   static_cast<uint32_t>(j), a.phys.seed, T->key, wd + 4 * j);
   // bin b = floor(w nb / 2^32), fraction ((w nb mod 2^32) + 1/2) / 2^32.
   // y = w nb 2^-32 is exact in fp64 (at most 39 significant bits), so b and the
-  // fraction come out exactly with full-rate fp64 instructions.
+  // fraction come out exactly with full-rate fp64 instructions.  The Jacobian
+  // prod_m nb width_m takes nb^ND once.
   double jac = 1.0;
   const double nbscale = static_cast<double>(nb) * 0x1p-32;
 #pragma unroll
@@ -236,10 +237,14 @@ __device__ __forceinline__ double vegas_map(const KArgs &a, const TaskDev *__res
     const int b = static_cast<int>(fb);
     const double r = (y - fb) + 0x1p-33;
     const double2 ew = g[m * nb + b];
-    x[m] = ew.x + r * ew.y;
-    jac *= static_cast<double>(nb) * ew.y;
+    x[m] = fma(r, ew.y, ew.x);
+    jac *= ew.y;
     bins[m] = b;
   }
+  double nbp = static_cast<double>(nb);
+#pragma unroll
+  for (int m = 1; m < ND; ++m) nbp *= static_cast<double>(nb);
+  jac *= nbp;
   return jac;
 }
 
@@ -280,13 +285,30 @@ template <>
 __device__ __forceinline__ float fma_t<float>(float x, float y, float z) {
   return __builtin_fmaf(x, y, z);
 }
-template <typename F>
-__device__ __forceinline__ F coef_val(const CoefDev &c) {
-  return c.d;
+// The 2^ORDER coefficients of a configuration in precision F (contiguous).
+template <int ORDER, typename F>
+__device__ __forceinline__ const F *coef_run(const double *block) {
+  return block;
 }
 template <>
-__device__ __forceinline__ float coef_val<float>(const CoefDev &c) {
-  return c.f;
+__device__ __forceinline__ const float *coef_run<1, float>(const double *block) {
+  return reinterpret_cast<const float *>(block + 2);
+}
+template <>
+__device__ __forceinline__ const float *coef_run<2, float>(const double *block) {
+  return reinterpret_cast<const float *>(block + 4);
+}
+template <>
+__device__ __forceinline__ const float *coef_run<3, float>(const double *block) {
+  return reinterpret_cast<const float *>(block + 8);
+}
+template <>
+__device__ __forceinline__ const float *coef_run<4, float>(const double *block) {
+  return reinterpret_cast<const float *>(block + 16);
+}
+template <>
+__device__ __forceinline__ const float *coef_run<5, float>(const double *block) {
+  return reinterpret_cast<const float *>(block + 32);
 }
 template <typename F>
 __device__ __forceinline__ F term_mult(const TermDev &t) {
@@ -356,13 +378,16 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
       if (Q == 4) ok = (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
       if (ok) {
         ++units;
-        const CoefDev *__restrict__ C = a.gcoef + G[gi].coef_off;
+        const F *__restrict__ C = coef_run<ORDER, F>(a.gcoef + G[gi].coef_off);
+        F c[NA * NB];  // one batch of scalar loads, then the multiply-adds
+#pragma unroll
+        for (int i = 0; i < NA * NB; ++i) c[i] = C[i];
         F gs = F(0);
 #pragma unroll
         for (int eb = 0; eb < NB; ++eb) {
           F in = F(0);
 #pragma unroll
-          for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(coef_val<F>(C[eb * NA + ea]), MA[ea], in);
+          for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(c[eb * NA + ea], MA[ea], in);
           gs = fma_t<F>(in, MB[eb], gs);
         }
         if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER>(D, tau, Dn, deps));
@@ -881,8 +906,17 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 }
 
 // One task per launch: block b processes work item item_begin + b.
+// The fifth-order fp32 kernels carry the inlined fp64 re-evaluation path on
+// top of their own state; asking for two waves per SIMD keeps them within
+// 256 VGPRs (a few spilled dwords on the re-evaluation path instead of half
+// the occupancy).
+template <int ORDER, int P>
+constexpr int min_waves() {
+  return (P == 1 && ORDER == 5) ? 2 : 1;
+}
+
 template <int ORDER, int Q, int P>
-__global__ __launch_bounds__(256) void sample_single(KArgs a, int t) {
+__global__ __launch_bounds__(256, (min_waves<ORDER, P>())) void sample_single(KArgs a, int t) {
   extern __shared__ double smem[];
   process_item<ORDER, Q, P>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
 }
@@ -893,7 +927,7 @@ __global__ __launch_bounds__(256) void sample_single(KArgs a, int t) {
 // olist[k0].x + b.  One launch per order keeps each launch's register
 // allocation that of its own order.
 template <int ORDER, int Q, int P>
-__global__ __launch_bounds__(256) void sample_order(KArgs a, int k0, int k1) {
+__global__ __launch_bounds__(256, (min_waves<ORDER, P>())) void sample_order(KArgs a, int k0, int k1) {
   extern __shared__ double smem[];
   const int2 *__restrict__ ol = a.olist;
   const int item = ol[k0].x + static_cast<int>(blockIdx.x);

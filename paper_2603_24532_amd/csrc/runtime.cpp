@@ -268,7 +268,7 @@ void fill_diag_dev(const Diagram &d, DiagDev &dd) {
 // are the device element indices at which the three vectors start, so the
 // offsets stored in the descriptor are absolute for the kernel's table bases.
 void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
-                         std::vector<TermDev> &terms, std::vector<CoefDev> &coefs,
+                         std::vector<TermDev> &terms, std::vector<double> &coefs,
                          size_t group_base, size_t term_base, size_t coef_base) {
   const LabelTables lt = label_tables(d, q);
   dd.group_off = static_cast<int>(group_base + groups.size());
@@ -282,7 +282,11 @@ void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<Group
     gd.first = static_cast<int>(t0 + g.first);
     gd.count = g.count;
     gd.coef_off = static_cast<int>(coef_base + coefs.size());
-    for (double c : g.coef) coefs.push_back(CoefDev{c, static_cast<float>(c), 0.0f});
+    const size_t n = g.coef.size(), at = coefs.size();
+    coefs.resize(at + coef_slots(d.order), 0.0);
+    std::copy(g.coef.begin(), g.coef.end(), coefs.begin() + at);
+    float *f = reinterpret_cast<float *>(coefs.data() + at + n);
+    for (size_t i = 0; i < n; ++i) f[i] = static_cast<float>(g.coef[i]);
     groups.push_back(gd);
   }
   for (const auto &t : lt.terms) {
@@ -449,7 +453,7 @@ Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, 
   L.terms = off;
   off = align256(off + std::max<size_t>(1, set->terms.size()) * sizeof(TermDev));
   L.coefs = off;
-  off = align256(off + std::max<size_t>(1, set->coefs.size()) * sizeof(CoefDev));
+  off = align256(off + std::max<size_t>(1, set->coefs.size()) * sizeof(double));
   size_t gd = 0, hd = 0;
   for (const auto &td : set->tasks) {
     gd += 3 * (td.order + 1) * (nb + 1);
@@ -564,7 +568,7 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
   set->d_diags = reinterpret_cast<DiagDev *>(base + L.diags);
   set->d_groups = reinterpret_cast<GroupDev *>(base + L.groups);
   set->d_terms = reinterpret_cast<TermDev *>(base + L.terms);
-  set->d_coefs = reinterpret_cast<CoefDev *>(base + L.coefs);
+  set->d_coefs = reinterpret_cast<double *>(base + L.coefs);
   set->d_grids = reinterpret_cast<double *>(base + L.grids);
   set->d_hists = reinterpret_cast<double *>(base + L.hists);
   set->d_partials = reinterpret_cast<double *>(base + L.partials);
@@ -589,7 +593,7 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
     HIPCHK(ctx, hipMemcpyAsync(set->d_terms, set->terms.data(), set->terms.size() * sizeof(TermDev),
                                hipMemcpyHostToDevice, ctx->stream));
   if (!set->coefs.empty())
-    HIPCHK(ctx, hipMemcpyAsync(set->d_coefs, set->coefs.data(), set->coefs.size() * sizeof(CoefDev),
+    HIPCHK(ctx, hipMemcpyAsync(set->d_coefs, set->coefs.data(), set->coefs.size() * sizeof(double),
                                hipMemcpyHostToDevice, ctx->stream));
   int rc = upload_params(set);
   if (rc) return rc;

@@ -53,7 +53,7 @@ struct mbpt_task_set {
   std::vector<mbpt::DiagDev> diags;
   std::vector<mbpt::GroupDev> groups;
   std::vector<mbpt::TermDev> terms;
-  std::vector<mbpt::CoefDev> coefs;
+  std::vector<double> coefs;        // see coef_slots
   std::vector<int> task_diag;
   std::vector<mbpt::FlopModel> flops, diag_flops;
   int max_nd = 0;
@@ -70,7 +70,7 @@ struct mbpt_task_set {
   mbpt::DiagDev *d_diags = nullptr;
   mbpt::GroupDev *d_groups = nullptr;
   mbpt::TermDev *d_terms = nullptr;
-  mbpt::CoefDev *d_coefs = nullptr;
+  double *d_coefs = nullptr;
   double *d_hf = nullptr;   // HF spline entries (2 tables per task)
   double *d_gl = nullptr;   // Gauss-Legendre rule for the HF tables
   bool hf_dirty = true;     // HF tables must be (re)computed before use
@@ -95,7 +95,7 @@ int hip_fail(mbpt_context *ctx, hipError_t e, const char *what);
 void count_flops(const Diagram &d, int q, int half_exp, int label_mode, int spectrum,
                  FlopModel &f);
 void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
-                         std::vector<TermDev> &terms, std::vector<CoefDev> &coefs,
+                         std::vector<TermDev> &terms, std::vector<double> &coefs,
                          size_t group_base, size_t term_base, size_t coef_base);
 void fill_diag_dev(const Diagram &d, DiagDev &dd);
 void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T);

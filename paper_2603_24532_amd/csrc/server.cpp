@@ -167,7 +167,7 @@ struct mbpt_server {
     DiagDev dd;
     std::vector<GroupDev> groups;
     std::vector<TermDev> terms;
-    std::vector<CoefDev> coefs;
+    std::vector<double> coefs;
     FlopModel fm;
     size_t bytes;  // arena bytes of the three tables
   };
@@ -200,7 +200,7 @@ KArgs server_kargs(const mbpt_server *s) {
   // workspace base
   a.groups = reinterpret_cast<const GroupDev *>(b);
   a.terms = reinterpret_cast<const TermDev *>(b);
-  a.gcoef = reinterpret_cast<const CoefDev *>(b);
+  a.gcoef = reinterpret_cast<const double *>(b);
   a.olist = reinterpret_cast<const int2 *>(b + s->L.olist);
   a.grids = reinterpret_cast<double *>(b + s->L.grids);
   a.hists = reinterpret_cast<double *>(b + s->L.hists);
@@ -267,7 +267,7 @@ const mbpt_server::Compiled &compiled_of(mbpt_server *s, int order, int id) {
   count_flops(*d, 4, s->ctx->v.reg_exp / 2, s->ctx->desc.label_mode, MBPT_SPECTRUM_FREE, c.fm);
   c.fm.all_units = s->ctx->desc.label_mode ? c.dd.nterms : c.dd.ngroups;
   c.bytes = a256(c.groups.size() * sizeof(GroupDev)) + a256(c.terms.size() * sizeof(TermDev)) +
-            a256(c.coefs.size() * sizeof(CoefDev));
+            a256(c.coefs.size() * sizeof(double));
   return s->compiled.emplace(key, std::move(c)).first->second;
 }
 
@@ -278,7 +278,7 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   const mbpt_server::Compiled &c = compiled_of(s, q.r.order, q.r.diagram_id);
   const size_t gbytes = a256(c.groups.size() * sizeof(GroupDev));
   const size_t tbytes = a256(c.terms.size() * sizeof(TermDev));
-  const size_t need_bytes = gbytes + tbytes + a256(c.coefs.size() * sizeof(CoefDev));
+  const size_t need_bytes = gbytes + tbytes + a256(c.coefs.size() * sizeof(double));
   const size_t need_items = items_of(q.r.samples_per_iter);
   // staging: tables (arena image), descriptor, task record
   const size_t stage_need = need_bytes + a256(sizeof(DiagDev)) + a256(sizeof(TaskDev));
@@ -300,7 +300,7 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   const size_t c_off = t_off + tbytes;
   const int g_index = static_cast<int>(g_off / sizeof(GroupDev));
   const int t_index = static_cast<int>(t_off / sizeof(TermDev));
-  const int c_index = static_cast<int>(c_off / sizeof(CoefDev));
+  const int c_index = static_cast<int>(c_off / sizeof(double));
   char *st = s->stage + s->stage_used;
   auto *sg = reinterpret_cast<GroupDev *>(st);
   for (size_t i = 0; i < c.groups.size(); ++i) {
@@ -309,7 +309,7 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
     sg[i].coef_off += c_index;
   }
   std::memcpy(st + gbytes, c.terms.data(), c.terms.size() * sizeof(TermDev));
-  std::memcpy(st + gbytes + tbytes, c.coefs.data(), c.coefs.size() * sizeof(CoefDev));
+  std::memcpy(st + gbytes + tbytes, c.coefs.data(), c.coefs.size() * sizeof(double));
   auto *sd = reinterpret_cast<DiagDev *>(st + need_bytes);
   *sd = c.dd;
   sd->group_off += g_index;
