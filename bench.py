@@ -346,56 +346,67 @@ def serve_workload(args):
                          rel=float(rng.uniform(0.001, 0.01))))
     samples, floor, cap = 1 << 18, 1e-3, 1 << 25
     torch_stream = torch.cuda.Stream()
-    ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP32, label_mode=LABEL_MODE)
-    slots = 512
-    nbytes = M.mbpt_server_workspace_query(ctx, slots, samples)
-    buf, ptr = M.device_workspace(nbytes)
-    srv = M.mbpt_server_create(ctx, slots, samples, nreq + 1, ptr, nbytes)
-    M.mbpt_kernel_stats(ctx)
-    tickets = [None] * nreq
-    t0 = time.perf_counter()
-    nxt, depth, steps = 0, [], 0
-    while True:
-        now = time.perf_counter() - t0
-        while nxt < nreq and arrivals[nxt] <= now:
-            r = reqs[nxt]
-            tickets[nxt] = M.mbpt_server_submit(srv, r["order"], r["did"], M.MBPT_NUCLEAR, r["n"],
-                                                r["x"], r["rel"], floor, samples, cap)
-            nxt += 1
-        na, nq = M.mbpt_server_step(srv)
-        steps += 1
-        if steps % 200 == 0:
-            print(f"[serve] t={now:.1f}s submitted={nxt} resident={na} queued={nq}",
-                  file=sys.stderr, flush=True)
-        depth.append(na + nq)
-        if nxt == nreq and na == 0 and nq == 0:
-            break
-        if na == 0 and nq == 0 and nxt < nreq:
-            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
-    wall = time.perf_counter() - t0
-    st = M.mbpt_kernel_stats(ctx)
-    tts, waits, per_order = [], [], {}
-    for t, r in zip(tickets, reqs):
-        res, done, ts, ta, tf = M.mbpt_server_poll(srv, t)
-        tts.append(tf - ts)
-        waits.append(ta - ts)
-        po = per_order.setdefault(r["order"], {"tts": [], "iters": [], "capped": 0})
-        po["tts"].append(tf - ts)
-        po["iters"].append(res.iters_done)
-        po["capped"] += int(res.n_evals >= cap)
-    M.mbpt_server_destroy(srv)
-    M.mbpt_context_destroy(ctx)
-    out = {"served_fp32": {"Gevals_per_s": st["evals"] / wall / 1e9, "wall_s": wall,
-                           "p50_time_to_sigma_s": _pct(tts, 50), "p99_time_to_sigma_s": _pct(tts, 99),
-                           "p99_admission_wait_s": _pct(waits, 99), "rounds": steps,
-                           "mean_in_system": float(np.mean(depth)),
-                           "kernel_busy_frac": st["kernel_ms"] * 1e-3 / wall,
-                           "per_order": {str(o): {"requests": len(v["tts"]),
-                                                  "p50_s": _pct(v["tts"], 50),
-                                                  "p99_s": _pct(v["tts"], 99),
-                                                  "mean_iterations": float(np.mean(v["iters"])),
-                                                  "at_eval_cap": v["capped"]}
-                                         for o, v in sorted(per_order.items())}}}
+
+    def served(warm_dn, label):
+        ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP32,
+                                    label_mode=LABEL_MODE)
+        slots = 512
+        nbytes = M.mbpt_server_workspace_query(ctx, slots, samples)
+        buf, ptr = M.device_workspace(nbytes)
+        srv = M.mbpt_server_create(ctx, slots, samples, nreq + 1, ptr, nbytes)
+        if warm_dn > 0:
+            M.mbpt_server_set_warm_start(srv, warm_dn, 0.1)
+        M.mbpt_kernel_stats(ctx)
+        tickets = [None] * nreq
+        t0 = time.perf_counter()
+        nxt, depth, steps = 0, [], 0
+        while True:
+            now = time.perf_counter() - t0
+            while nxt < nreq and arrivals[nxt] <= now:
+                r = reqs[nxt]
+                tickets[nxt] = M.mbpt_server_submit(srv, r["order"], r["did"], M.MBPT_NUCLEAR,
+                                                    r["n"], r["x"], r["rel"], floor, samples, cap)
+                nxt += 1
+            na, nq = M.mbpt_server_step(srv)
+            steps += 1
+            if steps % 200 == 0:
+                print(f"[serve {label}] t={now:.1f}s submitted={nxt} resident={na} queued={nq}",
+                      file=sys.stderr, flush=True)
+            depth.append(na + nq)
+            if nxt == nreq and na == 0 and nq == 0:
+                break
+            if na == 0 and nq == 0 and nxt < nreq:
+                time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+        wall = time.perf_counter() - t0
+        st = M.mbpt_kernel_stats(ctx)
+        tts, waits, per_order = [], [], {}
+        for t, r in zip(tickets, reqs):
+            res, done, ts, ta, tf = M.mbpt_server_poll(srv, t)
+            tts.append(tf - ts)
+            waits.append(ta - ts)
+            po = per_order.setdefault(r["order"], {"tts": [], "iters": [], "capped": 0})
+            po["tts"].append(tf - ts)
+            po["iters"].append(res.iters_done)
+            po["capped"] += int(res.n_evals >= cap)
+        warm = M.mbpt_server_warm_starts(srv)
+        M.mbpt_server_destroy(srv)
+        M.mbpt_context_destroy(ctx)
+        return tts, {"Gevals_per_s": st["evals"] / wall / 1e9, "wall_s": wall,
+                     "p50_time_to_sigma_s": _pct(tts, 50), "p99_time_to_sigma_s": _pct(tts, 99),
+                     "p99_admission_wait_s": _pct(waits, 99), "steps": steps,
+                     "mean_in_system": float(np.mean(depth)),
+                     "kernel_busy_frac": st["kernel_ms"] * 1e-3 / wall,
+                     "warm_starts": warm,
+                     "per_order": {str(o): {"requests": len(v["tts"]),
+                                            "p50_s": _pct(v["tts"], 50),
+                                            "p99_s": _pct(v["tts"], 99),
+                                            "mean_iterations": float(np.mean(v["iters"])),
+                                            "at_eval_cap": v["capped"]}
+                                   for o, v in sorted(per_order.items())}}
+
+    tts, out_cold = served(0.0, "cold")
+    _, out_warm = served(0.02, "warm")
+    out = {"served_fp32": out_cold, "served_fp32_warm_start_dn0.02_dx0.1": out_warm}
     # plain path: one request at a time, fp64, one launch per iteration
     nplain = min(nreq, 200)
     ctx = M.mbpt_context_create(stream=torch_stream.cuda_stream, precision=M.MBPT_FP64, label_mode=LABEL_MODE)

@@ -274,11 +274,16 @@ int mbpt_task_flops(const mbpt_task_set *set, int task, double *flops, double *t
 /* A server owns one device workspace (caller-owned, size from
  * mbpt_server_workspace_query) holding up to max_slots resident tasks.
  * Requests queue on submit; mbpt_server_step admits queued requests into free
- * slots (by slot count and workspace bytes), runs one VEGAS iteration for
- * every resident task in one persistent launch, and retires tasks whose sigma
- * reached max(sigma_rel |E|, sigma_abs) or whose evaluations reached
- * max_evals.  A request's random stream is keyed by its ticket, so its result
- * does not depend on what else is resident. */
+ * slots (by slot count and workspace bytes), runs for every resident task the
+ * VEGAS iterations its own estimates predict it still needs (the first three
+ * at once, then ceil(k ((sigma/target)^2 - 1)), at most 32, within max_evals;
+ * one launch per order present per iteration, one host synchronisation per
+ * step), and retires tasks whose sigma reached max(sigma_rel |E|, sigma_abs)
+ * (after at least three iterations) or whose evaluations reached max_evals.
+ * A request's random stream is keyed by its ticket and its iteration plan by
+ * its own state, so its result does not depend on what else is resident
+ * (unless warm starts are on, see mbpt_server_set_warm_start).  The server
+ * takes the free spectrum only (EINVAL / ESTATE with HF). */
 typedef struct mbpt_request {
   int order;
   int diagram_id;
@@ -298,10 +303,22 @@ int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max_samples_pe
 void mbpt_server_destroy(mbpt_server *srv);
 /* Queue a request; *ticket identifies it.  EBUSY if the queue is full. */
 int mbpt_server_submit(mbpt_server *srv, const mbpt_request *req, uint64_t *ticket);
-/* One scheduling round (admit, one iteration for all resident tasks, retire).
+/* One scheduling step (admit, the planned iterations of all resident tasks,
+ * retire).
  * *n_active receives the resident count after the round, *n_queued the queue
  * length. */
 int mbpt_server_step(mbpt_server *srv, int *n_active, int *n_queued);
+/* Warm start across EOS points (off by default): a newly admitted request
+ * whose (order, diagram, matter) matches one retired earlier within
+ * |n - n'| <= max_dn [fm^-3] and |x - x'| <= max_dx starts from the nearest
+ * such request's adapted VEGAS grid instead of the uniform one (the hypercube
+ * variables are scaled by the Fermi momenta, so neighbouring EOS points need
+ * nearly the same grid).  The server keeps the grids of its last max_slots
+ * retirements in its workspace.  With warm starts on, a result depends on
+ * which requests retired before it was admitted.  max_dn <= 0 switches it
+ * off.  *count of mbpt_server_warm_starts: admissions that started warm. */
+int mbpt_server_set_warm_start(mbpt_server *srv, double max_dn, double max_dx);
+int mbpt_server_warm_starts(const mbpt_server *srv, uint64_t *count);
 /* Result of a ticket: *done = 1 once retired (result valid), else 0 (result
  * holds the running estimate if resident).  Times are host wall-clock seconds
  * from the server's creation: submit, admit and finish. */

@@ -25,6 +25,7 @@ EXPORTED = [
     "mbpt_context_create", "mbpt_context_destroy", "mbpt_last_error", "mbpt_set_interaction",
     "mbpt_set_precision", "mbpt_num_diagrams", "mbpt_diagram_matrix", "mbpt_diagram_label_stats",
     "mbpt_diagram_label_poly", "mbpt_set_spectrum", "mbpt_hf_nodes",
+    "mbpt_server_set_warm_start", "mbpt_server_warm_starts",
     "mbpt_create_task_set", "mbpt_create_diagram_set", "mbpt_task_set_destroy", "mbpt_task_count",
     "mbpt_set_density", "mbpt_set_asymmetry", "mbpt_set_launch_mode", "mbpt_set_blocking",
     "mbpt_workspace_query", "mbpt_bind_workspace", "mbpt_reset", "mbpt_integrate",
@@ -136,6 +137,8 @@ def lib():
         "mbpt_server_destroy": [_P],
         "mbpt_server_submit": [_P, ctypes.POINTER(mbpt_request), ctypes.POINTER(ctypes.c_uint64)],
         "mbpt_server_step": [_P, _IP, _IP],
+        "mbpt_server_set_warm_start": [_P, ctypes.c_double, ctypes.c_double],
+        "mbpt_server_warm_starts": [_P, ctypes.POINTER(ctypes.c_uint64)],
         "mbpt_server_poll": [_P, ctypes.c_uint64, ctypes.POINTER(mbpt_result), _IP, _DP, _DP,
                              _DP],
     }
@@ -398,6 +401,16 @@ def mbpt_server_step(srv):
     a, q = ctypes.c_int(), ctypes.c_int()
     _check(lib().mbpt_server_step(srv, ctypes.byref(a), ctypes.byref(q)), _srv_ctx.get(srv))
     return a.value, q.value
+
+
+def mbpt_server_set_warm_start(srv, max_dn, max_dx):
+    _check(lib().mbpt_server_set_warm_start(srv, max_dn, max_dx))
+
+
+def mbpt_server_warm_starts(srv):
+    n = ctypes.c_uint64()
+    _check(lib().mbpt_server_warm_starts(srv, ctypes.byref(n)))
+    return n.value
 
 
 def mbpt_server_poll(srv, ticket):

@@ -433,12 +433,24 @@ size_t items_for(const mbpt_task_set *set, uint64_t samples) {
   return static_cast<size_t>((samples + chunk - 1) / chunk);
 }
 
+// Samples per thread unless set explicitly: a task's max_samples spread over
+// about two blocks per CU (one task's iteration lasts as long as its slowest
+// block), between 1 and 16.
+int auto_spt(const mbpt_task_set *set, uint64_t max_samples) {
+  const uint64_t per = static_cast<uint64_t>(set->block) * 2 * std::max(1, set->ctx->num_cus);
+  return static_cast<int>(std::max<uint64_t>(1, std::min<uint64_t>(16, max_samples / per)));
+}
+
 struct Layout {
   size_t tasks, olist, diags, groups, terms, coefs, grids, hists, partials, counters, reslog, hf,
       gl, total;
 };
 
 Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, int nb) {
+  // item capacity for the blocking the set will have once bound
+  const uint64_t chunk = static_cast<uint64_t>(set->block) *
+                         (set->blocking_auto ? auto_spt(set, max_samples) : set->spt);
+  const size_t items_per_task = static_cast<size_t>((max_samples + chunk - 1) / chunk);
   Layout L{};
   size_t off = 0;
   const size_t nt = set->tasks.size();
@@ -463,7 +475,7 @@ Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, 
   off = align256(off + gd * sizeof(double));
   L.hists = off;
   off = align256(off + hd * sizeof(double));
-  const size_t items = nt * items_for(set, max_samples);
+  const size_t items = nt * items_per_task;
   L.partials = off;
   off = align256(off + items * 4 * sizeof(double));
   L.counters = off;
@@ -562,6 +574,7 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
   set->ws_bytes = bytes;
   set->max_samples = max_samples;
   set->max_iters = max_iters;
+  if (set->blocking_auto) set->spt = auto_spt(set, max_samples);
   set->max_items = set->tasks.size() * items_for(set, max_samples);
   set->d_tasks = reinterpret_cast<TaskDev *>(base + L.tasks);
   set->d_olist = reinterpret_cast<int2 *>(base + L.olist);
@@ -775,6 +788,7 @@ extern "C" int mbpt_set_blocking(mbpt_task_set *set, int threads_per_block, int 
   }
   set->block = threads_per_block;
   set->spt = samples_per_thread;
+  set->blocking_auto = false;
   set->drop_graph();
   set->oranges.clear();
   return MBPT_OK;

@@ -50,6 +50,7 @@ struct mbpt_task_set {
   std::vector<mbpt_task_desc> tasks;
   int launch_mode = MBPT_LAUNCH_PER_TASK;
   int block = 256, spt = 16;
+  bool blocking_auto = true;  // spt chosen at bind from the sample count
   std::vector<mbpt::DiagDev> diags;
   std::vector<mbpt::GroupDev> groups;
   std::vector<mbpt::TermDev> terms;

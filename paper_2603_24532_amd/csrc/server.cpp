@@ -40,7 +40,7 @@ namespace {
 constexpr int kMinIters = 3;
 constexpr int kMaxPlan = 32;  // iterations per step at most
 constexpr int kBlock = 256;
-constexpr int kSpt = 16;
+constexpr int kMaxSpt = 16;
 constexpr size_t kTermBytesPerSlot = 64 * 1024;
 
 size_t a256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -92,7 +92,7 @@ struct Req {
 };
 
 struct Layout {
-  size_t tasks, olist, diags, grids, hists, reslog, partials, counters, arena, arena_bytes;
+  size_t tasks, olist, diags, grids, hists, reslog, cache, partials, counters, arena, arena_bytes;
   size_t max_items;
 };
 
@@ -101,8 +101,17 @@ struct Layout {
 // is reused once the step's closing synchronisation has passed.
 constexpr size_t kStageBytes = 4u << 20;
 
-size_t items_of(uint64_t samples) {
-  const uint64_t chunk = static_cast<uint64_t>(kBlock) * kSpt;
+// Samples per thread of a server's work items: requests of up to
+// max_samples_per_iter samples should still spread over about two blocks per
+// CU (a request's iteration latency is that of its slowest block), up to 16.
+int server_spt(const mbpt_context *ctx, uint64_t max_samples) {
+  const uint64_t per = static_cast<uint64_t>(kBlock) * 2 * std::max(1, ctx->num_cus);
+  const uint64_t spt = max_samples / per;
+  return static_cast<int>(std::max<uint64_t>(1, std::min<uint64_t>(kMaxSpt, spt)));
+}
+
+size_t items_of(uint64_t samples, int spt) {
+  const uint64_t chunk = static_cast<uint64_t>(kBlock) * spt;
   return static_cast<size_t>((samples + chunk - 1) / chunk);
 }
 
@@ -111,7 +120,8 @@ size_t slot_table_bytes(int slots, int nb) {
          a256(slots * sizeof(DiagDev)) +
          a256(static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double)) +
          a256(static_cast<size_t>(slots) * kMaxDim * nb * sizeof(double)) +
-         a256(static_cast<size_t>(slots) * 2 * sizeof(double));
+         a256(static_cast<size_t>(slots) * 2 * sizeof(double)) +
+         a256(static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double));
 }
 
 // Slot table first, then the term arena (kTermBytesPerSlot per slot), then
@@ -130,6 +140,8 @@ bool make_layout(int slots, int nb, size_t bytes, Layout &L) {
   off = a256(off + static_cast<size_t>(slots) * kMaxDim * nb * sizeof(double));
   L.reslog = off;
   off = a256(off + static_cast<size_t>(slots) * 2 * sizeof(double));
+  L.cache = off;  // grids of recent retirements (warm starts)
+  off = a256(off + static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double));
   L.arena = off;
   L.arena_bytes = static_cast<size_t>(slots) * kTermBytesPerSlot;
   off += L.arena_bytes;
@@ -151,6 +163,7 @@ double now_s(std::chrono::steady_clock::time_point t0) {
 struct mbpt_server {
   mbpt_context *ctx = nullptr;
   int max_slots = 0, max_queue = 0;
+  int spt = 16;  // samples per thread of the work items (server_spt)
   uint64_t max_samples = 0;
   char *ws = nullptr;
   Layout L{};
@@ -180,6 +193,16 @@ struct mbpt_server {
   std::vector<int2> olist;
   std::vector<OrderRange> ranges;
   std::vector<int> admitted;      // slots admitted in the current step
+  // warm starts: grids of recent retirements, one cache entry per slot
+  struct CacheEntry {
+    bool valid = false;
+    int order = 0, id = 0, matter = 0;
+    double density = 0.0, x = 0.0;
+    uint64_t stamp = 0;
+  };
+  std::vector<CacheEntry> cache;
+  uint64_t cache_clock = 0, warm_starts = 0;
+  double warm_dn = 0.0, warm_dx = 0.0;
   ~mbpt_server() {
     if (ctx) (void)hipStreamSynchronize(ctx->stream);
     if (stage) (void)hipHostFree(stage);
@@ -208,7 +231,7 @@ KArgs server_kargs(const mbpt_server *s) {
   a.counters = reinterpret_cast<uint64_t *>(b + s->L.counters);
   a.reslog = reinterpret_cast<double *>(b + s->L.reslog);
   a.ntasks = s->max_slots;
-  a.spt = kSpt;
+  a.spt = s->spt;
   a.label_mode = ctx->desc.label_mode;
   const mbpt_interaction &v = ctx->v;
   a.phys.V0 = v.C0 * v.hbarc;
@@ -279,7 +302,7 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   const size_t gbytes = a256(c.groups.size() * sizeof(GroupDev));
   const size_t tbytes = a256(c.terms.size() * sizeof(TermDev));
   const size_t need_bytes = gbytes + tbytes + a256(c.coefs.size() * sizeof(double));
-  const size_t need_items = items_of(q.r.samples_per_iter);
+  const size_t need_items = items_of(q.r.samples_per_iter, s->spt);
   // staging: tables (arena image), descriptor, task record
   const size_t stage_need = need_bytes + a256(sizeof(DiagDev)) + a256(sizeof(TaskDev));
   if (s->stage_used + stage_need > kStageBytes) return 1;  // next step
@@ -342,6 +365,33 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
                                   hipMemcpyHostToDevice, ctx->stream));
   KArgs a = server_kargs(s);
   MBPT_HIPCHK(ctx, launch_init(a, slot, 1, ctx->stream));
+  if (s->warm_dn > 0.0) {
+    // nearest retired grid of the same diagram and matter within the window
+    int best = -1;
+    double best_d = 0.0;
+    const int matter = q.r.matter;
+    for (int e = 0; e < static_cast<int>(s->cache.size()); ++e) {
+      const auto &ce = s->cache[e];
+      if (!ce.valid || ce.order != q.r.order || ce.id != q.r.diagram_id || ce.matter != matter)
+        continue;
+      const double dn = std::fabs(ce.density - q.r.density), dx = std::fabs(ce.x - q.r.proton_fraction);
+      if (dn > s->warm_dn || dx > s->warm_dx) continue;
+      const double dist = dn / s->warm_dn + (s->warm_dx > 0.0 ? dx / s->warm_dx : 0.0);
+      if (best < 0 || dist < best_d) {
+        best = e;
+        best_d = dist;
+      }
+    }
+    if (best >= 0) {
+      const size_t gbytes = static_cast<size_t>(d->ndim) * (ctx->desc.n_bins + 1) * sizeof(double);
+      MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.grids + T.grid_off * sizeof(double),
+                                      b + s->L.cache + best * kMaxDim * (ctx->desc.n_bins + 1) *
+                                                           sizeof(double),
+                                      gbytes, hipMemcpyDeviceToDevice, ctx->stream));
+      s->cache[best].stamp = ++s->cache_clock;
+      ++s->warm_starts;
+    }
+  }
   s->stage_used += stage_need;
   s->flops[slot] = c.fm;
   q.state = 1;
@@ -359,7 +409,9 @@ extern "C" int mbpt_server_workspace_query(const mbpt_context *ctx, int max_slot
   const size_t per_item = 4 * sizeof(double) + kItemCounters * sizeof(uint64_t);
   *bytes = slot_table_bytes(max_slots, ctx->desc.n_bins) +
            static_cast<size_t>(max_slots) * kTermBytesPerSlot +
-           static_cast<size_t>(max_slots) * items_of(max_samples_per_iter) * per_item + 2048;
+           static_cast<size_t>(max_slots) *
+               items_of(max_samples_per_iter, server_spt(ctx, max_samples_per_iter)) * per_item +
+           2048;
   return MBPT_OK;
 }
 
@@ -376,7 +428,7 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
   }
   Layout L{};
   if (!make_layout(max_slots, ctx->desc.n_bins, bytes, L) ||
-      L.max_items < items_of(max_samples_per_iter)) {
+      L.max_items < items_of(max_samples_per_iter, server_spt(ctx, max_samples_per_iter))) {
     set_err(ctx, "server_create: workspace too small for the slot table and one request");
     return MBPT_ENOMEM;
   }
@@ -385,11 +437,13 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
   s->max_slots = max_slots;
   s->max_queue = max_queue;
   s->max_samples = max_samples_per_iter;
+  s->spt = server_spt(ctx, max_samples_per_iter);
   s->ws = static_cast<char *>(device_ptr);
   s->L = L;
   s->items.init(0, L.max_items);
   s->bytes.init(0, L.arena_bytes);
   s->slot_req.assign(max_slots, -1);
+  s->cache.assign(max_slots, mbpt_server::CacheEntry{});
   s->h_tasks.assign(max_slots, TaskDev{});
   s->flops.assign(max_slots, FlopModel{});
   s->t0 = std::chrono::steady_clock::now();
@@ -544,6 +598,26 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
       if (converged || capped || !std::isfinite(q.res.E_per_A)) {
         q.state = 2;
         q.t_finish = t;
+        if (s->warm_dn > 0.0 && S.it_done >= kMinIters && std::isfinite(q.res.E_per_A)) {
+          // keep the adapted grid: replace the least recently used entry
+          int e = 0;
+          for (int k = 1; k < static_cast<int>(s->cache.size()); ++k)
+            if (!s->cache[k].valid || (s->cache[e].valid && s->cache[k].stamp < s->cache[e].stamp))
+              e = k;
+          auto &ce = s->cache[e];
+          ce.valid = true;
+          ce.order = q.r.order;
+          ce.id = q.r.diagram_id;
+          ce.matter = q.r.matter;
+          ce.density = q.r.density;
+          ce.x = q.r.proton_fraction;
+          ce.stamp = ++s->cache_clock;
+          const size_t gbytes = static_cast<size_t>(S.nd) * (ctx->desc.n_bins + 1) * sizeof(double);
+          MBPT_HIPCHK(ctx, hipMemcpyAsync(
+                               s->ws + s->L.cache + e * kMaxDim * (ctx->desc.n_bins + 1) * sizeof(double),
+                               s->ws + s->L.grids + S.grid_off * sizeof(double), gbytes,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+        }
         s->bytes.release(q.byte_at, q.byte_n);
         s->items.release(q.item_at, q.item_n);
         s->slot_req[i] = -1;
@@ -557,6 +631,19 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
   for (int i = 0; i < s->max_slots; ++i) na += s->slot_req[i] >= 0;
   if (n_active) *n_active = na;
   if (n_queued) *n_queued = static_cast<int>(s->queue.size());
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_server_set_warm_start(mbpt_server *s, double max_dn, double max_dx) {
+  if (!s || !(max_dx >= 0.0) || std::isnan(max_dn)) return MBPT_EINVAL;
+  s->warm_dn = max_dn > 0.0 ? max_dn : 0.0;
+  s->warm_dx = max_dx;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_server_warm_starts(const mbpt_server *s, uint64_t *count) {
+  if (!s || !count) return MBPT_EINVAL;
+  *count = s->warm_starts;
   return MBPT_OK;
 }
 

@@ -91,11 +91,16 @@ def test_alone_equals_in_the_mix(M):
 def test_admission_is_limited_by_memory(M):
     """A workspace that holds one request's work items at a time: the second
     request waits in the queue and is admitted after the first retires."""
+    import torch
     samples = 1 << 16
     ctx = M.mbpt_context_create()
     full = M.mbpt_server_workspace_query(ctx, 4, samples)
-    one = (samples + 4095) // 4096 * 56  # partial sums + counters of one request
     M.mbpt_context_destroy(ctx)
+    # work items of one request (blocks of 256 threads; samples per thread
+    # chosen so that a request spreads over about two blocks per CU, 1..16)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    spt = max(1, min(16, samples // (256 * 2 * cus)))
+    one = -(-samples // (256 * spt)) * 56  # partial sums + counters of one request
     # the query is slot table + term arena + 4 requests' items + 2048 slack;
     # keep room for the items of one request only
     nbytes = (full - 4 * one - 2048) + 512 + one + 300
@@ -134,3 +139,44 @@ def test_server_matches_task_set_stream(M):
         run.close()
     assert rs.iters_done == 5
     assert per[0].E_per_A == pytest.approx(rs.E_per_A, rel=1e-9)
+
+
+def test_warm_start_from_neighbouring_eos_point(M):
+    """A request retired at n = 0.16 seeds the grid of the same diagram at
+    n = 0.17: after the same three iterations its sigma is well below that of
+    the same request started from the uniform grid, and both estimates agree
+    within their combined sigma."""
+    base = (2, 0, 1, 0.16, 0.3, 0.0005, 1e-6, 1 << 15, 24 * (1 << 15))
+    probe = (2, 0, 1, 0.17, 0.3, 0.0, 0.0, 1 << 15, 3 * (1 << 15))
+    warm = Server(M)
+    cold = Server(M)
+    try:
+        M.mbpt_server_set_warm_start(warm.srv, 0.02, 0.05)
+        M.mbpt_server_submit(warm.srv, *base)
+        warm.run()
+        assert M.mbpt_server_warm_starts(warm.srv) == 0
+        tw = M.mbpt_server_submit(warm.srv, *probe)
+        warm.run()
+        assert M.mbpt_server_warm_starts(warm.srv) == 1
+        tc = M.mbpt_server_submit(cold.srv, *probe)
+        cold.run()
+        rw, *_ = M.mbpt_server_poll(warm.srv, tw)
+        rc, *_ = M.mbpt_server_poll(cold.srv, tc)
+    finally:
+        warm.close()
+        cold.close()
+    assert rw.iters_done == rc.iters_done == 3
+    assert rw.sigma < 0.7 * rc.sigma, (rw.sigma, rc.sigma)
+    assert abs(rw.E_per_A - rc.E_per_A) < 3 * (rw.sigma ** 2 + rc.sigma ** 2) ** 0.5
+    # outside the window (and for another diagram) nothing is reused
+    far = Server(M)
+    try:
+        M.mbpt_server_set_warm_start(far.srv, 0.005, 0.05)
+        M.mbpt_server_submit(far.srv, *base)
+        far.run()
+        M.mbpt_server_submit(far.srv, *probe)
+        M.mbpt_server_submit(far.srv, 3, 0, 1, 0.16, 0.3, 0.0, 0.0, 1 << 15, 3 * (1 << 15))
+        far.run()
+        assert M.mbpt_server_warm_starts(far.srv) == 0
+    finally:
+        far.close()
