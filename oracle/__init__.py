@@ -61,6 +61,7 @@ class Problem(ctypes.Structure):
         ("label_method", ctypes.c_int),
         ("spectrum", ctypes.c_int), ("hf_n", ctypes.c_int), ("hf_kmax", ctypes.c_double),
         ("hf_y", ctypes.POINTER(ctypes.c_double)), ("hf_m", ctypes.POINTER(ctypes.c_double)),
+        ("group", ctypes.c_int),
     ]
 
 
@@ -104,6 +105,9 @@ def lib():
         L.orc_spline_flat_ends.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
         L.orc_hf_spline_eval.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_double]
         L.orc_hf_spline_eval.restype = ctypes.c_double
+        L.orc_group_members.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.c_int]
+        L.orc_eval_x.argtypes = [ctypes.POINTER(Problem), dp, ctypes.c_uint64, dp]
         L.orc_map_samples.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_uint32,
                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                       ctypes.c_uint64, dp, dp, ctypes.POINTER(ctypes.c_int)]
@@ -135,7 +139,9 @@ HF_GAUSS = 64
 
 
 def problem(order, diagram_id=0, density=0.08, proton_fraction=0.0, q=2, seed=1,
-            task_key=0, label_method=0, spectrum=0, **kw):
+            task_key=0, label_method=0, spectrum=0, group=-1, **kw):
+    """group >= 0: the order's diagrams with that many particle-carried loops,
+    integrated as one summed integrand (diagram_id is then unused)."""
     p = dict(DEFAULTS)
     p.update(kw)
     pb = Problem(order=order, diagram_id=diagram_id, q=q, density=density,
@@ -143,12 +149,41 @@ def problem(order, diagram_id=0, density=0.08, proton_fraction=0.0, q=2, seed=1,
                  Lambda=p["Lambda"], reg_exp=p["reg_exp"], hbar2_m=p["hbar2_m"],
                  hbarc=p["hbarc"], n_bins=p["n_bins"], alpha=p["alpha"],
                  kcut_extra=p["kcut_extra"], seed=seed, task_key=task_key,
-                 label_method=label_method, spectrum=spectrum)
+                 label_method=label_method, spectrum=spectrum, group=group)
     if spectrum:
         if q == 4 and label_method != 0:
             raise ValueError("HF spectrum in nuclear matter needs the brute-force label sum")
         hf_tables(pb)
     return pb
+
+
+def group_members(order, p):
+    """Ids of the order's diagrams with p particle-carried loops."""
+    n = lib().orc_group_members(order, p, None, 0)
+    ids = (ctypes.c_int * max(1, n))()
+    lib().orc_group_members(order, p, ids, n)
+    return list(ids[:n])
+
+
+def groups(order):
+    """{p: member ids} over the p values present at this order."""
+    out = {}
+    for p in range(order + 2):
+        m = group_members(order, p)
+        if m:
+            out[p] = m
+    return out
+
+
+def eval_x(pb, x):
+    """Integrand (sphere Jacobian included, no VEGAS Jacobian) at hypercube
+    points x of shape (count, 3 (order + 1))."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(x.shape[0])
+    rc = lib().orc_eval_x(ctypes.byref(pb), _dp(x), x.shape[0], _dp(out))
+    if rc:
+        raise ValueError(f"orc_eval_x -> {rc}")
+    return out
 
 
 def hf_sigma(pb, tau, k, ng=HF_GAUSS):

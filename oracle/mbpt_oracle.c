@@ -395,7 +395,9 @@ typedef struct {
   int hf_n;               /* HF: spline intervals on [0, hf_kmax] */
   double hf_kmax;         /* HF: table range; Sigma = its last node value beyond */
   const double *hf_y;     /* HF: Sigma_tau(k_i), tau = n then p, 2 x (hf_n + 1) */
-  const double *hf_m;     /* HF: natural-spline second derivatives, same layout */
+  const double *hf_m;     /* HF: spline second derivatives, same layout */
+  int group;              /* -1: diagram_id alone; p >= 0: the group of the order's
+                             diagrams with p particle-carried loops (diagram_id unused) */
 } orc_problem;
 
 typedef struct {
@@ -784,6 +786,106 @@ static double phys_eval(const void *ctx, const double *x, double *wcond) {
   return jac * pt.f;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Diagram groups                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Particle-carried loops of a diagram: the loop momenta whose carrying line
+ * is a particle line.  With the spanning forest built particle lines first
+ * this is the cycle rank of the particle-line subgraph, a property of the
+ * diagram; grouping by it is this implementation's reading of the paper's
+ * grouping by particle-hole composition (it gives 1, 2, 4, 5 groups at orders
+ * 2..5, as Table I's N_grp). */
+static int particle_loops(const orc_diagram *d) {
+  int p = 0;
+  for (int j = 0; j < d->nloops; ++j) p += d->is_particle[d->loop_line[j]] ? 1 : 0;
+  return p;
+}
+
+/* Ids of the diagrams of `order` with p particle-carried loops, ascending;
+ * returns their number (ids written up to cap). */
+int orc_group_members(int order, int p, int *ids, int cap) {
+  int n = 0, nd = orc_num_diagrams(order);
+  for (int i = 0; i < nd; ++i) {
+    orc_diagram d;
+    if (orc_get_diagram(order, i, &d)) return -1;
+    if (particle_loops(&d) != p) continue;
+    if (ids && n < cap) ids[n] = i;
+    ++n;
+  }
+  return n;
+}
+
+/* A group's integrand at hypercube point x: the members' integrands summed,
+ * each member's loop momenta taken in the canonical order -- its particle
+ * loops first, then its hole loops, each in its own order -- so that loop c
+ * has the radius of a particle loop for c < p and of a hole loop otherwise. */
+typedef struct {
+  const orc_problem *pb;
+  const orc_medium *md;
+  int n, p, L;
+  orc_diagram *d;            /* n members */
+  int (*canon)[ORC_MAXLOOPS]; /* canon[i][c] = member i's loop at canonical slot c */
+} group_ctx;
+
+static double group_eval(const void *ctx, const double *x, double *wcond) {
+  const group_ctx *g = (const group_ctx *)ctx;
+  double kc[ORC_MAXLOOPS][3], jac = 1.0;
+  for (int c = 0; c < g->L; ++c) {
+    double R = c < g->p ? g->md->Rpart : g->md->Rhole;
+    double rad = R * x[3 * c];
+    double ct = 2.0 * x[3 * c + 1] - 1.0;
+    double st = sqrt(fmax(0.0, (1.0 - ct) * (1.0 + ct)));
+    double ph = 2.0 * M_PI * x[3 * c + 2];
+    kc[c][0] = rad * st * cos(ph);
+    kc[c][1] = rad * st * sin(ph);
+    kc[c][2] = rad * ct;
+    jac *= R * rad * rad * 2.0 * (2.0 * M_PI);
+  }
+  double f = 0.0, wc = 0.0;
+  for (int i = 0; i < g->n; ++i) {
+    double kl[ORC_MAXLOOPS][3];
+    for (int c = 0; c < g->L; ++c)
+      for (int a = 0; a < 3; ++a) kl[g->canon[i][c]][a] = kc[c][a];
+    orc_point pt;
+    eval_point(g->pb, &g->d[i], g->md, (const double(*)[3])kl, &pt);
+    f += pt.f;
+    wc += pt.wcond;
+  }
+  if (wcond) *wcond = fabs(jac) * wc;
+  return jac * f;
+}
+
+/* Members and canonical loop orders of pb's group; returns 0 or < 0. */
+static int group_setup(const orc_problem *pb, const orc_medium *md, group_ctx *g) {
+  g->pb = pb;
+  g->md = md;
+  g->p = pb->group;
+  g->L = pb->order + 1;
+  g->n = orc_group_members(pb->order, pb->group, NULL, 0);
+  if (g->n <= 0) return -1;
+  g->d = (orc_diagram *)malloc(sizeof(orc_diagram) * g->n);
+  g->canon = malloc(sizeof(*g->canon) * g->n);
+  int *ids = (int *)malloc(sizeof(int) * g->n);
+  orc_group_members(pb->order, pb->group, ids, g->n);
+  for (int i = 0; i < g->n; ++i) {
+    orc_get_diagram(pb->order, ids[i], &g->d[i]);
+    int c = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < g->L; ++j) {
+        const int part = g->d[i].is_particle[g->d[i].loop_line[j]] ? 1 : 0;
+        if ((pass == 0) == (part == 1)) g->canon[i][c++] = j;
+      }
+  }
+  free(ids);
+  return 0;
+}
+
+static void group_free(group_ctx *g) {
+  free(g->d);
+  free(g->canon);
+}
+
 /* Separable test integrand prod_m g(x_m), g a normalised Gaussian of width
  * `width` centred at 1/2 restricted to [0, 1]; its integral is
  * erf(1/(2 sqrt(2) width))^nd. */
@@ -828,11 +930,28 @@ int orc_fermi_momenta(const orc_problem *pb, double out[3]) {
 int orc_sample_values(const orc_problem *pb, const double *edges, uint32_t iter,
                       uint64_t first, uint64_t count, double *w_out,
                       double *wcond_out) {
-  orc_diagram d;
-  if (orc_get_diagram(pb->order, pb->diagram_id, &d)) return -1;
   if (pb->q == 2 && pb->proton_fraction != 0.0) return -2;
   orc_medium md;
   medium_of(pb, &md);
+  if (pb->group >= 0) {
+    group_ctx g;
+    if (group_setup(pb, &md, &g)) return -1;
+    const int nd = 3 * (pb->order + 1);
+#pragma omp parallel for schedule(static)
+    for (long long i = 0; i < (long long)count; ++i) {
+      double x[ORC_MAXDIM], wc;
+      int bins[ORC_MAXDIM];
+      double jv = vegas_map(nd, pb->n_bins, edges, pb->seed, pb->task_key, iter,
+                            first + (uint64_t)i, x, bins);
+      double w = group_eval(&g, x, &wc);
+      w_out[i] = jv * w;
+      if (wcond_out) wcond_out[i] = fabs(jv) * wc;
+    }
+    group_free(&g);
+    return 0;
+  }
+  orc_diagram d;
+  if (orc_get_diagram(pb->order, pb->diagram_id, &d)) return -1;
   phys_ctx ctx = {pb, &d, &md};
 #pragma omp parallel for schedule(static)
   for (long long i = 0; i < (long long)count; ++i) {
@@ -859,6 +978,26 @@ int orc_map_samples(int nd, int nb, const double *edges, uint32_t seed,
     if (bins_out)
       for (int m = 0; m < nd; ++m) bins_out[i * nd + m] = bins[m];
   }
+  return 0;
+}
+
+/* Integrand (single diagram or group, sphere Jacobian included, no VEGAS
+ * Jacobian) at explicit hypercube points x[count][3(order+1)]. */
+int orc_eval_x(const orc_problem *pb, const double *x, uint64_t count, double *w_out) {
+  orc_medium md;
+  medium_of(pb, &md);
+  const int nd = 3 * (pb->order + 1);
+  if (pb->group >= 0) {
+    group_ctx g;
+    if (group_setup(pb, &md, &g)) return -1;
+    for (uint64_t i = 0; i < count; ++i) w_out[i] = group_eval(&g, x + i * nd, NULL);
+    group_free(&g);
+    return 0;
+  }
+  orc_diagram d;
+  if (orc_get_diagram(pb->order, pb->diagram_id, &d)) return -1;
+  phys_ctx ctx = {pb, &d, &md};
+  for (uint64_t i = 0; i < count; ++i) w_out[i] = phys_eval(&ctx, x + i * nd, NULL);
   return 0;
 }
 
@@ -1048,11 +1187,20 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
 int orc_integrate(const orc_problem *pb, double *edges, uint64_t N, int iters,
                   uint32_t first_iter, int nthreads, double *I_out,
                   double *var_out, orc_result *res) {
-  orc_diagram d;
-  if (orc_get_diagram(pb->order, pb->diagram_id, &d)) return -1;
   if (pb->q == 2 && pb->proton_fraction != 0.0) return -2;
   orc_medium md;
   medium_of(pb, &md);
+  if (pb->group >= 0) {
+    group_ctx g;
+    if (group_setup(pb, &md, &g)) return -1;
+    int rc = vegas_run(3 * (pb->order + 1), pb->n_bins, pb->alpha, pb->seed, pb->task_key,
+                       group_eval, &g, edges, N, iters, first_iter, nthreads, I_out, var_out,
+                       res);
+    group_free(&g);
+    return rc;
+  }
+  orc_diagram d;
+  if (orc_get_diagram(pb->order, pb->diagram_id, &d)) return -1;
   phys_ctx ctx = {pb, &d, &md};
   return vegas_run(d.ndim, pb->n_bins, pb->alpha, pb->seed, pb->task_key, phys_eval,
                    &ctx, edges, N, iters, first_iter, nthreads, I_out, var_out, res);
