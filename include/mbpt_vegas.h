@@ -116,7 +116,14 @@ typedef struct mbpt_context_desc {
 /* One integration task: diagram `diagram_id` of order `order` (1..5; ids
  * index the deterministic generator list, see mbpt_num_diagrams) at density
  * [fm^-3] and proton fraction.  task_key is the second Philox key word: the
- * random stream of a task is (seed, task_key, iteration, sample). */
+ * random stream of a task is (seed, task_key, iteration, sample).
+ * group = 1: the task is a diagram group (Sec. "Automated evaluation": sums
+ * of diagrams of one order and particle-hole composition integrated
+ * together): diagram_id is then the number p of loop momenta carried by
+ * particle lines, and the task integrates the sum of the integrands of the
+ * order's diagrams with that p (mbpt_group_members), each member's loops
+ * taken particle loops first so that all share the loop radii; one VEGAS
+ * grid adapts to the sum.  Free spectrum only.  group = 0: one diagram. */
 typedef struct mbpt_task_desc {
   int order;
   int diagram_id;
@@ -124,6 +131,7 @@ typedef struct mbpt_task_desc {
   double density;
   double proton_fraction;
   uint32_t task_key;
+  int group;
 } mbpt_task_desc;
 
 /* Result of one task (or a sum over tasks).  E_per_A: inverse-variance
@@ -187,6 +195,12 @@ int mbpt_diagram_label_stats(int order, int id, int matter, int *n_assign, int *
  * (nothing written then).  coef may be NULL to query n_rows only. */
 int mbpt_diagram_label_poly(int order, int id, int matter, double *coef, int max_rows,
                             int *n_rows);
+
+/* Diagram groups of an order: the diagrams with p particle-carried loops
+ * (the cycle rank of their particle-line subgraph), ascending ids into
+ * caller-owned ids[cap]; *n receives the member count (0 for an empty group;
+ * orders 1..5 have 1, 1, 2, 4, 5 non-empty groups, Table I's N_grp). */
+int mbpt_group_members(int order, int p, int *ids, int cap, int *n);
 
 /* ---- task sets ------------------------------------------------------------ */
 /* Create a set of tasks (copied).  EINVAL on an unknown diagram, order outside

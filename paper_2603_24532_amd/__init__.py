@@ -25,7 +25,7 @@ EXPORTED = [
     "mbpt_context_create", "mbpt_context_destroy", "mbpt_last_error", "mbpt_set_interaction",
     "mbpt_set_precision", "mbpt_num_diagrams", "mbpt_diagram_matrix", "mbpt_diagram_label_stats",
     "mbpt_diagram_label_poly", "mbpt_set_spectrum", "mbpt_hf_nodes",
-    "mbpt_server_set_warm_start", "mbpt_server_warm_starts",
+    "mbpt_server_set_warm_start", "mbpt_server_warm_starts", "mbpt_group_members",
     "mbpt_create_task_set", "mbpt_create_diagram_set", "mbpt_task_set_destroy", "mbpt_task_count",
     "mbpt_set_density", "mbpt_set_asymmetry", "mbpt_set_launch_mode", "mbpt_set_blocking",
     "mbpt_workspace_query", "mbpt_bind_workspace", "mbpt_reset", "mbpt_integrate",
@@ -53,7 +53,7 @@ class mbpt_context_desc(ctypes.Structure):
 class mbpt_task_desc(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("diagram_id", ctypes.c_int), ("matter", ctypes.c_int),
                 ("density", ctypes.c_double), ("proton_fraction", ctypes.c_double),
-                ("task_key", ctypes.c_uint32)]
+                ("task_key", ctypes.c_uint32), ("group", ctypes.c_int)]
 
 
 class mbpt_result(ctypes.Structure):
@@ -103,6 +103,7 @@ def lib():
         "mbpt_num_diagrams": [ctypes.c_int, _IP],
         "mbpt_diagram_matrix": [ctypes.c_int, ctypes.c_int, _IP, _DP],
         "mbpt_diagram_label_stats": [ctypes.c_int, ctypes.c_int, ctypes.c_int, _IP, _IP, _IP],
+        "mbpt_group_members": [ctypes.c_int, ctypes.c_int, _IP, ctypes.c_int, _IP],
         "mbpt_diagram_label_poly": [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int, _IP],
         "mbpt_create_task_set": [_P, ctypes.POINTER(mbpt_task_desc), ctypes.c_int,
@@ -243,8 +244,18 @@ def mbpt_diagram_label_poly(order, did, matter):
     return [list(buf[r * nE:(r + 1) * nE]) for r in range(n.value)]
 
 
+def mbpt_group_members(order, p):
+    """Ids of the order's diagrams with p particle-carried loops."""
+    n = ctypes.c_int()
+    _check(lib().mbpt_group_members(order, p, None, 0, ctypes.byref(n)))
+    ids = (ctypes.c_int * max(1, n.value))()
+    _check(lib().mbpt_group_members(order, p, ids, n.value, ctypes.byref(n)))
+    return list(ids[:n.value])
+
+
 def mbpt_create_task_set(ctx, tasks):
-    """tasks: list of (order, diagram_id, matter, density, proton_fraction, task_key)."""
+    """tasks: list of (order, diagram_id, matter, density, proton_fraction, task_key
+    [, group]); group = 1 makes diagram_id the particle-loop count of a diagram group."""
     arr = (mbpt_task_desc * len(tasks))(*[mbpt_task_desc(*t) for t in tasks])
     h = _P()
     _check(lib().mbpt_create_task_set(ctx, arr, len(tasks), ctypes.byref(h)), ctx)

@@ -87,6 +87,8 @@ struct alignas(16) TaskDev {
   double inv_density;
   double band_k, band_d;
   double hf_h, hf_inv_h;  // HF spline step and its inverse
+  int ndiag;              // descriptors of the task from `diag` on (a diagram group: > 1)
+  int pad_nd;
   int active;
   int plan;             // iterations of the current launch sequence it takes part in
   // state (written by the device)

@@ -279,10 +279,37 @@ const Diagram *get_diagram(int order, int id) {
   return &ds[id];
 }
 
-void line_slots(const Diagram &d, int *slot_line) {
+int particle_loops(const Diagram &d) {
+  int p = 0;
+  for (int j = 0; j < d.nloops; ++j) p += d.particle[d.loop_line[j]] ? 1 : 0;
+  return p;
+}
+
+std::vector<int> group_members(int order, int p) {
+  std::vector<int> ids;
+  const int n = num_diagrams(order);
+  for (int i = 0; i < n; ++i) {
+    const Diagram *d = get_diagram(order, i);
+    if (d && particle_loops(*d) == p) ids.push_back(i);
+  }
+  return ids;
+}
+
+void canonical_loops(const Diagram &d, int *canon) {
+  int c = 0;
+  for (int j = 0; j < d.nloops; ++j)
+    if (d.particle[d.loop_line[j]]) canon[c++] = j;
+  for (int j = 0; j < d.nloops; ++j)
+    if (!d.particle[d.loop_line[j]]) canon[c++] = j;
+}
+
+void line_slots(const Diagram &d, int *slot_line, bool canonical) {
   bool is_loop[kMaxLines] = {};
+  int canon[kMaxLoops];
+  for (int j = 0; j < d.nloops; ++j) canon[j] = j;
+  if (canonical) canonical_loops(d, canon);
   for (int j = 0; j < d.nloops; ++j) {
-    slot_line[j] = d.loop_line[j];
+    slot_line[j] = d.loop_line[canon[j]];
     is_loop[d.loop_line[j]] = true;
   }
   int k = d.nloops;
@@ -290,10 +317,10 @@ void line_slots(const Diagram &d, int *slot_line) {
     if (!is_loop[l]) slot_line[k++] = l;
 }
 
-LabelTables label_tables(const Diagram &d, int q) {
+LabelTables label_tables(const Diagram &d, int q, bool canonical) {
   const LabelList ll = build_labels(d, q);
   int slot_line[kMaxLines];
-  line_slots(d, slot_line);
+  line_slots(d, slot_line, canonical);
   auto to_slots = [&](uint32_t tau) {
     uint32_t t = 0;
     for (int sl = 0; sl < d.nlines; ++sl)

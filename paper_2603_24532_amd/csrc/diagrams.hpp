@@ -48,9 +48,21 @@ struct LabelList {
   std::vector<LabelTerm> terms;  // sorted by tau_mask, then codes
 };
 
-// Line slots: slot j < L holds the line carrying loop momentum j, the tree
-// lines follow in line order.  slot_line[slot] = line.
-void line_slots(const Diagram &d, int *slot_line);
+// Loop momenta carried by particle lines (the cycle rank of the particle-line
+// subgraph, since the spanning forest takes particle lines first).  Diagrams
+// of an order with equal counts form a diagram group; this gives 1, 1, 2, 4, 5
+// groups at orders 1..5 (Table I, N_grp).
+int particle_loops(const Diagram &d);
+// Ids of the diagrams of `order` with p particle-carried loops, ascending.
+std::vector<int> group_members(int order, int p);
+// Canonical loop order of a group member: its particle loops first, then its
+// hole loops, each in the diagram's own order.  canon[c] = the diagram's loop.
+void canonical_loops(const Diagram &d, int *canon);
+
+// Line slots: slot j < L holds the line carrying loop momentum j (in the
+// canonical order if `canonical`), the tree lines follow in line order.
+// slot_line[slot] = line.
+void line_slots(const Diagram &d, int *slot_line, bool canonical = false);
 
 // Device-ready label tables of one diagram, with lines in slot order:
 // isospin groups (tau masks over slots), explicit terms and, per group, the
@@ -66,7 +78,7 @@ struct LabelTables {
   std::vector<Group> groups;
   std::vector<LabelTerm> terms;  // tau masks over slots
 };
-LabelTables label_tables(const Diagram &d, int q);
+LabelTables label_tables(const Diagram &d, int q, bool canonical = false);
 
 // Number of diagrams of an order (1..5), or -1.
 int num_diagrams(int order);

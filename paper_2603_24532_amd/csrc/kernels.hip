@@ -423,35 +423,17 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
   return acc;
 }
 
-// HF: single-particle energies of the Hartree-Fock spectrum (tables in LDS).
+// Contribution of one diagram at the loop momenta k (prefactor, regulators,
+// label sum and denominators; without the Jacobian and 1/n).  HF: single-
+// particle energies of the Hartree-Fock spectrum (tables in LDS).
 template <int ORDER, int Q, bool HF>
-__device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
-                                            const DiagDev *__restrict__ D,
-                                            const SampleLds &Ls, uint64_t s,
-                                            uint32_t iter, int *bins, uint32_t &npass,
-                                            uint32_t &nterms) {
+__device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
+                                                const DiagDev *__restrict__ D,
+                                                const SampleLds &Ls, const double (*k)[3],
+                                                uint32_t &npass, uint32_t &nterms) {
   constexpr int L = ORDER + 1;
   constexpr int NL = 2 * ORDER;
   constexpr int NC = ORDER - 1;
-  constexpr int ND = 3 * L;
-  double x[ND];
-  double jac = vegas_map<ND>(a, T, Ls.g, s, iter, x, bins);
-
-  // loop momenta: radius R x0, cos theta = 2 x1 - 1, azimuth 2 pi x2
-  double k[L][3];
-#pragma unroll
-  for (int j = 0; j < L; ++j) {
-    const double R = D->loop_part[j] ? T->Rp : T->Rh;
-    const double rad = R * x[3 * j];
-    const double ct = 2.0 * x[3 * j + 1] - 1.0;
-    const double st = sqrt_normal((1.0 - ct) * (1.0 + ct));
-    double sp, cp;
-    sincos_turn(Ls.turn, x[3 * j + 2], sp, cp);
-    k[j][0] = rad * st * cp;
-    k[j][1] = rad * st * sp;
-    k[j][2] = rad * ct;
-    jac *= R * rad * rad * (4.0 * M_PI);
-  }
 
   // line momenta -> occupation tests and energies (HF: plus the self-energy
   // of a neutron, and for nuclear matter the proton-neutron difference)
@@ -555,7 +537,48 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
 
   const double acc =
       label_sum<ORDER, Q, double, iso_den>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn, deps);
-  return jac * (D->pref * T->inv_density) * regall * acc * rinv[NR - 1];
+  return D->pref * regall * acc * rinv[NR - 1];
+}
+
+// One sample of a task: VEGAS map, loop momenta (radii from the first
+// descriptor: the members of a diagram group share them), then the diagram,
+// or (G) the task's T->ndiag group members summed.
+template <int ORDER, int Q, bool HF, bool G>
+__device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
+                                            const DiagDev *__restrict__ D,
+                                            const SampleLds &Ls, uint64_t s,
+                                            uint32_t iter, int *bins, uint32_t &npass,
+                                            uint32_t &nterms) {
+  constexpr int L = ORDER + 1;
+  constexpr int ND = 3 * L;
+  double x[ND];
+  double jac = vegas_map<ND>(a, T, Ls.g, s, iter, x, bins);
+
+  // loop momenta: radius R x0, cos theta = 2 x1 - 1, azimuth 2 pi x2
+  double k[L][3];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const double R = D->loop_part[j] ? T->Rp : T->Rh;
+    const double rad = R * x[3 * j];
+    const double ct = 2.0 * x[3 * j + 1] - 1.0;
+    const double st = sqrt_normal((1.0 - ct) * (1.0 + ct));
+    double sp, cp;
+    sincos_turn(Ls.turn, x[3 * j + 2], sp, cp);
+    k[j][0] = rad * st * cp;
+    k[j][1] = rad * st * sp;
+    k[j][2] = rad * ct;
+    jac *= R * rad * rad * (4.0 * M_PI);
+  }
+  double sum;
+  if constexpr (G) {
+    sum = 0.0;
+    const int nd = T->ndiag;
+    for (int di = 0; di < nd; ++di)
+      sum += diag_weight64<ORDER, Q, HF>(a, T, D + di, Ls, k, npass, nterms);
+  } else {
+    sum = diag_weight64<ORDER, Q, HF>(a, T, D, Ls, k, npass, nterms);
+  }
+  return jac * T->inv_density * sum;
 }
 
 // fp32 counterpart of masked_sum
@@ -592,37 +615,16 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 // band_d times the sum of its energies (cancellation), or a regulator exponent
 // or reciprocal product outside the fp32 range.  The caller then evaluates the
 // sample in fp64 from the same random words.
+// fp32 contribution of one diagram at the loop momenta k (see
+// diag_weight64); sets `fallback` instead when the sample needs fp64.
 template <int ORDER, int Q>
-__device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
-                                            const DiagDev *__restrict__ D,
-                                            const SampleLds &Ls, uint64_t s,
-                                            uint32_t iter, int *bins, uint32_t &npass,
-                                            uint32_t &nterms, bool &fallback) {
+__device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *__restrict__ T,
+                                                const DiagDev *__restrict__ D,
+                                                const float (*k)[3], uint32_t &npass,
+                                                uint32_t &nterms, bool &fallback) {
   constexpr int L = ORDER + 1;
   constexpr int NL = 2 * ORDER;
   constexpr int NC = ORDER - 1;
-  constexpr int ND = 3 * L;
-  double x[ND];
-  double jac = vegas_map<ND>(a, T, Ls.g, s, iter, x, bins);
-
-  // loop momenta; the azimuth goes to the hardware sine/cosine in revolutions
-  float k[L][3];
-#pragma unroll
-  for (int j = 0; j < L; ++j) {
-    const double R = D->loop_part[j] ? T->Rp : T->Rh;
-    const double rad64 = R * x[3 * j];
-    jac *= R * rad64 * rad64 * (4.0 * M_PI);
-    const float rad = static_cast<float>(rad64);
-    const float ct = static_cast<float>(2.0 * x[3 * j + 1] - 1.0);
-    const float st = __builtin_sqrtf(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
-    const float rev = static_cast<float>(x[3 * j + 2]);
-    const float sp = __builtin_amdgcn_sinf(rev), cp = __builtin_amdgcn_cosf(rev);
-    const float rs = rad * st;
-    k[j][0] = rs * cp;
-    k[j][1] = rs * sp;
-    k[j][2] = rad * ct;
-  }
-
   const float kFn2 = static_cast<float>(T->kF2[0]), kFp2 = static_cast<float>(T->kF2[1]);
   const float bandk = static_cast<float>(T->band_k), bandd = static_cast<float>(T->band_d);
   const float hb2m = static_cast<float>(a.phys.hb2m);
@@ -728,24 +730,79 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
   const float acc =
       label_sum<ORDER, Q, float, false>(a, D, Vd, Ve, okN, okP, lmask, nterms, nullptr, nullptr);
   ++npass;
-  return jac * (D->pref * T->inv_density) * static_cast<double>(regall) *
-         static_cast<double>(acc) * static_cast<double>(rinv[NR - 1]);
+  return D->pref * static_cast<double>(regall) * static_cast<double>(acc) *
+         static_cast<double>(rinv[NR - 1]);
 }
 
-// One sample in mode P: 0 fp64; 1 fp32 with the fp64 fallback; 2 fp64 with
-// the Hartree-Fock spectrum (the fp32 integrand has the free spectrum only).
+template <int ORDER, int Q, bool G>
+__device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
+                                            const DiagDev *__restrict__ D,
+                                            const SampleLds &Ls, uint64_t s,
+                                            uint32_t iter, int *bins, uint32_t &npass,
+                                            uint32_t &nterms, bool &fallback) {
+  constexpr int L = ORDER + 1;
+  constexpr int ND = 3 * L;
+  double x[ND];
+  double jac = vegas_map<ND>(a, T, Ls.g, s, iter, x, bins);
+
+  // loop momenta; the azimuth goes to the hardware sine/cosine in revolutions
+  float k[L][3];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const double R = D->loop_part[j] ? T->Rp : T->Rh;
+    const double rad64 = R * x[3 * j];
+    jac *= R * rad64 * rad64 * (4.0 * M_PI);
+    const float rad = static_cast<float>(rad64);
+    const float ct = static_cast<float>(2.0 * x[3 * j + 1] - 1.0);
+    const float st = __builtin_sqrtf(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
+    const float rev = static_cast<float>(x[3 * j + 2]);
+    const float sp = __builtin_amdgcn_sinf(rev), cp = __builtin_amdgcn_cosf(rev);
+    const float rs = rad * st;
+    k[j][0] = rs * cp;
+    k[j][1] = rs * sp;
+    k[j][2] = rad * ct;
+  }
+  double sum;
+  if constexpr (G) {
+    sum = 0.0;
+    const int nd = T->ndiag;
+    for (int di = 0; di < nd; ++di) {
+      sum += diag_weight32<ORDER, Q>(a, T, D + di, k, npass, nterms, fallback);
+      if (fallback) return 0.0;  // the whole sample is re-evaluated in fp64
+    }
+  } else {
+    sum = diag_weight32<ORDER, Q>(a, T, D, k, npass, nterms, fallback);
+    if (fallback) return 0.0;
+  }
+  return jac * T->inv_density * sum;
+}
+
+// Kernel mode P: 0 fp64; 1 fp32 with the fp64 fallback; 2 fp64 with the
+// Hartree-Fock spectrum (the fp32 integrand has the free spectrum only);
+// 3 and 4: modes 0 and 1 for diagram groups (tasks of several descriptors).
+template <int P>
+constexpr int prec_of() {
+  return P >= 3 ? P - 3 : P;
+}
+template <int P>
+constexpr bool group_of() {
+  return P >= 3;
+}
+
 template <int ORDER, int Q, int P>
 __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__restrict__ T,
                                               const DiagDev *__restrict__ D,
                                               const SampleLds &Ls, uint64_t s,
                                               uint32_t iter, int *bins, uint32_t &npass,
                                               uint32_t &nterms, uint32_t &nfb) {
-  if (P != 1) return eval_fp64<ORDER, Q, P == 2>(a, T, D, Ls, s, iter, bins, npass, nterms);
+  constexpr int PP = prec_of<P>();
+  constexpr bool G = group_of<P>();
+  if (PP != 1) return eval_fp64<ORDER, Q, PP == 2, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
   bool fb = false;
-  double w = eval_fp32<ORDER, Q>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
+  double w = eval_fp32<ORDER, Q, G>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
   if (fb) {
     ++nfb;
-    w = eval_fp64<ORDER, Q, false>(a, T, D, Ls, s, iter, bins, npass, nterms);
+    w = eval_fp64<ORDER, Q, false, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
   }
   return w;
 }
@@ -753,7 +810,7 @@ __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__r
 // HF spline tables held in LDS in mode P
 template <int Q, int P>
 constexpr int lds_tables() {
-  return P == 2 ? (Q == 4 ? 2 : 1) : 0;
+  return prec_of<P>() == 2 ? (Q == 4 ? 2 : 1) : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -798,12 +855,14 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       for (int m = 0; m < ND; ++m) atomicAdd(&h[m * nb + bins[m]], w2);
     }
   };
-  if (P != 1) {
+  constexpr int PP = prec_of<P>();
+  constexpr bool G = group_of<P>();
+  if (PP != 1) {
     for (int kk = 0; kk < a.spt; ++kk) {
       const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
       if (s < N) {
         int bins[ND];
-        const double w = eval_fp64<ORDER, Q, P == 2>(a, T, D, Ls, s, iter, bins, npass, nterms);
+        const double w = eval_fp64<ORDER, Q, PP == 2, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
         accumulate(w, bins);
       }
     }
@@ -818,7 +877,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       if (lane < take) {
         const uint64_t s = base + queue[lane];
         int bins[ND];
-        const double w = eval_fp64<ORDER, Q, false>(a, T, D, Ls, s, iter, bins, npass, nterms);
+        const double w = eval_fp64<ORDER, Q, false, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
         accumulate(w, bins);
       }
       __builtin_amdgcn_wave_barrier();
@@ -834,7 +893,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       bool fb = false;
       if (s < N) {
         int bins[ND];
-        const double w = eval_fp32<ORDER, Q>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
+        const double w = eval_fp32<ORDER, Q, G>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
         if (!fb) accumulate(w, bins);
       }
       const uint64_t mask = __ballot(fb);
@@ -906,13 +965,13 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 }
 
 // One task per launch: block b processes work item item_begin + b.
-// The fifth-order fp32 kernels carry the inlined fp64 re-evaluation path on
-// top of their own state; asking for two waves per SIMD keeps them within
-// 256 VGPRs (a few spilled dwords on the re-evaluation path instead of half
-// the occupancy).
+// The fifth-order fp32 kernels (which carry the inlined fp64 re-evaluation
+// path on top of their own state) and fifth-order group kernels (the member
+// loop keeps the loop momenta live) ask for two waves per SIMD, which holds
+// them within 256 VGPRs: a few spilled dwords instead of half the occupancy.
 template <int ORDER, int P>
 constexpr int min_waves() {
-  return (P == 1 && ORDER == 5) ? 2 : 1;
+  return (ORDER == 5 && (prec_of<P>() == 1 || group_of<P>())) ? 2 : 1;
 }
 
 template <int ORDER, int Q, int P>
@@ -1273,7 +1332,10 @@ __global__ void init_tasks(KArgs a, int first) {
 
 // Kernel mode from the precision and the spectrum: the HF spectrum runs the
 // fp64 integrand (mode 2) whatever the precision.
-static int mode_of(const KArgs &a, int prec) { return a.phys.spectrum ? 2 : (prec ? 1 : 0); }
+static int mode_of(const KArgs &a, int prec, bool group) {
+  if (a.phys.spectrum) return group ? -1 : 2;  // HF groups are not built
+  return (prec ? 1 : 0) + (group ? 3 : 0);
+}
 
 size_t sample_lds_bytes(int nd, int nb, int block, int ntab) {
   // turn table + HF tables + grid (e, width) pairs + histogram + reduction
@@ -1298,15 +1360,22 @@ static hipError_t single_q(const KArgs &a, int t, int order, int nitems, int blo
   return hipGetLastError();
 }
 
-hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int prec, int nitems,
-                                int block, hipStream_t st) {
-  switch (mode_of(a, prec) + 3 * (q == 4)) {
+hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int prec, bool group,
+                                int nitems, int block, hipStream_t st) {
+  const int m = mode_of(a, prec, group);
+  if (m < 0) return hipErrorInvalidValue;
+  switch (m + 5 * (q == 4)) {
     case 0: return single_q<2, 0>(a, t, order, nitems, block, st);
     case 1: return single_q<2, 1>(a, t, order, nitems, block, st);
     case 2: return single_q<2, 2>(a, t, order, nitems, block, st);
-    case 3: return single_q<4, 0>(a, t, order, nitems, block, st);
-    case 4: return single_q<4, 1>(a, t, order, nitems, block, st);
-    default: return single_q<4, 2>(a, t, order, nitems, block, st);
+    case 3: return single_q<2, 3>(a, t, order, nitems, block, st);
+    case 4: return single_q<2, 4>(a, t, order, nitems, block, st);
+    case 5: return single_q<4, 0>(a, t, order, nitems, block, st);
+    case 6: return single_q<4, 1>(a, t, order, nitems, block, st);
+    case 7: return single_q<4, 2>(a, t, order, nitems, block, st);
+    case 8: return single_q<4, 3>(a, t, order, nitems, block, st);
+    case 9: return single_q<4, 4>(a, t, order, nitems, block, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -1325,15 +1394,22 @@ static hipError_t order_qp(const KArgs &a, int order, int k0, int k1, int grid, 
   return hipGetLastError();
 }
 
-hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, int k0, int k1,
-                               int nitems, int block, hipStream_t st) {
-  switch (mode_of(a, prec) + 3 * (q == 4)) {
+hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, bool group, int k0,
+                               int k1, int nitems, int block, hipStream_t st) {
+  const int m = mode_of(a, prec, group);
+  if (m < 0) return hipErrorInvalidValue;
+  switch (m + 5 * (q == 4)) {
     case 0: return order_qp<2, 0>(a, order, k0, k1, nitems, block, st);
     case 1: return order_qp<2, 1>(a, order, k0, k1, nitems, block, st);
     case 2: return order_qp<2, 2>(a, order, k0, k1, nitems, block, st);
-    case 3: return order_qp<4, 0>(a, order, k0, k1, nitems, block, st);
-    case 4: return order_qp<4, 1>(a, order, k0, k1, nitems, block, st);
-    default: return order_qp<4, 2>(a, order, k0, k1, nitems, block, st);
+    case 3: return order_qp<2, 3>(a, order, k0, k1, nitems, block, st);
+    case 4: return order_qp<2, 4>(a, order, k0, k1, nitems, block, st);
+    case 5: return order_qp<4, 0>(a, order, k0, k1, nitems, block, st);
+    case 6: return order_qp<4, 1>(a, order, k0, k1, nitems, block, st);
+    case 7: return order_qp<4, 2>(a, order, k0, k1, nitems, block, st);
+    case 8: return order_qp<4, 3>(a, order, k0, k1, nitems, block, st);
+    case 9: return order_qp<4, 4>(a, order, k0, k1, nitems, block, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -1363,15 +1439,22 @@ static hipError_t dump_q(const KArgs &a, int t, int order, uint32_t iter, uint64
   return hipGetLastError();
 }
 
-hipError_t launch_dump(const KArgs &a, int t, int order, int q, int prec, uint32_t iter,
-                       uint64_t first, uint64_t count, double *out, hipStream_t st) {
-  switch (mode_of(a, prec) + 3 * (q == 4)) {
+hipError_t launch_dump(const KArgs &a, int t, int order, int q, int prec, bool group,
+                       uint32_t iter, uint64_t first, uint64_t count, double *out, hipStream_t st) {
+  const int m = mode_of(a, prec, group);
+  if (m < 0) return hipErrorInvalidValue;
+  switch (m + 5 * (q == 4)) {
     case 0: return dump_q<2, 0>(a, t, order, iter, first, count, out, st);
     case 1: return dump_q<2, 1>(a, t, order, iter, first, count, out, st);
     case 2: return dump_q<2, 2>(a, t, order, iter, first, count, out, st);
-    case 3: return dump_q<4, 0>(a, t, order, iter, first, count, out, st);
-    case 4: return dump_q<4, 1>(a, t, order, iter, first, count, out, st);
-    default: return dump_q<4, 2>(a, t, order, iter, first, count, out, st);
+    case 3: return dump_q<2, 3>(a, t, order, iter, first, count, out, st);
+    case 4: return dump_q<2, 4>(a, t, order, iter, first, count, out, st);
+    case 5: return dump_q<4, 0>(a, t, order, iter, first, count, out, st);
+    case 6: return dump_q<4, 1>(a, t, order, iter, first, count, out, st);
+    case 7: return dump_q<4, 2>(a, t, order, iter, first, count, out, st);
+    case 8: return dump_q<4, 3>(a, t, order, iter, first, count, out, st);
+    case 9: return dump_q<4, 4>(a, t, order, iter, first, count, out, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -91,6 +91,9 @@ void count_flops(const Diagram &d, int q, int half_exp, int label_mode, int spec
   }
   double acc = 10.0 + 1.0 + ND; // shifted sums (Neumaier), w^2, histogram adds
   f.pre = pre + pre_t + acc;    // every sample is accumulated
+  // map, loop momenta and accumulation: once per sample even for a group
+  f.transc_shared = 3.0 * L;
+  f.shared = 6.0 * ND + 13.0 * L + f.transc_shared + acc;
   f.post = post + post_t;
   f.all_units = 0.0;
   f.transc_pre = pre_t;
@@ -206,6 +209,15 @@ extern "C" int mbpt_diagram_label_stats(int order, int id, int matter, int *n_as
   return MBPT_OK;
 }
 
+extern "C" int mbpt_group_members(int order, int p, int *ids, int cap, int *n) {
+  if (!n || order < 1 || order > kMaxOrder || p < 0 || cap < 0) return MBPT_EINVAL;
+  const std::vector<int> m = group_members(order, p);
+  *n = static_cast<int>(m.size());
+  if (ids)
+    for (int i = 0; i < *n && i < cap; ++i) ids[i] = m[i];
+  return MBPT_OK;
+}
+
 extern "C" int mbpt_diagram_label_poly(int order, int id, int matter, double *coef, int max_rows,
                                        int *n_rows) {
   const Diagram *d = get_diagram(order, id);
@@ -226,23 +238,29 @@ extern "C" int mbpt_diagram_label_poly(int order, int id, int matter, double *co
 namespace mbpt {
 
 // Descriptor fields derived from the diagram alone (loop radii, masks in
-// line-slot order, prefactor with the (2 pi)^{-3L} measure).
-void fill_diag_dev(const Diagram &d, DiagDev &dd) {
-  int slot_line[kMaxLines];
-  line_slots(d, slot_line);
-  for (int j = 0; j < d.nloops; ++j) dd.loop_part[j] = d.particle[d.loop_line[j]] ? 1 : 0;
+// line-slot order, prefactor with the (2 pi)^{-3L} measure).  canonical: the
+// loops in the group-canonical order (particle loops first).
+void fill_diag_dev(const Diagram &d, DiagDev &dd, bool canonical) {
+  int slot_line[kMaxLines], canon[kMaxLoops], pos[kMaxLoops];
+  line_slots(d, slot_line, canonical);
+  for (int j = 0; j < d.nloops; ++j) canon[j] = j;
+  if (canonical) canonical_loops(d, canon);
+  for (int c = 0; c < d.nloops; ++c) pos[canon[c]] = c;
+  for (int c = 0; c < d.nloops; ++c) dd.loop_part[c] = d.particle[d.loop_line[canon[c]]] ? 1 : 0;
   dd.part_mask = 0;
   for (int sl = 0; sl < d.nlines; ++sl)
     if (d.particle[slot_line[sl]]) dd.part_mask |= 1u << sl;
   dd.line_mask = (1u << d.nlines) - 1u;
   dd.pref = d.prefactor * std::pow(2.0 * M_PI, -3.0 * d.nloops);
+  // coefficient of the diagram's loop j goes to bit pos[j]
   auto pack = [&](const int *c) {
     uint32_t m = 0;
     for (int j = 0; j < d.nloops; ++j) {
-      if (c[j] == 1) m |= 1u << j;
-      else if (c[j] == -1) m |= 1u << (8 + j);
-      else if (c[j] == 2) m |= 1u << (16 + j);
-      else if (c[j] == -2) m |= 1u << (24 + j);
+      const int b = pos[j];
+      if (c[j] == 1) m |= 1u << b;
+      else if (c[j] == -1) m |= 1u << (8 + b);
+      else if (c[j] == 2) m |= 1u << (16 + b);
+      else if (c[j] == -2) m |= 1u << (24 + b);
     }
     return m;
   };
@@ -269,8 +287,8 @@ void fill_diag_dev(const Diagram &d, DiagDev &dd) {
 // offsets stored in the descriptor are absolute for the kernel's table bases.
 void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
                          std::vector<TermDev> &terms, std::vector<double> &coefs,
-                         size_t group_base, size_t term_base, size_t coef_base) {
-  const LabelTables lt = label_tables(d, q);
+                         size_t group_base, size_t term_base, size_t coef_base, bool canonical) {
+  const LabelTables lt = label_tables(d, q, canonical);
   dd.group_off = static_cast<int>(group_base + groups.size());
   dd.ngroups = static_cast<int>(lt.groups.size());
   dd.term_off = static_cast<int>(term_base + terms.size());
@@ -362,37 +380,61 @@ int compile_tables(mbpt_task_set *set) {
   set->terms.clear();
   set->coefs.clear();
   set->task_diag.assign(set->tasks.size(), -1);
+  set->task_ndiag.assign(set->tasks.size(), 1);
   set->flops.assign(set->tasks.size(), FlopModel{});
-  std::vector<std::pair<int, int>> keys;
+  // one entry per distinct (order, id, group): first descriptor, count, model
+  struct Entry {
+    int order, id, group, first, count;
+    FlopModel fm;
+  };
+  std::vector<Entry> done;
   for (size_t t = 0; t < set->tasks.size(); ++t) {
     const auto &td = set->tasks[t];
-    const std::pair<int, int> key{td.order, td.diagram_id};
-    auto it = std::find(keys.begin(), keys.end(), key);
-    if (it != keys.end()) {
-      set->task_diag[t] = static_cast<int>(it - keys.begin());
-      set->flops[t] = set->diag_flops[set->task_diag[t]];
-      continue;
+    const Entry *hit = nullptr;
+    for (const auto &e : done)
+      if (e.order == td.order && e.id == td.diagram_id && e.group == td.group) hit = &e;
+    if (!hit) {
+      const std::vector<int> ids =
+          td.group ? group_members(td.order, td.diagram_id) : std::vector<int>{td.diagram_id};
+      Entry e{td.order, td.diagram_id, td.group, static_cast<int>(set->diags.size()),
+              static_cast<int>(ids.size()), FlopModel{}};
+      double units = 0.0, unit_flops = 0.0;
+      for (size_t i = 0; i < ids.size(); ++i) {
+        const Diagram *d = get_diagram(td.order, ids[i]);
+        if (!d) {
+          set_err(ctx, "unknown diagram");
+          return MBPT_EINVAL;
+        }
+        DiagDev dd{};
+        dd.order = d->order;
+        dd.nlines = d->nlines;
+        dd.nloops = d->nloops;
+        dd.ncuts = d->ncuts;
+        fill_diag_dev(*d, dd, td.group != 0);
+        append_label_tables(*d, q, dd, set->groups, set->terms, set->coefs, 0, 0, 0, td.group != 0);
+        set->diags.push_back(dd);
+        FlopModel fm;
+        count_flops(*d, q, ctx->v.reg_exp / 2, ctx->desc.label_mode, ctx->desc.spectrum, fm);
+        fm.all_units = ctx->desc.label_mode ? dd.nterms : dd.ngroups;
+        // a group shares the map and loop momenta; its pass and label-unit
+        // counters add up over members, so post and per_term are averages
+        e.fm.pre += i == 0 ? fm.pre : fm.pre - fm.shared;
+        e.fm.shared = fm.shared;
+        e.fm.post += fm.post / ids.size();
+        e.fm.transc_pre += i == 0 ? fm.transc_pre : fm.transc_pre - fm.transc_shared;
+        e.fm.transc_shared = fm.transc_shared;
+        e.fm.transc_post += fm.transc_post / ids.size();
+        units += fm.all_units;
+        unit_flops += fm.per_term * fm.all_units;
+      }
+      e.fm.all_units = units;
+      e.fm.per_term = units > 0.0 ? unit_flops / units : 0.0;
+      done.push_back(e);
+      hit = &done.back();
     }
-    const Diagram *d = get_diagram(td.order, td.diagram_id);
-    if (!d) {
-      set_err(ctx, "unknown diagram");
-      return MBPT_EINVAL;
-    }
-    DiagDev dd{};
-    dd.order = d->order;
-    dd.nlines = d->nlines;
-    dd.nloops = d->nloops;
-    dd.ncuts = d->ncuts;
-    fill_diag_dev(*d, dd);
-    append_label_tables(*d, q, dd, set->groups, set->terms, set->coefs, 0, 0, 0);
-    FlopModel fm;
-    count_flops(*d, q, ctx->v.reg_exp / 2, ctx->desc.label_mode, ctx->desc.spectrum, fm);
-    fm.all_units = ctx->desc.label_mode ? dd.nterms : dd.ngroups;
-    set->diag_flops.push_back(fm);
-    set->diags.push_back(dd);
-    keys.push_back(key);
-    set->task_diag[t] = static_cast<int>(keys.size()) - 1;
-    set->flops[t] = fm;
+    set->task_diag[t] = hit->first;
+    set->task_ndiag[t] = hit->count;
+    set->flops[t] = hit->fm;
   }
   set->max_nd = 0;
   for (const auto &td : set->tasks) set->max_nd = std::max(set->max_nd, 3 * (td.order + 1));
@@ -410,6 +452,7 @@ void fill_task_params(mbpt_task_set *set) {
     TaskDev &T = set->h_tasks[t];
     const int nd = 3 * (td.order + 1);
     T.diag = set->task_diag[t];
+    T.ndiag = set->task_ndiag[t];
     T.nd = nd;
     T.hf_off = static_cast<int>(t) * 2 * kHfEntries;
     T.grid_off = goff;
@@ -674,8 +717,16 @@ static int check_tasks(mbpt_context *ctx, const mbpt_task_desc *tasks, int n, in
       set_err(ctx, "task set: every task needs the same matter (NEUTRON or NUCLEAR)");
       return MBPT_EINVAL;
     }
-    if (!get_diagram(t.order, t.diagram_id)) {
-      set_err(ctx, "task set: unknown diagram");
+    if (t.group != 0 && t.group != 1) {
+      set_err(ctx, "task set: group must be 0 (one diagram) or 1 (a diagram group)");
+      return MBPT_EINVAL;
+    }
+    if (t.group ? group_members(t.order, t.diagram_id).empty() : !get_diagram(t.order, t.diagram_id)) {
+      set_err(ctx, "task set: unknown diagram or empty diagram group");
+      return MBPT_EINVAL;
+    }
+    if (t.group && ctx->desc.spectrum != MBPT_SPECTRUM_FREE) {
+      set_err(ctx, "task set: diagram groups take the free spectrum only");
       return MBPT_EINVAL;
     }
     if (!(t.density > 0.0) || !(t.proton_fraction >= 0.0 && t.proton_fraction <= 1.0) ||
@@ -831,6 +882,7 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
         size_t slot = 0;
         if (timed) timed_begin(ctx, slot);
         HIPCHK(ctx, launch_sample_single(a, t, set->tasks[t].order, set->q, ctx->desc.precision,
+                                         set->task_ndiag[t] > 1,
                                          set->h_tasks[t].nitems, set->block, ctx->stream));
         if (timed) timed_end(ctx, slot);
         HIPCHK(ctx, launch_finish(a, t, 1, 0, alpha, ctx->stream));
@@ -841,7 +893,7 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
     size_t slot = 0;
     if (timed) timed_begin(ctx, slot);
     for (const auto &r : set->oranges)
-      HIPCHK(ctx, launch_sample_order(a, r.order, set->q, ctx->desc.precision, r.k0, r.k1,
+      HIPCHK(ctx, launch_sample_order(a, r.order, set->q, ctx->desc.precision, r.group, r.k0, r.k1,
                                       r.nitems, set->block, ctx->stream));
     if (timed) timed_end(ctx, slot);
     HIPCHK(ctx, launch_finish(a, 0, nt, 0, alpha, ctx->stream));
@@ -873,6 +925,8 @@ void order_items(std::vector<TaskDev> &T, const std::vector<int> &active,
     r.k1 = k1;
     r.item_end = item;
     r.nitems = item - olist[k0].x;
+    r.group = false;
+    for (int k = k0; k < k1; ++k) r.group = r.group || T[olist[k].y].ndiag > 1;
     ranges.push_back(r);
   }
 }
@@ -1038,7 +1092,8 @@ extern "C" int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, ui
   const uint64_t cap = set->max_items * 4;
   for (uint64_t done = 0; done < count;) {
     const uint64_t n = std::min<uint64_t>(cap, count - done);
-    HIPCHK(ctx, launch_dump(a, task, set->tasks[task].order, set->q, ctx->desc.precision, iter,
+    HIPCHK(ctx, launch_dump(a, task, set->tasks[task].order, set->q, ctx->desc.precision,
+                            set->task_ndiag[task] > 1, iter,
                             first + done, n, set->d_partials, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(w_host + done, set->d_partials, n * sizeof(double),
                                hipMemcpyDeviceToHost, ctx->stream));

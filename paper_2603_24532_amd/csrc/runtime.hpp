@@ -15,6 +15,7 @@ namespace mbpt {
 // nitems items ending at item_end.
 struct OrderRange {
   int order, k0, k1, item_end, nitems;
+  bool group;  // some task of the range is a diagram group
 };
 
 // Algorithmic FLOPs of one evaluation (see count_flops).
@@ -24,6 +25,7 @@ struct FlopModel {
   double per_term = 0.0;   // per label unit evaluated (isospin group or explicit term)
   double transc_pre = 0.0, transc_post = 0.0;
   double all_units = 0.0;  // label units of the whole list (groups or terms)
+  double shared = 0.0, transc_shared = 0.0;  // part of pre a diagram group pays once
 };
 
 }  // namespace mbpt
@@ -55,8 +57,8 @@ struct mbpt_task_set {
   std::vector<mbpt::GroupDev> groups;
   std::vector<mbpt::TermDev> terms;
   std::vector<double> coefs;        // see coef_slots
-  std::vector<int> task_diag;
-  std::vector<mbpt::FlopModel> flops, diag_flops;
+  std::vector<int> task_diag, task_ndiag;  // first descriptor and count per task
+  std::vector<mbpt::FlopModel> flops;
   int max_nd = 0;
   std::vector<mbpt::TaskDev> h_tasks, last_state;
   int grid_doubles = 0, hist_doubles = 0;
@@ -97,8 +99,9 @@ void count_flops(const Diagram &d, int q, int half_exp, int label_mode, int spec
                  FlopModel &f);
 void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
                          std::vector<TermDev> &terms, std::vector<double> &coefs,
-                         size_t group_base, size_t term_base, size_t coef_base);
-void fill_diag_dev(const Diagram &d, DiagDev &dd);
+                         size_t group_base, size_t term_base, size_t coef_base,
+                         bool canonical = false);
+void fill_diag_dev(const Diagram &d, DiagDev &dd, bool canonical = false);
 void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T);
 void result_of(const TaskDev &S, mbpt_result &r);
 void timed_begin(mbpt_context *ctx, size_t &slot);

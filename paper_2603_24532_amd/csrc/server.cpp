@@ -353,6 +353,7 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   const double x = q.r.matter == MBPT_NUCLEAR ? q.r.proton_fraction : 0.0;
   fill_medium(ctx, q.r.density, x, T);
   T.active = 1;
+  T.ndiag = 1;
   s->h_tasks[slot] = T;
   *sT = T;
   char *b = s->ws;
@@ -564,7 +565,7 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
         while (k1 < r.k1 && s->h_tasks[s->olist[k1].y].plan > j) ++k1;
         if (k1 == r.k0) continue;
         const int end = k1 < r.k1 ? s->olist[k1].x : r.item_end;
-        MBPT_HIPCHK(ctx, launch_sample_order(a, r.order, 4, prec, r.k0, k1,
+        MBPT_HIPCHK(ctx, launch_sample_order(a, r.order, 4, prec, false, r.k0, k1,
                                              end - s->olist[r.k0].x, kBlock, ctx->stream));
       }
       MBPT_HIPCHK(ctx, launch_finish(a, 0, s->max_slots, j, ctx->desc.alpha, ctx->stream));

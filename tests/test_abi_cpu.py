@@ -194,3 +194,12 @@ def test_turn_table_values():
     before = open(hdr).read()
     subprocess.run([sys.executable, gen], check=True)
     assert open(hdr).read() == before
+
+
+def test_group_members_match_oracle(M, golden):
+    g = golden["n_grp_two_body"]
+    for order, n_grp in zip(g["orders"], g["values"]):
+        lib_groups = {p: M.mbpt_group_members(order, p) for p in range(order + 2)}
+        lib_groups = {p: m for p, m in lib_groups.items() if m}
+        assert len(lib_groups) == n_grp
+        assert lib_groups == O.groups(order)
