@@ -62,6 +62,7 @@ class Problem(ctypes.Structure):
         ("spectrum", ctypes.c_int), ("hf_n", ctypes.c_int), ("hf_kmax", ctypes.c_double),
         ("hf_y", ctypes.POINTER(ctypes.c_double)), ("hf_m", ctypes.POINTER(ctypes.c_double)),
         ("group", ctypes.c_int),
+        ("reg_k", ctypes.c_int), ("reg_eta", ctypes.c_double),
     ]
 
 
@@ -108,6 +109,11 @@ def lib():
         L.orc_group_members.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                         ctypes.c_int]
         L.orc_eval_x.argtypes = [ctypes.POINTER(Problem), dp, ctypes.c_uint64, dp]
+        L.orc_sample_values_reg.argtypes = [ctypes.POINTER(Problem), dp, ctypes.c_uint32,
+                                            ctypes.c_uint64, ctypes.c_uint64, dp]
+        L.orc_integrate_reg.argtypes = [ctypes.POINTER(Problem), dp, ctypes.c_uint64, ctypes.c_int,
+                                        ctypes.c_uint32, ctypes.c_int, dp, dp,
+                                        ctypes.POINTER(Result), dp, dp]
         L.orc_map_samples.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_uint32,
                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                       ctypes.c_uint64, dp, dp, ctypes.POINTER(ctypes.c_int)]
@@ -139,7 +145,7 @@ HF_GAUSS = 64
 
 
 def problem(order, diagram_id=0, density=0.08, proton_fraction=0.0, q=2, seed=1,
-            task_key=0, label_method=0, spectrum=0, group=-1, **kw):
+            task_key=0, label_method=0, spectrum=0, group=-1, reg_k=0, reg_eta=0.0, **kw):
     """group >= 0: the order's diagrams with that many particle-carried loops,
     integrated as one summed integrand (diagram_id is then unused)."""
     p = dict(DEFAULTS)
@@ -149,7 +155,8 @@ def problem(order, diagram_id=0, density=0.08, proton_fraction=0.0, q=2, seed=1,
                  Lambda=p["Lambda"], reg_exp=p["reg_exp"], hbar2_m=p["hbar2_m"],
                  hbarc=p["hbarc"], n_bins=p["n_bins"], alpha=p["alpha"],
                  kcut_extra=p["kcut_extra"], seed=seed, task_key=task_key,
-                 label_method=label_method, spectrum=spectrum, group=group)
+                 label_method=label_method, spectrum=spectrum, group=group, reg_k=reg_k,
+                 reg_eta=reg_eta)
     if spectrum:
         if q == 4 and label_method != 0:
             raise ValueError("HF spectrum in nuclear matter needs the brute-force label sum")
@@ -173,6 +180,33 @@ def groups(order):
         if m:
             out[p] = m
     return out
+
+
+def sample_values_reg(pb, edges, it, first, count):
+    """Regularised components (count, reg_k) of the same samples as sample_values."""
+    out = np.zeros((count, pb.reg_k))
+    rc = lib().orc_sample_values_reg(ctypes.byref(pb), _dp(np.ascontiguousarray(edges)), it,
+                                     first, count, _dp(out))
+    if rc:
+        raise ValueError(f"orc_sample_values_reg -> {rc}")
+    return out
+
+
+def integrate_reg(pb, N, iters, edges=None, nthreads=0):
+    """VEGAS run with the regularised components: (Result, I, var, Ireg[iters, K],
+    Vreg[iters, K], edges)."""
+    d = diagram(pb.order, pb.diagram_id if pb.group < 0 else 0)
+    if edges is None:
+        edges = uniform_grid(d.ndim, pb.n_bins)
+    edges = np.array(edges, dtype=np.float64)
+    I, V = np.zeros(iters), np.zeros(iters)
+    Ir, Vr = np.zeros((iters, pb.reg_k)), np.zeros((iters, pb.reg_k))
+    r = Result()
+    rc = lib().orc_integrate_reg(ctypes.byref(pb), _dp(edges), N, iters, 0, nthreads, _dp(I),
+                                 _dp(V), ctypes.byref(r), _dp(Ir), _dp(Vr))
+    if rc:
+        raise ValueError(f"orc_integrate_reg -> {rc}")
+    return r, I, V, Ir, Vr, edges
 
 
 def eval_x(pb, x):

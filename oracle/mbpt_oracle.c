@@ -398,6 +398,8 @@ typedef struct {
   const double *hf_m;     /* HF: spline second derivatives, same layout */
   int group;              /* -1: diagram_id alone; p >= 0: the group of the order's
                              diagrams with p particle-carried loops (diagram_id unused) */
+  int reg_k;              /* regularised components k = 1..reg_k (at most ORC_MAXREG) */
+  double reg_eta;         /* component k replaces every D_c by D_c - k reg_eta [MeV] */
 } orc_problem;
 
 typedef struct {
@@ -543,8 +545,11 @@ double orc_hf_spline_eval(const orc_problem *pb, int tau, double k) {
  * and every denominator taken in absolute value, times 1 + sum of the
  * denominator and regulator condition numbers) and the largest |D| condition
  * number seen. */
+#define ORC_MAXREG 4
+
 typedef struct {
   double f;
+  double freg[ORC_MAXREG];  /* regularised components k = 1..reg_k */
   double wcond;   /* condition scale, positive */
   double labelsum;
   double labelabs;
@@ -703,10 +708,29 @@ static void eval_point(const orc_problem *pb, const orc_diagram *d,
   out->labelsum = ls;
   out->labelabs = lsabs;
   out->pauli_any = any;
+  for (int k = 0; k < ORC_MAXREG; ++k) out->freg[k] = 0.0;
   if (!any) {
     out->f = 0.0;
     out->wcond = 0.0;
     return;
+  }
+  if (pb->reg_k > 0) {
+    /* regularised denominators D_c - eta_k (D_c < 0 for every allowed
+     * configuration of a Goldstone diagram: the shift moves the pole away) */
+    if (iso_den) {
+      for (int k = 0; k < pb->reg_k; ++k) out->freg[k] = NAN;
+    } else {
+      for (int k = 0; k < pb->reg_k; ++k) {
+        const double eta = (k + 1) * pb->reg_eta;
+        double dk = 1.0;
+        for (int c = 0; c < d->ncuts; ++c) {
+          double D = 0.0;
+          for (int l = 0; l < nl; ++l) D += d->cut[c][l] * eps[l];
+          dk *= D - eta;
+        }
+        out->freg[k] = d->prefactor * measure / pb->density / dk * ls;
+      }
+    }
   }
   if (iso_den) {
     /* denominators already inside ls; lsabs carries the condition terms */
@@ -776,13 +800,15 @@ typedef struct {
   const orc_medium *md;
 } phys_ctx;
 
-static double phys_eval(const void *ctx, const double *x, double *wcond) {
+static double phys_eval(const void *ctx, const double *x, double *wcond, double *wreg) {
   const phys_ctx *c = (const phys_ctx *)ctx;
   double kl[ORC_MAXLOOPS][3];
   double jac = loop_momenta(c->d, c->md, x, kl);
   orc_point pt;
   eval_point(c->pb, c->d, c->md, (const double(*)[3])kl, &pt);
   if (wcond) *wcond = fabs(jac) * pt.wcond;
+  if (wreg)
+    for (int k = 0; k < c->pb->reg_k; ++k) wreg[k] = jac * pt.freg[k];
   return jac * pt.f;
 }
 
@@ -828,7 +854,7 @@ typedef struct {
   int (*canon)[ORC_MAXLOOPS]; /* canon[i][c] = member i's loop at canonical slot c */
 } group_ctx;
 
-static double group_eval(const void *ctx, const double *x, double *wcond) {
+static double group_eval(const void *ctx, const double *x, double *wcond, double *wreg) {
   const group_ctx *g = (const group_ctx *)ctx;
   double kc[ORC_MAXLOOPS][3], jac = 1.0;
   for (int c = 0; c < g->L; ++c) {
@@ -842,7 +868,7 @@ static double group_eval(const void *ctx, const double *x, double *wcond) {
     kc[c][2] = rad * ct;
     jac *= R * rad * rad * 2.0 * (2.0 * M_PI);
   }
-  double f = 0.0, wc = 0.0;
+  double f = 0.0, wc = 0.0, fr[ORC_MAXREG] = {0.0, 0.0, 0.0, 0.0};
   for (int i = 0; i < g->n; ++i) {
     double kl[ORC_MAXLOOPS][3];
     for (int c = 0; c < g->L; ++c)
@@ -851,8 +877,11 @@ static double group_eval(const void *ctx, const double *x, double *wcond) {
     eval_point(g->pb, &g->d[i], g->md, (const double(*)[3])kl, &pt);
     f += pt.f;
     wc += pt.wcond;
+    for (int k = 0; k < g->pb->reg_k; ++k) fr[k] += pt.freg[k];
   }
   if (wcond) *wcond = fabs(jac) * wc;
+  if (wreg)
+    for (int k = 0; k < g->pb->reg_k; ++k) wreg[k] = jac * fr[k];
   return jac * f;
 }
 
@@ -894,7 +923,8 @@ typedef struct {
   int nd;
 } gauss_ctx;
 
-static double gauss_eval(const void *ctx, const double *x, double *wcond) {
+static double gauss_eval(const void *ctx, const double *x, double *wcond, double *wreg) {
+  (void)wreg;
   const gauss_ctx *g = (const gauss_ctx *)ctx;
   double v = 1.0;
   for (int m = 0; m < g->nd; ++m) {
@@ -905,7 +935,8 @@ static double gauss_eval(const void *ctx, const double *x, double *wcond) {
   return v;
 }
 
-typedef double (*integrand_fn)(const void *ctx, const double *x, double *wcond);
+typedef double (*integrand_fn)(const void *ctx, const double *x, double *wcond,
+                               double *wreg);
 
 /* ------------------------------------------------------------------------ */
 /* Exported evaluation entry points                                          */
@@ -943,7 +974,7 @@ int orc_sample_values(const orc_problem *pb, const double *edges, uint32_t iter,
       int bins[ORC_MAXDIM];
       double jv = vegas_map(nd, pb->n_bins, edges, pb->seed, pb->task_key, iter,
                             first + (uint64_t)i, x, bins);
-      double w = group_eval(&g, x, &wc);
+      double w = group_eval(&g, x, &wc, NULL);
       w_out[i] = jv * w;
       if (wcond_out) wcond_out[i] = fabs(jv) * wc;
     }
@@ -959,10 +990,41 @@ int orc_sample_values(const orc_problem *pb, const double *edges, uint32_t iter,
     int bins[ORC_MAXDIM];
     double jv = vegas_map(d.ndim, pb->n_bins, edges, pb->seed, pb->task_key, iter,
                           first + (uint64_t)i, x, bins);
-    double w = phys_eval(&ctx, x, &wc);
+    double w = phys_eval(&ctx, x, &wc, NULL);
     w_out[i] = jv * w;
     if (wcond_out) wcond_out[i] = fabs(jv) * wc;
   }
+  return 0;
+}
+
+/* Regularised components of samples [first, first+count):
+ * wreg_out[i * reg_k + k] (component k + 1, VEGAS Jacobian included). */
+int orc_sample_values_reg(const orc_problem *pb, const double *edges, uint32_t iter,
+                          uint64_t first, uint64_t count, double *wreg_out) {
+  if (pb->reg_k < 1 || pb->reg_k > ORC_MAXREG) return -3;
+  if (pb->q == 2 && pb->proton_fraction != 0.0) return -2;
+  orc_medium md;
+  medium_of(pb, &md);
+  const int nd = 3 * (pb->order + 1), K = pb->reg_k;
+  group_ctx g;
+  orc_diagram d;
+  phys_ctx ctx = {pb, &d, &md};
+  if (pb->group >= 0) {
+    if (group_setup(pb, &md, &g)) return -1;
+  } else if (orc_get_diagram(pb->order, pb->diagram_id, &d)) {
+    return -1;
+  }
+#pragma omp parallel for schedule(static)
+  for (long long i = 0; i < (long long)count; ++i) {
+    double x[ORC_MAXDIM], wr[ORC_MAXREG];
+    int bins[ORC_MAXDIM];
+    double jv = vegas_map(nd, pb->n_bins, edges, pb->seed, pb->task_key, iter,
+                          first + (uint64_t)i, x, bins);
+    if (pb->group >= 0) group_eval(&g, x, NULL, wr);
+    else phys_eval(&ctx, x, NULL, wr);
+    for (int k = 0; k < K; ++k) wreg_out[i * K + k] = jv * wr[k];
+  }
+  if (pb->group >= 0) group_free(&g);
   return 0;
 }
 
@@ -990,14 +1052,14 @@ int orc_eval_x(const orc_problem *pb, const double *x, uint64_t count, double *w
   if (pb->group >= 0) {
     group_ctx g;
     if (group_setup(pb, &md, &g)) return -1;
-    for (uint64_t i = 0; i < count; ++i) w_out[i] = group_eval(&g, x + i * nd, NULL);
+    for (uint64_t i = 0; i < count; ++i) w_out[i] = group_eval(&g, x + i * nd, NULL, NULL);
     group_free(&g);
     return 0;
   }
   orc_diagram d;
   if (orc_get_diagram(pb->order, pb->diagram_id, &d)) return -1;
   phys_ctx ctx = {pb, &d, &md};
-  for (uint64_t i = 0; i < count; ++i) w_out[i] = phys_eval(&ctx, x + i * nd, NULL);
+  for (uint64_t i = 0; i < count; ++i) w_out[i] = phys_eval(&ctx, x + i * nd, NULL, NULL);
   return 0;
 }
 
@@ -1116,18 +1178,24 @@ void orc_combine(int K, const double *I, const double *var, orc_result *res) {
  * order, so results do not depend on the thread count.  The variance sums use
  * the previous iteration's estimate as shift: S1 = sum(w - c),
  * S2 = sum (w - c)^2, I = c + S1/N, var = (S2/N - (S1/N)^2)/(N - 1). */
+/* nreg > 0: the integrand's regularised components are estimated from the
+ * same samples (shifted sums with the main component's shift; the grid
+ * adapts to the main component), per iteration into Ireg/Vreg[it * nreg + k]. */
 static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_key,
                      integrand_fn fn, const void *ctx, double *edges, uint64_t N,
                      int iters, uint32_t first_iter, int nthreads, double *I_out,
-                     double *var_out, orc_result *res) {
+                     double *var_out, orc_result *res, int nreg, double *Ireg,
+                     double *Vreg) {
   if (N < 2 || iters < 1 || nd < 1 || nd > ORC_MAXDIM || nb < 2 || nb > ORC_MAXBINS)
     return -3;
   uint64_t nchunks = (N + ORC_CHUNK - 1) / ORC_CHUNK;
   double *chist = calloc((size_t)nchunks * nd * nb, sizeof(double));
   ksum *cs1 = calloc(nchunks, sizeof(ksum));
   ksum *cs2 = calloc(nchunks, sizeof(ksum));
+  ksum *cr1 = calloc(nchunks * (nreg > 0 ? nreg : 1), sizeof(ksum));
+  ksum *cr2 = calloc(nchunks * (nreg > 0 ? nreg : 1), sizeof(ksum));
   double *I = calloc(iters, sizeof(double)), *V = calloc(iters, sizeof(double));
-  if (!chist || !cs1 || !cs2 || !I || !V) return -4;
+  if (!chist || !cs1 || !cs2 || !cr1 || !cr2 || !I || !V) return -4;
   double shift = 0.0;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -1137,7 +1205,8 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
     memset(chist, 0, sizeof(double) * (size_t)nchunks * nd * nb);
 #pragma omp parallel for schedule(dynamic, 1)
     for (long long c = 0; c < (long long)nchunks; ++c) {
-      ksum s1 = {0, 0}, s2 = {0, 0};
+      ksum s1 = {0, 0}, s2 = {0, 0}, r1[ORC_MAXREG], r2[ORC_MAXREG];
+      for (int k = 0; k < ORC_MAXREG; ++k) r1[k] = r2[k] = (ksum){0, 0};
       double *h = chist + (size_t)c * nd * nb;
       uint64_t s0 = (uint64_t)c * ORC_CHUNK;
       uint64_t s1e = s0 + ORC_CHUNK < N ? s0 + ORC_CHUNK : N;
@@ -1145,13 +1214,35 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
         double x[ORC_MAXDIM];
         int bins[ORC_MAXDIM];
         double jv = vegas_map(nd, nb, edges, seed, task_key, iter, s, x, bins);
-        double w = jv * fn(ctx, x, NULL);
+        double wr[ORC_MAXREG];
+        double w = jv * fn(ctx, x, NULL, nreg > 0 ? wr : NULL);
         ksum_add(&s1, w - shift);
         ksum_add(&s2, (w - shift) * (w - shift));
+        for (int k = 0; k < nreg; ++k) {
+          const double u = jv * wr[k] - shift;
+          ksum_add(&r1[k], u);
+          ksum_add(&r2[k], u * u);
+        }
         for (int m = 0; m < nd; ++m) h[m * nb + bins[m]] += w * w;
       }
       cs1[c] = s1;
       cs2[c] = s2;
+      for (int k = 0; k < nreg; ++k) {
+        cr1[c * nreg + k] = r1[k];
+        cr2[c * nreg + k] = r2[k];
+      }
+    }
+    for (int k = 0; k < nreg; ++k) {
+      ksum R1 = {0, 0}, R2 = {0, 0};
+      for (uint64_t c = 0; c < nchunks; ++c) {
+        ksum_add(&R1, ksum_val(&cr1[c * nreg + k]));
+        ksum_add(&R2, ksum_val(&cr2[c * nreg + k]));
+      }
+      const double q1 = ksum_val(&R1) / (double)N, q2 = ksum_val(&R2) / (double)N;
+      double v = (q2 - q1 * q1) / (double)(N - 1);
+      if (v < 0.0) v = 0.0;
+      if (Ireg) Ireg[(size_t)it * nreg + k] = shift + q1;
+      if (Vreg) Vreg[(size_t)it * nreg + k] = v;
     }
     ksum S1 = {0, 0}, S2 = {0, 0};
     for (uint64_t c = 0; c < nchunks; ++c) {
@@ -1179,14 +1270,15 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
   res->n_evals = N * (uint64_t)iters;
   if (I_out) memcpy(I_out, I, sizeof(double) * iters);
   if (var_out) memcpy(var_out, V, sizeof(double) * iters);
-  free(chist); free(cs1); free(cs2); free(I); free(V);
+  free(chist); free(cs1); free(cs2); free(cr1); free(cr2); free(I); free(V);
   return 0;
 }
 
 /* Full VEGAS run of one diagram at one EOS point. */
-int orc_integrate(const orc_problem *pb, double *edges, uint64_t N, int iters,
-                  uint32_t first_iter, int nthreads, double *I_out,
-                  double *var_out, orc_result *res) {
+int orc_integrate_reg(const orc_problem *pb, double *edges, uint64_t N, int iters,
+                      uint32_t first_iter, int nthreads, double *I_out, double *var_out,
+                      orc_result *res, double *Ireg, double *Vreg) {
+  const int nreg = pb->reg_k > ORC_MAXREG ? ORC_MAXREG : pb->reg_k;
   if (pb->q == 2 && pb->proton_fraction != 0.0) return -2;
   orc_medium md;
   medium_of(pb, &md);
@@ -1195,7 +1287,7 @@ int orc_integrate(const orc_problem *pb, double *edges, uint64_t N, int iters,
     if (group_setup(pb, &md, &g)) return -1;
     int rc = vegas_run(3 * (pb->order + 1), pb->n_bins, pb->alpha, pb->seed, pb->task_key,
                        group_eval, &g, edges, N, iters, first_iter, nthreads, I_out, var_out,
-                       res);
+                       res, nreg, Ireg, Vreg);
     group_free(&g);
     return rc;
   }
@@ -1203,8 +1295,20 @@ int orc_integrate(const orc_problem *pb, double *edges, uint64_t N, int iters,
   if (orc_get_diagram(pb->order, pb->diagram_id, &d)) return -1;
   phys_ctx ctx = {pb, &d, &md};
   return vegas_run(d.ndim, pb->n_bins, pb->alpha, pb->seed, pb->task_key, phys_eval,
-                   &ctx, edges, N, iters, first_iter, nthreads, I_out, var_out, res);
+                   &ctx, edges, N, iters, first_iter, nthreads, I_out, var_out, res, nreg, Ireg,
+                   Vreg);
 }
+
+/* Full VEGAS run of one diagram (or group) at one EOS point. */
+int orc_integrate(const orc_problem *pb, double *edges, uint64_t N, int iters,
+                  uint32_t first_iter, int nthreads, double *I_out,
+                  double *var_out, orc_result *res) {
+  orc_problem p = *pb;
+  p.reg_k = 0;
+  return orc_integrate_reg(&p, edges, N, iters, first_iter, nthreads, I_out, var_out, res, NULL,
+                           NULL);
+}
+
 
 /* VEGAS run of the separable Gaussian test integrand. */
 int orc_integrate_gaussian(int nd, double width, int nb, double alpha, uint32_t seed,
@@ -1213,7 +1317,7 @@ int orc_integrate_gaussian(int nd, double width, int nb, double alpha, uint32_t 
                            orc_result *res) {
   gauss_ctx g = {width, nd};
   return vegas_run(nd, nb, alpha, seed, task_key, gauss_eval, &g, edges, N, iters, 0,
-                   nthreads, I_out, var_out, res);
+                   nthreads, I_out, var_out, res, 0, NULL, NULL);
 }
 
 int orc_max_threads(void) {
