@@ -168,6 +168,19 @@ int mbpt_set_precision(mbpt_context *ctx, int precision);
 /* Switch the single-particle spectrum (MBPT_SPECTRUM_FREE / _HF) for later
  * integrate calls of every task set of the context. */
 int mbpt_set_spectrum(mbpt_context *ctx, int spectrum);
+/* Regularised components (Sec. "Automated approach": the sensitivity to a
+ * parameter added to every energy denominator): with n_eta in 1..4, every
+ * later iteration also estimates, from the same samples, the integrals with
+ * each energy denominator D_c replaced by D_c - k eta (k = 1..n_eta, eta > 0
+ * in MeV; D_c < 0 wherever a Goldstone diagram is allowed, so the shift moves
+ * every pole away).  The VEGAS grid adapts to the unregularised integrand; the
+ * components are evaluated in fp64 whatever the precision, with the free
+ * spectrum only (an HF context gives MBPT_ESTATE at integrate), and the server
+ * refuses them.  n_eta = 0 switches them off.  A task set keeps the setting
+ * its first iteration after a reset ran with: integrate returns MBPT_ESTATE
+ * if it has changed since (call mbpt_reset).  EINVAL on n_eta outside 0..4 or
+ * eta <= 0. */
+int mbpt_set_regularization(mbpt_context *ctx, int n_eta, double eta);
 
 /* ---- diagram generator (host only, no context needed) --------------------- */
 /* Number of two-body energy diagrams of an order (1, 1, 3, 39, 840 for orders
@@ -259,6 +272,34 @@ int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, uint64_t firs
  * memory); computes the tables first if needed.  MBPT_ESTATE unless the
  * context's spectrum is HF and a workspace is bound.  Blocks on the stream. */
 int mbpt_hf_nodes(mbpt_task_set *set, int task, int tau, double *sigma_host, double *h);
+/* Regularised components of samples [first, first+count) of iteration `iter`
+ * of one task (see mbpt_set_regularization; Jacobian included), into
+ * caller-owned host memory wreg_host[count * n_eta], row-major
+ * (wreg_host[i * n_eta + k]: component k + 1 of sample first + i).
+ * MBPT_ESTATE without a workspace or without regularised components (or with
+ * the HF spectrum).  Blocks on the stream. */
+int mbpt_dump_samples_reg(mbpt_task_set *set, int task, uint32_t iter, uint64_t first,
+                          uint64_t count, double *wreg_host);
+/* Per-iteration estimates of the regularised components of a task for the
+ * iterations stored since the last reset (at most max_iters, oldest first):
+ * I[i * n_eta + k], var[i * n_eta + k] for component k + 1 (shifted sums over
+ * the same samples as the main estimate, with its shift).  *count receives
+ * the iterations written (0 if none ran with components).  I, var: host
+ * memory of cap * n_eta doubles, may be NULL. */
+int mbpt_regularized_log(mbpt_task_set *set, int task, double *I, double *var, int cap,
+                         int *count);
+/* Cumulative regularised components of a task and their extrapolation to
+ * eta = 0 (Sec. "Automated approach": a quadratic fitted to the components).  Each component
+ * combines the logged iterations from index skip_iters on by inverse
+ * variance, into E[n_eta] +- sigma[n_eta] (may be NULL).  E0 +- sigma0 (may
+ * be NULL) is the constant term of the weighted least-squares polynomial in
+ * eta_k = k eta of degree min(2, n_eta - 1) (n_eta = 1: the one component);
+ * its error takes the components as independent, which they are not (they
+ * share samples), so it is an indication only.  MBPT_ESTATE without logged
+ * components or with no positive variance after skip_iters; MBPT_ENUMERIC if
+ * the fit is singular. */
+int mbpt_regularized(mbpt_task_set *set, int task, int skip_iters, double *E, double *sigma,
+                     double *E0, double *sigma0);
 /* Grid of a task (ndim x (n_bins+1) edges, host memory) for checkpointing,
  * and its restore.  ndim = 3 (order + 1). */
 int mbpt_get_grid(mbpt_task_set *set, int task, double *edges_host);

@@ -32,6 +32,8 @@ EXPORTED = [
     "mbpt_iteration_log", "mbpt_dump_samples", "mbpt_get_grid", "mbpt_set_grid",
     "mbpt_kernel_stats", "mbpt_task_flops", "mbpt_autotune", "mbpt_server_workspace_query", "mbpt_server_create",
     "mbpt_server_destroy", "mbpt_server_submit", "mbpt_server_step", "mbpt_server_poll",
+    "mbpt_set_regularization", "mbpt_dump_samples_reg", "mbpt_regularized_log",
+    "mbpt_regularized",
 ]
 
 
@@ -98,6 +100,11 @@ def lib():
         "mbpt_set_interaction": [_P, ctypes.POINTER(mbpt_interaction)],
         "mbpt_set_precision": [_P, ctypes.c_int],
         "mbpt_set_spectrum": [_P, ctypes.c_int],
+        "mbpt_set_regularization": [_P, ctypes.c_int, ctypes.c_double],
+        "mbpt_dump_samples_reg": [_P, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
+                                  ctypes.c_uint64, _DP],
+        "mbpt_regularized_log": [_P, ctypes.c_int, _DP, _DP, ctypes.c_int, _IP],
+        "mbpt_regularized": [_P, ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, _DP],
         "mbpt_hf_nodes": [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_double)],
         "mbpt_num_diagrams": [ctypes.c_int, _IP],
@@ -342,6 +349,43 @@ def mbpt_dump_samples(s, task, it, first, count):
     _check(lib().mbpt_dump_samples(s, task, it, first, count,
                                    out.ctypes.data_as(_DP)), _ctx_of_set(s))
     return out
+
+
+def mbpt_set_regularization(ctx, n_eta, eta):
+    _check(lib().mbpt_set_regularization(ctx, n_eta, eta), ctx)
+
+
+def mbpt_dump_samples_reg(s, task, it, first, count, n_eta):
+    """Regularised components (count, n_eta) of samples [first, first + count)."""
+    import numpy as np
+    out = np.empty((count, n_eta), dtype=np.float64)
+    _check(lib().mbpt_dump_samples_reg(s, task, it, first, count, out.ctypes.data_as(_DP)),
+           _ctx_of_set(s))
+    return out
+
+
+def mbpt_regularized_log(s, task, n_eta, cap=1024):
+    """Per-iteration component estimates: (I[iters, n_eta], var[iters, n_eta])."""
+    import numpy as np
+    I = np.zeros((cap, n_eta))
+    V = np.zeros((cap, n_eta))
+    n = ctypes.c_int()
+    _check(lib().mbpt_regularized_log(s, task, I.ctypes.data_as(_DP), V.ctypes.data_as(_DP), cap,
+                                      ctypes.byref(n)), _ctx_of_set(s))
+    return I[:n.value].copy(), V[:n.value].copy()
+
+
+def mbpt_regularized(s, task, n_eta, skip_iters=0):
+    """(E[n_eta], sigma[n_eta], E0, sigma0): cumulative components and their
+    extrapolation to eta = 0."""
+    import numpy as np
+    E = np.zeros(n_eta)
+    S = np.zeros(n_eta)
+    e0 = ctypes.c_double()
+    s0 = ctypes.c_double()
+    _check(lib().mbpt_regularized(s, task, skip_iters, E.ctypes.data_as(_DP), S.ctypes.data_as(_DP),
+                                  ctypes.byref(e0), ctypes.byref(s0)), _ctx_of_set(s))
+    return E, S, e0.value, s0.value
 
 
 def mbpt_get_grid(s, task, ndim, n_bins=50):

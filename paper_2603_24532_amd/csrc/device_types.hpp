@@ -73,6 +73,9 @@ constexpr int kHfEntries = kHfIntervals + 1;
 constexpr double kHfRangeLambda = 6.0;
 constexpr int kHfGauss = 64;  // Gauss-Legendre points per dimension
 
+// Regularised energy-denominator components (D_c -> D_c - k eta, k = 1..nreg).
+constexpr int kMaxReg = 4;
+
 // One task: parameters (host-written) and running state (device-written).
 struct alignas(16) TaskDev {
   int diag, nd, grid_off, hist_off;
@@ -119,6 +122,11 @@ struct KArgs {
   const double *gcoef;    // factorised label-sum coefficients (see coef_slots)
   const int2 *olist;      // (first item, task), grouped by order, ascending items
   double *hf;             // HF spline entries, 4 doubles each
+  double *cpart;          // per item: 2 kMaxReg component sums (regularised modes)
+  double *creslog;        // per logged iteration: kMaxReg (I, var) pairs
+  double reg_eta;         // component k + 1 shifts every denominator by -(k + 1) reg_eta
+  int nreg;               // components (0: none)
+  int pad_reg;
   int ntasks;
   int total_items;
   int spt;                // samples per thread per item

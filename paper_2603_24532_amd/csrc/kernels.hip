@@ -426,11 +426,13 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
 // Contribution of one diagram at the loop momenta k (prefactor, regulators,
 // label sum and denominators; without the Jacobian and 1/n).  HF: single-
 // particle energies of the Hartree-Fock spectrum (tables in LDS).
-template <int ORDER, int Q, bool HF>
+// REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
+// to wr[k - 1].
+template <int ORDER, int Q, bool HF, bool REG>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
-                                                uint32_t &npass, uint32_t &nterms) {
+                                                uint32_t &npass, uint32_t &nterms, double *wr) {
   constexpr int L = ORDER + 1;
   constexpr int NL = 2 * ORDER;
   constexpr int NC = ORDER - 1;
@@ -537,18 +539,30 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 
   const double acc =
       label_sum<ORDER, Q, double, iso_den>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn, deps);
-  return D->pref * regall * acc * rinv[NR - 1];
+  const double base = D->pref * regall * acc;
+  if constexpr (REG) {
+    for (int r = 0; r < a.nreg; ++r) {
+      const double eta = (r + 1) * a.reg_eta;
+      double pk = 1.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) pk *= Dn[c] - eta;
+      wr[r] += base / pk;
+    }
+  }
+  return base * rinv[NR - 1];
 }
 
 // One sample of a task: VEGAS map, loop momenta (radii from the first
 // descriptor: the members of a diagram group share them), then the diagram,
 // or (G) the task's T->ndiag group members summed.
-template <int ORDER, int Q, bool HF, bool G>
+// REG: the regularised components go to wr[0..nreg) (Jacobian and 1/n
+// included).
+template <int ORDER, int Q, bool HF, bool G, bool REG = false>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, uint64_t s,
                                             uint32_t iter, int *bins, uint32_t &npass,
-                                            uint32_t &nterms) {
+                                            uint32_t &nterms, double *wr = nullptr) {
   constexpr int L = ORDER + 1;
   constexpr int ND = 3 * L;
   double x[ND];
@@ -569,16 +583,21 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     k[j][2] = rad * ct;
     jac *= R * rad * rad * (4.0 * M_PI);
   }
+  if constexpr (REG)
+    for (int r = 0; r < kMaxReg; ++r) wr[r] = 0.0;
   double sum;
   if constexpr (G) {
     sum = 0.0;
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di)
-      sum += diag_weight64<ORDER, Q, HF>(a, T, D + di, Ls, k, npass, nterms);
+      sum += diag_weight64<ORDER, Q, HF, REG>(a, T, D + di, Ls, k, npass, nterms, wr);
   } else {
-    sum = diag_weight64<ORDER, Q, HF>(a, T, D, Ls, k, npass, nterms);
+    sum = diag_weight64<ORDER, Q, HF, REG>(a, T, D, Ls, k, npass, nterms, wr);
   }
-  return jac * T->inv_density * sum;
+  const double scale = jac * T->inv_density;
+  if constexpr (REG)
+    for (int r = 0; r < kMaxReg; ++r) wr[r] *= scale;
+  return scale * sum;
 }
 
 // fp32 counterpart of masked_sum
@@ -779,14 +798,19 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
 
 // Kernel mode P: 0 fp64; 1 fp32 with the fp64 fallback; 2 fp64 with the
 // Hartree-Fock spectrum (the fp32 integrand has the free spectrum only);
-// 3 and 4: modes 0 and 1 for diagram groups (tasks of several descriptors).
+// 3 and 4: modes 0 and 1 for diagram groups (tasks of several descriptors);
+// 5 and 6: fp64 with the regularised components, single diagrams / groups.
 template <int P>
 constexpr int prec_of() {
-  return P >= 3 ? P - 3 : P;
+  return (P == 1 || P == 4) ? 1 : (P == 2 ? 2 : 0);
 }
 template <int P>
 constexpr bool group_of() {
-  return P >= 3;
+  return P == 3 || P == 4 || P == 6;
+}
+template <int P>
+constexpr bool reg_of() {
+  return P >= 5;
 }
 
 template <int ORDER, int Q, int P>
@@ -845,6 +869,12 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
   const uint64_t base = static_cast<uint64_t>(item - T->item_begin) * bs * a.spt;
   double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
   uint32_t npass = 0, nterms = 0, nfb = 0;
+  // regularised components: sum (w_k - shift) and sum (w_k - shift)^2 with
+  // the main component's shift (a thread adds at most spt terms: plain sums)
+  constexpr bool R = reg_of<P>();
+  double rs[R ? 2 * kMaxReg : 1];
+#pragma unroll
+  for (int j = 0; j < (R ? 2 * kMaxReg : 1); ++j) rs[j] = 0.0;
   auto accumulate = [&](double w, const int *bins) {
     const double d = w - shift;
     kahan(s1, c1, d);
@@ -862,8 +892,22 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
       if (s < N) {
         int bins[ND];
-        const double w = eval_fp64<ORDER, Q, PP == 2, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
-        accumulate(w, bins);
+        if constexpr (R) {
+          double wr[kMaxReg];
+          const double w =
+              eval_fp64<ORDER, Q, false, G, true>(a, T, D, Ls, s, iter, bins, npass, nterms, wr);
+          accumulate(w, bins);
+#pragma unroll
+          for (int r = 0; r < kMaxReg; ++r) {
+            const double d = wr[r] - shift;
+            rs[2 * r] += d;
+            rs[2 * r + 1] += d * d;
+          }
+        } else {
+          const double w =
+              eval_fp64<ORDER, Q, PP == 2, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
+          accumulate(w, bins);
+        }
       }
     }
   } else {
@@ -922,9 +966,21 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
     npass += __shfl_xor(npass, off, 64);
     nterms += __shfl_xor(nterms, off, 64);
     nfb += __shfl_xor(nfb, off, 64);
+    if constexpr (R) {
+#pragma unroll
+      for (int j = 0; j < 2 * kMaxReg; ++j) rs[j] += __shfl_xor(rs[j], off, 64);
+    }
   }
   const int wave = tid >> 6, lane = tid & 63;
   uint32_t *ured = reinterpret_cast<uint32_t *>(red + 4 * (bs >> 6));
+  // component sums per wave in the (fp64-only, so unused) re-evaluation queue
+  double *rred = red + 6 * (bs >> 6);
+  if constexpr (R) {
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 2 * kMaxReg; ++j) rred[2 * kMaxReg * wave + j] = rs[j];
+    }
+  }
   if (lane == 0) {
     red[4 * wave + 0] = s1;
     red[4 * wave + 1] = c1;
@@ -955,6 +1011,14 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
     K[0] = P0;
     K[1] = P1;
     K[2] = P2;
+    if constexpr (R) {
+      double *cp = a.cpart + 2 * kMaxReg * store;
+      for (int j = 0; j < 2 * kMaxReg; ++j) {
+        double v = rred[j];
+        for (int w = 1; w < (bs >> 6); ++w) v += rred[2 * kMaxReg * w + j];
+        cp[j] = v;
+      }
+    }
   }
   __syncthreads();
   double *hg = a.hists + T->hist_off;
@@ -1105,11 +1169,33 @@ __global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task,
                                                         int step_iter) {
   __shared__ double red[4 * 4];
   __shared__ unsigned long long kred[4][kItemCounters];
+  __shared__ double cred[4][2 * kMaxReg];
   extern __shared__ double scratch[];
   const int t = first_task + blockIdx.x;
   TaskDev *T = a.tasks + t;
   if (!T->active || T->plan <= step_iter) return;
   const int tid = threadIdx.x, bs = blockDim.x;
+  // regularised components (same samples, main component's shift): item
+  // sums in item order per thread, then across the block
+  if (a.nreg > 0) {
+    double cs[2 * kMaxReg];
+#pragma unroll
+    for (int j = 0; j < 2 * kMaxReg; ++j) cs[j] = 0.0;
+    for (int it = T->store_begin + tid; it < T->store_begin + T->nitems; it += bs) {
+      const double *C = a.cpart + 2 * kMaxReg * static_cast<size_t>(it);
+#pragma unroll
+      for (int j = 0; j < 2 * kMaxReg; ++j) cs[j] += C[j];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int j = 0; j < 2 * kMaxReg; ++j) cs[j] += __shfl_xor(cs[j], off, 64);
+    }
+    if ((tid & 63) == 0) {
+#pragma unroll
+      for (int j = 0; j < 2 * kMaxReg; ++j) cred[tid >> 6][j] = cs[j];
+    }
+  }
   double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
   unsigned long long kc[kItemCounters] = {0, 0, 0};
   for (int it = T->store_begin + tid; it < T->store_begin + T->nitems; it += bs) {
@@ -1150,9 +1236,26 @@ __global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task,
     if (var < 0.0) var = 0.0;
     const double I = T->shift + m1;
     if (T->res_cap > 0) {
-      double *lg = a.reslog + 2 * (T->res_off + (T->it_done % T->res_cap));
+      const int slot = T->res_off + (T->it_done % T->res_cap);
+      double *lg = a.reslog + 2 * slot;
       lg[0] = I;
       lg[1] = var;
+      if (a.nreg > 0) {
+        double *cl = a.creslog + 2 * kMaxReg * static_cast<size_t>(slot);
+        for (int r = 0; r < a.nreg; ++r) {
+          double q1 = cred[0][2 * r], q2 = cred[0][2 * r + 1];
+          for (int w = 1; w < (bs >> 6); ++w) {
+            q1 += cred[w][2 * r];
+            q2 += cred[w][2 * r + 1];
+          }
+          q1 /= N;
+          q2 /= N;
+          double v = (q2 - q1 * q1) / (N - 1.0);
+          if (v < 0.0) v = 0.0;
+          cl[2 * r] = T->shift + q1;
+          cl[2 * r + 1] = v;
+        }
+      }
     }
     if (var > 0.0) {
       T->wsum += 1.0 / var;
@@ -1188,9 +1291,11 @@ __global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task,
 // ---------------------------------------------------------------------------
 // Per-sample dump for parity checks: thread i evaluates sample first + i.
 
+// Regularised modes: out_reg (if not null) receives the components,
+// out_reg[i * nreg + k] for component k + 1.
 template <int ORDER, int Q, int P>
 __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t iter, uint64_t first,
-                                                   uint64_t count, double *out) {
+                                                   uint64_t count, double *out, double *out_reg) {
   extern __shared__ double smem[];
   constexpr int ND = 3 * (ORDER + 1);
   const TaskDev *T = a.tasks + t;
@@ -1210,7 +1315,15 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
   if (i < count) {
     int bins[ND];
     uint32_t np = 0, nt = 0, nf = 0;
-    out[i] = eval_sample<ORDER, Q, P>(a, T, D, Ls, first + i, iter, bins, np, nt, nf);
+    if constexpr (reg_of<P>()) {
+      double wr[kMaxReg];
+      out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), true>(a, T, D, Ls, first + i, iter, bins,
+                                                               np, nt, wr);
+      if (out_reg)
+        for (int r = 0; r < a.nreg; ++r) out_reg[i * a.nreg + r] = wr[r];
+    } else {
+      out[i] = eval_sample<ORDER, Q, P>(a, T, D, Ls, first + i, iter, bins, np, nt, nf);
+    }
   }
 }
 
@@ -1332,7 +1445,10 @@ __global__ void init_tasks(KArgs a, int first) {
 
 // Kernel mode from the precision and the spectrum: the HF spectrum runs the
 // fp64 integrand (mode 2) whatever the precision.
+// The regularised components take the fp64 integrand (modes 5, 6) with the
+// free spectrum.
 static int mode_of(const KArgs &a, int prec, bool group) {
+  if (a.nreg > 0) return a.phys.spectrum ? -1 : 5 + (group ? 1 : 0);
   if (a.phys.spectrum) return group ? -1 : 2;  // HF groups are not built
   return (prec ? 1 : 0) + (group ? 3 : 0);
 }
@@ -1364,17 +1480,21 @@ hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int pre
                                 int nitems, int block, hipStream_t st) {
   const int m = mode_of(a, prec, group);
   if (m < 0) return hipErrorInvalidValue;
-  switch (m + 5 * (q == 4)) {
+  switch (m + 7 * (q == 4)) {
     case 0: return single_q<2, 0>(a, t, order, nitems, block, st);
     case 1: return single_q<2, 1>(a, t, order, nitems, block, st);
     case 2: return single_q<2, 2>(a, t, order, nitems, block, st);
     case 3: return single_q<2, 3>(a, t, order, nitems, block, st);
     case 4: return single_q<2, 4>(a, t, order, nitems, block, st);
-    case 5: return single_q<4, 0>(a, t, order, nitems, block, st);
-    case 6: return single_q<4, 1>(a, t, order, nitems, block, st);
-    case 7: return single_q<4, 2>(a, t, order, nitems, block, st);
-    case 8: return single_q<4, 3>(a, t, order, nitems, block, st);
-    case 9: return single_q<4, 4>(a, t, order, nitems, block, st);
+    case 5: return single_q<2, 5>(a, t, order, nitems, block, st);
+    case 6: return single_q<2, 6>(a, t, order, nitems, block, st);
+    case 7: return single_q<4, 0>(a, t, order, nitems, block, st);
+    case 8: return single_q<4, 1>(a, t, order, nitems, block, st);
+    case 9: return single_q<4, 2>(a, t, order, nitems, block, st);
+    case 10: return single_q<4, 3>(a, t, order, nitems, block, st);
+    case 11: return single_q<4, 4>(a, t, order, nitems, block, st);
+    case 12: return single_q<4, 5>(a, t, order, nitems, block, st);
+    case 13: return single_q<4, 6>(a, t, order, nitems, block, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1398,17 +1518,21 @@ hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, bool 
                                int k1, int nitems, int block, hipStream_t st) {
   const int m = mode_of(a, prec, group);
   if (m < 0) return hipErrorInvalidValue;
-  switch (m + 5 * (q == 4)) {
+  switch (m + 7 * (q == 4)) {
     case 0: return order_qp<2, 0>(a, order, k0, k1, nitems, block, st);
     case 1: return order_qp<2, 1>(a, order, k0, k1, nitems, block, st);
     case 2: return order_qp<2, 2>(a, order, k0, k1, nitems, block, st);
     case 3: return order_qp<2, 3>(a, order, k0, k1, nitems, block, st);
     case 4: return order_qp<2, 4>(a, order, k0, k1, nitems, block, st);
-    case 5: return order_qp<4, 0>(a, order, k0, k1, nitems, block, st);
-    case 6: return order_qp<4, 1>(a, order, k0, k1, nitems, block, st);
-    case 7: return order_qp<4, 2>(a, order, k0, k1, nitems, block, st);
-    case 8: return order_qp<4, 3>(a, order, k0, k1, nitems, block, st);
-    case 9: return order_qp<4, 4>(a, order, k0, k1, nitems, block, st);
+    case 5: return order_qp<2, 5>(a, order, k0, k1, nitems, block, st);
+    case 6: return order_qp<2, 6>(a, order, k0, k1, nitems, block, st);
+    case 7: return order_qp<4, 0>(a, order, k0, k1, nitems, block, st);
+    case 8: return order_qp<4, 1>(a, order, k0, k1, nitems, block, st);
+    case 9: return order_qp<4, 2>(a, order, k0, k1, nitems, block, st);
+    case 10: return order_qp<4, 3>(a, order, k0, k1, nitems, block, st);
+    case 11: return order_qp<4, 4>(a, order, k0, k1, nitems, block, st);
+    case 12: return order_qp<4, 5>(a, order, k0, k1, nitems, block, st);
+    case 13: return order_qp<4, 6>(a, order, k0, k1, nitems, block, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1423,37 +1547,42 @@ hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_it
 
 template <int Q, int P>
 static hipError_t dump_q(const KArgs &a, int t, int order, uint32_t iter, uint64_t first,
-                         uint64_t count, double *out, hipStream_t st) {
+                         uint64_t count, double *out, double *out_reg, hipStream_t st) {
   const int block = 256;
   const dim3 grid(static_cast<unsigned>((count + block - 1) / block));
   const size_t lds = kTurnEntries * sizeof(SinCos) + hf_lds_doubles(lds_tables<Q, P>()) * sizeof(double) +
                      2 * static_cast<size_t>(3 * (order + 1)) * a.phys.nb * sizeof(double);
   switch (order) {
-    case 1: hipLaunchKernelGGL((dump_samples<1, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
-    case 2: hipLaunchKernelGGL((dump_samples<2, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
-    case 3: hipLaunchKernelGGL((dump_samples<3, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
-    case 4: hipLaunchKernelGGL((dump_samples<4, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
-    case 5: hipLaunchKernelGGL((dump_samples<5, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out); break;
+    case 1: hipLaunchKernelGGL((dump_samples<1, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 2: hipLaunchKernelGGL((dump_samples<2, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 3: hipLaunchKernelGGL((dump_samples<3, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 4: hipLaunchKernelGGL((dump_samples<4, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 5: hipLaunchKernelGGL((dump_samples<5, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_dump(const KArgs &a, int t, int order, int q, int prec, bool group,
-                       uint32_t iter, uint64_t first, uint64_t count, double *out, hipStream_t st) {
+                       uint32_t iter, uint64_t first, uint64_t count, double *out, double *out_reg,
+                       hipStream_t st) {
   const int m = mode_of(a, prec, group);
   if (m < 0) return hipErrorInvalidValue;
-  switch (m + 5 * (q == 4)) {
-    case 0: return dump_q<2, 0>(a, t, order, iter, first, count, out, st);
-    case 1: return dump_q<2, 1>(a, t, order, iter, first, count, out, st);
-    case 2: return dump_q<2, 2>(a, t, order, iter, first, count, out, st);
-    case 3: return dump_q<2, 3>(a, t, order, iter, first, count, out, st);
-    case 4: return dump_q<2, 4>(a, t, order, iter, first, count, out, st);
-    case 5: return dump_q<4, 0>(a, t, order, iter, first, count, out, st);
-    case 6: return dump_q<4, 1>(a, t, order, iter, first, count, out, st);
-    case 7: return dump_q<4, 2>(a, t, order, iter, first, count, out, st);
-    case 8: return dump_q<4, 3>(a, t, order, iter, first, count, out, st);
-    case 9: return dump_q<4, 4>(a, t, order, iter, first, count, out, st);
+  switch (m + 7 * (q == 4)) {
+    case 0: return dump_q<2, 0>(a, t, order, iter, first, count, out, out_reg, st);
+    case 1: return dump_q<2, 1>(a, t, order, iter, first, count, out, out_reg, st);
+    case 2: return dump_q<2, 2>(a, t, order, iter, first, count, out, out_reg, st);
+    case 3: return dump_q<2, 3>(a, t, order, iter, first, count, out, out_reg, st);
+    case 4: return dump_q<2, 4>(a, t, order, iter, first, count, out, out_reg, st);
+    case 5: return dump_q<2, 5>(a, t, order, iter, first, count, out, out_reg, st);
+    case 6: return dump_q<2, 6>(a, t, order, iter, first, count, out, out_reg, st);
+    case 7: return dump_q<4, 0>(a, t, order, iter, first, count, out, out_reg, st);
+    case 8: return dump_q<4, 1>(a, t, order, iter, first, count, out, out_reg, st);
+    case 9: return dump_q<4, 2>(a, t, order, iter, first, count, out, out_reg, st);
+    case 10: return dump_q<4, 3>(a, t, order, iter, first, count, out, out_reg, st);
+    case 11: return dump_q<4, 4>(a, t, order, iter, first, count, out, out_reg, st);
+    case 12: return dump_q<4, 5>(a, t, order, iter, first, count, out, out_reg, st);
+    case 13: return dump_q<4, 6>(a, t, order, iter, first, count, out, out_reg, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -18,8 +18,11 @@ hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, bool 
 // iteration step_iter of the current launch sequence (plan > step_iter).
 hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_iter, double alpha,
                          hipStream_t st);
+// out_reg (regularised components, count * nreg; may be null) is written only
+// when a.nreg > 0.
 hipError_t launch_dump(const KArgs &a, int task, int order, int q, int prec, bool group,
-                       uint32_t iter, uint64_t first, uint64_t count, double *out, hipStream_t st);
+                       uint32_t iter, uint64_t first, uint64_t count, double *out, double *out_reg,
+                       hipStream_t st);
 hipError_t launch_init(const KArgs &a, int first, int ntasks, hipStream_t st);
 // HF spline tables of tasks [first, first + ntasks): ntab isospin tables each,
 // partners summed over npartner isospins; gl = Gauss-Legendre (x, w) on the

@@ -171,6 +171,18 @@ extern "C" int mbpt_set_spectrum(mbpt_context *ctx, int spectrum) {
   return MBPT_OK;
 }
 
+extern "C" int mbpt_set_regularization(mbpt_context *ctx, int n_eta, double eta) {
+  if (!ctx) return MBPT_EINVAL;
+  if (n_eta < 0 || n_eta > kMaxReg || (n_eta > 0 && !(eta > 0.0 && std::isfinite(eta)))) {
+    set_err(ctx, "set_regularization: n_eta must be 0..4 and eta > 0");
+    return MBPT_EINVAL;
+  }
+  ctx->reg_n = n_eta;
+  ctx->reg_eta = n_eta > 0 ? eta : 0.0;
+  ++ctx->epoch;
+  return MBPT_OK;
+}
+
 extern "C" int mbpt_set_precision(mbpt_context *ctx, int precision) {
   if (!ctx || (precision != MBPT_FP64 && precision != MBPT_FP32)) return MBPT_EINVAL;
   ctx->desc.precision = precision;
@@ -486,7 +498,7 @@ int auto_spt(const mbpt_task_set *set, uint64_t max_samples) {
 
 struct Layout {
   size_t tasks, olist, diags, groups, terms, coefs, grids, hists, partials, counters, reslog, hf,
-      gl, total;
+      gl, cpart, creslog, total;
 };
 
 Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, int nb) {
@@ -529,6 +541,12 @@ Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, 
   off = align256(off + nt * 2 * static_cast<size_t>(kHfEntries) * 4 * sizeof(double));
   L.gl = off;
   off = align256(off + 2 * kHfGauss * sizeof(double));
+  // regularised components: per-item sums and per-iteration estimates
+  L.cpart = off;
+  off = align256(off + items * 2 * kMaxReg * sizeof(double));
+  L.creslog = off;
+  off = align256(off + nt * static_cast<size_t>(std::max(1, max_iters)) * 2 * kMaxReg *
+                           sizeof(double));
   L.total = off;
   return L;
 }
@@ -548,6 +566,10 @@ KArgs kargs_of(const mbpt_task_set *set) {
   a.partials = set->d_partials;
   a.counters = set->d_counters;
   a.reslog = set->d_reslog;
+  a.cpart = set->d_cpart;
+  a.creslog = set->d_creslog;
+  a.nreg = ctx->reg_n;
+  a.reg_eta = ctx->reg_eta;
   a.ntasks = static_cast<int>(set->tasks.size());
   a.total_items = 0;
   a.spt = set->spt;
@@ -632,6 +654,9 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
   set->d_reslog = reinterpret_cast<double *>(base + L.reslog);
   set->d_hf = reinterpret_cast<double *>(base + L.hf);
   set->d_gl = reinterpret_cast<double *>(base + L.gl);
+  set->d_cpart = reinterpret_cast<double *>(base + L.cpart);
+  set->d_creslog = reinterpret_cast<double *>(base + L.creslog);
+  set->run_reg_n = -1;
   set->h_gl.assign(2 * kHfGauss, 0.0);
   gauss_legendre(kHfGauss, set->h_gl.data(), set->h_gl.data() + kHfGauss);
   HIPCHK(ctx, hipMemcpyAsync(set->d_gl, set->h_gl.data(), set->h_gl.size() * sizeof(double),
@@ -866,6 +891,7 @@ extern "C" int mbpt_reset(mbpt_task_set *set) {
   HIPCHK(ctx, launch_init(a, 0, static_cast<int>(set->tasks.size()), ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   set->last_state.clear();
+  set->run_reg_n = -1;
   return MBPT_OK;
 }
 
@@ -953,6 +979,18 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
     set_err(ctx, "integrate: more work items than the workspace holds");
     return MBPT_ENOMEM;
   }
+  // the component log holds one regularisation per run from a reset
+  if (ctx->reg_n > 0 && ctx->desc.spectrum != MBPT_SPECTRUM_FREE) {
+    set_err(ctx, "integrate: regularised components take the free spectrum only");
+    return MBPT_ESTATE;
+  }
+  if (set->run_reg_n >= 0 &&
+      (set->run_reg_n != ctx->reg_n || set->run_reg_eta != ctx->reg_eta)) {
+    set_err(ctx, "integrate: regularisation changed since the set's iterations began (reset first)");
+    return MBPT_ESTATE;
+  }
+  set->run_reg_n = ctx->reg_n;
+  set->run_reg_eta = ctx->reg_eta;
   sync_epoch(set);
   bool changed = false;
   std::vector<int> all(nt);
@@ -1094,12 +1132,159 @@ extern "C" int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, ui
     const uint64_t n = std::min<uint64_t>(cap, count - done);
     HIPCHK(ctx, launch_dump(a, task, set->tasks[task].order, set->q, ctx->desc.precision,
                             set->task_ndiag[task] > 1, iter,
-                            first + done, n, set->d_partials, ctx->stream));
+                            first + done, n, set->d_partials, nullptr, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(w_host + done, set->d_partials, n * sizeof(double),
                                hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     done += n;
   }
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_dump_samples_reg(mbpt_task_set *set, int task, uint32_t iter, uint64_t first,
+                                     uint64_t count, double *wreg_host) {
+  if (!set || !wreg_host || task < 0 || task >= static_cast<int>(set->tasks.size()))
+    return MBPT_EINVAL;
+  if (!set->ws) return MBPT_ESTATE;
+  mbpt_context *ctx = set->ctx;
+  const int K = ctx->reg_n;
+  if (K < 1 || ctx->desc.spectrum != MBPT_SPECTRUM_FREE) {
+    set_err(ctx, "dump_samples_reg: needs regularised components and the free spectrum");
+    return MBPT_ESTATE;
+  }
+  sync_epoch(set);
+  KArgs a = kargs_of(set);
+  // staging: main weights in the item partials, components in the item
+  // component sums (2 kMaxReg doubles per item)
+  const uint64_t cap = set->max_items * 2;
+  for (uint64_t done = 0; done < count;) {
+    const uint64_t n = std::min<uint64_t>(cap, count - done);
+    HIPCHK(ctx, launch_dump(a, task, set->tasks[task].order, set->q, ctx->desc.precision,
+                            set->task_ndiag[task] > 1, iter, first + done, n, set->d_partials,
+                            set->d_cpart, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(wreg_host + done * K, set->d_cpart, n * K * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    done += n;
+  }
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_regularized_log(mbpt_task_set *set, int task, double *I, double *var, int cap,
+                                    int *count) {
+  if (!set || !count || task < 0 || task >= static_cast<int>(set->tasks.size())) return MBPT_EINVAL;
+  if (!set->ws) return MBPT_ESTATE;
+  mbpt_context *ctx = set->ctx;
+  const int K = set->run_reg_n > 0 ? set->run_reg_n : 0;
+  TaskDev S;
+  HIPCHK(ctx, hipMemcpyAsync(&S, set->d_tasks + task, sizeof(TaskDev), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  const size_t per = 2 * static_cast<size_t>(kMaxReg);
+  std::vector<double> lg(per * set->max_iters);
+  HIPCHK(ctx, hipMemcpyAsync(lg.data(), set->d_creslog + per * task * set->max_iters,
+                             lg.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const int n = K > 0 ? std::min(std::min(S.it_done, set->max_iters), cap) : 0;
+  const int start = S.it_done - n;
+  for (int i = 0; i < n; ++i) {
+    const int slot = (start + i) % set->max_iters;
+    for (int k = 0; k < K; ++k) {
+      if (I) I[i * K + k] = lg[per * slot + 2 * k];
+      if (var) var[i * K + k] = lg[per * slot + 2 * k + 1];
+    }
+  }
+  *count = n;
+  return MBPT_OK;
+}
+
+namespace mbpt {
+
+// Weighted least squares of y_k = E_k against polynomials in eta_k of degree
+// deg (normal equations, at most 3 x 3, solved by Gaussian elimination with
+// partial pivoting); returns the constant term and its standard error from
+// the diagonal weights 1 / sigma_k^2.
+bool poly_fit_at_zero(const double *x, const double *y, const double *sig, int n, int deg,
+                      double &c0, double &s0) {
+  const int m = deg + 1;
+  double A[3][4] = {};
+  for (int k = 0; k < n; ++k) {
+    const double w = 1.0 / (sig[k] * sig[k]);
+    double pi[3] = {1.0, x[k], x[k] * x[k]};
+    for (int i = 0; i < m; ++i) {
+      for (int j = 0; j < m; ++j) A[i][j] += w * pi[i] * pi[j];
+      A[i][m] += w * pi[i] * y[k];
+    }
+  }
+  // inverse of the normal matrix (for the variance of c0) by Gauss-Jordan
+  double M[3][6] = {};
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) M[i][j] = A[i][j];
+    M[i][m + i] = 1.0;
+  }
+  for (int c = 0; c < m; ++c) {
+    int p = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(M[r][c]) > std::fabs(M[p][c])) p = r;
+    if (!(std::fabs(M[p][c]) > 0.0)) return false;
+    for (int j = 0; j < 2 * m; ++j) std::swap(M[c][j], M[p][j]);
+    const double d = M[c][c];
+    for (int j = 0; j < 2 * m; ++j) M[c][j] /= d;
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double f = M[r][c];
+      for (int j = 0; j < 2 * m; ++j) M[r][j] -= f * M[c][j];
+    }
+  }
+  c0 = 0.0;
+  for (int j = 0; j < m; ++j) c0 += M[0][m + j] * A[j][m];
+  s0 = std::sqrt(std::max(0.0, M[0][m]));
+  return true;
+}
+
+}  // namespace mbpt
+
+extern "C" int mbpt_regularized(mbpt_task_set *set, int task, int skip_iters, double *E,
+                                double *sigma, double *E0, double *sigma0) {
+  if (!set || task < 0 || task >= static_cast<int>(set->tasks.size()) || skip_iters < 0)
+    return MBPT_EINVAL;
+  if (!set->ws) return MBPT_ESTATE;
+  mbpt_context *ctx = set->ctx;
+  const int K = set->run_reg_n;
+  if (K < 1) {
+    set_err(ctx, "regularized: no iterations with regularised components since the last reset");
+    return MBPT_ESTATE;
+  }
+  std::vector<double> I(static_cast<size_t>(set->max_iters) * K), V(I.size());
+  int n = 0;
+  const int rc = mbpt_regularized_log(set, task, I.data(), V.data(), set->max_iters, &n);
+  if (rc) return rc;
+  double Ek[kMaxReg], Sk[kMaxReg], eta[kMaxReg];
+  for (int k = 0; k < K; ++k) {
+    double w = 0.0, wi = 0.0;
+    for (int i = skip_iters; i < n; ++i) {
+      const double v = V[static_cast<size_t>(i) * K + k];
+      if (v > 0.0) {
+        w += 1.0 / v;
+        wi += I[static_cast<size_t>(i) * K + k] / v;
+      }
+    }
+    if (!(w > 0.0)) {
+      set_err(ctx, "regularized: no iteration with a positive variance after the skipped ones");
+      return MBPT_ESTATE;
+    }
+    Ek[k] = wi / w;
+    Sk[k] = 1.0 / std::sqrt(w);
+    eta[k] = (k + 1) * set->run_reg_eta;
+    if (E) E[k] = Ek[k];
+    if (sigma) sigma[k] = Sk[k];
+  }
+  double c0 = Ek[0], s0 = Sk[0];
+  if (K > 1 && !mbpt::poly_fit_at_zero(eta, Ek, Sk, K, std::min(2, K - 1), c0, s0)) {
+    set_err(ctx, "regularized: singular extrapolation fit");
+    return MBPT_ENUMERIC;
+  }
+  if (E0) *E0 = c0;
+  if (sigma0) *sigma0 = s0;
   return MBPT_OK;
 }
 

@@ -43,6 +43,8 @@ struct mbpt_context {
   uint64_t evals = 0;
   double flops = 0.0;
   uint64_t epoch = 0;  // bumped when precision or interaction changes
+  int reg_n = 0;         // regularised components (0: none)
+  double reg_eta = 0.0;  // component k shifts every denominator by -k reg_eta
 };
 
 struct mbpt_task_set {
@@ -79,6 +81,11 @@ struct mbpt_task_set {
   bool hf_dirty = true;     // HF tables must be (re)computed before use
   std::vector<double> h_gl; // host copy of the rule (source of an async copy)
   double *d_grids = nullptr, *d_hists = nullptr, *d_partials = nullptr, *d_reslog = nullptr;
+  double *d_cpart = nullptr, *d_creslog = nullptr;  // regularised components
+  // regularisation the logged iterations ran with (fixed from the first
+  // iteration after a reset)
+  int run_reg_n = -1;
+  double run_reg_eta = 0.0;
   uint64_t *d_counters = nullptr;
   std::vector<int2> olist;                 // (first item, task) grouped by order
   std::vector<mbpt::OrderRange> oranges;   // one sample launch per order

@@ -423,8 +423,9 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
       (reinterpret_cast<uintptr_t>(device_ptr) & 255u))
     return MBPT_EINVAL;
   *out = nullptr;
-  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE) {
-    set_err(ctx, "server_create: the server supports the free spectrum only");
+  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE || ctx->reg_n > 0) {
+    set_err(ctx, "server_create: the server supports the free spectrum without regularised "
+                 "components only");
     return MBPT_EINVAL;
   }
   Layout L{};
@@ -504,8 +505,9 @@ extern "C" int mbpt_server_submit(mbpt_server *s, const mbpt_request *req, uint6
 extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
   if (!s) return MBPT_EINVAL;
   mbpt_context *ctx = s->ctx;
-  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE) {
-    set_err(ctx, "server_step: the server supports the free spectrum only");
+  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE || ctx->reg_n > 0) {
+    set_err(ctx, "server_step: the server supports the free spectrum without regularised "
+                 "components only");
     return MBPT_ESTATE;
   }
   while (!s->queue.empty()) {
