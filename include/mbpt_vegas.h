@@ -57,7 +57,8 @@ enum { MBPT_FP64 = 0, MBPT_FP32 = 1 };
  * isospin-dependent Pauli factors, any proton fraction in [0, 1]. */
 enum { MBPT_NEUTRON = 0, MBPT_NUCLEAR = 1 };
 /* How mbpt_integrate launches work.  PER_TASK: one sample launch per task and
- * iteration (the plain path); BATCHED: one persistent launch per iteration
+ * iteration (the plain path; within an iteration the tasks in turn, then one
+ * iteration-end launch for all of them); BATCHED: one persistent launch per iteration
  * covering every task of the set; GRAPH: BATCHED with the whole iteration
  * sequence captured once into a HIP graph and replayed (needs a non-default
  * stream: EINVAL on the null stream). */

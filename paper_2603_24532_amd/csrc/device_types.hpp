@@ -76,6 +76,11 @@ constexpr int kHfGauss = 64;  // Gauss-Legendre points per dimension
 // Regularised energy-denominator components (D_c -> D_c - k eta, k = 1..nreg).
 constexpr int kMaxReg = 4;
 
+// Iteration-end kernel: threads per task block and item loads in flight per
+// thread.
+constexpr int kFinishThreads = 1024;
+constexpr int kFinishBatch = 4;
+
 // One task: parameters (host-written) and running state (device-written).
 struct alignas(16) TaskDev {
   int diag, nd, grid_off, hist_off;

@@ -1165,23 +1165,28 @@ __device__ void refine_dim_wave(double *hist, double *edges, int nb, double alph
 
 // step_iter: index of this iteration within the launch sequence; tasks whose
 // plan ends before it sit this iteration out.
-__global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task, double alpha,
-                                                        int step_iter) {
-  __shared__ double red[4 * 4];
-  __shared__ unsigned long long kred[4][kItemCounters];
-  __shared__ double cred[4][2 * kMaxReg];
+// One block of kFinishThreads per task: every thread reduces a strided set of
+// item partials (loads of kFinishBatch items issued together, merged in item
+// order), then the waves reduce in order and each wave refines dimensions.
+__global__ __launch_bounds__(kFinishThreads) void finish_iteration(KArgs a, int first_task,
+                                                                   double alpha, int step_iter) {
+  constexpr int NW = kFinishThreads / 64;
+  __shared__ double red[NW * 4];
+  __shared__ unsigned long long kred[NW][kItemCounters];
+  __shared__ double cred[NW][2 * kMaxReg];
   extern __shared__ double scratch[];
   const int t = first_task + blockIdx.x;
   TaskDev *T = a.tasks + t;
   if (!T->active || T->plan <= step_iter) return;
   const int tid = threadIdx.x, bs = blockDim.x;
+  const int it0 = T->store_begin, it1 = T->store_begin + T->nitems;
   // regularised components (same samples, main component's shift): item
   // sums in item order per thread, then across the block
   if (a.nreg > 0) {
     double cs[2 * kMaxReg];
 #pragma unroll
     for (int j = 0; j < 2 * kMaxReg; ++j) cs[j] = 0.0;
-    for (int it = T->store_begin + tid; it < T->store_begin + T->nitems; it += bs) {
+    for (int it = it0 + tid; it < it1; it += bs) {
       const double *C = a.cpart + 2 * kMaxReg * static_cast<size_t>(it);
 #pragma unroll
       for (int j = 0; j < 2 * kMaxReg; ++j) cs[j] += C[j];
@@ -1198,11 +1203,28 @@ __global__ __launch_bounds__(256) void finish_iteration(KArgs a, int first_task,
   }
   double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
   unsigned long long kc[kItemCounters] = {0, 0, 0};
-  for (int it = T->store_begin + tid; it < T->store_begin + T->nitems; it += bs) {
-    const double *P = a.partials + 4 * static_cast<size_t>(it);
-    pair_merge(s1, c1, P[0], P[1]);
-    pair_merge(s2, c2, P[2], P[3]);
-    for (int j = 0; j < kItemCounters; ++j) kc[j] += a.counters[kItemCounters * static_cast<size_t>(it) + j];
+  for (int b0 = it0 + tid; b0 < it1; b0 += kFinishBatch * bs) {
+    double4 P[kFinishBatch];
+    unsigned long long K[kFinishBatch][kItemCounters];
+#pragma unroll
+    for (int u = 0; u < kFinishBatch; ++u) {
+      const int it = b0 + u * bs;
+      if (it < it1) {
+        P[u] = reinterpret_cast<const double4 *>(a.partials)[it];
+#pragma unroll
+        for (int j = 0; j < kItemCounters; ++j)
+          K[u][j] = a.counters[kItemCounters * static_cast<size_t>(it) + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kFinishBatch; ++u) {
+      if (b0 + u * bs < it1) {
+        pair_merge(s1, c1, P[u].x, P[u].y);
+        pair_merge(s2, c2, P[u].z, P[u].w);
+#pragma unroll
+        for (int j = 0; j < kItemCounters; ++j) kc[j] += K[u][j];
+      }
+    }
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -1539,9 +1561,10 @@ hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, bool 
 
 hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_iter, double alpha,
                          hipStream_t st) {
-  const size_t lds = 4 * static_cast<size_t>(2 * a.phys.nb + 2) * sizeof(double);
-  hipLaunchKernelGGL(finish_iteration, dim3(ntasks), dim3(256), lds, st, a, first_task, alpha,
-                     step_iter);
+  const size_t lds =
+      (kFinishThreads / 64) * static_cast<size_t>(2 * a.phys.nb + 2) * sizeof(double);
+  hipLaunchKernelGGL(finish_iteration, dim3(ntasks), dim3(kFinishThreads), lds, st, a, first_task,
+                     alpha, step_iter);
   return hipGetLastError();
 }
 

@@ -903,16 +903,19 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
   const int nt = static_cast<int>(set->tasks.size());
   const double alpha = ctx->desc.alpha;
   if (set->launch_mode == MBPT_LAUNCH_PER_TASK) {
-    for (int t = 0; t < nt; ++t)
-      for (int it = 0; it < iters; ++it) {
+    // one sample launch per task and iteration; the iteration ends of all
+    // tasks (independent of each other) share one launch
+    for (int it = 0; it < iters; ++it) {
+      for (int t = 0; t < nt; ++t) {
         size_t slot = 0;
         if (timed) timed_begin(ctx, slot);
         HIPCHK(ctx, launch_sample_single(a, t, set->tasks[t].order, set->q, ctx->desc.precision,
                                          set->task_ndiag[t] > 1,
                                          set->h_tasks[t].nitems, set->block, ctx->stream));
         if (timed) timed_end(ctx, slot);
-        HIPCHK(ctx, launch_finish(a, t, 1, 0, alpha, ctx->stream));
       }
+      HIPCHK(ctx, launch_finish(a, 0, nt, 0, alpha, ctx->stream));
+    }
     return MBPT_OK;
   }
   for (int it = 0; it < iters; ++it) {
