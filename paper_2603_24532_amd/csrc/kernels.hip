@@ -358,7 +358,9 @@ __device__ __forceinline__ double group_den(const DiagDev *__restrict__ D, uint3
 }
 
 // ISO: divide each configuration's sum by its own denominators (Dn, deps).
-template <int ORDER, int Q, typename F, bool ISO>
+// X: the explicit assignment list instead of the polynomial (compile-time, so
+// a kernel holds the state of one form only).
+template <int ORDER, int Q, typename F, bool ISO, bool X>
 __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict__ D,
                                        const F *Vd, const F *Ve, uint32_t okN, uint32_t okP,
                                        uint32_t lmask, uint32_t &units, const double *Dn,
@@ -366,7 +368,7 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
   const GroupDev *__restrict__ G = a.groups + D->group_off;
   const int ngroups = D->ngroups;
   F acc = F(0);
-  if (a.label_mode == 0) {
+  if constexpr (!X) {
     constexpr int H = ORDER / 2;
     constexpr int NA = 1 << H, NB = 1 << (ORDER - H);
     F MA[NA], MB[NB];
@@ -428,7 +430,7 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
 // particle energies of the Hartree-Fock spectrum (tables in LDS).
 // REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
 // to wr[k - 1].
-template <int ORDER, int Q, bool HF, bool REG>
+template <int ORDER, int Q, bool HF, bool REG, bool X>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
@@ -538,7 +540,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   const double regall = exp(-yreg * a.phys.invLn);
 
   const double acc =
-      label_sum<ORDER, Q, double, iso_den>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn, deps);
+      label_sum<ORDER, Q, double, iso_den, X>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn, deps);
   const double base = D->pref * regall * acc;
   if constexpr (REG) {
     for (int r = 0; r < a.nreg; ++r) {
@@ -557,7 +559,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 // or (G) the task's T->ndiag group members summed.
 // REG: the regularised components go to wr[0..nreg) (Jacobian and 1/n
 // included).
-template <int ORDER, int Q, bool HF, bool G, bool REG = false>
+template <int ORDER, int Q, bool HF, bool G, bool X, bool REG = false>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, uint64_t s,
@@ -590,9 +592,9 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     sum = 0.0;
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di)
-      sum += diag_weight64<ORDER, Q, HF, REG>(a, T, D + di, Ls, k, npass, nterms, wr);
+      sum += diag_weight64<ORDER, Q, HF, REG, X>(a, T, D + di, Ls, k, npass, nterms, wr);
   } else {
-    sum = diag_weight64<ORDER, Q, HF, REG>(a, T, D, Ls, k, npass, nterms, wr);
+    sum = diag_weight64<ORDER, Q, HF, REG, X>(a, T, D, Ls, k, npass, nterms, wr);
   }
   const double scale = jac * T->inv_density;
   if constexpr (REG)
@@ -636,7 +638,7 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 // sample in fp64 from the same random words.
 // fp32 contribution of one diagram at the loop momenta k (see
 // diag_weight64); sets `fallback` instead when the sample needs fp64.
-template <int ORDER, int Q>
+template <int ORDER, int Q, bool X>
 __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const float (*k)[3], uint32_t &npass,
@@ -747,13 +749,14 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   const float regall = __expf(-yexp);
 
   const float acc =
-      label_sum<ORDER, Q, float, false>(a, D, Vd, Ve, okN, okP, lmask, nterms, nullptr, nullptr);
+      label_sum<ORDER, Q, float, false, X>(a, D, Vd, Ve, okN, okP, lmask, nterms, nullptr,
+                                           nullptr);
   ++npass;
   return D->pref * static_cast<double>(regall) * static_cast<double>(acc) *
          static_cast<double>(rinv[NR - 1]);
 }
 
-template <int ORDER, int Q, bool G>
+template <int ORDER, int Q, bool G, bool X>
 __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, uint64_t s,
@@ -786,11 +789,11 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     sum = 0.0;
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di) {
-      sum += diag_weight32<ORDER, Q>(a, T, D + di, k, npass, nterms, fallback);
+      sum += diag_weight32<ORDER, Q, X>(a, T, D + di, k, npass, nterms, fallback);
       if (fallback) return 0.0;  // the whole sample is re-evaluated in fp64
     }
   } else {
-    sum = diag_weight32<ORDER, Q>(a, T, D, k, npass, nterms, fallback);
+    sum = diag_weight32<ORDER, Q, X>(a, T, D, k, npass, nterms, fallback);
     if (fallback) return 0.0;
   }
   return jac * T->inv_density * sum;
@@ -813,7 +816,7 @@ constexpr bool reg_of() {
   return P >= 5;
 }
 
-template <int ORDER, int Q, int P>
+template <int ORDER, int Q, int P, bool X>
 __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__restrict__ T,
                                               const DiagDev *__restrict__ D,
                                               const SampleLds &Ls, uint64_t s,
@@ -821,12 +824,13 @@ __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__r
                                               uint32_t &nterms, uint32_t &nfb) {
   constexpr int PP = prec_of<P>();
   constexpr bool G = group_of<P>();
-  if (PP != 1) return eval_fp64<ORDER, Q, PP == 2, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
+  if (PP != 1)
+    return eval_fp64<ORDER, Q, PP == 2, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms);
   bool fb = false;
-  double w = eval_fp32<ORDER, Q, G>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
+  double w = eval_fp32<ORDER, Q, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
   if (fb) {
     ++nfb;
-    w = eval_fp64<ORDER, Q, false, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
+    w = eval_fp64<ORDER, Q, false, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms);
   }
   return w;
 }
@@ -840,7 +844,7 @@ constexpr int lds_tables() {
 // ---------------------------------------------------------------------------
 // Work item: blockDim.x * spt consecutive samples of one task
 
-template <int ORDER, int Q, int P>
+template <int ORDER, int Q, int P, bool X>
 __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, double *smem) {
   constexpr int ND = 3 * (ORDER + 1);
   const TaskDev *__restrict__ T = a.tasks + t;
@@ -895,7 +899,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
         if constexpr (R) {
           double wr[kMaxReg];
           const double w =
-              eval_fp64<ORDER, Q, false, G, true>(a, T, D, Ls, s, iter, bins, npass, nterms, wr);
+              eval_fp64<ORDER, Q, false, G, X, true>(a, T, D, Ls, s, iter, bins, npass, nterms, wr);
           accumulate(w, bins);
 #pragma unroll
           for (int r = 0; r < kMaxReg; ++r) {
@@ -905,7 +909,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
           }
         } else {
           const double w =
-              eval_fp64<ORDER, Q, PP == 2, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
+              eval_fp64<ORDER, Q, PP == 2, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms);
           accumulate(w, bins);
         }
       }
@@ -921,7 +925,8 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       if (lane < take) {
         const uint64_t s = base + queue[lane];
         int bins[ND];
-        const double w = eval_fp64<ORDER, Q, false, G>(a, T, D, Ls, s, iter, bins, npass, nterms);
+        const double w =
+            eval_fp64<ORDER, Q, false, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms);
         accumulate(w, bins);
       }
       __builtin_amdgcn_wave_barrier();
@@ -937,7 +942,8 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       bool fb = false;
       if (s < N) {
         int bins[ND];
-        const double w = eval_fp32<ORDER, Q, G>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
+        const double w =
+            eval_fp32<ORDER, Q, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
         if (!fb) accumulate(w, bins);
       }
       const uint64_t mask = __ballot(fb);
@@ -1038,10 +1044,10 @@ constexpr int min_waves() {
   return (ORDER == 5 && (prec_of<P>() == 1 || group_of<P>())) ? 2 : 1;
 }
 
-template <int ORDER, int Q, int P>
+template <int ORDER, int Q, int P, bool X>
 __global__ __launch_bounds__(256, (min_waves<ORDER, P>())) void sample_single(KArgs a, int t) {
   extern __shared__ double smem[];
-  process_item<ORDER, Q, P>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
+  process_item<ORDER, Q, P, X>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
 }
 
 // One launch over the work items of the tasks of one order: olist[k0, k1)
@@ -1049,7 +1055,7 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, P>())) void sample_single(KA
 // numbered contiguously from olist[k0].x, and block b takes item
 // olist[k0].x + b.  One launch per order keeps each launch's register
 // allocation that of its own order.
-template <int ORDER, int Q, int P>
+template <int ORDER, int Q, int P, bool X>
 __global__ __launch_bounds__(256, (min_waves<ORDER, P>())) void sample_order(KArgs a, int k0, int k1) {
   extern __shared__ double smem[];
   const int2 *__restrict__ ol = a.olist;
@@ -1060,7 +1066,7 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, P>())) void sample_order(KAr
     if (ol[mid].x <= item) lo = mid;
     else hi = mid - 1;
   }
-  process_item<ORDER, Q, P>(a, ol[lo].y, item, smem);
+  process_item<ORDER, Q, P, X>(a, ol[lo].y, item, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1315,7 +1321,7 @@ __global__ __launch_bounds__(kFinishThreads) void finish_iteration(KArgs a, int 
 
 // Regularised modes: out_reg (if not null) receives the components,
 // out_reg[i * nreg + k] for component k + 1.
-template <int ORDER, int Q, int P>
+template <int ORDER, int Q, int P, bool X>
 __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t iter, uint64_t first,
                                                    uint64_t count, double *out, double *out_reg) {
   extern __shared__ double smem[];
@@ -1339,12 +1345,12 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
     uint32_t np = 0, nt = 0, nf = 0;
     if constexpr (reg_of<P>()) {
       double wr[kMaxReg];
-      out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), true>(a, T, D, Ls, first + i, iter, bins,
-                                                               np, nt, wr);
+      out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, true>(a, T, D, Ls, first + i, iter,
+                                                                  bins, np, nt, wr);
       if (out_reg)
         for (int r = 0; r < a.nreg; ++r) out_reg[i * a.nreg + r] = wr[r];
     } else {
-      out[i] = eval_sample<ORDER, Q, P>(a, T, D, Ls, first + i, iter, bins, np, nt, nf);
+      out[i] = eval_sample<ORDER, Q, P, X>(a, T, D, Ls, first + i, iter, bins, np, nt, nf);
     }
   }
 }
@@ -1483,19 +1489,28 @@ size_t sample_lds_bytes(int nd, int nb, int block, int ntab) {
          (block / 64) * 128 * sizeof(uint32_t);
 }
 
-template <int Q, int P>
-static hipError_t single_q(const KArgs &a, int t, int order, int nitems, int block,
-                           hipStream_t st) {
+template <int Q, int P, bool X>
+static hipError_t single_qx(const KArgs &a, int t, int order, int nitems, int block,
+                            hipStream_t st) {
   const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block, lds_tables<Q, P>());
   switch (order) {
-    case 1: hipLaunchKernelGGL((sample_single<1, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 2: hipLaunchKernelGGL((sample_single<2, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 3: hipLaunchKernelGGL((sample_single<3, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 4: hipLaunchKernelGGL((sample_single<4, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 5: hipLaunchKernelGGL((sample_single<5, Q, P>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 1: hipLaunchKernelGGL((sample_single<1, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 2: hipLaunchKernelGGL((sample_single<2, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 3: hipLaunchKernelGGL((sample_single<3, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 4: hipLaunchKernelGGL((sample_single<4, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 5: hipLaunchKernelGGL((sample_single<5, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// The label-sum form is a kernel template parameter: each kernel holds the
+// registers of one form only.
+template <int Q, int P>
+static hipError_t single_q(const KArgs &a, int t, int order, int nitems, int block,
+                           hipStream_t st) {
+  return a.label_mode ? single_qx<Q, P, true>(a, t, order, nitems, block, st)
+                      : single_qx<Q, P, false>(a, t, order, nitems, block, st);
 }
 
 hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int prec, bool group,
@@ -1521,19 +1536,26 @@ hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int pre
   }
 }
 
-template <int Q, int P>
-static hipError_t order_qp(const KArgs &a, int order, int k0, int k1, int grid, int block,
-                           hipStream_t st) {
+template <int Q, int P, bool X>
+static hipError_t order_qpx(const KArgs &a, int order, int k0, int k1, int grid, int block,
+                            hipStream_t st) {
   const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block, lds_tables<Q, P>());
   switch (order) {
-    case 1: hipLaunchKernelGGL((sample_order<1, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 2: hipLaunchKernelGGL((sample_order<2, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 3: hipLaunchKernelGGL((sample_order<3, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 4: hipLaunchKernelGGL((sample_order<4, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 5: hipLaunchKernelGGL((sample_order<5, Q, P>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 1: hipLaunchKernelGGL((sample_order<1, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 2: hipLaunchKernelGGL((sample_order<2, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 3: hipLaunchKernelGGL((sample_order<3, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 4: hipLaunchKernelGGL((sample_order<4, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 5: hipLaunchKernelGGL((sample_order<5, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int Q, int P>
+static hipError_t order_qp(const KArgs &a, int order, int k0, int k1, int grid, int block,
+                           hipStream_t st) {
+  return a.label_mode ? order_qpx<Q, P, true>(a, order, k0, k1, grid, block, st)
+                      : order_qpx<Q, P, false>(a, order, k0, k1, grid, block, st);
 }
 
 hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, bool group, int k0,
@@ -1568,22 +1590,29 @@ hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_it
   return hipGetLastError();
 }
 
-template <int Q, int P>
-static hipError_t dump_q(const KArgs &a, int t, int order, uint32_t iter, uint64_t first,
-                         uint64_t count, double *out, double *out_reg, hipStream_t st) {
+template <int Q, int P, bool X>
+static hipError_t dump_qx(const KArgs &a, int t, int order, uint32_t iter, uint64_t first,
+                          uint64_t count, double *out, double *out_reg, hipStream_t st) {
   const int block = 256;
   const dim3 grid(static_cast<unsigned>((count + block - 1) / block));
   const size_t lds = kTurnEntries * sizeof(SinCos) + hf_lds_doubles(lds_tables<Q, P>()) * sizeof(double) +
                      2 * static_cast<size_t>(3 * (order + 1)) * a.phys.nb * sizeof(double);
   switch (order) {
-    case 1: hipLaunchKernelGGL((dump_samples<1, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
-    case 2: hipLaunchKernelGGL((dump_samples<2, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
-    case 3: hipLaunchKernelGGL((dump_samples<3, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
-    case 4: hipLaunchKernelGGL((dump_samples<4, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
-    case 5: hipLaunchKernelGGL((dump_samples<5, Q, P>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 1: hipLaunchKernelGGL((dump_samples<1, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 2: hipLaunchKernelGGL((dump_samples<2, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 3: hipLaunchKernelGGL((dump_samples<3, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 4: hipLaunchKernelGGL((dump_samples<4, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 5: hipLaunchKernelGGL((dump_samples<5, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int Q, int P>
+static hipError_t dump_q(const KArgs &a, int t, int order, uint32_t iter, uint64_t first,
+                         uint64_t count, double *out, double *out_reg, hipStream_t st) {
+  return a.label_mode ? dump_qx<Q, P, true>(a, t, order, iter, first, count, out, out_reg, st)
+                      : dump_qx<Q, P, false>(a, t, order, iter, first, count, out, out_reg, st);
 }
 
 hipError_t launch_dump(const KArgs &a, int t, int order, int q, int prec, bool group,
