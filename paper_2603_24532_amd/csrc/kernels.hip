@@ -57,20 +57,32 @@ struct alignas(16) SinCos {
 };
 constexpr int kTurnEntries = MBPT_TURN_STEPS + 1;
 __constant__ SinCos kTurnDev[kTurnEntries] = {MBPT_TURN_TABLE_INIT};
+// 2^(j / 64), j = 0..63 (the table-driven exponential, copied into LDS beside
+// the turn table)
+constexpr int kExp2Entries = 64;
+__constant__ double kExp2Dev[kExp2Entries] = {MBPT_EXP2_TABLE_INIT};
 
-__device__ __forceinline__ void load_turn_table(SinCos *dst) {
+__device__ __forceinline__ void load_turn_table(SinCos *dst, double *ex) {
   for (int i = threadIdx.x; i < kTurnEntries; i += blockDim.x) dst[i] = kTurnDev[i];
+  for (int i = threadIdx.x; i < kExp2Entries; i += blockDim.x) ex[i] = kExp2Dev[i];
 }
 
-// What the integrand reads from LDS: the turn table, the HF spline entries of
-// the task (ntab isospin tables of kHfEntries x 4 doubles, absent with the
-// free spectrum) and the grid (e, width) pairs.  Block layout: turn table, HF
-// tables, grid pairs, then the kernel's own scratch.
+// What the integrand reads from LDS: the turn table, the 2^(j/64) table, the
+// HF spline entries of the task (ntab isospin tables of kHfEntries x 4
+// doubles, absent with the free spectrum) and the grid pairs (e_b + w_b 2^-33,
+// w_b).  Block layout: turn table, 2^(j/64) table, HF tables, grid pairs, then
+// the kernel's own scratch.
 struct SampleLds {
   const SinCos *turn;
+  const double *ex;
   const double *hf;
   const double2 *g;
 };
+
+// Bytes of the fixed tables at the start of a sample kernel's LDS.
+__host__ __device__ constexpr size_t fixed_lds_bytes() {
+  return kTurnEntries * sizeof(SinCos) + kExp2Entries * sizeof(double);
+}
 
 __host__ __device__ constexpr size_t hf_lds_doubles(int ntab) {
   return static_cast<size_t>(ntab) * kHfEntries * 4;
@@ -83,15 +95,17 @@ __device__ __forceinline__ double *carve_lds(const KArgs &a, const TaskDev *__re
                                              int ntab, int nd, double *smem, SampleLds &L,
                                              double2 *&g) {
   SinCos *turn = reinterpret_cast<SinCos *>(smem);
-  double *hf = reinterpret_cast<double *>(turn + kTurnEntries);
+  double *ex = reinterpret_cast<double *>(turn + kTurnEntries);
+  double *hf = ex + kExp2Entries;
   g = reinterpret_cast<double2 *>(hf + hf_lds_doubles(ntab));
-  load_turn_table(turn);
+  load_turn_table(turn, ex);
   if (ntab) {
     const double *src = a.hf + 4 * static_cast<size_t>(T->hf_off);
     const int n = static_cast<int>(hf_lds_doubles(ntab));
     for (int i = threadIdx.x; i < n; i += blockDim.x) hf[i] = src[i];
   }
   L.turn = turn;
+  L.ex = ex;
   L.hf = ntab ? hf : nullptr;
   L.g = g;
   return reinterpret_cast<double *>(g + nd * a.phys.nb);
@@ -182,21 +196,6 @@ __device__ __forceinline__ double sqrt_normal(double a) {
   return fma(d, h, g);
 }
 
-// Neumaier step: (s, c) += x
-__device__ __forceinline__ void neumaier(double &s, double &c, double x) {
-  const double t = s + x;
-  c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
-  s = t;
-}
-
-// Kahan step: (s, c) tracks sum = s - c
-__device__ __forceinline__ void kahan(double &s, double &c, double x) {
-  const double y = x - c;
-  const double t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
-
 // (s, c) += (s2, c2) with the rounding error of the leading parts kept
 __device__ __forceinline__ void pair_merge(double &s, double &c, double s2, double c2) {
   const double t = s + s2;
@@ -225,17 +224,17 @@ __device__ __forceinline__ double vegas_map(const KArgs &a, const TaskDev *__res
     philox4x32_10(static_cast<uint32_t>(s), static_cast<uint32_t>(s >> 32), iter,
                   static_cast<uint32_t>(j), a.phys.seed, T->key, wd + 4 * j);
   // bin b = floor(w nb / 2^32), fraction ((w nb mod 2^32) + 1/2) / 2^32.
-  // y = w nb 2^-32 is exact in fp64 (at most 39 significant bits), so b and the
-  // fraction come out exactly with full-rate fp64 instructions.  The Jacobian
-  // prod_m nb width_m takes nb^ND once.
+  // y = w nb 2^-32 is exact in fp64 (at most 39 significant bits), so b (the
+  // truncation of y >= 0) and y - b (v_fract_f64) come out exactly; the half
+  // is folded into the grid pair's first entry, e_b + w_b 2^-33.  The
+  // Jacobian prod_m nb width_m takes nb^ND once.
   double jac = 1.0;
   const double nbscale = static_cast<double>(nb) * 0x1p-32;
 #pragma unroll
   for (int m = 0; m < ND; ++m) {
     const double y = static_cast<double>(wd[m]) * nbscale;
-    const double fb = floor(y);
-    const int b = static_cast<int>(fb);
-    const double r = (y - fb) + 0x1p-33;
+    const int b = static_cast<int>(y);
+    const double r = __builtin_amdgcn_fract(y);
     const double2 ew = g[m * nb + b];
     x[m] = fma(r, ew.y, ew.x);
     jac *= ew.y;
@@ -425,6 +424,35 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
   return acc;
 }
 
+// exp(x) for x <= 0 by Tang's table-driven method (ACM TOMS 15, 1989): with
+// k = rint(64 x / ln 2) = 64 m + j, exp(x) = 2^m 2^(j/64) e^r, r = x - k ln2/64
+// (|r| <= ln2/128, reduced with the split constant so k HI is exact), e^r - 1
+// from its degree-6 Taylor polynomial (truncation below 3e-20) and 2^(j/64)
+// from the LDS table.  Within about one ulp; arguments below -1000 give 0.
+__device__ __forceinline__ double exp_nonpos(double x, const double *ex) {
+  x = fmax(x, -1000.0);
+  const double kd = __builtin_rint(x * MBPT_INV_LN2_64);
+  const int k = static_cast<int>(kd);
+  const double r = fma(-kd, MBPT_LN2_64_LO, fma(-kd, MBPT_LN2_64_HI, x));
+  double q = fma(r, 1.0 / 720.0, 1.0 / 120.0);
+  q = fma(q, r, 1.0 / 24.0);
+  q = fma(q, r, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  const double t = ex[k & 63];
+  return __builtin_ldexp(fma(t, r * q, t), k >> 6);
+}
+
+// 1/d from the hardware reciprocal and two Newton steps (d normal and finite;
+// within about one ulp).
+__device__ __forceinline__ double rcp_newton(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Contribution of one diagram at the loop momenta k (prefactor, regulators,
 // label sum and denominators; without the Jacobian and 1/n).  HF: single-
 // particle energies of the Hartree-Fock spectrum (tables in LDS).
@@ -523,7 +551,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   pre[0] = den[0];
 #pragma unroll
   for (int i = 1; i < NR; ++i) pre[i] = pre[i - 1] * den[i];
-  double inv = 1.0 / pre[NR - 1];
+  double inv = rcp_newton(pre[NR - 1]);
   double rinv[NR];
 #pragma unroll
   for (int i = NR - 1; i > 0; --i) {
@@ -537,7 +565,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
     Vd[v] = a.phys.V0 + a.phys.Vy * rinv[2 * v];
     Ve[v] = a.phys.V0 + a.phys.Vy * rinv[2 * v + 1];
   }
-  const double regall = exp(-yreg * a.phys.invLn);
+  const double regall = exp_nonpos(-yreg * a.phys.invLn, Ls.ex);
 
   const double acc =
       label_sum<ORDER, Q, double, iso_den, X>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn, deps);
@@ -862,7 +890,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
   for (int i = tid; i < ND * nb; i += bs) {
     const int m = i / nb, b = i - m * nb;
     const double e0 = ge[m * (nb + 1) + b], e1 = ge[m * (nb + 1) + b + 1];
-    g[i] = make_double2(e0, e1 - e0);
+    g[i] = make_double2(fma(e1 - e0, 0x1p-33, e0), e1 - e0);
     h[i] = 0.0;
   }
   __syncthreads();
@@ -879,10 +907,12 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
   double rs[R ? 2 * kMaxReg : 1];
 #pragma unroll
   for (int j = 0; j < (R ? 2 * kMaxReg : 1); ++j) rs[j] = 0.0;
+  // a thread adds at most spt terms of the shifted sums: plain sums; the
+  // merges across threads and items keep the rounding errors
   auto accumulate = [&](double w, const int *bins) {
     const double d = w - shift;
-    kahan(s1, c1, d);
-    kahan(s2, c2, d * d);
+    s1 += d;
+    s2 = fma(d, d, s2);
     const double w2 = w * w;
     if (w2 != 0.0) {
 #pragma unroll
@@ -959,10 +989,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
     }
     while (qn > 0) drain(qn < 64 ? qn : 64);
   }
-  // Kahan pairs hold s - c; the merges below use s + c
-  c1 = -c1;
-  c2 = -c2;
-  // wavefront butterfly, then waves in order
+  // wavefront butterfly, then waves in order (compensated pairs s + c)
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const double os1 = __shfl_xor(s1, off, 64), oc1 = __shfl_xor(c1, off, 64);
@@ -1336,7 +1363,7 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
   for (int i = threadIdx.x; i < ND * nb; i += blockDim.x) {
     const int m = i / nb, b = i - m * nb;
     const double e0 = ge[m * (nb + 1) + b], e1 = ge[m * (nb + 1) + b + 1];
-    g[i] = make_double2(e0, e1 - e0);
+    g[i] = make_double2(fma(e1 - e0, 0x1p-33, e0), e1 - e0);
   }
   __syncthreads();
   const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1482,9 +1509,9 @@ static int mode_of(const KArgs &a, int prec, bool group) {
 }
 
 size_t sample_lds_bytes(int nd, int nb, int block, int ntab) {
-  // turn table + HF tables + grid (e, width) pairs + histogram + reduction
+  // turn and 2^(j/64) tables + HF tables + grid pairs + histogram + reduction
   // scratch + fp64 re-evaluation queue (128 sample offsets per wavefront)
-  return kTurnEntries * sizeof(SinCos) + hf_lds_doubles(ntab) * sizeof(double) +
+  return fixed_lds_bytes() + hf_lds_doubles(ntab) * sizeof(double) +
          (3 * static_cast<size_t>(nd) * nb + 6 * (block / 64)) * sizeof(double) +
          (block / 64) * 128 * sizeof(uint32_t);
 }
@@ -1595,7 +1622,7 @@ static hipError_t dump_qx(const KArgs &a, int t, int order, uint32_t iter, uint6
                           uint64_t count, double *out, double *out_reg, hipStream_t st) {
   const int block = 256;
   const dim3 grid(static_cast<unsigned>((count + block - 1) / block));
-  const size_t lds = kTurnEntries * sizeof(SinCos) + hf_lds_doubles(lds_tables<Q, P>()) * sizeof(double) +
+  const size_t lds = fixed_lds_bytes() + hf_lds_doubles(lds_tables<Q, P>()) * sizeof(double) +
                      2 * static_cast<size_t>(3 * (order + 1)) * a.phys.nb * sizeof(double);
   switch (order) {
     case 1: hipLaunchKernelGGL((dump_samples<1, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
