@@ -458,7 +458,7 @@ __device__ __forceinline__ double rcp_newton(double d) {
 // particle energies of the Hartree-Fock spectrum (tables in LDS).
 // REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
 // to wr[k - 1].
-template <int ORDER, int Q, bool HF, bool REG, bool X>
+template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
@@ -524,9 +524,13 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   // their regulators: the regulator product over all vertices factors out of
   // every label term and is applied once, exp(-sum_v (p^n + p'^n) / Lambda^n).
   // The 2n Yukawa denominators and the product of energy denominators are
-  // inverted together with one division (prefix products).
+  // inverted together with one division (prefix products), or (PI) with one
+  // division per vertex pair (V_d, V_e) and one for the energy denominators,
+  // which keeps 4n + 2 fewer doubles live.
   constexpr int NR = 2 * ORDER + 1;
-  double den[NR];
+  constexpr bool kPairInv = PI;
+  double den[kPairInv ? 1 : NR];
+  double Vd[ORDER], Ve[ORDER];
   double yreg = 0.0;
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
@@ -543,27 +547,39 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
     }
     yreg += pn + qn;
     const double s2 = p2 + q2 + a.phys.m2;
-    den[2 * v] = s2 - 2.0 * pq;
-    den[2 * v + 1] = s2 + 2.0 * pq;
+    const double dd = s2 - 2.0 * pq, de = s2 + 2.0 * pq;
+    if constexpr (kPairInv) {
+      const double r = rcp_newton(dd * de);
+      Vd[v] = a.phys.V0 + a.phys.Vy * (de * r);
+      Ve[v] = a.phys.V0 + a.phys.Vy * (dd * r);
+    } else {
+      den[2 * v] = dd;
+      den[2 * v + 1] = de;
+    }
   }
-  den[NR - 1] = iso_den ? 1.0 : dprod;
-  double pre[NR];
-  pre[0] = den[0];
+  double rden;  // 1 / prod_c D_c (1 when the label sum divides per configuration)
+  if constexpr (kPairInv) {
+    rden = iso_den ? 1.0 : rcp_newton(dprod);
+  } else {
+    den[NR - 1] = iso_den ? 1.0 : dprod;
+    double pre[NR];
+    pre[0] = den[0];
 #pragma unroll
-  for (int i = 1; i < NR; ++i) pre[i] = pre[i - 1] * den[i];
-  double inv = rcp_newton(pre[NR - 1]);
-  double rinv[NR];
+    for (int i = 1; i < NR; ++i) pre[i] = pre[i - 1] * den[i];
+    double inv = rcp_newton(pre[NR - 1]);
+    double rinv[NR];
 #pragma unroll
-  for (int i = NR - 1; i > 0; --i) {
-    rinv[i] = inv * pre[i - 1];
-    inv *= den[i];
-  }
-  rinv[0] = inv;
-  double Vd[ORDER], Ve[ORDER];
+    for (int i = NR - 1; i > 0; --i) {
+      rinv[i] = inv * pre[i - 1];
+      inv *= den[i];
+    }
+    rinv[0] = inv;
 #pragma unroll
-  for (int v = 0; v < ORDER; ++v) {
-    Vd[v] = a.phys.V0 + a.phys.Vy * rinv[2 * v];
-    Ve[v] = a.phys.V0 + a.phys.Vy * rinv[2 * v + 1];
+    for (int v = 0; v < ORDER; ++v) {
+      Vd[v] = a.phys.V0 + a.phys.Vy * rinv[2 * v];
+      Ve[v] = a.phys.V0 + a.phys.Vy * rinv[2 * v + 1];
+    }
+    rden = rinv[NR - 1];
   }
   const double regall = exp_nonpos(-yreg * a.phys.invLn, Ls.ex);
 
@@ -579,7 +595,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
       wr[r] += base / pk;
     }
   }
-  return base * rinv[NR - 1];
+  return base * rden;
 }
 
 // One sample of a task: VEGAS map, loop momenta (radii from the first
@@ -587,7 +603,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 // or (G) the task's T->ndiag group members summed.
 // REG: the regularised components go to wr[0..nreg) (Jacobian and 1/n
 // included).
-template <int ORDER, int Q, bool HF, bool G, bool X, bool REG = false>
+template <int ORDER, int Q, bool HF, bool G, bool X, bool PI, bool REG = false>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, uint64_t s,
@@ -620,9 +636,9 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     sum = 0.0;
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di)
-      sum += diag_weight64<ORDER, Q, HF, REG, X>(a, T, D + di, Ls, k, npass, nterms, wr);
+      sum += diag_weight64<ORDER, Q, HF, REG, X, PI>(a, T, D + di, Ls, k, npass, nterms, wr);
   } else {
-    sum = diag_weight64<ORDER, Q, HF, REG, X>(a, T, D, Ls, k, npass, nterms, wr);
+    sum = diag_weight64<ORDER, Q, HF, REG, X, PI>(a, T, D, Ls, k, npass, nterms, wr);
   }
   const double scale = jac * T->inv_density;
   if constexpr (REG)
@@ -843,6 +859,15 @@ template <int P>
 constexpr bool reg_of() {
   return P >= 5;
 }
+// Per-vertex-pair inversion (see diag_weight64) where the registers it frees
+// give the kernel one more wave per SIMD: the third-order fp32 kernels (their
+// fp64 re-evaluation path) fit in 168 VGPRs with it (3 waves instead of 2).
+// Elsewhere the prefix form, which issues fewer instructions, at the same
+// occupancy.
+template <int ORDER, int Q, int P>
+constexpr bool pair_inv() {
+  return ORDER == 3 && prec_of<P>() == 1;
+}
 
 template <int ORDER, int Q, int P, bool X>
 __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__restrict__ T,
@@ -852,13 +877,14 @@ __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__r
                                               uint32_t &nterms, uint32_t &nfb) {
   constexpr int PP = prec_of<P>();
   constexpr bool G = group_of<P>();
+  constexpr bool PI = pair_inv<ORDER, Q, P>();
   if (PP != 1)
-    return eval_fp64<ORDER, Q, PP == 2, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms);
+    return eval_fp64<ORDER, Q, PP == 2, G, X, PI>(a, T, D, Ls, s, iter, bins, npass, nterms);
   bool fb = false;
   double w = eval_fp32<ORDER, Q, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
   if (fb) {
     ++nfb;
-    w = eval_fp64<ORDER, Q, false, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms);
+    w = eval_fp64<ORDER, Q, false, G, X, PI>(a, T, D, Ls, s, iter, bins, npass, nterms);
   }
   return w;
 }
@@ -921,6 +947,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
   };
   constexpr int PP = prec_of<P>();
   constexpr bool G = group_of<P>();
+  constexpr bool PI = pair_inv<ORDER, Q, P>();
   if (PP != 1) {
     for (int kk = 0; kk < a.spt; ++kk) {
       const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
@@ -929,7 +956,8 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
         if constexpr (R) {
           double wr[kMaxReg];
           const double w =
-              eval_fp64<ORDER, Q, false, G, X, true>(a, T, D, Ls, s, iter, bins, npass, nterms, wr);
+              eval_fp64<ORDER, Q, false, G, X, PI, true>(a, T, D, Ls, s, iter, bins, npass, nterms,
+                                                         wr);
           accumulate(w, bins);
 #pragma unroll
           for (int r = 0; r < kMaxReg; ++r) {
@@ -939,7 +967,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
           }
         } else {
           const double w =
-              eval_fp64<ORDER, Q, PP == 2, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms);
+              eval_fp64<ORDER, Q, PP == 2, G, X, PI>(a, T, D, Ls, s, iter, bins, npass, nterms);
           accumulate(w, bins);
         }
       }
@@ -956,7 +984,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
         const uint64_t s = base + queue[lane];
         int bins[ND];
         const double w =
-            eval_fp64<ORDER, Q, false, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms);
+            eval_fp64<ORDER, Q, false, G, X, PI>(a, T, D, Ls, s, iter, bins, npass, nterms);
         accumulate(w, bins);
       }
       __builtin_amdgcn_wave_barrier();
@@ -1353,6 +1381,7 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
                                                    uint64_t count, double *out, double *out_reg) {
   extern __shared__ double smem[];
   constexpr int ND = 3 * (ORDER + 1);
+  constexpr bool PI = pair_inv<ORDER, Q, P>();
   const TaskDev *T = a.tasks + t;
   const DiagDev *D = a.diags + T->diag;
   const int nb = a.phys.nb;
@@ -1372,8 +1401,8 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
     uint32_t np = 0, nt = 0, nf = 0;
     if constexpr (reg_of<P>()) {
       double wr[kMaxReg];
-      out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, true>(a, T, D, Ls, first + i, iter,
-                                                                  bins, np, nt, wr);
+      out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, PI, true>(a, T, D, Ls, first + i,
+                                                                      iter, bins, np, nt, wr);
       if (out_reg)
         for (int r = 0; r < a.nreg; ++r) out_reg[i * a.nreg + r] = wr[r];
     } else {
