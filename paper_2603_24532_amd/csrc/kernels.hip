@@ -1089,18 +1089,27 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
   }
 }
 
-// One task per launch: block b processes work item item_begin + b.
-// The fifth-order fp32 kernels (which carry the inlined fp64 re-evaluation
-// path on top of their own state) and fifth-order group kernels (the member
-// loop keeps the loop momenta live) ask for two waves per SIMD, which holds
-// them within 256 VGPRs: a few spilled dwords instead of half the occupancy.
-template <int ORDER, int P>
+// Waves per SIMD the sample kernels ask the compiler for (it then holds them
+// within 512 / waves VGPRs, spilling the rest).  Measured on MI355X: the
+// fourth-order kernels (fp64, fp32, groups) run 10-30% faster at 3 waves with
+// 100-200 spilled bytes per thread than at 2 waves without spills; the
+// fifth-order fp32, group and explicit-list kernels likewise gain at 3 waves,
+// while the fifth-order fp64 polynomial kernel (about 360 spilled bytes at 3)
+// is faster at 2; the fifth-order regularised group kernel stays within 256
+// VGPRs at 2.  Other kernels fit their natural occupancy.
+template <int ORDER, int P, bool X>
 constexpr int min_waves() {
-  return (ORDER == 5 && (prec_of<P>() == 1 || group_of<P>())) ? 2 : 1;
+  if (ORDER == 4) return (P == 0 || P == 1 || P == 3 || P == 4) ? 3 : 1;
+  if (ORDER == 5) {
+    if (P == 1 || P == 3 || P == 4 || (P == 0 && X)) return 3;
+    return P == 6 ? 2 : 1;
+  }
+  return 1;
 }
 
+// One task per launch: block b processes work item item_begin + b.
 template <int ORDER, int Q, int P, bool X>
-__global__ __launch_bounds__(256, (min_waves<ORDER, P>())) void sample_single(KArgs a, int t) {
+__global__ __launch_bounds__(256, (min_waves<ORDER, P, X>())) void sample_single(KArgs a, int t) {
   extern __shared__ double smem[];
   process_item<ORDER, Q, P, X>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
 }
@@ -1111,7 +1120,7 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, P>())) void sample_single(KA
 // olist[k0].x + b.  One launch per order keeps each launch's register
 // allocation that of its own order.
 template <int ORDER, int Q, int P, bool X>
-__global__ __launch_bounds__(256, (min_waves<ORDER, P>())) void sample_order(KArgs a, int k0, int k1) {
+__global__ __launch_bounds__(256, (min_waves<ORDER, P, X>())) void sample_order(KArgs a, int k0, int k1) {
   extern __shared__ double smem[];
   const int2 *__restrict__ ol = a.olist;
   const int item = ol[k0].x + static_cast<int>(blockIdx.x);
