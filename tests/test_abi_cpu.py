@@ -196,6 +196,33 @@ def test_turn_table_values():
     assert open(hdr).read() == before
 
 
+def test_exp_table_and_split_constant():
+    """The kernels' exponential: 2^(j/64) correctly rounded (checked against
+    exact rational bounds: t^64 brackets 2^j), and ln 2 / 64 split into a
+    36-bit leading part (so k * HI is exact for |k| < 2^17) plus the rest."""
+    import math
+    from fractions import Fraction
+    here = os.path.dirname(os.path.abspath(__file__))
+    text = open(os.path.join(here, "..", "paper_2603_24532_amd", "csrc", "turn_table.hpp")).read()
+    rows = re.findall(r"^\s+(0x\S+),\s+/\* j = (\d+) \*/", text, re.M)
+    assert [int(j) for _, j in rows] == list(range(64))
+    T = [float.fromhex(v) for v, _ in rows]
+    assert T[0] == 1.0
+    for j, t in enumerate(T):
+        # t is the double nearest to 2^(j/64): the midpoints to its neighbours
+        # raised to the 64th power bracket 2^j
+        lo = (Fraction(t) + Fraction(math.nextafter(t, 0.0))) / 2
+        hi = (Fraction(t) + Fraction(math.nextafter(t, 4.0))) / 2
+        assert lo ** 64 < 2 ** j < hi ** 64, j
+    hi_c = float.fromhex(re.search(r"#define MBPT_LN2_64_HI (\S+)", text).group(1))
+    lo_c = float.fromhex(re.search(r"#define MBPT_LN2_64_LO (\S+)", text).group(1))
+    inv = float.fromhex(re.search(r"#define MBPT_INV_LN2_64 (\S+)", text).group(1))
+    m, e = math.frexp(hi_c)
+    assert (m * 2 ** 36).is_integer()
+    assert abs(hi_c + lo_c - math.log(2) / 64) <= 2 ** -60 * math.log(2) / 64
+    assert abs(inv - 64 / math.log(2)) <= 2 ** -52 * inv
+
+
 def test_group_members_match_oracle(M, golden):
     g = golden["n_grp_two_body"]
     for order, n_grp in zip(g["orders"], g["values"]):
