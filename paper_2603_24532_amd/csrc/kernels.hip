@@ -1096,9 +1096,17 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 // fifth-order fp32, group and explicit-list kernels likewise gain at 3 waves,
 // while the fifth-order fp64 polynomial kernel (about 360 spilled bytes at 3)
 // is faster at 2; the fifth-order regularised group kernel stays within 256
-// VGPRs at 2.  Other kernels fit their natural occupancy.
-template <int ORDER, int P, bool X>
+// VGPRs at 2.  The HF kernels (isospin-dependent spectra keep per-line energy
+// differences live) run at 2 waves from third order on, 20-45% faster than at
+// one, except fifth-order neutron matter, which loses a third to its ~520
+// spilled bytes.  Other kernels fit their natural occupancy.
+template <int ORDER, int Q, int P, bool X>
 constexpr int min_waves() {
+  if (P == 2) {
+    if (ORDER == 2) return 3;
+    if (ORDER == 3 || ORDER == 4) return 2;
+    return (ORDER == 5 && Q == 4) ? 2 : 1;
+  }
   if (ORDER == 4) return (P == 0 || P == 1 || P == 3 || P == 4) ? 3 : 1;
   if (ORDER == 5) {
     if (P == 1 || P == 3 || P == 4 || (P == 0 && X)) return 3;
@@ -1109,7 +1117,7 @@ constexpr int min_waves() {
 
 // One task per launch: block b processes work item item_begin + b.
 template <int ORDER, int Q, int P, bool X>
-__global__ __launch_bounds__(256, (min_waves<ORDER, P, X>())) void sample_single(KArgs a, int t) {
+__global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_single(KArgs a, int t) {
   extern __shared__ double smem[];
   process_item<ORDER, Q, P, X>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
 }
@@ -1120,7 +1128,7 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, P, X>())) void sample_single
 // olist[k0].x + b.  One launch per order keeps each launch's register
 // allocation that of its own order.
 template <int ORDER, int Q, int P, bool X>
-__global__ __launch_bounds__(256, (min_waves<ORDER, P, X>())) void sample_order(KArgs a, int k0, int k1) {
+__global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_order(KArgs a, int k0, int k1) {
   extern __shared__ double smem[];
   const int2 *__restrict__ ol = a.olist;
   const int item = ol[k0].x + static_cast<int>(blockIdx.x);
