@@ -1090,16 +1090,18 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 }
 
 // Waves per SIMD the sample kernels ask the compiler for (it then holds them
-// within 512 / waves VGPRs, spilling the rest).  Measured on MI355X: the
-// fourth-order kernels (fp64, fp32, groups) run 10-30% faster at 3 waves with
-// 100-200 spilled bytes per thread than at 2 waves without spills; the
-// fifth-order fp32, group and explicit-list kernels likewise gain at 3 waves,
-// while the fifth-order fp64 polynomial kernel (about 360 spilled bytes at 3)
-// is faster at 2; the fifth-order regularised group kernel stays within 256
-// VGPRs at 2.  The HF kernels (isospin-dependent spectra keep per-line energy
-// differences live) run at 2 waves from third order on, 20-45% faster than at
-// one, except fifth-order neutron matter, which loses a third to its ~520
-// spilled bytes.  Other kernels fit their natural occupancy.
+// within 512 / waves VGPRs, spilling the rest), as measured on MI355X:
+// - fourth order: fp64, fp32, group and regularised kernels run 4-30% faster
+//   at 3 waves (100-200 spilled bytes per thread) than at 2 without spills;
+//   the regularised group kernel gains at 2;
+// - fifth order: fp32, group and explicit-list kernels gain at 3 waves; the
+//   fp64 polynomial kernel (about 360 spilled bytes at 3) and the regularised
+//   single-diagram kernel are faster at their natural occupancy; the
+//   regularised group kernel stays within 256 VGPRs at 2;
+// - HF kernels (isospin-dependent spectra keep per-line energy differences
+//   live): 2 waves from third order on, 20-45% faster than at one, except
+//   fifth-order neutron matter, which loses a third to ~520 spilled bytes.
+// Other kernels fit their natural occupancy.
 template <int ORDER, int Q, int P, bool X>
 constexpr int min_waves() {
   if (P == 2) {
@@ -1107,7 +1109,7 @@ constexpr int min_waves() {
     if (ORDER == 3 || ORDER == 4) return 2;
     return (ORDER == 5 && Q == 4) ? 2 : 1;
   }
-  if (ORDER == 4) return (P == 0 || P == 1 || P == 3 || P == 4) ? 3 : 1;
+  if (ORDER == 4) return (P == 0 || P == 1 || P == 3 || P == 4 || P == 5) ? 3 : 2;
   if (ORDER == 5) {
     if (P == 1 || P == 3 || P == 4 || (P == 0 && X)) return 3;
     return P == 6 ? 2 : 1;
