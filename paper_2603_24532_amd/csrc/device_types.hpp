@@ -30,6 +30,38 @@ struct alignas(16) DiagDev {
   int pad3[2];
 };
 
+// Orders 1 and 2 have one two-body diagram each.  Its descriptor masks (as the
+// generator compiles them, loops first) are compile-time constants for the
+// kernels of those orders, which then fold the loop-momentum sums, drop the
+// zero coefficients and share equal vertex momenta; compiling a task set
+// checks the generator's masks against these.
+template <int ORDER>
+struct FixedMasks {
+  static constexpr bool kFixed = false;
+};
+template <>
+struct FixedMasks<1> {
+  static constexpr bool kFixed = true;
+  static constexpr uint32_t line_mask = 0x3u, part_mask = 0x0u;
+  static constexpr uint32_t lmask[2] = {0x1u, 0x2u};
+  static constexpr uint32_t pmask_v[1] = {0x201u};
+  static constexpr uint32_t qmask_v[1] = {0x201u};
+  static constexpr uint32_t cut_hole[1] = {0x0u};
+  static constexpr uint32_t cut_part[1] = {0x0u};
+  static constexpr int loop_part[2] = {0, 0};
+};
+template <>
+struct FixedMasks<2> {
+  static constexpr bool kFixed = true;
+  static constexpr uint32_t line_mask = 0xFu, part_mask = 0x9u;
+  static constexpr uint32_t lmask[4] = {0x1u, 0x2u, 0x4u, 0x106u};
+  static constexpr uint32_t pmask_v[2] = {0x1000006u, 0x402u};
+  static constexpr uint32_t qmask_v[2] = {0x402u, 0x1000006u};
+  static constexpr uint32_t cut_hole[1] = {0x6u};
+  static constexpr uint32_t cut_part[1] = {0x9u};
+  static constexpr int loop_part[3] = {1, 0, 0};
+};
+
 // Isospin configuration: lines whose bit is set carry protons.  first/count:
 // its explicit terms; coef_off: its 2^n factorised coefficients.
 struct alignas(16) GroupDev {

@@ -162,13 +162,16 @@ __device__ __forceinline__ double mask_coef(uint32_t m, int j) {
   return __hiloint2double(static_cast<int>(hi), 0);
 }
 
-// sum_j c_j v_j over loops j < L (coefficients from the uniform bitmask m)
-template <int L, bool HALF = false>
+// sum_j c_j v_j over loops j < L (coefficients from the uniform bitmask m).
+// SKIP0: m is a compile-time constant, so zero coefficients are left out
+// (an fma with a zero coefficient is not foldable under IEEE rules).
+template <int L, bool HALF = false, bool SKIP0 = false>
 __device__ __forceinline__ void masked_sum(uint32_t m, const double (*k)[3], double *out) {
   double x = 0.0, y = 0.0, z = 0.0;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
     const double c = mask_coef<HALF>(m, j);
+    if (SKIP0 && c == 0.0) continue;
     x = fma(c, k[j][0], x);
     y = fma(c, k[j][1], y);
     z = fma(c, k[j][2], z);
@@ -176,6 +179,49 @@ __device__ __forceinline__ void masked_sum(uint32_t m, const double (*k)[3], dou
   out[0] = x;
   out[1] = y;
   out[2] = z;
+}
+
+// Descriptor masks: compile-time constants for orders 1 and 2 (FixedMasks),
+// else read from the descriptor.
+template <int ORDER>
+__device__ __forceinline__ uint32_t lmask_of(const DiagDev *__restrict__ D, int l) {
+  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::lmask[l];
+  else return D->lmask[l];
+}
+template <int ORDER>
+__device__ __forceinline__ uint32_t pmask_of(const DiagDev *__restrict__ D, int v) {
+  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::pmask_v[v];
+  else return D->pmask_v[v];
+}
+template <int ORDER>
+__device__ __forceinline__ uint32_t qmask_of(const DiagDev *__restrict__ D, int v) {
+  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::qmask_v[v];
+  else return D->qmask_v[v];
+}
+template <int ORDER>
+__device__ __forceinline__ uint32_t cut_hole_of(const DiagDev *__restrict__ D, int c) {
+  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::cut_hole[c];
+  else return D->cut_hole[c];
+}
+template <int ORDER>
+__device__ __forceinline__ uint32_t cut_part_of(const DiagDev *__restrict__ D, int c) {
+  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::cut_part[c];
+  else return D->cut_part[c];
+}
+template <int ORDER>
+__device__ __forceinline__ uint32_t line_mask_of(const DiagDev *__restrict__ D) {
+  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::line_mask;
+  else return D->line_mask;
+}
+template <int ORDER>
+__device__ __forceinline__ uint32_t part_mask_of(const DiagDev *__restrict__ D) {
+  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::part_mask;
+  else return D->part_mask;
+}
+template <int ORDER>
+__device__ __forceinline__ bool loop_part_of(const DiagDev *__restrict__ D, int j) {
+  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::loop_part[j] != 0;
+  else return D->loop_part[j] != 0;
 }
 
 // Square root of a finite a >= 0: hardware reciprocal square root refined by
@@ -343,7 +389,7 @@ __device__ __forceinline__ double group_den(const DiagDev *__restrict__ D, uint3
   double prod = 1.0;
 #pragma unroll
   for (int c = 0; c < ORDER - 1; ++c) {
-    const uint32_t hm = D->cut_hole[c] & tau, pm = D->cut_part[c] & tau;
+    const uint32_t hm = cut_hole_of<ORDER>(D, c) & tau, pm = cut_part_of<ORDER>(D, c) & tau;
     double Dc = Dn[c];
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
@@ -480,7 +526,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
       kv[1] = k[l][1];
       kv[2] = k[l][2];
     } else {
-      masked_sum<L>(D->lmask[l], k, kv);
+      masked_sum<L, false, FixedMasks<ORDER>::kFixed>(lmask_of<ORDER>(D, l), k, kv);
     }
     const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = a.phys.hb2m * k2;
@@ -495,7 +541,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
     if (Q == 4) inP |= (k2 < T->kF2[1]) ? (1u << l) : 0u;
   }
   // a hole line is allowed if occupied, a particle line if empty
-  const uint32_t lmask = D->line_mask, pmask = D->part_mask;
+  const uint32_t lmask = line_mask_of<ORDER>(D), pmask = part_mask_of<ORDER>(D);
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
   if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
@@ -508,13 +554,18 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   double Dn[NC > 0 ? NC : 1];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const uint32_t hm = D->cut_hole[c], pm = D->cut_part[c];
+    const uint32_t hm = cut_hole_of<ORDER>(D, c), pm = cut_part_of<ORDER>(D, c);
     double Dc = 0.0;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-      uint32_t hi = (hm & (1u << l)) ? 0x3FF00000u : 0u;
-      hi = (pm & (1u << l)) ? 0xBFF00000u : hi;
-      Dc = fma(__hiloint2double(static_cast<int>(hi), 0), eps[l], Dc);
+      if constexpr (FixedMasks<ORDER>::kFixed) {
+        if (hm & (1u << l)) Dc += eps[l];
+        else if (pm & (1u << l)) Dc -= eps[l];
+      } else {
+        uint32_t hi = (hm & (1u << l)) ? 0x3FF00000u : 0u;
+        hi = (pm & (1u << l)) ? 0xBFF00000u : hi;
+        Dc = fma(__hiloint2double(static_cast<int>(hi), 0), eps[l], Dc);
+      }
     }
     Dn[c] = Dc;
     dprod *= Dc;
@@ -535,15 +586,19 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
     double p[3], q[3];  // relative momenta p and p'
-    masked_sum<L, true>(D->pmask_v[v], k, p);
-    masked_sum<L, true>(D->qmask_v[v], k, q);
+    masked_sum<L, true, FixedMasks<ORDER>::kFixed>(pmask_of<ORDER>(D, v), k, p);
+    masked_sum<L, true, FixedMasks<ORDER>::kFixed>(qmask_of<ORDER>(D, v), k, q);
     const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const double pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
-    double pn = p2, qn = q2;
-    for (int e = 1; e < a.phys.half_exp; ++e) {
-      pn *= p2;
-      qn *= q2;
+    double pn = p2 * p2, qn = q2 * q2;  // exponent 4, the workload's
+    if (a.phys.half_exp != 2) {
+      pn = p2;
+      qn = q2;
+      for (int e = 1; e < a.phys.half_exp; ++e) {
+        pn *= p2;
+        qn *= q2;
+      }
     }
     yreg += pn + qn;
     const double s2 = p2 + q2 + a.phys.m2;
@@ -618,7 +673,7 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   double k[L][3];
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    const double R = D->loop_part[j] ? T->Rp : T->Rh;
+    const double R = loop_part_of<ORDER>(D, j) ? T->Rp : T->Rh;
     const double rad = R * x[3 * j];
     const double ct = 2.0 * x[3 * j + 1] - 1.0;
     const double st = sqrt_normal((1.0 - ct) * (1.0 + ct));
@@ -657,12 +712,13 @@ __device__ __forceinline__ float mask_coef_f(uint32_t m, int j) {
   return __uint_as_float(bits);
 }
 
-template <int L, bool HALF = false>
+template <int L, bool HALF = false, bool SKIP0 = false>
 __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], float *out) {
   float x = 0.0f, y = 0.0f, z = 0.0f;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
     const float c = mask_coef_f<HALF>(m, j);
+    if (SKIP0 && c == 0.0f) continue;
     x = fmaf(c, k[j][0], x);
     y = fmaf(c, k[j][1], y);
     z = fmaf(c, k[j][2], z);
@@ -704,7 +760,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
       kv[1] = k[l][1];
       kv[2] = k[l][2];
     } else {
-      masked_sum_f<L>(D->lmask[l], k, kv);
+      masked_sum_f<L, false, FixedMasks<ORDER>::kFixed>(lmask_of<ORDER>(D, l), k, kv);
     }
     const float k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = hb2m * k2;
@@ -719,7 +775,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
     fallback = true;
     return 0.0;
   }
-  const uint32_t lmask = D->line_mask, pmask = D->part_mask;
+  const uint32_t lmask = line_mask_of<ORDER>(D), pmask = part_mask_of<ORDER>(D);
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
   if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
@@ -727,7 +783,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   float dprod = 1.0f;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const uint32_t hm = D->cut_hole[c], pm = D->cut_part[c];
+    const uint32_t hm = cut_hole_of<ORDER>(D, c), pm = cut_part_of<ORDER>(D, c);
     float Dc = 0.0f, Dabs = 0.0f;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
@@ -748,8 +804,8 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
     float p[3], q[3];
-    masked_sum_f<L, true>(D->pmask_v[v], k, p);
-    masked_sum_f<L, true>(D->qmask_v[v], k, q);
+    masked_sum_f<L, true, FixedMasks<ORDER>::kFixed>(pmask_of<ORDER>(D, v), k, p);
+    masked_sum_f<L, true, FixedMasks<ORDER>::kFixed>(qmask_of<ORDER>(D, v), k, q);
     const float p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const float q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const float pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
@@ -815,7 +871,7 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
   float k[L][3];
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    const double R = D->loop_part[j] ? T->Rp : T->Rh;
+    const double R = loop_part_of<ORDER>(D, j) ? T->Rp : T->Rh;
     const double rad64 = R * x[3 * j];
     jac *= R * rad64 * rad64 * (4.0 * M_PI);
     const float rad = static_cast<float>(rad64);

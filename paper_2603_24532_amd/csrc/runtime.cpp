@@ -294,6 +294,37 @@ void fill_diag_dev(const Diagram &d, DiagDev &dd, bool canonical) {
     }
 }
 
+// The kernels of orders 1 and 2 take the descriptor masks of their one
+// diagram as compile-time constants (FixedMasks); true if the generator's
+// descriptors (plain and canonical loop order) are those (checked once).
+template <int ORDER>
+static bool fixed_masks_match(const DiagDev &dd) {
+  using F = FixedMasks<ORDER>;
+  constexpr int NL = 2 * ORDER, L = ORDER + 1, NC = ORDER - 1;
+  bool ok = dd.line_mask == F::line_mask && dd.part_mask == F::part_mask;
+  for (int l = 0; l < NL; ++l) ok = ok && dd.lmask[l] == F::lmask[l];
+  for (int v = 0; v < ORDER; ++v)
+    ok = ok && dd.pmask_v[v] == F::pmask_v[v] && dd.qmask_v[v] == F::qmask_v[v];
+  for (int c = 0; c < NC; ++c)
+    ok = ok && dd.cut_hole[c] == F::cut_hole[c] && dd.cut_part[c] == F::cut_part[c];
+  for (int j = 0; j < L; ++j) ok = ok && dd.loop_part[j] == F::loop_part[j];
+  return ok;
+}
+
+bool fixed_masks_ok() {
+  static const bool ok = [] {
+    bool r = true;
+    for (int canonical = 0; canonical < 2; ++canonical) {
+      DiagDev d1{}, d2{};
+      fill_diag_dev(*get_diagram(1, 0), d1, canonical != 0);
+      fill_diag_dev(*get_diagram(2, 0), d2, canonical != 0);
+      r = r && fixed_masks_match<1>(d1) && fixed_masks_match<2>(d2);
+    }
+    return r;
+  }();
+  return ok;
+}
+
 // Appends one diagram's label tables.  group_base / term_base / coef_base
 // are the device element indices at which the three vectors start, so the
 // offsets stored in the descriptor are absolute for the kernel's table bases.
@@ -768,6 +799,10 @@ extern "C" int mbpt_create_task_set(mbpt_context *ctx, const mbpt_task_desc *tas
                                     mbpt_task_set **out) {
   if (!ctx || !out) return MBPT_EINVAL;
   *out = nullptr;
+  if (!fixed_masks_ok()) {
+    set_err(ctx, "internal: the order-1/2 descriptors differ from the kernels' fixed masks");
+    return MBPT_EINVAL;
+  }
   int q = 2;
   int rc = check_tasks(ctx, tasks, n_tasks, &q);
   if (rc) return rc;

@@ -109,6 +109,7 @@ void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<Group
                          size_t group_base, size_t term_base, size_t coef_base,
                          bool canonical = false);
 void fill_diag_dev(const Diagram &d, DiagDev &dd, bool canonical = false);
+bool fixed_masks_ok();
 void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T);
 void result_of(const TaskDev &S, mbpt_result &r);
 void timed_begin(mbpt_context *ctx, size_t &slot);

@@ -428,6 +428,10 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
                  "components only");
     return MBPT_EINVAL;
   }
+  if (!fixed_masks_ok()) {
+    set_err(ctx, "internal: the order-1/2 descriptors differ from the kernels' fixed masks");
+    return MBPT_EINVAL;
+  }
   Layout L{};
   if (!make_layout(max_slots, ctx->desc.n_bins, bytes, L) ||
       L.max_items < items_of(max_samples_per_iter, server_spt(ctx, max_samples_per_iter))) {
