@@ -225,9 +225,10 @@ __device__ __forceinline__ bool loop_part_of(const DiagDev *__restrict__ D, int 
 }
 
 // Square root of a finite a >= 0: hardware reciprocal square root refined by
-// Newton steps on g = sqrt(a) and h = 1 / (2 sqrt(a)).  No rescaling: a is
-// clamped to the smallest normal (so 0 gives 1.5e-154), and the squared
-// momenta and (1 - c)(1 + c) that reach here are far from overflow.
+// one coupled step on g = sqrt(a) and h = 1 / (2 sqrt(a)) (doubling its
+// correct bits) and one Newton correction of g.  No rescaling: a is clamped to
+// the smallest normal (so 0 gives 1.5e-154), and the squared momenta and
+// (1 - c)(1 + c) that reach here are far from overflow.
 __device__ __forceinline__ double sqrt_normal(double a) {
   a = fmax(a, 0x1p-1022);
   const double y = __builtin_amdgcn_rsq(a);
@@ -236,9 +237,7 @@ __device__ __forceinline__ double sqrt_normal(double a) {
   const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
-  double d = fma(-g, g, a);
-  g = fma(d, h, g);
-  d = fma(-g, g, a);
+  const double d = fma(-g, g, a);
   return fma(d, h, g);
 }
 
