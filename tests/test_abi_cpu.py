@@ -162,7 +162,7 @@ def test_label_polynomial_closed_loop_rule_fifth_order(M):
 
 
 def test_turn_table_values():
-    """The kernels' {sin, cos}(2 pi k / 64) table: exact at the quarter turns,
+    """The kernels' {sin, cos}(2 pi k / N) table: exact at the quarter turns,
     within one ulp of the math library elsewhere, and reproduced by its
     generator."""
     import math
@@ -171,23 +171,26 @@ def test_turn_table_values():
     here = os.path.dirname(os.path.abspath(__file__))
     hdr = os.path.join(here, "..", "paper_2603_24532_amd", "csrc", "turn_table.hpp")
     text = open(hdr).read()
+    N = int(re.search(r"#define MBPT_TURN_STEPS (\d+)", text).group(1))
+    assert N % 4 == 0
     rows = re.findall(r"\{(\S+), (\S+)\},\s+/\* k = (\d+) \*/", text)
-    assert len(rows) == 65
+    assert len(rows) == N + 1
     S = [float.fromhex(a) for a, _, _ in rows]
     C = [float.fromhex(b) for _, b, _ in rows]
-    assert [int(k) for _, _, k in rows] == list(range(65))
-    for k in range(0, 65, 16):
-        assert (S[k], C[k]) == ([0.0, 1.0, 0.0, -1.0, 0.0][k // 16], [1.0, 0.0, -1.0, 0.0, 1.0][k // 16])
+    assert [int(k) for _, _, k in rows] == list(range(N + 1))
+    Q = N // 4
+    for k in range(0, N + 1, Q):
+        assert (S[k], C[k]) == ([0.0, 1.0, 0.0, -1.0, 0.0][k // Q], [1.0, 0.0, -1.0, 0.0, 1.0][k // Q])
     u = 2.0 ** -53
-    for k in range(65):
-        ang = 2 * math.pi * k / 64
+    for k in range(N + 1):
+        ang = 2 * math.pi * k / N
         # the library's own argument rounding limits this comparison to ~1e-15
         assert abs(S[k] - math.sin(ang)) < 2e-15 and abs(C[k] - math.cos(ang)) < 2e-15
         assert abs(S[k] * S[k] + C[k] * C[k] - 1.0) <= 4 * u
         # quarter-turn and reflection symmetries hold exactly for rounded values
-        assert S[(k + 16) % 64] == C[k % 64] and C[(k + 16) % 64] == -S[k % 64]
-        assert S[(64 - k) % 64] == -S[k % 64] and C[(64 - k) % 64] == C[k % 64]
-        if k <= 32:
+        assert S[(k + Q) % N] == C[k % N] and C[(k + Q) % N] == -S[k % N]
+        assert S[(N - k) % N] == -S[k % N] and C[(N - k) % N] == C[k % N]
+        if k <= N // 2:
             # double-angle formula within a few ulp
             assert abs(S[2 * k] - 2 * S[k] * C[k]) <= 4 * u
     gen = os.path.join(os.path.dirname(hdr), "gen_turn_table.py")
