@@ -17,7 +17,8 @@ struct alignas(16) DiagDev {
   int loop_part[8];       // 1 if loop j is carried by a particle line
   uint32_t part_mask;     // bit l: line l is a particle line
   uint32_t line_mask;     // bits of all lines
-  int pad[2];
+  int id;                 // diagram id within its order (generator order)
+  int pad1;
   double pref;            // (1/2)^{n_eq} (-1)^{n_h + n_loop} (2 pi)^{-3L}
   double pad0;
   // Signed 0/1/2 coefficients as loop bitmasks (bits 0-7: +1, 8-15: -1,
@@ -30,17 +31,19 @@ struct alignas(16) DiagDev {
   int pad3[2];
 };
 
-// Orders 1 and 2 have one two-body diagram each.  Its descriptor masks (as the
-// generator compiles them, loops first) are compile-time constants for the
-// kernels of those orders, which then fold the loop-momentum sums, drop the
-// zero coefficients and share equal vertex momenta; compiling a task set
-// checks the generator's masks against these.
-template <int ORDER>
+// Compile-time descriptor masks for the diagrams whose kernels are
+// specialised: the one two-body diagram of orders 1 and 2 and the three of
+// order 3 (variant V = diagram id; V = -1 is the generic, descriptor-driven
+// path).  The masks are those the generator compiles (loops first, plain
+// loop order); with them the compiler folds the loop-momentum sums, drops the
+// zero coefficients and shares equal vertex momenta.  Task-set and server
+// creation check the generator's masks against these.
+template <int ORDER, int V>
 struct FixedMasks {
   static constexpr bool kFixed = false;
 };
 template <>
-struct FixedMasks<1> {
+struct FixedMasks<1, 0> {
   static constexpr bool kFixed = true;
   static constexpr uint32_t line_mask = 0x3u, part_mask = 0x0u;
   static constexpr uint32_t lmask[2] = {0x1u, 0x2u};
@@ -51,7 +54,7 @@ struct FixedMasks<1> {
   static constexpr int loop_part[2] = {0, 0};
 };
 template <>
-struct FixedMasks<2> {
+struct FixedMasks<2, 0> {
   static constexpr bool kFixed = true;
   static constexpr uint32_t line_mask = 0xFu, part_mask = 0x9u;
   static constexpr uint32_t lmask[4] = {0x1u, 0x2u, 0x4u, 0x106u};
@@ -60,6 +63,39 @@ struct FixedMasks<2> {
   static constexpr uint32_t cut_hole[1] = {0x6u};
   static constexpr uint32_t cut_part[1] = {0x9u};
   static constexpr int loop_part[3] = {1, 0, 0};
+};
+template <>
+struct FixedMasks<3, 0> {
+  static constexpr bool kFixed = true;
+  static constexpr uint32_t line_mask = 0x3Fu, part_mask = 0x11u;
+  static constexpr uint32_t lmask[6] = {0x1u, 0x2u, 0x4u, 0x8u, 0x10Cu, 0x20Cu};
+  static constexpr uint32_t pmask_v[3] = {0x100000Cu, 0x200000Cu, 0x804u};
+  static constexpr uint32_t qmask_v[3] = {0x200000Cu, 0x804u, 0x100000Cu};
+  static constexpr uint32_t cut_hole[2] = {0x22u, 0xCu};
+  static constexpr uint32_t cut_part[2] = {0x11u, 0x11u};
+  static constexpr int loop_part[4] = {1, 0, 0, 0};
+};
+template <>
+struct FixedMasks<3, 1> {
+  static constexpr bool kFixed = true;
+  static constexpr uint32_t line_mask = 0x3Fu, part_mask = 0x31u;
+  static constexpr uint32_t lmask[6] = {0x1u, 0x2u, 0x4u, 0x8u, 0x803u, 0x10Cu};
+  static constexpr uint32_t pmask_v[3] = {0x8010402u, 0x201u, 0x804u};
+  static constexpr uint32_t qmask_v[3] = {0x402u, 0x8000003u, 0x100000Cu};
+  static constexpr uint32_t cut_hole[2] = {0x6u, 0xCu};
+  static constexpr uint32_t cut_part[2] = {0x30u, 0x21u};
+  static constexpr int loop_part[4] = {1, 0, 0, 0};
+};
+template <>
+struct FixedMasks<3, 2> {
+  static constexpr bool kFixed = true;
+  static constexpr uint32_t line_mask = 0x3Fu, part_mask = 0x33u;
+  static constexpr uint32_t lmask[6] = {0x1u, 0x2u, 0x4u, 0x8u, 0x10Cu, 0x20Cu};
+  static constexpr uint32_t pmask_v[3] = {0x100000Cu, 0x200000Cu, 0x804u};
+  static constexpr uint32_t qmask_v[3] = {0x804u, 0x100000Cu, 0x200000Cu};
+  static constexpr uint32_t cut_hole[2] = {0xCu, 0xCu};
+  static constexpr uint32_t cut_part[2] = {0x11u, 0x22u};
+  static constexpr int loop_part[4] = {1, 1, 0, 0};
 };
 
 // Isospin configuration: lines whose bit is set carry protons.  first/count:

@@ -12,6 +12,8 @@
 // elementwise with no contraction, so it runs on the vector ALUs (no MFMA).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_types.hpp"
 #include "turn_table.hpp"
 #include "kernels.hpp"
@@ -179,47 +181,65 @@ __device__ __forceinline__ void masked_sum(uint32_t m, const double (*k)[3], dou
   out[2] = z;
 }
 
-// Descriptor masks: compile-time constants for orders 1 and 2 (FixedMasks),
-// else read from the descriptor.
-template <int ORDER>
+// Descriptor masks of diagram variant V: compile-time constants where
+// FixedMasks<ORDER, V> has them, else read from the descriptor.
+template <int ORDER, int V>
 __device__ __forceinline__ uint32_t lmask_of(const DiagDev *__restrict__ D, int l) {
-  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::lmask[l];
+  if constexpr (FixedMasks<ORDER, V>::kFixed) return FixedMasks<ORDER, V>::lmask[l];
   else return D->lmask[l];
 }
-template <int ORDER>
+template <int ORDER, int V>
 __device__ __forceinline__ uint32_t pmask_of(const DiagDev *__restrict__ D, int v) {
-  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::pmask_v[v];
+  if constexpr (FixedMasks<ORDER, V>::kFixed) return FixedMasks<ORDER, V>::pmask_v[v];
   else return D->pmask_v[v];
 }
-template <int ORDER>
+template <int ORDER, int V>
 __device__ __forceinline__ uint32_t qmask_of(const DiagDev *__restrict__ D, int v) {
-  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::qmask_v[v];
+  if constexpr (FixedMasks<ORDER, V>::kFixed) return FixedMasks<ORDER, V>::qmask_v[v];
   else return D->qmask_v[v];
 }
-template <int ORDER>
+template <int ORDER, int V>
 __device__ __forceinline__ uint32_t cut_hole_of(const DiagDev *__restrict__ D, int c) {
-  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::cut_hole[c];
+  if constexpr (FixedMasks<ORDER, V>::kFixed) return FixedMasks<ORDER, V>::cut_hole[c];
   else return D->cut_hole[c];
 }
-template <int ORDER>
+template <int ORDER, int V>
 __device__ __forceinline__ uint32_t cut_part_of(const DiagDev *__restrict__ D, int c) {
-  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::cut_part[c];
+  if constexpr (FixedMasks<ORDER, V>::kFixed) return FixedMasks<ORDER, V>::cut_part[c];
   else return D->cut_part[c];
 }
-template <int ORDER>
+template <int ORDER, int V>
 __device__ __forceinline__ uint32_t line_mask_of(const DiagDev *__restrict__ D) {
-  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::line_mask;
+  if constexpr (FixedMasks<ORDER, V>::kFixed) return FixedMasks<ORDER, V>::line_mask;
   else return D->line_mask;
 }
-template <int ORDER>
+template <int ORDER, int V>
 __device__ __forceinline__ uint32_t part_mask_of(const DiagDev *__restrict__ D) {
-  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::part_mask;
+  if constexpr (FixedMasks<ORDER, V>::kFixed) return FixedMasks<ORDER, V>::part_mask;
   else return D->part_mask;
 }
-template <int ORDER>
+template <int ORDER, int V>
 __device__ __forceinline__ bool loop_part_of(const DiagDev *__restrict__ D, int j) {
-  if constexpr (FixedMasks<ORDER>::kFixed) return FixedMasks<ORDER>::loop_part[j] != 0;
+  if constexpr (FixedMasks<ORDER, V>::kFixed) return FixedMasks<ORDER, V>::loop_part[j] != 0;
   else return D->loop_part[j] != 0;
+}
+
+// Runs f(std::integral_constant<int, V>) with the diagram variant of a task
+// whose first descriptor is D: the one diagram of orders 1-2 (also as a
+// single-member group), the diagram id at order 3 for single-diagram tasks,
+// the generic path (-1) otherwise.  The branch is uniform per work item.
+template <int ORDER, bool G, typename Fn>
+__device__ __forceinline__ void with_variant(const DiagDev *__restrict__ D, Fn &&f) {
+  if constexpr (ORDER <= 2) {
+    f(std::integral_constant<int, 0>{});
+  } else if constexpr (ORDER == 3 && !G) {
+    // ids 0..2 are the order's only diagrams (the host validates task ids)
+    if (D->id == 0) f(std::integral_constant<int, 0>{});
+    else if (D->id == 1) f(std::integral_constant<int, 1>{});
+    else f(std::integral_constant<int, 2>{});
+  } else {
+    f(std::integral_constant<int, -1>{});
+  }
 }
 
 // Square root of a finite a >= 0: hardware reciprocal square root refined by
@@ -379,14 +399,14 @@ __device__ __forceinline__ void monomials(const F *Vd, const F *Ve, F *M) {
 // single-particle energies depend on isospin (HF spectrum in nuclear matter):
 // D_c = Dn_c + sum over the cut's proton lines of +-(eps_p - eps_n), with
 // Dn_c the denominator with every line a neutron.
-template <int ORDER>
+template <int ORDER, int V>
 __device__ __forceinline__ double group_den(const DiagDev *__restrict__ D, uint32_t tau,
                                             const double *Dn, const double *deps) {
   constexpr int NL = 2 * ORDER;
   double prod = 1.0;
 #pragma unroll
   for (int c = 0; c < ORDER - 1; ++c) {
-    const uint32_t hm = cut_hole_of<ORDER>(D, c) & tau, pm = cut_part_of<ORDER>(D, c) & tau;
+    const uint32_t hm = cut_hole_of<ORDER, V>(D, c) & tau, pm = cut_part_of<ORDER, V>(D, c) & tau;
     double Dc = Dn[c];
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
@@ -402,7 +422,7 @@ __device__ __forceinline__ double group_den(const DiagDev *__restrict__ D, uint3
 // ISO: divide each configuration's sum by its own denominators (Dn, deps).
 // X: the explicit assignment list instead of the polynomial (compile-time, so
 // a kernel holds the state of one form only).
-template <int ORDER, int Q, typename F, bool ISO, bool X>
+template <int ORDER, int Q, typename F, bool ISO, bool X, int V>
 __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict__ D,
                                        const F *Vd, const F *Ve, uint32_t okN, uint32_t okP,
                                        uint32_t lmask, uint32_t &units, const double *Dn,
@@ -434,7 +454,7 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
           for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(c[eb * NA + ea], MA[ea], in);
           gs = fma_t<F>(in, MB[eb], gs);
         }
-        if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER>(D, tau, Dn, deps));
+        if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER, V>(D, tau, Dn, deps));
         acc += gs;
       }
     }
@@ -459,7 +479,7 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
           }
           gs = fma_t<F>(term_mult<F>(tm), prod, gs);
         }
-        if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER>(D, tau, Dn, deps));
+        if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER, V>(D, tau, Dn, deps));
         acc += gs;
       }
     }
@@ -501,7 +521,7 @@ __device__ __forceinline__ double rcp_newton(double d) {
 // particle energies of the Hartree-Fock spectrum (tables in LDS).
 // REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
 // to wr[k - 1].
-template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI>
+template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
@@ -523,7 +543,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
       kv[1] = k[l][1];
       kv[2] = k[l][2];
     } else {
-      masked_sum<L, false, FixedMasks<ORDER>::kFixed>(lmask_of<ORDER>(D, l), k, kv);
+      masked_sum<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
     }
     const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = a.phys.hb2m * k2;
@@ -538,7 +558,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
     if (Q == 4) inP |= (k2 < T->kF2[1]) ? (1u << l) : 0u;
   }
   // a hole line is allowed if occupied, a particle line if empty
-  const uint32_t lmask = line_mask_of<ORDER>(D), pmask = part_mask_of<ORDER>(D);
+  const uint32_t lmask = line_mask_of<ORDER, V>(D), pmask = part_mask_of<ORDER, V>(D);
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
   if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
@@ -551,11 +571,11 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   double Dn[NC > 0 ? NC : 1];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const uint32_t hm = cut_hole_of<ORDER>(D, c), pm = cut_part_of<ORDER>(D, c);
+    const uint32_t hm = cut_hole_of<ORDER, V>(D, c), pm = cut_part_of<ORDER, V>(D, c);
     double Dc = 0.0;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-      if constexpr (FixedMasks<ORDER>::kFixed) {
+      if constexpr (FixedMasks<ORDER, V>::kFixed) {
         if (hm & (1u << l)) Dc += eps[l];
         else if (pm & (1u << l)) Dc -= eps[l];
       } else {
@@ -583,8 +603,8 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
     double p[3], q[3];  // relative momenta p and p'
-    masked_sum<L, true, FixedMasks<ORDER>::kFixed>(pmask_of<ORDER>(D, v), k, p);
-    masked_sum<L, true, FixedMasks<ORDER>::kFixed>(qmask_of<ORDER>(D, v), k, q);
+    masked_sum<L, true, FixedMasks<ORDER, V>::kFixed>(pmask_of<ORDER, V>(D, v), k, p);
+    masked_sum<L, true, FixedMasks<ORDER, V>::kFixed>(qmask_of<ORDER, V>(D, v), k, q);
     const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const double pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
@@ -636,7 +656,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   const double regall = exp_nonpos(-yreg * a.phys.invLn, Ls.ex);
 
   const double acc =
-      label_sum<ORDER, Q, double, iso_den, X>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn, deps);
+      label_sum<ORDER, Q, double, iso_den, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn, deps);
   const double base = D->pref * regall * acc;
   if constexpr (REG) {
     for (int r = 0; r < a.nreg; ++r) {
@@ -655,7 +675,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 // or (G) the task's T->ndiag group members summed.
 // REG: the regularised components go to wr[0..nreg) (Jacobian and 1/n
 // included).
-template <int ORDER, int Q, bool HF, bool G, bool X, bool PI, bool REG = false>
+template <int ORDER, int Q, bool HF, bool G, bool X, bool PI, int V, bool REG = false>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, uint64_t s,
@@ -670,7 +690,7 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   double k[L][3];
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    const double R = loop_part_of<ORDER>(D, j) ? T->Rp : T->Rh;
+    const double R = loop_part_of<ORDER, V>(D, j) ? T->Rp : T->Rh;
     const double rad = R * x[3 * j];
     const double ct = 2.0 * x[3 * j + 1] - 1.0;
     const double st = sqrt_normal((1.0 - ct) * (1.0 + ct));
@@ -688,9 +708,9 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     sum = 0.0;
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di)
-      sum += diag_weight64<ORDER, Q, HF, REG, X, PI>(a, T, D + di, Ls, k, npass, nterms, wr);
+      sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V>(a, T, D + di, Ls, k, npass, nterms, wr);
   } else {
-    sum = diag_weight64<ORDER, Q, HF, REG, X, PI>(a, T, D, Ls, k, npass, nterms, wr);
+    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V>(a, T, D, Ls, k, npass, nterms, wr);
   }
   const double scale = jac * T->inv_density;
   if constexpr (REG)
@@ -735,7 +755,7 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 // sample in fp64 from the same random words.
 // fp32 contribution of one diagram at the loop momenta k (see
 // diag_weight64); sets `fallback` instead when the sample needs fp64.
-template <int ORDER, int Q, bool X>
+template <int ORDER, int Q, bool X, int V>
 __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const float (*k)[3], uint32_t &npass,
@@ -757,7 +777,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
       kv[1] = k[l][1];
       kv[2] = k[l][2];
     } else {
-      masked_sum_f<L, false, FixedMasks<ORDER>::kFixed>(lmask_of<ORDER>(D, l), k, kv);
+      masked_sum_f<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
     }
     const float k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = hb2m * k2;
@@ -772,7 +792,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
     fallback = true;
     return 0.0;
   }
-  const uint32_t lmask = line_mask_of<ORDER>(D), pmask = part_mask_of<ORDER>(D);
+  const uint32_t lmask = line_mask_of<ORDER, V>(D), pmask = part_mask_of<ORDER, V>(D);
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
   if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
@@ -780,7 +800,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   float dprod = 1.0f;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const uint32_t hm = cut_hole_of<ORDER>(D, c), pm = cut_part_of<ORDER>(D, c);
+    const uint32_t hm = cut_hole_of<ORDER, V>(D, c), pm = cut_part_of<ORDER, V>(D, c);
     float Dc = 0.0f, Dabs = 0.0f;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
@@ -801,8 +821,8 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
     float p[3], q[3];
-    masked_sum_f<L, true, FixedMasks<ORDER>::kFixed>(pmask_of<ORDER>(D, v), k, p);
-    masked_sum_f<L, true, FixedMasks<ORDER>::kFixed>(qmask_of<ORDER>(D, v), k, q);
+    masked_sum_f<L, true, FixedMasks<ORDER, V>::kFixed>(pmask_of<ORDER, V>(D, v), k, p);
+    masked_sum_f<L, true, FixedMasks<ORDER, V>::kFixed>(qmask_of<ORDER, V>(D, v), k, q);
     const float p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const float q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const float pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
@@ -846,14 +866,14 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   const float regall = __expf(-yexp);
 
   const float acc =
-      label_sum<ORDER, Q, float, false, X>(a, D, Vd, Ve, okN, okP, lmask, nterms, nullptr,
+      label_sum<ORDER, Q, float, false, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms, nullptr,
                                            nullptr);
   ++npass;
   return D->pref * static_cast<double>(regall) * static_cast<double>(acc) *
          static_cast<double>(rinv[NR - 1]);
 }
 
-template <int ORDER, int Q, bool G, bool X>
+template <int ORDER, int Q, bool G, bool X, int V>
 __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, uint64_t s,
@@ -868,7 +888,7 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
   float k[L][3];
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    const double R = loop_part_of<ORDER>(D, j) ? T->Rp : T->Rh;
+    const double R = loop_part_of<ORDER, V>(D, j) ? T->Rp : T->Rh;
     const double rad64 = R * x[3 * j];
     jac *= R * rad64 * rad64 * (4.0 * M_PI);
     const float rad = static_cast<float>(rad64);
@@ -886,11 +906,11 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     sum = 0.0;
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di) {
-      sum += diag_weight32<ORDER, Q, X>(a, T, D + di, k, npass, nterms, fallback);
+      sum += diag_weight32<ORDER, Q, X, V>(a, T, D + di, k, npass, nterms, fallback);
       if (fallback) return 0.0;  // the whole sample is re-evaluated in fp64
     }
   } else {
-    sum = diag_weight32<ORDER, Q, X>(a, T, D, k, npass, nterms, fallback);
+    sum = diag_weight32<ORDER, Q, X, V>(a, T, D, k, npass, nterms, fallback);
     if (fallback) return 0.0;
   }
   return jac * T->inv_density * sum;
@@ -931,14 +951,20 @@ __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__r
   constexpr int PP = prec_of<P>();
   constexpr bool G = group_of<P>();
   constexpr bool PI = pair_inv<ORDER, Q, P>();
-  if (PP != 1)
-    return eval_fp64<ORDER, Q, PP == 2, G, X, PI>(a, T, D, Ls, s, iter, bins, npass, nterms);
-  bool fb = false;
-  double w = eval_fp32<ORDER, Q, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
-  if (fb) {
-    ++nfb;
-    w = eval_fp64<ORDER, Q, false, G, X, PI>(a, T, D, Ls, s, iter, bins, npass, nterms);
-  }
+  double w = 0.0;
+  with_variant<ORDER, G>(D, [&](auto vt) {
+    constexpr int V = decltype(vt)::value;
+    if (PP != 1) {
+      w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V>(a, T, D, Ls, s, iter, bins, npass, nterms);
+      return;
+    }
+    bool fb = false;
+    w = eval_fp32<ORDER, Q, G, X, V>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
+    if (fb) {
+      ++nfb;
+      w = eval_fp64<ORDER, Q, false, G, X, PI, V>(a, T, D, Ls, s, iter, bins, npass, nterms);
+    }
+  });
   return w;
 }
 
@@ -1001,75 +1027,79 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
   constexpr int PP = prec_of<P>();
   constexpr bool G = group_of<P>();
   constexpr bool PI = pair_inv<ORDER, Q, P>();
-  if (PP != 1) {
-    for (int kk = 0; kk < a.spt; ++kk) {
-      const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
-      if (s < N) {
-        int bins[ND];
-        if constexpr (R) {
-          double wr[kMaxReg];
-          const double w =
-              eval_fp64<ORDER, Q, false, G, X, PI, true>(a, T, D, Ls, s, iter, bins, npass, nterms,
-                                                         wr);
-          accumulate(w, bins);
-#pragma unroll
-          for (int r = 0; r < kMaxReg; ++r) {
-            const double d = wr[r] - shift;
-            rs[2 * r] += d;
-            rs[2 * r + 1] += d * d;
+  // the sample loops, specialised per diagram variant (uniform per item)
+  with_variant<ORDER, G>(D, [&](auto vt) {
+    constexpr int V = decltype(vt)::value;
+    if (PP != 1) {
+      for (int kk = 0; kk < a.spt; ++kk) {
+        const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
+        if (s < N) {
+          int bins[ND];
+          if constexpr (R) {
+            double wr[kMaxReg];
+            const double w =
+                eval_fp64<ORDER, Q, false, G, X, PI, V, true>(a, T, D, Ls, s, iter, bins, npass, nterms,
+                                                           wr);
+            accumulate(w, bins);
+  #pragma unroll
+            for (int r = 0; r < kMaxReg; ++r) {
+              const double d = wr[r] - shift;
+              rs[2 * r] += d;
+              rs[2 * r + 1] += d * d;
+            }
+          } else {
+            const double w =
+                eval_fp64<ORDER, Q, PP == 2, G, X, PI, V>(a, T, D, Ls, s, iter, bins, npass, nterms);
+            accumulate(w, bins);
           }
-        } else {
-          const double w =
-              eval_fp64<ORDER, Q, PP == 2, G, X, PI>(a, T, D, Ls, s, iter, bins, npass, nterms);
-          accumulate(w, bins);
         }
       }
+    } else {
+      // fp32 pass; samples in the fp64 band are queued per wavefront (ballot
+      // order, so the accumulation order is deterministic) and re-evaluated in
+      // fp64 by whole wavefronts, 64 at a time
+      const int lane = tid & 63;
+      uint32_t *queue = reinterpret_cast<uint32_t *>(red + 6 * (bs >> 6)) + 128 * (tid >> 6);
+      int qn = 0;  // wave-uniform
+      auto drain = [&](int take) {
+        if (lane < take) {
+          const uint64_t s = base + queue[lane];
+          int bins[ND];
+          const double w =
+              eval_fp64<ORDER, Q, false, G, X, PI, V>(a, T, D, Ls, s, iter, bins, npass, nterms);
+          accumulate(w, bins);
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int rest = qn - take;
+        uint32_t moved = (lane < rest) ? queue[take + lane] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) queue[lane] = moved;
+        __builtin_amdgcn_wave_barrier();
+        qn = rest;
+      };
+      for (int kk = 0; kk < a.spt; ++kk) {
+        const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
+        bool fb = false;
+        if (s < N) {
+          int bins[ND];
+          const double w =
+              eval_fp32<ORDER, Q, G, X, V>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
+          if (!fb) accumulate(w, bins);
+        }
+        const uint64_t mask = __ballot(fb);
+        if (fb) {
+          const int pos = qn + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+          queue[pos] = static_cast<uint32_t>(s - base);
+          ++nfb;
+        }
+        qn += __popcll(mask);
+        __builtin_amdgcn_wave_barrier();
+        if (qn >= 64) drain(64);
+      }
+      while (qn > 0) drain(qn < 64 ? qn : 64);
     }
-  } else {
-    // fp32 pass; samples in the fp64 band are queued per wavefront (ballot
-    // order, so the accumulation order is deterministic) and re-evaluated in
-    // fp64 by whole wavefronts, 64 at a time
-    const int lane = tid & 63;
-    uint32_t *queue = reinterpret_cast<uint32_t *>(red + 6 * (bs >> 6)) + 128 * (tid >> 6);
-    int qn = 0;  // wave-uniform
-    auto drain = [&](int take) {
-      if (lane < take) {
-        const uint64_t s = base + queue[lane];
-        int bins[ND];
-        const double w =
-            eval_fp64<ORDER, Q, false, G, X, PI>(a, T, D, Ls, s, iter, bins, npass, nterms);
-        accumulate(w, bins);
-      }
-      __builtin_amdgcn_wave_barrier();
-      const int rest = qn - take;
-      uint32_t moved = (lane < rest) ? queue[take + lane] : 0u;
-      __builtin_amdgcn_wave_barrier();
-      if (lane < rest) queue[lane] = moved;
-      __builtin_amdgcn_wave_barrier();
-      qn = rest;
-    };
-    for (int kk = 0; kk < a.spt; ++kk) {
-      const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
-      bool fb = false;
-      if (s < N) {
-        int bins[ND];
-        const double w =
-            eval_fp32<ORDER, Q, G, X>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
-        if (!fb) accumulate(w, bins);
-      }
-      const uint64_t mask = __ballot(fb);
-      if (fb) {
-        const int pos = qn + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
-        queue[pos] = static_cast<uint32_t>(s - base);
-        ++nfb;
-      }
-      qn += __popcll(mask);
-      __builtin_amdgcn_wave_barrier();
-      if (qn >= 64) drain(64);
-    }
-    while (qn > 0) drain(qn < 64 ? qn : 64);
-  }
+  });
   // wavefront butterfly, then waves in order (compensated pairs s + c)
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -1154,6 +1184,8 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 // - HF kernels (isospin-dependent spectra keep per-line energy differences
 //   live): 2 waves from third order on, 20-45% faster than at one, except
 //   fifth-order neutron matter, which loses a third to ~520 spilled bytes.
+// - third order, fp64 and fp32 (single diagrams specialised per diagram):
+//   4 waves with 60-130 spilled bytes beat 3 waves without (4-7%);
 // Other kernels fit their natural occupancy.
 template <int ORDER, int Q, int P, bool X>
 constexpr int min_waves() {
@@ -1162,6 +1194,7 @@ constexpr int min_waves() {
     if (ORDER == 3 || ORDER == 4) return 2;
     return (ORDER == 5 && Q == 4) ? 2 : 1;
   }
+  if (ORDER == 3 && (P == 0 || P == 1)) return 4;
   if (ORDER == 4) return (P == 0 || P == 1 || P == 3 || P == 4 || P == 5) ? 3 : 2;
   if (ORDER == 5) {
     if (P == 1 || P == 3 || P == 4 || (P == 0 && X)) return 3;
@@ -1473,8 +1506,11 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
     uint32_t np = 0, nt = 0, nf = 0;
     if constexpr (reg_of<P>()) {
       double wr[kMaxReg];
-      out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, PI, true>(a, T, D, Ls, first + i,
-                                                                      iter, bins, np, nt, wr);
+      with_variant<ORDER, group_of<P>()>(D, [&](auto vt) {
+        constexpr int V = decltype(vt)::value;
+        out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, PI, V, true>(a, T, D, Ls, first + i,
+                                                                         iter, bins, np, nt, wr);
+      });
       if (out_reg)
         for (int r = 0; r < a.nreg; ++r) out_reg[i * a.nreg + r] = wr[r];
     } else {

@@ -294,12 +294,13 @@ void fill_diag_dev(const Diagram &d, DiagDev &dd, bool canonical) {
     }
 }
 
-// The kernels of orders 1 and 2 take the descriptor masks of their one
-// diagram as compile-time constants (FixedMasks); true if the generator's
-// descriptors (plain and canonical loop order) are those (checked once).
-template <int ORDER>
+// The kernels of orders 1-3 take the descriptor masks of the order's
+// diagrams as compile-time constants (FixedMasks); true if the generator's
+// descriptors are those (checked once; order-3 group tasks take the generic
+// path, so only the plain loop order is checked there).
+template <int ORDER, int V>
 static bool fixed_masks_match(const DiagDev &dd) {
-  using F = FixedMasks<ORDER>;
+  using F = FixedMasks<ORDER, V>;
   constexpr int NL = 2 * ORDER, L = ORDER + 1, NC = ORDER - 1;
   bool ok = dd.line_mask == F::line_mask && dd.part_mask == F::part_mask;
   for (int l = 0; l < NL; ++l) ok = ok && dd.lmask[l] == F::lmask[l];
@@ -314,12 +315,18 @@ static bool fixed_masks_match(const DiagDev &dd) {
 bool fixed_masks_ok() {
   static const bool ok = [] {
     bool r = true;
+    auto dev = [](int order, int id, bool canonical) {
+      DiagDev d{};
+      fill_diag_dev(*get_diagram(order, id), d, canonical);
+      return d;
+    };
     for (int canonical = 0; canonical < 2; ++canonical) {
-      DiagDev d1{}, d2{};
-      fill_diag_dev(*get_diagram(1, 0), d1, canonical != 0);
-      fill_diag_dev(*get_diagram(2, 0), d2, canonical != 0);
-      r = r && fixed_masks_match<1>(d1) && fixed_masks_match<2>(d2);
+      r = r && fixed_masks_match<1, 0>(dev(1, 0, canonical != 0));
+      r = r && fixed_masks_match<2, 0>(dev(2, 0, canonical != 0));
     }
+    r = r && fixed_masks_match<3, 0>(dev(3, 0, false));
+    r = r && fixed_masks_match<3, 1>(dev(3, 1, false));
+    r = r && fixed_masks_match<3, 2>(dev(3, 2, false));
     return r;
   }();
   return ok;
@@ -450,6 +457,7 @@ int compile_tables(mbpt_task_set *set) {
         }
         DiagDev dd{};
         dd.order = d->order;
+        dd.id = d->id;
         dd.nlines = d->nlines;
         dd.nloops = d->nloops;
         dd.ncuts = d->ncuts;
@@ -800,7 +808,7 @@ extern "C" int mbpt_create_task_set(mbpt_context *ctx, const mbpt_task_desc *tas
   if (!ctx || !out) return MBPT_EINVAL;
   *out = nullptr;
   if (!fixed_masks_ok()) {
-    set_err(ctx, "internal: the order-1/2 descriptors differ from the kernels' fixed masks");
+    set_err(ctx, "internal: the order-1/2/3 descriptors differ from the kernels' fixed masks");
     return MBPT_EINVAL;
   }
   int q = 2;

@@ -282,6 +282,7 @@ const mbpt_server::Compiled &compiled_of(mbpt_server *s, int order, int id) {
   const Diagram *d = get_diagram(order, id);
   mbpt_server::Compiled c{};
   c.dd.order = d->order;
+  c.dd.id = d->id;
   c.dd.nlines = d->nlines;
   c.dd.nloops = d->nloops;
   c.dd.ncuts = d->ncuts;
@@ -429,7 +430,7 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
     return MBPT_EINVAL;
   }
   if (!fixed_masks_ok()) {
-    set_err(ctx, "internal: the order-1/2 descriptors differ from the kernels' fixed masks");
+    set_err(ctx, "internal: the order-1/2/3 descriptors differ from the kernels' fixed masks");
     return MBPT_EINVAL;
   }
   Layout L{};
