@@ -50,7 +50,7 @@ extern "C" {
 /* Integrand arithmetic.  FP64: everything in double.  FP32: the per-sample
  * integrand in float with the variance sums, the grid refinement and every
  * sample inside the near-Fermi-surface / small-denominator band re-evaluated in
- * double (compensated fp64 accumulation). */
+ * double (fp64 accumulation, compensated across threads and work items). */
 enum { MBPT_FP64 = 0, MBPT_FP32 = 1 };
 /* Matter: NEUTRON = pure neutron matter, spin labels only (degeneracy 2,
  * proton fraction must be 0); NUCLEAR = spin x isospin labels (degeneracy 4),

@@ -5,10 +5,10 @@
 // from the compiled descriptor -> Pauli factors (n_k for holes, 1 - n_k for
 // particles) -> energy denominators (eq:Dijkabc, free spectrum) ->
 // antisymmetrised matrix elements per vertex -> explicit spin(-isospin) label
-// sum -> weight.  Sums of (w - c) and (w - c)^2 are kept per thread with
-// Neumaier compensation, reduced across the wavefront and the block in a
-// fixed order and written per work item; refinement histograms of w^2 are
-// privatised in LDS and merged with fp64 atomics.  The integrand is
+// sum -> weight.  Sums of (w - c) and (w - c)^2 are kept per thread as plain
+// sums (at most spt terms), merged across the wavefront, the block and the
+// work items with compensated pair merges in a fixed order; refinement
+// histograms of w^2 are privatised in LDS and merged with fp64 atomics.  The integrand is
 // elementwise with no contraction, so it runs on the vector ALUs (no MFMA).
 #include <hip/hip_runtime.h>
 
@@ -46,12 +46,6 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
   out[3] = c3;
 }
 
-// sum_j c_j v_j over loops j < L with c_j in {0, +-1, +-2} given as the
-// uniform bitmask m (bits 0-7: +1, 8-15: -1, 16-23: +2, 24-31: -2); zero
-// coefficients cost nothing (uniform branches).
-// Coefficient c in {0, +-1, +-2} of loop j in the uniform bitmask m (bits
-// 0-7: +1, 8-15: -1, 16-23: +2, 24-31: -2) as a double, built from its bit
-// pattern with scalar instructions only.
 // sin and cos of 2 pi k / MBPT_TURN_STEPS (copied into LDS by every sample
 // kernel).
 struct alignas(16) SinCos {
@@ -150,8 +144,10 @@ __device__ __forceinline__ void sincos_turn(const SinCos *__restrict__ tab, doub
   c = fma(t.c, cm, fma(-t.s, sd, t.c));
 }
 
-// HALF: the coefficients halved (vertex relative momenta are half the
-// difference of two line momenta)
+// Coefficient c in {0, +-1, +-2} of loop j in the uniform bitmask m (bits
+// 0-7: +1, 8-15: -1, 16-23: +2, 24-31: -2) as a double, built from its bit
+// pattern with scalar instructions only.  HALF: the coefficients halved
+// (vertex relative momenta are half the difference of two line momenta).
 template <bool HALF = false>
 __device__ __forceinline__ double mask_coef(uint32_t m, int j) {
   uint32_t hi = 0u;

@@ -89,7 +89,7 @@ void count_flops(const Diagram &d, int q, int half_exp, int label_mode, int spec
     post += (1 << H) + (1 << (n - H)) - 2;
     f.per_term = 2.0 * ((1 << n) + (1 << (n - H))) + iso_den;
   }
-  double acc = 10.0 + 1.0 + ND; // shifted sums (Neumaier), w^2, histogram adds
+  double acc = 4.0 + 1.0 + ND;  // shifted sums (d = w - c, s1 += d, s2 += d^2), w^2, histogram adds
   f.pre = pre + pre_t + acc;    // every sample is accumulated
   // map, loop momenta and accumulation: once per sample even for a group
   f.transc_shared = 3.0 * L;
