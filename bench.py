@@ -452,7 +452,7 @@ def main():
     LABEL_MODE = args.label_mode
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
-              "this build has no multi-GPU path", file=sys.stderr)
+              "this library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload != "plain":
         if args.workload == "batched":
