@@ -238,6 +238,22 @@ __device__ __forceinline__ void with_variant(const DiagDev *__restrict__ D, Fn &
   }
 }
 
+// (p^2)^(reg_exp / 2) for the regulator exponent: HE > 0 is reg_exp / 2 fixed
+// at compile time (the kernels of orders 1-2 for the quartic regulator, whose
+// vertices then share their regulator factors), HE = 0 takes it from the
+// launch (a uniform loop).  Both multiply the same factors in the same order.
+template <int HE, typename F>
+__device__ __forceinline__ F reg_pow(F p2, int half_exp) {
+  F r = p2;
+  if constexpr (HE > 0) {
+#pragma unroll
+    for (int e = 1; e < HE; ++e) r *= p2;
+  } else {
+    for (int e = 1; e < half_exp; ++e) r *= p2;
+  }
+  return r;
+}
+
 // Square root of a finite a >= 0: hardware reciprocal square root refined by
 // one coupled step on g = sqrt(a) and h = 1 / (2 sqrt(a)) (doubling its
 // correct bits) and one Newton correction of g.  No rescaling: a is clamped to
@@ -285,8 +301,8 @@ __device__ __forceinline__ double vegas_map(const KArgs &a, const TaskDev *__res
   // bin b = floor(w nb / 2^32), fraction ((w nb mod 2^32) + 1/2) / 2^32.
   // y = w nb 2^-32 is exact in fp64 (at most 39 significant bits), so b (the
   // truncation of y >= 0) and y - b (v_fract_f64) come out exactly; the half
-  // is folded into the grid pair's first entry, e_b + w_b 2^-33.  The
-  // Jacobian prod_m nb width_m takes nb^ND once.
+  // is folded into the grid pair's first entry, e_b + w_b 2^-33.  Returns
+  // prod_m width_m; the factor nb^ND is in jac_const.
   double jac = 1.0;
   const double nbscale = static_cast<double>(nb) * 0x1p-32;
 #pragma unroll
@@ -299,11 +315,26 @@ __device__ __forceinline__ double vegas_map(const KArgs &a, const TaskDev *__res
     jac *= ew.y;
     bins[m] = b;
   }
-  double nbp = static_cast<double>(nb);
-#pragma unroll
-  for (int m = 1; m < ND; ++m) nbp *= static_cast<double>(nb);
-  jac *= nbp;
   return jac;
+}
+
+// Sample-independent part of the Jacobian of a task (uniform, hoisted out of
+// the sample loops): nb^ND from the VEGAS map, 4 pi R_j^3 per loop from the
+// spherical map (the rest, x0_j^2, is per sample), and 1/n.
+template <int ORDER, int V>
+__device__ __forceinline__ double jac_const(const KArgs &a, const TaskDev *__restrict__ T,
+                                            const DiagDev *__restrict__ D) {
+  constexpr int L = ORDER + 1;
+  double c = T->inv_density;
+  const double nb = static_cast<double>(a.phys.nb);
+#pragma unroll
+  for (int m = 0; m < 3 * L; ++m) c *= nb;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const double R = loop_part_of<ORDER, V>(D, j) ? T->Rp : T->Rh;
+    c *= (4.0 * M_PI) * R * R * R;
+  }
+  return c;
 }
 
 // True if some label assignment survives the Pauli factors: neutron matter
@@ -517,7 +548,7 @@ __device__ __forceinline__ double rcp_newton(double d) {
 // particle energies of the Hartree-Fock spectrum (tables in LDS).
 // REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
 // to wr[k - 1].
-template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V>
+template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V, int HE = 0>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
@@ -604,16 +635,8 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
     const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const double pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
-    double pn = p2 * p2, qn = q2 * q2;  // exponent 4, the workload's
-    if (a.phys.half_exp != 2) {
-      pn = p2;
-      qn = q2;
-      for (int e = 1; e < a.phys.half_exp; ++e) {
-        pn *= p2;
-        qn *= q2;
-      }
-    }
-    yreg += pn + qn;
+    const double pn = reg_pow<HE>(p2, a.phys.half_exp), qn = reg_pow<HE>(q2, a.phys.half_exp);
+    yreg = v == 0 ? pn + qn : yreg + (pn + qn);
     const double s2 = p2 + q2 + a.phys.m2;
     const double dd = s2 - 2.0 * pq, de = s2 + 2.0 * pq;
     if constexpr (kPairInv) {
@@ -671,10 +694,10 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 // or (G) the task's T->ndiag group members summed.
 // REG: the regularised components go to wr[0..nreg) (Jacobian and 1/n
 // included).
-template <int ORDER, int Q, bool HF, bool G, bool X, bool PI, int V, bool REG = false>
+template <int ORDER, int Q, bool HF, bool G, bool X, bool PI, int V, bool REG = false, int HE = 0>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
-                                            const SampleLds &Ls, uint64_t s,
+                                            const SampleLds &Ls, double jc, uint64_t s,
                                             uint32_t iter, int *bins, uint32_t &npass,
                                             uint32_t &nterms, double *wr = nullptr) {
   constexpr int L = ORDER + 1;
@@ -683,7 +706,9 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   double jac = vegas_map<ND>(a, T, Ls.g, s, iter, x, bins);
 
   // loop momenta: radius R x0, cos theta = 2 x1 - 1, azimuth 2 pi x2
+  // (Jacobian 4 pi R^3 x0^2 per loop)
   double k[L][3];
+  double x0p = 1.0;  // prod_j x0_j
 #pragma unroll
   for (int j = 0; j < L; ++j) {
     const double R = loop_part_of<ORDER, V>(D, j) ? T->Rp : T->Rh;
@@ -695,7 +720,7 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     k[j][0] = rad * st * cp;
     k[j][1] = rad * st * sp;
     k[j][2] = rad * ct;
-    jac *= R * rad * rad * (4.0 * M_PI);
+    x0p *= x[3 * j];
   }
   if constexpr (REG)
     for (int r = 0; r < kMaxReg; ++r) wr[r] = 0.0;
@@ -704,11 +729,11 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     sum = 0.0;
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di)
-      sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V>(a, T, D + di, Ls, k, npass, nterms, wr);
+      sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE>(a, T, D + di, Ls, k, npass, nterms, wr);
   } else {
-    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V>(a, T, D, Ls, k, npass, nterms, wr);
+    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE>(a, T, D, Ls, k, npass, nterms, wr);
   }
-  const double scale = jac * T->inv_density;
+  const double scale = jac * (x0p * x0p) * jc;
   if constexpr (REG)
     for (int r = 0; r < kMaxReg; ++r) wr[r] *= scale;
   return scale * sum;
@@ -751,7 +776,7 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 // sample in fp64 from the same random words.
 // fp32 contribution of one diagram at the loop momenta k (see
 // diag_weight64); sets `fallback` instead when the sample needs fp64.
-template <int ORDER, int Q, bool X, int V>
+template <int ORDER, int Q, bool X, int V, int HE = 0>
 __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const float (*k)[3], uint32_t &npass,
@@ -812,7 +837,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
 
   constexpr int NR = 2 * ORDER + 1;
   float den[NR];
-  float yreg = 0.0f;
+  float yreg = 0.0f;  // sum of the regulator exponents
   const float m2 = static_cast<float>(a.phys.m2);
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
@@ -822,12 +847,8 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
     const float p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const float q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const float pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
-    float pn = p2, qn = q2;
-    for (int e = 1; e < a.phys.half_exp; ++e) {
-      pn *= p2;
-      qn *= q2;
-    }
-    yreg += pn + qn;
+    const float pn = reg_pow<HE>(p2, a.phys.half_exp), qn = reg_pow<HE>(q2, a.phys.half_exp);
+    yreg = v == 0 ? pn + qn : yreg + (pn + qn);
     const float s2 = p2 + q2 + m2;
     den[2 * v] = s2 - 2.0f * pq;
     den[2 * v + 1] = s2 + 2.0f * pq;
@@ -869,10 +890,10 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
          static_cast<double>(rinv[NR - 1]);
 }
 
-template <int ORDER, int Q, bool G, bool X, int V>
+template <int ORDER, int Q, bool G, bool X, int V, int HE = 0>
 __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
-                                            const SampleLds &Ls, uint64_t s,
+                                            const SampleLds &Ls, double jc, uint64_t s,
                                             uint32_t iter, int *bins, uint32_t &npass,
                                             uint32_t &nterms, bool &fallback) {
   constexpr int L = ORDER + 1;
@@ -882,11 +903,12 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
 
   // loop momenta; the azimuth goes to the hardware sine/cosine in revolutions
   float k[L][3];
+  double x0p = 1.0;  // prod_j x0_j
 #pragma unroll
   for (int j = 0; j < L; ++j) {
     const double R = loop_part_of<ORDER, V>(D, j) ? T->Rp : T->Rh;
     const double rad64 = R * x[3 * j];
-    jac *= R * rad64 * rad64 * (4.0 * M_PI);
+    x0p *= x[3 * j];
     const float rad = static_cast<float>(rad64);
     const float ct = static_cast<float>(2.0 * x[3 * j + 1] - 1.0);
     const float st = __builtin_sqrtf(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
@@ -902,14 +924,14 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     sum = 0.0;
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di) {
-      sum += diag_weight32<ORDER, Q, X, V>(a, T, D + di, k, npass, nterms, fallback);
+      sum += diag_weight32<ORDER, Q, X, V, HE>(a, T, D + di, k, npass, nterms, fallback);
       if (fallback) return 0.0;  // the whole sample is re-evaluated in fp64
     }
   } else {
-    sum = diag_weight32<ORDER, Q, X, V>(a, T, D, k, npass, nterms, fallback);
+    sum = diag_weight32<ORDER, Q, X, V, HE>(a, T, D, k, npass, nterms, fallback);
     if (fallback) return 0.0;
   }
-  return jac * T->inv_density * sum;
+  return jac * (x0p * x0p) * jc * sum;
 }
 
 // Kernel mode P: 0 fp64; 1 fp32 with the fp64 fallback; 2 fp64 with the
@@ -950,15 +972,16 @@ __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__r
   double w = 0.0;
   with_variant<ORDER, G>(D, [&](auto vt) {
     constexpr int V = decltype(vt)::value;
+    const double jc = jac_const<ORDER, V>(a, T, D);
     if (PP != 1) {
-      w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V>(a, T, D, Ls, s, iter, bins, npass, nterms);
+      w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V>(a, T, D, Ls, jc, s, iter, bins, npass, nterms);
       return;
     }
     bool fb = false;
-    w = eval_fp32<ORDER, Q, G, X, V>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
+    w = eval_fp32<ORDER, Q, G, X, V>(a, T, D, Ls, jc, s, iter, bins, npass, nterms, fb);
     if (fb) {
       ++nfb;
-      w = eval_fp64<ORDER, Q, false, G, X, PI, V>(a, T, D, Ls, s, iter, bins, npass, nterms);
+      w = eval_fp64<ORDER, Q, false, G, X, PI, V>(a, T, D, Ls, jc, s, iter, bins, npass, nterms);
     }
   });
   return w;
@@ -971,9 +994,10 @@ constexpr int lds_tables() {
 }
 
 // ---------------------------------------------------------------------------
-// Work item: blockDim.x * spt consecutive samples of one task
+// Work item: blockDim.x * spt consecutive samples of one task (HE: the
+// regulator exponent's half fixed at compile time, or 0, see reg_pow)
 
-template <int ORDER, int Q, int P, bool X>
+template <int ORDER, int Q, int P, bool X, int HE>
 __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, double *smem) {
   constexpr int ND = 3 * (ORDER + 1);
   const TaskDev *__restrict__ T = a.tasks + t;
@@ -1026,6 +1050,7 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
   // the sample loops, specialised per diagram variant (uniform per item)
   with_variant<ORDER, G>(D, [&](auto vt) {
     constexpr int V = decltype(vt)::value;
+    const double jc = jac_const<ORDER, V>(a, T, D);
     if (PP != 1) {
       for (int kk = 0; kk < a.spt; ++kk) {
         const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
@@ -1034,18 +1059,18 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
           if constexpr (R) {
             double wr[kMaxReg];
             const double w =
-                eval_fp64<ORDER, Q, false, G, X, PI, V, true>(a, T, D, Ls, s, iter, bins, npass, nterms,
-                                                           wr);
+                eval_fp64<ORDER, Q, false, G, X, PI, V, true, HE>(a, T, D, Ls, jc, s, iter, bins,
+                                                                  npass, nterms, wr);
             accumulate(w, bins);
-  #pragma unroll
+#pragma unroll
             for (int r = 0; r < kMaxReg; ++r) {
               const double d = wr[r] - shift;
               rs[2 * r] += d;
               rs[2 * r + 1] += d * d;
             }
           } else {
-            const double w =
-                eval_fp64<ORDER, Q, PP == 2, G, X, PI, V>(a, T, D, Ls, s, iter, bins, npass, nterms);
+            const double w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V, false, HE>(
+                a, T, D, Ls, jc, s, iter, bins, npass, nterms);
             accumulate(w, bins);
           }
         }
@@ -1062,7 +1087,8 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
           const uint64_t s = base + queue[lane];
           int bins[ND];
           const double w =
-              eval_fp64<ORDER, Q, false, G, X, PI, V>(a, T, D, Ls, s, iter, bins, npass, nterms);
+              eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE>(a, T, D, Ls, jc, s, iter, bins,
+                                                                 npass, nterms);
           accumulate(w, bins);
         }
         __builtin_amdgcn_wave_barrier();
@@ -1079,13 +1105,14 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
         if (s < N) {
           int bins[ND];
           const double w =
-              eval_fp32<ORDER, Q, G, X, V>(a, T, D, Ls, s, iter, bins, npass, nterms, fb);
+              eval_fp32<ORDER, Q, G, X, V, HE>(a, T, D, Ls, jc, s, iter, bins, npass, nterms, fb);
           if (!fb) accumulate(w, bins);
         }
         const uint64_t mask = __ballot(fb);
         if (fb) {
-          const int pos = qn + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+          const int pos =
+              qn + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
           queue[pos] = static_cast<uint32_t>(s - base);
           ++nfb;
         }
@@ -1200,10 +1227,10 @@ constexpr int min_waves() {
 }
 
 // One task per launch: block b processes work item item_begin + b.
-template <int ORDER, int Q, int P, bool X>
+template <int ORDER, int Q, int P, bool X, int HE>
 __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_single(KArgs a, int t) {
   extern __shared__ double smem[];
-  process_item<ORDER, Q, P, X>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
+  process_item<ORDER, Q, P, X, HE>(a, t, a.tasks[t].item_begin + blockIdx.x, smem);
 }
 
 // One launch over the work items of the tasks of one order: olist[k0, k1)
@@ -1211,7 +1238,7 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_sin
 // numbered contiguously from olist[k0].x, and block b takes item
 // olist[k0].x + b.  One launch per order keeps each launch's register
 // allocation that of its own order.
-template <int ORDER, int Q, int P, bool X>
+template <int ORDER, int Q, int P, bool X, int HE>
 __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_order(KArgs a, int k0, int k1) {
   extern __shared__ double smem[];
   const int2 *__restrict__ ol = a.olist;
@@ -1222,7 +1249,7 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_ord
     if (ol[mid].x <= item) lo = mid;
     else hi = mid - 1;
   }
-  process_item<ORDER, Q, P, X>(a, ol[lo].y, item, smem);
+  process_item<ORDER, Q, P, X, HE>(a, ol[lo].y, item, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1504,8 +1531,8 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
       double wr[kMaxReg];
       with_variant<ORDER, group_of<P>()>(D, [&](auto vt) {
         constexpr int V = decltype(vt)::value;
-        out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, PI, V, true>(a, T, D, Ls, first + i,
-                                                                         iter, bins, np, nt, wr);
+        out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, PI, V, true>(
+            a, T, D, Ls, jac_const<ORDER, V>(a, T, D), first + i, iter, bins, np, nt, wr);
       });
       if (out_reg)
         for (int r = 0; r < a.nreg; ++r) out_reg[i * a.nreg + r] = wr[r];
@@ -1653,12 +1680,19 @@ template <int Q, int P, bool X>
 static hipError_t single_qx(const KArgs &a, int t, int order, int nitems, int block,
                             hipStream_t st) {
   const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block, lds_tables<Q, P>());
+  const bool q4 = a.phys.half_exp == 2;  // quartic regulator: orders 1-2 have fixed-exponent kernels
   switch (order) {
-    case 1: hipLaunchKernelGGL((sample_single<1, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 2: hipLaunchKernelGGL((sample_single<2, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 3: hipLaunchKernelGGL((sample_single<3, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 4: hipLaunchKernelGGL((sample_single<4, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 5: hipLaunchKernelGGL((sample_single<5, Q, P, X>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 1:
+      if (q4) hipLaunchKernelGGL((sample_single<1, Q, P, X, 2>), dim3(nitems), dim3(block), lds, st, a, t);
+      else hipLaunchKernelGGL((sample_single<1, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t);
+      break;
+    case 2:
+      if (q4) hipLaunchKernelGGL((sample_single<2, Q, P, X, 2>), dim3(nitems), dim3(block), lds, st, a, t);
+      else hipLaunchKernelGGL((sample_single<2, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t);
+      break;
+    case 3: hipLaunchKernelGGL((sample_single<3, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 4: hipLaunchKernelGGL((sample_single<4, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 5: hipLaunchKernelGGL((sample_single<5, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1700,12 +1734,19 @@ template <int Q, int P, bool X>
 static hipError_t order_qpx(const KArgs &a, int order, int k0, int k1, int grid, int block,
                             hipStream_t st) {
   const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block, lds_tables<Q, P>());
+  const bool q4 = a.phys.half_exp == 2;  // see single_qx
   switch (order) {
-    case 1: hipLaunchKernelGGL((sample_order<1, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 2: hipLaunchKernelGGL((sample_order<2, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 3: hipLaunchKernelGGL((sample_order<3, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 4: hipLaunchKernelGGL((sample_order<4, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 5: hipLaunchKernelGGL((sample_order<5, Q, P, X>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 1:
+      if (q4) hipLaunchKernelGGL((sample_order<1, Q, P, X, 2>), dim3(grid), dim3(block), lds, st, a, k0, k1);
+      else hipLaunchKernelGGL((sample_order<1, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1);
+      break;
+    case 2:
+      if (q4) hipLaunchKernelGGL((sample_order<2, Q, P, X, 2>), dim3(grid), dim3(block), lds, st, a, k0, k1);
+      else hipLaunchKernelGGL((sample_order<2, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1);
+      break;
+    case 3: hipLaunchKernelGGL((sample_order<3, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 4: hipLaunchKernelGGL((sample_order<4, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 5: hipLaunchKernelGGL((sample_order<5, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
