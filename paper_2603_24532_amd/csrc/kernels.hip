@@ -239,8 +239,8 @@ __device__ __forceinline__ void with_variant(const DiagDev *__restrict__ D, Fn &
 }
 
 // (p^2)^(reg_exp / 2) for the regulator exponent: HE > 0 is reg_exp / 2 fixed
-// at compile time (the kernels of orders 1-2 for the quartic regulator, whose
-// vertices then share their regulator factors), HE = 0 takes it from the
+// at compile time (the quartic regulator's kernels: no selects or loop, and
+// vertices with equal momenta share their factors), HE = 0 takes it from the
 // launch (a uniform loop).  Both multiply the same factors in the same order.
 template <int HE, typename F>
 __device__ __forceinline__ F reg_pow(F p2, int half_exp) {
@@ -960,7 +960,7 @@ constexpr bool pair_inv() {
   return ORDER == 3 && prec_of<P>() == 1;
 }
 
-template <int ORDER, int Q, int P, bool X>
+template <int ORDER, int Q, int P, bool X, int HE>
 __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__restrict__ T,
                                               const DiagDev *__restrict__ D,
                                               const SampleLds &Ls, uint64_t s,
@@ -974,14 +974,14 @@ __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__r
     constexpr int V = decltype(vt)::value;
     const double jc = jac_const<ORDER, V>(a, T, D);
     if (PP != 1) {
-      w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V>(a, T, D, Ls, jc, s, iter, bins, npass, nterms);
+      w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V, false, HE>(a, T, D, Ls, jc, s, iter, bins, npass, nterms);
       return;
     }
     bool fb = false;
-    w = eval_fp32<ORDER, Q, G, X, V>(a, T, D, Ls, jc, s, iter, bins, npass, nterms, fb);
+    w = eval_fp32<ORDER, Q, G, X, V, HE>(a, T, D, Ls, jc, s, iter, bins, npass, nterms, fb);
     if (fb) {
       ++nfb;
-      w = eval_fp64<ORDER, Q, false, G, X, PI, V>(a, T, D, Ls, jc, s, iter, bins, npass, nterms);
+      w = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE>(a, T, D, Ls, jc, s, iter, bins, npass, nterms);
     }
   });
   return w;
@@ -1504,7 +1504,7 @@ __global__ __launch_bounds__(kFinishThreads) void finish_iteration(KArgs a, int 
 
 // Regularised modes: out_reg (if not null) receives the components,
 // out_reg[i * nreg + k] for component k + 1.
-template <int ORDER, int Q, int P, bool X>
+template <int ORDER, int Q, int P, bool X, int HE>
 __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t iter, uint64_t first,
                                                    uint64_t count, double *out, double *out_reg) {
   extern __shared__ double smem[];
@@ -1531,13 +1531,13 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
       double wr[kMaxReg];
       with_variant<ORDER, group_of<P>()>(D, [&](auto vt) {
         constexpr int V = decltype(vt)::value;
-        out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, PI, V, true>(
+        out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, PI, V, true, HE>(
             a, T, D, Ls, jac_const<ORDER, V>(a, T, D), first + i, iter, bins, np, nt, wr);
       });
       if (out_reg)
         for (int r = 0; r < a.nreg; ++r) out_reg[i * a.nreg + r] = wr[r];
     } else {
-      out[i] = eval_sample<ORDER, Q, P, X>(a, T, D, Ls, first + i, iter, bins, np, nt, nf);
+      out[i] = eval_sample<ORDER, Q, P, X, HE>(a, T, D, Ls, first + i, iter, bins, np, nt, nf);
     }
   }
 }
@@ -1676,26 +1676,28 @@ size_t sample_lds_bytes(int nd, int nb, int block, int ntab) {
          (block / 64) * 128 * sizeof(uint32_t);
 }
 
-template <int Q, int P, bool X>
-static hipError_t single_qx(const KArgs &a, int t, int order, int nitems, int block,
-                            hipStream_t st) {
+template <int Q, int P, bool X, int HE>
+static hipError_t single_qxh(const KArgs &a, int t, int order, int nitems, int block,
+                             hipStream_t st) {
   const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block, lds_tables<Q, P>());
-  const bool q4 = a.phys.half_exp == 2;  // quartic regulator: orders 1-2 have fixed-exponent kernels
   switch (order) {
-    case 1:
-      if (q4) hipLaunchKernelGGL((sample_single<1, Q, P, X, 2>), dim3(nitems), dim3(block), lds, st, a, t);
-      else hipLaunchKernelGGL((sample_single<1, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t);
-      break;
-    case 2:
-      if (q4) hipLaunchKernelGGL((sample_single<2, Q, P, X, 2>), dim3(nitems), dim3(block), lds, st, a, t);
-      else hipLaunchKernelGGL((sample_single<2, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t);
-      break;
-    case 3: hipLaunchKernelGGL((sample_single<3, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 4: hipLaunchKernelGGL((sample_single<4, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t); break;
-    case 5: hipLaunchKernelGGL((sample_single<5, Q, P, X, 0>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 1: hipLaunchKernelGGL((sample_single<1, Q, P, X, HE>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 2: hipLaunchKernelGGL((sample_single<2, Q, P, X, HE>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 3: hipLaunchKernelGGL((sample_single<3, Q, P, X, HE>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 4: hipLaunchKernelGGL((sample_single<4, Q, P, X, HE>), dim3(nitems), dim3(block), lds, st, a, t); break;
+    case 5: hipLaunchKernelGGL((sample_single<5, Q, P, X, HE>), dim3(nitems), dim3(block), lds, st, a, t); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// The quartic regulator (reg_exp 4) has kernels with its exponent fixed at
+// compile time; other exponents take the kernels that read it at run time.
+template <int Q, int P, bool X>
+static hipError_t single_qx(const KArgs &a, int t, int order, int nitems, int block,
+                            hipStream_t st) {
+  return a.phys.half_exp == 2 ? single_qxh<Q, P, X, 2>(a, t, order, nitems, block, st)
+                              : single_qxh<Q, P, X, 0>(a, t, order, nitems, block, st);
 }
 
 // The label-sum form is a kernel template parameter: each kernel holds the
@@ -1730,26 +1732,26 @@ hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int pre
   }
 }
 
-template <int Q, int P, bool X>
-static hipError_t order_qpx(const KArgs &a, int order, int k0, int k1, int grid, int block,
-                            hipStream_t st) {
+template <int Q, int P, bool X, int HE>
+static hipError_t order_qpxh(const KArgs &a, int order, int k0, int k1, int grid, int block,
+                             hipStream_t st) {
   const size_t lds = sample_lds_bytes(3 * (order + 1), a.phys.nb, block, lds_tables<Q, P>());
-  const bool q4 = a.phys.half_exp == 2;  // see single_qx
   switch (order) {
-    case 1:
-      if (q4) hipLaunchKernelGGL((sample_order<1, Q, P, X, 2>), dim3(grid), dim3(block), lds, st, a, k0, k1);
-      else hipLaunchKernelGGL((sample_order<1, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1);
-      break;
-    case 2:
-      if (q4) hipLaunchKernelGGL((sample_order<2, Q, P, X, 2>), dim3(grid), dim3(block), lds, st, a, k0, k1);
-      else hipLaunchKernelGGL((sample_order<2, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1);
-      break;
-    case 3: hipLaunchKernelGGL((sample_order<3, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 4: hipLaunchKernelGGL((sample_order<4, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
-    case 5: hipLaunchKernelGGL((sample_order<5, Q, P, X, 0>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 1: hipLaunchKernelGGL((sample_order<1, Q, P, X, HE>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 2: hipLaunchKernelGGL((sample_order<2, Q, P, X, HE>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 3: hipLaunchKernelGGL((sample_order<3, Q, P, X, HE>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 4: hipLaunchKernelGGL((sample_order<4, Q, P, X, HE>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
+    case 5: hipLaunchKernelGGL((sample_order<5, Q, P, X, HE>), dim3(grid), dim3(block), lds, st, a, k0, k1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int Q, int P, bool X>
+static hipError_t order_qpx(const KArgs &a, int order, int k0, int k1, int grid, int block,
+                            hipStream_t st) {
+  return a.phys.half_exp == 2 ? order_qpxh<Q, P, X, 2>(a, order, k0, k1, grid, block, st)
+                              : order_qpxh<Q, P, X, 0>(a, order, k0, k1, grid, block, st);
 }
 
 template <int Q, int P>
@@ -1791,22 +1793,32 @@ hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_it
   return hipGetLastError();
 }
 
-template <int Q, int P, bool X>
-static hipError_t dump_qx(const KArgs &a, int t, int order, uint32_t iter, uint64_t first,
-                          uint64_t count, double *out, double *out_reg, hipStream_t st) {
+template <int Q, int P, bool X, int HE>
+static hipError_t dump_qxh(const KArgs &a, int t, int order, uint32_t iter, uint64_t first,
+                           uint64_t count, double *out, double *out_reg, hipStream_t st) {
   const int block = 256;
   const dim3 grid(static_cast<unsigned>((count + block - 1) / block));
   const size_t lds = fixed_lds_bytes() + hf_lds_doubles(lds_tables<Q, P>()) * sizeof(double) +
                      2 * static_cast<size_t>(3 * (order + 1)) * a.phys.nb * sizeof(double);
   switch (order) {
-    case 1: hipLaunchKernelGGL((dump_samples<1, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
-    case 2: hipLaunchKernelGGL((dump_samples<2, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
-    case 3: hipLaunchKernelGGL((dump_samples<3, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
-    case 4: hipLaunchKernelGGL((dump_samples<4, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
-    case 5: hipLaunchKernelGGL((dump_samples<5, Q, P, X>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 1: hipLaunchKernelGGL((dump_samples<1, Q, P, X, HE>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 2: hipLaunchKernelGGL((dump_samples<2, Q, P, X, HE>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 3: hipLaunchKernelGGL((dump_samples<3, Q, P, X, HE>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 4: hipLaunchKernelGGL((dump_samples<4, Q, P, X, HE>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
+    case 5: hipLaunchKernelGGL((dump_samples<5, Q, P, X, HE>), grid, dim3(block), lds, st, a, t, iter, first, count, out, out_reg); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// The same exponent class as the sample kernels, so that dumped weights come
+// from the arithmetic the integration runs.
+template <int Q, int P, bool X>
+static hipError_t dump_qx(const KArgs &a, int t, int order, uint32_t iter, uint64_t first,
+                          uint64_t count, double *out, double *out_reg, hipStream_t st) {
+  return a.phys.half_exp == 2
+             ? dump_qxh<Q, P, X, 2>(a, t, order, iter, first, count, out, out_reg, st)
+             : dump_qxh<Q, P, X, 0>(a, t, order, iter, first, count, out, out_reg, st);
 }
 
 template <int Q, int P>
