@@ -82,7 +82,9 @@ enum { MBPT_SPECTRUM_FREE = 0, MBPT_SPECTRUM_HF = 1 };
  * <12|V(1 - P12)|34> (Sec. "Implementing chiral forces": regulator f_NN of the
  * nonlocal form, commuting with the antisymmetrizer).  Units: C0 [fm^2], Cy
  * dimensionless, mpi and Lambda [fm^-1], hbar2_m = hbar^2/m [MeV fm^2], hbarc
- * [MeV fm].  reg_exp must be an even integer in [2, 16]. */
+ * [MeV fm].  reg_exp must be an even integer in [2, 16]; reg_exp = 4 runs
+ * sample kernels with the exponent fixed at compile time (the fastest), other
+ * values run kernels that read it at launch (same arithmetic). */
 typedef struct mbpt_interaction {
   double C0, Cy, mpi, Lambda;
   int reg_exp;
