@@ -84,7 +84,7 @@ enum { MBPT_SPECTRUM_FREE = 0, MBPT_SPECTRUM_HF = 1 };
  * dimensionless, mpi and Lambda [fm^-1], hbar2_m = hbar^2/m [MeV fm^2], hbarc
  * [MeV fm].  reg_exp must be an even integer in [2, 16]; reg_exp = 4 runs
  * sample kernels with the exponent fixed at compile time (the fastest), other
- * values run kernels that read it at launch (same arithmetic). */
+ * values run kernels that read it at launch (the same operations). */
 typedef struct mbpt_interaction {
   double C0, Cy, mpi, Lambda;
   int reg_exp;
