@@ -219,23 +219,72 @@ int mbpt_diagram_label_poly(int order, int id, int matter, double *coef, int max
 int mbpt_group_members(int order, int p, int *ids, int cap, int *n);
 
 /* ---- task sets ------------------------------------------------------------ */
-/* Create a set of tasks (copied).  EINVAL on an unknown diagram, order outside
+/* A task set is the unit of batching: its tasks may mix orders, diagrams,
+ * diagram groups, densities and proton fractions (one matter per set), and
+ * mbpt_integrate runs all of them together, in BATCHED / GRAPH mode with one
+ * sample launch per order present per iteration and one iteration-end launch
+ * for all tasks.  It takes the place of a separate batch call over
+ * (diagram set, n, x) triples: give each triple a task of one set.
+ * Create a set of tasks (copied).  EINVAL on an unknown diagram, order outside
  * 1..5, density <= 0, proton fraction outside [0,1], or NEUTRON with x != 0. */
 int mbpt_create_task_set(mbpt_context *ctx, const mbpt_task_desc *tasks, int n_tasks,
                          mbpt_task_set **out);
-/* Convenience: the listed diagrams of one order (ids NULL = all) at density
- * 0.16 fm^-3, x = 0, task_key = position in the list. */
-int mbpt_create_diagram_set(mbpt_context *ctx, int order, const int *ids, int n_ids, int matter,
+/* A diagram given by its lines and vertices (Sec. "Automated approach": a
+ * diagram is read from its table of lines and vertices).  order: n = 1..5
+ * vertices at time levels 0..n-1, bottom first.  nlines: must be 2n (<= 10).
+ * Line l runs from level line_from[l] to level line_to[l]: a particle line if
+ * from < to, a hole line if from > to (first order: two hole self-lines
+ * 0 -> 0).  vertex[v] = {o1, o2, i1, i2}: the line ids of the antisymmetrised
+ * matrix element <o1 o2|V(1 - P12)|i1 i2> at vertex v (o1, o2 leave v; i1, i2
+ * enter v).  Dimensions 3(n + 1) <= 18.  Entries beyond nlines / order are
+ * ignored. */
+typedef struct mbpt_diagram_desc {
+  int order;
+  int nlines;
+  int line_from[10];
+  int line_to[10];
+  int vertex[5][4];
+} mbpt_diagram_desc;
+
+/* Create a set of one task per descriptor (density 0.16 fm^-3, x = 0,
+ * task_key = position; move them with mbpt_set_density / _asymmetry).  Each
+ * descriptor is validated -- order 1..5, nlines = 2 order, levels in range,
+ * no self-line above first order, two lines leaving and two entering every
+ * vertex, vertex slots naming four distinct lines that leave (o1, o2) or
+ * enter (i1, i2) it, all vertices connected -- else MBPT_EINVAL with the
+ * reason in mbpt_last_error.  A two-body energy diagram is fixed by its
+ * line-count matrix (relabelling lines, or exchanging a vertex's incoming
+ * pair, which flips the sign of the matrix element and of the closed-loop
+ * count together, leaves its value unchanged), so a valid descriptor runs the
+ * library's compiled form of the generator diagram with the same matrix: its
+ * label list (the nonzero spin(-isospin) assignments) is derived, not
+ * supplied, and its samples are those of that generator id. */
+int mbpt_create_diagram_set(mbpt_context *ctx, const mbpt_diagram_desc *descs, int n, int matter,
                             mbpt_task_set **out);
+/* Validate one descriptor and return the generator id of its diagram (the
+ * same checks; EINVAL without a message, as no context is involved). */
+int mbpt_diagram_desc_id(const mbpt_diagram_desc *desc, int *id);
+/* The generator's own descriptor of diagram `id` of an order (lines in the
+ * compiled order: particles, then holes). */
+int mbpt_diagram_desc_of(int order, int id, mbpt_diagram_desc *out);
+/* Convenience: the listed generator diagrams of one order (ids NULL = all) at
+ * density 0.16 fm^-3, x = 0, task_key = position in the list. */
+int mbpt_create_diagram_set_from_order(mbpt_context *ctx, int order, const int *ids, int n_ids,
+                                       int matter, mbpt_task_set **out);
 void mbpt_task_set_destroy(mbpt_task_set *set);
 int mbpt_task_count(const mbpt_task_set *set, int *n);
-/* Move every task of the set to a new density [fm^-3] or proton fraction; the
- * grids are kept (warm start). */
+/* Move every task of the set to a new density [fm^-3] or proton fraction.
+ * The VEGAS grids and the Philox iteration words are kept (warm start: the
+ * next iteration starts from the adapted grid with fresh random numbers);
+ * the running sums, counters and iteration logs restart, so later results
+ * estimate the new EOS point from its own iterations only.  EINVAL on
+ * density <= 0, x outside [0, 1], or x != 0 in a NEUTRON set. */
 int mbpt_set_density(mbpt_task_set *set, double density);
 int mbpt_set_asymmetry(mbpt_task_set *set, double proton_fraction);
 int mbpt_set_launch_mode(mbpt_task_set *set, int mode);
-/* Work decomposition: threads per block (64..1024, multiple of 64) and samples
- * per thread per work item (1..256).  Defaults 256 and 16. */
+/* Work decomposition: threads per block (64..256, multiple of 64; the sample
+ * kernels are built for at most 256) and samples per thread per work item
+ * (1..256).  Defaults 256 and 16.  EINVAL outside these ranges. */
 int mbpt_set_blocking(mbpt_task_set *set, int threads_per_block, int samples_per_thread);
 
 /* Device workspace bytes needed for up to max_samples_per_iter samples per
@@ -325,6 +374,19 @@ int mbpt_autotune(mbpt_task_set *set, uint64_t samples_per_iter, int *threads_pe
  * add/mul = 1, each exp/sqrt/sincos/division = 1). */
 int mbpt_kernel_stats(mbpt_context *ctx, uint64_t *launches, double *kernel_ms,
                       uint64_t *evals, double *flops);
+/* The algorithmic FLOP model behind those figures for one diagram (host only,
+ * no context): *pre FLOPs every sample costs (VEGAS map, loop and line
+ * momenta, Pauli tests, accumulation), *post those of a sample past the Pauli
+ * test (denominators, matrix elements, monomial tables, weight), *per_unit
+ * those of one label unit evaluated (an isospin configuration of the
+ * polynomial form, label_mode 0, or one compressed assignment term, label_mode
+ * 1), *units the diagram's label units.  FMA = 2, add/mul = 1, each
+ * exp/sqrt/sin/cos/division = 1.  mbpt_kernel_stats multiplies them with the
+ * device's per-task counts of samples, passing samples and units evaluated.
+ * EINVAL on an unknown diagram or a bad matter, label_mode, reg_exp (even,
+ * 2..16) or spectrum. */
+int mbpt_diagram_flops(int order, int id, int matter, int label_mode, int reg_exp, int spectrum,
+                       double *pre, double *post, double *per_unit, double *units);
 /* Algorithmic FLOPs and transcendental count per evaluation of a task. */
 int mbpt_task_flops(const mbpt_task_set *set, int task, double *flops, double *transcendentals);
 

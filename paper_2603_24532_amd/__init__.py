@@ -26,14 +26,15 @@ EXPORTED = [
     "mbpt_set_precision", "mbpt_num_diagrams", "mbpt_diagram_matrix", "mbpt_diagram_label_stats",
     "mbpt_diagram_label_poly", "mbpt_set_spectrum", "mbpt_hf_nodes",
     "mbpt_server_set_warm_start", "mbpt_server_warm_starts", "mbpt_group_members",
-    "mbpt_create_task_set", "mbpt_create_diagram_set", "mbpt_task_set_destroy", "mbpt_task_count",
+    "mbpt_create_task_set", "mbpt_create_diagram_set", "mbpt_create_diagram_set_from_order",
+    "mbpt_diagram_desc_id", "mbpt_diagram_desc_of", "mbpt_task_set_destroy", "mbpt_task_count",
     "mbpt_set_density", "mbpt_set_asymmetry", "mbpt_set_launch_mode", "mbpt_set_blocking",
     "mbpt_workspace_query", "mbpt_bind_workspace", "mbpt_reset", "mbpt_integrate",
     "mbpt_iteration_log", "mbpt_dump_samples", "mbpt_get_grid", "mbpt_set_grid",
     "mbpt_kernel_stats", "mbpt_task_flops", "mbpt_autotune", "mbpt_server_workspace_query", "mbpt_server_create",
     "mbpt_server_destroy", "mbpt_server_submit", "mbpt_server_step", "mbpt_server_poll",
     "mbpt_set_regularization", "mbpt_dump_samples_reg", "mbpt_regularized_log",
-    "mbpt_regularized",
+    "mbpt_regularized", "mbpt_diagram_flops",
 ]
 
 
@@ -56,6 +57,12 @@ class mbpt_task_desc(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("diagram_id", ctypes.c_int), ("matter", ctypes.c_int),
                 ("density", ctypes.c_double), ("proton_fraction", ctypes.c_double),
                 ("task_key", ctypes.c_uint32), ("group", ctypes.c_int)]
+
+
+class mbpt_diagram_desc(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("nlines", ctypes.c_int),
+                ("line_from", ctypes.c_int * 10), ("line_to", ctypes.c_int * 10),
+                ("vertex", (ctypes.c_int * 4) * 5)]
 
 
 class mbpt_result(ctypes.Structure):
@@ -115,8 +122,12 @@ def lib():
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int, _IP],
         "mbpt_create_task_set": [_P, ctypes.POINTER(mbpt_task_desc), ctypes.c_int,
                                  ctypes.POINTER(_P)],
-        "mbpt_create_diagram_set": [_P, ctypes.c_int, _IP, ctypes.c_int, ctypes.c_int,
-                                    ctypes.POINTER(_P)],
+        "mbpt_create_diagram_set": [_P, ctypes.POINTER(mbpt_diagram_desc), ctypes.c_int,
+                                    ctypes.c_int, ctypes.POINTER(_P)],
+        "mbpt_create_diagram_set_from_order": [_P, ctypes.c_int, _IP, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(_P)],
+        "mbpt_diagram_desc_id": [ctypes.POINTER(mbpt_diagram_desc), _IP],
+        "mbpt_diagram_desc_of": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(mbpt_diagram_desc)],
         "mbpt_task_set_destroy": [_P],
         "mbpt_task_count": [_P, _IP],
         "mbpt_set_density": [_P, ctypes.c_double],
@@ -137,6 +148,8 @@ def lib():
         "mbpt_kernel_stats": [_P, ctypes.POINTER(ctypes.c_uint64), _DP,
                               ctypes.POINTER(ctypes.c_uint64), _DP],
         "mbpt_task_flops": [_P, ctypes.c_int, _DP, _DP],
+        "mbpt_diagram_flops": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_int, _DP, _DP, _DP, _DP],
         "mbpt_autotune": [_P, ctypes.c_uint64, _IP, _IP, _DP],
         "mbpt_server_workspace_query": [_P, ctypes.c_int, ctypes.c_uint64,
                                         ctypes.POINTER(ctypes.c_size_t)],
@@ -270,13 +283,51 @@ def mbpt_create_task_set(ctx, tasks):
     return h.value
 
 
-def mbpt_create_diagram_set(ctx, order, ids=None, matter=MBPT_NEUTRON):
+def _desc(d):
+    """dict(order, lines=[(from, to), ...], vertex=[[o1, o2, i1, i2], ...]) -> struct"""
+    out = mbpt_diagram_desc()
+    out.order = d["order"]
+    out.nlines = len(d["lines"])
+    for l, (a, b) in enumerate(d["lines"]):
+        out.line_from[l] = a
+        out.line_to[l] = b
+    for v, slots in enumerate(d["vertex"]):
+        for k, l in enumerate(slots):
+            out.vertex[v][k] = l
+    return out
+
+
+def mbpt_create_diagram_set(ctx, descs, matter=MBPT_NEUTRON):
+    """descs: list of dict(order, lines=[(from, to), ...], vertex=[[o1, o2, i1, i2], ...])."""
+    arr = (mbpt_diagram_desc * len(descs))(*[_desc(d) for d in descs])
+    h = _P()
+    _check(lib().mbpt_create_diagram_set(ctx, arr, len(descs), matter, ctypes.byref(h)), ctx)
+    _set_ctx[h.value] = ctx
+    return h.value
+
+
+def mbpt_diagram_desc_id(desc):
+    i = ctypes.c_int()
+    _check(lib().mbpt_diagram_desc_id(ctypes.byref(_desc(desc)), ctypes.byref(i)))
+    return i.value
+
+
+def mbpt_diagram_desc_of(order, did):
+    d = mbpt_diagram_desc()
+    _check(lib().mbpt_diagram_desc_of(order, did, ctypes.byref(d)))
+    return dict(order=d.order,
+                lines=[(d.line_from[l], d.line_to[l]) for l in range(d.nlines)],
+                vertex=[[d.vertex[v][k] for k in range(4)] for v in range(d.order)])
+
+
+def mbpt_create_diagram_set_from_order(ctx, order, ids=None, matter=MBPT_NEUTRON):
     h = _P()
     if ids is None:
-        rc = lib().mbpt_create_diagram_set(ctx, order, None, 0, matter, ctypes.byref(h))
+        rc = lib().mbpt_create_diagram_set_from_order(ctx, order, None, 0, matter, ctypes.byref(h))
     else:
         arr = (ctypes.c_int * len(ids))(*ids)
-        rc = lib().mbpt_create_diagram_set(ctx, order, arr, len(ids), matter, ctypes.byref(h))
+        rc = lib().mbpt_create_diagram_set_from_order(ctx, order, arr, len(ids), matter,
+                                                      ctypes.byref(h))
     _check(rc, ctx)
     _set_ctx[h.value] = ctx
     return h.value
@@ -413,6 +464,14 @@ def mbpt_task_flops(s, task):
     f, t = ctypes.c_double(), ctypes.c_double()
     _check(lib().mbpt_task_flops(s, task, ctypes.byref(f), ctypes.byref(t)), _ctx_of_set(s))
     return f.value, t.value
+
+
+def mbpt_diagram_flops(order, did, matter, label_mode=0, reg_exp=4, spectrum=0):
+    """dict(pre, post, per_unit, units) of the algorithmic FLOP model."""
+    v = [ctypes.c_double() for _ in range(4)]
+    _check(lib().mbpt_diagram_flops(order, did, matter, label_mode, reg_exp, spectrum,
+                                    *[ctypes.byref(x) for x in v]))
+    return dict(zip(("pre", "post", "per_unit", "units"), (x.value for x in v)))
 
 
 def mbpt_autotune(s, samples_per_iter):

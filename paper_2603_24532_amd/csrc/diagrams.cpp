@@ -5,6 +5,7 @@
 #include <array>
 #include <map>
 #include <mutex>
+#include <string>
 
 namespace mbpt {
 namespace {
@@ -277,6 +278,71 @@ const Diagram *get_diagram(int order, int id) {
   const auto &ds = diagrams_of(order);
   if (id < 0 || id >= static_cast<int>(ds.size())) return nullptr;
   return &ds[id];
+}
+
+int diagram_from_lines(int order, int nlines, const int *from, const int *to,
+                       const int (*vertex)[4], std::string &err) {
+  if (order < 1 || order > kMaxOrder) {
+    err = "order must be 1..5";
+    return -1;
+  }
+  if (nlines != 2 * order) {
+    err = "an order-n two-body energy diagram has 2n lines";
+    return -1;
+  }
+  Mat m{};
+  int nout[kMaxOrder] = {}, nin[kMaxOrder] = {};
+  for (int l = 0; l < nlines; ++l) {
+    const int u = from[l], v = to[l];
+    if (u < 0 || u >= order || v < 0 || v >= order) {
+      err = "line " + std::to_string(l) + ": level outside 0..order-1";
+      return -1;
+    }
+    if (u == v && order > 1) {
+      err = "line " + std::to_string(l) + ": self-line above first order";
+      return -1;
+    }
+    ++m[u * kMaxOrder + v];
+    ++nout[u];
+    ++nin[v];
+  }
+  for (int v = 0; v < order; ++v) {
+    if (nout[v] != 2 || nin[v] != 2) {
+      err = "vertex " + std::to_string(v) + ": needs two lines leaving and two entering";
+      return -1;
+    }
+    // outgoing slots name two distinct lines, incoming slots two distinct
+    // lines (at first order the two self-lines fill both pairs)
+    bool used[2][kMaxLines] = {};
+    for (int s = 0; s < 4; ++s) {
+      const int l = vertex[v][s];
+      if (l < 0 || l >= nlines || used[s / 2][l]) {
+        err = "vertex " + std::to_string(v) + ": o1, o2 and i1, i2 must name distinct lines";
+        return -1;
+      }
+      used[s / 2][l] = true;
+      // slots 0, 1 (o1, o2) leave the vertex, slots 2, 3 (i1, i2) enter it
+      const bool ok = s < 2 ? from[l] == v : to[l] == v;
+      if (!ok) {
+        err = "vertex " + std::to_string(v) + ": slot " + std::to_string(s) +
+              " names a line that does not " + (s < 2 ? "leave" : "enter") + " it";
+        return -1;
+      }
+    }
+  }
+  if (order > 1 && !is_connected(order, m)) {
+    err = "the lines do not connect all vertices (not a linked energy diagram)";
+    return -1;
+  }
+  const auto &ds = diagrams_of(order);
+  for (const auto &d : ds) {
+    bool same = true;
+    for (int u = 0; u < order && same; ++u)
+      for (int v = 0; v < order && same; ++v) same = d.M[u][v] == m[u * kMaxOrder + v];
+    if (same) return d.id;
+  }
+  err = "no generator diagram has these lines";  // unreachable for a valid diagram
+  return -1;
 }
 
 int particle_loops(const Diagram &d) {

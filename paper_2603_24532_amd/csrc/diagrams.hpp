@@ -9,6 +9,7 @@
 // multiplicity) terms.
 #pragma once
 #include <cstdint>
+#include <string>
 #include <vector>
 
 namespace mbpt {
@@ -47,6 +48,19 @@ struct LabelList {
   int n_isospin = 0;   // distinct isospin configurations among them
   std::vector<LabelTerm> terms;  // sorted by tau_mask, then codes
 };
+
+// Validates a diagram given by its lines and vertices and returns the
+// generator id of the same Hugenholtz diagram, or -1 with `err` set.  Line l
+// runs from time level from[l] to level to[l] (particle if from < to, hole if
+// from > to; at first order two hole self-lines 0 -> 0); vertex[v] lists the
+// line ids of <o1 o2|V|i1 i2> at vertex v (o1, o2 leave it, i1, i2 enter it).
+// A two-body energy diagram is fixed by its line-count matrix M[u][v]:
+// relabelling its lines, or exchanging a vertex's two incoming lines (which
+// flips the antisymmetrised matrix element and the closed-loop count
+// together), leaves its value unchanged, so every valid description of a
+// matrix maps to the generator's compiled form of that matrix.
+int diagram_from_lines(int order, int nlines, const int *from, const int *to,
+                       const int (*vertex)[4], std::string &err);
 
 // Loop momenta carried by particle lines (the cycle rank of the particle-line
 // subgraph, since the spanning forest takes particle lines first).  Diagrams

@@ -23,11 +23,45 @@ hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_it
 hipError_t launch_dump(const KArgs &a, int task, int order, int q, int prec, bool group,
                        uint32_t iter, uint64_t first, uint64_t count, double *out, double *out_reg,
                        hipStream_t st);
-hipError_t launch_init(const KArgs &a, int first, int ntasks, hipStream_t st);
+// Zero histograms and running state of tasks [first, first + ntasks); grids
+// to uniform and the Philox iteration word to 0 unless keep_grid.
+hipError_t launch_init(const KArgs &a, int first, int ntasks, hipStream_t st,
+                       bool keep_grid = false);
 // HF spline tables of tasks [first, first + ntasks): ntab isospin tables each,
 // partners summed over npartner isospins; gl = Gauss-Legendre (x, w) on the
 // device.
 hipError_t launch_hf(const KArgs &a, const double *gl, int first, int ntasks, int ntab,
                      int npartner, hipStream_t st);
+
+// Per-(order, q) launchers, defined in kernels_inst.hip (one object per pair).
+template <int ORDER, int Q>
+hipError_t launch_single_oq(const KArgs &a, int t, int prec, bool group, int nitems, int block,
+                            hipStream_t st);
+template <int ORDER, int Q>
+hipError_t launch_order_oq(const KArgs &a, int prec, bool group, int k0, int k1, int grid,
+                           int block, hipStream_t st);
+template <int ORDER, int Q>
+hipError_t launch_dump_oq(const KArgs &a, int t, int prec, bool group, uint32_t iter,
+                          uint64_t first, uint64_t count, double *out, double *out_reg,
+                          hipStream_t st);
+#define MBPT_DECLARE_OQ(O, Q)                                                                   \
+  template <>                                                                                   \
+  hipError_t launch_single_oq<O, Q>(const KArgs &, int, int, bool, int, int, hipStream_t);      \
+  template <>                                                                                   \
+  hipError_t launch_order_oq<O, Q>(const KArgs &, int, bool, int, int, int, int, hipStream_t);  \
+  template <>                                                                                   \
+  hipError_t launch_dump_oq<O, Q>(const KArgs &, int, int, bool, uint32_t, uint64_t, uint64_t,  \
+                                  double *, double *, hipStream_t);
+MBPT_DECLARE_OQ(1, 2)
+MBPT_DECLARE_OQ(1, 4)
+MBPT_DECLARE_OQ(2, 2)
+MBPT_DECLARE_OQ(2, 4)
+MBPT_DECLARE_OQ(3, 2)
+MBPT_DECLARE_OQ(3, 4)
+MBPT_DECLARE_OQ(4, 2)
+MBPT_DECLARE_OQ(4, 4)
+MBPT_DECLARE_OQ(5, 2)
+MBPT_DECLARE_OQ(5, 4)
+#undef MBPT_DECLARE_OQ
 
 }  // namespace mbpt

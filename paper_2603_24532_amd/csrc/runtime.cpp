@@ -827,8 +827,8 @@ extern "C" int mbpt_create_task_set(mbpt_context *ctx, const mbpt_task_desc *tas
   return MBPT_OK;
 }
 
-extern "C" int mbpt_create_diagram_set(mbpt_context *ctx, int order, const int *ids, int n_ids,
-                                       int matter, mbpt_task_set **out) {
+extern "C" int mbpt_create_diagram_set_from_order(mbpt_context *ctx, int order, const int *ids,
+                                                  int n_ids, int matter, mbpt_task_set **out) {
   if (!ctx || !out) return MBPT_EINVAL;
   const int nd = num_diagrams(order);
   if (nd < 0) return MBPT_EINVAL;
@@ -848,6 +848,59 @@ extern "C" int mbpt_create_diagram_set(mbpt_context *ctx, int order, const int *
   return mbpt_create_task_set(ctx, ts.data(), static_cast<int>(ts.size()), out);
 }
 
+extern "C" int mbpt_diagram_desc_id(const mbpt_diagram_desc *d, int *id) {
+  if (!d || !id) return MBPT_EINVAL;
+  std::string err;
+  const int r = diagram_from_lines(d->order, d->nlines, d->line_from, d->line_to, d->vertex, err);
+  if (r < 0) return MBPT_EINVAL;
+  *id = r;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_diagram_desc_of(int order, int id, mbpt_diagram_desc *out) {
+  const Diagram *d = get_diagram(order, id);
+  if (!d || !out) return MBPT_EINVAL;
+  *out = mbpt_diagram_desc{};
+  out->order = d->order;
+  out->nlines = d->nlines;
+  for (int l = 0; l < d->nlines; ++l) {
+    out->line_from[l] = d->tail[l];
+    out->line_to[l] = d->head[l];
+  }
+  for (int v = 0; v < d->order; ++v) {
+    out->vertex[v][0] = d->vout[v][0];
+    out->vertex[v][1] = d->vout[v][1];
+    out->vertex[v][2] = d->vin[v][0];
+    out->vertex[v][3] = d->vin[v][1];
+  }
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_create_diagram_set(mbpt_context *ctx, const mbpt_diagram_desc *descs, int n,
+                                       int matter, mbpt_task_set **out) {
+  if (!ctx || !out || !descs || n < 1) return MBPT_EINVAL;
+  *out = nullptr;
+  std::vector<mbpt_task_desc> ts;
+  for (int i = 0; i < n; ++i) {
+    std::string err;
+    const mbpt_diagram_desc &d = descs[i];
+    const int id = diagram_from_lines(d.order, d.nlines, d.line_from, d.line_to, d.vertex, err);
+    if (id < 0) {
+      set_err(ctx, "create_diagram_set: descriptor " + std::to_string(i) + ": " + err);
+      return MBPT_EINVAL;
+    }
+    mbpt_task_desc t{};
+    t.order = d.order;
+    t.diagram_id = id;
+    t.matter = matter;
+    t.density = 0.16;
+    t.proton_fraction = 0.0;
+    t.task_key = static_cast<uint32_t>(i);
+    ts.push_back(t);
+  }
+  return mbpt_create_task_set(ctx, ts.data(), n, out);
+}
+
 extern "C" void mbpt_task_set_destroy(mbpt_task_set *set) {
   if (!set) return;
   set->drop_graph();
@@ -860,16 +913,31 @@ extern "C" int mbpt_task_count(const mbpt_task_set *set, int *n) {
   return MBPT_OK;
 }
 
+namespace mbpt {
+// A task set moved to another EOS point: new medium parameters, running sums,
+// counters and iteration logs restarted (the old point's iterations estimate
+// another integral), grids and Philox iteration words kept (warm start).
+static int move_eos_point(mbpt_task_set *set) {
+  set->drop_graph();
+  set->hf_dirty = true;
+  if (!set->ws) return MBPT_OK;
+  fill_task_params(set);
+  int rc = upload_params(set);
+  if (rc) return rc;
+  mbpt_context *ctx = set->ctx;
+  KArgs a = kargs_of(set);
+  HIPCHK(ctx, launch_init(a, 0, static_cast<int>(set->tasks.size()), ctx->stream, true));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  set->last_state.clear();
+  set->run_reg_n = -1;
+  return MBPT_OK;
+}
+}  // namespace mbpt
+
 extern "C" int mbpt_set_density(mbpt_task_set *set, double density) {
   if (!set || !(density > 0.0)) return MBPT_EINVAL;
   for (auto &t : set->tasks) t.density = density;
-  set->drop_graph();
-  set->hf_dirty = true;
-  if (set->ws) {
-    fill_task_params(set);
-    return upload_params(set);
-  }
-  return MBPT_OK;
+  return move_eos_point(set);
 }
 
 extern "C" int mbpt_set_asymmetry(mbpt_task_set *set, double x) {
@@ -879,13 +947,7 @@ extern "C" int mbpt_set_asymmetry(mbpt_task_set *set, double x) {
     return MBPT_EINVAL;
   }
   for (auto &t : set->tasks) t.proton_fraction = x;
-  set->drop_graph();
-  set->hf_dirty = true;
-  if (set->ws) {
-    fill_task_params(set);
-    return upload_params(set);
-  }
-  return MBPT_OK;
+  return move_eos_point(set);
 }
 
 extern "C" int mbpt_set_launch_mode(mbpt_task_set *set, int mode) {
@@ -1402,6 +1464,24 @@ extern "C" int mbpt_kernel_stats(mbpt_context *ctx, uint64_t *launches, double *
   return MBPT_OK;
 }
 
+extern "C" int mbpt_diagram_flops(int order, int id, int matter, int label_mode, int reg_exp,
+                                  int spectrum, double *pre, double *post, double *per_unit,
+                                  double *units) {
+  const Diagram *d = get_diagram(order, id);
+  if (!d || (matter != MBPT_NEUTRON && matter != MBPT_NUCLEAR) || (label_mode & ~1) ||
+      reg_exp < 2 || reg_exp > 16 || (reg_exp & 1) || (spectrum & ~1))
+    return MBPT_EINVAL;
+  const int q = matter == MBPT_NUCLEAR ? 4 : 2;
+  FlopModel f;
+  count_flops(*d, q, reg_exp / 2, label_mode, spectrum, f);
+  const LabelTables lt = label_tables(*d, q);
+  if (pre) *pre = f.pre;
+  if (post) *post = f.post;
+  if (per_unit) *per_unit = f.per_term;
+  if (units) *units = static_cast<double>(label_mode ? lt.terms.size() : lt.groups.size());
+  return MBPT_OK;
+}
+
 extern "C" int mbpt_task_flops(const mbpt_task_set *set, int task, double *flops,
                                double *transcendentals) {
   if (!set || task < 0 || task >= static_cast<int>(set->tasks.size())) return MBPT_EINVAL;
@@ -1443,14 +1523,23 @@ extern "C" int mbpt_autotune(mbpt_task_set *set, uint64_t samples_per_iter, int 
   const int old_block = set->block, old_spt = set->spt;
   int best_b = old_block, best_s = old_spt;
   double best_ms = -1.0;
+  // the workspace holds items for the bind-time shape: only shapes with
+  // work items at least that large fit
+  const size_t bound_chunk = set->max_items / std::max<size_t>(1, set->tasks.size());
+  auto fits = [&](int b, int sp) {
+    set->block = b;
+    set->spt = sp;
+    const bool ok = items_for(set, samples_per_iter) <= bound_chunk;
+    set->block = old_block;
+    set->spt = old_spt;
+    return ok;
+  };
   auto it = tune_cache().find(key);
-  if (it != tune_cache().end()) {
+  if (it != tune_cache().end() && fits(it->second.first, it->second.second)) {
+    // a shape tuned on another workspace applies only if this one holds it
     best_b = it->second.first;
     best_s = it->second.second;
   } else {
-    // the workspace holds items for the bind-time shape: only shapes with
-    // work items at least that large fit
-    const size_t bound_chunk = set->max_items / std::max<size_t>(1, set->tasks.size());
     const int blocks[] = {64, 128, 256};
     const int spts[] = {4, 8, 16, 32};
     bool warmed = false;

@@ -233,3 +233,112 @@ def test_group_members_match_oracle(M, golden):
         lib_groups = {p: m for p, m in lib_groups.items() if m}
         assert len(lib_groups) == n_grp
         assert lib_groups == O.groups(order)
+
+
+# ---------------------------------------------------------------------------
+# Descriptor input (a diagram given by its lines and vertices)
+
+def _hand_order2():
+    """The second-order diagram written by hand: two particle lines 0 -> 1
+    and two hole lines 1 -> 0, listed holes first, with vertex 1's incoming
+    pair exchanged relative to vertex 0's outgoing pair."""
+    return dict(order=2, lines=[(1, 0), (0, 1), (1, 0), (0, 1)],
+                vertex=[[1, 3, 0, 2], [2, 0, 3, 1]])
+
+
+def test_descriptor_round_trip_every_diagram(M):
+    for order in range(1, 6):
+        for did in range(M.mbpt_num_diagrams(order)):
+            d = M.mbpt_diagram_desc_of(order, did)
+            assert M.mbpt_diagram_desc_id(d) == did
+
+
+def test_descriptor_relabelled_lines_map_to_the_same_diagram(M):
+    rng = np.random.default_rng(7)
+    for order in (3, 4):
+        for did in rng.choice(M.mbpt_num_diagrams(order), size=min(8, M.mbpt_num_diagrams(order)),
+                              replace=False):
+            d = M.mbpt_diagram_desc_of(order, int(did))
+            perm = rng.permutation(len(d["lines"]))       # new id of old line l = perm[l]
+            lines = [None] * len(d["lines"])
+            for l, ft in enumerate(d["lines"]):
+                lines[perm[l]] = ft
+            vertex = []
+            for slots in d["vertex"]:
+                o1, o2, i1, i2 = (int(perm[l]) for l in slots)
+                vertex.append([o2, o1, i1, i2] if rng.random() < 0.5 else [o1, o2, i2, i1])
+            assert M.mbpt_diagram_desc_id(dict(order=order, lines=lines, vertex=vertex)) == did
+
+
+def test_hand_built_second_order_descriptor(M):
+    assert M.mbpt_diagram_desc_id(_hand_order2()) == 0
+    od = O.diagram_dict(2, 0)
+    assert od["M"] == [[0, 2], [2, 0]]
+
+
+@pytest.mark.parametrize("bad", [
+    dict(order=2, lines=[(1, 0), (0, 1), (1, 0)], vertex=[[1, 3, 0, 2], [2, 0, 3, 1]]),   # 3 lines
+    dict(order=2, lines=[(1, 0), (0, 2), (1, 0), (0, 1)], vertex=[[1, 3, 0, 2], [2, 0, 3, 1]]),
+    dict(order=2, lines=[(1, 1), (0, 1), (1, 0), (0, 0)], vertex=[[1, 3, 0, 2], [2, 0, 3, 1]]),
+    dict(order=2, lines=[(1, 0), (0, 1), (1, 0), (0, 1)], vertex=[[1, 1, 0, 2], [2, 0, 3, 1]]),
+    dict(order=2, lines=[(1, 0), (0, 1), (1, 0), (0, 1)], vertex=[[0, 3, 1, 2], [2, 0, 3, 1]]),
+    dict(order=0, lines=[], vertex=[]),
+    dict(order=6, lines=[(0, 1)] * 10, vertex=[[0, 0, 0, 0]] * 5),
+    # two second-order pieces stacked: every vertex is fine, the whole is unlinked
+    dict(order=4, lines=[(0, 1), (0, 1), (1, 0), (1, 0), (2, 3), (2, 3), (3, 2), (3, 2)],
+         vertex=[[0, 1, 2, 3], [2, 3, 0, 1], [4, 5, 6, 7], [6, 7, 4, 5]]),
+], ids=["nlines", "level", "selfline", "repeat", "direction", "order0", "order6", "unlinked"])
+def test_descriptor_validation_rejects(M, bad):
+    with pytest.raises(M.MbptError) as e:
+        M.mbpt_diagram_desc_id(bad)
+    assert e.value.code == M.MBPT_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# FLOP model behind the roofline numbers, pinned by hand counts
+
+def test_flop_model_second_order_neutron_by_hand(M):
+    f = M.mbpt_diagram_flops(2, 0, M.MBPT_NEUTRON)
+    # every sample: 9 dimensions x 6 (bin fraction 2, x = e + r w 2, Jacobian
+    # 2) = 54; 3 loops x 13 (radius, cos, sin theta, components, Jacobian) =
+    # 39 plus 3 x 3 transcendentals (sqrt, sin, cos) = 9; the one tree line
+    # k_3 = k_1 + k_2 - k_0 costs 3 x 2 = 6 adds; 4 lines x (k^2 5, eps 1,
+    # Fermi test 1) = 28; accumulation 4 + 1 + 9 histogram adds = 14
+    assert f["pre"] == 54 + 39 + 9 + 6 + 28 + 14
+    # past the Pauli test: the cut's 4 energies 3 adds; 2 vertices x (p, p'
+    # 6 + 6, p^2 p'^2 p.p' 15, quartic powers 2, exponent 2, q^2 +- 6, C0 + 2,
+    # regulator products 2, V_d - V_e 1 = 42) = 84; weight 3; monomial tables
+    # of the 1 + 1 vertex halves 2 + 2 - 2 = 2; transcendentals 2 x (exp and
+    # two divisions) + 1 division = 7
+    assert f["post"] == 3 + 84 + 3 + 2 + 7
+    # one isospin configuration in neutron matter, 2 (2^2 + 2^1) FLOPs
+    assert f["units"] == 1 and f["per_unit"] == 12
+    # explicit form: the 6 nonzero spin assignments compress to their
+    # distinct vertex-code patterns, n + 1 = 3 FLOPs each
+    fx = M.mbpt_diagram_flops(2, 0, M.MBPT_NEUTRON, label_mode=1)
+    assert fx["per_unit"] == 3 and fx["pre"] == f["pre"]
+    assert fx["post"] == f["post"] - 2          # no monomial tables
+
+
+def test_flop_model_first_order_and_exponent(M):
+    f = M.mbpt_diagram_flops(1, 0, M.MBPT_NEUTRON)
+    # 6 dimensions x 6 + 2 loops x 13 + 2 x 3 transcendentals, no tree line,
+    # 2 lines x 7, accumulation 4 + 1 + 6
+    assert f["pre"] == 36 + 26 + 6 + 0 + 14 + 11
+    # no cut; one vertex 42; weight 3; monomial tables 1 + 2 - 2 = 1;
+    # transcendentals: exp and two divisions, no denominator division
+    assert f["post"] == 42 + 3 + 1 + 3
+    # exponent 8: two more multiplies per power, two powers per vertex
+    f8 = M.mbpt_diagram_flops(1, 0, M.MBPT_NEUTRON, reg_exp=8)
+    assert f8["post"] - f["post"] == 2 * (4 - 2)
+    # nuclear matter: two Fermi tests per line
+    fn = M.mbpt_diagram_flops(1, 0, M.MBPT_NUCLEAR)
+    assert fn["pre"] - f["pre"] == 2
+
+
+def test_flop_model_units_match_label_statistics(M):
+    for order, did in ((2, 0), (3, 1), (4, 17), (5, 400)):
+        for matter in (M.MBPT_NEUTRON, M.MBPT_NUCLEAR):
+            _, n_iso, n_terms = M.mbpt_diagram_label_stats(order, did, matter)
+            assert M.mbpt_diagram_flops(order, did, matter)["units"] == n_iso
+            assert M.mbpt_diagram_flops(order, did, matter, label_mode=1)["units"] == n_terms
