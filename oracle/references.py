@@ -19,6 +19,12 @@ textbook results:
   vacuum second-Born term added back (medium-subtracted second order); its
   ratio to (3/5) E_F (kF a)^2 is the Huang-Yang/Lee-Yang coefficient
   4 (11 - 2 ln 2) / (21 pi^2).
+* ``hf_self_energy``: the HF self-energy of eq:spe as a 1-D integral over the
+  momentum transfer (solid angle of the partner's Fermi sphere in closed form).
+* ``second_order``: Eq. (2) in neutron or asymmetric nuclear matter with the
+  free or the HF spectrum (eq:Dijkabc with each line's isospin): a second,
+  independent 5-D quadrature (general Pauli limits per isospin pair, the
+  relative azimuth integrated in closed form).
 """
 import math
 
@@ -246,3 +252,225 @@ def lee_yang_x2(kF, C0=-0.1, hbar2_m=41.47, hbarc=HBARC, **npts):
 
 
 LEE_YANG_COEF = 4.0 * (11.0 - 2.0 * math.log(2.0)) / (21.0 * math.pi ** 2)
+
+
+# --------------------------------------------------------------------------
+# Second order, neutron or nuclear matter, free or Hartree-Fock spectrum
+# --------------------------------------------------------------------------
+
+def hf_self_energy(k, density, x=0.0, q=2, tau=0, C0=-1.0, Cy=-2.0, mpi=0.7, Lambda=2.0,
+                   reg_exp=4.0, hbarc=HBARC, ng=64):
+    """Sigma_tau(k) [MeV] of eq:spe for the spin(-isospin)-independent
+    interaction, written as a 1-D integral over u = |k - k'| = 2p:
+
+       Sigma_tau(k) = sum_tau' (2pi)^-3 int du u^2 Omega_tau'(u) [2 Vd(u/2) - delta Ve(u/2)],
+
+    where Omega(u) is the solid angle of the directions of u for which the
+    partner k' = k - u lies inside the Fermi sphere of tau' (4 pi while
+    u < kF - k, else 2 pi (1 - (k^2 + u^2 - kF^2) / (2 k u)), zero beyond
+    u = k + kF), Vd(p) = V(p, p) (zero momentum transfer, both partner
+    spins) and Ve(p) = V(p, -p) (transfer 2p, equal spin and isospin only).
+    Array k allowed."""
+    k = np.atleast_1d(np.asarray(k, dtype=np.float64))
+    kfs = [fermi_momentum(density)] if q == 2 else [fermi_momentum((1.0 - x) * density),
+                                                    fermi_momentum(x * density)]
+    tg, wg = _gl(ng)
+    out = np.zeros_like(k)
+
+    def g(u, same):
+        p = 0.5 * u
+        f2 = np.exp(-2.0 * (p / Lambda) ** reg_exp)
+        vd = hbarc * (C0 + Cy / (mpi * mpi)) * f2
+        ve = hbarc * (C0 + Cy / (4.0 * p * p + mpi * mpi)) * f2
+        return 2.0 * vd - (ve if same else 0.0)
+
+    for tp, kf in enumerate(kfs):
+        if kf <= 0.0:
+            continue
+        same = tp == tau
+        lo = np.abs(kf - k)
+        # full sphere part: 0 <= u < kF - k (only when k < kF)
+        full = np.where(k < kf, lo, 0.0)
+        u1 = 0.5 * full[:, None] * (tg[None, :] + 1.0)
+        w1 = 0.5 * full[:, None] * wg[None, :]
+        acc = (w1 * u1 * u1 * 4.0 * math.pi * g(u1, same)).sum(axis=1)
+        # partial part: |k - kF| < u < k + kF
+        a, b = lo, k + kf
+        u2 = 0.5 * (b - a)[:, None] * tg[None, :] + 0.5 * (b + a)[:, None]
+        w2 = 0.5 * (b - a)[:, None] * wg[None, :]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            c0 = (k[:, None] ** 2 + u2 * u2 - kf * kf) / (2.0 * k[:, None] * u2)
+        c0 = np.clip(np.nan_to_num(c0, nan=1.0), -1.0, 1.0)
+        acc += (w2 * u2 * u2 * 2.0 * math.pi * (1.0 - c0) * g(u2, same)).sum(axis=1)
+        out += acc / (2.0 * math.pi) ** 3
+    return out
+
+
+def _smooth_nodes(a, b, n):
+    """Gauss-Legendre on [a, b] through s = t^2 (3 - 2t): nodes clustered at
+    both ends (for the logarithmic endpoint behaviour of 1/D)."""
+    t, w = _gl_interval(0.0, 1.0, n)
+    s = t * t * (3.0 - 2.0 * t)
+    return a + (b - a) * s, (b - a) * 6.0 * t * (1.0 - t) * w
+
+
+def _segments(bps, lo, hi):
+    pts = sorted({lo, hi, *[v for v in bps if lo < v < hi]})
+    return list(zip(pts[:-1], pts[1:]))
+
+
+def second_order(density, x=0.0, q=2, spectrum="free", C0=-1.0, Cy=-2.0, mpi=0.7,
+                 Lambda=2.0, reg_exp=4.0, hbar2_m=41.47, hbarc=HBARC, pcut_factor=3.5,
+                 n_k=16, n_pp=10, n_cp=10, n_p=12, n_c=10, hf_grid=0.004):
+    """Second-order energy per particle [MeV], Eq. (2), with the free spectrum
+    or the HF spectrum eps_tau(k) = hbar^2 k^2 / 2m + Sigma_tau(k) (eq:spe,
+    eq:Dijkabc with each line's own isospin), in neutron (q = 2) or nuclear
+    (q = 4, proton fraction x) matter.
+
+    Coordinates K = k_i + k_j (along z), p' = (k_i - k_j) / 2, p = (k_a - k_b) / 2;
+    the hole pair has |K/2 + p'| < kF_ti, |K/2 - p'| < kF_tj, the particle pair
+    |K/2 + p| >= kF_ta, |K/2 - p| >= kF_tb, which bound cos(theta') and
+    cos(theta) (the angles to K) for each (K, p', p).  The spin-summed squared
+    matrix elements (equal isospins: 4 Vd^2 + 4 Ve^2 - 4 Vd Ve; unequal: 4 Vd^2
+    with the particles keeping the holes' isospins, 4 Ve^2 with them swapped)
+    are integrated over the relative azimuth in closed form, since only the
+    Yukawa denominators depend on it:
+       int dphi / (a -+ b cos phi) = 2 pi / sqrt(a^2 - b^2),
+       int dphi / (a -+ b cos phi)^2 = 2 pi a / (a^2 - b^2)^(3/2),
+       1 / ((a_d - b c)(a_e + b c)) = [1 / (a_d - b c) + 1 / (a_e + b c)] / (a_d + a_e).
+    The remaining 5-D integral is Gauss-Legendre on pieces between the points
+    where a Pauli limit changes form, graded at both ends of every piece."""
+    kfs = [fermi_momentum(density)] if q == 2 else [fermi_momentum((1.0 - x) * density),
+                                                    fermi_momentum(x * density)]
+    if q == 2 and x != 0.0:
+        raise ValueError("neutron matter needs x = 0")
+    kmax_all = max(kfs)
+    pcut = kmax_all + pcut_factor * Lambda
+    eps_fns = []
+    for t in range(len(kfs)):
+        if spectrum == "hf":
+            kk = np.arange(0.0, 2.0 * kmax_all + pcut + 4 * hf_grid, hf_grid)
+            sig = hf_self_energy(kk, density, x, q, t, C0, Cy, mpi, Lambda, reg_exp, hbarc)
+            from scipy.interpolate import CubicSpline
+            spl = CubicSpline(kk, sig)
+            eps_fns.append(lambda k, s=spl: 0.5 * hbar2_m * k * k + s(k))
+        elif spectrum == "free":
+            eps_fns.append(lambda k: 0.5 * hbar2_m * k * k)
+        else:
+            raise ValueError(spectrum)
+
+    # (hole isospins, particle isospins, label-sum kind)
+    combos = []
+    for ti in range(len(kfs)):
+        for tj in range(len(kfs)):
+            if ti == tj:
+                combos.append((ti, tj, ti, tj, "same"))
+            else:
+                combos.append((ti, tj, ti, tj, "direct"))
+                combos.append((ti, tj, tj, ti, "exchange"))
+
+    def ang_lim(kfa, kfb, K, r, hole):
+        """cos-theta interval from the two Pauli conditions (arrays over r)."""
+        with np.errstate(divide="ignore", invalid="ignore"):
+            A = (kfa * kfa - K * K / 4.0 - r * r) / (K * r)
+            B = (kfb * kfb - K * K / 4.0 - r * r) / (K * r)
+        if hole:   # |K/2 + r| < kfa  and  |K/2 - r| < kfb
+            return np.maximum(-1.0, -B), np.minimum(1.0, A)
+        return np.maximum(-1.0, A), np.minimum(1.0, -B)   # outside both
+
+    tc, wcr = _gl_interval(0.0, 1.0, n_c)
+    sc = tc * tc * (3.0 - 2.0 * tc)
+    wsc = 6.0 * tc * (1.0 - tc) * wcr
+    tcp, wcpr = _gl_interval(0.0, 1.0, n_cp)
+    scp = tcp * tcp * (3.0 - 2.0 * tcp)
+    wscp = 6.0 * tcp * (1.0 - tcp) * wcpr
+    m2 = mpi * mpi
+    total = 0.0
+    for ti, tj, ta, tb, kind in combos:
+        ki, kj, ka, kb = kfs[ti], kfs[tj], kfs[ta], kfs[tb]
+        if ki <= 0.0 or kj <= 0.0:
+            continue
+        ei, ej, ea, eb = eps_fns[ti], eps_fns[tj], eps_fns[ta], eps_fns[tb]
+        for K0, K1 in _segments([abs(ki - kj)], 0.0, ki + kj):
+            Ks, wK = _gl_interval(K0, K1, n_k)
+            for K, wk in zip(Ks, wK):
+                # hole relative momenta
+                hb = [abs(ki - K / 2), ki + K / 2, abs(kj - K / 2), kj + K / 2]
+                e2 = 0.5 * (ki * ki + kj * kj) - K * K / 4.0
+                if e2 > 0:
+                    hb.append(math.sqrt(e2))
+                pps, wpps = [], []
+                for a, b in _segments(hb, 0.0, 0.5 * (ki + kj)):
+                    lo, hi = ang_lim(ki, kj, K, np.array([0.5 * (a + b)]), True)
+                    if hi[0] <= lo[0]:
+                        continue
+                    r, w = _smooth_nodes(a, b, n_pp)
+                    pps.append(r)
+                    wpps.append(w)
+                if not pps:
+                    continue
+                pp = np.concatenate(pps)
+                wpp = np.concatenate(wpps)
+                lo, hi = ang_lim(ki, kj, K, pp, True)
+                ok = hi > lo
+                pp, wpp, lo, hi = pp[ok], wpp[ok], lo[ok], hi[ok]
+                cp = lo[:, None] + (hi - lo)[:, None] * scp[None, :]        # (P', C')
+                wcp = (hi - lo)[:, None] * wscp[None, :]
+                # particle relative momenta
+                pb_ = [abs(ka - K / 2), ka + K / 2, abs(kb - K / 2), kb + K / 2]
+                e2 = 0.5 * (ka * ka + kb * kb) - K * K / 4.0
+                if e2 > 0:
+                    pb_.append(math.sqrt(e2))
+                ps, wps = [], []
+                for a, b in _segments(pb_, 0.0, pcut):
+                    lo2, hi2 = ang_lim(ka, kb, K, np.array([0.5 * (a + b)]), False)
+                    if hi2[0] <= lo2[0]:
+                        continue
+                    r, w = _smooth_nodes(a, b, n_p)
+                    ps.append(r)
+                    wps.append(w)
+                p = np.concatenate(ps)
+                wp = np.concatenate(wps)
+                lo2, hi2 = ang_lim(ka, kb, K, p, False)
+                ok = hi2 > lo2
+                p, wp, lo2, hi2 = p[ok], wp[ok], lo2[ok], hi2[ok]
+                c = lo2[:, None] + (hi2 - lo2)[:, None] * sc[None, :]       # (P, C)
+                wc = (hi2 - lo2)[:, None] * wsc[None, :]
+                # energies: holes depend on (p', c'), particles on (p, c)
+                kh1 = np.sqrt(np.maximum(0.0, K * K / 4 + pp[:, None] ** 2 + K * pp[:, None] * cp))
+                kh2 = np.sqrt(np.maximum(0.0, K * K / 4 + pp[:, None] ** 2 - K * pp[:, None] * cp))
+                kp1 = np.sqrt(np.maximum(0.0, K * K / 4 + p[:, None] ** 2 + K * p[:, None] * c))
+                kp2 = np.sqrt(np.maximum(0.0, K * K / 4 + p[:, None] ** 2 - K * p[:, None] * c))
+                eh = ei(kh1) + ej(kh2)                                       # (P', C')
+                ep = ea(kp1) + eb(kp2)                                       # (P, C)
+                D = eh[:, :, None, None] - ep[None, None, :, :]              # (P', C', P, C)
+                # azimuth-integrated label sums
+                P4 = pp[:, None, None, None]
+                Q4 = p[None, None, :, None]
+                ccp = cp[:, :, None, None] * c[None, None, :, :]
+                ssp = (np.sqrt(np.maximum(0.0, 1 - cp * cp))[:, :, None, None]
+                       * np.sqrt(np.maximum(0.0, 1 - c * c))[None, None, :, :])
+                base = P4 * P4 + Q4 * Q4 + m2
+                ad = base - 2.0 * P4 * Q4 * ccp
+                ae = base + 2.0 * P4 * Q4 * ccp
+                bb = 2.0 * P4 * Q4 * ssp
+                rd = np.sqrt(ad * ad - bb * bb)
+                re = np.sqrt(ae * ae - bb * bb)
+                i1d, i1e = 2.0 * math.pi / rd, 2.0 * math.pi / re
+                i2d, i2e = 2.0 * math.pi * ad / rd ** 3, 2.0 * math.pi * ae / re ** 3
+                F2 = (hbarc * np.exp(-(P4 / Lambda) ** reg_exp - (Q4 / Lambda) ** reg_exp)) ** 2
+                vdd = F2 * (2 * math.pi * C0 * C0 + 2 * C0 * Cy * i1d + Cy * Cy * i2d)
+                vee = F2 * (2 * math.pi * C0 * C0 + 2 * C0 * Cy * i1e + Cy * Cy * i2e)
+                if kind == "same":
+                    vde = F2 * (2 * math.pi * C0 * C0 + C0 * Cy * (i1d + i1e)
+                                + Cy * Cy * (i1d + i1e) / (ad + ae))
+                    ls = 4.0 * vdd + 4.0 * vee - 4.0 * vde
+                elif kind == "direct":
+                    ls = 4.0 * vdd
+                else:
+                    ls = 4.0 * vee
+                wt = ((wpp * pp * pp)[:, None, None, None] * wcp[:, :, None, None]
+                      * (wp * p * p)[None, None, :, None] * wc[None, None, :, :])
+                total += wk * K * K * float((wt * ls / D).sum())
+    # 1/4 (2pi)^-9, 4 pi (K direction), 2 pi (azimuth of p' about K)
+    return 0.25 * (2.0 * math.pi) ** -9 * 4.0 * math.pi * 2.0 * math.pi * total / density

@@ -94,3 +94,80 @@ def test_hf_changes_the_second_order_energy():
     w1, _ = O.sample_values(hf, grid, 0, 0, 2000)
     nz = w0 != 0
     assert np.median(np.abs(w1[nz] / w0[nz] - 1.0)) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# The HF spectrum inside the second-order denominators, pinned by an
+# independent reduced-dimension quadrature (references.second_order)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,x,q", [(0.08, 0.0, 2), (0.12, 0.1, 4)])
+def test_hf_self_energy_two_quadratures(n, x, q):
+    # the oracle integrates over the partner momentum k' (|k'|, angle); the
+    # reference over the transfer |k - k'| with the solid angle in closed form
+    pb = O.problem(1, 0, density=n, proton_fraction=x, q=q)
+    ks = np.array([0.0, 0.3, 0.9, 1.2, 1.6, 2.5, 4.0])
+    for t in range(2 if q == 4 else 1):
+        ref = R.hf_self_energy(ks, n, x, q, t, ng=96)
+        for k, r in zip(ks, ref):
+            assert abs(O.hf_sigma(pb, t, k) - r) < 1e-10 * max(1.0, abs(r)), (t, k)
+
+
+def test_general_second_order_quadrature_matches_neutron_matter_one():
+    # two separately written quadratures of Eq. (2) (the neutron-matter one is
+    # itself pinned by the Lee-Yang coefficient)
+    a = R.second_order_pnm(0.08, n_k=16, n_pp=16, n_cp=12, n_p=24, n_c=16, n_phi=24)
+    b = R.second_order(0.08, n_k=24, n_pp=14, n_cp=14, n_p=16, n_c=14)
+    assert abs(a - b) < 3e-5 * abs(a)
+
+
+@pytest.mark.parametrize("spectrum", ["free", "hf"])
+def test_general_second_order_quadrature_converged(spectrum):
+    a = R.second_order(0.12, 0.1, 4, spectrum=spectrum, n_k=12, n_pp=8, n_cp=8, n_p=10, n_c=8)
+    b = R.second_order(0.12, 0.1, 4, spectrum=spectrum)
+    assert abs(a - b) < 5e-4 * abs(b)
+
+
+def test_nuclear_quadrature_neutron_limit_and_symmetry():
+    # x = 0 nuclear matter is neutron matter; x <-> 1 - x is a relabelling
+    a = R.second_order(0.08, 0.0, 2, spectrum="hf")
+    b = R.second_order(0.08, 0.0, 4, spectrum="hf")
+    assert abs(a - b) < 1e-12 * abs(a)
+    c = R.second_order(0.16, 0.2, 4, spectrum="hf")
+    d = R.second_order(0.16, 0.8, 4, spectrum="hf")
+    assert abs(c - d) < 1e-12 * abs(c)
+
+
+@pytest.mark.parametrize("n,x,q", [(0.08, 0.0, 2), (0.12, 0.1, 4), (0.16, 0.3, 4)])
+def test_mc_second_order_hf_against_quadrature(n, x, q):
+    """The oracle's Monte Carlo with the HF spectrum (spline tables, per-line
+    isospin in every denominator) agrees with the quadrature within 3 sigma,
+    while the free-spectrum value is many sigma away.  At x = 0.1 exchanging
+    the neutron and proton self-energies moves the quadrature by 4% (25
+    sigma here), averaging them by 2%."""
+    ref = R.second_order(n, x, q, spectrum="hf")
+    free = R.second_order(n, x, q, spectrum="free")
+    pb = O.problem(2, 0, density=n, proton_fraction=x, q=q, spectrum=1, seed=1)
+    r, I, V, e = O.integrate(pb, 1 << 18, 10)
+    assert abs(r.mean - ref) < 3.0 * r.sigma, (r.mean, r.sigma, ref)
+    assert abs(r.mean - free) > 30.0 * r.sigma
+
+
+def test_mc_second_order_nuclear_free_against_quadrature():
+    ref = R.second_order(0.16, 0.3, 4)
+    pb = O.problem(2, 0, density=0.16, proton_fraction=0.3, q=4, seed=2)
+    r, I, V, e = O.integrate(pb, 1 << 18, 10)
+    assert abs(r.mean - ref) < 3.0 * r.sigma, (r.mean, r.sigma, ref)
+
+
+@pytest.mark.parametrize("order,did,n,x", [(2, 0, 0.16, 0.2), (3, 2, 0.12, 0.35)])
+def test_hf_mirror_proton_fraction(order, did, n, x):
+    # exchanging neutrons and protons relabels every isospin sum: the HF
+    # integrand at x equals the one at 1 - x sample by sample
+    a = O.problem(order, did, density=n, proton_fraction=x, q=4, spectrum=1)
+    b = O.problem(order, did, density=n, proton_fraction=1.0 - x, q=4, spectrum=1)
+    grid = O.uniform_grid(3 * (order + 1))
+    wa, ca = O.sample_values(a, grid, 0, 0, 600)
+    wb, _ = O.sample_values(b, grid, 0, 0, 600)
+    assert np.count_nonzero(wa) > 20
+    assert np.all(np.abs(wa - wb) <= 1e-12 * ca + 1e-300)
