@@ -46,8 +46,12 @@ def test_fp32_per_sample(M, order, did, q, n, x):
         finally:
             run.close()
         ratio = np.abs(w - wo) / np.maximum(co, 1e-300)
+        nz = wo != 0
+        rel = np.abs(w[nz] - wo[nz]) / np.abs(wo[nz])
         print(f"  label_mode {label_mode}: max |dw|/W_cond = {ratio.max():.3e}, "
-              f"nonzero {np.count_nonzero(wo)}")
+              f"nonzero {np.count_nonzero(wo)}; plain relative: max {rel.max():.3e}, "
+              f"median {np.median(rel):.2e}, fraction above 1e-5 {np.mean(rel > 1e-5):.2e}, "
+              f"max W_cond/|w| {np.max(co[nz] / np.abs(wo[nz])):.2e}", flush=True)
         assert np.all(np.abs(w - wo) <= TOL32 * co + 1e-300), (label_mode, ratio.max())
 
 
