@@ -352,6 +352,29 @@ int mbpt_regularized_log(mbpt_task_set *set, int task, double *I, double *var, i
  * the fit is singular. */
 int mbpt_regularized(mbpt_task_set *set, int task, int skip_iters, double *E, double *sigma,
                      double *E0, double *sigma0);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mbpt_integrate
+ * on a set that has no workspace bound, with the set's device state held in a
+ * static device array of MBPT_NOALLOC_SCRATCH_BYTES that the library keeps on
+ * each GPU it runs on until the process ends.  Each call starts every task of
+ * the set from a uniform grid at iteration 0, runs `iters` iterations on the
+ * context stream and returns the results as mbpt_integrate does (same work
+ * decomposition as a workspace bound with max_samples_per_iter =
+ * samples_per_iter, so the same estimates up to the order of the fp64
+ * histogram atomics); nothing persists in the set, which is left unbound
+ * (mbpt_iteration_log, mbpt_get_grid and mbpt_dump_samples still need a
+ * bound workspace).  No device memory, event or graph is created: launches
+ * are neither graph-captured nor timed.  Every call on one GPU uses that GPU's
+ * one array, which keeps the last call's contents (each call initialises what
+ * it reads): calls that overlap on one GPU, from two host threads or on two
+ * streams, race and corrupt each other's results.  EINVAL on a null set,
+ * iters < 1 or samples_per_iter < 2; ESTATE if a workspace is bound; ENOMEM,
+ * with the byte counts in mbpt_last_error, if the set needs more scratch at
+ * this sample and iteration count than the array holds. */
+#define MBPT_NOALLOC_SCRATCH_BYTES (32u << 20)
+int mbpt_integrate_noalloc(mbpt_task_set *set, uint64_t samples_per_iter, int iters,
+                           mbpt_result *per_task, mbpt_result *total);
+
 /* Grid of a task (ndim x (n_bins+1) edges, host memory) for checkpointing,
  * and its restore.  ndim = 3 (order + 1). */
 int mbpt_get_grid(mbpt_task_set *set, int task, double *edges_host);

@@ -34,7 +34,7 @@ EXPORTED = [
     "mbpt_kernel_stats", "mbpt_task_flops", "mbpt_autotune", "mbpt_server_workspace_query", "mbpt_server_create",
     "mbpt_server_destroy", "mbpt_server_submit", "mbpt_server_step", "mbpt_server_poll",
     "mbpt_set_regularization", "mbpt_dump_samples_reg", "mbpt_regularized_log",
-    "mbpt_regularized", "mbpt_diagram_flops",
+    "mbpt_regularized", "mbpt_diagram_flops", "mbpt_integrate_noalloc",
 ]
 
 
@@ -139,6 +139,8 @@ def lib():
         "mbpt_bind_workspace": [_P, _P, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int],
         "mbpt_reset": [_P],
         "mbpt_integrate": [_P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(mbpt_result),
+                           ctypes.POINTER(mbpt_result)],
+        "mbpt_integrate_noalloc": [_P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(mbpt_result),
                            ctypes.POINTER(mbpt_result)],
         "mbpt_iteration_log": [_P, ctypes.c_int, _DP, _DP, ctypes.c_int, _IP],
         "mbpt_dump_samples": [_P, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
@@ -382,6 +384,17 @@ def mbpt_integrate(s, samples_per_iter, iters):
     per = (mbpt_result * n)()
     tot = mbpt_result()
     _check(lib().mbpt_integrate(s, samples_per_iter, iters, per, ctypes.byref(tot)),
+           _ctx_of_set(s))
+    return list(per), tot
+
+
+def mbpt_integrate_noalloc(s, samples_per_iter, iters):
+    """mbpt_integrate on a set without a workspace, in the library's static
+    device scratch: (per-task results list, total result)."""
+    n = mbpt_task_count(s)
+    per = (mbpt_result * n)()
+    tot = mbpt_result()
+    _check(lib().mbpt_integrate_noalloc(s, samples_per_iter, iters, per, ctypes.byref(tot)),
            _ctx_of_set(s))
     return list(per), tot
 

@@ -1131,7 +1131,7 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
   uint64_t evals_before = 0;
   {
     int rc = 0;
-    if (set->launch_mode == MBPT_LAUNCH_GRAPH) {
+    if (set->launch_mode == MBPT_LAUNCH_GRAPH && !set->noalloc) {
       if (ctx->stream == nullptr) {
         set_err(ctx, "integrate: GRAPH launch mode needs a non-default stream to capture on");
         return MBPT_EINVAL;
@@ -1154,7 +1154,7 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
       HIPCHK(ctx, hipGraphLaunch(set->graph_exec, ctx->stream));
       timed_end(ctx, slot);
     } else {
-      rc = enqueue_iterations(set, a, iters, true);
+      rc = enqueue_iterations(set, a, iters, !set->noalloc);
       if (rc) return rc;
     }
   }
@@ -1199,6 +1199,60 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
   if (status) set_err(ctx, "integrate: non-finite estimate");
   return status;
 }
+
+namespace mbpt {
+
+// mbpt_integrate for a set without a workspace, inside device memory the
+// caller supplies for this call only: bind (uploads the descriptors and
+// parameters, starts every task from a uniform grid at iteration 0), run
+// without graph capture or timing events, then leave the set unbound.
+int integrate_in(mbpt_task_set *set, void *base, size_t bytes, uint64_t samples_per_iter,
+                 int iters, mbpt_result *per_task, mbpt_result *total) {
+  if (!set || !base || iters < 1 || samples_per_iter < 2) return MBPT_EINVAL;
+  mbpt_context *ctx = set->ctx;
+  if (set->ws) {
+    set_err(ctx, "integrate_noalloc: the set has a workspace bound (use mbpt_integrate)");
+    return MBPT_ESTATE;
+  }
+  const size_t need = layout_of(set, samples_per_iter, iters, ctx->desc.n_bins).total;
+  if (need > bytes) {
+    set_err(ctx, "integrate_noalloc: " + std::to_string(set->tasks.size()) + " tasks at " +
+                     std::to_string(samples_per_iter) + " samples per iteration and " +
+                     std::to_string(iters) + " iterations need " + std::to_string(need) +
+                     " bytes of device scratch, more than the " + std::to_string(bytes) +
+                     " bytes available");
+    return MBPT_ENOMEM;
+  }
+  int rc = bind(set, base, bytes, samples_per_iter, iters);
+  if (rc == MBPT_OK) {
+    set->noalloc = true;
+    rc = mbpt_integrate(set, samples_per_iter, iters, per_task, total);
+    set->noalloc = false;
+  }
+  set->drop_graph();
+  set->ws = nullptr;
+  set->ws_bytes = 0;
+  set->max_samples = 0;
+  set->max_iters = 0;
+  set->max_items = 0;
+  set->d_tasks = nullptr;
+  set->d_olist = nullptr;
+  set->d_diags = nullptr;
+  set->d_groups = nullptr;
+  set->d_terms = nullptr;
+  set->d_coefs = nullptr;
+  set->d_grids = set->d_hists = set->d_partials = set->d_reslog = nullptr;
+  set->d_cpart = set->d_creslog = nullptr;
+  set->d_counters = nullptr;
+  set->d_hf = set->d_gl = nullptr;
+  set->hf_dirty = true;
+  set->oranges.clear();
+  set->last_state.clear();
+  set->run_reg_n = -1;
+  return rc;
+}
+
+}  // namespace mbpt
 
 extern "C" int mbpt_iteration_log(mbpt_task_set *set, int task, double *I, double *var, int cap,
                                   int *count) {

@@ -91,6 +91,8 @@ struct mbpt_task_set {
   std::vector<mbpt::OrderRange> oranges;   // one sample launch per order
   hipGraphExec_t graph_exec = nullptr;
   int graph_iters = 0;
+  // set while mbpt_integrate_noalloc runs: no graph capture, no timing events
+  bool noalloc = false;
   void drop_graph() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     graph_exec = nullptr;
@@ -120,6 +122,8 @@ int ensure_hf(mbpt_task_set *set);
 void sync_epoch(mbpt_task_set *set);
 void order_items(std::vector<TaskDev> &T, const std::vector<int> &active,
                  std::vector<int2> &olist, std::vector<OrderRange> &ranges);
+int integrate_in(mbpt_task_set *set, void *base, size_t bytes, uint64_t samples_per_iter,
+                 int iters, mbpt_result *per_task, mbpt_result *total);
 }  // namespace mbpt
 
 #define MBPT_HIPCHK(ctx, call)                                      \
