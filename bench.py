@@ -104,6 +104,10 @@ def parse():
                          "the others run one part alone (for profiling)")
     ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"],
                     help="nuclear4 alone: which integrand(s) to run")
+    ap.add_argument("--order", type=int, default=4, choices=(2, 3, 4, 5),
+                    help="nuclear4 alone: the order of the diagrams (4 in the headline)")
+    ap.add_argument("--stride", type=int, default=1,
+                    help="nuclear4 alone: every stride-th diagram of the order")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device three times "
                          "(reference dispatch for rocprofv3 byte counters)")
@@ -223,9 +227,11 @@ def _chi2(per):
 # Headline: all fourth-order diagrams, nuclear matter, 15 EOS points
 # --------------------------------------------------------------------------
 
-def c4_tasks(M):
-    return [(4, d, M.MBPT_NUCLEAR, n, x, 10000 * d + 100 * i + j)
-            for d in range(M.mbpt_num_diagrams(4))
+def c4_tasks(M, order=4, stride=1):
+    """Diagrams 0, stride, 2 stride, ... of an order (all 39 at fourth order
+    for the headline) x the 15 EOS points."""
+    return [(order, d, M.MBPT_NUCLEAR, n, x, 10000 * d + 100 * i + j)
+            for d in range(0, M.mbpt_num_diagrams(order), stride)
             for i, n in enumerate(DENSITIES_C4) for j, x in enumerate(FRACTIONS_C4)]
 
 
@@ -245,7 +251,7 @@ def flop_models(M, tasks):
 
 
 def nuclear4(args, M, stream, precisions=("fp32", "fp64"), extras=True):
-    tasks = c4_tasks(M)
+    tasks = c4_tasks(M, args.order, args.stride)
     N = 1 << args.samples_log2
     legs = {}
     for p in precisions:
