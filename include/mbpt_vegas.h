@@ -403,7 +403,9 @@ int mbpt_kernel_stats(mbpt_context *ctx, uint64_t *launches, double *kernel_ms,
  * test (denominators, matrix elements, monomial tables, weight), *per_unit
  * those of one label unit evaluated (an isospin configuration of the
  * polynomial form, label_mode 0, or one compressed assignment term, label_mode
- * 1), *units the diagram's label units.  FMA = 2, add/mul = 1, each
+ * 1), *units the diagram's label units (nuclear matter with the free spectrum
+ * and label_mode 0 evaluates one polynomial per passing sample, the cycle form
+ * of the label sum: 1 unit).  FMA = 2, add/mul = 1, each
  * exp/sqrt/sin/cos/division = 1.  mbpt_kernel_stats multiplies them with the
  * device's per-task counts of samples, passing samples and units evaluated.
  * EINVAL on an unknown diagram or a bad matter, label_mode, reg_exp (even,

@@ -8,6 +8,9 @@
 namespace mbpt {
 
 constexpr int kMaxBins = 128;
+// Distinct label cycles of one diagram over all vertex-term choices (at most
+// 33 at fifth order, 17 at fourth)
+constexpr int kMaxCycles = 40;
 constexpr int kBlockMax = 1024;
 
 // Compiled diagram (read wave-uniformly through the scalar cache).
@@ -29,6 +32,17 @@ struct alignas(16) DiagDev {
   uint32_t cut_hole[4];   // D_c = sum_{holes in c} eps - sum_{particles in c} eps
   uint32_t cut_part[4];
   int pad3[2];
+  // Label cycles (nuclear matter): choosing the direct or the exchange term
+  // at every vertex (E, bit v = exchange at vertex v) ties the labels of the
+  // lines into closed cycles.  cyc_mask[k]: the ncyc distinct cycles of all
+  // E as line-slot masks; per E, the set of its cycles (bit k for cycle k)
+  // and their number: cyc_e[E] = set | number << 56, and for diagrams with at
+  // most 24 cycles also cyc_e32[E] = set | number << 24.
+  int ncyc;
+  int pad4;
+  uint32_t cyc_mask[kMaxCycles];
+  uint64_t cyc_e[32];
+  uint32_t cyc_e32[32];
 };
 
 // Compile-time descriptor masks for the diagrams whose kernels are

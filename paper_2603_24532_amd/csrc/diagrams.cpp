@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <array>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <string>
@@ -424,6 +425,80 @@ LabelTables label_tables(const Diagram &d, int q, bool canonical) {
     i = j;
   }
   return out;
+}
+
+CycleTables cycle_tables(const Diagram &d, bool canonical) {
+  int slot_line[kMaxLines], slot_of[kMaxLines];
+  line_slots(d, slot_line, canonical);
+  for (int sl = 0; sl < d.nlines; ++sl) slot_of[slot_line[sl]] = sl;
+  CycleTables out;
+  const int n = d.order, nE = 1 << n;
+  for (int E = 0; E < nE; ++E) {
+    int root[kMaxLines];
+    for (int l = 0; l < d.nlines; ++l) root[l] = l;
+    auto find = [&](int x) {
+      while (root[x] != x) x = root[x] = root[root[x]];
+      return x;
+    };
+    for (int v = 0; v < n; ++v) {
+      const int o1 = d.vout[v][0], o2 = d.vout[v][1];
+      const int i1 = d.vin[v][0], i2 = d.vin[v][1];
+      const bool ex = (E >> v) & 1;
+      root[find(o1)] = find(ex ? i2 : i1);
+      root[find(o2)] = find(ex ? i1 : i2);
+    }
+    uint32_t comp[kMaxLines] = {};
+    for (int l = 0; l < d.nlines; ++l) comp[find(l)] |= 1u << slot_of[l];
+    uint64_t bits = 0;
+    int count = 0;
+    for (int l = 0; l < d.nlines; ++l) {
+      if (!comp[l]) continue;
+      ++count;
+      size_t k = 0;
+      while (k < out.masks.size() && out.masks[k] != comp[l]) ++k;
+      if (k == out.masks.size()) out.masks.push_back(comp[l]);
+      bits |= uint64_t{1} << k;
+    }
+    out.of_e.push_back(bits);
+    out.n_of_e.push_back(count);
+  }
+  return out;
+}
+
+bool cycles_match_label_tables(const Diagram &d, int q, bool canonical) {
+  const LabelTables lt = label_tables(d, q, canonical);
+  const CycleTables ct = cycle_tables(d, canonical);
+  const int nE = 1 << d.order;
+  for (const auto &g : lt.groups)
+    for (int E = 0; E < nE; ++E) {
+      bool constant = true;
+      for (size_t k = 0; k < ct.masks.size(); ++k) {
+        if (!((ct.of_e[E] >> k) & 1u)) continue;
+        const uint32_t t = g.tau & ct.masks[k];
+        constant = constant && (t == 0u || t == ct.masks[k]);
+      }
+      const int sign = __builtin_popcount(static_cast<unsigned>(E)) & 1 ? -1 : 1;
+      const double want = constant ? sign * std::ldexp(1.0, ct.n_of_e[E]) : 0.0;
+      if (g.coef[E] != want) return false;
+    }
+  // every isospin pattern constant on some E's cycles is one of the groups
+  // (q = 4): count them against the table's groups
+  if (q == 4) {
+    std::vector<uint32_t> seen;
+    for (int E = 0; E < nE; ++E) {
+      std::vector<uint32_t> cyc;
+      for (size_t k = 0; k < ct.masks.size(); ++k)
+        if ((ct.of_e[E] >> k) & 1u) cyc.push_back(ct.masks[k]);
+      for (uint32_t pick = 0; pick < (1u << cyc.size()); ++pick) {
+        uint32_t tau = 0;
+        for (size_t c = 0; c < cyc.size(); ++c)
+          if ((pick >> c) & 1u) tau |= cyc[c];
+        if (std::find(seen.begin(), seen.end(), tau) == seen.end()) seen.push_back(tau);
+      }
+    }
+    if (seen.size() != lt.groups.size()) return false;
+  }
+  return true;
 }
 
 LabelList build_labels(const Diagram &d, int q) {

@@ -94,6 +94,24 @@ struct LabelTables {
 };
 LabelTables label_tables(const Diagram &d, int q, bool canonical = false);
 
+// Label cycles of the vertex-term choices E (bit v of E: exchange at vertex
+// v).  With the direct term the labels of o1 and i1 and of o2 and i2 are
+// equal, with the exchange term those of o1 and i2 and of o2 and i1; every
+// line meets two vertex slots, so for each E the lines fall into closed
+// cycles of equal labels.  For a spin(-isospin)-independent interaction the
+// label sum of E is then (-1)^{|E|} prod_{cycles} (spin states x sum over the
+// isospins allowed on every line of the cycle), and the coefficient of E in
+// an isospin configuration's polynomial (label_tables) is (-1)^{|E|}
+// 2^{cycles(E)} if the configuration is constant on each cycle of E, else 0.
+struct CycleTables {
+  std::vector<uint32_t> masks;  // distinct cycles as line-slot masks
+  std::vector<uint64_t> of_e;   // per E: bit k set if cycle k is one of E's
+  std::vector<int> n_of_e;      // per E: its number of cycles
+};
+CycleTables cycle_tables(const Diagram &d, bool canonical = false);
+// True if every coefficient of label_tables(d, q) equals the cycle form above.
+bool cycles_match_label_tables(const Diagram &d, int q, bool canonical = false);
+
 // Number of diagrams of an order (1..5), or -1.
 int num_diagrams(int order);
 // Diagram `id` of an order (ids follow the lexicographic order of the

@@ -77,7 +77,41 @@ struct SampleLds {
   const double *ex;
   const double *hf;
   const double2 *g;
+  const void *cyc;  // label-cycle table of the item's diagram (cycle-form kernels)
 };
+
+// Label-cycle bit vectors: bit k of CycWord<ORDER> stands for cycle k of a
+// diagram (at most 17 at fourth order, 33 at fifth).
+template <int ORDER>
+using CycWord = std::conditional_t<(ORDER >= 5), uint64_t, uint32_t>;
+
+// The nuclear-matter label sum runs in the cycle form (see label_sum) for
+// single diagrams with the free spectrum and the factorised label sum.
+template <int ORDER, int Q, bool G, bool X, bool HF>
+constexpr bool cycle_form() {
+  return Q == 4 && ORDER >= 2 && !G && !X && !HF;
+}
+
+// Bytes of the label-cycle table: one CycWord per set of lines.
+template <int ORDER>
+__host__ __device__ constexpr size_t cycle_table_bytes() {
+  return (size_t{1} << (2 * ORDER)) * sizeof(CycWord<ORDER>);
+}
+
+// tab[s] = the cycles of diagram D that contain no line of the line set s
+// (bit k set if (s & cycle k) = 0); built by the whole block.
+template <int ORDER>
+__device__ __forceinline__ void build_cycle_table(const DiagDev *__restrict__ D,
+                                                  CycWord<ORDER> *tab) {
+  const int K = D->ncyc;
+  for (int s = threadIdx.x; s < (1 << (2 * ORDER)); s += blockDim.x) {
+    CycWord<ORDER> w = 0;
+    for (int k = 0; k < K; ++k)
+      w |= (static_cast<uint32_t>(s) & D->cyc_mask[k]) == 0u ? (CycWord<ORDER>(1) << k)
+                                                            : CycWord<ORDER>(0);
+    tab[s] = w;
+  }
+}
 
 // Bytes of the fixed tables at the start of a sample kernel's LDS.
 __host__ __device__ constexpr size_t fixed_lds_bytes() {
@@ -108,6 +142,7 @@ __device__ __forceinline__ double *carve_lds(const KArgs &a, const TaskDev *__re
   L.ex = ex;
   L.hf = ntab ? hf : nullptr;
   L.g = g;
+  L.cyc = nullptr;
   return reinterpret_cast<double *>(g + nd * a.phys.nb);
 }
 
@@ -450,6 +485,97 @@ __device__ __forceinline__ double group_den(const DiagDev *__restrict__ D, uint3
   return prod;
 }
 
+// True if some vertex-term choice E has every one of its label cycles
+// allowed for at least one isospin (ab: cycles allowed as neutrons or as
+// protons): exactly when some isospin configuration passes the Pauli test.
+// Cycle set and cycle count of E (fourth order and below: at most 17
+// cycles, the 32-bit packing).
+template <int ORDER>
+__device__ __forceinline__ void cycles_of_e(const DiagDev *__restrict__ D, int E,
+                                            CycWord<ORDER> &m, uint32_t &n) {
+  if constexpr (ORDER >= 5) {
+    const uint64_t w = D->cyc_e[E];
+    m = w & ((uint64_t{1} << 56) - 1);
+    n = static_cast<uint32_t>(w >> 56);
+  } else {
+    const uint32_t w = D->cyc_e32[E];
+    m = w & 0xFFFFFFu;
+    n = w >> 24;
+  }
+}
+
+template <int ORDER>
+__device__ __forceinline__ bool cycle_any(const DiagDev *__restrict__ D, CycWord<ORDER> ab) {
+  bool any = false;
+#pragma unroll
+  for (int E = 0; E < (1 << ORDER); ++E) {
+    CycWord<ORDER> m;
+    uint32_t n;
+    cycles_of_e<ORDER>(D, E, m, n);
+    any |= (ab & m) == m;
+  }
+  return any;
+}
+
+// 2^e for 0 <= e <= 30 from its bit pattern
+template <typename F>
+__device__ __forceinline__ F pow2_bits(uint32_t e) {
+  return __hiloint2double(static_cast<int>((1023u + e) << 20), 0);
+}
+template <>
+__device__ __forceinline__ float pow2_bits<float>(uint32_t e) {
+  return __uint_as_float((127u + e) << 23);
+}
+
+template <int ORDER, typename W>
+__device__ __forceinline__ uint32_t popc_w(W x) {
+  if constexpr (sizeof(W) == 8) return static_cast<uint32_t>(__popcll(x));
+  else return static_cast<uint32_t>(__popc(x));
+}
+
+// Cycle form of the nuclear-matter label sum.  Expanding every vertex into
+// its direct and exchange terms, the choice E (bit v: exchange at vertex v)
+// contributes (-1)^{|E|} prod_{v not in E} V_d,v prod_{v in E} V_e,v times
+// the number of labellings that keep each of E's label cycles uniform with
+// every line allowed: 2 spin states times the isospins (neutron, proton)
+// allowed on all of the cycle's lines, per cycle.  With cA / cB the cycles
+// whose lines are all allowed as neutrons / protons, E's count is 0 if a
+// cycle is allowed for neither, else 2^{cycles(E) + cycles allowed for both}.
+// The monomials carry the sign (-V_e) and are tabulated as in the
+// configuration form; the counts are integers, so the sum equals the sum over
+// isospin configurations up to rounding.
+template <int ORDER, typename F>
+__device__ __forceinline__ F label_sum_cycles(const DiagDev *__restrict__ D, const F *Vd,
+                                              const F *Ve, CycWord<ORDER> cA, CycWord<ORDER> cB) {
+  using W = CycWord<ORDER>;
+  constexpr int H = ORDER / 2;
+  constexpr int NA = 1 << H, NB = 1 << (ORDER - H);
+  F nVe[ORDER];
+#pragma unroll
+  for (int v = 0; v < ORDER; ++v) nVe[v] = -Ve[v];
+  F MA[NA], MB[NB];
+  monomials<H>(Vd, nVe, MA);
+  monomials<ORDER - H>(Vd + H, nVe + H, MB);
+  const W ab = cA | cB, both = cA & cB;
+  F acc = F(0);
+#pragma unroll
+  for (int eb = 0; eb < NB; ++eb) {
+    F in = F(0);
+#pragma unroll
+    for (int ea = 0; ea < NA; ++ea) {
+      const int E = ea | (eb << H);
+      W m;
+      uint32_t n;
+      cycles_of_e<ORDER>(D, E, m, n);
+      const uint32_t e = popc_w<ORDER>(both & m) + n;
+      const F c = (ab & m) == m ? pow2_bits<F>(e) : F(0);
+      in = fma_t<F>(c, MA[ea], in);
+    }
+    acc = fma_t<F>(in, MB[eb], acc);
+  }
+  return acc;
+}
+
 // ISO: divide each configuration's sum by its own denominators (Dn, deps).
 // X: the explicit assignment list instead of the polynomial (compile-time, so
 // a kernel holds the state of one form only).
@@ -552,7 +678,7 @@ __device__ __forceinline__ double rcp_newton(double d) {
 // particle energies of the Hartree-Fock spectrum (tables in LDS).
 // REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
 // to wr[k - 1].
-template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V, int HE = 0>
+template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V, int HE = 0, bool CY = false>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
@@ -592,7 +718,15 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   const uint32_t lmask = line_mask_of<ORDER, V>(D), pmask = part_mask_of<ORDER, V>(D);
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
-  if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
+  CycWord<ORDER> cA = 0, cB = 0;
+  if constexpr (CY) {
+    const CycWord<ORDER> *tab = static_cast<const CycWord<ORDER> *>(Ls.cyc);
+    cA = tab[~okN & lmask];
+    cB = tab[~okP & lmask];
+    if (!cycle_any<ORDER>(D, cA | cB)) return 0.0;
+  } else {
+    if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
+  }
   ++npass;
 
   // energy denominators (with every line a neutron when they depend on
@@ -678,8 +812,14 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   }
   const double regall = exp_nonpos(-yreg * a.phys.invLn, Ls.ex);
 
-  const double acc =
-      label_sum<ORDER, Q, double, iso_den, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn, deps);
+  double acc;
+  if constexpr (CY) {
+    ++nterms;
+    acc = label_sum_cycles<ORDER, double>(D, Vd, Ve, cA, cB);
+  } else {
+    acc = label_sum<ORDER, Q, double, iso_den, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn,
+                                                     deps);
+  }
   const double base = D->pref * regall * acc;
   if constexpr (REG) {
     for (int r = 0; r < a.nreg; ++r) {
@@ -735,7 +875,8 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     for (int di = 0; di < nd; ++di)
       sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE>(a, T, D + di, Ls, k, npass, nterms, wr);
   } else {
-    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE>(a, T, D, Ls, k, npass, nterms, wr);
+    constexpr bool CY = cycle_form<ORDER, Q, false, X, HF>();
+    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, CY>(a, T, D, Ls, k, npass, nterms, wr);
   }
   const double scale = jac * (x0p * x0p) * jc;
   if constexpr (REG)
@@ -780,11 +921,12 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 // sample in fp64 from the same random words.
 // fp32 contribution of one diagram at the loop momenta k (see
 // diag_weight64); sets `fallback` instead when the sample needs fp64.
-template <int ORDER, int Q, bool X, int V, int HE = 0>
+template <int ORDER, int Q, bool X, int V, int HE = 0, bool CY = false>
 __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
-                                                const float (*k)[3], uint32_t &npass,
-                                                uint32_t &nterms, bool &fallback) {
+                                                const SampleLds &Ls, const float (*k)[3],
+                                                uint32_t &npass, uint32_t &nterms,
+                                                bool &fallback) {
   constexpr int L = ORDER + 1;
   constexpr int NL = 2 * ORDER;
   constexpr int NC = ORDER - 1;
@@ -820,7 +962,15 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   const uint32_t lmask = line_mask_of<ORDER, V>(D), pmask = part_mask_of<ORDER, V>(D);
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
-  if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
+  CycWord<ORDER> cA = 0, cB = 0;
+  if constexpr (CY) {
+    const CycWord<ORDER> *tab = static_cast<const CycWord<ORDER> *>(Ls.cyc);
+    cA = tab[~okN & lmask];
+    cB = tab[~okP & lmask];
+    if (!cycle_any<ORDER>(D, cA | cB)) return 0.0;
+  } else {
+    if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
+  }
 
   float dprod = 1.0f;
 #pragma unroll
@@ -886,9 +1036,14 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   }
   const float regall = __expf(-yexp);
 
-  const float acc =
-      label_sum<ORDER, Q, float, false, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms, nullptr,
-                                           nullptr);
+  float acc;
+  if constexpr (CY) {
+    ++nterms;
+    acc = label_sum_cycles<ORDER, float>(D, Vd, Ve, cA, cB);
+  } else {
+    acc = label_sum<ORDER, Q, float, false, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms, nullptr,
+                                                 nullptr);
+  }
   ++npass;
   return D->pref * static_cast<double>(regall) * static_cast<double>(acc) *
          static_cast<double>(rinv[NR - 1]);
@@ -931,13 +1086,14 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     // that falls back is counted once, by its fp64 re-evaluation
     uint32_t gpass = 0, gterms = 0;
     for (int di = 0; di < nd; ++di) {
-      sum += diag_weight32<ORDER, Q, X, V, HE>(a, T, D + di, k, gpass, gterms, fallback);
+      sum += diag_weight32<ORDER, Q, X, V, HE>(a, T, D + di, Ls, k, gpass, gterms, fallback);
       if (fallback) return 0.0;  // the whole sample is re-evaluated in fp64
     }
     npass += gpass;
     nterms += gterms;
   } else {
-    sum = diag_weight32<ORDER, Q, X, V, HE>(a, T, D, k, npass, nterms, fallback);
+    constexpr bool CY = cycle_form<ORDER, Q, false, X, false>();
+    sum = diag_weight32<ORDER, Q, X, V, HE, CY>(a, T, D, Ls, k, npass, nterms, fallback);
     if (fallback) return 0.0;
   }
   return jac * (x0p * x0p) * jc * sum;
@@ -996,6 +1152,13 @@ __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__r
   return w;
 }
 
+// Bytes of the label-cycle table a sample or dump kernel of mode P holds in LDS.
+template <int ORDER, int Q, int P, bool X>
+constexpr size_t cycle_lds_bytes() {
+  return cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>() ? cycle_table_bytes<ORDER>()
+                                                                    : 0;
+}
+
 // HF spline tables held in LDS in mode P
 template <int Q, int P>
 constexpr int lds_tables() {
@@ -1026,6 +1189,13 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
     const double e0 = ge[m * (nb + 1) + b], e1 = ge[m * (nb + 1) + b + 1];
     g[i] = make_double2(fma(e1 - e0, 0x1p-33, e0), e1 - e0);
     h[i] = 0.0;
+  }
+  // label-cycle table after the reduction scratch and the re-evaluation queue
+  if constexpr (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>()) {
+    CycWord<ORDER> *tab = reinterpret_cast<CycWord<ORDER> *>(
+        reinterpret_cast<uint32_t *>(red + 6 * (bs >> 6)) + 128 * (bs >> 6));
+    build_cycle_table<ORDER>(D, tab);
+    Ls.cyc = tab;
   }
   __syncthreads();
 
@@ -1283,6 +1453,11 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
     const int m = i / nb, b = i - m * nb;
     const double e0 = ge[m * (nb + 1) + b], e1 = ge[m * (nb + 1) + b + 1];
     g[i] = make_double2(fma(e1 - e0, 0x1p-33, e0), e1 - e0);
+  }
+  if constexpr (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>()) {
+    CycWord<ORDER> *tab = reinterpret_cast<CycWord<ORDER> *>(g + ND * nb);
+    build_cycle_table<ORDER>(D, tab);
+    Ls.cyc = tab;
   }
   __syncthreads();
   const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -52,7 +52,8 @@ hipError_t launch_single_oq<O, Q>(const KArgs &a, int t, int prec, bool group, i
     constexpr int P = decltype(p)::value;
     constexpr bool X = decltype(x)::value;
     constexpr int HE = decltype(h)::value;
-    const size_t lds = sample_lds_bytes(3 * (O + 1), a.phys.nb, block, lds_tables<Q, P>());
+    const size_t lds = sample_lds_bytes(3 * (O + 1), a.phys.nb, block, lds_tables<Q, P>()) +
+                       cycle_lds_bytes<O, Q, P, X>();
     hipLaunchKernelGGL((sample_single<O, Q, P, X, HE>), dim3(nitems), dim3(block), lds, st, a, t);
     return hipGetLastError();
   });
@@ -65,7 +66,8 @@ hipError_t launch_order_oq<O, Q>(const KArgs &a, int prec, bool group, int k0, i
     constexpr int P = decltype(p)::value;
     constexpr bool X = decltype(x)::value;
     constexpr int HE = decltype(h)::value;
-    const size_t lds = sample_lds_bytes(3 * (O + 1), a.phys.nb, block, lds_tables<Q, P>());
+    const size_t lds = sample_lds_bytes(3 * (O + 1), a.phys.nb, block, lds_tables<Q, P>()) +
+                       cycle_lds_bytes<O, Q, P, X>();
     hipLaunchKernelGGL((sample_order<O, Q, P, X, HE>), dim3(grid), dim3(block), lds, st, a, k0,
                        k1);
     return hipGetLastError();
@@ -85,7 +87,8 @@ hipError_t launch_dump_oq<O, Q>(const KArgs &a, int t, int prec, bool group, uin
     const int block = 256;
     const dim3 grid(static_cast<unsigned>((count + block - 1) / block));
     const size_t lds = fixed_lds_bytes() + hf_lds_doubles(lds_tables<Q, P>()) * sizeof(double) +
-                       2 * static_cast<size_t>(3 * (O + 1)) * a.phys.nb * sizeof(double);
+                       2 * static_cast<size_t>(3 * (O + 1)) * a.phys.nb * sizeof(double) +
+                       cycle_lds_bytes<O, Q, P, X>();
     hipLaunchKernelGGL((dump_samples<O, Q, P, X, HE>), grid, dim3(block), lds, st, a, t, iter,
                        first, count, out, out_reg);
     return hipGetLastError();

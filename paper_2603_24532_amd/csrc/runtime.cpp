@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -335,10 +336,30 @@ bool fixed_masks_ok() {
 // Appends one diagram's label tables.  group_base / term_base / coef_base
 // are the device element indices at which the three vectors start, so the
 // offsets stored in the descriptor are absolute for the kernel's table bases.
-void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
+bool append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
                          std::vector<TermDev> &terms, std::vector<double> &coefs,
                          size_t group_base, size_t term_base, size_t coef_base, bool canonical) {
   const LabelTables lt = label_tables(d, q, canonical);
+  // label cycles (the nuclear-matter kernels sum over vertex-term choices
+  // with them); checked once per diagram against the configuration tables
+  const CycleTables ct = cycle_tables(d, canonical);
+  if (ct.masks.size() > static_cast<size_t>(kMaxCycles) || ct.of_e.size() > 32) return false;
+  dd.ncyc = static_cast<int>(ct.masks.size());
+  for (size_t k = 0; k < ct.masks.size(); ++k) dd.cyc_mask[k] = ct.masks[k];
+  for (size_t E = 0; E < ct.of_e.size(); ++E) {
+    const uint64_t n = static_cast<uint64_t>(ct.n_of_e[E]);
+    dd.cyc_e[E] = ct.of_e[E] | n << 56;
+    dd.cyc_e32[E] = ct.masks.size() <= 24 ? static_cast<uint32_t>(ct.of_e[E] | n << 24) : 0u;
+  }
+  {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, bool>, bool> checked;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(d.order, d.id, q, canonical);
+    auto it = checked.find(key);
+    if (it == checked.end()) it = checked.emplace(key, cycles_match_label_tables(d, q, canonical)).first;
+    if (!it->second) return false;
+  }
   dd.group_off = static_cast<int>(group_base + groups.size());
   dd.ngroups = static_cast<int>(lt.groups.size());
   dd.term_off = static_cast<int>(term_base + terms.size());
@@ -364,6 +385,7 @@ void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<Group
     tm.multf = static_cast<float>(t.mult);
     terms.push_back(tm);
   }
+  return true;
 }
 
 // Medium-dependent task fields: Fermi momenta, loop radii, 1/density, bands.
@@ -462,11 +484,20 @@ int compile_tables(mbpt_task_set *set) {
         dd.nloops = d->nloops;
         dd.ncuts = d->ncuts;
         fill_diag_dev(*d, dd, td.group != 0);
-        append_label_tables(*d, q, dd, set->groups, set->terms, set->coefs, 0, 0, 0, td.group != 0);
+        if (!append_label_tables(*d, q, dd, set->groups, set->terms, set->coefs, 0, 0, 0,
+                                 td.group != 0)) {
+          set_err(ctx, "create_task_set: label cycle tables disagree with the label tables");
+          return MBPT_EINVAL;
+        }
         set->diags.push_back(dd);
         FlopModel fm;
         count_flops(*d, q, ctx->v.reg_exp / 2, ctx->desc.label_mode, ctx->desc.spectrum, fm);
-        fm.all_units = ctx->desc.label_mode ? dd.nterms : dd.ngroups;
+        // the nuclear-matter factorised label sum of a single diagram with the
+        // free spectrum is the cycle form: one polynomial per passing sample
+        fm.all_units = ctx->desc.label_mode ? dd.nterms
+                       : (q == 4 && !td.group && ctx->desc.spectrum == MBPT_SPECTRUM_FREE)
+                           ? 1
+                           : dd.ngroups;
         // a group shares the map and loop momenta; its pass and label-unit
         // counters add up over members, so post and per_term are averages
         e.fm.pre += i == 0 ? fm.pre : fm.pre - fm.shared;
@@ -1532,7 +1563,10 @@ extern "C" int mbpt_diagram_flops(int order, int id, int matter, int label_mode,
   if (pre) *pre = f.pre;
   if (post) *post = f.post;
   if (per_unit) *per_unit = f.per_term;
-  if (units) *units = static_cast<double>(label_mode ? lt.terms.size() : lt.groups.size());
+  if (units)
+    *units = static_cast<double>(label_mode ? lt.terms.size()
+                                 : (q == 4 && spectrum == MBPT_SPECTRUM_FREE) ? 1
+                                                                              : lt.groups.size());
   return MBPT_OK;
 }
 

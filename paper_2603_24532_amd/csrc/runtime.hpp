@@ -106,7 +106,7 @@ void set_err(mbpt_context *ctx, const std::string &msg);
 int hip_fail(mbpt_context *ctx, hipError_t e, const char *what);
 void count_flops(const Diagram &d, int q, int half_exp, int label_mode, int spectrum,
                  FlopModel &f);
-void append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
+bool append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<GroupDev> &groups,
                          std::vector<TermDev> &terms, std::vector<double> &coefs,
                          size_t group_base, size_t term_base, size_t coef_base,
                          bool canonical = false);

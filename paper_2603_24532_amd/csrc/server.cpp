@@ -183,6 +183,7 @@ struct mbpt_server {
     std::vector<double> coefs;
     FlopModel fm;
     size_t bytes;  // arena bytes of the three tables
+    bool valid;    // label cycle tables agree with the configuration tables
   };
   std::map<std::pair<int, int>, Compiled> compiled;
   // pinned staging (see kStageBytes) and its fill level within a step
@@ -287,9 +288,9 @@ const mbpt_server::Compiled &compiled_of(mbpt_server *s, int order, int id) {
   c.dd.nloops = d->nloops;
   c.dd.ncuts = d->ncuts;
   fill_diag_dev(*d, c.dd);
-  append_label_tables(*d, 4, c.dd, c.groups, c.terms, c.coefs, 0, 0, 0);
+  c.valid = append_label_tables(*d, 4, c.dd, c.groups, c.terms, c.coefs, 0, 0, 0);
   count_flops(*d, 4, s->ctx->v.reg_exp / 2, s->ctx->desc.label_mode, MBPT_SPECTRUM_FREE, c.fm);
-  c.fm.all_units = s->ctx->desc.label_mode ? c.dd.nterms : c.dd.ngroups;
+  c.fm.all_units = s->ctx->desc.label_mode ? c.dd.nterms : 1;  // cycle form
   c.bytes = a256(c.groups.size() * sizeof(GroupDev)) + a256(c.terms.size() * sizeof(TermDev)) +
             a256(c.coefs.size() * sizeof(double));
   return s->compiled.emplace(key, std::move(c)).first->second;
@@ -492,6 +493,10 @@ extern "C" int mbpt_server_submit(mbpt_server *s, const mbpt_request *req, uint6
   if (static_cast<int>(s->queue.size()) >= s->max_queue) {
     set_err(ctx, "server_submit: queue full");
     return MBPT_EBUSY;
+  }
+  if (!compiled_of(s, req->order, req->diagram_id).valid) {
+    set_err(ctx, "server_submit: label cycle tables disagree with the label tables");
+    return MBPT_EINVAL;
   }
   if (compiled_of(s, req->order, req->diagram_id).bytes > kTermBytesPerSlot) {
     set_err(ctx, "server_submit: diagram label tables exceed the per-slot table arena");

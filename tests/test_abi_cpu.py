@@ -340,5 +340,11 @@ def test_flop_model_units_match_label_statistics(M):
     for order, did in ((2, 0), (3, 1), (4, 17), (5, 400)):
         for matter in (M.MBPT_NEUTRON, M.MBPT_NUCLEAR):
             _, n_iso, n_terms = M.mbpt_diagram_label_stats(order, did, matter)
-            assert M.mbpt_diagram_flops(order, did, matter)["units"] == n_iso
+            # neutron matter: one isospin configuration; nuclear matter with
+            # the free spectrum: the cycle form, one polynomial per sample;
+            # with the HF spectrum every configuration has its own
+            # denominators
+            nuclear = matter == M.MBPT_NUCLEAR
+            assert M.mbpt_diagram_flops(order, did, matter)["units"] == (1 if nuclear else n_iso)
+            assert M.mbpt_diagram_flops(order, did, matter, spectrum=1)["units"] == n_iso
             assert M.mbpt_diagram_flops(order, did, matter, label_mode=1)["units"] == n_terms
