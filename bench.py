@@ -108,6 +108,8 @@ def parse():
                     help="nuclear4 alone: the order of the diagrams (4 in the headline)")
     ap.add_argument("--stride", type=int, default=1,
                     help="nuclear4 alone: every stride-th diagram of the order")
+    ap.add_argument("--launch", default="batched", choices=["batched", "persistent"],
+                    help="nuclear4 alone: one block per work item (batched) or persistent blocks")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device three times "
                          "(reference dispatch for rocprofv3 byte counters)")
@@ -257,8 +259,9 @@ def nuclear4(args, M, stream, precisions=("fp32", "fp64"), extras=True):
     for p in precisions:
         log(f"[nuclear4] {p}: {len(tasks)} tasks, {args.warmup} + {args.steps} iterations "
             f"x 2^{args.samples_log2}")
+        mode = M.MBPT_LAUNCH_PERSISTENT if args.launch == "persistent" else M.MBPT_LAUNCH_BATCHED
         legs[p] = run_set(M, tasks, N, args.steps, args.warmup, stream,
-                          precision=1 if p == "fp32" else 0, mode=M.MBPT_LAUNCH_BATCHED)
+                          precision=1 if p == "fp32" else 0, mode=mode)
         log(f"[nuclear4] {p}: {_rate(legs[p]):.2f} Gevals/s")
     if not extras:
         return tasks, legs
@@ -269,6 +272,9 @@ def nuclear4(args, M, stream, precisions=("fp32", "fp64"), extras=True):
     log("[nuclear4] fp32 graph-captured")
     legs["graph_fp32"] = run_set(M, tasks, N, few, 1, stream, precision=1,
                                  mode=M.MBPT_LAUNCH_GRAPH)
+    log("[nuclear4] fp32 persistent blocks")
+    legs["persistent_fp32"] = run_set(M, tasks, N, few, 1, stream, precision=1,
+                                      mode=M.MBPT_LAUNCH_PERSISTENT)
     return tasks, legs
 
 
@@ -294,14 +300,17 @@ def batched(args, M, stream):
     """Orders 2 + 3 (pp, hh, ph) x 9 neutron-matter densities = 36 tasks,
     2^26 samples per iteration per task, 10 iterations: the plain
     one-diagram-per-launch fp64 path, and fp64 / fp32 with one launch per order
-    per iteration (graph-captured, autotuned work decomposition)."""
+    per iteration (graph-captured, autotuned work decomposition), and with one
+    persistent launch per order per iteration."""
     N, iters = 1 << 26, 10
     tasks = [(o, d, M.MBPT_NEUTRON, n, 0.0, 1000 * o + 100 * d + i)
              for (o, d) in ((2, 0), (3, 0), (3, 1), (3, 2)) for i, n in enumerate(DENSITIES_PNM)]
     out = {}
     for label, prec, mode in (("plain_fp64", 0, M.MBPT_LAUNCH_PER_TASK),
                               ("batched_fp64", 0, M.MBPT_LAUNCH_GRAPH),
-                              ("batched_fp32", 1, M.MBPT_LAUNCH_GRAPH)):
+                              ("batched_fp32", 1, M.MBPT_LAUNCH_GRAPH),
+                              ("persistent_fp64", 0, M.MBPT_LAUNCH_PERSISTENT),
+                              ("persistent_fp32", 1, M.MBPT_LAUNCH_PERSISTENT)):
         plain = mode == M.MBPT_LAUNCH_PER_TASK
         r = run_set(M, tasks, N, iters, 1, stream, precision=prec, mode=mode,
                     blocking=(256, 16) if plain else (64, 4), autotune=not plain)
@@ -316,6 +325,8 @@ def batched(args, M, stream):
         log(f"[batched] {label}: {out[label]['Gevals_per_s']:.2f} Gevals/s")
     e64, e32 = out.pop("batched_fp64_E"), out.pop("batched_fp32_E")
     out.pop("plain_fp64_E")
+    out.pop("persistent_fp64_E")
+    out.pop("persistent_fp32_E")
     out["fp32_vs_fp64_same_streams_z"] = _zstats(e32, e64)
     out["speedup_fp32_vs_plain_fp64"] = (out["batched_fp32"]["Gevals_per_s"] /
                                          out["plain_fp64"]["Gevals_per_s"])
@@ -613,6 +624,7 @@ def headline(args, M, stream):
                  "time_to_1pct_sigma": f64["clock"]},
         "plain_fp64_one_launch_per_task": {"value": _rate(legs["plain_fp64"]), "unit": "Gevals/s"},
         "graph_fp32": {"value": _rate(legs["graph_fp32"]), "unit": "Gevals/s"},
+        "persistent_fp32": {"value": _rate(legs["persistent_fp32"]), "unit": "Gevals/s"},
         "vs_plain_fp64": value / _rate(legs["plain_fp64"]),
         "fp32_vs_fp64_same_streams_z": _zstats(f32["per"], f64["per"]),
         "chi2_dof": {"fp32": _chi2(f32["per"]), "fp64": _chi2(f64["per"])},

@@ -58,11 +58,21 @@ enum { MBPT_FP64 = 0, MBPT_FP32 = 1 };
 enum { MBPT_NEUTRON = 0, MBPT_NUCLEAR = 1 };
 /* How mbpt_integrate launches work.  PER_TASK: one sample launch per task and
  * iteration (the plain path; within an iteration the tasks in turn, then one
- * iteration-end launch for all of them); BATCHED: one persistent launch per iteration
- * covering every task of the set; GRAPH: BATCHED with the whole iteration
+ * iteration-end launch for all of them); BATCHED: per iteration one sample launch
+ * per order present, each covering the work items of every task of that order
+ * (one block per work item), then one iteration-end launch; GRAPH: BATCHED with the whole iteration
  * sequence captured once into a HIP graph and replayed (needs a non-default
- * stream: EINVAL on the null stream). */
-enum { MBPT_LAUNCH_PER_TASK = 0, MBPT_LAUNCH_BATCHED = 1, MBPT_LAUNCH_GRAPH = 2 };
+ * stream: EINVAL on the null stream); PERSISTENT: per iteration one
+ * persistent launch per order present (about as many blocks as are resident
+ * at once; each claims chunks of work items from a counter, keeps the current
+ * task's grid and histogram in LDS across its items and merges the histogram
+ * once per run of a task's items), then the iteration-end launch. */
+enum {
+  MBPT_LAUNCH_PER_TASK = 0,
+  MBPT_LAUNCH_BATCHED = 1,
+  MBPT_LAUNCH_GRAPH = 2,
+  MBPT_LAUNCH_PERSISTENT = 3
+};
 /* Single-particle energies in the energy denominators (eq:Dijkabc).  FREE:
  * eps = hbar^2 k^2 / 2m.  HF: the Hartree-Fock spectrum of eq:spe,
  * eps_tau(k) = hbar^2 k^2 / 2m + Sigma_tau(k) with Sigma_tau(k) the sum over
@@ -352,6 +362,21 @@ int mbpt_regularized_log(mbpt_task_set *set, int task, double *I, double *var, i
  * the fit is singular. */
 int mbpt_regularized(mbpt_task_set *set, int task, int skip_iters, double *E, double *sigma,
                      double *E0, double *sigma0);
+/* One-shot batch over many (diagram, EOS point) tasks: a task set of the n
+ * tasks is created, bound to the caller's device workspace (bytes from
+ * mbpt_batch_workspace_query for the same tasks, samples and iterations),
+ * integrated from uniform grids for `iters` iterations of samples_per_iter
+ * samples each with one sample launch per order per iteration (BATCHED), and
+ * destroyed.  out[n] receives the per-task results (may be NULL), *total their
+ * sum (may be NULL).  The workspace is borrowed for the call only.  The tasks
+ * must share one matter (EINVAL otherwise); other errors as
+ * mbpt_create_task_set, mbpt_bind_workspace and mbpt_integrate. */
+int mbpt_batch_workspace_query(mbpt_context *ctx, const mbpt_task_desc *tasks, int n_tasks,
+                               uint64_t samples_per_iter, int iters, size_t *bytes);
+int mbpt_integrate_batch(mbpt_context *ctx, const mbpt_task_desc *tasks, int n_tasks,
+                         uint64_t samples_per_iter, int iters, void *device_ptr, size_t bytes,
+                         mbpt_result *out, mbpt_result *total);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): mbpt_integrate
  * on a set that has no workspace bound, with the set's device state held in a

@@ -17,7 +17,7 @@ MBPT_OK, MBPT_EINVAL, MBPT_ENOMEM, MBPT_EHIP, MBPT_ENUMERIC, MBPT_EBUSY, MBPT_ES
     0, -1, -2, -3, -4, -5, -6)
 MBPT_FP64, MBPT_FP32 = 0, 1
 MBPT_NEUTRON, MBPT_NUCLEAR = 0, 1
-MBPT_LAUNCH_PER_TASK, MBPT_LAUNCH_BATCHED, MBPT_LAUNCH_GRAPH = 0, 1, 2
+MBPT_LAUNCH_PER_TASK, MBPT_LAUNCH_BATCHED, MBPT_LAUNCH_GRAPH, MBPT_LAUNCH_PERSISTENT = 0, 1, 2, 3
 MBPT_SPECTRUM_FREE, MBPT_SPECTRUM_HF = 0, 1
 HF_ENTRIES = 513  # spline nodes of an HF table
 
@@ -35,6 +35,7 @@ EXPORTED = [
     "mbpt_server_destroy", "mbpt_server_submit", "mbpt_server_step", "mbpt_server_poll",
     "mbpt_set_regularization", "mbpt_dump_samples_reg", "mbpt_regularized_log",
     "mbpt_regularized", "mbpt_diagram_flops", "mbpt_integrate_noalloc",
+    "mbpt_batch_workspace_query", "mbpt_integrate_batch",
 ]
 
 
@@ -140,6 +141,12 @@ def lib():
         "mbpt_reset": [_P],
         "mbpt_integrate": [_P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(mbpt_result),
                            ctypes.POINTER(mbpt_result)],
+        "mbpt_batch_workspace_query": [_P, ctypes.POINTER(mbpt_task_desc), ctypes.c_int,
+                                       ctypes.c_uint64, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_size_t)],
+        "mbpt_integrate_batch": [_P, ctypes.POINTER(mbpt_task_desc), ctypes.c_int, ctypes.c_uint64,
+                                 ctypes.c_int, _P, ctypes.c_size_t, ctypes.POINTER(mbpt_result),
+                                 ctypes.POINTER(mbpt_result)],
         "mbpt_integrate_noalloc": [_P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(mbpt_result),
                            ctypes.POINTER(mbpt_result)],
         "mbpt_iteration_log": [_P, ctypes.c_int, _DP, _DP, ctypes.c_int, _IP],
@@ -385,6 +392,26 @@ def mbpt_integrate(s, samples_per_iter, iters):
     tot = mbpt_result()
     _check(lib().mbpt_integrate(s, samples_per_iter, iters, per, ctypes.byref(tot)),
            _ctx_of_set(s))
+    return list(per), tot
+
+
+def _task_array(tasks):
+    return (mbpt_task_desc * len(tasks))(*[mbpt_task_desc(*t) for t in tasks])
+
+
+def mbpt_batch_workspace_query(ctx, tasks, samples_per_iter, iters):
+    b = ctypes.c_size_t()
+    _check(lib().mbpt_batch_workspace_query(ctx, _task_array(tasks), len(tasks), samples_per_iter,
+                                            iters, ctypes.byref(b)), ctx)
+    return b.value
+
+
+def mbpt_integrate_batch(ctx, tasks, samples_per_iter, iters, device_ptr, nbytes):
+    """One-shot batch: (per-task results list, total result)."""
+    per = (mbpt_result * len(tasks))()
+    tot = mbpt_result()
+    _check(lib().mbpt_integrate_batch(ctx, _task_array(tasks), len(tasks), samples_per_iter, iters,
+                                      device_ptr, nbytes, per, ctypes.byref(tot)), ctx)
     return list(per), tot
 
 

@@ -192,6 +192,11 @@ struct alignas(16) TaskDev {
   uint64_t nevals, nfallback, npass, nterms;
 };
 
+// Work-item counters of the persistent launches, one per order (index 1..5),
+// and the blocks per compute unit such a launch starts.
+constexpr int kQueueSlots = 8;
+constexpr int kPersistentBlocksPerCu = 16;
+
 // Per work item counters: fp64 fallbacks, samples past the Pauli test, label
 // terms evaluated.
 constexpr int kItemCounters = 3;
@@ -211,6 +216,7 @@ struct KArgs {
   double *hf;             // HF spline entries, 4 doubles each
   double *cpart;          // per item: 2 kMaxReg component sums (regularised modes)
   double *creslog;        // per logged iteration: kMaxReg (I, var) pairs
+  int *queue;             // per order: work-item counter of the persistent launches (may be null)
   double reg_eta;         // component k + 1 shifts every denominator by -(k + 1) reg_eta
   int nreg;               // components (0: none)
   int pad_reg;

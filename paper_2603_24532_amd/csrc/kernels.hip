@@ -133,6 +133,8 @@ __global__ __launch_bounds__(kFinishThreads) void finish_iteration(KArgs a, int 
   extern __shared__ double scratch[];
   const int t = first_task + blockIdx.x;
   TaskDev *T = a.tasks + t;
+  // the persistent launches of the next iteration claim items from zero
+  if (a.queue && blockIdx.x == 0 && threadIdx.x < kQueueSlots) a.queue[threadIdx.x] = 0;
   if (!T->active || T->plan <= step_iter) return;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int it0 = T->store_begin, it1 = T->store_begin + T->nitems;
@@ -367,6 +369,7 @@ __global__ void hf_spline(KArgs a, int first, int ntasks, int ntab) {
 __global__ void init_tasks(KArgs a, int first, int keep_grid) {
   TaskDev *T = a.tasks + first + blockIdx.x;
   const int nb = a.phys.nb;
+  if (a.queue && blockIdx.x == 0 && threadIdx.x < kQueueSlots) a.queue[threadIdx.x] = 0;
   if (!keep_grid) {
     for (int i = threadIdx.x; i < T->nd * (nb + 1); i += blockDim.x) {
       const int b = i % (nb + 1);
@@ -422,6 +425,13 @@ hipError_t launch_sample_single(const KArgs &a, int t, int order, int q, int pre
 hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, bool group, int k0,
                                int k1, int nitems, int block, hipStream_t st) {
 #define MBPT_CALL(O, Q) launch_order_oq<O, Q>(a, prec, group, k0, k1, nitems, block, st)
+  MBPT_OQ_SWITCH(MBPT_CALL)
+#undef MBPT_CALL
+}
+
+hipError_t launch_sample_persistent(const KArgs &a, int order, int q, int prec, bool group, int k0,
+                                    int k1, int nitems, int block, int cus, hipStream_t st) {
+#define MBPT_CALL(O, Q) launch_persist_oq<O, Q>(a, prec, group, k0, k1, nitems, block, cus, st)
   MBPT_OQ_SWITCH(MBPT_CALL)
 #undef MBPT_CALL
 }

@@ -14,6 +14,11 @@ hipError_t launch_sample_single(const KArgs &a, int task, int order, int q, int 
 // Items [olist[k0].x, olist[k0].x + nitems) of the tasks listed in olist[k0, k1).
 hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, bool group, int k0,
                                int k1, int nitems, int block, hipStream_t st);
+// The same items with a persistent grid (about as many blocks as are resident
+// at once on `cus` compute units) claiming chunks of items from the order's
+// counter a.queue[order] (zero at launch).
+hipError_t launch_sample_persistent(const KArgs &a, int order, int q, int prec, bool group, int k0,
+                                    int k1, int nitems, int block, int cus, hipStream_t st);
 // Iteration end of tasks [first_task, first_task + ntasks) that take part in
 // iteration step_iter of the current launch sequence (plan > step_iter).
 hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_iter, double alpha,
@@ -41,6 +46,9 @@ template <int ORDER, int Q>
 hipError_t launch_order_oq(const KArgs &a, int prec, bool group, int k0, int k1, int grid,
                            int block, hipStream_t st);
 template <int ORDER, int Q>
+hipError_t launch_persist_oq(const KArgs &a, int prec, bool group, int k0, int k1, int nitems,
+                             int block, int cus, hipStream_t st);
+template <int ORDER, int Q>
 hipError_t launch_dump_oq(const KArgs &a, int t, int prec, bool group, uint32_t iter,
                           uint64_t first, uint64_t count, double *out, double *out_reg,
                           hipStream_t st);
@@ -49,6 +57,9 @@ hipError_t launch_dump_oq(const KArgs &a, int t, int prec, bool group, uint32_t 
   hipError_t launch_single_oq<O, Q>(const KArgs &, int, int, bool, int, int, hipStream_t);      \
   template <>                                                                                   \
   hipError_t launch_order_oq<O, Q>(const KArgs &, int, bool, int, int, int, int, hipStream_t);  \
+  template <>                                                                                   \
+  hipError_t launch_persist_oq<O, Q>(const KArgs &, int, bool, int, int, int, int, int,         \
+                                     hipStream_t);                                              \
   template <>                                                                                   \
   hipError_t launch_dump_oq<O, Q>(const KArgs &, int, int, bool, uint32_t, uint64_t, uint64_t,  \
                                   double *, double *, hipStream_t);

@@ -1169,35 +1169,89 @@ constexpr int lds_tables() {
 // Work item: blockDim.x * spt consecutive samples of one task (HE: the
 // regulator exponent's half fixed at compile time, or 0, see reg_pow)
 
+// LDS of a sample block: turn and 2^(j/64) tables, HF tables, grid (e, width)
+// pairs, histogram, reduction scratch, fp64 re-evaluation queue (128 sample
+// offsets per wavefront), label-cycle table.
+struct BlockLds {
+  SampleLds Ls;
+  double2 *g;
+  double *h;
+  double *red;
+};
+
+// Carves the block's LDS and loads the task-independent tables.
+template <int ORDER, int Q, int P, bool X>
+__device__ __forceinline__ void block_lds(const KArgs &a, double *smem, BlockLds &B) {
+  constexpr int ND = 3 * (ORDER + 1);
+  constexpr int ntab = lds_tables<Q, P>();
+  SinCos *turn = reinterpret_cast<SinCos *>(smem);
+  double *ex = reinterpret_cast<double *>(turn + kTurnEntries);
+  double *hf = ex + kExp2Entries;
+  B.g = reinterpret_cast<double2 *>(hf + hf_lds_doubles(ntab));
+  B.h = reinterpret_cast<double *>(B.g + ND * a.phys.nb);
+  B.red = B.h + ND * a.phys.nb;
+  const int nw = blockDim.x >> 6;
+  B.Ls.turn = turn;
+  B.Ls.ex = ex;
+  B.Ls.hf = ntab ? hf : nullptr;
+  B.Ls.g = B.g;
+  B.Ls.cyc = cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>()
+                 ? reinterpret_cast<uint32_t *>(B.red + 6 * nw) + 128 * nw
+                 : nullptr;
+  load_turn_table(turn, ex);
+}
+
+// Loads task t's tables into the block's LDS: HF spline entries, grid pairs
+// (e_b + w_b 2^-33, w_b), a zeroed histogram and the label-cycle table of its
+// diagram.  The caller synchronises before and after.
+template <int ORDER, int Q, int P, bool X>
+__device__ __forceinline__ void task_lds(const KArgs &a, int t, BlockLds &B) {
+  constexpr int ND = 3 * (ORDER + 1);
+  constexpr int ntab = lds_tables<Q, P>();
+  const TaskDev *__restrict__ T = a.tasks + t;
+  const int nb = a.phys.nb;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  if constexpr (ntab > 0) {
+    double *hf = const_cast<double *>(B.Ls.hf);
+    const double *src = a.hf + 4 * static_cast<size_t>(T->hf_off);
+    const int n = static_cast<int>(hf_lds_doubles(ntab));
+    for (int i = tid; i < n; i += bs) hf[i] = src[i];
+  }
+  const double *ge = a.grids + T->grid_off;
+  for (int i = tid; i < ND * nb; i += bs) {
+    const int m = i / nb, b = i - m * nb;
+    const double e0 = ge[m * (nb + 1) + b], e1 = ge[m * (nb + 1) + b + 1];
+    B.g[i] = make_double2(fma(e1 - e0, 0x1p-33, e0), e1 - e0);
+    B.h[i] = 0.0;
+  }
+  if constexpr (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>())
+    build_cycle_table<ORDER>(a.diags + T->diag,
+                             static_cast<CycWord<ORDER> *>(const_cast<void *>(B.Ls.cyc)));
+}
+
+// Adds the block's LDS histogram of task t to the task's histogram.
+template <int ORDER>
+__device__ __forceinline__ void hist_flush(const KArgs &a, int t, const double *h) {
+  constexpr int ND = 3 * (ORDER + 1);
+  double *hg = a.hists + a.tasks[t].hist_off;
+  for (int i = threadIdx.x; i < ND * a.phys.nb; i += blockDim.x) {
+    const double v = h[i];
+    if (v != 0.0) atomicAdd(&hg[i], v);
+  }
+}
+
+// The samples of one work item of task t (the task's tables in LDS): sums,
+// histogram entries (LDS), and the item's partial sums and counters.
 template <int ORDER, int Q, int P, bool X, int HE>
-__device__ __forceinline__ void process_item(const KArgs &a, int t, int item, double *smem) {
+__device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, const BlockLds &B) {
   constexpr int ND = 3 * (ORDER + 1);
   const TaskDev *__restrict__ T = a.tasks + t;
   const DiagDev *__restrict__ D = a.diags + T->diag;
   const int nb = a.phys.nb;
   const int tid = threadIdx.x, bs = blockDim.x;
-  // LDS: turn table, HF tables, grid (e, width) pairs, histogram, reduction
-  // scratch
-  __syncthreads();  // previous item done with LDS
-  SampleLds Ls;
-  double2 *g;
-  double *h = carve_lds(a, T, lds_tables<Q, P>(), ND, smem, Ls, g);
-  double *red = h + ND * nb;
-  const double *ge = a.grids + T->grid_off;
-  for (int i = tid; i < ND * nb; i += bs) {
-    const int m = i / nb, b = i - m * nb;
-    const double e0 = ge[m * (nb + 1) + b], e1 = ge[m * (nb + 1) + b + 1];
-    g[i] = make_double2(fma(e1 - e0, 0x1p-33, e0), e1 - e0);
-    h[i] = 0.0;
-  }
-  // label-cycle table after the reduction scratch and the re-evaluation queue
-  if constexpr (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>()) {
-    CycWord<ORDER> *tab = reinterpret_cast<CycWord<ORDER> *>(
-        reinterpret_cast<uint32_t *>(red + 6 * (bs >> 6)) + 128 * (bs >> 6));
-    build_cycle_table<ORDER>(D, tab);
-    Ls.cyc = tab;
-  }
-  __syncthreads();
+  const SampleLds &Ls = B.Ls;
+  double *h = B.h;
+  double *red = B.red;
 
   const uint64_t N = T->nsamples;
   const uint32_t iter = T->iter;
@@ -1366,12 +1420,18 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
       }
     }
   }
+}
+
+// One work item with its own setup and histogram merge.
+template <int ORDER, int Q, int P, bool X, int HE>
+__device__ __forceinline__ void process_item(const KArgs &a, int t, int item, double *smem) {
+  BlockLds B;
+  block_lds<ORDER, Q, P, X>(a, smem, B);
+  task_lds<ORDER, Q, P, X>(a, t, B);
   __syncthreads();
-  double *hg = a.hists + T->hist_off;
-  for (int i = tid; i < ND * nb; i += bs) {
-    const double v = h[i];
-    if (v != 0.0) atomicAdd(&hg[i], v);
-  }
+  item_samples<ORDER, Q, P, X, HE>(a, t, item, B);
+  __syncthreads();
+  hist_flush<ORDER>(a, t, B.h);
 }
 
 // Waves per SIMD the sample kernels ask the compiler for (it then holds them
@@ -1429,6 +1489,56 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_ord
     else hi = mid - 1;
   }
   process_item<ORDER, Q, P, X, HE>(a, ol[lo].y, item, smem);
+}
+
+// Persistent launch over the work items of the tasks of one order (as
+// sample_order, nitems items from olist[k0].x on): a grid of about as many
+// blocks as are resident on the device at once; each block claims chunks of
+// `chunk` consecutive items from the order's counter a.queue[ORDER] until all
+// are taken.  Claims ascend, so a block meets the tasks in ascending order:
+// it keeps the current task's grid, histogram and label-cycle table in LDS
+// across that task's items and merges the histogram into the task's once per
+// run of items (instead of once per item).  The counter starts at zero (task
+// set initialisation) and the iteration end zeroes it for the next iteration.
+template <int ORDER, int Q, int P, bool X, int HE>
+__global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_persistent(
+    KArgs a, int k0, int k1, int nitems, int chunk) {
+  extern __shared__ double smem[];
+  __shared__ int claim;
+  const int2 *__restrict__ ol = a.olist;
+  const int first = ol[k0].x;
+  BlockLds B;
+  block_lds<ORDER, Q, P, X>(a, smem, B);
+  int cur = -1, lo = k0;
+  for (;;) {
+    __syncthreads();  // every thread has read the previous claim
+    if (threadIdx.x == 0) claim = atomicAdd(a.queue + ORDER, chunk);
+    __syncthreads();
+    const int c0 = claim;
+    if (c0 >= nitems) break;
+    const int c1 = min(c0 + chunk, nitems);
+    for (int k = c0; k < c1; ++k) {
+      const int item = first + k;
+      while (lo + 1 < k1 && ol[lo + 1].x <= item) ++lo;
+      const int t = ol[lo].y;
+      __syncthreads();  // the previous item's reduction scratch has been read
+      if (t != cur) {
+        if (cur >= 0) hist_flush<ORDER>(a, cur, B.h);
+        __syncthreads();
+        task_lds<ORDER, Q, P, X>(a, t, B);
+        __syncthreads();
+        cur = t;
+      }
+      // opaque to the optimiser: nothing of one item's evaluation is kept
+      // live into the next (the body then has the registers of a one-item
+      // kernel)
+      int tt = t, ii = item;
+      asm volatile("" : "+s"(tt), "+s"(ii));
+      item_samples<ORDER, Q, P, X, HE>(a, tt, ii, B);
+    }
+  }
+  __syncthreads();
+  if (cur >= 0) hist_flush<ORDER>(a, cur, B.h);
 }
 
 // ---------------------------------------------------------------------------

@@ -5,6 +5,8 @@
 // parallel; kernels.hip dispatches to the launchers defined here.
 #include "kernels_dev.hpp"
 
+#include <algorithm>
+
 #if !defined(MBPT_INST_ORDER) || !defined(MBPT_INST_Q)
 #error "compile with -DMBPT_INST_ORDER=<order> -DMBPT_INST_Q=<2|4>"
 #endif
@@ -70,6 +72,29 @@ hipError_t launch_order_oq<O, Q>(const KArgs &a, int prec, bool group, int k0, i
                        cycle_lds_bytes<O, Q, P, X>();
     hipLaunchKernelGGL((sample_order<O, Q, P, X, HE>), dim3(grid), dim3(block), lds, st, a, k0,
                        k1);
+    return hipGetLastError();
+  });
+}
+
+template <>
+hipError_t launch_persist_oq<O, Q>(const KArgs &a, int prec, bool group, int k0, int k1, int nitems,
+                                   int block, int cus, hipStream_t st) {
+  if (!a.queue) return hipErrorInvalidValue;
+  return with_kernel(a, mode_of(a, prec, group), [&](auto p, auto x, auto h) -> hipError_t {
+    constexpr int P = decltype(p)::value;
+    constexpr bool X = decltype(x)::value;
+    constexpr int HE = decltype(h)::value;
+    const size_t lds = sample_lds_bytes(3 * (O + 1), a.phys.nb, block, lds_tables<Q, P>()) +
+                       cycle_lds_bytes<O, Q, P, X>();
+    auto kern = sample_persistent<O, Q, P, X, HE>;
+    // more blocks than can be resident: the extra ones start as others
+    // finish and find the counter exhausted, so the device stays full
+    // whatever the occupancy of this kernel
+    const int grid = std::max(1, std::min(nitems, kPersistentBlocksPerCu * std::max(1, cus)));
+    // about eight claims per block: small enough chunks to balance the
+    // blocks' finishing times, large enough to keep a block on one task
+    const int chunk = std::max(1, nitems / (8 * grid));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a, k0, k1, nitems, chunk);
     return hipGetLastError();
   });
 }

@@ -568,7 +568,7 @@ int auto_spt(const mbpt_task_set *set, uint64_t max_samples) {
 
 struct Layout {
   size_t tasks, olist, diags, groups, terms, coefs, grids, hists, partials, counters, reslog, hf,
-      gl, cpart, creslog, total;
+      gl, cpart, creslog, queue, total;
 };
 
 Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, int nb) {
@@ -617,6 +617,8 @@ Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, 
   L.creslog = off;
   off = align256(off + nt * static_cast<size_t>(std::max(1, max_iters)) * 2 * kMaxReg *
                            sizeof(double));
+  L.queue = off;  // work-item counters of the persistent launches
+  off = align256(off + kQueueSlots * sizeof(int));
   L.total = off;
   return L;
 }
@@ -638,6 +640,7 @@ KArgs kargs_of(const mbpt_task_set *set) {
   a.reslog = set->d_reslog;
   a.cpart = set->d_cpart;
   a.creslog = set->d_creslog;
+  a.queue = set->d_queue;
   a.nreg = ctx->reg_n;
   a.reg_eta = ctx->reg_eta;
   a.ntasks = static_cast<int>(set->tasks.size());
@@ -726,6 +729,7 @@ int bind(mbpt_task_set *set, void *ptr, size_t bytes, uint64_t max_samples, int 
   set->d_gl = reinterpret_cast<double *>(base + L.gl);
   set->d_cpart = reinterpret_cast<double *>(base + L.cpart);
   set->d_creslog = reinterpret_cast<double *>(base + L.creslog);
+  set->d_queue = reinterpret_cast<int *>(base + L.queue);
   set->run_reg_n = -1;
   set->h_gl.assign(2 * kHfGauss, 0.0);
   gauss_legendre(kHfGauss, set->h_gl.data(), set->h_gl.data() + kHfGauss);
@@ -982,7 +986,7 @@ extern "C" int mbpt_set_asymmetry(mbpt_task_set *set, double x) {
 }
 
 extern "C" int mbpt_set_launch_mode(mbpt_task_set *set, int mode) {
-  if (!set || mode < MBPT_LAUNCH_PER_TASK || mode > MBPT_LAUNCH_GRAPH) return MBPT_EINVAL;
+  if (!set || mode < MBPT_LAUNCH_PER_TASK || mode > MBPT_LAUNCH_PERSISTENT) return MBPT_EINVAL;
   set->launch_mode = mode;
   set->drop_graph();
   set->oranges.clear();
@@ -1054,12 +1058,19 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
     }
     return MBPT_OK;
   }
+  const bool persistent = set->launch_mode == MBPT_LAUNCH_PERSISTENT;
   for (int it = 0; it < iters; ++it) {
     size_t slot = 0;
     if (timed) timed_begin(ctx, slot);
-    for (const auto &r : set->oranges)
-      HIPCHK(ctx, launch_sample_order(a, r.order, set->q, ctx->desc.precision, r.group, r.k0, r.k1,
-                                      r.nitems, set->block, ctx->stream));
+    for (const auto &r : set->oranges) {
+      if (persistent)
+        HIPCHK(ctx, launch_sample_persistent(a, r.order, set->q, ctx->desc.precision, r.group, r.k0,
+                                             r.k1, r.nitems, set->block, ctx->num_cus,
+                                             ctx->stream));
+      else
+        HIPCHK(ctx, launch_sample_order(a, r.order, set->q, ctx->desc.precision, r.group, r.k0,
+                                        r.k1, r.nitems, set->block, ctx->stream));
+    }
     if (timed) timed_end(ctx, slot);
     HIPCHK(ctx, launch_finish(a, 0, nt, 0, alpha, ctx->stream));
   }
@@ -1231,6 +1242,32 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
   return status;
 }
 
+extern "C" int mbpt_batch_workspace_query(mbpt_context *ctx, const mbpt_task_desc *tasks,
+                                          int n_tasks, uint64_t samples_per_iter, int iters,
+                                          size_t *bytes) {
+  if (!ctx || !tasks || n_tasks < 1 || !bytes) return MBPT_EINVAL;
+  mbpt_task_set *set = nullptr;
+  int rc = mbpt_create_task_set(ctx, tasks, n_tasks, &set);
+  if (rc) return rc;
+  rc = mbpt_workspace_query(set, samples_per_iter, iters, bytes);
+  mbpt_task_set_destroy(set);
+  return rc;
+}
+
+extern "C" int mbpt_integrate_batch(mbpt_context *ctx, const mbpt_task_desc *tasks, int n_tasks,
+                                    uint64_t samples_per_iter, int iters, void *device_ptr,
+                                    size_t bytes, mbpt_result *out, mbpt_result *total) {
+  if (!ctx || !tasks || n_tasks < 1) return MBPT_EINVAL;
+  mbpt_task_set *set = nullptr;
+  int rc = mbpt_create_task_set(ctx, tasks, n_tasks, &set);
+  if (rc) return rc;
+  rc = mbpt_set_launch_mode(set, MBPT_LAUNCH_BATCHED);
+  if (!rc) rc = mbpt_bind_workspace(set, device_ptr, bytes, samples_per_iter, iters);
+  if (!rc) rc = mbpt_integrate(set, samples_per_iter, iters, out, total);
+  mbpt_task_set_destroy(set);
+  return rc;
+}
+
 namespace mbpt {
 
 // mbpt_integrate for a set without a workspace, inside device memory the
@@ -1274,6 +1311,7 @@ int integrate_in(mbpt_task_set *set, void *base, size_t bytes, uint64_t samples_
   set->d_coefs = nullptr;
   set->d_grids = set->d_hists = set->d_partials = set->d_reslog = nullptr;
   set->d_cpart = set->d_creslog = nullptr;
+  set->d_queue = nullptr;
   set->d_counters = nullptr;
   set->d_hf = set->d_gl = nullptr;
   set->hf_dirty = true;

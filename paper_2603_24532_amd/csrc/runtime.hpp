@@ -87,6 +87,7 @@ struct mbpt_task_set {
   int run_reg_n = -1;
   double run_reg_eta = 0.0;
   uint64_t *d_counters = nullptr;
+  int *d_queue = nullptr;  // work-item counters of the persistent launches
   std::vector<int2> olist;                 // (first item, task) grouped by order
   std::vector<mbpt::OrderRange> oranges;   // one sample launch per order
   hipGraphExec_t graph_exec = nullptr;

@@ -9,8 +9,9 @@
 //
 // One round (mbpt_server_step): admit queued requests in arrival order while a
 // slot is free and there is room for the head request's items and terms; run
-// one VEGAS iteration for every resident request with a single persistent
-// launch plus the iteration-end launch; copy the task states back; retire
+// the planned VEGAS iterations of every resident request, each iteration one
+// sample launch per order present (over the work items of all of that order's
+// requests) plus the iteration-end launch; copy the task states back; retire
 // requests whose sigma reached max(sigma_rel |E|, sigma_abs) after at least
 // kMinIters iterations, or whose evaluations reached max_evals.  A request
 // samples its own Philox stream (key = ticket), so its result does not depend

@@ -69,15 +69,16 @@ NUCLEAR = [_task(2, 0, 4, 0.16, 0.3, 11), _task(3, 1, 4, 0.12, 0.5, 12),
            _task(4, 20, 4, 0.16, 0.4, 13), _task(5, 300, 4, 0.20, 0.1, 14)]
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("matter", ["neutron", "nuclear"])
 def test_launch_modes_against_oracle(M, mode, matter):
-    """Per-task launches (mode 0), one launch per order (1) and the captured
-    graph (2), each over two integrate calls (the graph is replayed)."""
+    """Per-task launches (mode 0), one launch per order (1), the captured
+    graph (2) and persistent launches (3), each over two integrate calls (the
+    graph is replayed)."""
     tasks = NEUTRON if matter == "neutron" else NUCLEAR
     print(f"case mode={mode} matter={matter}", flush=True)
     N = 1 << 15
-    run = Run(M, tasks, max_samples=N, mode=mode, spt=4)
+    run = Run(M, tasks, max_samples=N, mode=mode, spt=1 if mode == 3 else 4)
     try:
         M.mbpt_integrate(run.set, N, 3)
         per, _ = M.mbpt_integrate(run.set, N, 3)
@@ -219,3 +220,28 @@ def test_served_requests_against_oracle(M, precision):
         else:
             assert dev <= 3.0 * ro.sigma
             assert dev <= 1e-4 * abs(ro.mean) + 1e-2 * ro.sigma
+
+
+def test_integrate_batch_against_oracle(M):
+    """The one-shot batch entry point (task set created, bound to the caller's
+    workspace, integrated and destroyed in one call) against the oracle."""
+    import torch
+    tasks = [_task(2, 0, 4, 0.16, 0.3, 41), _task(3, 2, 4, 0.12, 0.2, 42),
+             _task(4, 11, 4, 0.20, 0.1, 43)]
+    N, iters = 1 << 14, 4
+    stream = torch.cuda.Stream()
+    ctx = M.mbpt_context_create(stream=stream.cuda_stream)
+    try:
+        nbytes = M.mbpt_batch_workspace_query(ctx, tasks, N, iters)
+        buf, ptr = M.device_workspace(nbytes)
+        per, tot = M.mbpt_integrate_batch(ctx, tasks, N, iters, ptr, nbytes)
+        with pytest.raises(M.MbptError):  # too small a workspace
+            M.mbpt_integrate_batch(ctx, tasks, N, iters, ptr, nbytes // 2)
+    finally:
+        M.mbpt_context_destroy(ctx)
+    for k, t in enumerate(tasks):
+        r, Io, Vo, _ = _oracle_log(t, N, iters)
+        assert per[k].iters_done == iters and per[k].n_evals == N * iters
+        assert abs(per[k].E_per_A - r.mean) <= 1e-9 * abs(r.mean) + 1e-6 * r.sigma
+        assert per[k].sigma == pytest.approx(r.sigma, rel=1e-6, abs=1e-300)
+    assert tot.E_per_A == pytest.approx(sum(p.E_per_A for p in per), rel=1e-12)
