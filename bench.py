@@ -99,7 +99,7 @@ def parse():
     ap.add_argument("--label-mode", type=int, default=0, choices=(0, 1),
                     help="label sums: 0 polynomial per isospin configuration, 1 explicit list")
     ap.add_argument("--workload", default="metric",
-                    choices=["metric", "nuclear4", "batched", "serve", "plain"],
+                    choices=["metric", "nuclear4", "groups4", "batched", "serve", "plain"],
                     help="metric (default): the headline line with every sub-workload; "
                          "the others run one part alone (for profiling)")
     ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"],
@@ -108,6 +108,9 @@ def parse():
                     help="nuclear4 alone: the order of the diagrams (4 in the headline)")
     ap.add_argument("--stride", type=int, default=1,
                     help="nuclear4 alone: every stride-th diagram of the order")
+    ap.add_argument("--train", type=int, default=4,
+                    help="headline: training iterations (grid adapts) before the evaluation "
+                         "iterations (frozen grid) that make the estimate")
     ap.add_argument("--launch", default="batched", choices=["batched", "persistent"],
                     help="nuclear4 alone: one block per work item (batched) or persistent blocks")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -164,14 +167,21 @@ class SigmaClock:
 
 
 def run_set(M, tasks, N, steps, warmup, stream, precision=0, mode=1, seed=1, blocking=None,
-            autotune=False, keep=False):
+            autotune=False, keep=False, train=0, reg=None):
     """Create, bind and run a task set: `warmup` iterations, a reset (uniform
     grids, iteration 0), then `steps` iterations timed one by one on the
-    library's stream.  Returns timing, kernel statistics and results."""
+    library's stream.  train: training iterations before the grid is frozen
+    (the estimate then combines the evaluation iterations); reg: (components,
+    eta) of the regularised denominators.  Returns timing, kernel statistics
+    and results."""
     ctx = M.mbpt_context_create(stream=stream.cuda_stream, precision=precision, seed=seed,
                                 label_mode=LABEL_MODE)
+    if reg:
+        M.mbpt_set_regularization(ctx, *reg)
     s = M.mbpt_create_task_set(ctx, tasks)
     M.mbpt_set_launch_mode(s, mode)
+    if train:
+        M.mbpt_set_training(s, train)
     if blocking:
         M.mbpt_set_blocking(s, *blocking)
     cap = max(steps, warmup, 1) + 1
@@ -195,6 +205,8 @@ def run_set(M, tasks, N, steps, warmup, stream, precision=0, mode=1, seed=1, blo
     st = M.mbpt_kernel_stats(ctx)
     out = dict(dt=dt, stats=st, per=per, clock=clock.summary(), tuned=tuned,
                fallback=sum(r.n_fp64_fallback for r in per) / max(1, sum(r.n_evals for r in per)))
+    if reg:
+        out["reg"] = [M.mbpt_regularized(s, k, reg[0], train) for k in range(len(tasks))]
     if keep:
         out["set"], out["ctx"], out["buf"] = s, ctx, buf
     else:
@@ -261,7 +273,7 @@ def nuclear4(args, M, stream, precisions=("fp32", "fp64"), extras=True):
             f"x 2^{args.samples_log2}")
         mode = M.MBPT_LAUNCH_PERSISTENT if args.launch == "persistent" else M.MBPT_LAUNCH_BATCHED
         legs[p] = run_set(M, tasks, N, args.steps, args.warmup, stream,
-                          precision=1 if p == "fp32" else 0, mode=mode)
+                          precision=1 if p == "fp32" else 0, mode=mode, train=args.train)
         log(f"[nuclear4] {p}: {_rate(legs[p]):.2f} Gevals/s")
     if not extras:
         return tasks, legs
@@ -290,6 +302,44 @@ def roofline_of(leg, peak, extra=None):
     if extra:
         r.update(extra)
     return r
+
+
+def groups4(args, M, stream):
+    """The 39 fourth-order diagrams as the order's diagram groups (diagrams
+    with equal numbers of particle-carried loops summed into one integrand,
+    Table I's N_grp = 4) at the 15 EOS points: training then evaluation
+    iterations; fp64, fp32 (same Philox streams) and fp64 with another seed,
+    and fp64 with four regularised denominator components extrapolated to
+    eta = 0 (Sec. "Automated approach": groups and the regularisation
+    parameter are how fourth and fifth order are evaluated)."""
+    import numpy as np
+    gs = [p for p in range(6) if M.mbpt_group_members(4, p)]
+    tasks = [(4, p, M.MBPT_NUCLEAR, n, x, 20000 + 100 * p + 10 * i + j, 1)
+             for p in gs for i, n in enumerate(DENSITIES_C4) for j, x in enumerate(FRACTIONS_C4)]
+    N, iters, train = 1 << 22, 12, 4
+    legs = {}
+    for label, prec, seed, reg in (("fp64", 0, 1, None), ("fp32", 1, 1, None),
+                                   ("fp64_seed2", 0, 2, None), ("fp64_reg", 0, 1, (4, 1.0))):
+        legs[label] = run_set(M, tasks, N, iters, 0, stream, precision=prec, seed=seed,
+                              mode=M.MBPT_LAUNCH_BATCHED, train=train, reg=reg)
+        log(f"[groups4] {label}: {_rate(legs[label]):.2f} G group-sample evaluations/s")
+    e0 = np.array([r[2] for r in legs["fp64_reg"]["reg"]])
+    s0 = np.array([r[3] for r in legs["fp64_reg"]["reg"]])
+    em = np.array([r.E_per_A for r in legs["fp64_reg"]["per"]])
+    sm = np.array([r.sigma for r in legs["fp64_reg"]["per"]])
+    zr = np.abs(e0 - em) / np.hypot(s0, sm)
+    return {"workload": f"{len(gs)} fourth-order diagram groups ({len(tasks)} tasks with the 15 "
+                        f"EOS points), nuclear matter, {train} training + {iters - train} "
+                        f"evaluation iterations x 2^22 samples",
+            "groups": {str(p): len(M.mbpt_group_members(4, p)) for p in gs},
+            "rate": {k: _rate(v) for k, v in legs.items()},
+            "unit": "G group-sample evaluations/s",
+            "fp32_vs_fp64_same_streams_z": _zstats(legs["fp32"]["per"], legs["fp64"]["per"]),
+            "fp64_seed1_vs_seed2_z": _zstats(legs["fp64_seed2"]["per"], legs["fp64"]["per"]),
+            "chi2_dof": {k: _chi2(v["per"]) for k, v in legs.items()},
+            "regularised_extrapolation_vs_direct_z": {
+                "max": float(zr.max()), "median": float(np.median(zr)),
+                "frac_within_3sigma": float((zr < 3).mean())}}
 
 
 # --------------------------------------------------------------------------
@@ -609,6 +659,7 @@ def headline(args, M, stream):
             "integrand": "fp32 (fp64 VEGAS map, accumulation, refinement and near-singular "
                          "re-evaluation band)",
             "launch": "one sample launch per order per iteration + one iteration-end launch",
+            "training_iterations": args.train,
             "interaction": "C0=-1 fm^2, Cy=-2, mpi=0.7, Lambda=2, n=4", "seed": 1,
             "label_sum": "polynomial" if LABEL_MODE == 0 else "explicit",
         },
@@ -655,12 +706,16 @@ def main():
             "time_to_1pct_sigma": l["clock"]} for p, l in legs.items()}
     elif args.workload == "batched":
         line = batched(args, M, stream)
+    elif args.workload == "groups4":
+        line = groups4(args, M, stream)
     elif args.workload == "serve":
         line = serve(args, M, stream)
     elif args.workload == "plain":
         line = plain_scan(args, M, stream)
     else:
         line = headline(args, M, stream)
+        log("[bench] fourth-order diagram groups")
+        line["fourth_order_groups"] = groups4(args, M, stream)
         log("[bench] batched orders 2+3")
         line["orders_2_3_batched"] = batched(args, M, stream)
         log("[bench] served stream")

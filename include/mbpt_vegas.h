@@ -292,6 +292,15 @@ int mbpt_task_count(const mbpt_task_set *set, int *n);
 int mbpt_set_density(mbpt_task_set *set, double density);
 int mbpt_set_asymmetry(mbpt_task_set *set, double proton_fraction);
 int mbpt_set_launch_mode(mbpt_task_set *set, int mode);
+/* Training and evaluation phases (Sec. "MC integration: PVegas"): with
+ * train_iters > 0 the first train_iters iterations of every task after a
+ * reset or an EOS-point move adapt its grid (training); from then on the grid
+ * is frozen and the estimate, its sigma and chi2/dof combine the evaluation
+ * iterations only (the training iterations stay in mbpt_iteration_log).
+ * Until the first evaluation iteration the result combines the training
+ * iterations.  0 (default): every iteration adapts the grid and is combined.
+ * Applies from the set's next iteration.  EINVAL if train_iters < 0. */
+int mbpt_set_training(mbpt_task_set *set, int train_iters);
 /* Work decomposition: threads per block (64..256, multiple of 64; the sample
  * kernels are built for at most 256) and samples per thread per work item
  * (1..256).  Defaults 256 and 16.  EINVAL outside these ranges. */

@@ -63,6 +63,7 @@ class Problem(ctypes.Structure):
         ("hf_y", ctypes.POINTER(ctypes.c_double)), ("hf_m", ctypes.POINTER(ctypes.c_double)),
         ("group", ctypes.c_int),
         ("reg_k", ctypes.c_int), ("reg_eta", ctypes.c_double),
+        ("train_iters", ctypes.c_int),
     ]
 
 
@@ -145,7 +146,8 @@ HF_GAUSS = 64
 
 
 def problem(order, diagram_id=0, density=0.08, proton_fraction=0.0, q=2, seed=1,
-            task_key=0, label_method=0, spectrum=0, group=-1, reg_k=0, reg_eta=0.0, **kw):
+            task_key=0, label_method=0, spectrum=0, group=-1, reg_k=0, reg_eta=0.0,
+            train_iters=0, **kw):
     """group >= 0: the order's diagrams with that many particle-carried loops,
     integrated as one summed integrand (diagram_id is then unused)."""
     p = dict(DEFAULTS)
@@ -156,7 +158,7 @@ def problem(order, diagram_id=0, density=0.08, proton_fraction=0.0, q=2, seed=1,
                  hbarc=p["hbarc"], n_bins=p["n_bins"], alpha=p["alpha"],
                  kcut_extra=p["kcut_extra"], seed=seed, task_key=task_key,
                  label_method=label_method, spectrum=spectrum, group=group, reg_k=reg_k,
-                 reg_eta=reg_eta)
+                 reg_eta=reg_eta, train_iters=train_iters)
     if spectrum:
         if q == 4 and label_method != 0:
             raise ValueError("HF spectrum in nuclear matter needs the brute-force label sum")

@@ -400,6 +400,9 @@ typedef struct {
                              diagrams with p particle-carried loops (diagram_id unused) */
   int reg_k;              /* regularised components k = 1..reg_k (at most ORC_MAXREG) */
   double reg_eta;         /* component k replaces every D_c by D_c - k reg_eta [MeV] */
+  int train_iters;        /* > 0: training/evaluation phases (Sec. "MC integration"):
+                             the first train_iters iterations adapt the grid, the rest
+                             keep it frozen and alone make the combined estimate */
 } orc_problem;
 
 typedef struct {
@@ -1185,7 +1188,7 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
                      integrand_fn fn, const void *ctx, double *edges, uint64_t N,
                      int iters, uint32_t first_iter, int nthreads, double *I_out,
                      double *var_out, orc_result *res, int nreg, double *Ireg,
-                     double *Vreg) {
+                     double *Vreg, int train_iters) {
   if (N < 2 || iters < 1 || nd < 1 || nd > ORC_MAXDIM || nb < 2 || nb > ORC_MAXBINS)
     return -3;
   uint64_t nchunks = (N + ORC_CHUNK - 1) / ORC_CHUNK;
@@ -1255,7 +1258,9 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
     if (var < 0.0) var = 0.0;
     I[it] = shift + m1;
     V[it] = var;
-    for (int m = 0; m < nd; ++m) {
+    /* training phase: adapt; evaluation phase: the grid stays frozen */
+    const int adapt = train_iters <= 0 || it < train_iters;
+    for (int m = 0; m < nd && adapt; ++m) {
       double hist[ORC_MAXBINS];
       for (int b = 0; b < nb; ++b) {
         double s = 0.0;
@@ -1266,7 +1271,12 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
     }
     shift = I[it];
   }
-  orc_combine(iters, I, V, res);
+  /* with a training phase, the evaluation iterations alone (once there are
+   * any) make the combined estimate */
+  if (train_iters > 0 && iters > train_iters)
+    orc_combine(iters - train_iters, I + train_iters, V + train_iters, res);
+  else
+    orc_combine(iters, I, V, res);
   res->n_evals = N * (uint64_t)iters;
   if (I_out) memcpy(I_out, I, sizeof(double) * iters);
   if (var_out) memcpy(var_out, V, sizeof(double) * iters);
@@ -1287,7 +1297,7 @@ int orc_integrate_reg(const orc_problem *pb, double *edges, uint64_t N, int iter
     if (group_setup(pb, &md, &g)) return -1;
     int rc = vegas_run(3 * (pb->order + 1), pb->n_bins, pb->alpha, pb->seed, pb->task_key,
                        group_eval, &g, edges, N, iters, first_iter, nthreads, I_out, var_out,
-                       res, nreg, Ireg, Vreg);
+                       res, nreg, Ireg, Vreg, pb->train_iters);
     group_free(&g);
     return rc;
   }
@@ -1296,7 +1306,7 @@ int orc_integrate_reg(const orc_problem *pb, double *edges, uint64_t N, int iter
   phys_ctx ctx = {pb, &d, &md};
   return vegas_run(d.ndim, pb->n_bins, pb->alpha, pb->seed, pb->task_key, phys_eval,
                    &ctx, edges, N, iters, first_iter, nthreads, I_out, var_out, res, nreg, Ireg,
-                   Vreg);
+                   Vreg, pb->train_iters);
 }
 
 /* Full VEGAS run of one diagram (or group) at one EOS point. */
@@ -1317,7 +1327,7 @@ int orc_integrate_gaussian(int nd, double width, int nb, double alpha, uint32_t 
                            orc_result *res) {
   gauss_ctx g = {width, nd};
   return vegas_run(nd, nb, alpha, seed, task_key, gauss_eval, &g, edges, N, iters, 0,
-                   nthreads, I_out, var_out, res, 0, NULL, NULL);
+                   nthreads, I_out, var_out, res, 0, NULL, NULL, 0);
 }
 
 int orc_max_threads(void) {

@@ -35,7 +35,7 @@ EXPORTED = [
     "mbpt_server_destroy", "mbpt_server_submit", "mbpt_server_step", "mbpt_server_poll",
     "mbpt_set_regularization", "mbpt_dump_samples_reg", "mbpt_regularized_log",
     "mbpt_regularized", "mbpt_diagram_flops", "mbpt_integrate_noalloc",
-    "mbpt_batch_workspace_query", "mbpt_integrate_batch",
+    "mbpt_batch_workspace_query", "mbpt_integrate_batch", "mbpt_set_training",
 ]
 
 
@@ -134,6 +134,7 @@ def lib():
         "mbpt_set_density": [_P, ctypes.c_double],
         "mbpt_set_asymmetry": [_P, ctypes.c_double],
         "mbpt_set_launch_mode": [_P, ctypes.c_int],
+        "mbpt_set_training": [_P, ctypes.c_int],
         "mbpt_set_blocking": [_P, ctypes.c_int, ctypes.c_int],
         "mbpt_workspace_query": [_P, ctypes.c_uint64, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_size_t)],
@@ -363,6 +364,10 @@ def mbpt_set_asymmetry(s, x):
 
 def mbpt_set_launch_mode(s, mode):
     _check(lib().mbpt_set_launch_mode(s, mode), _ctx_of_set(s))
+
+
+def mbpt_set_training(s, train_iters):
+    _check(lib().mbpt_set_training(s, train_iters), _ctx_of_set(s))
 
 
 def mbpt_set_blocking(s, threads_per_block, samples_per_thread):

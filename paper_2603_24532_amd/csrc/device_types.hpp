@@ -178,7 +178,7 @@ struct alignas(16) TaskDev {
   double band_k, band_d;
   double hf_h, hf_inv_h;  // HF spline step and its inverse
   int ndiag;              // descriptors of the task from `diag` on (a diagram group: > 1)
-  int pad_nd;
+  int train_iters;        // > 0: first train_iters iterations are training (see finish_iteration)
   int active;
   int plan;             // iterations of the current launch sequence it takes part in
   // state (written by the device)
@@ -187,7 +187,7 @@ struct alignas(16) TaskDev {
   double shift;
   double wsum, wisum, wi2sum, zsum;
   int nzero;
-  int pad2;
+  int ncomb;            // iterations combined into the running sums
   double lastI, lastV;
   uint64_t nevals, nfallback, npass, nterms;
 };

@@ -237,6 +237,14 @@ __global__ __launch_bounds__(kFinishThreads) void finish_iteration(KArgs a, int 
         }
       }
     }
+    // training/evaluation split: the first evaluation iteration discards
+    // the training iterations from the running sums
+    if (T->train_iters > 0 && T->it_done == T->train_iters) {
+      T->wsum = T->wisum = T->wi2sum = T->zsum = 0.0;
+      T->nzero = 0;
+      T->ncomb = 0;
+    }
+    T->ncomb += 1;
     if (var > 0.0) {
       T->wsum += 1.0 / var;
       T->wisum += I / var;
@@ -255,14 +263,16 @@ __global__ __launch_bounds__(kFinishThreads) void finish_iteration(KArgs a, int 
     T->npass += F[1];
     T->nterms += F[2];
   }
-  // refinement: one wavefront per dimension
+  // refinement: one wavefront per dimension; with a training phase the grid
+  // is frozen once the training iterations are done
   __syncthreads();
   const int nb = a.phys.nb;
+  const bool refine = T->train_iters <= 0 || T->it_done <= T->train_iters;
   double *scr = scratch + static_cast<size_t>(wave) * (2 * nb + 2);
   for (int m = wave; m < T->nd; m += (bs >> 6)) {
     double *hist = a.hists + T->hist_off + m * nb;
     double *edges = a.grids + T->grid_off + m * (nb + 1);
-    refine_dim_wave(hist, edges, nb, alpha, scr);
+    if (refine) refine_dim_wave(hist, edges, nb, alpha, scr);
     __syncwarp();
     for (int b = lane; b < nb; b += 64) hist[b] = 0.0;
   }
@@ -383,6 +393,7 @@ __global__ void init_tasks(KArgs a, int first, int keep_grid) {
     T->shift = 0.0;
     T->wsum = T->wisum = T->wi2sum = T->zsum = 0.0;
     T->nzero = 0;
+    T->ncomb = 0;
     T->lastI = T->lastV = 0.0;
     T->nevals = T->nfallback = T->npass = T->nterms = 0;
   }

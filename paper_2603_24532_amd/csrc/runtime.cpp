@@ -548,6 +548,7 @@ void fill_task_params(mbpt_task_set *set) {
     fill_medium(ctx, td.density, td.proton_fraction, T);
     T.active = 1;
     T.plan = 0x7fffffff;  // every iteration
+    T.train_iters = set->train_iters;
   }
   set->grid_doubles = goff;
   set->hist_doubles = hoff;
@@ -801,7 +802,7 @@ void result_of(const TaskDev &S, mbpt_result &r) {
     r.E_per_A = S.wisum / S.wsum;
     r.sigma = 1.0 / std::sqrt(S.wsum);
     const double chi2 = S.wi2sum - S.wisum * S.wisum / S.wsum;
-    r.chi2_dof = S.it_done > 1 ? std::max(0.0, chi2) / (S.it_done - 1) : 0.0;
+    r.chi2_dof = S.ncomb > 1 ? std::max(0.0, chi2) / (S.ncomb - 1) : 0.0;
   }
 }
 
@@ -983,6 +984,15 @@ extern "C" int mbpt_set_asymmetry(mbpt_task_set *set, double x) {
   }
   for (auto &t : set->tasks) t.proton_fraction = x;
   return move_eos_point(set);
+}
+
+extern "C" int mbpt_set_training(mbpt_task_set *set, int train_iters) {
+  if (!set || train_iters < 0) return MBPT_EINVAL;
+  set->train_iters = train_iters;
+  for (auto &T : set->h_tasks) T.train_iters = train_iters;
+  set->drop_graph();
+  if (!set->ws) return MBPT_OK;
+  return upload_params(set);
 }
 
 extern "C" int mbpt_set_launch_mode(mbpt_task_set *set, int mode) {

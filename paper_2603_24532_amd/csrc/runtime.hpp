@@ -53,6 +53,7 @@ struct mbpt_task_set {
   int q = 2;
   std::vector<mbpt_task_desc> tasks;
   int launch_mode = MBPT_LAUNCH_PER_TASK;
+  int train_iters = 0;  // training/evaluation split (0: off)
   int block = 256, spt = 16;
   bool blocking_auto = true;  // spt chosen at bind from the sample count
   std::vector<mbpt::DiagDev> diags;

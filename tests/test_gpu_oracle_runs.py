@@ -245,3 +245,28 @@ def test_integrate_batch_against_oracle(M):
         assert abs(per[k].E_per_A - r.mean) <= 1e-9 * abs(r.mean) + 1e-6 * r.sigma
         assert per[k].sigma == pytest.approx(r.sigma, rel=1e-6, abs=1e-300)
     assert tot.E_per_A == pytest.approx(sum(p.E_per_A for p in per), rel=1e-12)
+
+
+@pytest.mark.parametrize("matter", ["neutron", "nuclear"])
+def test_training_phase_against_oracle(M, matter):
+    """Training/evaluation split: the first iterations adapt the grid, then it
+    is frozen and only the evaluation iterations make E, sigma and chi2/dof."""
+    tasks = NEUTRON[:2] if matter == "neutron" else NUCLEAR[:3]
+    N, train, iters = 1 << 14, 3, 7
+    run = Run(M, tasks, max_samples=N, mode=1)
+    try:
+        M.mbpt_set_training(run.set, train)
+        per, _ = M.mbpt_integrate(run.set, N, iters)
+        for k, t in enumerate(tasks):
+            Ig, Vg = M.mbpt_iteration_log(run.set, k)
+            order, did, m, n, x, key = t
+            pb = O.problem(order, did, density=n, proton_fraction=x, q=4 if m else 2, seed=1,
+                           task_key=key, label_method=0 if not m else 1, train_iters=train)
+            r, Io, Vo, _ = O.integrate(pb, N, iters)
+            _close_log(Ig, Vg, Io, Vo, ("training", t))
+            assert per[k].iters_done == iters
+            assert abs(per[k].E_per_A - r.mean) <= 1e-9 * abs(r.mean) + 1e-6 * r.sigma
+            assert per[k].sigma == pytest.approx(r.sigma, rel=1e-6, abs=1e-300)
+            assert per[k].chi2_dof == pytest.approx(r.chi2_dof, rel=1e-5, abs=1e-9)
+    finally:
+        run.close()

@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 
 import oracle as O
 
@@ -93,3 +94,27 @@ def test_thread_count_independence():
     r1, I1, V1, e1 = O.integrate(pb, 20000, 3, nthreads=1)
     r4, I4, V4, e4 = O.integrate(pb, 20000, 3, nthreads=4)
     assert np.array_equal(I1, I4) and np.array_equal(V1, V4) and np.array_equal(e1, e4)
+
+
+def test_training_then_frozen_grid_evaluation():
+    """Training/evaluation phases (Sec. "MC integration: PVegas"): the
+    training iterations are those of a plain run, the grid stops changing when
+    training ends, and the estimate is the inverse-variance mean of the
+    evaluation iterations alone (which still agree with the quadrature)."""
+    from oracle import references as R
+    N, train, iters = 1 << 15, 3, 8
+    r, I, V, e = O.integrate(O.problem(2, 0, density=0.1, train_iters=train), N, iters)
+    r0, I0, V0, e0 = O.integrate(O.problem(2, 0, density=0.1), N, train)
+    assert np.array_equal(I[:train], I0) and np.array_equal(V[:train], V0)
+    assert np.array_equal(e, e0)  # frozen after training
+    w = 1.0 / V[train:]
+    mean = float(np.sum(w * I[train:]) / np.sum(w))
+    assert r.mean == pytest.approx(mean, rel=1e-13)
+    assert r.sigma == pytest.approx(float(np.sum(w) ** -0.5), rel=1e-13)
+    chi2 = float(np.sum(w * (I[train:] - mean) ** 2)) / (iters - train - 1)
+    assert r.chi2_dof == pytest.approx(chi2, rel=1e-10)
+    ref = R.second_order(0.1)
+    assert abs(r.mean - ref) < 3.0 * r.sigma
+    # only training iterations so far: they make the estimate
+    rt, It, Vt, _ = O.integrate(O.problem(2, 0, density=0.1, train_iters=train), N, train)
+    assert rt.mean == pytest.approx(r0.mean, rel=1e-13)
