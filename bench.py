@@ -167,7 +167,7 @@ class SigmaClock:
 
 
 def run_set(M, tasks, N, steps, warmup, stream, precision=0, mode=1, seed=1, blocking=None,
-            autotune=False, keep=False, train=0, reg=None):
+            autotune=False, keep=False, train=0, reg=None, rel_target=0.0):
     """Create, bind and run a task set: `warmup` iterations, a reset (uniform
     grids, iteration 0), then `steps` iterations timed one by one on the
     library's stream.  train: training iterations before the grid is frozen
@@ -178,6 +178,8 @@ def run_set(M, tasks, N, steps, warmup, stream, precision=0, mode=1, seed=1, blo
                                 label_mode=LABEL_MODE)
     if reg:
         M.mbpt_set_regularization(ctx, *reg)
+    if rel_target:
+        M.mbpt_set_fp32_target(ctx, rel_target)
     s = M.mbpt_create_task_set(ctx, tasks)
     M.mbpt_set_launch_mode(s, mode)
     if train:
@@ -284,6 +286,9 @@ def nuclear4(args, M, stream, precisions=("fp32", "fp64"), extras=True):
     log("[nuclear4] fp32 graph-captured")
     legs["graph_fp32"] = run_set(M, tasks, N, few, 1, stream, precision=1,
                                  mode=M.MBPT_LAUNCH_GRAPH)
+    log("[nuclear4] fp32 with the 1e-5 relative target per value")
+    legs["fp32_rel1e-5"] = run_set(M, tasks, N, few, 1, stream, precision=1,
+                                   mode=M.MBPT_LAUNCH_BATCHED, train=args.train, rel_target=1e-5)
     log("[nuclear4] fp32 persistent blocks")
     legs["persistent_fp32"] = run_set(M, tasks, N, few, 1, stream, precision=1,
                                       mode=M.MBPT_LAUNCH_PERSISTENT)
@@ -676,6 +681,8 @@ def headline(args, M, stream):
         "plain_fp64_one_launch_per_task": {"value": _rate(legs["plain_fp64"]), "unit": "Gevals/s"},
         "graph_fp32": {"value": _rate(legs["graph_fp32"]), "unit": "Gevals/s"},
         "persistent_fp32": {"value": _rate(legs["persistent_fp32"]), "unit": "Gevals/s"},
+        "fp32_rel_target_1e-5": {"value": _rate(legs["fp32_rel1e-5"]), "unit": "Gevals/s",
+                                 "fp64_fallback_fraction": legs["fp32_rel1e-5"]["fallback"]},
         "vs_plain_fp64": value / _rate(legs["plain_fp64"]),
         "fp32_vs_fp64_same_streams_z": _zstats(f32["per"], f64["per"]),
         "chi2_dof": {"fp32": _chi2(f32["per"]), "fp64": _chi2(f64["per"])},

@@ -194,6 +194,15 @@ int mbpt_set_spectrum(mbpt_context *ctx, int spectrum);
  * if it has changed since (call mbpt_reset).  EINVAL on n_eta outside 0..4 or
  * eta <= 0. */
 int mbpt_set_regularization(mbpt_context *ctx, int n_eta, double eta);
+/* FP32 precision: relative accuracy target per integrand value (0, the
+ * default: only the near-Fermi-surface and small-denominator bands of the
+ * context description).  With rel > 0 every fp32 sample also carries a
+ * first-order bound of its relative error (from the regulator exponent, the
+ * condition numbers of the energy and Yukawa denominators and the label sum's
+ * cancellation, in units of the fp32 rounding unit) and is re-evaluated in
+ * fp64 when the bound exceeds rel, so that each value is within rel of the
+ * fp64 integrand.  Takes effect at the next integrate.  EINVAL if rel < 0. */
+int mbpt_set_fp32_target(mbpt_context *ctx, double rel);
 
 /* ---- diagram generator (host only, no context needed) --------------------- */
 /* Number of two-body energy diagrams of an order (1, 1, 3, 39, 840 for orders

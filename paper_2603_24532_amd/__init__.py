@@ -36,6 +36,7 @@ EXPORTED = [
     "mbpt_set_regularization", "mbpt_dump_samples_reg", "mbpt_regularized_log",
     "mbpt_regularized", "mbpt_diagram_flops", "mbpt_integrate_noalloc",
     "mbpt_batch_workspace_query", "mbpt_integrate_batch", "mbpt_set_training",
+    "mbpt_set_fp32_target",
 ]
 
 
@@ -135,6 +136,7 @@ def lib():
         "mbpt_set_asymmetry": [_P, ctypes.c_double],
         "mbpt_set_launch_mode": [_P, ctypes.c_int],
         "mbpt_set_training": [_P, ctypes.c_int],
+        "mbpt_set_fp32_target": [_P, ctypes.c_double],
         "mbpt_set_blocking": [_P, ctypes.c_int, ctypes.c_int],
         "mbpt_workspace_query": [_P, ctypes.c_uint64, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_size_t)],
@@ -364,6 +366,10 @@ def mbpt_set_asymmetry(s, x):
 
 def mbpt_set_launch_mode(s, mode):
     _check(lib().mbpt_set_launch_mode(s, mode), _ctx_of_set(s))
+
+
+def mbpt_set_fp32_target(ctx, rel):
+    _check(lib().mbpt_set_fp32_target(ctx, rel), ctx)
 
 
 def mbpt_set_training(s, train_iters):

@@ -176,6 +176,7 @@ struct alignas(16) TaskDev {
   double Rh, Rp;        // loop radii for hole / particle loop lines
   double inv_density;
   double band_k, band_d;
+  double rel_target;    // fp32: relative accuracy target per value (0: bands only)
   double hf_h, hf_inv_h;  // HF spline step and its inverse
   int ndiag;              // descriptors of the task from `diag` on (a diagram group: > 1)
   int train_iters;        // > 0: first train_iters iterations are training (see finish_iteration)

@@ -544,9 +544,10 @@ __device__ __forceinline__ uint32_t popc_w(W x) {
 // The monomials carry the sign (-V_e) and are tabulated as in the
 // configuration form; the counts are integers, so the sum equals the sum over
 // isospin configurations up to rounding.
-template <int ORDER, typename F>
+template <int ORDER, typename F, bool ABS = false>
 __device__ __forceinline__ F label_sum_cycles(const DiagDev *__restrict__ D, const F *Vd,
-                                              const F *Ve, CycWord<ORDER> cA, CycWord<ORDER> cB) {
+                                              const F *Ve, CycWord<ORDER> cA, CycWord<ORDER> cB,
+                                              F *absum = nullptr) {
   using W = CycWord<ORDER>;
   constexpr int H = ORDER / 2;
   constexpr int NA = 1 << H, NB = 1 << (ORDER - H);
@@ -557,10 +558,17 @@ __device__ __forceinline__ F label_sum_cycles(const DiagDev *__restrict__ D, con
   monomials<H>(Vd, nVe, MA);
   monomials<ORDER - H>(Vd + H, nVe + H, MB);
   const W ab = cA | cB, both = cA & cB;
-  F acc = F(0);
+  F AA[ABS ? NA : 1], AB[ABS ? NB : 1];
+  if constexpr (ABS) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) AA[i] = fabs(MA[i]);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) AB[i] = fabs(MB[i]);
+  }
+  F acc = F(0), aacc = F(0);
 #pragma unroll
   for (int eb = 0; eb < NB; ++eb) {
-    F in = F(0);
+    F in = F(0), ain = F(0);
 #pragma unroll
     for (int ea = 0; ea < NA; ++ea) {
       const int E = ea | (eb << H);
@@ -570,29 +578,41 @@ __device__ __forceinline__ F label_sum_cycles(const DiagDev *__restrict__ D, con
       const uint32_t e = popc_w<ORDER>(both & m) + n;
       const F c = (ab & m) == m ? pow2_bits<F>(e) : F(0);
       in = fma_t<F>(c, MA[ea], in);
+      if constexpr (ABS) ain = fma_t<F>(c, AA[ea], ain);
     }
     acc = fma_t<F>(in, MB[eb], acc);
+    if constexpr (ABS) aacc = fma_t<F>(ain, AB[eb], aacc);
   }
+  if constexpr (ABS) *absum = aacc;
   return acc;
 }
 
 // ISO: divide each configuration's sum by its own denominators (Dn, deps).
 // X: the explicit assignment list instead of the polynomial (compile-time, so
 // a kernel holds the state of one form only).
-template <int ORDER, int Q, typename F, bool ISO, bool X, int V>
+// ABS: also the same sum with every term in absolute value (*absum), the
+// scale against which the fp32 integrand's cancellation is judged.
+template <int ORDER, int Q, typename F, bool ISO, bool X, int V, bool ABS = false>
 __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict__ D,
                                        const F *Vd, const F *Ve, uint32_t okN, uint32_t okP,
                                        uint32_t lmask, uint32_t &units, const double *Dn,
-                                       const double *deps) {
+                                       const double *deps, F *absum = nullptr) {
   const GroupDev *__restrict__ G = a.groups + D->group_off;
   const int ngroups = D->ngroups;
-  F acc = F(0);
+  F acc = F(0), aacc = F(0);
   if constexpr (!X) {
     constexpr int H = ORDER / 2;
     constexpr int NA = 1 << H, NB = 1 << (ORDER - H);
     F MA[NA], MB[NB];
     monomials<H>(Vd, Ve, MA);
     monomials<ORDER - H>(Vd + H, Ve + H, MB);
+    F AA[ABS ? NA : 1], AB[ABS ? NB : 1];
+    if constexpr (ABS) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) AA[i] = fabs(MA[i]);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) AB[i] = fabs(MB[i]);
+    }
     for (int gi = 0; gi < ngroups; ++gi) {
       const uint32_t tau = G[gi].tau;
       bool ok = true;
@@ -611,6 +631,15 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
           for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(c[eb * NA + ea], MA[ea], in);
           gs = fma_t<F>(in, MB[eb], gs);
         }
+        if constexpr (ABS) {
+#pragma unroll
+          for (int eb = 0; eb < NB; ++eb) {
+            F in = F(0);
+#pragma unroll
+            for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(fabs(c[eb * NA + ea]), AA[ea], in);
+            aacc = fma_t<F>(in, AB[eb], aacc);
+          }
+        }
         if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER, V>(D, tau, Dn, deps));
         acc += gs;
       }
@@ -626,21 +655,24 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
         F gs = F(0);
         for (int t = first; t < first + cnt; ++t) {
           const TermDev tm = a.terms[t];
-          F prod = F(1);
+          F prod = F(1), aprod = F(1);
 #pragma unroll
           for (int v = 0; v < ORDER; ++v) {
             const uint32_t code = (tm.codes >> (2 * v)) & 3u;
             const F ca = code != 1u ? F(1) : F(0);
             const F cb = code != 0u ? F(-1) : F(0);
             prod *= fma_t<F>(ca, Vd[v], cb * Ve[v]);
+            if constexpr (ABS) aprod *= fma_t<F>(ca, fabs(Vd[v]), -cb * fabs(Ve[v]));
           }
           gs = fma_t<F>(term_mult<F>(tm), prod, gs);
+          if constexpr (ABS) aacc = fma_t<F>(fabs(term_mult<F>(tm)), aprod, aacc);
         }
         if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER, V>(D, tau, Dn, deps));
         acc += gs;
       }
     }
   }
+  if constexpr (ABS) *absum = aacc;
   return acc;
 }
 
@@ -973,6 +1005,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   }
 
   float dprod = 1.0f;
+  float kcut = 0.0f;  // sum of the cuts' condition numbers (sum |eps|) / |D|
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const uint32_t hm = cut_hole_of<ORDER, V>(D, c), pm = cut_part_of<ORDER, V>(D, c);
@@ -986,12 +1019,14 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
       Dabs = fmaf(fabsf(cf), eps[l], Dabs);
     }
     near |= fabsf(Dc) < bandd * Dabs;
+    kcut = fmaf(Dabs, __builtin_amdgcn_rcpf(fabsf(Dc)), kcut);
     dprod *= Dc;
   }
 
   constexpr int NR = 2 * ORDER + 1;
   float den[NR];
   float yreg = 0.0f;  // sum of the regulator exponents
+  float yscale[ORDER];  // |p|^2 + |p'|^2 + 2 |p.p'| + m^2: scale of the Yukawa denominators
   const float m2 = static_cast<float>(a.phys.m2);
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
@@ -1006,6 +1041,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
     const float s2 = p2 + q2 + m2;
     den[2 * v] = s2 - 2.0f * pq;
     den[2 * v + 1] = s2 + 2.0f * pq;
+    yscale[v] = s2 + 2.0f * fabsf(pq);
   }
   den[NR - 1] = dprod;
   float pre[NR];
@@ -1037,12 +1073,41 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   const float regall = __expf(-yexp);
 
   float acc;
-  if constexpr (CY) {
-    ++nterms;
-    acc = label_sum_cycles<ORDER, float>(D, Vd, Ve, cA, cB);
+  const uint32_t nterms0 = nterms;
+  if (T->rel_target > 0.0) {
+    // relative-accuracy target per value: a first-order bound on the fp32
+    // evaluation's relative error, in units of the fp32 rounding unit u:
+    // the regulator exponent (its momenta carry a few u each), the cuts'
+    // and the Yukawa denominators' condition numbers, the label sum's
+    // cancellation (sum of |terms| / |sum|) and a constant for the rest
+    float aabs;
+    if constexpr (CY) {
+      ++nterms;
+      acc = label_sum_cycles<ORDER, float, true>(D, Vd, Ve, cA, cB, &aabs);
+    } else {
+      acc = label_sum<ORDER, Q, float, false, X, V, true>(a, D, Vd, Ve, okN, okP, lmask, nterms,
+                                                          nullptr, nullptr, &aabs);
+    }
+    float ky = 0.0f;
+#pragma unroll
+    for (int v = 0; v < ORDER; ++v)
+      ky = fmaf(yscale[v], rinv[2 * v] + rinv[2 * v + 1], ky);
+    const float cancel = aabs * __builtin_amdgcn_rcpf(fabsf(acc));
+    const float bound =
+        0x1p-24f * (8.0f * yexp + 4.0f * kcut + 4.0f * ky + 8.0f * cancel + 64.0f);
+    if (!(bound <= static_cast<float>(T->rel_target))) {
+      nterms = nterms0;
+      fallback = true;
+      return 0.0;
+    }
   } else {
-    acc = label_sum<ORDER, Q, float, false, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms, nullptr,
-                                                 nullptr);
+    if constexpr (CY) {
+      ++nterms;
+      acc = label_sum_cycles<ORDER, float>(D, Vd, Ve, cA, cB);
+    } else {
+      acc = label_sum<ORDER, Q, float, false, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms,
+                                                   nullptr, nullptr);
+    }
   }
   ++npass;
   return D->pref * static_cast<double>(regall) * static_cast<double>(acc) *

@@ -184,6 +184,13 @@ extern "C" int mbpt_set_regularization(mbpt_context *ctx, int n_eta, double eta)
   return MBPT_OK;
 }
 
+extern "C" int mbpt_set_fp32_target(mbpt_context *ctx, double rel) {
+  if (!ctx || !(rel >= 0.0) || !std::isfinite(rel)) return MBPT_EINVAL;
+  ctx->fp32_rel_target = rel;
+  ++ctx->epoch;
+  return MBPT_OK;
+}
+
 extern "C" int mbpt_set_precision(mbpt_context *ctx, int precision) {
   if (!ctx || (precision != MBPT_FP64 && precision != MBPT_FP32)) return MBPT_EINVAL;
   ctx->desc.precision = precision;
@@ -400,6 +407,7 @@ void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T) 
   T.inv_density = 1.0 / density;
   T.band_k = ctx->desc.fp32_band_k;
   T.band_d = ctx->desc.fp32_band_d;
+  T.rel_target = ctx->fp32_rel_target;
   // HF spline range: beyond kF,max + kHfRangeLambda Lambda every partner
   // momentum p exceeds 3 Lambda and the regulator leaves Sigma < 1e-70
   T.hf_h = (kFmax + kHfRangeLambda * ctx->v.Lambda) / kHfIntervals;
@@ -663,12 +671,21 @@ KArgs kargs_of(const mbpt_task_set *set) {
 
 // Precision, interaction or spectrum changed since the set last ran: captured
 // launches, launch shapes and HF tables are stale.
-void sync_epoch(mbpt_task_set *set) {
-  if (set->epoch == set->ctx->epoch) return;
+int upload_params(mbpt_task_set *set);
+
+int sync_epoch(mbpt_task_set *set) {
+  if (set->epoch == set->ctx->epoch) return MBPT_OK;
   set->drop_graph();
   set->oranges.clear();
   set->hf_dirty = true;
+  // context settings the tasks carry (uploaded with the parameters)
+  for (auto &T : set->h_tasks) {
+    T.band_k = set->ctx->desc.fp32_band_k;
+    T.band_d = set->ctx->desc.fp32_band_d;
+    T.rel_target = set->ctx->fp32_rel_target;
+  }
   set->epoch = set->ctx->epoch;
+  return set->ws ? upload_params(set) : MBPT_OK;
 }
 
 // (Re)computes the HF spline tables of every task when the spectrum is HF and
@@ -1151,7 +1168,10 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
   }
   set->run_reg_n = ctx->reg_n;
   set->run_reg_eta = ctx->reg_eta;
-  sync_epoch(set);
+  {
+    const int rc = sync_epoch(set);
+    if (rc) return rc;
+  }
   bool changed = false;
   std::vector<int> all(nt);
   for (int t = 0; t < nt; ++t) {
@@ -1361,7 +1381,10 @@ extern "C" int mbpt_dump_samples(mbpt_task_set *set, int task, uint32_t iter, ui
   if (!set || !w_host || task < 0 || task >= static_cast<int>(set->tasks.size())) return MBPT_EINVAL;
   if (!set->ws) return MBPT_ESTATE;
   mbpt_context *ctx = set->ctx;
-  sync_epoch(set);
+  {
+    const int rc = sync_epoch(set);
+    if (rc) return rc;
+  }
   {
     const int rc = ensure_hf(set);
     if (rc) return rc;
@@ -1393,7 +1416,10 @@ extern "C" int mbpt_dump_samples_reg(mbpt_task_set *set, int task, uint32_t iter
     set_err(ctx, "dump_samples_reg: needs regularised components and the free spectrum");
     return MBPT_ESTATE;
   }
-  sync_epoch(set);
+  {
+    const int rc = sync_epoch(set);
+    if (rc) return rc;
+  }
   KArgs a = kargs_of(set);
   // staging: main weights in the item partials, components in the item
   // component sums (2 kMaxReg doubles per item)
@@ -1539,7 +1565,10 @@ extern "C" int mbpt_hf_nodes(mbpt_task_set *set, int task, int tau, double *sigm
     set_err(ctx, "hf_nodes: needs the HF spectrum and a bound workspace");
     return MBPT_ESTATE;
   }
-  sync_epoch(set);
+  {
+    const int rc = sync_epoch(set);
+    if (rc) return rc;
+  }
   int rc = ensure_hf(set);
   if (rc) return rc;
   const TaskDev &T = set->h_tasks[task];

@@ -45,6 +45,7 @@ struct mbpt_context {
   uint64_t epoch = 0;  // bumped when precision or interaction changes
   int reg_n = 0;         // regularised components (0: none)
   double reg_eta = 0.0;  // component k shifts every denominator by -k reg_eta
+  double fp32_rel_target = 0.0;  // see mbpt_set_fp32_target
 };
 
 struct mbpt_task_set {
@@ -121,7 +122,7 @@ void timed_end(mbpt_context *ctx, size_t slot);
 void resolve_timing(mbpt_context *ctx);
 void gauss_legendre(int n, double *x, double *w);
 int ensure_hf(mbpt_task_set *set);
-void sync_epoch(mbpt_task_set *set);
+int sync_epoch(mbpt_task_set *set);
 void order_items(std::vector<TaskDev> &T, const std::vector<int> &active,
                  std::vector<int2> &olist, std::vector<OrderRange> &ranges);
 int integrate_in(mbpt_task_set *set, void *base, size_t bytes, uint64_t samples_per_iter,
