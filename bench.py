@@ -394,15 +394,19 @@ def batched(args, M, stream):
 # Served request stream
 # --------------------------------------------------------------------------
 
-def _requests(M, nreq, rate, seed):
+def _requests(M, nreq, rate, seed, groups=False):
+    """Poisson arrivals; one diagram uniform in an order's list, or with
+    groups a diagram group (orders 2-4) uniform among the order's groups."""
     import numpy as np
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
     ndiag = {o: M.mbpt_num_diagrams(o) for o in (2, 3, 4, 5)}
+    pgroups = {o: [p for p in range(o + 1) if M.mbpt_group_members(o, p)] for o in (2, 3, 4)}
     reqs = []
     for _ in range(nreq):
-        o = int(rng.integers(2, 6))
-        reqs.append(dict(order=o, did=int(rng.integers(0, ndiag[o])),
+        o = int(rng.integers(2, 5 if groups else 6))
+        did = int(rng.choice(pgroups[o])) if groups else int(rng.integers(0, ndiag[o]))
+        reqs.append(dict(order=o, did=did, group=int(groups),
                          n=float(rng.uniform(0.04, 0.24)), x=float(rng.uniform(0.0, 0.5)),
                          rel=float(rng.uniform(0.001, 0.01))))
     return arrivals, reqs
@@ -411,14 +415,18 @@ def _requests(M, nreq, rate, seed):
 SERVE_SAMPLES, SERVE_CAP = 1 << 18, 1 << 25
 
 
-def serve_stream(M, stream, nreq, rate, seed, label, precision=1):
+def serve_stream(M, stream, nreq, rate, seed, label, precision=1, groups=False, reg=None):
     """Open-loop Poisson arrivals through the continuous-batching server.
     Time-to-sigma is counted over the requests that met their sigma target;
-    requests retired at the evaluation cap are censored and reported apart."""
+    requests retired at the evaluation cap are censored and reported apart.
+    groups: requests for diagram groups; reg = (n_eta, eta): regularised
+    components, the target then applying to their extrapolation."""
     import numpy as np
-    arrivals, reqs = _requests(M, nreq, rate, seed)
+    arrivals, reqs = _requests(M, nreq, rate, seed, groups)
     ctx = M.mbpt_context_create(stream=stream.cuda_stream, precision=precision,
                                 label_mode=LABEL_MODE)
+    if reg is not None:
+        M.mbpt_set_regularization(ctx, *reg)
     slots = 512
     nbytes = M.mbpt_server_workspace_query(ctx, slots, SERVE_SAMPLES)
     buf, ptr = M.device_workspace(nbytes)
@@ -433,7 +441,7 @@ def serve_stream(M, stream, nreq, rate, seed, label, precision=1):
             r = reqs[nxt]
             tickets[nxt] = M.mbpt_server_submit(srv, r["order"], r["did"], M.MBPT_NUCLEAR, r["n"],
                                                 r["x"], r["rel"], SIGMA_FLOOR, SERVE_SAMPLES,
-                                                SERVE_CAP)
+                                                SERVE_CAP, group=r["group"])
             nxt += 1
         na, nq = M.mbpt_server_step(srv)
         steps += 1
@@ -449,6 +457,12 @@ def serve_stream(M, stream, nreq, rate, seed, label, precision=1):
     met, retire, waits, censored, per_order = [], [], [], 0, {}
     for t, r in zip(tickets, reqs):
         res, done, ts, ta, tf = M.mbpt_server_poll(srv, t)
+        if reg is not None:
+            try:
+                _, _, E0, S0 = M.mbpt_server_poll_regularized(srv, t, reg[0])
+            except M.MbptError:  # no extrapolation (mixed exact and inexact components)
+                E0, S0 = float("nan"), float("inf")
+            res.E_per_A, res.sigma = E0, S0  # the target applies to the extrapolation
         retire.append(tf - ts)
         waits.append(ta - ts)
         po = per_order.setdefault(r["order"], {"met": [], "censored": 0, "iters": []})
@@ -533,6 +547,18 @@ def serve(args, M, stream):
     out["plain_fp64_rate_50_first_%d" % nplain] = serve_plain(M, stream, nplain, 50.0, 12345)
     out["served_rate_50_first_%d_same_requests" % nplain] = serve_stream(
         M, stream, nplain, 50.0, 12345, "50/s first")
+    ng = min(args.requests, 300)
+    log(f"[serve] {ng} diagram-group requests (orders 2-4) at 50/s")
+    out["groups_rate_50"] = serve_stream(M, stream, ng, 50.0, 2468, "groups 50/s", groups=True)
+    out["groups_rate_50"]["workload"] = "as above, but each request a diagram group of orders " \
+                                        "2-4 (group uniform among the order's)"
+    log(f"[serve] {ng} diagram-group requests with 3 regularised components at 50/s")
+    out["groups_regularized_rate_50"] = serve_stream(M, stream, ng, 50.0, 2468,
+                                                     "groups+reg 50/s", groups=True,
+                                                     reg=(3, 1.0))
+    out["groups_regularized_rate_50"]["workload"] = \
+        "the same group requests with 3 regularised components (shifts 1, 2, 3 MeV, fp64 " \
+        "integrand), sigma target on the quadratic extrapolation to zero shift"
     return out
 
 

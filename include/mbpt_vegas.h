@@ -461,20 +461,38 @@ int mbpt_task_flops(const mbpt_task_set *set, int task, double *flops, double *t
 /* ---- serving: continuous batching of EOS-point requests ------------------ */
 /* A server owns one device workspace (caller-owned, size from
  * mbpt_server_workspace_query) holding up to max_slots resident tasks.
- * Requests queue on submit; mbpt_server_step admits queued requests into free
- * slots (by slot count and workspace bytes), runs for every resident task the
- * VEGAS iterations its own estimates predict it still needs (the first three
- * at once, then ceil(k ((sigma/target)^2 - 1)), at most 32, within max_evals;
- * one launch per order present per iteration, one host synchronisation per
- * step), and retires tasks whose sigma reached max(sigma_rel |E|, sigma_abs)
- * (after at least three iterations) or whose evaluations reached max_evals.
+ * Requests queue on submit; mbpt_server_step admits queued requests in
+ * arrival order into free slots (by slot count, descriptor entries, table
+ * arena bytes and work items), runs for every resident task the VEGAS
+ * iterations its own estimates predict it still needs (the first three at
+ * once, then ceil(k ((sigma/target)^2 - 1)), at most 32, within max_evals; one
+ * launch per order present per iteration, one host synchronisation per step),
+ * and retires tasks whose sigma reached max(sigma_rel |E|, sigma_abs) (after
+ * at least three iterations) or whose evaluations reached max_evals.
  * A request's random stream is keyed by its ticket and its iteration plan by
  * its own state, so its result does not depend on what else is resident
  * (unless warm starts are on, see mbpt_server_set_warm_start).  The server
- * takes the free spectrum only (EINVAL / ESTATE with HF). */
+ * takes the free spectrum only (EINVAL / ESTATE with HF).
+ *
+ * Diagram groups (Sec. III.A; the grouping of mbpt_task_desc.group): a request
+ * with group = 1 integrates the summed integrand of the order's diagrams with
+ * diagram_id particle-carried loops in one VEGAS integral.  Its members take
+ * consecutive entries of the server's descriptor table (24 entries per slot)
+ * and their label tables bytes of the table arena (64 KiB per slot); a request
+ * that would not fit an empty server is refused at submit (ENOMEM), others
+ * wait for retirements.
+ *
+ * Regularised components (Sec. III.A): the context's mbpt_set_regularization
+ * at mbpt_server_workspace_query and mbpt_server_create applies to every
+ * request of the server for its lifetime (later changes of the context's
+ * setting do not reach it).  Each request then also integrates the n_eta
+ * shifted components over the same samples (fp64 integrand, whatever the
+ * precision), the host combines them by inverse variance every step, and the
+ * sigma target applies to their extrapolation to zero shift (see
+ * mbpt_server_poll_regularized) instead of the main estimate. */
 typedef struct mbpt_request {
   int order;
-  int diagram_id;
+  int diagram_id;       /* diagram id, or with group = 1 particle-carried loops */
   int matter;
   double density;
   double proton_fraction;
@@ -482,6 +500,7 @@ typedef struct mbpt_request {
   double sigma_abs;
   uint64_t samples_per_iter;
   uint64_t max_evals;
+  int group;            /* 0: one diagram, 1: a diagram group */
 } mbpt_request;
 
 int mbpt_server_workspace_query(const mbpt_context *ctx, int max_slots,
@@ -512,6 +531,17 @@ int mbpt_server_warm_starts(const mbpt_server *srv, uint64_t *count);
  * from the server's creation: submit, admit and finish. */
 int mbpt_server_poll(mbpt_server *srv, uint64_t ticket, mbpt_result *res, int *done,
                      double *t_submit, double *t_admit, double *t_finish);
+/* Regularised components of a ticket (a server created with components):
+ * E[n_eta] +- sigma[n_eta] per component, combined over the request's
+ * iterations by inverse variance (iterations without variance are exact),
+ * and E0 +- sigma0, the constant term of the weighted least-squares
+ * polynomial in eta_k = k eta of degree min(2, n_eta - 1) (as
+ * mbpt_regularized, an indication only: the components share samples).
+ * Current values for a resident request, final ones once retired; the
+ * pointers may be NULL.  EINVAL on an unknown ticket, ESTATE without
+ * components or before the first extrapolation. */
+int mbpt_server_poll_regularized(mbpt_server *srv, uint64_t ticket, double *E, double *sigma,
+                                 double *E0, double *sigma0);
 
 #ifdef __cplusplus
 }

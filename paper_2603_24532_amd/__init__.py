@@ -33,6 +33,7 @@ EXPORTED = [
     "mbpt_iteration_log", "mbpt_dump_samples", "mbpt_get_grid", "mbpt_set_grid",
     "mbpt_kernel_stats", "mbpt_task_flops", "mbpt_autotune", "mbpt_server_workspace_query", "mbpt_server_create",
     "mbpt_server_destroy", "mbpt_server_submit", "mbpt_server_step", "mbpt_server_poll",
+    "mbpt_server_poll_regularized",
     "mbpt_set_regularization", "mbpt_dump_samples_reg", "mbpt_regularized_log",
     "mbpt_regularized", "mbpt_diagram_flops", "mbpt_integrate_noalloc",
     "mbpt_batch_workspace_query", "mbpt_integrate_batch", "mbpt_set_training",
@@ -78,7 +79,8 @@ class mbpt_request(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("diagram_id", ctypes.c_int), ("matter", ctypes.c_int),
                 ("density", ctypes.c_double), ("proton_fraction", ctypes.c_double),
                 ("sigma_rel", ctypes.c_double), ("sigma_abs", ctypes.c_double),
-                ("samples_per_iter", ctypes.c_uint64), ("max_evals", ctypes.c_uint64)]
+                ("samples_per_iter", ctypes.c_uint64), ("max_evals", ctypes.c_uint64),
+                ("group", ctypes.c_int)]
 
 
 class MbptError(RuntimeError):
@@ -172,6 +174,7 @@ def lib():
         "mbpt_server_step": [_P, _IP, _IP],
         "mbpt_server_set_warm_start": [_P, ctypes.c_double, ctypes.c_double],
         "mbpt_server_warm_starts": [_P, ctypes.POINTER(ctypes.c_uint64)],
+        "mbpt_server_poll_regularized": [_P, ctypes.c_uint64, _DP, _DP, _DP, _DP],
         "mbpt_server_poll": [_P, ctypes.c_uint64, ctypes.POINTER(mbpt_result), _IP, _DP, _DP,
                              _DP],
     }
@@ -554,9 +557,10 @@ def mbpt_server_destroy(srv):
 
 
 def mbpt_server_submit(srv, order, diagram_id, matter, density, proton_fraction, sigma_rel,
-                       sigma_abs, samples_per_iter, max_evals):
+                       sigma_abs, samples_per_iter, max_evals, group=0):
+    """group = 1 makes diagram_id the particle-loop count of a diagram group."""
     r = mbpt_request(order, diagram_id, matter, density, proton_fraction, sigma_rel, sigma_abs,
-                     samples_per_iter, max_evals)
+                     samples_per_iter, max_evals, group)
     t = ctypes.c_uint64()
     _check(lib().mbpt_server_submit(srv, ctypes.byref(r), ctypes.byref(t)), _srv_ctx.get(srv))
     return t.value
@@ -586,6 +590,16 @@ def mbpt_server_poll(srv, ticket):
                                   ctypes.byref(ts), ctypes.byref(ta), ctypes.byref(tf)),
            _srv_ctx.get(srv))
     return r, bool(done.value), ts.value, ta.value, tf.value
+
+
+def mbpt_server_poll_regularized(srv, ticket, n_eta):
+    """Components (E[n_eta], sigma[n_eta]) and their extrapolation (E0, sigma0)."""
+    E = (ctypes.c_double * n_eta)()
+    S = (ctypes.c_double * n_eta)()
+    e0, s0 = ctypes.c_double(), ctypes.c_double()
+    _check(lib().mbpt_server_poll_regularized(srv, ticket, E, S, ctypes.byref(e0),
+                                              ctypes.byref(s0)), _srv_ctx.get(srv))
+    return list(E), list(S), e0.value, s0.value
 
 
 # --------------------------------------------------------------------------

@@ -452,6 +452,59 @@ void gauss_legendre(int n, double *x, double *w) {
 
 // Compile a task list's diagrams into device tables (one descriptor per
 // distinct (order, id)).
+int compile_task_diagrams(mbpt_context *ctx, int q, int order, int id, bool group,
+                          std::vector<DiagDev> &dds, std::vector<GroupDev> &groups,
+                          std::vector<TermDev> &terms, std::vector<double> &coefs,
+                          FlopModel &model) {
+  const std::vector<int> ids = group ? group_members(order, id) : std::vector<int>{id};
+  if (ids.empty()) {
+    set_err(ctx, "unknown diagram or empty diagram group");
+    return MBPT_EINVAL;
+  }
+  model = FlopModel{};
+  double units = 0.0, unit_flops = 0.0;
+  for (size_t i = 0; i < ids.size(); ++i) {
+    const Diagram *d = get_diagram(order, ids[i]);
+    if (!d) {
+      set_err(ctx, "unknown diagram");
+      return MBPT_EINVAL;
+    }
+    DiagDev dd{};
+    dd.order = d->order;
+    dd.id = d->id;
+    dd.nlines = d->nlines;
+    dd.nloops = d->nloops;
+    dd.ncuts = d->ncuts;
+    fill_diag_dev(*d, dd, group);
+    if (!append_label_tables(*d, q, dd, groups, terms, coefs, 0, 0, 0, group)) {
+      set_err(ctx, "label cycle tables disagree with the label tables");
+      return MBPT_EINVAL;
+    }
+    dds.push_back(dd);
+    FlopModel fm;
+    count_flops(*d, q, ctx->v.reg_exp / 2, ctx->desc.label_mode, ctx->desc.spectrum, fm);
+    // the nuclear-matter factorised label sum of a single diagram with the
+    // free spectrum is the cycle form: one polynomial per passing sample
+    fm.all_units = ctx->desc.label_mode ? dd.nterms
+                   : (q == 4 && !group && ctx->desc.spectrum == MBPT_SPECTRUM_FREE)
+                       ? 1
+                       : dd.ngroups;
+    // a group shares the map and loop momenta; its pass and label-unit
+    // counters add up over members, so post and per_term are averages
+    model.pre += i == 0 ? fm.pre : fm.pre - fm.shared;
+    model.shared = fm.shared;
+    model.post += fm.post / ids.size();
+    model.transc_pre += i == 0 ? fm.transc_pre : fm.transc_pre - fm.transc_shared;
+    model.transc_shared = fm.transc_shared;
+    model.transc_post += fm.transc_post / ids.size();
+    units += fm.all_units;
+    unit_flops += fm.per_term * fm.all_units;
+  }
+  model.all_units = units;
+  model.per_term = units > 0.0 ? unit_flops / units : 0.0;
+  return MBPT_OK;
+}
+
 int compile_tables(mbpt_task_set *set) {
   mbpt_context *ctx = set->ctx;
   const int q = set->q;
@@ -474,51 +527,12 @@ int compile_tables(mbpt_task_set *set) {
     for (const auto &e : done)
       if (e.order == td.order && e.id == td.diagram_id && e.group == td.group) hit = &e;
     if (!hit) {
-      const std::vector<int> ids =
-          td.group ? group_members(td.order, td.diagram_id) : std::vector<int>{td.diagram_id};
-      Entry e{td.order, td.diagram_id, td.group, static_cast<int>(set->diags.size()),
-              static_cast<int>(ids.size()), FlopModel{}};
-      double units = 0.0, unit_flops = 0.0;
-      for (size_t i = 0; i < ids.size(); ++i) {
-        const Diagram *d = get_diagram(td.order, ids[i]);
-        if (!d) {
-          set_err(ctx, "unknown diagram");
-          return MBPT_EINVAL;
-        }
-        DiagDev dd{};
-        dd.order = d->order;
-        dd.id = d->id;
-        dd.nlines = d->nlines;
-        dd.nloops = d->nloops;
-        dd.ncuts = d->ncuts;
-        fill_diag_dev(*d, dd, td.group != 0);
-        if (!append_label_tables(*d, q, dd, set->groups, set->terms, set->coefs, 0, 0, 0,
-                                 td.group != 0)) {
-          set_err(ctx, "create_task_set: label cycle tables disagree with the label tables");
-          return MBPT_EINVAL;
-        }
-        set->diags.push_back(dd);
-        FlopModel fm;
-        count_flops(*d, q, ctx->v.reg_exp / 2, ctx->desc.label_mode, ctx->desc.spectrum, fm);
-        // the nuclear-matter factorised label sum of a single diagram with the
-        // free spectrum is the cycle form: one polynomial per passing sample
-        fm.all_units = ctx->desc.label_mode ? dd.nterms
-                       : (q == 4 && !td.group && ctx->desc.spectrum == MBPT_SPECTRUM_FREE)
-                           ? 1
-                           : dd.ngroups;
-        // a group shares the map and loop momenta; its pass and label-unit
-        // counters add up over members, so post and per_term are averages
-        e.fm.pre += i == 0 ? fm.pre : fm.pre - fm.shared;
-        e.fm.shared = fm.shared;
-        e.fm.post += fm.post / ids.size();
-        e.fm.transc_pre += i == 0 ? fm.transc_pre : fm.transc_pre - fm.transc_shared;
-        e.fm.transc_shared = fm.transc_shared;
-        e.fm.transc_post += fm.transc_post / ids.size();
-        units += fm.all_units;
-        unit_flops += fm.per_term * fm.all_units;
-      }
-      e.fm.all_units = units;
-      e.fm.per_term = units > 0.0 ? unit_flops / units : 0.0;
+      Entry e{td.order, td.diagram_id, td.group, static_cast<int>(set->diags.size()), 0,
+              FlopModel{}};
+      const int rc = compile_task_diagrams(ctx, q, td.order, td.diagram_id, td.group != 0,
+                                           set->diags, set->groups, set->terms, set->coefs, e.fm);
+      if (rc) return rc;
+      e.count = static_cast<int>(set->diags.size()) - e.first;
       done.push_back(e);
       hit = &done.back();
     }

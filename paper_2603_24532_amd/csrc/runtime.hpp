@@ -114,6 +114,16 @@ bool append_label_tables(const Diagram &d, int q, DiagDev &dd, std::vector<Group
                          size_t group_base, size_t term_base, size_t coef_base,
                          bool canonical = false);
 void fill_diag_dev(const Diagram &d, DiagDev &dd, bool canonical = false);
+// Descriptors (appended to dds), label tables (appended to groups, terms,
+// coefs; a descriptor's offsets index those vectors) and the combined FLOP
+// model of one task: one diagram, or with group the members of the order's
+// diagram group with id particle-carried loops, in canonical loop order.
+int compile_task_diagrams(mbpt_context *ctx, int q, int order, int id, bool group,
+                          std::vector<DiagDev> &dds, std::vector<GroupDev> &groups,
+                          std::vector<TermDev> &terms, std::vector<double> &coefs,
+                          FlopModel &model);
+bool poly_fit_at_zero(const double *x, const double *y, const double *sig, int n, int deg,
+                      double &c0, double &s0);
 bool fixed_masks_ok();
 void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T);
 void result_of(const TaskDev &S, mbpt_result &r);

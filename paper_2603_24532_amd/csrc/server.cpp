@@ -1,11 +1,13 @@
 // Continuous-batching server for EOS-point requests (see include/mbpt_vegas.h).
 //
-// Layout of the caller's workspace: a slot table (TaskDev, DiagDev, grid,
-// histogram and iteration log per slot), two parallel per-work-item regions
-// (partial sums, counters) indexed by a storage index, and a byte arena for
-// the isospin groups and label terms of each resident request.  Storage-index
-// ranges and arena bytes are handed out first-fit and returned at retirement;
-// both are bookkept on the host.
+// Layout of the caller's workspace: a slot table (TaskDev, grid, histogram and
+// iteration-log ring per slot), a descriptor table (kDiagsPerSlot DiagDev
+// entries per slot on average; a diagram group's members take consecutive
+// entries), parallel per-work-item regions (partial sums, counters and, with
+// regularised components, component sums) indexed by a storage index, and a
+// byte arena for the isospin groups and label terms of each resident request.
+// Descriptor entries, storage-index ranges and arena bytes are handed out
+// first-fit and returned at retirement; all three are bookkept on the host.
 //
 // One round (mbpt_server_step): admit queued requests in arrival order while a
 // slot is free and there is room for the head request's items and terms; run
@@ -13,7 +15,11 @@
 // sample launch per order present (over the work items of all of that order's
 // requests) plus the iteration-end launch; copy the task states back; retire
 // requests whose sigma reached max(sigma_rel |E|, sigma_abs) after at least
-// kMinIters iterations, or whose evaluations reached max_evals.  A request
+// kMinIters iterations, or whose evaluations reached max_evals.  With
+// regularised components (fixed at creation from the context) the host
+// combines each request's per-iteration component estimates, read back from
+// the slot's log ring every step, and the target applies to the
+// extrapolation to zero shift.  A request
 // samples its own Philox stream (key = ticket), so its result does not depend
 // on what else is resident.  Requests run through the spin x isospin kernel; a
 // neutron-matter request runs at proton fraction 0, where that label sum equals
@@ -26,6 +32,8 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "diagrams.hpp"
@@ -43,6 +51,12 @@ constexpr int kMaxPlan = 32;  // iterations per step at most
 constexpr int kBlock = 256;
 constexpr int kMaxSpt = 16;
 constexpr size_t kTermBytesPerSlot = 64 * 1024;
+// descriptor entries per slot on average (the largest fourth-order diagram
+// group has 22 members)
+constexpr int kDiagsPerSlot = 24;
+// per-slot iteration-log ring: one step's iterations at most, read back by
+// the host after every step
+constexpr int kLogIters = kMaxPlan;
 
 size_t a256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
@@ -82,6 +96,18 @@ struct Ranges {
   }
 };
 
+// Regularised components of a request, combined over its iterations on the
+// host: inverse-variance sums of the iterations with a positive variance, and
+// count and sum of those without (exact: every sample zero or equal).
+struct RegSums {
+  double w[kMaxReg] = {}, wi[kMaxReg] = {}, zsum[kMaxReg] = {};
+  int nzero[kMaxReg] = {};
+  int iters = 0;  // iterations folded in
+  double E[kMaxReg] = {}, sigma[kMaxReg] = {};
+  double E0 = 0.0, sigma0 = 0.0;
+  bool ok = false;  // estimates and extrapolation valid
+};
+
 struct Req {
   mbpt_request r{};
   uint64_t ticket = 0;
@@ -89,18 +115,20 @@ struct Req {
   int slot = -1;
   double t_submit = 0, t_admit = -1, t_finish = -1;
   mbpt_result res{};
-  size_t item_at = 0, item_n = 0, byte_at = 0, byte_n = 0;
+  size_t item_at = 0, item_n = 0, byte_at = 0, byte_n = 0, diag_at = 0, diag_n = 0;
+  RegSums reg;
 };
 
 struct Layout {
-  size_t tasks, olist, diags, grids, hists, reslog, cache, partials, counters, arena, arena_bytes;
-  size_t max_items;
+  size_t tasks, olist, diags, grids, hists, reslog, creslog, cache, partials, counters, cpart,
+      arena, arena_bytes;
+  size_t max_items, max_diags;
 };
 
 // Pinned host staging of one step: admitted tables, descriptors and task
 // records, the parameter upload, the order list and the state download.  It
 // is reused once the step's closing synchronisation has passed.
-constexpr size_t kStageBytes = 4u << 20;
+constexpr size_t kStageBytes = 16u << 20;
 
 // Samples per thread of a server's work items: requests of up to
 // max_samples_per_iter samples should still spread over about two blocks per
@@ -116,43 +144,49 @@ size_t items_of(uint64_t samples, int spt) {
   return static_cast<size_t>((samples + chunk - 1) / chunk);
 }
 
-size_t slot_table_bytes(int slots, int nb) {
-  return a256(slots * sizeof(TaskDev)) + a256(slots * sizeof(int2)) +
-         a256(slots * sizeof(DiagDev)) +
-         a256(static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double)) +
-         a256(static_cast<size_t>(slots) * kMaxDim * nb * sizeof(double)) +
-         a256(static_cast<size_t>(slots) * 2 * sizeof(double)) +
-         a256(static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double));
+size_t per_item_bytes(int nreg) {
+  return 4 * sizeof(double) + kItemCounters * sizeof(uint64_t) +
+         (nreg > 0 ? 2 * kMaxReg * sizeof(double) : 0);
 }
 
-// Slot table first, then the term arena (kTermBytesPerSlot per slot), then
-// the item regions filling the rest.
-bool make_layout(int slots, int nb, size_t bytes, Layout &L) {
+// Slot table, descriptor table, log rings and warm-start cache, then the
+// table arena (kTermBytesPerSlot per slot), then the item regions filling the
+// rest.  Returns the offset where the item regions begin.
+size_t fixed_layout(int slots, int nb, Layout &L) {
   size_t off = 0;
   L.tasks = off;
   off = a256(off + slots * sizeof(TaskDev));
   L.olist = off;
   off = a256(off + slots * sizeof(int2));
   L.diags = off;
-  off = a256(off + slots * sizeof(DiagDev));
+  L.max_diags = static_cast<size_t>(slots) * kDiagsPerSlot;
+  off = a256(off + L.max_diags * sizeof(DiagDev));
   L.grids = off;
   off = a256(off + static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double));
   L.hists = off;
   off = a256(off + static_cast<size_t>(slots) * kMaxDim * nb * sizeof(double));
   L.reslog = off;
-  off = a256(off + static_cast<size_t>(slots) * 2 * sizeof(double));
+  off = a256(off + static_cast<size_t>(slots) * kLogIters * 2 * sizeof(double));
+  L.creslog = off;
+  off = a256(off + static_cast<size_t>(slots) * kLogIters * 2 * kMaxReg * sizeof(double));
   L.cache = off;  // grids of recent retirements (warm starts)
   off = a256(off + static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double));
   L.arena = off;
   L.arena_bytes = static_cast<size_t>(slots) * kTermBytesPerSlot;
-  off += L.arena_bytes;
-  if (bytes <= off + 512) return false;
-  const size_t per_item = 4 * sizeof(double) + kItemCounters * sizeof(uint64_t);
-  L.max_items = (bytes - off - 512) / per_item;
+  return off + L.arena_bytes;
+}
+
+bool make_layout(int slots, int nb, int nreg, size_t bytes, Layout &L) {
+  const size_t off = fixed_layout(slots, nb, L);
+  if (bytes <= off + 768) return false;
+  const size_t per_item = per_item_bytes(nreg);
+  L.max_items = (bytes - off - 768) / per_item;
   if (L.max_items > 0x7fffffffull) L.max_items = 0x7fffffffull;
   L.partials = a256(off);
   L.counters = a256(L.partials + L.max_items * 4 * sizeof(double));
-  return L.counters + L.max_items * kItemCounters * sizeof(uint64_t) <= bytes;
+  L.cpart = a256(L.counters + L.max_items * kItemCounters * sizeof(uint64_t));
+  const size_t end = nreg > 0 ? L.cpart + L.max_items * 2 * kMaxReg * sizeof(double) : L.cpart;
+  return end <= bytes;
 }
 
 double now_s(std::chrono::steady_clock::time_point t0) {
@@ -168,7 +202,9 @@ struct mbpt_server {
   uint64_t max_samples = 0;
   char *ws = nullptr;
   Layout L{};
-  Ranges items, bytes;
+  Ranges items, bytes, diags;
+  int reg_n = 0;          // regularised components of every request (0: none)
+  double reg_eta = 0.0;
   std::vector<int64_t> slot_req;  // ticket per slot, -1 if free
   std::vector<TaskDev> h_tasks;
   std::deque<uint64_t> queue;
@@ -176,21 +212,25 @@ struct mbpt_server {
   uint64_t next_ticket = 1;
   std::chrono::steady_clock::time_point t0;
   std::vector<FlopModel> flops;
-  // compiled tables per (order, diagram id), offsets relative to 0
+  // compiled descriptors and tables per (order, diagram id or group, group
+  // flag), offsets relative to 0
   struct Compiled {
-    DiagDev dd;
+    std::vector<DiagDev> dds;  // one, or the members of a diagram group
     std::vector<GroupDev> groups;
     std::vector<TermDev> terms;
     std::vector<double> coefs;
     FlopModel fm;
-    size_t bytes;  // arena bytes of the three tables
-    bool valid;    // label cycle tables agree with the configuration tables
+    size_t bytes = 0;    // arena bytes of the three tables
+    int rc = MBPT_OK;    // compilation status (EINVAL: unknown diagram or group,
+                         // label cycle tables that disagree with the label tables)
+    std::string err;
   };
-  std::map<std::pair<int, int>, Compiled> compiled;
+  std::map<std::tuple<int, int, int>, Compiled> compiled;
   // pinned staging (see kStageBytes) and its fill level within a step
   char *stage = nullptr;
   size_t stage_used = 0;
   TaskDev *pin_tasks = nullptr;   // parameter upload / state download
+  double *pin_creslog = nullptr;  // component log rings (regularised servers)
   int2 *pin_olist = nullptr;
   std::vector<int2> olist;
   std::vector<OrderRange> ranges;
@@ -198,7 +238,7 @@ struct mbpt_server {
   // warm starts: grids of recent retirements, one cache entry per slot
   struct CacheEntry {
     bool valid = false;
-    int order = 0, id = 0, matter = 0;
+    int order = 0, id = 0, group = 0, matter = 0;
     double density = 0.0, x = 0.0;
     uint64_t stamp = 0;
   };
@@ -210,6 +250,7 @@ struct mbpt_server {
     if (stage) (void)hipHostFree(stage);
     if (pin_tasks) (void)hipHostFree(pin_tasks);
     if (pin_olist) (void)hipHostFree(pin_olist);
+    if (pin_creslog) (void)hipHostFree(pin_creslog);
   }
 };
 
@@ -232,6 +273,10 @@ KArgs server_kargs(const mbpt_server *s) {
   a.partials = reinterpret_cast<double *>(b + s->L.partials);
   a.counters = reinterpret_cast<uint64_t *>(b + s->L.counters);
   a.reslog = reinterpret_cast<double *>(b + s->L.reslog);
+  a.creslog = reinterpret_cast<double *>(b + s->L.creslog);
+  a.cpart = s->reg_n > 0 ? reinterpret_cast<double *>(b + s->L.cpart) : nullptr;
+  a.nreg = s->reg_n;
+  a.reg_eta = s->reg_eta;
   a.ntasks = s->max_slots;
   a.spt = s->spt;
   a.label_mode = ctx->desc.label_mode;
@@ -253,15 +298,17 @@ KArgs server_kargs(const mbpt_server *s) {
 // sigma predicts are needed to reach its target (at least 1, at most
 // kMaxPlan), within its evaluation cap.  It depends on the request's own
 // state only, so a result does not depend on the requests sharing the GPU.
-int plan_of(const Req &q) {
+// With regularised components the estimate is the extrapolation E0 +- sigma0.
+int plan_of(const Req &q, bool reg) {
   const mbpt_result &r = q.res;
+  const double E = reg ? q.reg.E0 : r.E_per_A, sigma = reg ? q.reg.sigma0 : r.sigma;
   int plan;
-  if (r.iters_done < kMinIters) {
-    plan = kMinIters - r.iters_done;
+  if (r.iters_done < kMinIters || (reg && !q.reg.ok)) {
+    plan = std::max(1, kMinIters - r.iters_done);
   } else {
-    const double target = std::max(q.r.sigma_rel * std::fabs(r.E_per_A), q.r.sigma_abs);
-    if (target > 0.0 && r.sigma > 0.0) {
-      const double ratio = (r.sigma / target) * (r.sigma / target);
+    const double target = std::max(q.r.sigma_rel * std::fabs(E), q.r.sigma_abs);
+    if (target > 0.0 && sigma > 0.0) {
+      const double ratio = (sigma / target) * (sigma / target);
       const double need = std::ceil(r.iters_done * (ratio - 1.0));
       plan = need < 1.0 ? 1 : (need > kMaxPlan ? kMaxPlan : static_cast<int>(need));
     } else {
@@ -276,50 +323,61 @@ int plan_of(const Req &q) {
   return plan;
 }
 
-// Tables of a diagram compiled once per server (offsets relative to 0).
-const mbpt_server::Compiled &compiled_of(mbpt_server *s, int order, int id) {
-  auto key = std::make_pair(order, id);
+// Descriptors and tables of a request's diagram or diagram group, compiled
+// once per server (offsets relative to 0).
+const mbpt_server::Compiled &compiled_of(mbpt_server *s, int order, int id, int group) {
+  auto key = std::make_tuple(order, id, group);
   auto it = s->compiled.find(key);
   if (it != s->compiled.end()) return it->second;
-  const Diagram *d = get_diagram(order, id);
   mbpt_server::Compiled c{};
-  c.dd.order = d->order;
-  c.dd.id = d->id;
-  c.dd.nlines = d->nlines;
-  c.dd.nloops = d->nloops;
-  c.dd.ncuts = d->ncuts;
-  fill_diag_dev(*d, c.dd);
-  c.valid = append_label_tables(*d, 4, c.dd, c.groups, c.terms, c.coefs, 0, 0, 0);
-  count_flops(*d, 4, s->ctx->v.reg_exp / 2, s->ctx->desc.label_mode, MBPT_SPECTRUM_FREE, c.fm);
-  c.fm.all_units = s->ctx->desc.label_mode ? c.dd.nterms : 1;  // cycle form
+  mbpt_context *ctx = s->ctx;
+  const std::string saved = ctx->err;
+  c.rc = compile_task_diagrams(ctx, 4, order, id, group != 0, c.dds, c.groups, c.terms, c.coefs,
+                               c.fm);
+  if (c.rc) {
+    c.err = ctx->err;
+    ctx->err = saved;
+  }
   c.bytes = a256(c.groups.size() * sizeof(GroupDev)) + a256(c.terms.size() * sizeof(TermDev)) +
             a256(c.coefs.size() * sizeof(double));
   return s->compiled.emplace(key, std::move(c)).first->second;
 }
 
+size_t stage_bytes_of(const mbpt_server::Compiled &c) {
+  return c.bytes + a256(c.dds.size() * sizeof(DiagDev)) + a256(sizeof(TaskDev));
+}
+
 // Returns 0 when admitted, 1 when it does not fit now, < 0 on a HIP error.
 int admit_one(mbpt_server *s, Req &q, int slot) {
   mbpt_context *ctx = s->ctx;
-  const Diagram *d = get_diagram(q.r.order, q.r.diagram_id);
-  const mbpt_server::Compiled &c = compiled_of(s, q.r.order, q.r.diagram_id);
+  const mbpt_server::Compiled &c = compiled_of(s, q.r.order, q.r.diagram_id, q.r.group);
   const size_t gbytes = a256(c.groups.size() * sizeof(GroupDev));
   const size_t tbytes = a256(c.terms.size() * sizeof(TermDev));
-  const size_t need_bytes = gbytes + tbytes + a256(c.coefs.size() * sizeof(double));
+  const size_t need_bytes = c.bytes;
   const size_t need_items = items_of(q.r.samples_per_iter, s->spt);
-  // staging: tables (arena image), descriptor, task record
-  const size_t stage_need = need_bytes + a256(sizeof(DiagDev)) + a256(sizeof(TaskDev));
+  const size_t need_diags = c.dds.size();
+  const size_t dbytes = a256(need_diags * sizeof(DiagDev));
+  // staging: tables (arena image), descriptors, task record
+  const size_t stage_need = stage_bytes_of(c);
   if (s->stage_used + stage_need > kStageBytes) return 1;  // next step
-  size_t byte_at = 0, item_at = 0;
+  size_t byte_at = 0, item_at = 0, diag_at = 0;
   if (!s->bytes.alloc(need_bytes, byte_at)) return 1;
   if (!s->items.alloc(need_items, item_at)) {
     s->bytes.release(byte_at, need_bytes);
+    return 1;
+  }
+  if (!s->diags.alloc(need_diags, diag_at)) {
+    s->bytes.release(byte_at, need_bytes);
+    s->items.release(item_at, need_items);
     return 1;
   }
   q.byte_at = byte_at;
   q.byte_n = need_bytes;
   q.item_at = item_at;
   q.item_n = need_items;
-  // byte offsets from the workspace base; the descriptor holds element
+  q.diag_at = diag_at;
+  q.diag_n = need_diags;
+  // byte offsets from the workspace base; the descriptors hold element
   // indices from that base
   const size_t g_off = s->L.arena + byte_at;
   const size_t t_off = g_off + gbytes;
@@ -337,34 +395,38 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   std::memcpy(st + gbytes, c.terms.data(), c.terms.size() * sizeof(TermDev));
   std::memcpy(st + gbytes + tbytes, c.coefs.data(), c.coefs.size() * sizeof(double));
   auto *sd = reinterpret_cast<DiagDev *>(st + need_bytes);
-  *sd = c.dd;
-  sd->group_off += g_index;
-  sd->term_off += t_index;
-  auto *sT = reinterpret_cast<TaskDev *>(st + need_bytes + a256(sizeof(DiagDev)));
+  for (size_t i = 0; i < need_diags; ++i) {
+    sd[i] = c.dds[i];
+    sd[i].group_off += g_index;
+    sd[i].term_off += t_index;
+  }
+  auto *sT = reinterpret_cast<TaskDev *>(st + need_bytes + dbytes);
   TaskDev T{};
-  T.diag = slot;
-  T.nd = d->ndim;
+  T.diag = static_cast<int>(diag_at);
+  T.ndiag = static_cast<int>(need_diags);
+  T.nd = 3 * (q.r.order + 1);
   T.grid_off = slot * kMaxDim * (ctx->desc.n_bins + 1);
   T.hist_off = slot * kMaxDim * ctx->desc.n_bins;
-  T.res_off = slot;
-  T.res_cap = 1;
+  T.res_off = slot * kLogIters;
+  T.res_cap = kLogIters;
   T.key = static_cast<uint32_t>(q.ticket);
-  T.order = d->order;
+  T.order = q.r.order;
   T.nsamples = q.r.samples_per_iter;
   T.nitems = static_cast<int>(need_items);
   T.store_begin = static_cast<int>(item_at);
   const double x = q.r.matter == MBPT_NUCLEAR ? q.r.proton_fraction : 0.0;
   fill_medium(ctx, q.r.density, x, T);
   T.active = 1;
-  T.ndiag = 1;
   s->h_tasks[slot] = T;
   *sT = T;
   char *b = s->ws;
   // asynchronous copies from pinned staging: the step's closing
   // synchronisation orders them before the staging is reused
-  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + g_off, st, need_bytes, hipMemcpyHostToDevice, ctx->stream));
-  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.diags + slot * sizeof(DiagDev), sd, sizeof(DiagDev),
-                                  hipMemcpyHostToDevice, ctx->stream));
+  if (need_bytes)
+    MBPT_HIPCHK(ctx, hipMemcpyAsync(b + g_off, st, need_bytes, hipMemcpyHostToDevice, ctx->stream));
+  MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.diags + diag_at * sizeof(DiagDev), sd,
+                                  need_diags * sizeof(DiagDev), hipMemcpyHostToDevice,
+                                  ctx->stream));
   MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.tasks + slot * sizeof(TaskDev), sT, sizeof(TaskDev),
                                   hipMemcpyHostToDevice, ctx->stream));
   KArgs a = server_kargs(s);
@@ -376,7 +438,8 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
     const int matter = q.r.matter;
     for (int e = 0; e < static_cast<int>(s->cache.size()); ++e) {
       const auto &ce = s->cache[e];
-      if (!ce.valid || ce.order != q.r.order || ce.id != q.r.diagram_id || ce.matter != matter)
+      if (!ce.valid || ce.order != q.r.order || ce.id != q.r.diagram_id ||
+          ce.group != q.r.group || ce.matter != matter)
         continue;
       const double dn = std::fabs(ce.density - q.r.density), dx = std::fabs(ce.x - q.r.proton_fraction);
       if (dn > s->warm_dn || dx > s->warm_dx) continue;
@@ -387,7 +450,7 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
       }
     }
     if (best >= 0) {
-      const size_t gbytes = static_cast<size_t>(d->ndim) * (ctx->desc.n_bins + 1) * sizeof(double);
+      const size_t gbytes = static_cast<size_t>(T.nd) * (ctx->desc.n_bins + 1) * sizeof(double);
       MBPT_HIPCHK(ctx, hipMemcpyAsync(b + s->L.grids + T.grid_off * sizeof(double),
                                       b + s->L.cache + best * kMaxDim * (ctx->desc.n_bins + 1) *
                                                            sizeof(double),
@@ -405,16 +468,72 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   return 0;
 }
 
+// Folds the iterations a request ran since the last step into its component
+// sums (from the slot's log ring, read back with the step's state) and
+// updates the component estimates and their extrapolation to zero shift:
+// each component combines its iterations by inverse variance (iterations
+// without variance are exact: their plain mean, sigma 0, as for the main
+// estimate); E0 +- sigma0 is the constant term of the weighted least-squares
+// polynomial in eta_k = k eta of degree min(2, K - 1), unweighted with sigma0
+// = 0 when every component is exact.
+void fold_components(mbpt_server *s, Req &q, const TaskDev &S) {
+  RegSums &g = q.reg;
+  const int K = s->reg_n;
+  for (int it = g.iters; it < S.it_done; ++it) {
+    const double *cl =
+        s->pin_creslog + static_cast<size_t>(S.res_off + it % kLogIters) * 2 * kMaxReg;
+    for (int k = 0; k < K; ++k) {
+      const double I = cl[2 * k], v = cl[2 * k + 1];
+      if (v > 0.0) {
+        g.w[k] += 1.0 / v;
+        g.wi[k] += I / v;
+      } else {
+        g.zsum[k] += I;
+        ++g.nzero[k];
+      }
+    }
+  }
+  g.iters = S.it_done;
+  if (g.iters < 1) return;
+  double eta[kMaxReg], sig[kMaxReg], ones[kMaxReg];
+  bool exact = true;
+  for (int k = 0; k < K; ++k) {
+    if (g.nzero[k] > 0) {
+      g.E[k] = g.zsum[k] / g.nzero[k];
+      g.sigma[k] = 0.0;
+    } else {
+      g.E[k] = g.wi[k] / g.w[k];
+      g.sigma[k] = 1.0 / std::sqrt(g.w[k]);
+      exact = false;
+    }
+    eta[k] = (k + 1) * s->reg_eta;
+    ones[k] = 1.0;
+  }
+  bool all_positive = true;
+  for (int k = 0; k < K; ++k) all_positive = all_positive && g.sigma[k] > 0.0;
+  if (K == 1) {
+    g.E0 = g.E[0];
+    g.sigma0 = g.sigma[0];
+    g.ok = true;
+  } else if (all_positive || exact) {
+    for (int k = 0; k < K; ++k) sig[k] = all_positive ? g.sigma[k] : ones[k];
+    g.ok = poly_fit_at_zero(eta, g.E, sig, K, std::min(2, K - 1), g.E0, g.sigma0);
+    if (exact) g.sigma0 = 0.0;
+  } else {
+    g.ok = false;  // some components exact, others not: no extrapolation yet
+  }
+}
+
 }  // namespace
 
 extern "C" int mbpt_server_workspace_query(const mbpt_context *ctx, int max_slots,
                                            uint64_t max_samples_per_iter, size_t *bytes) {
   if (!ctx || !bytes || max_slots < 1 || max_samples_per_iter < 2) return MBPT_EINVAL;
-  const size_t per_item = 4 * sizeof(double) + kItemCounters * sizeof(uint64_t);
-  *bytes = slot_table_bytes(max_slots, ctx->desc.n_bins) +
-           static_cast<size_t>(max_slots) * kTermBytesPerSlot +
+  Layout L{};
+  *bytes = fixed_layout(max_slots, ctx->desc.n_bins, L) +
            static_cast<size_t>(max_slots) *
-               items_of(max_samples_per_iter, server_spt(ctx, max_samples_per_iter)) * per_item +
+               items_of(max_samples_per_iter, server_spt(ctx, max_samples_per_iter)) *
+               per_item_bytes(ctx->reg_n) +
            2048;
   return MBPT_OK;
 }
@@ -426,9 +545,8 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
       (reinterpret_cast<uintptr_t>(device_ptr) & 255u))
     return MBPT_EINVAL;
   *out = nullptr;
-  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE || ctx->reg_n > 0) {
-    set_err(ctx, "server_create: the server supports the free spectrum without regularised "
-                 "components only");
+  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE) {
+    set_err(ctx, "server_create: the server supports the free spectrum only");
     return MBPT_EINVAL;
   }
   if (!fixed_masks_ok()) {
@@ -436,7 +554,7 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
     return MBPT_EINVAL;
   }
   Layout L{};
-  if (!make_layout(max_slots, ctx->desc.n_bins, bytes, L) ||
+  if (!make_layout(max_slots, ctx->desc.n_bins, ctx->reg_n, bytes, L) ||
       L.max_items < items_of(max_samples_per_iter, server_spt(ctx, max_samples_per_iter))) {
     set_err(ctx, "server_create: workspace too small for the slot table and one request");
     return MBPT_ENOMEM;
@@ -451,6 +569,9 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
   s->L = L;
   s->items.init(0, L.max_items);
   s->bytes.init(0, L.arena_bytes);
+  s->diags.init(0, L.max_diags);
+  s->reg_n = ctx->reg_n;
+  s->reg_eta = ctx->reg_eta;
   s->slot_req.assign(max_slots, -1);
   s->cache.assign(max_slots, mbpt_server::CacheEntry{});
   s->h_tasks.assign(max_slots, TaskDev{});
@@ -461,7 +582,11 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
       hipHostMalloc(reinterpret_cast<void **>(&s->pin_tasks), max_slots * sizeof(TaskDev),
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void **>(&s->pin_olist), max_slots * sizeof(int2),
-                    hipHostMallocDefault) != hipSuccess) {
+                    hipHostMallocDefault) != hipSuccess ||
+      (s->reg_n > 0 &&
+       hipHostMalloc(reinterpret_cast<void **>(&s->pin_creslog),
+                     static_cast<size_t>(max_slots) * kLogIters * 2 * kMaxReg * sizeof(double),
+                     hipHostMallocDefault) != hipSuccess)) {
     set_err(ctx, "server_create: pinned host allocation failed");
     delete s;
     return MBPT_EHIP;
@@ -483,8 +608,9 @@ extern "C" void mbpt_server_destroy(mbpt_server *s) { delete s; }
 extern "C" int mbpt_server_submit(mbpt_server *s, const mbpt_request *req, uint64_t *ticket) {
   if (!s || !req || !ticket) return MBPT_EINVAL;
   mbpt_context *ctx = s->ctx;
-  const Diagram *d = get_diagram(req->order, req->diagram_id);
-  if (!d || !(req->density > 0) || !(req->proton_fraction >= 0 && req->proton_fraction <= 1) ||
+  const bool known = req->group == 1 ? !group_members(req->order, req->diagram_id).empty()
+                                       : req->group == 0 && get_diagram(req->order, req->diagram_id);
+  if (!known || !(req->density > 0) || !(req->proton_fraction >= 0 && req->proton_fraction <= 1) ||
       (req->matter != MBPT_NEUTRON && req->matter != MBPT_NUCLEAR) ||
       (req->matter == MBPT_NEUTRON && req->proton_fraction != 0.0) || req->samples_per_iter < 2 ||
       req->samples_per_iter > s->max_samples || !(req->sigma_rel >= 0) || !(req->sigma_abs >= 0)) {
@@ -495,12 +621,19 @@ extern "C" int mbpt_server_submit(mbpt_server *s, const mbpt_request *req, uint6
     set_err(ctx, "server_submit: queue full");
     return MBPT_EBUSY;
   }
-  if (!compiled_of(s, req->order, req->diagram_id).valid) {
-    set_err(ctx, "server_submit: label cycle tables disagree with the label tables");
-    return MBPT_EINVAL;
+  const mbpt_server::Compiled &c = compiled_of(s, req->order, req->diagram_id, req->group);
+  if (c.rc) {
+    set_err(ctx, "server_submit: " + c.err);
+    return c.rc;
   }
-  if (compiled_of(s, req->order, req->diagram_id).bytes > kTermBytesPerSlot) {
-    set_err(ctx, "server_submit: diagram label tables exceed the per-slot table arena");
+  // a request that could never be admitted, even into an empty server
+  if (c.bytes > s->L.arena_bytes || c.dds.size() > s->L.max_diags ||
+      stage_bytes_of(c) > kStageBytes) {
+    set_err(ctx, "server_submit: the request's " + std::to_string(c.dds.size()) +
+                     " descriptors and " + std::to_string(c.bytes) +
+                     " table bytes exceed the server's descriptor table (" +
+                     std::to_string(s->L.max_diags) + ") or table arena (" +
+                     std::to_string(s->L.arena_bytes) + " bytes)");
     return MBPT_ENOMEM;
   }
   Req q;
@@ -516,11 +649,11 @@ extern "C" int mbpt_server_submit(mbpt_server *s, const mbpt_request *req, uint6
 extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
   if (!s) return MBPT_EINVAL;
   mbpt_context *ctx = s->ctx;
-  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE || ctx->reg_n > 0) {
-    set_err(ctx, "server_step: the server supports the free spectrum without regularised "
-                 "components only");
+  if (ctx->desc.spectrum != MBPT_SPECTRUM_FREE) {
+    set_err(ctx, "server_step: the server supports the free spectrum only");
     return MBPT_ESTATE;
   }
+  const bool reg = s->reg_n > 0;
   while (!s->queue.empty()) {
     int slot = -1;
     for (int i = 0; i < s->max_slots; ++i)
@@ -543,7 +676,7 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
   for (int i = 0; i < s->max_slots; ++i) {
     TaskDev &T = s->h_tasks[i];
     if (s->slot_req[i] >= 0) {
-      T.plan = plan_of(s->reqs[static_cast<uint64_t>(s->slot_req[i])]);
+      T.plan = plan_of(s->reqs[static_cast<uint64_t>(s->slot_req[i])], reg);
       K = std::max(K, T.plan);
       active.push_back(i);
     } else {
@@ -578,7 +711,7 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
         while (k1 < r.k1 && s->h_tasks[s->olist[k1].y].plan > j) ++k1;
         if (k1 == r.k0) continue;
         const int end = k1 < r.k1 ? s->olist[k1].x : r.item_end;
-        MBPT_HIPCHK(ctx, launch_sample_order(a, r.order, 4, prec, false, r.k0, k1,
+        MBPT_HIPCHK(ctx, launch_sample_order(a, r.order, 4, prec, r.group, r.k0, k1,
                                              end - s->olist[r.k0].x, kBlock, ctx->stream));
       }
       MBPT_HIPCHK(ctx, launch_finish(a, 0, s->max_slots, j, ctx->desc.alpha, ctx->stream));
@@ -588,6 +721,11 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
     MBPT_HIPCHK(ctx, hipMemcpyAsync(s->pin_tasks, s->ws + s->L.tasks,
                                     s->max_slots * sizeof(TaskDev), hipMemcpyDeviceToHost,
                                     ctx->stream));
+    if (reg)
+      MBPT_HIPCHK(ctx, hipMemcpyAsync(s->pin_creslog, s->ws + s->L.creslog,
+                                      static_cast<size_t>(s->max_slots) * kLogIters * 2 * kMaxReg *
+                                          sizeof(double),
+                                      hipMemcpyDeviceToHost, ctx->stream));
     MBPT_HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     s->stage_used = 0;
     resolve_timing(ctx);
@@ -606,10 +744,13 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
       H.npass = S.npass;
       H.nterms = S.nterms;
       result_of(S, q.res);
-      const double target = std::max(q.r.sigma_rel * std::fabs(q.res.E_per_A), q.r.sigma_abs);
-      const bool converged = S.it_done >= kMinIters && q.res.sigma <= target;
+      if (reg) fold_components(s, q, S);
+      const double E = reg ? q.reg.E0 : q.res.E_per_A, sigma = reg ? q.reg.sigma0 : q.res.sigma;
+      const double target = std::max(q.r.sigma_rel * std::fabs(E), q.r.sigma_abs);
+      const bool converged =
+          S.it_done >= kMinIters && sigma <= target && (!reg || q.reg.ok);
       const bool capped = q.r.max_evals > 0 && S.nevals >= q.r.max_evals;
-      if (converged || capped || !std::isfinite(q.res.E_per_A)) {
+      if (converged || capped || !std::isfinite(q.res.E_per_A) || (reg && !std::isfinite(E))) {
         q.state = 2;
         q.t_finish = t;
         if (s->warm_dn > 0.0 && S.it_done >= kMinIters && std::isfinite(q.res.E_per_A)) {
@@ -622,6 +763,7 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
           ce.valid = true;
           ce.order = q.r.order;
           ce.id = q.r.diagram_id;
+          ce.group = q.r.group;
           ce.matter = q.r.matter;
           ce.density = q.r.density;
           ce.x = q.r.proton_fraction;
@@ -634,6 +776,7 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
         }
         s->bytes.release(q.byte_at, q.byte_n);
         s->items.release(q.item_at, q.item_n);
+        s->diags.release(q.diag_at, q.diag_n);
         s->slot_req[i] = -1;
         H = TaskDev{};
       }
@@ -672,5 +815,26 @@ extern "C" int mbpt_server_poll(mbpt_server *s, uint64_t ticket, mbpt_result *re
   if (t_submit) *t_submit = q.t_submit;
   if (t_admit) *t_admit = q.t_admit;
   if (t_finish) *t_finish = q.t_finish;
+  return MBPT_OK;
+}
+
+extern "C" int mbpt_server_poll_regularized(mbpt_server *s, uint64_t ticket, double *E,
+                                            double *sigma, double *E0, double *sigma0) {
+  if (!s) return MBPT_EINVAL;
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return MBPT_EINVAL;
+  const Req &q = it->second;
+  if (s->reg_n < 1 || q.reg.iters < 1 || !q.reg.ok) {
+    set_err(s->ctx, s->reg_n < 1 ? "server_poll_regularized: the server has no regularised "
+                                   "components"
+                                 : "server_poll_regularized: no extrapolation yet");
+    return MBPT_ESTATE;
+  }
+  for (int k = 0; k < s->reg_n; ++k) {
+    if (E) E[k] = q.reg.E[k];
+    if (sigma) sigma[k] = q.reg.sigma[k];
+  }
+  if (E0) *E0 = q.reg.E0;
+  if (sigma0) *sigma0 = q.reg.sigma0;
   return MBPT_OK;
 }

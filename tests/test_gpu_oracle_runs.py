@@ -162,11 +162,13 @@ def test_eos_move_keeps_grid_against_oracle(M, move):
 
 
 class _Server:
-    def __init__(self, M, precision, slots=8, max_samples=1 << 15):
+    def __init__(self, M, precision, slots=8, max_samples=1 << 15, reg=None):
         import torch
         self.M = M
         self.stream = torch.cuda.Stream()
         self.ctx = M.mbpt_context_create(stream=self.stream.cuda_stream, precision=precision)
+        if reg is not None:
+            M.mbpt_set_regularization(self.ctx, *reg)
         nbytes = M.mbpt_server_workspace_query(self.ctx, slots, max_samples)
         self.buf, ptr = M.device_workspace(nbytes)
         self.srv = M.mbpt_server_create(self.ctx, slots, max_samples, 64, ptr, nbytes)
@@ -220,6 +222,138 @@ def test_served_requests_against_oracle(M, precision):
         else:
             assert dev <= 3.0 * ro.sigma
             assert dev <= 1e-4 * abs(ro.mean) + 1e-2 * ro.sigma
+
+
+SERVED_GROUPS = [  # order, particle loops, matter, n, x, samples per iteration, iterations
+    (3, 1, 1, 0.12, 0.2, 1 << 14, 4), (4, 0, 1, 0.16, 0.3, 1 << 12, 3),
+    (4, 2, 0, 0.16, 0.0, 1 << 12, 3), (2, 1, 1, 0.08, 0.5, 1 << 14, 3),
+    (4, 3, 1, 0.20, 0.1, 1 << 13, 3),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_served_groups_against_oracle(M, precision):
+    """Diagram groups served together with single diagrams (the order-3 and
+    order-4 launches mix both), each against the oracle's group integral over
+    the same stream: fp64 to 1e-9, the fp32 integrand within 3 sigma and
+    1e-4 |E| + 1e-2 sigma of the fp64 oracle."""
+    prec = M.MBPT_FP64 if precision == "fp64" else M.MBPT_FP32
+    s = _Server(M, prec, slots=12)
+    try:
+        tickets = [M.mbpt_server_submit(s.srv, o, p, m, n, x, 0.0, 0.0, S, it * S, group=1)
+                   for o, p, m, n, x, S, it in SERVED_GROUPS]
+        single = [M.mbpt_server_submit(s.srv, o, d, m, n, x, 0.0, 0.0, S, it * S)
+                  for o, d, m, n, x, S, it in SERVED[1:3]]
+        s.drain()
+        res = [M.mbpt_server_poll(s.srv, t) for t in tickets + single]
+    finally:
+        s.close()
+    cases = [(o, p, m, n, x, S, it, p) for o, p, m, n, x, S, it in SERVED_GROUPS] + \
+            [(o, d, m, n, x, S, it, -1) for o, d, m, n, x, S, it in SERVED[1:3]]
+    for (o, d, m, n, x, S, it, grp), t, (r, done, *_) in zip(cases, tickets + single, res):
+        assert done and r.iters_done == it and r.n_evals == it * S
+        q = 4 if m else 2
+        pb = O.problem(o, 0 if grp >= 0 else d, density=n, proton_fraction=x, q=q, seed=1,
+                       task_key=t, group=grp, label_method=0 if q == 2 else 1)
+        ro, _, _, _ = O.integrate(pb, S, it)
+        dev = abs(r.E_per_A - ro.mean)
+        print(f"{precision} order {o} {'group p' if grp >= 0 else 'id'} {d} matter {m}: "
+              f"E {r.E_per_A:.9f} oracle {ro.mean:.9f} +- {ro.sigma:.2e}", flush=True)
+        if precision == "fp64":
+            assert r.E_per_A == pytest.approx(ro.mean, rel=1e-9, abs=1e-300)
+            assert r.sigma == pytest.approx(ro.sigma, rel=1e-6, abs=1e-300)
+        else:
+            assert dev <= 3.0 * ro.sigma
+            assert dev <= 1e-4 * abs(ro.mean) + 1e-2 * ro.sigma
+
+
+def _wls_at_zero(eta, E, s, deg):
+    A = np.vander(eta, deg + 1, increasing=True) / s[:, None]
+    coef, *_ = np.linalg.lstsq(A, E / s, rcond=None)
+    return coef[0], np.sqrt(np.linalg.inv(A.T @ A)[0, 0])
+
+
+def test_served_regularized_against_oracle(M):
+    """A server created with three regularised components: every request
+    (single diagrams and a group, neutron and nuclear matter) integrates the
+    components over its own samples; per component the inverse-variance
+    combination of the oracle's per-iteration estimates, and their quadratic
+    extrapolation to zero shift, match what the server reports.  The main
+    estimate is unchanged by the components."""
+    K, eta = 3, 1.0
+    s = _Server(M, M.MBPT_FP64, reg=(K, eta))
+    reqs = [(2, 0, 1, 0.16, 0.3, 1 << 14, 4, -1), (3, 1, 0, 0.12, 0.0, 1 << 13, 4, -1),
+            (3, 1, 1, 0.12, 0.2, 1 << 13, 3, 1), (4, 11, 1, 0.20, 0.2, 1 << 12, 3, -1)]
+    try:
+        tickets = [M.mbpt_server_submit(s.srv, o, d, m, n, x, 0.0, 0.0, S, it * S,
+                                        group=1 if g >= 0 else 0)
+                   for o, d, m, n, x, S, it, g in reqs]
+        s.drain()
+        res = [M.mbpt_server_poll(s.srv, t) for t in tickets]
+        comps = [M.mbpt_server_poll_regularized(s.srv, t, K) for t in tickets]
+    finally:
+        s.close()
+    for (o, d, m, n, x, S, it, g), t, (r, done, *_), (E, Sg, E0, S0) in zip(
+            reqs, tickets, res, comps):
+        assert done and r.iters_done == it
+        q = 4 if m else 2
+        pb = O.problem(o, 0 if g >= 0 else d, density=n, proton_fraction=x, q=q, seed=1,
+                       task_key=t, group=g, label_method=0 if q == 2 else 1, reg_k=K,
+                       reg_eta=eta)
+        ro, _, _, Iro, Vro, _ = O.integrate_reg(pb, S, it)
+        w = 1.0 / Vro
+        Eo = (Iro * w).sum(0) / w.sum(0)
+        So = 1.0 / np.sqrt(w.sum(0))
+        e0, s0 = _wls_at_zero(eta * np.arange(1, K + 1), Eo, So, 2)
+        print(f"order {o} id {d} group {g} matter {m}: E {r.E_per_A:.6e} components "
+              f"{np.round(E, 9)} oracle {np.round(Eo, 9)} E0 {E0:.9e} oracle {e0:.9e} "
+              f"+- {s0:.2e}", flush=True)
+        assert r.E_per_A == pytest.approx(ro.mean, rel=1e-9, abs=1e-300)
+        assert np.allclose(E, Eo, rtol=1e-9, atol=0)
+        assert np.allclose(Sg, So, rtol=1e-6, atol=0)
+        assert abs(E0 - e0) <= 1e-8 * abs(e0) + 1e-6 * s0 and S0 == pytest.approx(s0, rel=1e-6)
+
+
+def test_served_regularized_target_on_extrapolation(M):
+    """With components the sigma target applies to the extrapolated value,
+    whose error (components taken as independent; they share samples) is
+    several times the main estimate's: at 1% the request runs past the point
+    where the main estimate alone would have retired."""
+    K, eta = 3, 1.0
+    s = _Server(M, M.MBPT_FP64, reg=(K, eta))
+    try:
+        t = M.mbpt_server_submit(s.srv, 2, 0, 1, 0.16, 0.3, 1e-2, 0.0, 1 << 15, 1 << 24)
+        s.drain()
+        r, done, *_ = M.mbpt_server_poll(s.srv, t)
+        E, Sg, E0, S0 = M.mbpt_server_poll_regularized(s.srv, t, K)
+    finally:
+        s.close()
+    print(f"E {r.E_per_A:.6f} +- {r.sigma:.2e}; E0 {E0:.6f} +- {S0:.2e}; iterations "
+          f"{r.iters_done}", flush=True)
+    assert done and r.n_evals < 1 << 24
+    assert S0 <= 1e-2 * abs(E0)
+    assert S0 > 2.0 * r.sigma and r.sigma < 0.5e-2 * abs(r.E_per_A)
+
+
+def test_server_group_and_regularization_refusals(M):
+    s = _Server(M, M.MBPT_FP64, slots=1)
+    try:
+        for bad in ((4, 7, 1), (9, 0, 1), (2, 0, 2)):  # no group of 7 loops; order 9; group 2
+            with pytest.raises(M.MbptError) as e:
+                M.mbpt_server_submit(s.srv, bad[0], bad[1], 1, 0.16, 0.3, 0.0, 0.0, 1 << 12,
+                                     1 << 13, group=bad[2])
+            assert e.value.code == M.MBPT_EINVAL
+        # the largest fifth-order group does not fit a one-slot server
+        with pytest.raises(M.MbptError) as e:
+            M.mbpt_server_submit(s.srv, 5, 1, 1, 0.16, 0.3, 0.0, 0.0, 1 << 12, 1 << 13, group=1)
+        assert e.value.code == M.MBPT_ENOMEM
+        t = M.mbpt_server_submit(s.srv, 2, 0, 1, 0.16, 0.3, 0.0, 0.0, 1 << 12, 1 << 13)
+        s.drain()
+        with pytest.raises(M.MbptError) as e:  # no components on this server
+            M.mbpt_server_poll_regularized(s.srv, t, 2)
+        assert e.value.code == M.MBPT_ESTATE
+    finally:
+        s.close()
 
 
 def test_integrate_batch_against_oracle(M):
