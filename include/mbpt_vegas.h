@@ -361,23 +361,26 @@ int mbpt_hf_nodes(mbpt_task_set *set, int task, int tau, double *sigma_host, dou
 int mbpt_dump_samples_reg(mbpt_task_set *set, int task, uint32_t iter, uint64_t first,
                           uint64_t count, double *wreg_host);
 /* Per-iteration estimates of the regularised components of a task for the
- * iterations stored since the last reset (at most max_iters, oldest first):
- * I[i * n_eta + k], var[i * n_eta + k] for component k + 1 (shifted sums over
- * the same samples as the main estimate, with its shift).  *count receives
- * the iterations written (0 if none ran with components).  I, var: host
- * memory of cap * n_eta doubles, may be NULL. */
+ * iterations stored since the last reset (at most max_iters, oldest first),
+ * n_eta + 1 columns: I[i * (n_eta + 1) + k], var[i * (n_eta + 1) + k] for
+ * component k + 1 (k < n_eta; shifted sums over the same samples as the main
+ * estimate, with its shift), and in column n_eta the extrapolation to zero
+ * shift, integrated per sample as sum_k a_k w_k (a_k: the weights with which
+ * the equal-weight least-squares polynomial of degree min(2, n_eta - 1) in
+ * eta_k = k eta through the components takes its value at eta = 0; for three
+ * components 3, -3, 1), so that its variance carries the components'
+ * correlation.  *count receives the iterations written (0 if none ran with
+ * components).  I, var: host memory of cap * (n_eta + 1) doubles, may be
+ * NULL. */
 int mbpt_regularized_log(mbpt_task_set *set, int task, double *I, double *var, int cap,
                          int *count);
 /* Cumulative regularised components of a task and their extrapolation to
- * eta = 0 (Sec. "Automated approach": a quadratic fitted to the components).  Each component
+ * eta = 0 (Sec. III.A: a quadratic fitted to the components).  Each
+ * component, and the extrapolation (column n_eta of mbpt_regularized_log),
  * combines the logged iterations from index skip_iters on by inverse
- * variance, into E[n_eta] +- sigma[n_eta] (may be NULL).  E0 +- sigma0 (may
- * be NULL) is the constant term of the weighted least-squares polynomial in
- * eta_k = k eta of degree min(2, n_eta - 1) (n_eta = 1: the one component);
- * its error takes the components as independent, which they are not (they
- * share samples), so it is an indication only.  MBPT_ESTATE without logged
- * components or with no positive variance after skip_iters; MBPT_ENUMERIC if
- * the fit is singular. */
+ * variance, into E[n_eta] +- sigma[n_eta] and E0 +- sigma0 (each may be
+ * NULL).  MBPT_ESTATE without logged components or with no positive variance
+ * after skip_iters. */
 int mbpt_regularized(mbpt_task_set *set, int task, int skip_iters, double *E, double *sigma,
                      double *E0, double *sigma0);
 /* One-shot batch over many (diagram, EOS point) tasks: a task set of the n
@@ -486,10 +489,11 @@ int mbpt_task_flops(const mbpt_task_set *set, int task, double *flops, double *t
  * at mbpt_server_workspace_query and mbpt_server_create applies to every
  * request of the server for its lifetime (later changes of the context's
  * setting do not reach it).  Each request then also integrates the n_eta
- * shifted components over the same samples (fp64 integrand, whatever the
- * precision), the host combines them by inverse variance every step, and the
- * sigma target applies to their extrapolation to zero shift (see
- * mbpt_server_poll_regularized) instead of the main estimate. */
+ * shifted components and their extrapolation to zero shift over the same
+ * samples (fp64 integrand, whatever the precision; see mbpt_regularized_log),
+ * the host combines them by inverse variance every step, and the sigma target
+ * applies to the extrapolation (see mbpt_server_poll_regularized) instead of
+ * the main estimate. */
 typedef struct mbpt_request {
   int order;
   int diagram_id;       /* diagram id, or with group = 1 particle-carried loops */
@@ -532,14 +536,12 @@ int mbpt_server_warm_starts(const mbpt_server *srv, uint64_t *count);
 int mbpt_server_poll(mbpt_server *srv, uint64_t ticket, mbpt_result *res, int *done,
                      double *t_submit, double *t_admit, double *t_finish);
 /* Regularised components of a ticket (a server created with components):
- * E[n_eta] +- sigma[n_eta] per component, combined over the request's
- * iterations by inverse variance (iterations without variance are exact),
- * and E0 +- sigma0, the constant term of the weighted least-squares
- * polynomial in eta_k = k eta of degree min(2, n_eta - 1) (as
- * mbpt_regularized, an indication only: the components share samples).
- * Current values for a resident request, final ones once retired; the
- * pointers may be NULL.  EINVAL on an unknown ticket, ESTATE without
- * components or before the first extrapolation. */
+ * E[n_eta] +- sigma[n_eta] per component and E0 +- sigma0 for the
+ * extrapolation to zero shift (as in mbpt_regularized), each combined over
+ * the request's iterations by inverse variance (iterations without variance
+ * are exact).  Current values for a resident request, final ones once
+ * retired; the pointers may be NULL.  EINVAL on an unknown ticket, ESTATE
+ * without components or before the request's first iteration. */
 int mbpt_server_poll_regularized(mbpt_server *srv, uint64_t ticket, double *E, double *sigma,
                                  double *E0, double *sigma0);
 

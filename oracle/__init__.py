@@ -112,6 +112,7 @@ def lib():
         L.orc_eval_x.argtypes = [ctypes.POINTER(Problem), dp, ctypes.c_uint64, dp]
         L.orc_sample_values_reg.argtypes = [ctypes.POINTER(Problem), dp, ctypes.c_uint32,
                                             ctypes.c_uint64, ctypes.c_uint64, dp]
+        L.orc_extrapolation_weights.argtypes = [ctypes.c_int, dp]
         L.orc_integrate_reg.argtypes = [ctypes.POINTER(Problem), dp, ctypes.c_uint64, ctypes.c_int,
                                         ctypes.c_uint32, ctypes.c_int, dp, dp,
                                         ctypes.POINTER(Result), dp, dp]
@@ -194,21 +195,37 @@ def sample_values_reg(pb, edges, it, first, count):
     return out
 
 
-def integrate_reg(pb, N, iters, edges=None, nthreads=0):
+def integrate_reg(pb, N, iters, edges=None, nthreads=0, extrapolation=False):
     """VEGAS run with the regularised components: (Result, I, var, Ireg[iters, K],
-    Vreg[iters, K], edges)."""
+    Vreg[iters, K], edges); with extrapolation=True also the per-iteration
+    estimates and variances of the extrapolation to zero shift, integrated per
+    sample as sum_k a_k w_k: (Result, I, var, Ireg, Vreg, Iex[iters],
+    Vex[iters], edges)."""
     d = diagram(pb.order, pb.diagram_id if pb.group < 0 else 0)
     if edges is None:
         edges = uniform_grid(d.ndim, pb.n_bins)
     edges = np.array(edges, dtype=np.float64)
     I, V = np.zeros(iters), np.zeros(iters)
-    Ir, Vr = np.zeros((iters, pb.reg_k)), np.zeros((iters, pb.reg_k))
+    K = pb.reg_k
+    Ir, Vr = np.zeros((iters, K + 1)), np.zeros((iters, K + 1))
     r = Result()
     rc = lib().orc_integrate_reg(ctypes.byref(pb), _dp(edges), N, iters, 0, nthreads, _dp(I),
                                  _dp(V), ctypes.byref(r), _dp(Ir), _dp(Vr))
     if rc:
         raise ValueError(f"orc_integrate_reg -> {rc}")
-    return r, I, V, Ir, Vr, edges
+    if extrapolation:
+        return r, I, V, Ir[:, :K].copy(), Vr[:, :K].copy(), Ir[:, K].copy(), Vr[:, K].copy(), edges
+    return r, I, V, Ir[:, :K].copy(), Vr[:, :K].copy(), edges
+
+
+def extrapolation_weights(K):
+    """a_k with sum_k a_k y_k = value at eta = 0 of the equal-weight least-squares
+    polynomial of degree min(2, K - 1) through (k eta, y_k), k = 1..K."""
+    a = np.zeros(K)
+    rc = lib().orc_extrapolation_weights(K, _dp(a))
+    if rc:
+        raise ValueError(f"orc_extrapolation_weights -> {rc}")
+    return a
 
 
 def eval_x(pb, x):

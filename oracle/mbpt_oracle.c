@@ -1181,9 +1181,50 @@ void orc_combine(int K, const double *I, const double *var, orc_result *res) {
  * order, so results do not depend on the thread count.  The variance sums use
  * the previous iteration's estimate as shift: S1 = sum(w - c),
  * S2 = sum (w - c)^2, I = c + S1/N, var = (S2/N - (S1/N)^2)/(N - 1). */
+/* Weights a_k (k = 1..K) of the extrapolation to zero shift: the value at
+ * eta = 0 of the least-squares polynomial of degree min(2, K - 1) through the
+ * K points (k eta, y_k) with equal weights is sum_k a_k y_k (independent of
+ * eta).  Written out as a = first row of (V^T V)^{-1} V^T, V[k][j] = k^j,
+ * with the normal equations solved by Gauss-Jordan elimination. */
+int orc_extrapolation_weights(int K, double *a) {
+  if (K < 1 || K > ORC_MAXREG) return -3;
+  const int m = K - 1 < 2 ? K - 1 + 1 : 3;  /* polynomial coefficients */
+  double A[3][3] = {{0}}, Inv[3][3] = {{0}};
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j)
+      for (int k = 1; k <= K; ++k) A[i][j] += pow((double)k, i) * pow((double)k, j);
+  for (int i = 0; i < m; ++i) Inv[i][i] = 1.0;
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    for (int j = 0; j < m; ++j) {
+      double t = A[c][j]; A[c][j] = A[piv][j]; A[piv][j] = t;
+      t = Inv[c][j]; Inv[c][j] = Inv[piv][j]; Inv[piv][j] = t;
+    }
+    const double d = A[c][c];
+    for (int j = 0; j < m; ++j) { A[c][j] /= d; Inv[c][j] /= d; }
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double f = A[r][c];
+      for (int j = 0; j < m; ++j) { A[r][j] -= f * A[c][j]; Inv[r][j] -= f * Inv[c][j]; }
+    }
+  }
+  for (int k = 1; k <= K; ++k) {
+    double v = 0.0;
+    for (int j = 0; j < m; ++j) v += Inv[0][j] * pow((double)k, j);
+    a[k - 1] = v;
+  }
+  return 0;
+}
+
 /* nreg > 0: the integrand's regularised components are estimated from the
  * same samples (shifted sums with the main component's shift; the grid
- * adapts to the main component), per iteration into Ireg/Vreg[it * nreg + k]. */
+ * adapts to the main component), per iteration into Ireg/Vreg[it * (nreg + 1)
+ * + k] for component k + 1, and in column nreg the extrapolation to zero
+ * shift integrated as an integrand of its own: sum_k a_k w_k per sample
+ * (orc_extrapolation_weights), so that its variance carries the components'
+ * correlation (they share samples). */
 static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_key,
                      integrand_fn fn, const void *ctx, double *edges, uint64_t N,
                      int iters, uint32_t first_iter, int nthreads, double *I_out,
@@ -1195,8 +1236,11 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
   double *chist = calloc((size_t)nchunks * nd * nb, sizeof(double));
   ksum *cs1 = calloc(nchunks, sizeof(ksum));
   ksum *cs2 = calloc(nchunks, sizeof(ksum));
-  ksum *cr1 = calloc(nchunks * (nreg > 0 ? nreg : 1), sizeof(ksum));
-  ksum *cr2 = calloc(nchunks * (nreg > 0 ? nreg : 1), sizeof(ksum));
+  const int ncol = nreg > 0 ? nreg + 1 : 1;  /* components, then the extrapolation */
+  double ax[ORC_MAXREG] = {0};
+  if (nreg > 0 && orc_extrapolation_weights(nreg, ax)) return -3;
+  ksum *cr1 = calloc(nchunks * ncol, sizeof(ksum));
+  ksum *cr2 = calloc(nchunks * ncol, sizeof(ksum));
   double *I = calloc(iters, sizeof(double)), *V = calloc(iters, sizeof(double));
   if (!chist || !cs1 || !cs2 || !cr1 || !cr2 || !I || !V) return -4;
   double shift = 0.0;
@@ -1208,8 +1252,8 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
     memset(chist, 0, sizeof(double) * (size_t)nchunks * nd * nb);
 #pragma omp parallel for schedule(dynamic, 1)
     for (long long c = 0; c < (long long)nchunks; ++c) {
-      ksum s1 = {0, 0}, s2 = {0, 0}, r1[ORC_MAXREG], r2[ORC_MAXREG];
-      for (int k = 0; k < ORC_MAXREG; ++k) r1[k] = r2[k] = (ksum){0, 0};
+      ksum s1 = {0, 0}, s2 = {0, 0}, r1[ORC_MAXREG + 1], r2[ORC_MAXREG + 1];
+      for (int k = 0; k <= ORC_MAXREG; ++k) r1[k] = r2[k] = (ksum){0, 0};
       double *h = chist + (size_t)c * nd * nb;
       uint64_t s0 = (uint64_t)c * ORC_CHUNK;
       uint64_t s1e = s0 + ORC_CHUNK < N ? s0 + ORC_CHUNK : N;
@@ -1221,31 +1265,38 @@ static int vegas_run(int nd, int nb, double alpha, uint32_t seed, uint32_t task_
         double w = jv * fn(ctx, x, NULL, nreg > 0 ? wr : NULL);
         ksum_add(&s1, w - shift);
         ksum_add(&s2, (w - shift) * (w - shift));
-        for (int k = 0; k < nreg; ++k) {
-          const double u = jv * wr[k] - shift;
-          ksum_add(&r1[k], u);
-          ksum_add(&r2[k], u * u);
+        if (nreg > 0) {
+          double ex = 0.0;
+          for (int k = 0; k < nreg; ++k) {
+            const double u = jv * wr[k] - shift;
+            ksum_add(&r1[k], u);
+            ksum_add(&r2[k], u * u);
+            ex += ax[k] * jv * wr[k];
+          }
+          const double u = ex - shift;
+          ksum_add(&r1[nreg], u);
+          ksum_add(&r2[nreg], u * u);
         }
         for (int m = 0; m < nd; ++m) h[m * nb + bins[m]] += w * w;
       }
       cs1[c] = s1;
       cs2[c] = s2;
-      for (int k = 0; k < nreg; ++k) {
-        cr1[c * nreg + k] = r1[k];
-        cr2[c * nreg + k] = r2[k];
+      for (int k = 0; k < ncol && nreg > 0; ++k) {
+        cr1[c * ncol + k] = r1[k];
+        cr2[c * ncol + k] = r2[k];
       }
     }
-    for (int k = 0; k < nreg; ++k) {
+    for (int k = 0; k < ncol && nreg > 0; ++k) {
       ksum R1 = {0, 0}, R2 = {0, 0};
       for (uint64_t c = 0; c < nchunks; ++c) {
-        ksum_add(&R1, ksum_val(&cr1[c * nreg + k]));
-        ksum_add(&R2, ksum_val(&cr2[c * nreg + k]));
+        ksum_add(&R1, ksum_val(&cr1[c * ncol + k]));
+        ksum_add(&R2, ksum_val(&cr2[c * ncol + k]));
       }
       const double q1 = ksum_val(&R1) / (double)N, q2 = ksum_val(&R2) / (double)N;
       double v = (q2 - q1 * q1) / (double)(N - 1);
       if (v < 0.0) v = 0.0;
-      if (Ireg) Ireg[(size_t)it * nreg + k] = shift + q1;
-      if (Vreg) Vreg[(size_t)it * nreg + k] = v;
+      if (Ireg) Ireg[(size_t)it * ncol + k] = shift + q1;
+      if (Vreg) Vreg[(size_t)it * ncol + k] = v;
     }
     ksum S1 = {0, 0}, S2 = {0, 0};
     for (uint64_t c = 0; c < nchunks; ++c) {

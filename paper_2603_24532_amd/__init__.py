@@ -469,15 +469,19 @@ def mbpt_dump_samples_reg(s, task, it, first, count, n_eta):
     return out
 
 
-def mbpt_regularized_log(s, task, n_eta, cap=1024):
-    """Per-iteration component estimates: (I[iters, n_eta], var[iters, n_eta])."""
+def mbpt_regularized_log(s, task, n_eta, cap=1024, extrapolation=False):
+    """Per-iteration component estimates: (I[iters, n_eta], var[iters, n_eta]);
+    with extrapolation=True also the extrapolation's (I0[iters], var0[iters])."""
     import numpy as np
-    I = np.zeros((cap, n_eta))
-    V = np.zeros((cap, n_eta))
+    I = np.zeros((cap, n_eta + 1))
+    V = np.zeros((cap, n_eta + 1))
     n = ctypes.c_int()
     _check(lib().mbpt_regularized_log(s, task, I.ctypes.data_as(_DP), V.ctypes.data_as(_DP), cap,
                                       ctypes.byref(n)), _ctx_of_set(s))
-    return I[:n.value].copy(), V[:n.value].copy()
+    I, V = I[:n.value], V[:n.value]
+    if extrapolation:
+        return I[:, :n_eta].copy(), V[:, :n_eta].copy(), I[:, n_eta].copy(), V[:, n_eta].copy()
+    return I[:, :n_eta].copy(), V[:, :n_eta].copy()
 
 
 def mbpt_regularized(s, task, n_eta, skip_iters=0):

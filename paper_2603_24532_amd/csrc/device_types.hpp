@@ -157,6 +157,11 @@ constexpr int kHfGauss = 64;  // Gauss-Legendre points per dimension
 
 // Regularised energy-denominator components (D_c -> D_c - k eta, k = 1..nreg).
 constexpr int kMaxReg = 4;
+// Sums per work item and per logged iteration of the regularised modes: a
+// (sum, sum of squares) or (I, var) pair for each of the kMaxReg components,
+// then one for the extrapolation to zero shift integrated per sample as
+// sum_k reg_coef[k] w_k.
+constexpr int kRegSums = 2 * (kMaxReg + 1);
 
 // Iteration-end kernel: threads per task block and item loads in flight per
 // thread.
@@ -215,10 +220,11 @@ struct KArgs {
   const double *gcoef;    // factorised label-sum coefficients (see coef_slots)
   const int2 *olist;      // (first item, task), grouped by order, ascending items
   double *hf;             // HF spline entries, 4 doubles each
-  double *cpart;          // per item: 2 kMaxReg component sums (regularised modes)
-  double *creslog;        // per logged iteration: kMaxReg (I, var) pairs
+  double *cpart;          // per item: kRegSums component sums (regularised modes)
+  double *creslog;        // per logged iteration: kRegSums, (I, var) pairs
   int *queue;             // per order: work-item counter of the persistent launches (may be null)
   double reg_eta;         // component k + 1 shifts every denominator by -(k + 1) reg_eta
+  double reg_coef[kMaxReg];  // extrapolation weights (0 beyond nreg)
   int nreg;               // components (0: none)
   int pad_reg;
   int ntasks;

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kFinishThreads) void finish_iteration(KArgs a, int 
   constexpr int NW = kFinishThreads / 64;
   __shared__ double red[NW * 4];
   __shared__ unsigned long long kred[NW][kItemCounters];
-  __shared__ double cred[NW][2 * kMaxReg];
+  __shared__ double cred[NW][kRegSums];
   extern __shared__ double scratch[];
   const int t = first_task + blockIdx.x;
   TaskDev *T = a.tasks + t;
@@ -141,22 +141,22 @@ __global__ __launch_bounds__(kFinishThreads) void finish_iteration(KArgs a, int 
   // regularised components (same samples, main component's shift): item
   // sums in item order per thread, then across the block
   if (a.nreg > 0) {
-    double cs[2 * kMaxReg];
+    double cs[kRegSums];
 #pragma unroll
-    for (int j = 0; j < 2 * kMaxReg; ++j) cs[j] = 0.0;
+    for (int j = 0; j < kRegSums; ++j) cs[j] = 0.0;
     for (int it = it0 + tid; it < it1; it += bs) {
-      const double *C = a.cpart + 2 * kMaxReg * static_cast<size_t>(it);
+      const double *C = a.cpart + kRegSums * static_cast<size_t>(it);
 #pragma unroll
-      for (int j = 0; j < 2 * kMaxReg; ++j) cs[j] += C[j];
+      for (int j = 0; j < kRegSums; ++j) cs[j] += C[j];
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
-      for (int j = 0; j < 2 * kMaxReg; ++j) cs[j] += __shfl_xor(cs[j], off, 64);
+      for (int j = 0; j < kRegSums; ++j) cs[j] += __shfl_xor(cs[j], off, 64);
     }
     if ((tid & 63) == 0) {
 #pragma unroll
-      for (int j = 0; j < 2 * kMaxReg; ++j) cred[tid >> 6][j] = cs[j];
+      for (int j = 0; j < kRegSums; ++j) cred[tid >> 6][j] = cs[j];
     }
   }
   double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
@@ -221,8 +221,10 @@ __global__ __launch_bounds__(kFinishThreads) void finish_iteration(KArgs a, int 
       lg[0] = I;
       lg[1] = var;
       if (a.nreg > 0) {
-        double *cl = a.creslog + 2 * kMaxReg * static_cast<size_t>(slot);
-        for (int r = 0; r < a.nreg; ++r) {
+        // components 1..nreg, then the extrapolation in the last pair
+        double *cl = a.creslog + kRegSums * static_cast<size_t>(slot);
+        for (int j = 0; j <= a.nreg; ++j) {
+          const int r = j < a.nreg ? j : kMaxReg;
           double q1 = cred[0][2 * r], q2 = cred[0][2 * r + 1];
           for (int w = 1; w < (bs >> 6); ++w) {
             q1 += cred[w][2 * r];

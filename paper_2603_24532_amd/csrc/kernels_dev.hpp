@@ -1327,9 +1327,9 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
   // regularised components: sum (w_k - shift) and sum (w_k - shift)^2 with
   // the main component's shift (a thread adds at most spt terms: plain sums)
   constexpr bool R = reg_of<P>();
-  double rs[R ? 2 * kMaxReg : 1];
+  double rs[R ? kRegSums : 1];
 #pragma unroll
-  for (int j = 0; j < (R ? 2 * kMaxReg : 1); ++j) rs[j] = 0.0;
+  for (int j = 0; j < (R ? kRegSums : 1); ++j) rs[j] = 0.0;
   // a thread adds at most spt terms of the shifted sums: plain sums; the
   // merges across threads and items keep the rounding errors
   auto accumulate = [&](double w, const int *bins) {
@@ -1360,12 +1360,18 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
                 eval_fp64<ORDER, Q, false, G, X, PI, V, true, HE>(a, T, D, Ls, jc, s, iter, bins,
                                                                   npass, nterms, wr);
             accumulate(w, bins);
+            // the extrapolation's weights sum to one, so its shifted value
+            // is the weighted sum of the components' shifted values
+            double dx = 0.0;
 #pragma unroll
             for (int r = 0; r < kMaxReg; ++r) {
               const double d = wr[r] - shift;
               rs[2 * r] += d;
               rs[2 * r + 1] += d * d;
+              dx = fma(a.reg_coef[r], d, dx);
             }
+            rs[2 * kMaxReg] += dx;
+            rs[2 * kMaxReg + 1] += dx * dx;
           } else {
             const double w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V, false, HE>(
                 a, T, D, Ls, jc, s, iter, bins, npass, nterms);
@@ -1433,7 +1439,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
     nfb += __shfl_xor(nfb, off, 64);
     if constexpr (R) {
 #pragma unroll
-      for (int j = 0; j < 2 * kMaxReg; ++j) rs[j] += __shfl_xor(rs[j], off, 64);
+      for (int j = 0; j < kRegSums; ++j) rs[j] += __shfl_xor(rs[j], off, 64);
     }
   }
   const int wave = tid >> 6, lane = tid & 63;
@@ -1443,7 +1449,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
   if constexpr (R) {
     if (lane == 0) {
 #pragma unroll
-      for (int j = 0; j < 2 * kMaxReg; ++j) rred[2 * kMaxReg * wave + j] = rs[j];
+      for (int j = 0; j < kRegSums; ++j) rred[kRegSums * wave + j] = rs[j];
     }
   }
   if (lane == 0) {
@@ -1477,10 +1483,10 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
     K[1] = P1;
     K[2] = P2;
     if constexpr (R) {
-      double *cp = a.cpart + 2 * kMaxReg * store;
-      for (int j = 0; j < 2 * kMaxReg; ++j) {
+      double *cp = a.cpart + kRegSums * store;
+      for (int j = 0; j < kRegSums; ++j) {
         double v = rred[j];
-        for (int w = 1; w < (bs >> 6); ++w) v += rred[2 * kMaxReg * w + j];
+        for (int w = 1; w < (bs >> 6); ++w) v += rred[kRegSums * w + j];
         cp[j] = v;
       }
     }

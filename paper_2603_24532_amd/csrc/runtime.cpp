@@ -636,9 +636,9 @@ Layout layout_of(const mbpt_task_set *set, uint64_t max_samples, int max_iters, 
   off = align256(off + 2 * kHfGauss * sizeof(double));
   // regularised components: per-item sums and per-iteration estimates
   L.cpart = off;
-  off = align256(off + items * 2 * kMaxReg * sizeof(double));
+  off = align256(off + items * kRegSums * sizeof(double));
   L.creslog = off;
-  off = align256(off + nt * static_cast<size_t>(std::max(1, max_iters)) * 2 * kMaxReg *
+  off = align256(off + nt * static_cast<size_t>(std::max(1, max_iters)) * kRegSums *
                            sizeof(double));
   L.queue = off;  // work-item counters of the persistent launches
   off = align256(off + kQueueSlots * sizeof(int));
@@ -666,6 +666,7 @@ KArgs kargs_of(const mbpt_task_set *set) {
   a.queue = set->d_queue;
   a.nreg = ctx->reg_n;
   a.reg_eta = ctx->reg_eta;
+  extrapolation_weights(ctx->reg_n, a.reg_coef);
   a.ntasks = static_cast<int>(set->tasks.size());
   a.total_items = 0;
   a.spt = set->spt;
@@ -1436,7 +1437,7 @@ extern "C" int mbpt_dump_samples_reg(mbpt_task_set *set, int task, uint32_t iter
   }
   KArgs a = kargs_of(set);
   // staging: main weights in the item partials, components in the item
-  // component sums (2 kMaxReg doubles per item)
+  // component sums (kRegSums doubles per item)
   const uint64_t cap = set->max_items * 2;
   for (uint64_t done = 0; done < count;) {
     const uint64_t n = std::min<uint64_t>(cap, count - done);
@@ -1460,18 +1461,20 @@ extern "C" int mbpt_regularized_log(mbpt_task_set *set, int task, double *I, dou
   TaskDev S;
   HIPCHK(ctx, hipMemcpyAsync(&S, set->d_tasks + task, sizeof(TaskDev), hipMemcpyDeviceToHost,
                              ctx->stream));
-  const size_t per = 2 * static_cast<size_t>(kMaxReg);
+  const size_t per = kRegSums;
   std::vector<double> lg(per * set->max_iters);
   HIPCHK(ctx, hipMemcpyAsync(lg.data(), set->d_creslog + per * task * set->max_iters,
                              lg.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   const int n = K > 0 ? std::min(std::min(S.it_done, set->max_iters), cap) : 0;
   const int start = S.it_done - n;
+  // columns: components 1..K, then the extrapolation (last pair of a log entry)
   for (int i = 0; i < n; ++i) {
     const int slot = (start + i) % set->max_iters;
-    for (int k = 0; k < K; ++k) {
-      if (I) I[i * K + k] = lg[per * slot + 2 * k];
-      if (var) var[i * K + k] = lg[per * slot + 2 * k + 1];
+    for (int k = 0; k <= K; ++k) {
+      const int r = k < K ? k : kMaxReg;
+      if (I) I[i * (K + 1) + k] = lg[per * slot + 2 * r];
+      if (var) var[i * (K + 1) + k] = lg[per * slot + 2 * r + 1];
     }
   }
   *count = n;
@@ -1522,6 +1525,24 @@ bool poly_fit_at_zero(const double *x, const double *y, const double *sig, int n
   return true;
 }
 
+// Weights a_k of the extrapolation to zero shift: the equal-weight
+// least-squares polynomial of degree min(2, K - 1) through (k, y_k), k = 1..K,
+// takes the value sum_k a_k y_k at 0 (a_k = that value for y = the k-th unit
+// vector; the shift's scale drops out).  Zero beyond K.
+void extrapolation_weights(int K, double *a) {
+  double x[kMaxReg], ones[kMaxReg], e[kMaxReg];
+  for (int k = 0; k < kMaxReg; ++k) {
+    x[k] = k + 1.0;
+    ones[k] = 1.0;
+    a[k] = 0.0;
+  }
+  for (int k = 0; k < K; ++k) {
+    for (int j = 0; j < K; ++j) e[j] = j == k ? 1.0 : 0.0;
+    double c0 = 0.0, s0 = 0.0;
+    if (poly_fit_at_zero(x, e, ones, K, std::min(2, K - 1), c0, s0)) a[k] = c0;
+  }
+}
+
 }  // namespace mbpt
 
 extern "C" int mbpt_regularized(mbpt_task_set *set, int task, int skip_iters, double *E,
@@ -1535,37 +1556,34 @@ extern "C" int mbpt_regularized(mbpt_task_set *set, int task, int skip_iters, do
     set_err(ctx, "regularized: no iterations with regularised components since the last reset");
     return MBPT_ESTATE;
   }
-  std::vector<double> I(static_cast<size_t>(set->max_iters) * K), V(I.size());
+  std::vector<double> I(static_cast<size_t>(set->max_iters) * (K + 1)), V(I.size());
   int n = 0;
   const int rc = mbpt_regularized_log(set, task, I.data(), V.data(), set->max_iters, &n);
   if (rc) return rc;
-  double Ek[kMaxReg], Sk[kMaxReg], eta[kMaxReg];
-  for (int k = 0; k < K; ++k) {
+  // components 1..K, then the extrapolation (column K), each combined over
+  // the iterations from skip_iters on by inverse variance
+  for (int k = 0; k <= K; ++k) {
     double w = 0.0, wi = 0.0;
     for (int i = skip_iters; i < n; ++i) {
-      const double v = V[static_cast<size_t>(i) * K + k];
+      const double v = V[static_cast<size_t>(i) * (K + 1) + k];
       if (v > 0.0) {
         w += 1.0 / v;
-        wi += I[static_cast<size_t>(i) * K + k] / v;
+        wi += I[static_cast<size_t>(i) * (K + 1) + k] / v;
       }
     }
     if (!(w > 0.0)) {
       set_err(ctx, "regularized: no iteration with a positive variance after the skipped ones");
       return MBPT_ESTATE;
     }
-    Ek[k] = wi / w;
-    Sk[k] = 1.0 / std::sqrt(w);
-    eta[k] = (k + 1) * set->run_reg_eta;
-    if (E) E[k] = Ek[k];
-    if (sigma) sigma[k] = Sk[k];
+    const double Ek = wi / w, Sk = 1.0 / std::sqrt(w);
+    if (k < K) {
+      if (E) E[k] = Ek;
+      if (sigma) sigma[k] = Sk;
+    } else {
+      if (E0) *E0 = Ek;
+      if (sigma0) *sigma0 = Sk;
+    }
   }
-  double c0 = Ek[0], s0 = Sk[0];
-  if (K > 1 && !mbpt::poly_fit_at_zero(eta, Ek, Sk, K, std::min(2, K - 1), c0, s0)) {
-    set_err(ctx, "regularized: singular extrapolation fit");
-    return MBPT_ENUMERIC;
-  }
-  if (E0) *E0 = c0;
-  if (sigma0) *sigma0 = s0;
   return MBPT_OK;
 }
 

@@ -124,6 +124,7 @@ int compile_task_diagrams(mbpt_context *ctx, int q, int order, int id, bool grou
                           FlopModel &model);
 bool poly_fit_at_zero(const double *x, const double *y, const double *sig, int n, int deg,
                       double &c0, double &s0);
+void extrapolation_weights(int K, double *a);
 bool fixed_masks_ok();
 void fill_medium(const mbpt_context *ctx, double density, double x, TaskDev &T);
 void result_of(const TaskDev &S, mbpt_result &r);

@@ -96,16 +96,17 @@ struct Ranges {
   }
 };
 
-// Regularised components of a request, combined over its iterations on the
-// host: inverse-variance sums of the iterations with a positive variance, and
-// count and sum of those without (exact: every sample zero or equal).
+// Regularised components of a request and their extrapolation to zero shift
+// (index kMaxReg), combined over its iterations on the host: inverse-variance
+// sums of the iterations with a positive variance, and count and sum of those
+// without (exact: every sample zero or equal).
 struct RegSums {
-  double w[kMaxReg] = {}, wi[kMaxReg] = {}, zsum[kMaxReg] = {};
-  int nzero[kMaxReg] = {};
+  double w[kMaxReg + 1] = {}, wi[kMaxReg + 1] = {}, zsum[kMaxReg + 1] = {};
+  int nzero[kMaxReg + 1] = {};
   int iters = 0;  // iterations folded in
   double E[kMaxReg] = {}, sigma[kMaxReg] = {};
   double E0 = 0.0, sigma0 = 0.0;
-  bool ok = false;  // estimates and extrapolation valid
+  bool ok = false;  // estimates valid (at least one iteration)
 };
 
 struct Req {
@@ -146,7 +147,7 @@ size_t items_of(uint64_t samples, int spt) {
 
 size_t per_item_bytes(int nreg) {
   return 4 * sizeof(double) + kItemCounters * sizeof(uint64_t) +
-         (nreg > 0 ? 2 * kMaxReg * sizeof(double) : 0);
+         (nreg > 0 ? kRegSums * sizeof(double) : 0);
 }
 
 // Slot table, descriptor table, log rings and warm-start cache, then the
@@ -168,7 +169,7 @@ size_t fixed_layout(int slots, int nb, Layout &L) {
   L.reslog = off;
   off = a256(off + static_cast<size_t>(slots) * kLogIters * 2 * sizeof(double));
   L.creslog = off;
-  off = a256(off + static_cast<size_t>(slots) * kLogIters * 2 * kMaxReg * sizeof(double));
+  off = a256(off + static_cast<size_t>(slots) * kLogIters * kRegSums * sizeof(double));
   L.cache = off;  // grids of recent retirements (warm starts)
   off = a256(off + static_cast<size_t>(slots) * kMaxDim * (nb + 1) * sizeof(double));
   L.arena = off;
@@ -185,7 +186,7 @@ bool make_layout(int slots, int nb, int nreg, size_t bytes, Layout &L) {
   L.partials = a256(off);
   L.counters = a256(L.partials + L.max_items * 4 * sizeof(double));
   L.cpart = a256(L.counters + L.max_items * kItemCounters * sizeof(uint64_t));
-  const size_t end = nreg > 0 ? L.cpart + L.max_items * 2 * kMaxReg * sizeof(double) : L.cpart;
+  const size_t end = nreg > 0 ? L.cpart + L.max_items * kRegSums * sizeof(double) : L.cpart;
   return end <= bytes;
 }
 
@@ -277,6 +278,7 @@ KArgs server_kargs(const mbpt_server *s) {
   a.cpart = s->reg_n > 0 ? reinterpret_cast<double *>(b + s->L.cpart) : nullptr;
   a.nreg = s->reg_n;
   a.reg_eta = s->reg_eta;
+  extrapolation_weights(s->reg_n, a.reg_coef);
   a.ntasks = s->max_slots;
   a.spt = s->spt;
   a.label_mode = ctx->desc.label_mode;
@@ -468,60 +470,44 @@ int admit_one(mbpt_server *s, Req &q, int slot) {
   return 0;
 }
 
-// Folds the iterations a request ran since the last step into its component
-// sums (from the slot's log ring, read back with the step's state) and
-// updates the component estimates and their extrapolation to zero shift:
-// each component combines its iterations by inverse variance (iterations
-// without variance are exact: their plain mean, sigma 0, as for the main
-// estimate); E0 +- sigma0 is the constant term of the weighted least-squares
-// polynomial in eta_k = k eta of degree min(2, K - 1), unweighted with sigma0
-// = 0 when every component is exact.
+// Folds the iterations a request ran since the last step into its sums of
+// the components and of the extrapolation (from the slot's log ring, read back
+// with the step's state: components in the first pairs of a log entry, the
+// extrapolation in its last pair) and updates the estimates: each combines its
+// iterations by inverse variance; iterations without variance are exact
+// (their plain mean, sigma 0, as for the main estimate).
 void fold_components(mbpt_server *s, Req &q, const TaskDev &S) {
   RegSums &g = q.reg;
   const int K = s->reg_n;
   for (int it = g.iters; it < S.it_done; ++it) {
-    const double *cl =
-        s->pin_creslog + static_cast<size_t>(S.res_off + it % kLogIters) * 2 * kMaxReg;
-    for (int k = 0; k < K; ++k) {
-      const double I = cl[2 * k], v = cl[2 * k + 1];
+    const double *cl = s->pin_creslog + static_cast<size_t>(S.res_off + it % kLogIters) * kRegSums;
+    for (int j = 0; j <= K; ++j) {
+      const int r = j < K ? j : kMaxReg;
+      const double I = cl[2 * r], v = cl[2 * r + 1];
       if (v > 0.0) {
-        g.w[k] += 1.0 / v;
-        g.wi[k] += I / v;
+        g.w[r] += 1.0 / v;
+        g.wi[r] += I / v;
       } else {
-        g.zsum[k] += I;
-        ++g.nzero[k];
+        g.zsum[r] += I;
+        ++g.nzero[r];
       }
     }
   }
   g.iters = S.it_done;
   if (g.iters < 1) return;
-  double eta[kMaxReg], sig[kMaxReg], ones[kMaxReg];
-  bool exact = true;
-  for (int k = 0; k < K; ++k) {
-    if (g.nzero[k] > 0) {
-      g.E[k] = g.zsum[k] / g.nzero[k];
-      g.sigma[k] = 0.0;
+  for (int j = 0; j <= K; ++j) {
+    const int r = j < K ? j : kMaxReg;
+    const double E = g.nzero[r] > 0 ? g.zsum[r] / g.nzero[r] : g.wi[r] / g.w[r];
+    const double sg = g.nzero[r] > 0 ? 0.0 : 1.0 / std::sqrt(g.w[r]);
+    if (j < K) {
+      g.E[j] = E;
+      g.sigma[j] = sg;
     } else {
-      g.E[k] = g.wi[k] / g.w[k];
-      g.sigma[k] = 1.0 / std::sqrt(g.w[k]);
-      exact = false;
+      g.E0 = E;
+      g.sigma0 = sg;
     }
-    eta[k] = (k + 1) * s->reg_eta;
-    ones[k] = 1.0;
   }
-  bool all_positive = true;
-  for (int k = 0; k < K; ++k) all_positive = all_positive && g.sigma[k] > 0.0;
-  if (K == 1) {
-    g.E0 = g.E[0];
-    g.sigma0 = g.sigma[0];
-    g.ok = true;
-  } else if (all_positive || exact) {
-    for (int k = 0; k < K; ++k) sig[k] = all_positive ? g.sigma[k] : ones[k];
-    g.ok = poly_fit_at_zero(eta, g.E, sig, K, std::min(2, K - 1), g.E0, g.sigma0);
-    if (exact) g.sigma0 = 0.0;
-  } else {
-    g.ok = false;  // some components exact, others not: no extrapolation yet
-  }
+  g.ok = true;
 }
 
 }  // namespace
@@ -585,7 +571,7 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
                     hipHostMallocDefault) != hipSuccess ||
       (s->reg_n > 0 &&
        hipHostMalloc(reinterpret_cast<void **>(&s->pin_creslog),
-                     static_cast<size_t>(max_slots) * kLogIters * 2 * kMaxReg * sizeof(double),
+                     static_cast<size_t>(max_slots) * kLogIters * kRegSums * sizeof(double),
                      hipHostMallocDefault) != hipSuccess)) {
     set_err(ctx, "server_create: pinned host allocation failed");
     delete s;
@@ -723,7 +709,7 @@ extern "C" int mbpt_server_step(mbpt_server *s, int *n_active, int *n_queued) {
                                     ctx->stream));
     if (reg)
       MBPT_HIPCHK(ctx, hipMemcpyAsync(s->pin_creslog, s->ws + s->L.creslog,
-                                      static_cast<size_t>(s->max_slots) * kLogIters * 2 * kMaxReg *
+                                      static_cast<size_t>(s->max_slots) * kLogIters * kRegSums *
                                           sizeof(double),
                                       hipMemcpyDeviceToHost, ctx->stream));
     MBPT_HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -827,7 +813,7 @@ extern "C" int mbpt_server_poll_regularized(mbpt_server *s, uint64_t ticket, dou
   if (s->reg_n < 1 || q.reg.iters < 1 || !q.reg.ok) {
     set_err(s->ctx, s->reg_n < 1 ? "server_poll_regularized: the server has no regularised "
                                    "components"
-                                 : "server_poll_regularized: no extrapolation yet");
+                                 : "server_poll_regularized: no iteration yet");
     return MBPT_ESTATE;
   }
   for (int k = 0; k < s->reg_n; ++k) {
