@@ -312,7 +312,13 @@ int mbpt_set_launch_mode(mbpt_task_set *set, int mode);
 int mbpt_set_training(mbpt_task_set *set, int train_iters);
 /* Work decomposition: threads per block (64..256, multiple of 64; the sample
  * kernels are built for at most 256) and samples per thread per work item
- * (1..256).  Defaults 256 and 16.  EINVAL outside these ranges. */
+ * (1..256).  EINVAL outside these ranges.  Without this call the block has
+ * 256 threads and the samples per thread are chosen at mbpt_bind_workspace
+ * for the launch mode the set has then: the larger of a task's samples over
+ * about two blocks per CU (at most 16) and one launch's samples (one task in
+ * the per-task mode, all tasks of an order otherwise) over about 16 blocks
+ * per CU (at most 256).  A later mbpt_set_launch_mode keeps that choice.
+ * ESTATE for smaller work items than the bound workspace was sized for. */
 int mbpt_set_blocking(mbpt_task_set *set, int threads_per_block, int samples_per_thread);
 
 /* Device workspace bytes needed for up to max_samples_per_iter samples per
@@ -428,7 +434,7 @@ int mbpt_set_grid(mbpt_task_set *set, int task, const double *edges_host);
 
 /* Autotuner: times one iteration of the whole set for each candidate work
  * decomposition (threads per block in {64, 128, 256} x samples per thread in
- * {4, 8, 16, 32}, limited to what the bound workspace holds), keeps the
+ * {4, 8, 16, 32, 64, 128, 256}, limited to what the bound workspace holds), keeps the
  * fastest (mbpt_set_blocking) and resets the set (grids uniform, iteration 0),
  * so tuning never leaks into results.  The choice is cached per (matter,
  * precision, launch mode, orders present, samples_per_iter); a cached choice

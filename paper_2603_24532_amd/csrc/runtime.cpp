@@ -581,12 +581,29 @@ size_t items_for(const mbpt_task_set *set, uint64_t samples) {
   return static_cast<size_t>((samples + chunk - 1) / chunk);
 }
 
-// Samples per thread unless set explicitly: a task's max_samples spread over
-// about two blocks per CU (one task's iteration lasts as long as its slowest
-// block), between 1 and 16.
+// Samples per thread unless set explicitly, chosen at bind for the launch
+// mode the set has then: the larger of (a) a task's max_samples spread over
+// about two blocks per CU, at most 16 (one task's iteration lasts as long as
+// its slowest block), and (b) the samples of one launch spread over about 16
+// blocks per CU, at most 256 (a launch covers one task in the per-task mode,
+// all the tasks of an order otherwise): large work items halve the per-item
+// costs (grid and tables into LDS, the histogram merge, the last partial
+// fp64 re-evaluation round of the fp32 path) while a launch still spans many
+// rounds of blocks.
 int auto_spt(const mbpt_task_set *set, uint64_t max_samples) {
-  const uint64_t per = static_cast<uint64_t>(set->block) * 2 * std::max(1, set->ctx->num_cus);
-  return static_cast<int>(std::max<uint64_t>(1, std::min<uint64_t>(16, max_samples / per)));
+  const uint64_t cus = static_cast<uint64_t>(std::max(1, set->ctx->num_cus));
+  const uint64_t a =
+      std::max<uint64_t>(1, std::min<uint64_t>(16, max_samples / (set->block * 2 * cus)));
+  uint64_t per_launch = max_samples;
+  if (set->launch_mode != MBPT_LAUNCH_PER_TASK) {
+    int count[kMaxOrder + 1] = {};
+    int most = 1;
+    for (const auto &t : set->tasks)
+      if (t.order >= 1 && t.order <= kMaxOrder) most = std::max(most, ++count[t.order]);
+    per_launch = max_samples * static_cast<uint64_t>(most);
+  }
+  const uint64_t b = std::min<uint64_t>(256, per_launch / (set->block * 16 * cus));
+  return static_cast<int>(std::max(a, b));
 }
 
 struct Layout {
@@ -1738,7 +1755,7 @@ extern "C" int mbpt_autotune(mbpt_task_set *set, uint64_t samples_per_iter, int 
     best_s = it->second.second;
   } else {
     const int blocks[] = {64, 128, 256};
-    const int spts[] = {4, 8, 16, 32};
+    const int spts[] = {4, 8, 16, 32, 64, 128, 256};
     bool warmed = false;
     for (int b : blocks)
       for (int sp : spts) {

@@ -87,6 +87,34 @@ def test_launch_modes_against_oracle(M, mode, matter):
         run.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("block,spt", [(256, 256), (64, 128)])
+def test_large_work_items_against_oracle(M, precision, block, spt):
+    """Work items of 8192 to 65536 samples (what the automatic choice takes for
+    launches over many tasks: long per-thread sums, many fp32 re-evaluation
+    rounds per wavefront), a ragged sample count, one launch per order.  FP64:
+    every iteration as the other launch forms; the fp32 integrand: each result
+    within 3 sigma and 1e-4 |E| + 1e-2 sigma of the fp64 oracle."""
+    tasks = NUCLEAR[:3] + [_task(3, 2, 4, 0.20, 0.1, 15)]
+    N = 3 * block * spt + 12345
+    prec = M.MBPT_FP64 if precision == "fp64" else M.MBPT_FP32
+    print(f"case block={block} spt={spt} N={N} {precision}", flush=True)
+    run = Run(M, tasks, max_samples=N, mode=1, block=block, spt=spt, precision=prec)
+    try:
+        per, _ = M.mbpt_integrate(run.set, N, 3)
+        if precision == "fp64":
+            _compare_logs(M, run.set, tasks, N, 3, per, f"block {block} spt {spt}")
+            return
+    finally:
+        run.close()
+    for k, t in enumerate(tasks):
+        r, _, _, _ = _oracle_log(t, N, 3)
+        dev = abs(per[k].E_per_A - r.mean)
+        print(f"fp32 task {t}: E {per[k].E_per_A:.9f} oracle {r.mean:.9f} +- {r.sigma:.2e}",
+              flush=True)
+        assert dev <= 3.0 * r.sigma and dev <= 1e-4 * abs(r.mean) + 1e-2 * r.sigma
+
+
 def test_autotuned_shape_against_oracle(M):
     tasks = NEUTRON[:2] + [_task(2, 0, 2, 0.06, 0.0, 9)]
     N = 1 << 16
