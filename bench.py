@@ -49,7 +49,12 @@ KERNEL_SOURCES = ("paper_2603_24532_amd/csrc/kernels_dev.hpp",
                   "paper_2603_24532_amd/csrc/kernels.hip",
                   "paper_2603_24532_amd/csrc/device_types.hpp",
                   "paper_2603_24532_amd/csrc/turn_table.hpp")
-TRAFFIC = None
+TRAFFIC = {"sha256": "dfab04fd2651845e852d26a9bed54224e67bd08b38ea920ebe40baa0e6fbb9fc",
+           "block": 256, "spt": 256,
+           # sample_order<4,4,1>: mean of the two dispatches of each run
+           "fetch_kib": 17367.5, "write_kib": 774709.0,
+           # 256 MiB device copy: FETCH_SIZE 131092.5 KiB, WRITE_SIZE 262144 KiB
+           "fetch_scale": 262144.0 / 131092.5, "write_scale": 1.0}
 
 
 def kernel_sources_sha256():
@@ -191,6 +196,7 @@ def run_set(M, tasks, N, steps, warmup, stream, precision=0, mode=1, seed=1, blo
     buf, ptr = M.device_workspace(nbytes)
     M.mbpt_bind_workspace(s, ptr, nbytes, N, cap)
     tuned = M.mbpt_autotune(s, N) if autotune else None
+    blocking_used = M.mbpt_get_blocking(s)
     for _ in range(warmup):
         M.mbpt_integrate(s, N, 1)
     M.mbpt_reset(s)
@@ -206,6 +212,7 @@ def run_set(M, tasks, N, steps, warmup, stream, precision=0, mode=1, seed=1, blo
     dt = time.perf_counter() - t0
     st = M.mbpt_kernel_stats(ctx)
     out = dict(dt=dt, stats=st, per=per, clock=clock.summary(), tuned=tuned,
+               blocking=blocking_used,
                fallback=sum(r.n_fp64_fallback for r in per) / max(1, sum(r.n_evals for r in per)))
     if reg:
         out["reg"] = [M.mbpt_regularized(s, k, reg[0], train) for k in range(len(tasks))]
@@ -666,7 +673,7 @@ def headline(args, M, stream):
     f32, f64 = legs["fp32"], legs["fp64"]
     value = _rate(f32)
     fact, s3n = flop_models(M, tasks)
-    block = spt = None
+    block, spt = f32["blocking"]
     line = {
         "metric": "Gevals/s at orders 2-5 (FP32 vs FP64); p50/p99 time-to-1%-sigma per EOS-point",
         "value": value,
@@ -696,6 +703,7 @@ def headline(args, M, stream):
         },
         "roofline": roofline_of(f32, FP32_VECTOR_PEAK_TFLOPS, {
             "kernel": "sample_order<4,4,1> (fourth order, nuclear matter, fp32 integrand)",
+            "threads_per_block": block, "samples_per_thread": spt,
             "traffic": traffic_bytes_per_launch(block, spt),
             "frac_of_unpacked_fp32_peak": None,
             "flops_per_eval_if_all_pass_factorised": fact,

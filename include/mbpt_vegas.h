@@ -320,6 +320,8 @@ int mbpt_set_training(mbpt_task_set *set, int train_iters);
  * per CU (at most 256).  A later mbpt_set_launch_mode keeps that choice.
  * ESTATE for smaller work items than the bound workspace was sized for. */
 int mbpt_set_blocking(mbpt_task_set *set, int threads_per_block, int samples_per_thread);
+/* The work decomposition in effect (the automatic choice once bound). */
+int mbpt_get_blocking(const mbpt_task_set *set, int *threads_per_block, int *samples_per_thread);
 
 /* Device workspace bytes needed for up to max_samples_per_iter samples per
  * task and iteration and up to max_iters stored per-iteration estimates. */

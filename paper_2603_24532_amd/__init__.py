@@ -29,6 +29,7 @@ EXPORTED = [
     "mbpt_create_task_set", "mbpt_create_diagram_set", "mbpt_create_diagram_set_from_order",
     "mbpt_diagram_desc_id", "mbpt_diagram_desc_of", "mbpt_task_set_destroy", "mbpt_task_count",
     "mbpt_set_density", "mbpt_set_asymmetry", "mbpt_set_launch_mode", "mbpt_set_blocking",
+    "mbpt_get_blocking",
     "mbpt_workspace_query", "mbpt_bind_workspace", "mbpt_reset", "mbpt_integrate",
     "mbpt_iteration_log", "mbpt_dump_samples", "mbpt_get_grid", "mbpt_set_grid",
     "mbpt_kernel_stats", "mbpt_task_flops", "mbpt_autotune", "mbpt_server_workspace_query", "mbpt_server_create",
@@ -140,6 +141,7 @@ def lib():
         "mbpt_set_training": [_P, ctypes.c_int],
         "mbpt_set_fp32_target": [_P, ctypes.c_double],
         "mbpt_set_blocking": [_P, ctypes.c_int, ctypes.c_int],
+        "mbpt_get_blocking": [_P, _IP, _IP],
         "mbpt_workspace_query": [_P, ctypes.c_uint64, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_size_t)],
         "mbpt_bind_workspace": [_P, _P, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int],
@@ -381,6 +383,13 @@ def mbpt_set_training(s, train_iters):
 
 def mbpt_set_blocking(s, threads_per_block, samples_per_thread):
     _check(lib().mbpt_set_blocking(s, threads_per_block, samples_per_thread), _ctx_of_set(s))
+
+
+def mbpt_get_blocking(s):
+    """(threads per block, samples per thread) in effect."""
+    b, p = ctypes.c_int(), ctypes.c_int()
+    _check(lib().mbpt_get_blocking(s, ctypes.byref(b), ctypes.byref(p)), _ctx_of_set(s))
+    return b.value, p.value
 
 
 def mbpt_workspace_query(s, max_samples_per_iter, max_iters):

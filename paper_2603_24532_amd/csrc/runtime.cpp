@@ -1052,6 +1052,14 @@ extern "C" int mbpt_set_launch_mode(mbpt_task_set *set, int mode) {
   return MBPT_OK;
 }
 
+extern "C" int mbpt_get_blocking(const mbpt_task_set *set, int *threads_per_block,
+                                 int *samples_per_thread) {
+  if (!set || !threads_per_block || !samples_per_thread) return MBPT_EINVAL;
+  *threads_per_block = set->block;
+  *samples_per_thread = set->spt;
+  return MBPT_OK;
+}
+
 extern "C" int mbpt_set_blocking(mbpt_task_set *set, int threads_per_block, int samples_per_thread) {
   if (!set || threads_per_block < 64 || threads_per_block > 256 || (threads_per_block % 64) ||
       samples_per_thread < 1 || samples_per_thread > 256)
