@@ -165,9 +165,13 @@ class SigmaClock:
     def summary(self):
         hit = [v for v in self.t_point.values() if v is not None]
         th = [v for v in self.t_task if v is not None]
+        # percentiles over those that reached the target; the others are
+        # censored at the end of the run and counted apart
         return {"eos_points": len(self.t_point), "eos_points_reaching_target": len(hit),
+                "eos_points_censored_at_run_end": len(self.t_point) - len(hit),
                 "p50_s": _pct(hit, 50), "p99_s": _pct(hit, 99),
                 "tasks": len(self.t_task), "tasks_reaching_target": len(th),
+                "tasks_censored_at_run_end": len(self.t_task) - len(th),
                 "task_p50_s": _pct(th, 50), "task_p99_s": _pct(th, 99)}
 
 
