@@ -69,9 +69,11 @@ def test_noalloc_matches_workspace_path(M, precision):
         with pytest.raises(M.MbptError) as e:
             M.mbpt_iteration_log(s_small, 0)
         assert e.value.code == M.MBPT_ESTATE
-        # more than the static array holds
+        # more than the static array holds at any work decomposition (the
+        # iteration log alone: 4 tasks x 2^20 iterations x 16 bytes = 64 MiB);
+        # refused before any launch
         with pytest.raises(M.MbptError) as e:
-            M.mbpt_integrate_noalloc(s_big, 1 << 30, 64)
+            M.mbpt_integrate_noalloc(s_big, 1 << 40, 1 << 20)
         assert e.value.code == M.MBPT_ENOMEM
         assert "scratch" in M.mbpt_last_error(ctx)
         M.mbpt_task_set_destroy(s_big)
