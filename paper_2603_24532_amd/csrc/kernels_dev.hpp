@@ -1519,6 +1519,11 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 //   fifth-order neutron matter, which loses a third to ~520 spilled bytes.
 // - third order, fp64 and fp32 (single diagrams specialised per diagram):
 //   4 waves with 60-130 spilled bytes beat 3 waves without (4-7%);
+// - nuclear matter with the cycle form of the label sum (single diagrams,
+//   work items of up to 65536 samples): fourth-order fp32 and fp64 at 4 waves
+//   (72-124 spilled bytes) beat 3 waves by 6% and 3%; fifth-order fp32 at 4
+//   waves beats 3 by 4%, fifth-order fp64 at 3 waves beats its natural 2 by 8%;
+//   fourth-order nuclear group kernels at 4 waves beat 3 by 7-8%.
 // Other kernels fit their natural occupancy.
 template <int ORDER, int Q, int P, bool X>
 constexpr int min_waves() {
@@ -1527,6 +1532,11 @@ constexpr int min_waves() {
     if (ORDER == 3 || ORDER == 4) return 2;
     return (ORDER == 5 && Q == 4) ? 2 : 1;
   }
+  if (Q == 4 && !X && (P == 0 || P == 1)) {
+    if (ORDER == 4) return 4;
+    if (ORDER == 5) return P == 1 ? 4 : 3;
+  }
+  if (Q == 4 && !X && ORDER == 4 && (P == 3 || P == 4)) return 4;
   if (ORDER == 3 && (P == 0 || P == 1)) return 4;
   if (ORDER == 4) return (P == 0 || P == 1 || P == 3 || P == 4 || P == 5) ? 3 : 2;
   if (ORDER == 5) {
