@@ -21,6 +21,8 @@ DEVICE = ["--offload-arch=gfx950", "-munsafe-fp-atomics",
 HOST_SOURCES = ("runtime.cpp", "diagrams.cpp", "server.cpp")
 DEVICE_SOURCES = ("kernels.hip", "noalloc.hip")
 INST_PAIRS = [(o, q) for o in (5, 4, 3, 2, 1) for q in (4, 2)]  # slowest first
+# per-diagram fourth-order kernels: (first diagram id, ids) per translation unit
+FIXED4_CHUNKS = [(0, 10), (10, 10), (20, 10), (30, 9)]
 
 
 def _jobs():
@@ -30,6 +32,11 @@ def _jobs():
         jobs.append((obj, [HIPCC, *COMMON, *DEVICE, f"-DMBPT_INST_ORDER={o}",
                            f"-DMBPT_INST_Q={q}", "-c", os.path.join(CSRC, "kernels_inst.hip"),
                            "-o", obj]))
+    for first, count in FIXED4_CHUNKS:
+        obj = os.path.join(BUILD, f"kernels_o4f{first}.o")
+        jobs.append((obj, [HIPCC, *COMMON, *DEVICE, f"-DMBPT_FIXED_FIRST={first}",
+                           f"-DMBPT_FIXED_COUNT={count}", "-c",
+                           os.path.join(CSRC, "kernels_o4fixed.hip"), "-o", obj]))
     for src in DEVICE_SOURCES:
         if os.path.exists(os.path.join(CSRC, src)):
             obj = os.path.join(BUILD, src + ".o")

@@ -46,12 +46,13 @@ struct alignas(16) DiagDev {
 };
 
 // Compile-time descriptor masks for the diagrams whose kernels are
-// specialised: the one two-body diagram of orders 1 and 2 and the three of
-// order 3 (variant V = diagram id; V = -1 is the generic, descriptor-driven
-// path).  The masks are those the generator compiles (loops first, plain
-// loop order); with them the compiler folds the loop-momentum sums, drops the
-// zero coefficients and shares equal vertex momenta.  Task-set and server
-// creation check the generator's masks against these.
+// specialised: the one two-body diagram of orders 1 and 2, the three of
+// order 3 and the 39 of order 4 (variant V = diagram id; V = -1 is the
+// generic, descriptor-driven path).  The masks are those the generator
+// compiles (loops first, plain loop order); with them the compiler folds the
+// loop-momentum sums, drops the zero coefficients and shares equal vertex
+// momenta.  Task-set and server creation check the generator's masks against
+// these.
 template <int ORDER, int V>
 struct FixedMasks {
   static constexpr bool kFixed = false;
@@ -111,6 +112,13 @@ struct FixedMasks<3, 2> {
   static constexpr uint32_t cut_part[2] = {0x11u, 0x22u};
   static constexpr int loop_part[4] = {1, 1, 0, 0};
 };
+
+}  // namespace mbpt
+
+// the 39 fourth-order diagrams (generated; per-diagram fourth-order kernels)
+#include "fixed_masks_o4.hpp"
+
+namespace mbpt {
 
 // Isospin configuration: lines whose bit is set carry protons.  first/count:
 // its explicit terms; coef_off: its 2^n factorised coefficients.

@@ -442,6 +442,17 @@ hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, bool 
 #undef MBPT_CALL
 }
 
+hipError_t launch_sample_order_fixed4(const KArgs &a, int id, int prec, int k0, int k1, int nitems,
+                                      int block, hipStream_t st) {
+  switch (id / kFixed4Chunk) {
+    case 0: return launch_o4_fixed<0>(a, id, prec, k0, k1, nitems, block, st);
+    case 1: return launch_o4_fixed<10>(a, id, prec, k0, k1, nitems, block, st);
+    case 2: return launch_o4_fixed<20>(a, id, prec, k0, k1, nitems, block, st);
+    case 3: return launch_o4_fixed<30>(a, id, prec, k0, k1, nitems, block, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_sample_persistent(const KArgs &a, int order, int q, int prec, bool group, int k0,
                                     int k1, int nitems, int block, int cus, hipStream_t st) {
 #define MBPT_CALL(O, Q) launch_persist_oq<O, Q>(a, prec, group, k0, k1, nitems, block, cus, st)

@@ -19,6 +19,12 @@ hipError_t launch_sample_order(const KArgs &a, int order, int q, int prec, bool 
 // counter a.queue[order] (zero at launch).
 hipError_t launch_sample_persistent(const KArgs &a, int order, int q, int prec, bool group, int k0,
                                     int k1, int nitems, int block, int cus, hipStream_t st);
+// Items of the tasks of the fourth-order diagram `id` (olist[k0, k1), nitems
+// items from olist[k0].x) in nuclear matter with the quartic regulator and the
+// polynomial label sums, fp64 (prec 0) or fp32 (1): the per-diagram kernel
+// with compile-time descriptor masks (kernels_o4fixed.hip).
+hipError_t launch_sample_order_fixed4(const KArgs &a, int id, int prec, int k0, int k1, int nitems,
+                                      int block, hipStream_t st);
 // Iteration end of tasks [first_task, first_task + ntasks) that take part in
 // iteration step_iter of the current launch sequence (plan > step_iter).
 hipError_t launch_finish(const KArgs &a, int first_task, int ntasks, int step_iter, double alpha,
@@ -52,6 +58,20 @@ template <int ORDER, int Q>
 hipError_t launch_dump_oq(const KArgs &a, int t, int prec, bool group, uint32_t iter,
                           uint64_t first, uint64_t count, double *out, double *out_reg,
                           hipStream_t st);
+// Per-diagram fourth-order launchers for the ids [FIRST, FIRST + kFixed4Chunk),
+// one translation unit each.
+constexpr int kFixed4Chunk = 10;
+template <int FIRST>
+hipError_t launch_o4_fixed(const KArgs &a, int id, int prec, int k0, int k1, int nitems, int block,
+                           hipStream_t st);
+template <>
+hipError_t launch_o4_fixed<0>(const KArgs &, int, int, int, int, int, int, hipStream_t);
+template <>
+hipError_t launch_o4_fixed<10>(const KArgs &, int, int, int, int, int, int, hipStream_t);
+template <>
+hipError_t launch_o4_fixed<20>(const KArgs &, int, int, int, int, int, int, hipStream_t);
+template <>
+hipError_t launch_o4_fixed<30>(const KArgs &, int, int, int, int, int, int, hipStream_t);
 #define MBPT_DECLARE_OQ(O, Q)                                                                   \
   template <>                                                                                   \
   hipError_t launch_single_oq<O, Q>(const KArgs &, int, int, bool, int, int, hipStream_t);      \

@@ -1307,7 +1307,9 @@ __device__ __forceinline__ void hist_flush(const KArgs &a, int t, const double *
 
 // The samples of one work item of task t (the task's tables in LDS): sums,
 // histogram entries (LDS), and the item's partial sums and counters.
-template <int ORDER, int Q, int P, bool X, int HE>
+// VF >= 0: the descriptor variant fixed at compile time (a per-diagram
+// kernel); -2: chosen per work item from the task's diagram (with_variant).
+template <int ORDER, int Q, int P, bool X, int HE, int VF = -2>
 __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, const BlockLds &B) {
   constexpr int ND = 3 * (ORDER + 1);
   const TaskDev *__restrict__ T = a.tasks + t;
@@ -1346,7 +1348,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
   constexpr bool G = group_of<P>();
   constexpr bool PI = pair_inv<ORDER, Q, P>();
   // the sample loops, specialised per diagram variant (uniform per item)
-  with_variant<ORDER, G>(D, [&](auto vt) {
+  auto loops = [&](auto vt) {
     constexpr int V = decltype(vt)::value;
     const double jc = jac_const<ORDER, V>(a, T, D);
     if (PP != 1) {
@@ -1426,7 +1428,9 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
       }
       while (qn > 0) drain(qn < 64 ? qn : 64);
     }
-  });
+  };
+  if constexpr (VF >= 0) loops(std::integral_constant<int, VF>{});
+  else with_variant<ORDER, G>(D, loops);
   // wavefront butterfly, then waves in order (compensated pairs s + c)
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -1494,13 +1498,13 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
 }
 
 // One work item with its own setup and histogram merge.
-template <int ORDER, int Q, int P, bool X, int HE>
+template <int ORDER, int Q, int P, bool X, int HE, int VF = -2>
 __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, double *smem) {
   BlockLds B;
   block_lds<ORDER, Q, P, X>(a, smem, B);
   task_lds<ORDER, Q, P, X>(a, t, B);
   __syncthreads();
-  item_samples<ORDER, Q, P, X, HE>(a, t, item, B);
+  item_samples<ORDER, Q, P, X, HE, VF>(a, t, item, B);
   __syncthreads();
   hist_flush<ORDER>(a, t, B.h);
 }
@@ -1570,6 +1574,28 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_ord
     else hi = mid - 1;
   }
   process_item<ORDER, Q, P, X, HE>(a, ol[lo].y, item, smem);
+}
+
+// sample_order for the tasks of one diagram whose descriptor masks are
+// compile-time constants (FixedMasks<ORDER, V>, V = the diagram id): the
+// loop-momentum sums keep only their nonzero terms and need no scalar
+// decoding.  The same arithmetic as the descriptor-driven kernel (a product
+// with a coefficient 0, +-1, +-2 or +-1/2 is exact), so the per-sample
+// weights are identical.
+template <int ORDER, int Q, int P, int HE, int V>
+__global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, false>())) void sample_order_fixed(
+    KArgs a, int k0, int k1) {
+  static_assert(FixedMasks<ORDER, V>::kFixed, "a per-diagram kernel needs the diagram's masks");
+  extern __shared__ double smem[];
+  const int2 *__restrict__ ol = a.olist;
+  const int item = ol[k0].x + static_cast<int>(blockIdx.x);
+  int lo = k0, hi = k1 - 1;  // last entry with first item <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ol[mid].x <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  process_item<ORDER, Q, P, false, HE, V>(a, ol[lo].y, item, smem);
 }
 
 // Persistent launch over the work items of the tasks of one order (as

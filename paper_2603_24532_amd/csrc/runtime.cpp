@@ -11,6 +11,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "diagrams.hpp"
@@ -320,6 +321,11 @@ static bool fixed_masks_match(const DiagDev &dd) {
   return ok;
 }
 
+template <typename Dev, int... I>
+static bool fixed4_match(Dev &&dev, std::integer_sequence<int, I...>) {
+  return (fixed_masks_match<4, I>(dev(4, I, false)) && ...);
+}
+
 bool fixed_masks_ok() {
   static const bool ok = [] {
     bool r = true;
@@ -335,6 +341,9 @@ bool fixed_masks_ok() {
     r = r && fixed_masks_match<3, 0>(dev(3, 0, false));
     r = r && fixed_masks_match<3, 1>(dev(3, 1, false));
     r = r && fixed_masks_match<3, 2>(dev(3, 2, false));
+    // the 39 fourth-order diagrams of the per-diagram kernels
+    r = r && num_diagrams(4) == 39 &&
+        fixed4_match(dev, std::make_integer_sequence<int, 39>{});
     return r;
   }();
   return ok;
@@ -1126,17 +1135,38 @@ int enqueue_iterations(mbpt_task_set *set, KArgs &a, int iters, bool timed) {
     return MBPT_OK;
   }
   const bool persistent = set->launch_mode == MBPT_LAUNCH_PERSISTENT;
+  // fourth-order nuclear-matter single diagrams with the quartic regulator,
+  // the polynomial label sums and the free spectrum take the per-diagram
+  // kernels (compile-time masks): one launch per diagram of the order's range
+  // (the tasks are numbered by diagram, see mbpt_integrate)
+  const int prec = ctx->desc.precision;
+  auto fixed4 = [&](const OrderRange &r) {
+    return !persistent && r.order == 4 && set->q == 4 && !r.group && ctx->desc.label_mode == 0 &&
+           a.phys.half_exp == 2 && a.phys.spectrum == MBPT_SPECTRUM_FREE && a.nreg == 0 &&
+           (prec == MBPT_FP64 || prec == MBPT_FP32);
+  };
+  auto id_of = [&](int k) { return set->diags[set->task_diag[set->olist[k].y]].id; };
   for (int it = 0; it < iters; ++it) {
     size_t slot = 0;
     if (timed) timed_begin(ctx, slot);
     for (const auto &r : set->oranges) {
-      if (persistent)
-        HIPCHK(ctx, launch_sample_persistent(a, r.order, set->q, ctx->desc.precision, r.group, r.k0,
-                                             r.k1, r.nitems, set->block, ctx->num_cus,
-                                             ctx->stream));
-      else
-        HIPCHK(ctx, launch_sample_order(a, r.order, set->q, ctx->desc.precision, r.group, r.k0,
-                                        r.k1, r.nitems, set->block, ctx->stream));
+      if (persistent) {
+        HIPCHK(ctx, launch_sample_persistent(a, r.order, set->q, prec, r.group, r.k0, r.k1,
+                                             r.nitems, set->block, ctx->num_cus, ctx->stream));
+      } else if (fixed4(r)) {
+        for (int ka = r.k0; ka < r.k1;) {
+          const int id = id_of(ka);
+          int kb = ka + 1;
+          while (kb < r.k1 && id_of(kb) == id) ++kb;
+          const int end = kb < r.k1 ? set->olist[kb].x : r.item_end;
+          HIPCHK(ctx, launch_sample_order_fixed4(a, id, prec == MBPT_FP32 ? 1 : 0, ka, kb,
+                                                 end - set->olist[ka].x, set->block, ctx->stream));
+          ka = kb;
+        }
+      } else {
+        HIPCHK(ctx, launch_sample_order(a, r.order, set->q, prec, r.group, r.k0, r.k1, r.nitems,
+                                        set->block, ctx->stream));
+      }
     }
     if (timed) timed_end(ctx, slot);
     HIPCHK(ctx, launch_finish(a, 0, nt, 0, alpha, ctx->stream));
@@ -1221,6 +1251,11 @@ extern "C" int mbpt_integrate(mbpt_task_set *set, uint64_t samples_per_iter, int
     T.nitems = per;
     T.nsamples = samples_per_iter;
   }
+  // within an order, tasks numbered by diagram (the per-diagram kernels take
+  // one diagram's tasks per launch)
+  std::stable_sort(all.begin(), all.end(), [&](int x, int y) {
+    return set->diags[set->task_diag[x]].id < set->diags[set->task_diag[y]].id;
+  });
   if (changed || set->oranges.empty()) {
     order_items(set->h_tasks, all, set->olist, set->oranges);
     for (int t = 0; t < nt; ++t) set->h_tasks[t].store_begin = set->h_tasks[t].item_begin;
