@@ -39,23 +39,27 @@ DENSITIES_C4 = [0.08, 0.12, 0.16, 0.20, 0.24]
 FRACTIONS_C4 = [0.0, 0.25, 0.5]
 SIGMA_FLOOR = 1e-3  # MeV: absolute sigma floor of the 1% target
 
-# HBM traffic of one headline sample-kernel launch, from two rocprofv3 --pmc
-# runs of `bench.py --workload nuclear4` (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch) scaled by the same counters' reading for a device-to-device copy
+# HBM traffic of one headline iteration's sample launches (the 39 per-diagram
+# launches), from two rocprofv3 --pmc runs of `bench.py --workload nuclear4`
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, summed over an iteration's
+# dispatches) scaled by the same counters' reading for a device-to-device copy
 # of known size (--copy-calibration-mib).  Valid only for the kernel sources
 # and work decomposition it was measured with (None: not measured).
 KERNEL_SOURCES = ("paper_2603_24532_amd/csrc/kernels_dev.hpp",
                   "paper_2603_24532_amd/csrc/kernels_inst.hip",
+                  "paper_2603_24532_amd/csrc/kernels_o4fixed.hip",
                   "paper_2603_24532_amd/csrc/kernels.hip",
                   "paper_2603_24532_amd/csrc/device_types.hpp",
+                  "paper_2603_24532_amd/csrc/fixed_masks_o4.hpp",
                   "paper_2603_24532_amd/csrc/turn_table.hpp")
-TRAFFIC = {"sha256": "34d39e789dae2b18b68b097a4ee66327a589c4cb68d352b431ddc45b5a27533e",
+TRAFFIC = {"sha256": "4168a6472efff7331bd689f1817cb8c40c75611d8bbf2f40aa0fb54cf248fa7d",
            "block": 256, "spt": 256,
-           # sample_order<4,4,1>: mean over the 16 timed dispatches of
+           # the 39 sample_order_fixed<4,4,1,2,id> dispatches of an iteration,
+           # summed, mean over the 16 timed iterations of
            # `--workload nuclear4 --precision fp32 --steps 16 --warmup 2 --train 4`
-           "fetch_kib": 109005.15, "write_kib": 15326990.0,
-           # 256 MiB device copy: FETCH_SIZE 131089.3 KiB, WRITE_SIZE 262144 KiB
-           "fetch_scale": 262144.0 / 131089.3, "write_scale": 1.0}
+           "fetch_kib": 60476.36, "write_kib": 942763.6,
+           # 256 MiB device copy: FETCH_SIZE 131085.5 KiB, WRITE_SIZE 262144 KiB
+           "fetch_scale": 262144.0 / 131085.5, "write_scale": 1.0}
 
 
 def kernel_sources_sha256():
@@ -707,7 +711,8 @@ def headline(args, M, stream):
             "label_sum": "polynomial" if LABEL_MODE == 0 else "explicit",
         },
         "roofline": roofline_of(f32, FP32_VECTOR_PEAK_TFLOPS, {
-            "kernel": "sample_order<4,4,1> (fourth order, nuclear matter, fp32 integrand)",
+            "kernel": "sample_order_fixed<4,4,1,2,id> (fourth order, nuclear matter, fp32 "
+                      "integrand; one launch per diagram id, 39 per iteration, timed together)",
             "threads_per_block": block, "samples_per_thread": spt,
             "traffic": traffic_bytes_per_launch(block, spt),
             "frac_of_unpacked_fp32_peak": None,
