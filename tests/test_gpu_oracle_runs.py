@@ -115,6 +115,33 @@ def test_large_work_items_against_oracle(M, precision, block, spt):
         assert dev <= 3.0 * r.sigma and dev <= 1e-4 * abs(r.mean) + 1e-2 * r.sigma
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_every_fourth_order_diagram_kernel_against_oracle(M, precision):
+    """All 39 fourth-order diagrams in one nuclear-matter set, one launch per
+    order: each takes its own per-diagram kernel (compile-time masks).  Each
+    diagram's iterations against the oracle's: fp64 as the other launch forms
+    (1e-9 relative, 1e-6 sigma), the fp32 integrand within 3 sigma and
+    1e-4 |E| + 1e-2 sigma of the fp64 oracle; ragged sample count, two
+    iterations (the second on a refined grid)."""
+    tasks = [_task(4, d, 4, 0.12 + 0.02 * (d % 4), 0.1 * (d % 5), 400 + d) for d in range(39)]
+    N, iters = 3000 + 17, 2
+    prec = M.MBPT_FP64 if precision == "fp64" else M.MBPT_FP32
+    run = Run(M, tasks, max_samples=N, mode=M.MBPT_LAUNCH_BATCHED, block=64, spt=4,
+              precision=prec)
+    try:
+        per, _ = M.mbpt_integrate(run.set, N, iters)
+        if precision == "fp64":
+            _compare_logs(M, run.set, tasks, N, iters, per, "per-diagram")
+            return
+    finally:
+        run.close()
+    for k, t in enumerate(tasks):
+        r, _, _, _ = _oracle_log(t, N, iters)
+        dev = abs(per[k].E_per_A - r.mean)
+        assert dev <= 3.0 * r.sigma + 1e-300 and dev <= 1e-4 * abs(r.mean) + 1e-2 * r.sigma, \
+            (t, per[k].E_per_A, r.mean, r.sigma)
+
+
 def test_autotuned_shape_against_oracle(M):
     tasks = NEUTRON[:2] + [_task(2, 0, 2, 0.06, 0.0, 9)]
     N = 1 << 16
