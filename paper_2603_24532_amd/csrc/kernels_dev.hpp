@@ -1579,9 +1579,10 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_ord
 // sample_order for the tasks of one diagram whose descriptor masks are
 // compile-time constants (FixedMasks<ORDER, V>, V = the diagram id): the
 // loop-momentum sums keep only their nonzero terms and need no scalar
-// decoding.  The same arithmetic as the descriptor-driven kernel (a product
-// with a coefficient 0, +-1, +-2 or +-1/2 is exact), so the per-sample
-// weights are identical.  Built for 3 waves per SIMD: measured on the 585
+// decoding.  The same operations as the descriptor-driven kernel (a product
+// with a coefficient 0, +-1, +-2 or +-1/2 is exact), but with the masks known
+// the compiler may fuse other multiply-adds (shared vertex momenta), so the
+// weights agree to their last bits.  Built for 3 waves per SIMD: measured on the 585
 // fourth-order nuclear-matter tasks, fp64 41.3 Gevals/s at 3 against 32.6 at 4
 // (and 41.1 at 2), fp32 within 2% at 3 and 4 (36.7 at 2).
 template <int ORDER, int Q, int P, int HE, int V>
