@@ -311,6 +311,25 @@ def nuclear4(args, M, stream, precisions=("fp32", "fp64"), extras=True):
     return tasks, legs
 
 
+def fifth_order(args, M, stream):
+    """Fifth order in nuclear matter: every 42nd of the 840 diagrams (20) at the
+    15 EOS points, 300 tasks, 2^22 samples per task and iteration, 1 warm-up
+    and 3 timed iterations, fp32 and fp64, one launch per iteration (the
+    descriptor-driven kernels)."""
+    tasks = c4_tasks(M, 5, 42)
+    N = 1 << 22
+    out = {"workload": "fifth-order diagrams 0, 42, ..., 798 (20) x the 15 EOS points of the "
+                       "headline, nuclear matter, 300 tasks, 3 iterations x 2^22 samples"}
+    for p in ("fp32", "fp64"):
+        r = run_set(M, tasks, N, 3, 1, stream, precision=1 if p == "fp32" else 0,
+                    mode=M.MBPT_LAUNCH_BATCHED)
+        out[p] = {"Gevals_per_s": _rate(r), "roofline": roofline_of(
+            r, FP32_VECTOR_PEAK_TFLOPS if p == "fp32" else FP64_VECTOR_PEAK_TFLOPS),
+            "chi2_dof": _chi2(r["per"]), "fp64_fallback_fraction": r["fallback"]}
+        log(f"[fifth order] {p}: {out[p]['Gevals_per_s']:.2f} Gevals/s")
+    return out
+
+
 def roofline_of(leg, peak, extra=None):
     st = leg["stats"]
     avg_ms = st["kernel_ms"] / max(1, st["launches"])
@@ -767,6 +786,8 @@ def main():
         line = headline(args, M, stream)
         log("[bench] fourth-order diagram groups")
         line["fourth_order_groups"] = groups4(args, M, stream)
+        log("[bench] fifth order")
+        line["fifth_order_nuclear"] = fifth_order(args, M, stream)
         log("[bench] batched orders 2+3")
         line["orders_2_3_batched"] = batched(args, M, stream)
         log("[bench] served stream")
