@@ -78,7 +78,39 @@ struct SampleLds {
   const double *hf;
   const double2 *g;
   const void *cyc;  // label-cycle table of the item's diagram (cycle-form kernels)
+  // loop coefficients of the item's diagram, decoded once per task into LDS
+  // (coef_tab): kCoefStride per momentum sum, the 2 ORDER line slots then
+  // (2p, 2p') of every vertex halved, fp64 and fp32 copies
+  const double *cd;
+  const float *cf;
 };
+
+// Diagram variant of a sample kernel's work items (template argument VF):
+// a diagram id >= 0 fixes the descriptor masks at compile time (per-diagram
+// kernels); kPerItem picks the variant per work item (with_variant) and, at
+// orders 4 and 5, reads the loop coefficients from a table in LDS;
+// kPerItemMasks picks it per item and decodes the coefficients from the
+// masks.
+constexpr int kPerItem = -2, kPerItemMasks = -3;
+
+constexpr int kCoefStride = 8;
+// Descriptor-driven single-diagram sample kernels of orders 4 and 5 (kPerItem)
+// read the loop coefficients of their momentum sums from LDS instead of
+// decoding them from the descriptor's bit masks per sum and sample on the
+// scalar unit.  Measured on MI355X: 9-18% faster fp64 (fifth order, fourth
+// order per task, with components, explicit label lists), fp32 the same or
+// faster, but slower in the persistent kernels (their registers are already
+// spilled), which keep the masks.
+template <int ORDER, int P, int VF>
+constexpr bool coef_tab() {
+  return ORDER >= 4 && !(P == 3 || P == 4 || P == 6) && VF == kPerItem;  // not the group modes
+}
+template <int ORDER, int P, int VF>
+constexpr size_t coef_lds_bytes() {
+  return coef_tab<ORDER, P, VF>()
+             ? static_cast<size_t>(4 * ORDER) * kCoefStride * (sizeof(double) + sizeof(float))
+             : 0;
+}
 
 // Label-cycle bit vectors: bit k of CycWord<ORDER> stands for cycle k of a
 // diagram (at most 17 at fourth order, 33 at fifth).
@@ -143,6 +175,8 @@ __device__ __forceinline__ double *carve_lds(const KArgs &a, const TaskDev *__re
   L.hf = ntab ? hf : nullptr;
   L.g = g;
   L.cyc = nullptr;
+  L.cd = nullptr;
+  L.cf = nullptr;
   return reinterpret_cast<double *>(g + nd * a.phys.nb);
 }
 
@@ -210,6 +244,36 @@ __device__ __forceinline__ void masked_sum(uint32_t m, const double (*k)[3], dou
     x = fma(c, k[j][0], x);
     y = fma(c, k[j][1], y);
     z = fma(c, k[j][2], z);
+  }
+  out[0] = x;
+  out[1] = y;
+  out[2] = z;
+}
+
+// sum_j c_j v_j over loops j < L with the coefficients c read from a table:
+// the same operations, in the same order, as masked_sum of the mask they were
+// decoded from (zero coefficients included).
+template <int L>
+__device__ __forceinline__ void table_sum(const double *c, const double (*k)[3], double *out) {
+  double x = 0.0, y = 0.0, z = 0.0;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    x = fma(c[j], k[j][0], x);
+    y = fma(c[j], k[j][1], y);
+    z = fma(c[j], k[j][2], z);
+  }
+  out[0] = x;
+  out[1] = y;
+  out[2] = z;
+}
+template <int L>
+__device__ __forceinline__ void table_sum_f(const float *c, const float (*k)[3], float *out) {
+  float x = 0.0f, y = 0.0f, z = 0.0f;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    x = fmaf(c[j], k[j][0], x);
+    y = fmaf(c[j], k[j][1], y);
+    z = fmaf(c[j], k[j][2], z);
   }
   out[0] = x;
   out[1] = y;
@@ -710,7 +774,8 @@ __device__ __forceinline__ double rcp_newton(double d) {
 // particle energies of the Hartree-Fock spectrum (tables in LDS).
 // REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
 // to wr[k - 1].
-template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V, int HE = 0, bool CY = false>
+template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V, int HE = 0, bool CY = false,
+          bool TAB = false>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
@@ -732,7 +797,8 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
       kv[1] = k[l][1];
       kv[2] = k[l][2];
     } else {
-      masked_sum<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
+      if constexpr (TAB) table_sum<L>(Ls.cd + kCoefStride * l, k, kv);
+      else masked_sum<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
     }
     const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = a.phys.hb2m * k2;
@@ -800,8 +866,13 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
     double p[3], q[3];  // relative momenta p and p'
-    masked_sum<L, true, FixedMasks<ORDER, V>::kFixed>(pmask_of<ORDER, V>(D, v), k, p);
-    masked_sum<L, true, FixedMasks<ORDER, V>::kFixed>(qmask_of<ORDER, V>(D, v), k, q);
+    if constexpr (TAB) {
+      table_sum<L>(Ls.cd + kCoefStride * (2 * ORDER + 2 * v), k, p);
+      table_sum<L>(Ls.cd + kCoefStride * (2 * ORDER + 2 * v + 1), k, q);
+    } else {
+      masked_sum<L, true, FixedMasks<ORDER, V>::kFixed>(pmask_of<ORDER, V>(D, v), k, p);
+      masked_sum<L, true, FixedMasks<ORDER, V>::kFixed>(qmask_of<ORDER, V>(D, v), k, q);
+    }
     const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const double pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
@@ -870,7 +941,8 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 // or (G) the task's T->ndiag group members summed.
 // REG: the regularised components go to wr[0..nreg) (Jacobian and 1/n
 // included).
-template <int ORDER, int Q, bool HF, bool G, bool X, bool PI, int V, bool REG = false, int HE = 0>
+template <int ORDER, int Q, bool HF, bool G, bool X, bool PI, int V, bool REG = false, int HE = 0,
+          bool TAB = false>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, double jc, uint64_t s,
@@ -908,7 +980,8 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
       sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE>(a, T, D + di, Ls, k, npass, nterms, wr);
   } else {
     constexpr bool CY = cycle_form<ORDER, Q, false, X, HF>();
-    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, CY>(a, T, D, Ls, k, npass, nterms, wr);
+    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, CY, TAB>(a, T, D, Ls, k, npass, nterms,
+                                                                wr);
   }
   const double scale = jac * (x0p * x0p) * jc;
   if constexpr (REG)
@@ -953,7 +1026,7 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 // sample in fp64 from the same random words.
 // fp32 contribution of one diagram at the loop momenta k (see
 // diag_weight64); sets `fallback` instead when the sample needs fp64.
-template <int ORDER, int Q, bool X, int V, int HE = 0, bool CY = false>
+template <int ORDER, int Q, bool X, int V, int HE = 0, bool CY = false, bool TAB = false>
 __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const float (*k)[3],
@@ -976,7 +1049,8 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
       kv[1] = k[l][1];
       kv[2] = k[l][2];
     } else {
-      masked_sum_f<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
+      if constexpr (TAB) table_sum_f<L>(Ls.cf + kCoefStride * l, k, kv);
+      else masked_sum_f<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
     }
     const float k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
     eps[l] = hb2m * k2;
@@ -1031,8 +1105,13 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
     float p[3], q[3];
-    masked_sum_f<L, true, FixedMasks<ORDER, V>::kFixed>(pmask_of<ORDER, V>(D, v), k, p);
-    masked_sum_f<L, true, FixedMasks<ORDER, V>::kFixed>(qmask_of<ORDER, V>(D, v), k, q);
+    if constexpr (TAB) {
+      table_sum_f<L>(Ls.cf + kCoefStride * (2 * ORDER + 2 * v), k, p);
+      table_sum_f<L>(Ls.cf + kCoefStride * (2 * ORDER + 2 * v + 1), k, q);
+    } else {
+      masked_sum_f<L, true, FixedMasks<ORDER, V>::kFixed>(pmask_of<ORDER, V>(D, v), k, p);
+      masked_sum_f<L, true, FixedMasks<ORDER, V>::kFixed>(qmask_of<ORDER, V>(D, v), k, q);
+    }
     const float p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const float q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
     const float pq = p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
@@ -1114,7 +1193,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
          static_cast<double>(rinv[NR - 1]);
 }
 
-template <int ORDER, int Q, bool G, bool X, int V, int HE = 0>
+template <int ORDER, int Q, bool G, bool X, int V, int HE = 0, bool TAB = false>
 __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, double jc, uint64_t s,
@@ -1158,7 +1237,7 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     nterms += gterms;
   } else {
     constexpr bool CY = cycle_form<ORDER, Q, false, X, false>();
-    sum = diag_weight32<ORDER, Q, X, V, HE, CY>(a, T, D, Ls, k, npass, nterms, fallback);
+    sum = diag_weight32<ORDER, Q, X, V, HE, CY, TAB>(a, T, D, Ls, k, npass, nterms, fallback);
     if (fallback) return 0.0;
   }
   return jac * (x0p * x0p) * jc * sum;
@@ -1244,8 +1323,9 @@ struct BlockLds {
   double *red;
 };
 
-// Carves the block's LDS and loads the task-independent tables.
-template <int ORDER, int Q, int P, bool X>
+// Carves the block's LDS and loads the task-independent tables (VF: see
+// kPerItem).
+template <int ORDER, int Q, int P, bool X, int VF = kPerItem>
 __device__ __forceinline__ void block_lds(const KArgs &a, double *smem, BlockLds &B) {
   constexpr int ND = 3 * (ORDER + 1);
   constexpr int ntab = lds_tables<Q, P>();
@@ -1260,16 +1340,25 @@ __device__ __forceinline__ void block_lds(const KArgs &a, double *smem, BlockLds
   B.Ls.ex = ex;
   B.Ls.hf = ntab ? hf : nullptr;
   B.Ls.g = B.g;
-  B.Ls.cyc = cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>()
-                 ? reinterpret_cast<uint32_t *>(B.red + 6 * nw) + 128 * nw
-                 : nullptr;
+  uint32_t *queue_end = reinterpret_cast<uint32_t *>(B.red + 6 * nw) + 128 * nw;
+  B.Ls.cyc = cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>() ? queue_end : nullptr;
+  B.Ls.cd = nullptr;
+  B.Ls.cf = nullptr;
+  if constexpr (coef_tab<ORDER, P, VF>()) {
+    // after the cycle table (a multiple of 8 bytes)
+    double *cd = reinterpret_cast<double *>(reinterpret_cast<char *>(queue_end) +
+                                            cycle_lds_bytes<ORDER, Q, P, X>());
+    B.Ls.cd = cd;
+    B.Ls.cf = reinterpret_cast<const float *>(cd + 4 * ORDER * kCoefStride);
+  }
   load_turn_table(turn, ex);
 }
 
 // Loads task t's tables into the block's LDS: HF spline entries, grid pairs
-// (e_b + w_b 2^-33, w_b), a zeroed histogram and the label-cycle table of its
-// diagram.  The caller synchronises before and after.
-template <int ORDER, int Q, int P, bool X>
+// (e_b + w_b 2^-33, w_b), a zeroed histogram, the label-cycle table of its
+// diagram and its loop coefficients.  The caller synchronises before and
+// after.
+template <int ORDER, int Q, int P, bool X, int VF = kPerItem>
 __device__ __forceinline__ void task_lds(const KArgs &a, int t, BlockLds &B) {
   constexpr int ND = 3 * (ORDER + 1);
   constexpr int ntab = lds_tables<Q, P>();
@@ -1292,6 +1381,32 @@ __device__ __forceinline__ void task_lds(const KArgs &a, int t, BlockLds &B) {
   if constexpr (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>())
     build_cycle_table<ORDER>(a.diags + T->diag,
                              static_cast<CycWord<ORDER> *>(const_cast<void *>(B.Ls.cyc)));
+  if constexpr (coef_tab<ORDER, P, VF>()) {
+    // decoded by the helpers of masked_sum, so a table sum performs the
+    // same operations on the same values
+    constexpr int L = ORDER + 1, NL = 2 * ORDER, NS = 4 * ORDER;
+    const DiagDev *__restrict__ D = a.diags + T->diag;
+    double *cd = const_cast<double *>(B.Ls.cd);
+    float *cf = const_cast<float *>(B.Ls.cf);
+    for (int i = tid; i < NS * kCoefStride; i += bs) {
+      const int sm = i / kCoefStride, j = i - sm * kCoefStride;
+      double c = 0.0;
+      float f = 0.0f;
+      if (j < L) {
+        if (sm < NL) {
+          c = mask_coef<false>(D->lmask[sm], j);
+          f = mask_coef_f<false>(D->lmask[sm], j);
+        } else {
+          const int v = (sm - NL) >> 1;
+          const uint32_t m = ((sm - NL) & 1) ? D->qmask_v[v] : D->pmask_v[v];
+          c = mask_coef<true>(m, j);
+          f = mask_coef_f<true>(m, j);
+        }
+      }
+      cd[i] = c;
+      cf[i] = f;
+    }
+  }
 }
 
 // Adds the block's LDS histogram of task t to the task's histogram.
@@ -1307,9 +1422,8 @@ __device__ __forceinline__ void hist_flush(const KArgs &a, int t, const double *
 
 // The samples of one work item of task t (the task's tables in LDS): sums,
 // histogram entries (LDS), and the item's partial sums and counters.
-// VF >= 0: the descriptor variant fixed at compile time (a per-diagram
-// kernel); -2: chosen per work item from the task's diagram (with_variant).
-template <int ORDER, int Q, int P, bool X, int HE, int VF = -2>
+// VF: the diagram variant (see kPerItem).
+template <int ORDER, int Q, int P, bool X, int HE, int VF = kPerItem>
 __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, const BlockLds &B) {
   constexpr int ND = 3 * (ORDER + 1);
   const TaskDev *__restrict__ T = a.tasks + t;
@@ -1350,6 +1464,10 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
   // the sample loops, specialised per diagram variant (uniform per item)
   auto loops = [&](auto vt) {
     constexpr int V = decltype(vt)::value;
+    // loop coefficients from the LDS table (descriptor-driven kernels of
+    // orders 4 and 5)
+    constexpr bool TAB = coef_tab<ORDER, P, VF>();
+    static_assert(!TAB || !FixedMasks<ORDER, V>::kFixed, "fixed masks need no table");
     const double jc = jac_const<ORDER, V>(a, T, D);
     if (PP != 1) {
       for (int kk = 0; kk < a.spt; ++kk) {
@@ -1358,9 +1476,8 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
           int bins[ND];
           if constexpr (R) {
             double wr[kMaxReg];
-            const double w =
-                eval_fp64<ORDER, Q, false, G, X, PI, V, true, HE>(a, T, D, Ls, jc, s, iter, bins,
-                                                                  npass, nterms, wr);
+            const double w = eval_fp64<ORDER, Q, false, G, X, PI, V, true, HE, TAB>(
+                a, T, D, Ls, jc, s, iter, bins, npass, nterms, wr);
             accumulate(w, bins);
             // the extrapolation's weights sum to one, so its shifted value
             // is the weighted sum of the components' shifted values
@@ -1375,7 +1492,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
             rs[2 * kMaxReg] += dx;
             rs[2 * kMaxReg + 1] += dx * dx;
           } else {
-            const double w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V, false, HE>(
+            const double w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V, false, HE, TAB>(
                 a, T, D, Ls, jc, s, iter, bins, npass, nterms);
             accumulate(w, bins);
           }
@@ -1392,9 +1509,8 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
         if (lane < take) {
           const uint64_t s = base + queue[lane];
           int bins[ND];
-          const double w =
-              eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE>(a, T, D, Ls, jc, s, iter, bins,
-                                                                 npass, nterms);
+          const double w = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE, TAB>(
+              a, T, D, Ls, jc, s, iter, bins, npass, nterms);
           accumulate(w, bins);
         }
         __builtin_amdgcn_wave_barrier();
@@ -1410,8 +1526,8 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
         bool fb = false;
         if (s < N) {
           int bins[ND];
-          const double w =
-              eval_fp32<ORDER, Q, G, X, V, HE>(a, T, D, Ls, jc, s, iter, bins, npass, nterms, fb);
+          const double w = eval_fp32<ORDER, Q, G, X, V, HE, TAB>(a, T, D, Ls, jc, s, iter, bins,
+                                                                 npass, nterms, fb);
           if (!fb) accumulate(w, bins);
         }
         const uint64_t mask = __ballot(fb);
@@ -1498,11 +1614,11 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
 }
 
 // One work item with its own setup and histogram merge.
-template <int ORDER, int Q, int P, bool X, int HE, int VF = -2>
+template <int ORDER, int Q, int P, bool X, int HE, int VF = kPerItem>
 __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, double *smem) {
   BlockLds B;
-  block_lds<ORDER, Q, P, X>(a, smem, B);
-  task_lds<ORDER, Q, P, X>(a, t, B);
+  block_lds<ORDER, Q, P, X, VF>(a, smem, B);
+  task_lds<ORDER, Q, P, X, VF>(a, t, B);
   __syncthreads();
   item_samples<ORDER, Q, P, X, HE, VF>(a, t, item, B);
   __syncthreads();
@@ -1548,6 +1664,23 @@ constexpr int min_waves() {
     return P == 6 ? 2 : 1;
   }
   return 1;
+}
+
+// Waves per SIMD of the persistent kernels: their item loop leaves more
+// registers live than a one-item kernel, and at the one-item kernels'
+// occupancy the nuclear-matter kernels of orders 4 and 5 spilled 180-600
+// bytes per lane.  Measured on MI355X (every third fourth-order diagram and
+// every 42nd fifth-order one at the 15 nuclear-matter points, 2^22 samples
+// per task): fourth order fp32 23.6 Gevals/s at 3 waves against 20.3 at 4,
+// fp64 21.5 at 2 against 11.9 at 4; fifth order fp32 13.0 at 2 against 3.9 at
+// 4, fp64 7.4 at 2 against 5.6 at 3.
+template <int ORDER, int Q, int P, bool X>
+constexpr int persistent_waves() {
+  if (Q == 4 && !X && (P == 0 || P == 1)) {
+    if (ORDER == 4) return P == 1 ? 3 : 2;
+    if (ORDER == 5) return 2;
+  }
+  return min_waves<ORDER, Q, P, X>();
 }
 
 // One task per launch: block b processes work item item_begin + b.
@@ -1611,14 +1744,14 @@ __global__ __launch_bounds__(256, 3) void sample_order_fixed(
 // run of items (instead of once per item).  The counter starts at zero (task
 // set initialisation) and the iteration end zeroes it for the next iteration.
 template <int ORDER, int Q, int P, bool X, int HE>
-__global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_persistent(
+__global__ __launch_bounds__(256, (persistent_waves<ORDER, Q, P, X>())) void sample_persistent(
     KArgs a, int k0, int k1, int nitems, int chunk) {
   extern __shared__ double smem[];
   __shared__ int claim;
   const int2 *__restrict__ ol = a.olist;
   const int first = ol[k0].x;
   BlockLds B;
-  block_lds<ORDER, Q, P, X>(a, smem, B);
+  block_lds<ORDER, Q, P, X, kPerItemMasks>(a, smem, B);
   int cur = -1, lo = k0;
   for (;;) {
     __syncthreads();  // every thread has read the previous claim
@@ -1635,7 +1768,7 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_per
       if (t != cur) {
         if (cur >= 0) hist_flush<ORDER>(a, cur, B.h);
         __syncthreads();
-        task_lds<ORDER, Q, P, X>(a, t, B);
+        task_lds<ORDER, Q, P, X, kPerItemMasks>(a, t, B);
         __syncthreads();
         cur = t;
       }
@@ -1644,7 +1777,7 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_per
       // kernel)
       int tt = t, ii = item;
       asm volatile("" : "+s"(tt), "+s"(ii));
-      item_samples<ORDER, Q, P, X, HE>(a, tt, ii, B);
+      item_samples<ORDER, Q, P, X, HE, kPerItemMasks>(a, tt, ii, B);
     }
   }
   __syncthreads();
