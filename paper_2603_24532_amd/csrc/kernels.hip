@@ -406,10 +406,11 @@ __global__ void init_tasks(KArgs a, int first, int keep_grid) {
 
 size_t sample_lds_bytes(int nd, int nb, int block, int ntab) {
   // turn and 2^(j/64) tables + HF tables + grid pairs + histogram + reduction
-  // scratch + fp64 re-evaluation queue (128 sample offsets per wavefront)
+  // scratch + fp64 re-evaluation and Pauli screen queues (128 sample offsets
+  // per wavefront each)
   return fixed_lds_bytes() + hf_lds_doubles(ntab) * sizeof(double) +
          (3 * static_cast<size_t>(nd) * nb + 6 * (block / 64)) * sizeof(double) +
-         (block / 64) * 128 * sizeof(uint32_t);
+         (block / 64) * 256 * sizeof(uint32_t);
 }
 
 // Dispatch on (order, q) to the launchers of kernels_inst.hip.

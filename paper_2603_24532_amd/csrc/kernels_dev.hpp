@@ -775,7 +775,7 @@ __device__ __forceinline__ double rcp_newton(double d) {
 // REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
 // to wr[k - 1].
 template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V, int HE = 0, bool CY = false,
-          bool TAB = false>
+          bool TAB = false, bool SCR = false>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
@@ -825,6 +825,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   } else {
     if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
   }
+  if constexpr (SCR) return 1.0;  // the Pauli screen (see screen_on)
   ++npass;
 
   // energy denominators (with every line a neutron when they depend on
@@ -942,7 +943,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 // REG: the regularised components go to wr[0..nreg) (Jacobian and 1/n
 // included).
 template <int ORDER, int Q, bool HF, bool G, bool X, bool PI, int V, bool REG = false, int HE = 0,
-          bool TAB = false>
+          bool TAB = false, bool SCR = false>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, double jc, uint64_t s,
@@ -980,8 +981,9 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
       sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE>(a, T, D + di, Ls, k, npass, nterms, wr);
   } else {
     constexpr bool CY = cycle_form<ORDER, Q, false, X, HF>();
-    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, CY, TAB>(a, T, D, Ls, k, npass, nterms,
-                                                                wr);
+    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, CY, TAB, SCR>(a, T, D, Ls, k, npass,
+                                                                     nterms, wr);
+    if constexpr (SCR) return sum;
   }
   const double scale = jac * (x0p * x0p) * jc;
   if constexpr (REG)
@@ -1026,7 +1028,8 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 // sample in fp64 from the same random words.
 // fp32 contribution of one diagram at the loop momenta k (see
 // diag_weight64); sets `fallback` instead when the sample needs fp64.
-template <int ORDER, int Q, bool X, int V, int HE = 0, bool CY = false, bool TAB = false>
+template <int ORDER, int Q, bool X, int V, int HE = 0, bool CY = false, bool TAB = false,
+          bool SCR = false>
 __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const float (*k)[3],
@@ -1062,6 +1065,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
     }
   }
   if (near) {
+    if constexpr (SCR) return 1.0;  // the Pauli screen (see screen_on)
     fallback = true;
     return 0.0;
   }
@@ -1077,6 +1081,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   } else {
     if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
   }
+  if constexpr (SCR) return 1.0;
 
   float dprod = 1.0f;
   float kcut = 0.0f;  // sum of the cuts' condition numbers (sum |eps|) / |D|
@@ -1193,7 +1198,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
          static_cast<double>(rinv[NR - 1]);
 }
 
-template <int ORDER, int Q, bool G, bool X, int V, int HE = 0, bool TAB = false>
+template <int ORDER, int Q, bool G, bool X, int V, int HE = 0, bool TAB = false, bool SCR = false>
 __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, double jc, uint64_t s,
@@ -1237,7 +1242,8 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     nterms += gterms;
   } else {
     constexpr bool CY = cycle_form<ORDER, Q, false, X, false>();
-    sum = diag_weight32<ORDER, Q, X, V, HE, CY, TAB>(a, T, D, Ls, k, npass, nterms, fallback);
+    sum = diag_weight32<ORDER, Q, X, V, HE, CY, TAB, SCR>(a, T, D, Ls, k, npass, nterms, fallback);
+    if constexpr (SCR) return sum;
     if (fallback) return 0.0;
   }
   return jac * (x0p * x0p) * jc * sum;
@@ -1296,6 +1302,48 @@ __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__r
   return w;
 }
 
+// Pauli screen of the sample loops in mode P: every sample first runs the
+// integrand up to its Pauli test (the map, the momenta, the occupations and,
+// in nuclear matter, the label cycles left open); a sample that fails adds
+// its zero at once, and the others are queued per wavefront and evaluated 64
+// at a time, from their random words again.  Most samples are Pauli-blocked,
+// so whole wavefronts then run the denominators, interactions and label sum
+// instead of wavefronts with most lanes idle.  The queued evaluation repeats
+// the screen's arithmetic, so both take the same Pauli decision; a sample the
+// fp32 screen finds within the fp64 band is queued, and its evaluation then
+// falls back.  Fifth-order single diagrams (the free spectrum, the factorised
+// label sums), where the work after the Pauli test dominates: measured on
+// MI355X, nuclear matter fp32 and fp64 +25% (fp64 persistent +80%), neutron
+// matter fp32 +18% and fp64 +8% (fp64 persistent -10%).  At fourth order it
+// was slower (per-diagram kernels -13%, persistent -10 to -17%).
+template <int ORDER, int Q, int P, bool X>
+constexpr bool screen_on() {
+  return ORDER >= 5 && (P == 0 || P == 1) && !X;
+}
+
+// Appends the lanes with `flag` set to a wavefront's queue in LDS (ballot
+// order, so the order is deterministic); n is wave-uniform.
+__device__ __forceinline__ void wave_queue_push(uint32_t *q, int &n, bool flag, uint32_t v) {
+  const uint64_t mask = __ballot(flag);
+  if (flag)
+    q[n + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u))] = v;
+  n += __popcll(mask);
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Drops the first `take` entries of a wavefront's queue (take <= 64, at most
+// 64 entries left behind them).
+__device__ __forceinline__ void wave_queue_pop(uint32_t *q, int &n, int take, int lane) {
+  __builtin_amdgcn_wave_barrier();
+  const int rest = n - take;
+  const uint32_t moved = (lane < rest) ? q[take + lane] : 0u;
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rest) q[lane] = moved;
+  __builtin_amdgcn_wave_barrier();
+  n = rest;
+}
+
 // Bytes of the label-cycle table a sample or dump kernel of mode P holds in LDS.
 template <int ORDER, int Q, int P, bool X>
 constexpr size_t cycle_lds_bytes() {
@@ -1314,8 +1362,9 @@ constexpr int lds_tables() {
 // regulator exponent's half fixed at compile time, or 0, see reg_pow)
 
 // LDS of a sample block: turn and 2^(j/64) tables, HF tables, grid (e, width)
-// pairs, histogram, reduction scratch, fp64 re-evaluation queue (128 sample
-// offsets per wavefront), label-cycle table.
+// pairs, histogram, reduction scratch, fp64 re-evaluation queues and Pauli
+// screen queues (128 sample offsets per wavefront each), label-cycle table,
+// loop-coefficient table.
 struct BlockLds {
   SampleLds Ls;
   double2 *g;
@@ -1340,7 +1389,7 @@ __device__ __forceinline__ void block_lds(const KArgs &a, double *smem, BlockLds
   B.Ls.ex = ex;
   B.Ls.hf = ntab ? hf : nullptr;
   B.Ls.g = B.g;
-  uint32_t *queue_end = reinterpret_cast<uint32_t *>(B.red + 6 * nw) + 128 * nw;
+  uint32_t *queue_end = reinterpret_cast<uint32_t *>(B.red + 6 * nw) + 256 * nw;
   B.Ls.cyc = cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>() ? queue_end : nullptr;
   B.Ls.cd = nullptr;
   B.Ls.cf = nullptr;
@@ -1458,9 +1507,20 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
       for (int m = 0; m < ND; ++m) atomicAdd(&h[m * nb + bins[m]], w2);
     }
   };
+  // a sample that fails the Pauli screen: weight zero
+  auto accumulate_zero = [&]() {
+    const double d = -shift;
+    s1 += d;
+    s2 = fma(d, d, s2);
+  };
   constexpr int PP = prec_of<P>();
   constexpr bool G = group_of<P>();
   constexpr bool PI = pair_inv<ORDER, Q, P>();
+  constexpr bool SCR = screen_on<ORDER, Q, P, X>();
+  const int lane = tid & 63;
+  // per wavefront: the fp64 re-evaluation queue, then the Pauli screen's
+  uint32_t *queue = reinterpret_cast<uint32_t *>(red + 6 * (bs >> 6)) + 128 * (tid >> 6);
+  uint32_t *pqueue = queue + 128 * (bs >> 6);
   // the sample loops, specialised per diagram variant (uniform per item)
   auto loops = [&](auto vt) {
     constexpr int V = decltype(vt)::value;
@@ -1469,7 +1529,32 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
     constexpr bool TAB = coef_tab<ORDER, P, VF>();
     static_assert(!TAB || !FixedMasks<ORDER, V>::kFixed, "fixed masks need no table");
     const double jc = jac_const<ORDER, V>(a, T, D);
-    if (PP != 1) {
+    if constexpr (SCR && PP == 0) {
+      int pn = 0;  // wave-uniform
+      auto drain_pass = [&](int take) {
+        if (lane < take) {
+          const uint64_t s = base + pqueue[lane];
+          int bins[ND];
+          const double w = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE, TAB>(
+              a, T, D, Ls, jc, s, iter, bins, npass, nterms);
+          accumulate(w, bins);
+        }
+        wave_queue_pop(pqueue, pn, take, lane);
+      };
+      for (int kk = 0; kk < a.spt; ++kk) {
+        const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
+        bool go = false;
+        if (s < N) {
+          int bins[ND];
+          go = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE, TAB, true>(
+                   a, T, D, Ls, jc, s, iter, bins, npass, nterms) != 0.0;
+          if (!go) accumulate_zero();
+        }
+        wave_queue_push(pqueue, pn, go, static_cast<uint32_t>(s - base));
+        if (pn >= 64) drain_pass(64);
+      }
+      while (pn > 0) drain_pass(pn < 64 ? pn : 64);
+    } else if constexpr (PP != 1) {
       for (int kk = 0; kk < a.spt; ++kk) {
         const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
         if (s < N) {
@@ -1502,8 +1587,6 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
       // fp32 pass; samples in the fp64 band are queued per wavefront (ballot
       // order, so the accumulation order is deterministic) and re-evaluated in
       // fp64 by whole wavefronts, 64 at a time
-      const int lane = tid & 63;
-      uint32_t *queue = reinterpret_cast<uint32_t *>(red + 6 * (bs >> 6)) + 128 * (tid >> 6);
       int qn = 0;  // wave-uniform
       auto drain = [&](int take) {
         if (lane < take) {
@@ -1521,26 +1604,59 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
         __builtin_amdgcn_wave_barrier();
         qn = rest;
       };
-      for (int kk = 0; kk < a.spt; ++kk) {
-        const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
-        bool fb = false;
-        if (s < N) {
-          int bins[ND];
-          const double w = eval_fp32<ORDER, Q, G, X, V, HE, TAB>(a, T, D, Ls, jc, s, iter, bins,
-                                                                 npass, nterms, fb);
-          if (!fb) accumulate(w, bins);
+      if constexpr (SCR) {
+        int pn = 0;  // wave-uniform
+        auto drain_pass = [&](int take) {
+          bool fb = false;
+          uint32_t off = 0u;
+          if (lane < take) {
+            off = pqueue[lane];
+            int bins[ND];
+            const double w = eval_fp32<ORDER, Q, G, X, V, HE, TAB>(a, T, D, Ls, jc, base + off,
+                                                                   iter, bins, npass, nterms, fb);
+            if (!fb) accumulate(w, bins);
+          }
+          if (fb) ++nfb;
+          wave_queue_push(queue, qn, fb, off);
+          wave_queue_pop(pqueue, pn, take, lane);
+          if (qn >= 64) drain(64);
+        };
+        for (int kk = 0; kk < a.spt; ++kk) {
+          const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
+          bool go = false;
+          if (s < N) {
+            int bins[ND];
+            bool unused = false;
+            go = eval_fp32<ORDER, Q, G, X, V, HE, TAB, true>(a, T, D, Ls, jc, s, iter, bins, npass,
+                                                             nterms, unused) != 0.0;
+            if (!go) accumulate_zero();
+          }
+          wave_queue_push(pqueue, pn, go, static_cast<uint32_t>(s - base));
+          if (pn >= 64) drain_pass(64);
         }
-        const uint64_t mask = __ballot(fb);
-        if (fb) {
-          const int pos =
-              qn + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                             __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
-          queue[pos] = static_cast<uint32_t>(s - base);
-          ++nfb;
+        while (pn > 0) drain_pass(pn < 64 ? pn : 64);
+      } else {
+        for (int kk = 0; kk < a.spt; ++kk) {
+          const uint64_t s = base + static_cast<uint64_t>(kk) * bs + tid;
+          bool fb = false;
+          if (s < N) {
+            int bins[ND];
+            const double w = eval_fp32<ORDER, Q, G, X, V, HE, TAB>(a, T, D, Ls, jc, s, iter, bins,
+                                                                   npass, nterms, fb);
+            if (!fb) accumulate(w, bins);
+          }
+          const uint64_t mask = __ballot(fb);
+          if (fb) {
+            const int pos = qn + __builtin_amdgcn_mbcnt_hi(
+                                     static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+            queue[pos] = static_cast<uint32_t>(s - base);
+            ++nfb;
+          }
+          qn += __popcll(mask);
+          __builtin_amdgcn_wave_barrier();
+          if (qn >= 64) drain(64);
         }
-        qn += __popcll(mask);
-        __builtin_amdgcn_wave_barrier();
-        if (qn >= 64) drain(64);
       }
       while (qn > 0) drain(qn < 64 ? qn : 64);
     }
@@ -1562,7 +1678,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
       for (int j = 0; j < kRegSums; ++j) rs[j] += __shfl_xor(rs[j], off, 64);
     }
   }
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = tid >> 6;
   uint32_t *ured = reinterpret_cast<uint32_t *>(red + 4 * (bs >> 6));
   // component sums per wave in the (fp64-only, so unused) re-evaluation queue
   double *rred = red + 6 * (bs >> 6);
@@ -1641,9 +1757,10 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 //   4 waves with 60-130 spilled bytes beat 3 waves without (4-7%);
 // - nuclear matter with the cycle form of the label sum (single diagrams,
 //   work items of up to 65536 samples): fourth-order fp32 and fp64 at 4 waves
-//   (72-124 spilled bytes) beat 3 waves by 6% and 3%; fifth-order fp32 at 4
-//   waves beats 3 by 4%, fifth-order fp64 at 3 waves beats its natural 2 by 8%;
-//   fourth-order nuclear group kernels at 4 waves beat 3 by 7-8%.
+//   (72-124 spilled bytes) beat 3 waves by 6% and 3%; fourth-order nuclear
+//   group kernels at 4 waves beat 3 by 7-8%;
+// - fifth-order nuclear matter with the Pauli screen: fp32 at 3 waves beats 4
+//   by 8% and 2 by 11%, fp64 at 3 beats 2 by 11% and 4 by 16%.
 // Other kernels fit their natural occupancy.
 template <int ORDER, int Q, int P, bool X>
 constexpr int min_waves() {
@@ -1654,7 +1771,7 @@ constexpr int min_waves() {
   }
   if (Q == 4 && !X && (P == 0 || P == 1)) {
     if (ORDER == 4) return 4;
-    if (ORDER == 5) return P == 1 ? 4 : 3;
+    if (ORDER == 5) return 3;
   }
   if (Q == 4 && !X && ORDER == 4 && (P == 3 || P == 4)) return 4;
   if (ORDER == 3 && (P == 0 || P == 1)) return 4;

@@ -139,6 +139,40 @@ def test_launch_modes_agree(M):
         assert np.allclose(other, res[0], rtol=1e-7, atol=0), (res[0], other)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("matter", ["nuclear", "neutron"])
+def test_coefficient_table_equals_masks(M, precision, matter):
+    """The descriptor-driven kernels of orders 4 and 5 read the loop
+    coefficients from a table in LDS in the per-task and per-order launches,
+    and decode them from the descriptor masks in the persistent launches.  The
+    same operations on the same values: with the same work items, the first
+    iteration (uniform grid, no histogram dependence) gives bit-identical
+    estimates, variances and fp32 fallback counts."""
+    if matter == "nuclear":
+        tasks = [_task(5, 300, 4, 0.20, 0.1, 14), _task(5, 611, 4, 0.12, 0.5, 15)]
+    else:
+        tasks = [_task(5, 42, 2, 0.16, 0.0, 16), _task(4, 7, 2, 0.16, 0.0, 6),
+                 _task(4, 30, 2, 0.08, 0.0, 7)]
+    N = (1 << 16) + 777
+    prec = M.MBPT_FP64 if precision == "fp64" else M.MBPT_FP32
+    out = {}
+    for mode in (0, 1, 3):
+        print(f"case table/masks {matter} mode={mode} {precision}", flush=True)
+        run = Run(M, tasks, max_samples=N, mode=mode, precision=prec, spt=16)
+        try:
+            per, _ = M.mbpt_integrate(run.set, N, 1)
+            logs = [M.mbpt_iteration_log(run.set, k) for k in range(len(tasks))]
+        finally:
+            run.close()
+        out[mode] = ([(p.n_evals, p.n_fp64_fallback) for p in per],
+                     np.array([[l[0][0], l[1][0]] for l in logs]))
+    for mode in (0, 1):
+        assert out[mode][0] == out[3][0], (mode, out[mode][0], out[3][0])
+        assert np.array_equal(out[mode][1], out[3][1]), (mode, out[mode][1], out[3][1])
+    if precision == "fp32":
+        assert sum(f for _, f in out[3][0]) > 0  # the fallback path ran
+
+
 def test_resume_equals_uninterrupted(M):
     tasks = [_task(2, 0, 2, 0.12, 0.0, 3)]
     a = Run(M, tasks, max_samples=30000)
