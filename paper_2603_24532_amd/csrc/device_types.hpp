@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace mbpt {
 
@@ -117,6 +118,18 @@ struct FixedMasks<3, 2> {
 
 // the 39 fourth-order diagrams (generated; per-diagram fourth-order kernels)
 #include "fixed_masks_o4.hpp"
+
+namespace mbpt {
+
+// FixedMasks that also hold the diagram's label cycles as compile-time
+// constants (cyc_e32, the packing of DiagDev::cyc_e32): the generated
+// fourth-order tables.
+template <typename F, typename = void>
+struct fixed_cycles : std::false_type {};
+template <typename F>
+struct fixed_cycles<F, std::void_t<decltype(F::cyc_e32)>> : std::true_type {};
+
+}  // namespace mbpt
 
 namespace mbpt {
 

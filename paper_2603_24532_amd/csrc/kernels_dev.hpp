@@ -554,10 +554,16 @@ __device__ __forceinline__ double group_den(const DiagDev *__restrict__ D, uint3
 // protons): exactly when some isospin configuration passes the Pauli test.
 // Cycle set and cycle count of E (fourth order and below: at most 17
 // cycles, the 32-bit packing).
-template <int ORDER>
+// V: the diagram variant; where FixedMasks<ORDER, V> holds the cycles they
+// are compile-time constants.
+template <int ORDER, int V = -1>
 __device__ __forceinline__ void cycles_of_e(const DiagDev *__restrict__ D, int E,
                                             CycWord<ORDER> &m, uint32_t &n) {
-  if constexpr (ORDER >= 5) {
+  if constexpr (ORDER == 4 && fixed_cycles<FixedMasks<ORDER, V>>::value) {
+    const uint32_t w = FixedMasks<ORDER, V>::cyc_e32[E];
+    m = w & 0xFFFFFFu;
+    n = w >> 24;
+  } else if constexpr (ORDER >= 5) {
     const uint64_t w = D->cyc_e[E];
     m = w & ((uint64_t{1} << 56) - 1);
     n = static_cast<uint32_t>(w >> 56);
@@ -568,14 +574,14 @@ __device__ __forceinline__ void cycles_of_e(const DiagDev *__restrict__ D, int E
   }
 }
 
-template <int ORDER>
+template <int ORDER, int V = -1>
 __device__ __forceinline__ bool cycle_any(const DiagDev *__restrict__ D, CycWord<ORDER> ab) {
   bool any = false;
 #pragma unroll
   for (int E = 0; E < (1 << ORDER); ++E) {
     CycWord<ORDER> m;
     uint32_t n;
-    cycles_of_e<ORDER>(D, E, m, n);
+    cycles_of_e<ORDER, V>(D, E, m, n);
     any |= (ab & m) == m;
   }
   return any;
@@ -608,7 +614,7 @@ __device__ __forceinline__ uint32_t popc_w(W x) {
 // The monomials carry the sign (-V_e) and are tabulated as in the
 // configuration form; the counts are integers, so the sum equals the sum over
 // isospin configurations up to rounding.
-template <int ORDER, typename F, bool ABS = false>
+template <int ORDER, typename F, bool ABS = false, int V = -1>
 __device__ __forceinline__ F label_sum_cycles(const DiagDev *__restrict__ D, const F *Vd,
                                               const F *Ve, CycWord<ORDER> cA, CycWord<ORDER> cB,
                                               F *absum = nullptr) {
@@ -638,7 +644,7 @@ __device__ __forceinline__ F label_sum_cycles(const DiagDev *__restrict__ D, con
       const int E = ea | (eb << H);
       W m;
       uint32_t n;
-      cycles_of_e<ORDER>(D, E, m, n);
+      cycles_of_e<ORDER, V>(D, E, m, n);
       const uint32_t e = popc_w<ORDER>(both & m) + n;
       const F c = (ab & m) == m ? pow2_bits<F>(e) : F(0);
       in = fma_t<F>(c, MA[ea], in);
@@ -821,7 +827,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
     const CycWord<ORDER> *tab = static_cast<const CycWord<ORDER> *>(Ls.cyc);
     cA = tab[~okN & lmask];
     cB = tab[~okP & lmask];
-    if (!cycle_any<ORDER>(D, cA | cB)) return 0.0;
+    if (!cycle_any<ORDER, V>(D, cA | cB)) return 0.0;
   } else {
     if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
   }
@@ -919,7 +925,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   double acc;
   if constexpr (CY) {
     ++nterms;
-    acc = label_sum_cycles<ORDER, double>(D, Vd, Ve, cA, cB);
+    acc = label_sum_cycles<ORDER, double, false, V>(D, Vd, Ve, cA, cB);
   } else {
     acc = label_sum<ORDER, Q, double, iso_den, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms, Dn,
                                                      deps);
@@ -1077,7 +1083,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
     const CycWord<ORDER> *tab = static_cast<const CycWord<ORDER> *>(Ls.cyc);
     cA = tab[~okN & lmask];
     cB = tab[~okP & lmask];
-    if (!cycle_any<ORDER>(D, cA | cB)) return 0.0;
+    if (!cycle_any<ORDER, V>(D, cA | cB)) return 0.0;
   } else {
     if (!pauli_allowed<Q>(a, D, okN, okP, lmask)) return 0.0;
   }
@@ -1167,7 +1173,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
     float aabs;
     if constexpr (CY) {
       ++nterms;
-      acc = label_sum_cycles<ORDER, float, true>(D, Vd, Ve, cA, cB, &aabs);
+      acc = label_sum_cycles<ORDER, float, true, V>(D, Vd, Ve, cA, cB, &aabs);
     } else {
       acc = label_sum<ORDER, Q, float, false, X, V, true>(a, D, Vd, Ve, okN, okP, lmask, nterms,
                                                           nullptr, nullptr, &aabs);
@@ -1187,7 +1193,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   } else {
     if constexpr (CY) {
       ++nterms;
-      acc = label_sum_cycles<ORDER, float>(D, Vd, Ve, cA, cB);
+      acc = label_sum_cycles<ORDER, float, false, V>(D, Vd, Ve, cA, cB);
     } else {
       acc = label_sum<ORDER, Q, float, false, X, V>(a, D, Vd, Ve, okN, okP, lmask, nterms,
                                                    nullptr, nullptr);

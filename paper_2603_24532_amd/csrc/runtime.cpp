@@ -321,9 +321,23 @@ static bool fixed_masks_match(const DiagDev &dd) {
   return ok;
 }
 
+// The fourth-order tables also fix the label cycles per vertex-term choice.
+template <int V>
+static bool fixed_cycles_match(const Diagram &d) {
+  using F = FixedMasks<4, V>;
+  const CycleTables ct = cycle_tables(d, false);
+  if (ct.masks.size() > 24 || ct.of_e.size() != 16) return false;
+  bool ok = true;
+  for (int E = 0; E < 16; ++E)
+    ok = ok && F::cyc_e32[E] ==
+                   static_cast<uint32_t>(ct.of_e[E] | static_cast<uint64_t>(ct.n_of_e[E]) << 24);
+  return ok;
+}
+
 template <typename Dev, int... I>
 static bool fixed4_match(Dev &&dev, std::integer_sequence<int, I...>) {
-  return (fixed_masks_match<4, I>(dev(4, I, false)) && ...);
+  return ((fixed_masks_match<4, I>(dev(4, I, false)) &&
+           fixed_cycles_match<I>(*get_diagram(4, I))) && ...);
 }
 
 bool fixed_masks_ok() {
@@ -902,7 +916,7 @@ extern "C" int mbpt_create_task_set(mbpt_context *ctx, const mbpt_task_desc *tas
   if (!ctx || !out) return MBPT_EINVAL;
   *out = nullptr;
   if (!fixed_masks_ok()) {
-    set_err(ctx, "internal: the order-1/2/3 descriptors differ from the kernels' fixed masks");
+    set_err(ctx, "internal: the generator's descriptors differ from the kernels' compile-time tables");
     return MBPT_EINVAL;
   }
   int q = 2;
