@@ -117,6 +117,15 @@ constexpr size_t coef_lds_bytes() {
 template <int ORDER>
 using CycWord = std::conditional_t<(ORDER >= 5), uint64_t, uint32_t>;
 
+// Fifth-order diagrams with at most 24 label cycles (696 of the 840) run the
+// variant kNarrowCycles of the cycle-form kernels, with 32-bit cycle words
+// (the packing of DiagDev::cyc_e32): half the scalar registers for the
+// per-E words and single-word bit operations per term.
+constexpr int kNarrowCycles = -4;
+constexpr int kNarrowCycleMax = 24;
+template <int ORDER, int V>
+using CycWordV = std::conditional_t<(ORDER >= 5 && V != kNarrowCycles), uint64_t, uint32_t>;
+
 // The nuclear-matter label sum runs in the cycle form (see label_sum) for
 // single diagrams with the free spectrum and the factorised label sum.
 template <int ORDER, int Q, bool G, bool X, bool HF>
@@ -132,17 +141,26 @@ __host__ __device__ constexpr size_t cycle_table_bytes() {
 
 // tab[s] = the cycles of diagram D that contain no line of the line set s
 // (bit k set if (s & cycle k) = 0); built by the whole block.
-template <int ORDER>
-__device__ __forceinline__ void build_cycle_table(const DiagDev *__restrict__ D,
-                                                  CycWord<ORDER> *tab) {
+template <typename W>
+__device__ __forceinline__ void fill_cycle_table(const DiagDev *__restrict__ D, int nsets,
+                                                 W *tab) {
   const int K = D->ncyc;
-  for (int s = threadIdx.x; s < (1 << (2 * ORDER)); s += blockDim.x) {
-    CycWord<ORDER> w = 0;
+  for (int s = threadIdx.x; s < nsets; s += blockDim.x) {
+    W w = 0;
     for (int k = 0; k < K; ++k)
-      w |= (static_cast<uint32_t>(s) & D->cyc_mask[k]) == 0u ? (CycWord<ORDER>(1) << k)
-                                                            : CycWord<ORDER>(0);
+      w |= (static_cast<uint32_t>(s) & D->cyc_mask[k]) == 0u ? (W(1) << k) : W(0);
     tab[s] = w;
   }
+}
+// In the words of the variant with_variant picks for D: 32 bits for a
+// fifth-order diagram of at most kNarrowCycleMax cycles.
+template <int ORDER>
+__device__ __forceinline__ void build_cycle_table(const DiagDev *__restrict__ D, void *tab) {
+  constexpr int NS = 1 << (2 * ORDER);
+  if (ORDER >= 5 && D->ncyc <= kNarrowCycleMax)
+    fill_cycle_table(D, NS, static_cast<uint32_t *>(tab));
+  else
+    fill_cycle_table(D, NS, static_cast<CycWord<ORDER> *>(tab));
 }
 
 // Bytes of the fixed tables at the start of a sample kernel's LDS.
@@ -326,8 +344,10 @@ __device__ __forceinline__ bool loop_part_of(const DiagDev *__restrict__ D, int 
 // Runs f(std::integral_constant<int, V>) with the diagram variant of a task
 // whose first descriptor is D: the one diagram of orders 1-2 (also as a
 // single-member group), the diagram id at order 3 for single-diagram tasks,
-// the generic path (-1) otherwise.  The branch is uniform per work item.
-template <int ORDER, bool G, typename Fn>
+// for the cycle form (CYF) at fifth order kNarrowCycles where the diagram
+// has at most kNarrowCycleMax cycles, the generic path (-1) otherwise.  The
+// branch is uniform per work item.
+template <int ORDER, bool G, bool CYF = false, typename Fn>
 __device__ __forceinline__ void with_variant(const DiagDev *__restrict__ D, Fn &&f) {
   if constexpr (ORDER <= 2) {
     f(std::integral_constant<int, 0>{});
@@ -336,6 +356,9 @@ __device__ __forceinline__ void with_variant(const DiagDev *__restrict__ D, Fn &
     if (D->id == 0) f(std::integral_constant<int, 0>{});
     else if (D->id == 1) f(std::integral_constant<int, 1>{});
     else f(std::integral_constant<int, 2>{});
+  } else if constexpr (ORDER >= 5 && CYF) {
+    if (D->ncyc <= kNarrowCycleMax) f(std::integral_constant<int, kNarrowCycles>{});
+    else f(std::integral_constant<int, -1>{});
   } else {
     f(std::integral_constant<int, -1>{});
   }
@@ -558,9 +581,13 @@ __device__ __forceinline__ double group_den(const DiagDev *__restrict__ D, uint3
 // are compile-time constants.
 template <int ORDER, int V = -1>
 __device__ __forceinline__ void cycles_of_e(const DiagDev *__restrict__ D, int E,
-                                            CycWord<ORDER> &m, uint32_t &n) {
+                                            CycWordV<ORDER, V> &m, uint32_t &n) {
   if constexpr (ORDER == 4 && fixed_cycles<FixedMasks<ORDER, V>>::value) {
     const uint32_t w = FixedMasks<ORDER, V>::cyc_e32[E];
+    m = w & 0xFFFFFFu;
+    n = w >> 24;
+  } else if constexpr (ORDER >= 5 && V == kNarrowCycles) {
+    const uint32_t w = D->cyc_e32[E];
     m = w & 0xFFFFFFu;
     n = w >> 24;
   } else if constexpr (ORDER >= 5) {
@@ -575,11 +602,11 @@ __device__ __forceinline__ void cycles_of_e(const DiagDev *__restrict__ D, int E
 }
 
 template <int ORDER, int V = -1>
-__device__ __forceinline__ bool cycle_any(const DiagDev *__restrict__ D, CycWord<ORDER> ab) {
+__device__ __forceinline__ bool cycle_any(const DiagDev *__restrict__ D, CycWordV<ORDER, V> ab) {
   bool any = false;
 #pragma unroll
   for (int E = 0; E < (1 << ORDER); ++E) {
-    CycWord<ORDER> m;
+    CycWordV<ORDER, V> m;
     uint32_t n;
     cycles_of_e<ORDER, V>(D, E, m, n);
     any |= (ab & m) == m;
@@ -616,9 +643,9 @@ __device__ __forceinline__ uint32_t popc_w(W x) {
 // isospin configurations up to rounding.
 template <int ORDER, typename F, bool ABS = false, int V = -1>
 __device__ __forceinline__ F label_sum_cycles(const DiagDev *__restrict__ D, const F *Vd,
-                                              const F *Ve, CycWord<ORDER> cA, CycWord<ORDER> cB,
-                                              F *absum = nullptr) {
-  using W = CycWord<ORDER>;
+                                              const F *Ve, CycWordV<ORDER, V> cA,
+                                              CycWordV<ORDER, V> cB, F *absum = nullptr) {
+  using W = CycWordV<ORDER, V>;
   constexpr int H = ORDER / 2;
   constexpr int NA = 1 << H, NB = 1 << (ORDER - H);
   F nVe[ORDER];
@@ -822,9 +849,9 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
   const uint32_t lmask = line_mask_of<ORDER, V>(D), pmask = part_mask_of<ORDER, V>(D);
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
-  CycWord<ORDER> cA = 0, cB = 0;
+  CycWordV<ORDER, V> cA = 0, cB = 0;
   if constexpr (CY) {
-    const CycWord<ORDER> *tab = static_cast<const CycWord<ORDER> *>(Ls.cyc);
+    const CycWordV<ORDER, V> *tab = static_cast<const CycWordV<ORDER, V> *>(Ls.cyc);
     cA = tab[~okN & lmask];
     cB = tab[~okP & lmask];
     if (!cycle_any<ORDER, V>(D, cA | cB)) return 0.0;
@@ -1078,9 +1105,9 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
   const uint32_t lmask = line_mask_of<ORDER, V>(D), pmask = part_mask_of<ORDER, V>(D);
   const uint32_t okN = (inN ^ pmask) & lmask;
   const uint32_t okP = (inP ^ pmask) & lmask;
-  CycWord<ORDER> cA = 0, cB = 0;
+  CycWordV<ORDER, V> cA = 0, cB = 0;
   if constexpr (CY) {
-    const CycWord<ORDER> *tab = static_cast<const CycWord<ORDER> *>(Ls.cyc);
+    const CycWordV<ORDER, V> *tab = static_cast<const CycWordV<ORDER, V> *>(Ls.cyc);
     cA = tab[~okN & lmask];
     cB = tab[~okP & lmask];
     if (!cycle_any<ORDER, V>(D, cA | cB)) return 0.0;
@@ -1291,7 +1318,7 @@ __device__ __forceinline__ double eval_sample(const KArgs &a, const TaskDev *__r
   constexpr bool G = group_of<P>();
   constexpr bool PI = pair_inv<ORDER, Q, P>();
   double w = 0.0;
-  with_variant<ORDER, G>(D, [&](auto vt) {
+  with_variant<ORDER, G, cycle_form<ORDER, Q, G, X, PP == 2>()>(D, [&](auto vt) {
     constexpr int V = decltype(vt)::value;
     const double jc = jac_const<ORDER, V>(a, T, D);
     if (PP != 1) {
@@ -1434,8 +1461,7 @@ __device__ __forceinline__ void task_lds(const KArgs &a, int t, BlockLds &B) {
     B.h[i] = 0.0;
   }
   if constexpr (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>())
-    build_cycle_table<ORDER>(a.diags + T->diag,
-                             static_cast<CycWord<ORDER> *>(const_cast<void *>(B.Ls.cyc)));
+    build_cycle_table<ORDER>(a.diags + T->diag, const_cast<void *>(B.Ls.cyc));
   if constexpr (coef_tab<ORDER, P, VF>()) {
     // decoded by the helpers of masked_sum, so a table sum performs the
     // same operations on the same values
@@ -1668,7 +1694,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
     }
   };
   if constexpr (VF >= 0) loops(std::integral_constant<int, VF>{});
-  else with_variant<ORDER, G>(D, loops);
+  else with_variant<ORDER, G, cycle_form<ORDER, Q, G, X, PP == 2>()>(D, loops);
   // wavefront butterfly, then waves in order (compensated pairs s + c)
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -1832,15 +1858,17 @@ __global__ __launch_bounds__(256, (min_waves<ORDER, Q, P, X>())) void sample_ord
   process_item<ORDER, Q, P, X, HE>(a, ol[lo].y, item, smem);
 }
 
-// sample_order for the tasks of one diagram whose descriptor masks are
-// compile-time constants (FixedMasks<ORDER, V>, V = the diagram id): the
-// loop-momentum sums keep only their nonzero terms and need no scalar
-// decoding.  The same operations as the descriptor-driven kernel (a product
-// with a coefficient 0, +-1, +-2 or +-1/2 is exact), but with the masks known
-// the compiler may fuse other multiply-adds (shared vertex momenta), so the
-// weights agree to their last bits.  Built for 3 waves per SIMD: measured on the 585
-// fourth-order nuclear-matter tasks, fp64 41.3 Gevals/s at 3 against 32.6 at 4
-// (and 41.1 at 2), fp32 within 2% at 3 and 4 (36.7 at 2).
+// sample_order for the tasks of one diagram whose descriptor masks and label
+// cycles are compile-time constants (FixedMasks<ORDER, V>, V = the diagram
+// id): the loop-momentum sums keep only their nonzero terms and need no
+// scalar decoding, and the cycle words take no scalar registers.  The same
+// operations as the descriptor-driven kernel (a product with a coefficient 0,
+// +-1, +-2 or +-1/2 is exact), but with the masks known the compiler may fuse
+// other multiply-adds (shared vertex momenta), so the weights agree to their
+// last bits.  Built for 3 waves per SIMD, as measured on the 585
+// fourth-order nuclear-matter tasks: fp64 44.1 Gevals/s at 3 against 36.6 at
+// 4 and 44.1 at 2; fp32 47.6 at 3 against 41.0 at 2 and 49.5 at 4, where 31
+// spilled VGPRs raise the HBM traffic from 1.1 GB to 17 GB per iteration.
 template <int ORDER, int Q, int P, int HE, int V>
 __global__ __launch_bounds__(256, 3) void sample_order_fixed(
     KArgs a, int k0, int k1) {
@@ -1931,7 +1959,7 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
     g[i] = make_double2(fma(e1 - e0, 0x1p-33, e0), e1 - e0);
   }
   if constexpr (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>()) {
-    CycWord<ORDER> *tab = reinterpret_cast<CycWord<ORDER> *>(g + ND * nb);
+    void *tab = g + ND * nb;
     build_cycle_table<ORDER>(D, tab);
     Ls.cyc = tab;
   }
@@ -1942,7 +1970,8 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
     uint32_t np = 0, nt = 0, nf = 0;
     if constexpr (reg_of<P>()) {
       double wr[kMaxReg];
-      with_variant<ORDER, group_of<P>()>(D, [&](auto vt) {
+      with_variant<ORDER, group_of<P>(), cycle_form<ORDER, Q, group_of<P>(), X, false>()>(
+          D, [&](auto vt) {
         constexpr int V = decltype(vt)::value;
         out[i] = eval_fp64<ORDER, Q, false, group_of<P>(), X, PI, V, true, HE>(
             a, T, D, Ls, jac_const<ORDER, V>(a, T, D), first + i, iter, bins, np, nt, wr);
