@@ -348,3 +348,26 @@ def test_flop_model_units_match_label_statistics(M):
             assert M.mbpt_diagram_flops(order, did, matter)["units"] == (1 if nuclear else n_iso)
             assert M.mbpt_diagram_flops(order, did, matter, spectrum=1)["units"] == n_iso
             assert M.mbpt_diagram_flops(order, did, matter, label_mode=1)["units"] == n_terms
+
+
+def test_generated_fourth_order_tables_match_the_generator(M, tmp_path):
+    """The per-diagram fourth-order kernels take their descriptor masks and
+    label cycles from csrc/fixed_masks_o4.hpp.  Rebuilding its generator
+    against the library and running it reproduces the committed header byte
+    for byte (task-set and server creation also check the tables at run
+    time, on the GPU)."""
+    import shutil
+    import subprocess
+    M.lib()
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not shutil.which(hipcc):
+        pytest.skip("no hipcc")
+    pkg = os.path.join(ROOT, "paper_2603_24532_amd")
+    csrc = os.path.join(pkg, "csrc")
+    exe = str(tmp_path / "gen_fixed_masks")
+    subprocess.run([hipcc, "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", csrc,
+                    os.path.join(csrc, "gen_fixed_masks.cpp"), "-L", pkg, "-lmbpt_vegas",
+                    f"-Wl,-rpath,{pkg}", "-o", exe], check=True, capture_output=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    assert out == open(os.path.join(csrc, "fixed_masks_o4.hpp")).read()
+    assert out.count("struct FixedMasks<4, ") == 39 and out.count("cyc_e32[16]") == 39
