@@ -176,6 +176,11 @@ constexpr int kHfEntries = kHfIntervals + 1;
 constexpr double kHfRangeLambda = 6.0;
 constexpr int kHfGauss = 64;  // Gauss-Legendre points per dimension
 
+// Diagram groups of orders 3 and 4 in nuclear matter hold one label-cycle
+// table per member in LDS: at most this many members (the largest group has
+// 22, checked when task sets and servers are created).
+constexpr int kGroupCycleTables = 22;
+
 // Regularised energy-denominator components (D_c -> D_c - k eta, k = 1..nreg).
 constexpr int kMaxReg = 4;
 // Sums per work item and per logged iteration of the regularised modes: a

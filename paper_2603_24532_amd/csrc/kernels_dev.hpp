@@ -132,6 +132,12 @@ template <int ORDER, int Q, bool G, bool X, bool HF>
 constexpr bool cycle_form() {
   return Q == 4 && ORDER >= 2 && !G && !X && !HF;
 }
+// Diagram groups of orders 3 and 4 run the cycle form per member, with one
+// cycle table per member in LDS (kGroupCycleTables of them).
+template <int ORDER, int Q, bool X, bool HF>
+constexpr bool group_cycle_form() {
+  return Q == 4 && (ORDER == 3 || ORDER == 4) && !X && !HF;
+}
 
 // Bytes of the label-cycle table: one CycWord per set of lines.
 template <int ORDER>
@@ -1010,8 +1016,17 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
   if constexpr (G) {
     sum = 0.0;
     const int nd = T->ndiag;
-    for (int di = 0; di < nd; ++di)
-      sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE>(a, T, D + di, Ls, k, npass, nterms, wr);
+    for (int di = 0; di < nd; ++di) {
+      if constexpr (group_cycle_form<ORDER, Q, X, HF>()) {
+        SampleLds Lm = Ls;  // the member's cycle table
+        Lm.cyc = static_cast<const char *>(Ls.cyc) + di * cycle_table_bytes<ORDER>();
+        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, true>(a, T, D + di, Lm, k, npass,
+                                                                    nterms, wr);
+      } else {
+        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE>(a, T, D + di, Ls, k, npass, nterms,
+                                                              wr);
+      }
+    }
   } else {
     constexpr bool CY = cycle_form<ORDER, Q, false, X, HF>();
     sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, CY, TAB, SCR>(a, T, D, Ls, k, npass,
@@ -1268,7 +1283,14 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     // that falls back is counted once, by its fp64 re-evaluation
     uint32_t gpass = 0, gterms = 0;
     for (int di = 0; di < nd; ++di) {
-      sum += diag_weight32<ORDER, Q, X, V, HE>(a, T, D + di, Ls, k, gpass, gterms, fallback);
+      if constexpr (group_cycle_form<ORDER, Q, X, false>()) {
+        SampleLds Lm = Ls;  // the member's cycle table
+        Lm.cyc = static_cast<const char *>(Ls.cyc) + di * cycle_table_bytes<ORDER>();
+        sum += diag_weight32<ORDER, Q, X, V, HE, true>(a, T, D + di, Lm, k, gpass, gterms,
+                                                       fallback);
+      } else {
+        sum += diag_weight32<ORDER, Q, X, V, HE>(a, T, D + di, Ls, k, gpass, gterms, fallback);
+      }
       if (fallback) return 0.0;  // the whole sample is re-evaluated in fp64
     }
     npass += gpass;
@@ -1380,8 +1402,27 @@ __device__ __forceinline__ void wave_queue_pop(uint32_t *q, int &n, int take, in
 // Bytes of the label-cycle table a sample or dump kernel of mode P holds in LDS.
 template <int ORDER, int Q, int P, bool X>
 constexpr size_t cycle_lds_bytes() {
-  return cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>() ? cycle_table_bytes<ORDER>()
-                                                                    : 0;
+  if (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>()) return cycle_table_bytes<ORDER>();
+  if (group_of<P>() && group_cycle_form<ORDER, Q, X, prec_of<P>() == 2>())
+    return kGroupCycleTables * cycle_table_bytes<ORDER>();
+  return 0;
+}
+template <int ORDER, int Q, int P, bool X>
+constexpr bool holds_cycles() {
+  return cycle_lds_bytes<ORDER, Q, P, X>() > 0;
+}
+
+// Builds the label-cycle tables of task T's diagram (one) or of its group's
+// members (one per member, consecutive) at tab; the whole block takes part.
+template <int ORDER, int Q, int P, bool X>
+__device__ __forceinline__ void build_task_cycles(const DiagDev *__restrict__ D,
+                                                  const TaskDev *__restrict__ T, void *tab) {
+  if constexpr (group_of<P>()) {
+    for (int di = 0; di < T->ndiag; ++di)
+      build_cycle_table<ORDER>(D + di, static_cast<char *>(tab) + di * cycle_table_bytes<ORDER>());
+  } else {
+    build_cycle_table<ORDER>(D, tab);
+  }
 }
 
 // HF spline tables held in LDS in mode P
@@ -1423,7 +1464,7 @@ __device__ __forceinline__ void block_lds(const KArgs &a, double *smem, BlockLds
   B.Ls.hf = ntab ? hf : nullptr;
   B.Ls.g = B.g;
   uint32_t *queue_end = reinterpret_cast<uint32_t *>(B.red + 6 * nw) + 256 * nw;
-  B.Ls.cyc = cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>() ? queue_end : nullptr;
+  B.Ls.cyc = holds_cycles<ORDER, Q, P, X>() ? queue_end : nullptr;
   B.Ls.cd = nullptr;
   B.Ls.cf = nullptr;
   if constexpr (coef_tab<ORDER, P, VF>()) {
@@ -1460,8 +1501,8 @@ __device__ __forceinline__ void task_lds(const KArgs &a, int t, BlockLds &B) {
     B.g[i] = make_double2(fma(e1 - e0, 0x1p-33, e0), e1 - e0);
     B.h[i] = 0.0;
   }
-  if constexpr (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>())
-    build_cycle_table<ORDER>(a.diags + T->diag, const_cast<void *>(B.Ls.cyc));
+  if constexpr (holds_cycles<ORDER, Q, P, X>())
+    build_task_cycles<ORDER, Q, P, X>(a.diags + T->diag, T, const_cast<void *>(B.Ls.cyc));
   if constexpr (coef_tab<ORDER, P, VF>()) {
     // decoded by the helpers of masked_sum, so a table sum performs the
     // same operations on the same values
@@ -1958,9 +1999,9 @@ __global__ __launch_bounds__(256) void dump_samples(KArgs a, int t, uint32_t ite
     const double e0 = ge[m * (nb + 1) + b], e1 = ge[m * (nb + 1) + b + 1];
     g[i] = make_double2(fma(e1 - e0, 0x1p-33, e0), e1 - e0);
   }
-  if constexpr (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>()) {
+  if constexpr (holds_cycles<ORDER, Q, P, X>()) {
     void *tab = g + ND * nb;
-    build_cycle_table<ORDER>(D, tab);
+    build_task_cycles<ORDER, Q, P, X>(D, T, tab);
     Ls.cyc = tab;
   }
   __syncthreads();

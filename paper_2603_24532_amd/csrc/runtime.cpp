@@ -358,6 +358,10 @@ bool fixed_masks_ok() {
     // the 39 fourth-order diagrams of the per-diagram kernels
     r = r && num_diagrams(4) == 39 &&
         fixed4_match(dev, std::make_integer_sequence<int, 39>{});
+    // groups of orders 3 and 4 hold one cycle table per member in LDS
+    for (int order = 3; order <= 4; ++order)
+      for (int p = 0; p <= order; ++p)
+        r = r && group_members(order, p).size() <= static_cast<size_t>(kGroupCycleTables);
     return r;
   }();
   return ok;
