@@ -1831,7 +1831,8 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 // - nuclear matter with the cycle form of the label sum (single diagrams,
 //   work items of up to 65536 samples): fourth-order fp32 and fp64 at 4 waves
 //   (72-124 spilled bytes) beat 3 waves by 6% and 3%; fourth-order nuclear
-//   group kernels at 4 waves beat 3 by 7-8%;
+//   group kernels, whose per-member cycle tables leave LDS for 3 blocks per
+//   CU, run 3-5% faster at 3 waves than at 4 and 8-13% faster than at 2;
 // - fifth-order nuclear matter with the Pauli screen: fp32 at 3 waves beats 4
 //   by 8% and 2 by 11%, fp64 at 3 beats 2 by 11% and 4 by 16%.
 // Other kernels fit their natural occupancy.
@@ -1846,7 +1847,6 @@ constexpr int min_waves() {
     if (ORDER == 4) return 4;
     if (ORDER == 5) return 3;
   }
-  if (Q == 4 && !X && ORDER == 4 && (P == 3 || P == 4)) return 4;
   if (ORDER == 3 && (P == 0 || P == 1)) return 4;
   if (ORDER == 4) return (P == 0 || P == 1 || P == 3 || P == 4 || P == 5) ? 3 : 2;
   if (ORDER == 5) {
