@@ -14,6 +14,11 @@ constexpr int kMaxBins = 128;
 constexpr int kMaxCycles = 40;
 constexpr int kBlockMax = 1024;
 
+// Decoded loop coefficients per descriptor: 4 n sums (n <= 5) of at most
+// 6 loops, padded to 8.
+constexpr int kDescCoefSums = 20;
+constexpr int kDescCoefStride = 8;
+
 // Compiled diagram (read wave-uniformly through the scalar cache).
 struct alignas(16) DiagDev {
   int order, nlines, nloops, ncuts;
@@ -44,6 +49,13 @@ struct alignas(16) DiagDev {
   uint32_t cyc_mask[kMaxCycles];
   uint64_t cyc_e[32];
   uint32_t cyc_e32[32];
+  // The loop coefficients of lmask / pmask_v / qmask_v decoded (the vertex
+  // sums halved): sum s < 2 order is line slot s, then (2p, 2p') of each
+  // vertex; fp64, then fp32.  The group kernels, whose member loop runs at
+  // run time, read them through the scalar cache instead of decoding the
+  // masks per sum and sample.
+  double coef_d[kDescCoefSums][kDescCoefStride];
+  float coef_f[kDescCoefSums][kDescCoefStride];
 };
 
 // Compile-time descriptor masks for the diagrams whose kernels are

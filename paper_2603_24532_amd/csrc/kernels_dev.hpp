@@ -814,7 +814,7 @@ __device__ __forceinline__ double rcp_newton(double d) {
 // REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
 // to wr[k - 1].
 template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V, int HE = 0, bool CY = false,
-          bool TAB = false, bool SCR = false>
+          bool TAB = false, bool SCR = false, bool TD = false>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
@@ -837,6 +837,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
       kv[2] = k[l][2];
     } else {
       if constexpr (TAB) table_sum<L>(Ls.cd + kCoefStride * l, k, kv);
+      else if constexpr (TD) table_sum<L>(D->coef_d[l], k, kv);
       else masked_sum<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
     }
     const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
@@ -909,6 +910,9 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
     if constexpr (TAB) {
       table_sum<L>(Ls.cd + kCoefStride * (2 * ORDER + 2 * v), k, p);
       table_sum<L>(Ls.cd + kCoefStride * (2 * ORDER + 2 * v + 1), k, q);
+    } else if constexpr (TD) {
+      table_sum<L>(D->coef_d[2 * ORDER + 2 * v], k, p);
+      table_sum<L>(D->coef_d[2 * ORDER + 2 * v + 1], k, q);
     } else {
       masked_sum<L, true, FixedMasks<ORDER, V>::kFixed>(pmask_of<ORDER, V>(D, v), k, p);
       masked_sum<L, true, FixedMasks<ORDER, V>::kFixed>(qmask_of<ORDER, V>(D, v), k, q);
@@ -1017,14 +1021,16 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     sum = 0.0;
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di) {
+      // the members' loop coefficients from their descriptors
+      constexpr bool TD = !FixedMasks<ORDER, V>::kFixed;
       if constexpr (group_cycle_form<ORDER, Q, X, HF>()) {
         SampleLds Lm = Ls;  // the member's cycle table
         Lm.cyc = static_cast<const char *>(Ls.cyc) + di * cycle_table_bytes<ORDER>();
-        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, true>(a, T, D + di, Lm, k, npass,
-                                                                    nterms, wr);
+        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, true, false, false, TD>(
+            a, T, D + di, Lm, k, npass, nterms, wr);
       } else {
-        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE>(a, T, D + di, Ls, k, npass, nterms,
-                                                              wr);
+        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, false, false, false, TD>(
+            a, T, D + di, Ls, k, npass, nterms, wr);
       }
     }
   } else {
@@ -1077,7 +1083,7 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 // fp32 contribution of one diagram at the loop momenta k (see
 // diag_weight64); sets `fallback` instead when the sample needs fp64.
 template <int ORDER, int Q, bool X, int V, int HE = 0, bool CY = false, bool TAB = false,
-          bool SCR = false>
+          bool SCR = false, bool TD = false>
 __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const float (*k)[3],
@@ -1101,6 +1107,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
       kv[2] = k[l][2];
     } else {
       if constexpr (TAB) table_sum_f<L>(Ls.cf + kCoefStride * l, k, kv);
+      else if constexpr (TD) table_sum_f<L>(D->coef_f[l], k, kv);
       else masked_sum_f<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
     }
     const float k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
@@ -1161,6 +1168,9 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
     if constexpr (TAB) {
       table_sum_f<L>(Ls.cf + kCoefStride * (2 * ORDER + 2 * v), k, p);
       table_sum_f<L>(Ls.cf + kCoefStride * (2 * ORDER + 2 * v + 1), k, q);
+    } else if constexpr (TD) {
+      table_sum_f<L>(D->coef_f[2 * ORDER + 2 * v], k, p);
+      table_sum_f<L>(D->coef_f[2 * ORDER + 2 * v + 1], k, q);
     } else {
       masked_sum_f<L, true, FixedMasks<ORDER, V>::kFixed>(pmask_of<ORDER, V>(D, v), k, p);
       masked_sum_f<L, true, FixedMasks<ORDER, V>::kFixed>(qmask_of<ORDER, V>(D, v), k, q);
@@ -1283,13 +1293,15 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     // that falls back is counted once, by its fp64 re-evaluation
     uint32_t gpass = 0, gterms = 0;
     for (int di = 0; di < nd; ++di) {
+      constexpr bool TD = !FixedMasks<ORDER, V>::kFixed;
       if constexpr (group_cycle_form<ORDER, Q, X, false>()) {
         SampleLds Lm = Ls;  // the member's cycle table
         Lm.cyc = static_cast<const char *>(Ls.cyc) + di * cycle_table_bytes<ORDER>();
-        sum += diag_weight32<ORDER, Q, X, V, HE, true>(a, T, D + di, Lm, k, gpass, gterms,
-                                                       fallback);
+        sum += diag_weight32<ORDER, Q, X, V, HE, true, false, false, TD>(a, T, D + di, Lm, k,
+                                                                          gpass, gterms, fallback);
       } else {
-        sum += diag_weight32<ORDER, Q, X, V, HE>(a, T, D + di, Ls, k, gpass, gterms, fallback);
+        sum += diag_weight32<ORDER, Q, X, V, HE, false, false, false, TD>(a, T, D + di, Ls, k,
+                                                                           gpass, gterms, fallback);
       }
       if (fallback) return 0.0;  // the whole sample is re-evaluated in fp64
     }

@@ -301,6 +301,29 @@ void fill_diag_dev(const Diagram &d, DiagDev &dd, bool canonical) {
       if (d.cut[c][l] > 0) dd.cut_hole[c] |= 1u << sl;
       if (d.cut[c][l] < 0) dd.cut_part[c] |= 1u << sl;
     }
+  // the masks decoded: bit j +1, 8 + j -1, 16 + j +2, 24 + j -2 (halved
+  // for the vertex sums)
+  auto unpack = [&](uint32_t m, double scale, int s) {
+    for (int j = 0; j < kDescCoefStride; ++j) {
+      double c = 0.0;
+      if (j < 8) {
+        if (m & (1u << j)) c = 1.0;
+        if (m & (1u << (8 + j))) c = -1.0;
+        if (m & (1u << (16 + j))) c = 2.0;
+        if (m & (1u << (24 + j))) c = -2.0;
+      }
+      dd.coef_d[s][j] = c * scale;
+      dd.coef_f[s][j] = static_cast<float>(c * scale);
+    }
+  };
+  for (int s = 0; s < kDescCoefSums; ++s)
+    for (int j = 0; j < kDescCoefStride; ++j) dd.coef_d[s][j] = dd.coef_f[s][j] = 0;
+  const int nl = 2 * d.order;
+  for (int sl = 0; sl < nl && sl < d.nlines; ++sl) unpack(dd.lmask[sl], 1.0, sl);
+  for (int v = 0; v < d.order; ++v) {
+    unpack(dd.pmask_v[v], 0.5, nl + 2 * v);
+    unpack(dd.qmask_v[v], 0.5, nl + 2 * v + 1);
+  }
 }
 
 // The kernels of orders 1-3 take the descriptor masks of the order's
