@@ -77,39 +77,25 @@ struct SampleLds {
   const double *ex;
   const double *hf;
   const double2 *g;
-  const void *cyc;  // label-cycle table of the item's diagram (cycle-form kernels)
-  // loop coefficients of the item's diagram, decoded once per task into LDS
-  // (coef_tab): kCoefStride per momentum sum, the 2 ORDER line slots then
-  // (2p, 2p') of every vertex halved, fp64 and fp32 copies
-  const double *cd;
-  const float *cf;
+  const void *cyc;  // label-cycle table(s) of the item's diagram(s) (cycle-form kernels)
 };
 
 // Diagram variant of a sample kernel's work items (template argument VF):
 // a diagram id >= 0 fixes the descriptor masks at compile time (per-diagram
-// kernels); kPerItem picks the variant per work item (with_variant) and, at
-// orders 4 and 5, reads the loop coefficients from a table in LDS;
-// kPerItemMasks picks it per item and decodes the coefficients from the
-// masks.
-constexpr int kPerItem = -2, kPerItemMasks = -3;
+// kernels); kPerItem picks the variant per work item (with_variant).
+constexpr int kPerItem = -2;
 
-constexpr int kCoefStride = 8;
-// Descriptor-driven single-diagram sample kernels of orders 4 and 5 (kPerItem)
-// read the loop coefficients of their momentum sums from LDS instead of
-// decoding them from the descriptor's bit masks per sum and sample on the
-// scalar unit.  Measured on MI355X: 9-18% faster fp64 (fifth order, fourth
-// order per task, with components, explicit label lists), fp32 the same or
-// faster, but slower in the persistent kernels (their registers are already
-// spilled), which keep the masks.
+// The descriptor-driven single-diagram sample kernels of orders 4 and 5 read
+// the loop coefficients of their momentum sums decoded in the descriptor
+// (DiagDev::coef_d / coef_f) through the scalar cache, instead of decoding
+// them from the bit masks per sum and sample on the scalar unit (so do the
+// group kernels, per member).  Measured on MI355X against the masks: 9-13%
+// faster at fourth order (per task, with components, neutron matter), 6-10%
+// at fifth order, and 5-10% in the persistent kernels; against a table of
+// the same values in LDS, 2-9% faster.
 template <int ORDER, int P, int VF>
-constexpr bool coef_tab() {
-  return ORDER >= 4 && !(P == 3 || P == 4 || P == 6) && VF == kPerItem;  // not the group modes
-}
-template <int ORDER, int P, int VF>
-constexpr size_t coef_lds_bytes() {
-  return coef_tab<ORDER, P, VF>()
-             ? static_cast<size_t>(4 * ORDER) * kCoefStride * (sizeof(double) + sizeof(float))
-             : 0;
+constexpr bool desc_coef() {
+  return ORDER >= 4 && !(P == 3 || P == 4 || P == 6) && VF < 0;  // not the group modes
 }
 
 // Label-cycle bit vectors: bit k of CycWord<ORDER> stands for cycle k of a
@@ -199,8 +185,6 @@ __device__ __forceinline__ double *carve_lds(const KArgs &a, const TaskDev *__re
   L.hf = ntab ? hf : nullptr;
   L.g = g;
   L.cyc = nullptr;
-  L.cd = nullptr;
-  L.cf = nullptr;
   return reinterpret_cast<double *>(g + nd * a.phys.nb);
 }
 
@@ -814,7 +798,7 @@ __device__ __forceinline__ double rcp_newton(double d) {
 // REG: also add the regularised components w_k = w prod_c D_c / (D_c - k eta)
 // to wr[k - 1].
 template <int ORDER, int Q, bool HF, bool REG, bool X, bool PI, int V, int HE = 0, bool CY = false,
-          bool TAB = false, bool SCR = false, bool TD = false>
+          bool SCR = false, bool TD = false>
 __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const double (*k)[3],
@@ -836,8 +820,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
       kv[1] = k[l][1];
       kv[2] = k[l][2];
     } else {
-      if constexpr (TAB) table_sum<L>(Ls.cd + kCoefStride * l, k, kv);
-      else if constexpr (TD) table_sum<L>(D->coef_d[l], k, kv);
+      if constexpr (TD) table_sum<L>(D->coef_d[l], k, kv);
       else masked_sum<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
     }
     const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
@@ -907,10 +890,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
     double p[3], q[3];  // relative momenta p and p'
-    if constexpr (TAB) {
-      table_sum<L>(Ls.cd + kCoefStride * (2 * ORDER + 2 * v), k, p);
-      table_sum<L>(Ls.cd + kCoefStride * (2 * ORDER + 2 * v + 1), k, q);
-    } else if constexpr (TD) {
+    if constexpr (TD) {
       table_sum<L>(D->coef_d[2 * ORDER + 2 * v], k, p);
       table_sum<L>(D->coef_d[2 * ORDER + 2 * v + 1], k, q);
     } else {
@@ -986,7 +966,7 @@ __device__ __forceinline__ double diag_weight64(const KArgs &a, const TaskDev *_
 // REG: the regularised components go to wr[0..nreg) (Jacobian and 1/n
 // included).
 template <int ORDER, int Q, bool HF, bool G, bool X, bool PI, int V, bool REG = false, int HE = 0,
-          bool TAB = false, bool SCR = false>
+          bool SCR = false, bool TD = false>
 __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, double jc, uint64_t s,
@@ -1022,21 +1002,21 @@ __device__ __forceinline__ double eval_fp64(const KArgs &a, const TaskDev *__res
     const int nd = T->ndiag;
     for (int di = 0; di < nd; ++di) {
       // the members' loop coefficients from their descriptors
-      constexpr bool TD = !FixedMasks<ORDER, V>::kFixed;
+      constexpr bool TDG = !FixedMasks<ORDER, V>::kFixed;
       if constexpr (group_cycle_form<ORDER, Q, X, HF>()) {
         SampleLds Lm = Ls;  // the member's cycle table
         Lm.cyc = static_cast<const char *>(Ls.cyc) + di * cycle_table_bytes<ORDER>();
-        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, true, false, false, TD>(
+        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, true, false, TDG>(
             a, T, D + di, Lm, k, npass, nterms, wr);
       } else {
-        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, false, false, false, TD>(
+        sum += diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, false, false, TDG>(
             a, T, D + di, Ls, k, npass, nterms, wr);
       }
     }
   } else {
     constexpr bool CY = cycle_form<ORDER, Q, false, X, HF>();
-    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, CY, TAB, SCR>(a, T, D, Ls, k, npass,
-                                                                     nterms, wr);
+    sum = diag_weight64<ORDER, Q, HF, REG, X, PI, V, HE, CY, SCR, TD>(a, T, D, Ls, k, npass,
+                                                                    nterms, wr);
     if constexpr (SCR) return sum;
   }
   const double scale = jac * (x0p * x0p) * jc;
@@ -1082,8 +1062,8 @@ __device__ __forceinline__ void masked_sum_f(uint32_t m, const float (*k)[3], fl
 // sample in fp64 from the same random words.
 // fp32 contribution of one diagram at the loop momenta k (see
 // diag_weight64); sets `fallback` instead when the sample needs fp64.
-template <int ORDER, int Q, bool X, int V, int HE = 0, bool CY = false, bool TAB = false,
-          bool SCR = false, bool TD = false>
+template <int ORDER, int Q, bool X, int V, int HE = 0, bool CY = false, bool SCR = false,
+          bool TD = false>
 __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *__restrict__ T,
                                                 const DiagDev *__restrict__ D,
                                                 const SampleLds &Ls, const float (*k)[3],
@@ -1106,8 +1086,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
       kv[1] = k[l][1];
       kv[2] = k[l][2];
     } else {
-      if constexpr (TAB) table_sum_f<L>(Ls.cf + kCoefStride * l, k, kv);
-      else if constexpr (TD) table_sum_f<L>(D->coef_f[l], k, kv);
+      if constexpr (TD) table_sum_f<L>(D->coef_f[l], k, kv);
       else masked_sum_f<L, false, FixedMasks<ORDER, V>::kFixed>(lmask_of<ORDER, V>(D, l), k, kv);
     }
     const float k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
@@ -1165,10 +1144,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
 #pragma unroll
   for (int v = 0; v < ORDER; ++v) {
     float p[3], q[3];
-    if constexpr (TAB) {
-      table_sum_f<L>(Ls.cf + kCoefStride * (2 * ORDER + 2 * v), k, p);
-      table_sum_f<L>(Ls.cf + kCoefStride * (2 * ORDER + 2 * v + 1), k, q);
-    } else if constexpr (TD) {
+    if constexpr (TD) {
       table_sum_f<L>(D->coef_f[2 * ORDER + 2 * v], k, p);
       table_sum_f<L>(D->coef_f[2 * ORDER + 2 * v + 1], k, q);
     } else {
@@ -1256,7 +1232,7 @@ __device__ __forceinline__ double diag_weight32(const KArgs &a, const TaskDev *_
          static_cast<double>(rinv[NR - 1]);
 }
 
-template <int ORDER, int Q, bool G, bool X, int V, int HE = 0, bool TAB = false, bool SCR = false>
+template <int ORDER, int Q, bool G, bool X, int V, int HE = 0, bool SCR = false, bool TD = false>
 __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__restrict__ T,
                                             const DiagDev *__restrict__ D,
                                             const SampleLds &Ls, double jc, uint64_t s,
@@ -1293,15 +1269,15 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     // that falls back is counted once, by its fp64 re-evaluation
     uint32_t gpass = 0, gterms = 0;
     for (int di = 0; di < nd; ++di) {
-      constexpr bool TD = !FixedMasks<ORDER, V>::kFixed;
+      constexpr bool TDG = !FixedMasks<ORDER, V>::kFixed;
       if constexpr (group_cycle_form<ORDER, Q, X, false>()) {
         SampleLds Lm = Ls;  // the member's cycle table
         Lm.cyc = static_cast<const char *>(Ls.cyc) + di * cycle_table_bytes<ORDER>();
-        sum += diag_weight32<ORDER, Q, X, V, HE, true, false, false, TD>(a, T, D + di, Lm, k,
-                                                                          gpass, gterms, fallback);
+        sum += diag_weight32<ORDER, Q, X, V, HE, true, false, TDG>(a, T, D + di, Lm, k, gpass,
+                                                                    gterms, fallback);
       } else {
-        sum += diag_weight32<ORDER, Q, X, V, HE, false, false, false, TD>(a, T, D + di, Ls, k,
-                                                                           gpass, gterms, fallback);
+        sum += diag_weight32<ORDER, Q, X, V, HE, false, false, TDG>(a, T, D + di, Ls, k, gpass,
+                                                                     gterms, fallback);
       }
       if (fallback) return 0.0;  // the whole sample is re-evaluated in fp64
     }
@@ -1309,7 +1285,7 @@ __device__ __forceinline__ double eval_fp32(const KArgs &a, const TaskDev *__res
     nterms += gterms;
   } else {
     constexpr bool CY = cycle_form<ORDER, Q, false, X, false>();
-    sum = diag_weight32<ORDER, Q, X, V, HE, CY, TAB, SCR>(a, T, D, Ls, k, npass, nterms, fallback);
+    sum = diag_weight32<ORDER, Q, X, V, HE, CY, SCR, TD>(a, T, D, Ls, k, npass, nterms, fallback);
     if constexpr (SCR) return sum;
     if (fallback) return 0.0;
   }
@@ -1392,9 +1368,11 @@ constexpr bool screen_on() {
 // order, so the order is deterministic); n is wave-uniform.
 __device__ __forceinline__ void wave_queue_push(uint32_t *q, int &n, bool flag, uint32_t v) {
   const uint64_t mask = __ballot(flag);
-  if (flag)
-    q[n + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u))] = v;
+  if (flag) {
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+        static_cast<uint32_t>(mask >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+    q[n + static_cast<int>(below)] = v;
+  }
   n += __popcll(mask);
   __builtin_amdgcn_wave_barrier();
 }
@@ -1414,7 +1392,8 @@ __device__ __forceinline__ void wave_queue_pop(uint32_t *q, int &n, int take, in
 // Bytes of the label-cycle table a sample or dump kernel of mode P holds in LDS.
 template <int ORDER, int Q, int P, bool X>
 constexpr size_t cycle_lds_bytes() {
-  if (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>()) return cycle_table_bytes<ORDER>();
+  if (cycle_form<ORDER, Q, group_of<P>(), X, prec_of<P>() == 2>())
+    return cycle_table_bytes<ORDER>();
   if (group_of<P>() && group_cycle_form<ORDER, Q, X, prec_of<P>() == 2>())
     return kGroupCycleTables * cycle_table_bytes<ORDER>();
   return 0;
@@ -1458,9 +1437,8 @@ struct BlockLds {
   double *red;
 };
 
-// Carves the block's LDS and loads the task-independent tables (VF: see
-// kPerItem).
-template <int ORDER, int Q, int P, bool X, int VF = kPerItem>
+// Carves the block's LDS and loads the task-independent tables.
+template <int ORDER, int Q, int P, bool X>
 __device__ __forceinline__ void block_lds(const KArgs &a, double *smem, BlockLds &B) {
   constexpr int ND = 3 * (ORDER + 1);
   constexpr int ntab = lds_tables<Q, P>();
@@ -1477,23 +1455,13 @@ __device__ __forceinline__ void block_lds(const KArgs &a, double *smem, BlockLds
   B.Ls.g = B.g;
   uint32_t *queue_end = reinterpret_cast<uint32_t *>(B.red + 6 * nw) + 256 * nw;
   B.Ls.cyc = holds_cycles<ORDER, Q, P, X>() ? queue_end : nullptr;
-  B.Ls.cd = nullptr;
-  B.Ls.cf = nullptr;
-  if constexpr (coef_tab<ORDER, P, VF>()) {
-    // after the cycle table (a multiple of 8 bytes)
-    double *cd = reinterpret_cast<double *>(reinterpret_cast<char *>(queue_end) +
-                                            cycle_lds_bytes<ORDER, Q, P, X>());
-    B.Ls.cd = cd;
-    B.Ls.cf = reinterpret_cast<const float *>(cd + 4 * ORDER * kCoefStride);
-  }
   load_turn_table(turn, ex);
 }
 
 // Loads task t's tables into the block's LDS: HF spline entries, grid pairs
-// (e_b + w_b 2^-33, w_b), a zeroed histogram, the label-cycle table of its
-// diagram and its loop coefficients.  The caller synchronises before and
-// after.
-template <int ORDER, int Q, int P, bool X, int VF = kPerItem>
+// (e_b + w_b 2^-33, w_b), a zeroed histogram and the label-cycle table(s) of
+// its diagram(s).  The caller synchronises before and after.
+template <int ORDER, int Q, int P, bool X>
 __device__ __forceinline__ void task_lds(const KArgs &a, int t, BlockLds &B) {
   constexpr int ND = 3 * (ORDER + 1);
   constexpr int ntab = lds_tables<Q, P>();
@@ -1515,32 +1483,6 @@ __device__ __forceinline__ void task_lds(const KArgs &a, int t, BlockLds &B) {
   }
   if constexpr (holds_cycles<ORDER, Q, P, X>())
     build_task_cycles<ORDER, Q, P, X>(a.diags + T->diag, T, const_cast<void *>(B.Ls.cyc));
-  if constexpr (coef_tab<ORDER, P, VF>()) {
-    // decoded by the helpers of masked_sum, so a table sum performs the
-    // same operations on the same values
-    constexpr int L = ORDER + 1, NL = 2 * ORDER, NS = 4 * ORDER;
-    const DiagDev *__restrict__ D = a.diags + T->diag;
-    double *cd = const_cast<double *>(B.Ls.cd);
-    float *cf = const_cast<float *>(B.Ls.cf);
-    for (int i = tid; i < NS * kCoefStride; i += bs) {
-      const int sm = i / kCoefStride, j = i - sm * kCoefStride;
-      double c = 0.0;
-      float f = 0.0f;
-      if (j < L) {
-        if (sm < NL) {
-          c = mask_coef<false>(D->lmask[sm], j);
-          f = mask_coef_f<false>(D->lmask[sm], j);
-        } else {
-          const int v = (sm - NL) >> 1;
-          const uint32_t m = ((sm - NL) & 1) ? D->qmask_v[v] : D->pmask_v[v];
-          c = mask_coef<true>(m, j);
-          f = mask_coef_f<true>(m, j);
-        }
-      }
-      cd[i] = c;
-      cf[i] = f;
-    }
-  }
 }
 
 // Adds the block's LDS histogram of task t to the task's histogram.
@@ -1611,8 +1553,8 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
     constexpr int V = decltype(vt)::value;
     // loop coefficients from the LDS table (descriptor-driven kernels of
     // orders 4 and 5)
-    constexpr bool TAB = coef_tab<ORDER, P, VF>();
-    static_assert(!TAB || !FixedMasks<ORDER, V>::kFixed, "fixed masks need no table");
+    // the loop coefficients decoded in the descriptor (desc_coef)
+    constexpr bool TD = desc_coef<ORDER, P, VF>() && !FixedMasks<ORDER, V>::kFixed;
     const double jc = jac_const<ORDER, V>(a, T, D);
     if constexpr (SCR && PP == 0) {
       int pn = 0;  // wave-uniform
@@ -1620,7 +1562,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
         if (lane < take) {
           const uint64_t s = base + pqueue[lane];
           int bins[ND];
-          const double w = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE, TAB>(
+          const double w = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE, false, TD>(
               a, T, D, Ls, jc, s, iter, bins, npass, nterms);
           accumulate(w, bins);
         }
@@ -1631,7 +1573,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
         bool go = false;
         if (s < N) {
           int bins[ND];
-          go = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE, TAB, true>(
+          go = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE, true, TD>(
                    a, T, D, Ls, jc, s, iter, bins, npass, nterms) != 0.0;
           if (!go) accumulate_zero();
         }
@@ -1646,7 +1588,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
           int bins[ND];
           if constexpr (R) {
             double wr[kMaxReg];
-            const double w = eval_fp64<ORDER, Q, false, G, X, PI, V, true, HE, TAB>(
+            const double w = eval_fp64<ORDER, Q, false, G, X, PI, V, true, HE, false, TD>(
                 a, T, D, Ls, jc, s, iter, bins, npass, nterms, wr);
             accumulate(w, bins);
             // the extrapolation's weights sum to one, so its shifted value
@@ -1662,7 +1604,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
             rs[2 * kMaxReg] += dx;
             rs[2 * kMaxReg + 1] += dx * dx;
           } else {
-            const double w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V, false, HE, TAB>(
+            const double w = eval_fp64<ORDER, Q, PP == 2, G, X, PI, V, false, HE, false, TD>(
                 a, T, D, Ls, jc, s, iter, bins, npass, nterms);
             accumulate(w, bins);
           }
@@ -1677,7 +1619,7 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
         if (lane < take) {
           const uint64_t s = base + queue[lane];
           int bins[ND];
-          const double w = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE, TAB>(
+          const double w = eval_fp64<ORDER, Q, false, G, X, PI, V, false, HE, false, TD>(
               a, T, D, Ls, jc, s, iter, bins, npass, nterms);
           accumulate(w, bins);
         }
@@ -1697,8 +1639,8 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
           if (lane < take) {
             off = pqueue[lane];
             int bins[ND];
-            const double w = eval_fp32<ORDER, Q, G, X, V, HE, TAB>(a, T, D, Ls, jc, base + off,
-                                                                   iter, bins, npass, nterms, fb);
+            const double w = eval_fp32<ORDER, Q, G, X, V, HE, false, TD>(
+                a, T, D, Ls, jc, base + off, iter, bins, npass, nterms, fb);
             if (!fb) accumulate(w, bins);
           }
           if (fb) ++nfb;
@@ -1712,8 +1654,8 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
           if (s < N) {
             int bins[ND];
             bool unused = false;
-            go = eval_fp32<ORDER, Q, G, X, V, HE, TAB, true>(a, T, D, Ls, jc, s, iter, bins, npass,
-                                                             nterms, unused) != 0.0;
+            go = eval_fp32<ORDER, Q, G, X, V, HE, true, TD>(a, T, D, Ls, jc, s, iter, bins,
+                                                                 npass, nterms, unused) != 0.0;
             if (!go) accumulate_zero();
           }
           wave_queue_push(pqueue, pn, go, static_cast<uint32_t>(s - base));
@@ -1726,8 +1668,8 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
           bool fb = false;
           if (s < N) {
             int bins[ND];
-            const double w = eval_fp32<ORDER, Q, G, X, V, HE, TAB>(a, T, D, Ls, jc, s, iter, bins,
-                                                                   npass, nterms, fb);
+            const double w = eval_fp32<ORDER, Q, G, X, V, HE, false, TD>(
+                a, T, D, Ls, jc, s, iter, bins, npass, nterms, fb);
             if (!fb) accumulate(w, bins);
           }
           const uint64_t mask = __ballot(fb);
@@ -1818,8 +1760,8 @@ __device__ __forceinline__ void item_samples(const KArgs &a, int t, int item, co
 template <int ORDER, int Q, int P, bool X, int HE, int VF = kPerItem>
 __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, double *smem) {
   BlockLds B;
-  block_lds<ORDER, Q, P, X, VF>(a, smem, B);
-  task_lds<ORDER, Q, P, X, VF>(a, t, B);
+  block_lds<ORDER, Q, P, X>(a, smem, B);
+  task_lds<ORDER, Q, P, X>(a, t, B);
   __syncthreads();
   item_samples<ORDER, Q, P, X, HE, VF>(a, t, item, B);
   __syncthreads();
@@ -1955,7 +1897,7 @@ __global__ __launch_bounds__(256, (persistent_waves<ORDER, Q, P, X>())) void sam
   const int2 *__restrict__ ol = a.olist;
   const int first = ol[k0].x;
   BlockLds B;
-  block_lds<ORDER, Q, P, X, kPerItemMasks>(a, smem, B);
+  block_lds<ORDER, Q, P, X>(a, smem, B);
   int cur = -1, lo = k0;
   for (;;) {
     __syncthreads();  // every thread has read the previous claim
@@ -1972,7 +1914,7 @@ __global__ __launch_bounds__(256, (persistent_waves<ORDER, Q, P, X>())) void sam
       if (t != cur) {
         if (cur >= 0) hist_flush<ORDER>(a, cur, B.h);
         __syncthreads();
-        task_lds<ORDER, Q, P, X, kPerItemMasks>(a, t, B);
+        task_lds<ORDER, Q, P, X>(a, t, B);
         __syncthreads();
         cur = t;
       }
@@ -1981,7 +1923,7 @@ __global__ __launch_bounds__(256, (persistent_waves<ORDER, Q, P, X>())) void sam
       // kernel)
       int tt = t, ii = item;
       asm volatile("" : "+s"(tt), "+s"(ii));
-      item_samples<ORDER, Q, P, X, HE, kPerItemMasks>(a, tt, ii, B);
+      item_samples<ORDER, Q, P, X, HE>(a, tt, ii, B);
     }
   }
   __syncthreads();

@@ -55,7 +55,7 @@ hipError_t launch_single_oq<O, Q>(const KArgs &a, int t, int prec, bool group, i
     constexpr bool X = decltype(x)::value;
     constexpr int HE = decltype(h)::value;
     const size_t lds = sample_lds_bytes(3 * (O + 1), a.phys.nb, block, lds_tables<Q, P>()) +
-                       cycle_lds_bytes<O, Q, P, X>() + coef_lds_bytes<O, P, kPerItem>();
+                       cycle_lds_bytes<O, Q, P, X>();
     hipLaunchKernelGGL((sample_single<O, Q, P, X, HE>), dim3(nitems), dim3(block), lds, st, a, t);
     return hipGetLastError();
   });
@@ -69,7 +69,7 @@ hipError_t launch_order_oq<O, Q>(const KArgs &a, int prec, bool group, int k0, i
     constexpr bool X = decltype(x)::value;
     constexpr int HE = decltype(h)::value;
     const size_t lds = sample_lds_bytes(3 * (O + 1), a.phys.nb, block, lds_tables<Q, P>()) +
-                       cycle_lds_bytes<O, Q, P, X>() + coef_lds_bytes<O, P, kPerItem>();
+                       cycle_lds_bytes<O, Q, P, X>();
     hipLaunchKernelGGL((sample_order<O, Q, P, X, HE>), dim3(grid), dim3(block), lds, st, a, k0,
                        k1);
     return hipGetLastError();

@@ -141,13 +141,14 @@ def test_launch_modes_agree(M):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("matter", ["nuclear", "neutron"])
-def test_coefficient_table_equals_masks(M, precision, matter):
-    """The descriptor-driven kernels of orders 4 and 5 read the loop
-    coefficients from a table in LDS in the per-task and per-order launches,
-    and decode them from the descriptor masks in the persistent launches.  The
-    same operations on the same values: with the same work items, the first
-    iteration (uniform grid, no histogram dependence) gives bit-identical
-    estimates, variances and fp32 fallback counts."""
+def test_descriptor_coefficients_equal_masks(M, precision, matter):
+    """The descriptor-driven sample kernels of orders 4 and 5 read the loop
+    coefficients decoded in the descriptor; the per-sample dump kernel
+    decodes them from the masks.  Same operations on the same values: the
+    first iteration (uniform grid, no histogram dependence) of the per-task,
+    per-order and persistent launches is bit-identical across the three
+    (with the same work items), fallback counts included, and equals the mean
+    of the dumped weights to the rounding of the sums."""
     if matter == "nuclear":
         tasks = [_task(5, 300, 4, 0.20, 0.1, 14), _task(5, 611, 4, 0.12, 0.5, 15)]
     else:
@@ -155,11 +156,13 @@ def test_coefficient_table_equals_masks(M, precision, matter):
                  _task(4, 30, 2, 0.08, 0.0, 7)]
     N = (1 << 16) + 777
     prec = M.MBPT_FP64 if precision == "fp64" else M.MBPT_FP32
-    out = {}
+    out, dumps = {}, None
     for mode in (0, 1, 3):
-        print(f"case table/masks {matter} mode={mode} {precision}", flush=True)
+        print(f"case descriptor coefficients {matter} mode={mode} {precision}", flush=True)
         run = Run(M, tasks, max_samples=N, mode=mode, precision=prec, spt=16)
         try:
+            if dumps is None:
+                dumps = [M.mbpt_dump_samples(run.set, k, 0, 0, N) for k in range(len(tasks))]
             per, _ = M.mbpt_integrate(run.set, N, 1)
             logs = [M.mbpt_iteration_log(run.set, k) for k in range(len(tasks))]
         finally:
@@ -169,6 +172,11 @@ def test_coefficient_table_equals_masks(M, precision, matter):
     for mode in (0, 1):
         assert out[mode][0] == out[3][0], (mode, out[mode][0], out[3][0])
         assert np.array_equal(out[mode][1], out[3][1]), (mode, out[mode][1], out[3][1])
+    for k in range(len(tasks)):
+        w = dumps[k]
+        assert np.count_nonzero(w) > 0
+        assert abs(out[1][1][k, 0] - w.mean()) <= 1e-12 * np.abs(w).mean(), (k, out[1][1][k, 0],
+                                                                             w.mean())
     if precision == "fp32":
         assert sum(f for _, f in out[3][0]) > 0  # the fallback path ran
 
