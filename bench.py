@@ -52,7 +52,7 @@ KERNEL_SOURCES = ("paper_2603_24532_amd/csrc/kernels_dev.hpp",
                   "paper_2603_24532_amd/csrc/device_types.hpp",
                   "paper_2603_24532_amd/csrc/fixed_masks_o4.hpp",
                   "paper_2603_24532_amd/csrc/turn_table.hpp")
-TRAFFIC = {"sha256": "bd32c177e9de4ee2655fbef8c520461bfc0ca718be84d4cdf8ad27139ff8604f",
+TRAFFIC = {"sha256": "a09a08b6f672fbc7061aa819171c841c99aded0d4ddc68dd590b9fb8ed2589bf",
            "block": 256, "spt": 256,
            # the 39 sample_order_fixed<4,4,1,2,id> dispatches of an iteration,
            # summed, mean over the 16 timed iterations of

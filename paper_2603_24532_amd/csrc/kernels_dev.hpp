@@ -1428,8 +1428,8 @@ constexpr int lds_tables() {
 
 // LDS of a sample block: turn and 2^(j/64) tables, HF tables, grid (e, width)
 // pairs, histogram, reduction scratch, fp64 re-evaluation queues and Pauli
-// screen queues (128 sample offsets per wavefront each), label-cycle table,
-// loop-coefficient table.
+// screen queues (128 sample offsets per wavefront each), label-cycle
+// table(s).
 struct BlockLds {
   SampleLds Ls;
   double2 *g;
