@@ -1783,8 +1783,9 @@ __device__ __forceinline__ void process_item(const KArgs &a, int t, int item, do
 // - third order, fp64 and fp32 (single diagrams specialised per diagram):
 //   4 waves with 60-130 spilled bytes beat 3 waves without (4-7%);
 // - nuclear matter with the cycle form of the label sum (single diagrams,
-//   work items of up to 65536 samples): fourth-order fp32 and fp64 at 4 waves
-//   (72-124 spilled bytes) beat 3 waves by 6% and 3%; fourth-order nuclear
+//   work items of up to 65536 samples): fourth-order fp32 at 4 waves beats 3
+//   by 1-6%; fourth-order fp64, with the loop coefficients from the
+//   descriptor, runs 4% faster at 3 waves than at 4; fourth-order nuclear
 //   group kernels, whose per-member cycle tables leave LDS for 3 blocks per
 //   CU, run 3-5% faster at 3 waves than at 4 and 8-13% faster than at 2;
 // - fifth-order nuclear matter with the Pauli screen: fp32 at 3 waves beats 4
@@ -1798,7 +1799,7 @@ constexpr int min_waves() {
     return (ORDER == 5 && Q == 4) ? 2 : 1;
   }
   if (Q == 4 && !X && (P == 0 || P == 1)) {
-    if (ORDER == 4) return 4;
+    if (ORDER == 4) return P == 1 ? 4 : 3;
     if (ORDER == 5) return 3;
   }
   if (ORDER == 3 && (P == 0 || P == 1)) return 4;
