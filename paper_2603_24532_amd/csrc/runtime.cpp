@@ -943,7 +943,8 @@ extern "C" int mbpt_create_task_set(mbpt_context *ctx, const mbpt_task_desc *tas
   if (!ctx || !out) return MBPT_EINVAL;
   *out = nullptr;
   if (!fixed_masks_ok()) {
-    set_err(ctx, "internal: the generator's descriptors differ from the kernels' compile-time tables");
+    set_err(ctx, "internal: the generator's descriptors differ from the kernels' compile-time "
+                 "tables or exceed their group limit");
     return MBPT_EINVAL;
   }
   int q = 2;

@@ -536,7 +536,8 @@ extern "C" int mbpt_server_create(mbpt_context *ctx, int max_slots, uint64_t max
     return MBPT_EINVAL;
   }
   if (!fixed_masks_ok()) {
-    set_err(ctx, "internal: the generator's descriptors differ from the kernels' compile-time tables");
+    set_err(ctx, "internal: the generator's descriptors differ from the kernels' compile-time "
+                 "tables or exceed their group limit");
     return MBPT_EINVAL;
   }
   Layout L{};
