@@ -52,7 +52,7 @@ KERNEL_SOURCES = ("paper_2603_24532_amd/csrc/kernels_dev.hpp",
                   "paper_2603_24532_amd/csrc/device_types.hpp",
                   "paper_2603_24532_amd/csrc/fixed_masks_o4.hpp",
                   "paper_2603_24532_amd/csrc/turn_table.hpp")
-TRAFFIC = {"sha256": "655f0b72b9ce357b464d3f0624bb3c279f14e3fa3f39ac334d6110bbe43c9d7c",
+TRAFFIC = {"sha256": "cf063b5dfac7cc8582f8cebc56104b306497df6f22fa5863cf80ccdc296e7aab",
            "block": 256, "spt": 256,
            # the 39 sample_order_fixed<4,4,1,2,id> dispatches of an iteration,
            # summed, mean over the 16 timed iterations of

@@ -61,7 +61,9 @@ struct alignas(16) DiagDev {
 // Compile-time descriptor masks for the diagrams whose kernels are
 // specialised: the one two-body diagram of orders 1 and 2, the three of
 // order 3 and the 39 of order 4 (variant V = diagram id; V = -1 is the
-// generic, descriptor-driven path).  The masks are those the generator
+// generic, descriptor-driven path).  From order 2 on they also hold the
+// label-cycle words per vertex-term choice (cyc_e32, the packing of
+// DiagDev::cyc_e32, plain loop order).  The masks are those the generator
 // compiles (loops first, plain loop order); with them the compiler folds the
 // loop-momentum sums, drops the zero coefficients and shares equal vertex
 // momenta.  Task-set and server creation check the generator's masks against
@@ -91,6 +93,7 @@ struct FixedMasks<2, 0> {
   static constexpr uint32_t cut_hole[1] = {0x6u};
   static constexpr uint32_t cut_part[1] = {0x9u};
   static constexpr int loop_part[3] = {1, 0, 0};
+  static constexpr uint32_t cyc_e32[4] = {0x2000003u, 0x1000004u, 0x1000004u, 0x2000018u};
 };
 template <>
 struct FixedMasks<3, 0> {
@@ -102,6 +105,8 @@ struct FixedMasks<3, 0> {
   static constexpr uint32_t cut_hole[2] = {0x22u, 0xCu};
   static constexpr uint32_t cut_part[2] = {0x11u, 0x11u};
   static constexpr int loop_part[4] = {1, 0, 0, 0};
+  static constexpr uint32_t cyc_e32[8] = {0x2000003u, 0x1000004u, 0x1000004u, 0x2000018u,
+                                          0x1000004u, 0x2000060u, 0x2000180u, 0x1000004u};
 };
 template <>
 struct FixedMasks<3, 1> {
@@ -113,6 +118,8 @@ struct FixedMasks<3, 1> {
   static constexpr uint32_t cut_hole[2] = {0x6u, 0xCu};
   static constexpr uint32_t cut_part[2] = {0x30u, 0x21u};
   static constexpr int loop_part[4] = {1, 0, 0, 0};
+  static constexpr uint32_t cyc_e32[8] = {0x2000003u, 0x1000004u, 0x3000019u, 0x2000030u,
+                                          0x1000004u, 0x20000C0u, 0x2000108u, 0x1000004u};
 };
 template <>
 struct FixedMasks<3, 2> {
@@ -124,6 +131,8 @@ struct FixedMasks<3, 2> {
   static constexpr uint32_t cut_hole[2] = {0xCu, 0xCu};
   static constexpr uint32_t cut_part[2] = {0x11u, 0x22u};
   static constexpr int loop_part[4] = {1, 1, 0, 0};
+  static constexpr uint32_t cyc_e32[8] = {0x2000003u, 0x1000004u, 0x1000004u, 0x2000018u,
+                                          0x1000004u, 0x2000060u, 0x2000180u, 0x1000004u};
 };
 
 }  // namespace mbpt

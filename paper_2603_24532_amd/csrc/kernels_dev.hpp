@@ -572,7 +572,7 @@ __device__ __forceinline__ double group_den(const DiagDev *__restrict__ D, uint3
 template <int ORDER, int V = -1>
 __device__ __forceinline__ void cycles_of_e(const DiagDev *__restrict__ D, int E,
                                             CycWordV<ORDER, V> &m, uint32_t &n) {
-  if constexpr (ORDER == 4 && fixed_cycles<FixedMasks<ORDER, V>>::value) {
+  if constexpr (ORDER <= 4 && fixed_cycles<FixedMasks<ORDER, V>>::value) {
     const uint32_t w = FixedMasks<ORDER, V>::cyc_e32[E];
     m = w & 0xFFFFFFu;
     n = w >> 24;

@@ -344,14 +344,16 @@ static bool fixed_masks_match(const DiagDev &dd) {
   return ok;
 }
 
-// The fourth-order tables also fix the label cycles per vertex-term choice.
-template <int V>
+// The tables of orders 2-4 also fix the label cycles per vertex-term choice
+// (plain loop order: the single-diagram kernels).
+template <int ORDER, int V>
 static bool fixed_cycles_match(const Diagram &d) {
-  using F = FixedMasks<4, V>;
+  using F = FixedMasks<ORDER, V>;
+  constexpr int NE = 1 << ORDER;
   const CycleTables ct = cycle_tables(d, false);
-  if (ct.masks.size() > 24 || ct.of_e.size() != 16) return false;
+  if (ct.masks.size() > 24 || ct.of_e.size() != static_cast<size_t>(NE)) return false;
   bool ok = true;
-  for (int E = 0; E < 16; ++E)
+  for (int E = 0; E < NE; ++E)
     ok = ok && F::cyc_e32[E] ==
                    static_cast<uint32_t>(ct.of_e[E] | static_cast<uint64_t>(ct.n_of_e[E]) << 24);
   return ok;
@@ -360,7 +362,7 @@ static bool fixed_cycles_match(const Diagram &d) {
 template <typename Dev, int... I>
 static bool fixed4_match(Dev &&dev, std::integer_sequence<int, I...>) {
   return ((fixed_masks_match<4, I>(dev(4, I, false)) &&
-           fixed_cycles_match<I>(*get_diagram(4, I))) && ...);
+           fixed_cycles_match<4, I>(*get_diagram(4, I))) && ...);
 }
 
 bool fixed_masks_ok() {
@@ -378,6 +380,9 @@ bool fixed_masks_ok() {
     r = r && fixed_masks_match<3, 0>(dev(3, 0, false));
     r = r && fixed_masks_match<3, 1>(dev(3, 1, false));
     r = r && fixed_masks_match<3, 2>(dev(3, 2, false));
+    r = r && fixed_cycles_match<2, 0>(*get_diagram(2, 0));
+    r = r && fixed_cycles_match<3, 0>(*get_diagram(3, 0)) &&
+        fixed_cycles_match<3, 1>(*get_diagram(3, 1)) && fixed_cycles_match<3, 2>(*get_diagram(3, 2));
     // the 39 fourth-order diagrams of the per-diagram kernels
     r = r && num_diagrams(4) == 39 &&
         fixed4_match(dev, std::make_integer_sequence<int, 39>{});
