@@ -52,7 +52,7 @@ KERNEL_SOURCES = ("paper_2603_24532_amd/csrc/kernels_dev.hpp",
                   "paper_2603_24532_amd/csrc/device_types.hpp",
                   "paper_2603_24532_amd/csrc/fixed_masks_o4.hpp",
                   "paper_2603_24532_amd/csrc/turn_table.hpp")
-TRAFFIC = {"sha256": "cf063b5dfac7cc8582f8cebc56104b306497df6f22fa5863cf80ccdc296e7aab",
+TRAFFIC = {"sha256": "9483813bd2837d6e66fee87a74160847bf49805f81185ccea30be27f592e023d",
            "block": 256, "spt": 256,
            # the 39 sample_order_fixed<4,4,1,2,id> dispatches of an iteration,
            # summed, mean over the 16 timed iterations of

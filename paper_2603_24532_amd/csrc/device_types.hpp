@@ -63,7 +63,9 @@ struct alignas(16) DiagDev {
 // order 3 and the 39 of order 4 (variant V = diagram id; V = -1 is the
 // generic, descriptor-driven path).  From order 2 on they also hold the
 // label-cycle words per vertex-term choice (cyc_e32, the packing of
-// DiagDev::cyc_e32, plain loop order).  The masks are those the generator
+// DiagDev::cyc_e32, plain loop order), and at orders 2 and 3 the
+// coefficients of the neutron-matter label polynomial (label_coef_q2, its
+// one isospin configuration).  The masks are those the generator
 // compiles (loops first, plain loop order); with them the compiler folds the
 // loop-momentum sums, drops the zero coefficients and shares equal vertex
 // momenta.  Task-set and server creation check the generator's masks against
@@ -94,6 +96,7 @@ struct FixedMasks<2, 0> {
   static constexpr uint32_t cut_part[1] = {0x9u};
   static constexpr int loop_part[3] = {1, 0, 0};
   static constexpr uint32_t cyc_e32[4] = {0x2000003u, 0x1000004u, 0x1000004u, 0x2000018u};
+  static constexpr double label_coef_q2[4] = {4, -2, -2, 4};
 };
 template <>
 struct FixedMasks<3, 0> {
@@ -107,6 +110,7 @@ struct FixedMasks<3, 0> {
   static constexpr int loop_part[4] = {1, 0, 0, 0};
   static constexpr uint32_t cyc_e32[8] = {0x2000003u, 0x1000004u, 0x1000004u, 0x2000018u,
                                           0x1000004u, 0x2000060u, 0x2000180u, 0x1000004u};
+  static constexpr double label_coef_q2[8] = {4, -2, -2, 4, -2, 4, 4, -2};
 };
 template <>
 struct FixedMasks<3, 1> {
@@ -120,6 +124,7 @@ struct FixedMasks<3, 1> {
   static constexpr int loop_part[4] = {1, 0, 0, 0};
   static constexpr uint32_t cyc_e32[8] = {0x2000003u, 0x1000004u, 0x3000019u, 0x2000030u,
                                           0x1000004u, 0x20000C0u, 0x2000108u, 0x1000004u};
+  static constexpr double label_coef_q2[8] = {4, -2, -8, 4, -2, 4, 4, -2};
 };
 template <>
 struct FixedMasks<3, 2> {
@@ -133,6 +138,7 @@ struct FixedMasks<3, 2> {
   static constexpr int loop_part[4] = {1, 1, 0, 0};
   static constexpr uint32_t cyc_e32[8] = {0x2000003u, 0x1000004u, 0x1000004u, 0x2000018u,
                                           0x1000004u, 0x2000060u, 0x2000180u, 0x1000004u};
+  static constexpr double label_coef_q2[8] = {4, -2, -2, 4, -2, 4, 4, -2};
 };
 
 }  // namespace mbpt
@@ -149,6 +155,11 @@ template <typename F, typename = void>
 struct fixed_cycles : std::false_type {};
 template <typename F>
 struct fixed_cycles<F, std::void_t<decltype(F::cyc_e32)>> : std::true_type {};
+// FixedMasks with the neutron-matter label coefficients (label_coef_q2).
+template <typename F, typename = void>
+struct fixed_labels : std::false_type {};
+template <typename F>
+struct fixed_labels<F, std::void_t<decltype(F::label_coef_q2)>> : std::true_type {};
 
 }  // namespace mbpt
 

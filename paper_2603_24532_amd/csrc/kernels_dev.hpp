@@ -700,35 +700,50 @@ __device__ __forceinline__ F label_sum(const KArgs &a, const DiagDev *__restrict
 #pragma unroll
       for (int i = 0; i < NB; ++i) AB[i] = fabs(MB[i]);
     }
-    for (int gi = 0; gi < ngroups; ++gi) {
-      const uint32_t tau = G[gi].tau;
-      bool ok = true;
-      if (Q == 4) ok = (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
-      if (ok) {
-        ++units;
-        const F *__restrict__ C = coef_run<ORDER, F>(a.gcoef + G[gi].coef_off);
-        F c[NA * NB];  // one batch of scalar loads, then the multiply-adds
+    // one isospin configuration's polynomial sum_E c_E prod V
+    auto add_config = [&](const F *c, uint32_t tau) {
+      F gs = F(0);
 #pragma unroll
-        for (int i = 0; i < NA * NB; ++i) c[i] = C[i];
-        F gs = F(0);
+      for (int eb = 0; eb < NB; ++eb) {
+        F in = F(0);
+#pragma unroll
+        for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(c[eb * NA + ea], MA[ea], in);
+        gs = fma_t<F>(in, MB[eb], gs);
+      }
+      if constexpr (ABS) {
 #pragma unroll
         for (int eb = 0; eb < NB; ++eb) {
           F in = F(0);
 #pragma unroll
-          for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(c[eb * NA + ea], MA[ea], in);
-          gs = fma_t<F>(in, MB[eb], gs);
+          for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(fabs(c[eb * NA + ea]), AA[ea], in);
+          aacc = fma_t<F>(in, AB[eb], aacc);
         }
-        if constexpr (ABS) {
+      }
+      if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER, V>(D, tau, Dn, deps));
+      acc += gs;
+    };
+    if constexpr (Q == 2 && fixed_labels<FixedMasks<ORDER, V>>::value) {
+      // neutron matter, a diagram of the fixed tables: its one configuration
+      // with compile-time coefficients
+      F c[NA * NB];
 #pragma unroll
-          for (int eb = 0; eb < NB; ++eb) {
-            F in = F(0);
+      for (int i = 0; i < NA * NB; ++i)
+        c[i] = static_cast<F>(FixedMasks<ORDER, V>::label_coef_q2[i]);
+      ++units;
+      add_config(c, 0u);
+    } else {
+      for (int gi = 0; gi < ngroups; ++gi) {
+        const uint32_t tau = G[gi].tau;
+        bool ok = true;
+        if (Q == 4) ok = (((~tau & ~okN) | (tau & ~okP)) & lmask) == 0u;
+        if (ok) {
+          ++units;
+          const F *__restrict__ C = coef_run<ORDER, F>(a.gcoef + G[gi].coef_off);
+          F c[NA * NB];  // one batch of scalar loads, then the multiply-adds
 #pragma unroll
-            for (int ea = 0; ea < NA; ++ea) in = fma_t<F>(fabs(c[eb * NA + ea]), AA[ea], in);
-            aacc = fma_t<F>(in, AB[eb], aacc);
-          }
+          for (int i = 0; i < NA * NB; ++i) c[i] = C[i];
+          add_config(c, tau);
         }
-        if constexpr (ISO) gs = static_cast<F>(static_cast<double>(gs) / group_den<ORDER, V>(D, tau, Dn, deps));
-        acc += gs;
       }
     }
   } else {

@@ -359,6 +359,20 @@ static bool fixed_cycles_match(const Diagram &d) {
   return ok;
 }
 
+// The tables of orders 2 and 3 also fix the neutron-matter label
+// coefficients: one isospin configuration (all neutrons).
+template <int ORDER, int V>
+static bool fixed_labels_match(const Diagram &d, bool canonical) {
+  using F = FixedMasks<ORDER, V>;
+  const LabelTables lt = label_tables(d, 2, canonical);
+  if (lt.groups.size() != 1 || lt.groups[0].tau != 0u ||
+      lt.groups[0].coef.size() != (size_t{1} << ORDER))
+    return false;
+  bool ok = true;
+  for (int i = 0; i < (1 << ORDER); ++i) ok = ok && lt.groups[0].coef[i] == F::label_coef_q2[i];
+  return ok;
+}
+
 template <typename Dev, int... I>
 static bool fixed4_match(Dev &&dev, std::integer_sequence<int, I...>) {
   return ((fixed_masks_match<4, I>(dev(4, I, false)) &&
@@ -381,6 +395,12 @@ bool fixed_masks_ok() {
     r = r && fixed_masks_match<3, 1>(dev(3, 1, false));
     r = r && fixed_masks_match<3, 2>(dev(3, 2, false));
     r = r && fixed_cycles_match<2, 0>(*get_diagram(2, 0));
+    // order 2: single diagrams and (single-member) groups take the table
+    r = r && fixed_labels_match<2, 0>(*get_diagram(2, 0), false) &&
+        fixed_labels_match<2, 0>(*get_diagram(2, 0), true);
+    r = r && fixed_labels_match<3, 0>(*get_diagram(3, 0), false) &&
+        fixed_labels_match<3, 1>(*get_diagram(3, 1), false) &&
+        fixed_labels_match<3, 2>(*get_diagram(3, 2), false);
     r = r && fixed_cycles_match<3, 0>(*get_diagram(3, 0)) &&
         fixed_cycles_match<3, 1>(*get_diagram(3, 1)) && fixed_cycles_match<3, 2>(*get_diagram(3, 2));
     // the 39 fourth-order diagrams of the per-diagram kernels
