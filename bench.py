@@ -52,7 +52,7 @@ KERNEL_SOURCES = ("paper_2603_24532_amd/csrc/kernels_dev.hpp",
                   "paper_2603_24532_amd/csrc/device_types.hpp",
                   "paper_2603_24532_amd/csrc/fixed_masks_o4.hpp",
                   "paper_2603_24532_amd/csrc/turn_table.hpp")
-TRAFFIC = {"sha256": "9483813bd2837d6e66fee87a74160847bf49805f81185ccea30be27f592e023d",
+TRAFFIC = {"sha256": "62d0b7c09ded4130c6eb2a38ecfbc58b69f0803efa1f763951120f7ada27c528",
            "block": 256, "spt": 256,
            # the 39 sample_order_fixed<4,4,1,2,id> dispatches of an iteration,
            # summed, mean over the 16 timed iterations of

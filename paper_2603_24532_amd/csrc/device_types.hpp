@@ -63,9 +63,9 @@ struct alignas(16) DiagDev {
 // order 3 and the 39 of order 4 (variant V = diagram id; V = -1 is the
 // generic, descriptor-driven path).  From order 2 on they also hold the
 // label-cycle words per vertex-term choice (cyc_e32, the packing of
-// DiagDev::cyc_e32, plain loop order), and at orders 2 and 3 the
-// coefficients of the neutron-matter label polynomial (label_coef_q2, its
-// one isospin configuration).  The masks are those the generator
+// DiagDev::cyc_e32, plain loop order), and at orders 1-3 the coefficients
+// of the neutron-matter label polynomial (label_coef_q2, its one isospin
+// configuration).  The masks are those the generator
 // compiles (loops first, plain loop order); with them the compiler folds the
 // loop-momentum sums, drops the zero coefficients and shares equal vertex
 // momenta.  Task-set and server creation check the generator's masks against
@@ -84,6 +84,7 @@ struct FixedMasks<1, 0> {
   static constexpr uint32_t cut_hole[1] = {0x0u};
   static constexpr uint32_t cut_part[1] = {0x0u};
   static constexpr int loop_part[2] = {0, 0};
+  static constexpr double label_coef_q2[2] = {4, -2};
 };
 template <>
 struct FixedMasks<2, 0> {

@@ -359,8 +359,8 @@ static bool fixed_cycles_match(const Diagram &d) {
   return ok;
 }
 
-// The tables of orders 2 and 3 also fix the neutron-matter label
-// coefficients: one isospin configuration (all neutrons).
+// The tables of orders 1-3 also fix the neutron-matter label coefficients:
+// one isospin configuration (all neutrons).
 template <int ORDER, int V>
 static bool fixed_labels_match(const Diagram &d, bool canonical) {
   using F = FixedMasks<ORDER, V>;
@@ -395,7 +395,9 @@ bool fixed_masks_ok() {
     r = r && fixed_masks_match<3, 1>(dev(3, 1, false));
     r = r && fixed_masks_match<3, 2>(dev(3, 2, false));
     r = r && fixed_cycles_match<2, 0>(*get_diagram(2, 0));
-    // order 2: single diagrams and (single-member) groups take the table
+    // orders 1 and 2: single diagrams and (single-member) groups take the table
+    r = r && fixed_labels_match<1, 0>(*get_diagram(1, 0), false) &&
+        fixed_labels_match<1, 0>(*get_diagram(1, 0), true);
     r = r && fixed_labels_match<2, 0>(*get_diagram(2, 0), false) &&
         fixed_labels_match<2, 0>(*get_diagram(2, 0), true);
     r = r && fixed_labels_match<3, 0>(*get_diagram(3, 0), false) &&
